@@ -1,0 +1,179 @@
+/*
+ * vie.h -- C ABI of the MI355X FFT-VIE / far-field / two-photon library.
+ *
+ * Problem (arXiv 2508.16471, Sec. II-C): a lossless dielectric body of
+ * piecewise-constant permittivity eps_r in vacuum, lit by plane-wave input
+ * channels (e^{-i w t} convention).  The polarisation current
+ * J = -i w (eps - eps0) E (eq. Js_def) solves the volume integral equation
+ * eq. 24 with the free-space dyadic Green's function (eq. dyadicG).  The
+ * library discretises it on the body's uniform voxel grid (pulse basis,
+ * centre collocation, equal-volume-sphere self term) in the contrast-current
+ * unknown w = chi E, chi = eps_r - 1:
+ *
+ *     w_m - chi_m sum_n Ghat_mn w_n = chi_m e_m,
+ *     Ghat_mn = k0^2 h^3 G(r_m - r_n) (m != n),  Ghat_mm = s I,
+ *     s = -1/3 + 2/3 (cos x + x sin x - 1) + i k0^3 h^3 / (6 pi),
+ *     x = k0 h (3 / 4 pi)^(1/3),
+ *
+ * solves it with BiCGSTAB around an FFT-accelerated product (Sec. II-C),
+ * evaluates the far-field amplitude of eq. 25,
+ *     F(r) = k0^2 h^3 / (4 pi) (I - r r) sum_n w_n exp(-i k0 r . r_n)
+ * (so that E_sca ~ F e^{i k0 R} / R), and the two-photon observables g2
+ * (eq. 10) and the coincidence number Nc(dtau) (eqs. 18-22).
+ * J^s follows from w as J^s = -i w eps0 w.
+ *
+ * Conventions
+ *   - Lengths in any unit, the same for h, origin and 1/k0.
+ *   - Grids: n[3] = (N1, N2, N3) voxels, x fastest in memory; voxel (i,j,l)
+ *     is centred at origin + h (i, j, l).
+ *   - Complex vectors of a body are [component 0..2][z][y][x], interleaved
+ *     (re, im) doubles: 3 * N1 * N2 * N3 vie_c64 per right-hand side.
+ *   - Every pointer argument is owned by the caller; host pointers unless
+ *     the function name ends in _dev (then device pointers on the current
+ *     HIP device, and the call is asynchronous on the context's stream).
+ *   - Errors are negative return codes; nothing is thrown across the ABI.
+ *     After VIE_EINVAL / VIE_ENOTSUP the context stays usable.  After
+ *     VIE_EDEVICE the context is poisoned: later calls return VIE_ESTATE and
+ *     the caller must vie_destroy() it.
+ *   - A context is not thread-safe; use one per host thread.
+ */
+#ifndef VIE_H
+#define VIE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vie_ctx vie_ctx;
+typedef struct { double re, im; } vie_c64;
+
+enum vie_status {
+  VIE_OK = 0,
+  VIE_EINVAL = -1,  /* invalid argument (shape, range, NaN, NULL)            */
+  VIE_ENOMEM = -2,  /* device or host allocation failed                      */
+  VIE_EDEVICE = -3, /* HIP runtime error; context poisoned                   */
+  VIE_ENOCONV = -4, /* a right-hand side missed tol within max_iter          */
+  VIE_ENOTSUP = -5, /* valid but unsupported request (e.g. grid too large)   */
+  VIE_ESTATE = -6   /* call on a poisoned / unprepared context               */
+};
+
+enum { VIE_FP64 = 0, VIE_MIXED = 1 };
+enum { VIE_NORM_R1 = 0, VIE_NORM_R2 = 1 };
+enum { VIE_FLAG_TIMING = 1 }; /* record per-kernel HIP-event durations */
+
+/* One body on its own uniform grid (eq. 24's volume V, discretised). */
+typedef struct {
+  int32_t n[3];        /* voxels per axis, each 1..256                          */
+  double h;            /* voxel edge > 0                                        */
+  double origin[3];    /* centre of voxel (0,0,0)                               */
+  const double *eps_r; /* host, N1*N2*N3 relative permittivities, x fastest,   */
+                       /* finite and >= 1 (lossless, eps_r = 1 is background);  */
+                       /* copied during vie_setup                               */
+} vie_body;
+
+typedef struct {
+  double k0;          /* free-space wavenumber > 0                              */
+  int32_t precision;  /* VIE_FP64: FP64 FFT product; VIE_MIXED: FP32 FFT       */
+                      /* product inside FP64 iterative refinement               */
+  double tol;         /* stop when ||b - A w|| / ||b|| <= tol, measured with    */
+                      /* the FP64 operator (A = I - chi Ghat, b = chi e)        */
+  int32_t max_iter;   /* BiCGSTAB iterations per right-hand side (all cycles)   */
+  double inner_tol;   /* MIXED: residual reduction per refinement cycle (1e-3) */
+  int32_t warm_start; /* 1: start from the loaded network's prediction (with    */
+                      /* residual check and fallback to w = 0)                  */
+  int32_t flags;      /* VIE_FLAG_* bits                                        */
+} vie_options;
+
+/* Incident channel e(r) = pol exp(i k0 khat . r); |khat| = 1, pol . khat = 0. */
+typedef struct {
+  double khat[3];
+  vie_c64 pol[3];
+} vie_planewave;
+
+typedef struct {
+  int32_t iters;      /* BiCGSTAB iterations (all refinement cycles)            */
+  int32_t matvecs;    /* operator products (FP32 and FP64)                      */
+  int32_t cycles;     /* refinement / restart cycles                            */
+  int32_t converged;  /* 1 if rel_res <= tol                                    */
+  int32_t fallback;   /* 1 if a warm start was rejected and w = 0 was used      */
+  int32_t warm;       /* 1 if the warm start was used                           */
+  double rel_res;     /* final true ||b - A w|| / ||b|| (FP64 operator)         */
+  double rel_res_x0;  /* true relative residual of the initial guess            */
+} vie_stats;
+
+/* Set up a context for n_bodies bodies: copies eps_r (chi = eps_r - 1) to
+ * the device, builds the FP64 (and FP32) octant spectrum of the circulant
+ * embedding of Ghat for each distinct (grid, h, k0), allocates Krylov and FFT
+ * workspaces.  Returns VIE_EINVAL on bad shapes/values, VIE_ENOTSUP if a
+ * grid exceeds 256 per axis. */
+int vie_setup(const vie_body *bodies, int32_t n_bodies, const vie_options *opt,
+              vie_ctx **out);
+
+/* Solve eq. 24 (discretised as above) for every right-hand side: body b gets
+ * nrhs_per_body[b] channels taken in order from inc[].  All right-hand sides
+ * of all bodies are advanced together (batched kernels); stats (caller array,
+ * one entry per right-hand side, may be NULL) report iterations and the final
+ * FP64 true residual.  Solutions stay on the device (vie_get_current,
+ * vie_farfield).  Returns VIE_ENOCONV if any right-hand side missed tol
+ * (stats and the best iterate are still filled in). */
+int vie_solve(vie_ctx *ctx, const vie_planewave *inc, const int32_t *nrhs_per_body,
+              vie_stats *stats);
+
+/* Far-field amplitude (eq. 25, normalisation above) of every right-hand
+ * side of `body` at ndir directions (theta, phi in radians):
+ * F[(rhs * ndir + d) * 2 + {0,1}] = (F_theta, F_phi) with
+ * theta-hat = (cos t cos p, cos t sin p, -sin t), phi-hat = (-sin p, cos p, 0).
+ * Host arrays. */
+int vie_farfield(vie_ctx *ctx, int32_t body, const double *theta, const double *phi,
+                 int32_t ndir, vie_c64 *F);
+
+/* Two-photon observables of two populated channels from the 2x2 transfer
+ * coefficients T = (T_a1, T_a2, T_b1, T_b2) (eqs. field_transfer1/2; T_aj is
+ * detector a's projected far-field amplitude for channel j, eq. Eproj).
+ *   g2 (eq. 10) with weights omega[2] (NULL: equal);
+ *   Nc_raw[k] = sigma sqrt(pi) (|A_d|^2 + |A_e|^2 + 2 Re(A_d A_e*) c_k),
+ *     A_d = T_a1 T_b2, A_e = T_a2 T_b1, c_k = exp(-dtau_k^2 / sigma^2)
+ *     (eqs. 19-22 with K = 1 and baseband Gaussian wavepackets);
+ *   Nc_norm = Nc_raw / D_c with D_c = sigma sqrt(pi) (|A_d|^2 + |A_e|^2)
+ *     (VIE_NORM_R1, -> 1 at large delay, eq. 18) or
+ *     D_c = sigma sqrt(pi) G1_a G1_b (VIE_NORM_R2, Nc_norm(0) = g2).
+ * A dark detector (zero denominator) gives NaN and VIE_OK.  Host arrays;
+ * g2, Nc_raw, Nc_norm may each be NULL. */
+int hom_g2(const vie_c64 T[4], const double *omega, double sigma, const double *dtau,
+           int32_t ndelay, int32_t norm, double *g2, double *Nc_raw, double *Nc_norm);
+
+/* Copy the solution w = chi E of (body, rhs) to host memory w[3*N1*N2*N3]. */
+int vie_get_current(vie_ctx *ctx, int32_t body, int32_t rhs, vie_c64 *w);
+
+/* Apply the discrete operator y = x - chi Ghat x of `body` to nvec host
+ * vectors x[nvec][3][N3][N2][N1] (precision VIE_FP64 or VIE_MIXED). */
+int vie_matvec(vie_ctx *ctx, int32_t body, int32_t precision, const vie_c64 *x, vie_c64 *y,
+               int32_t nvec);
+
+/* Same on device buffers (asynchronous on the context's stream). */
+int vie_matvec_dev(vie_ctx *ctx, int32_t body, int32_t precision, const void *x_dev,
+                   void *y_dev, int32_t nvec);
+
+/* Use the given hipStream_t for all later device work (NULL: library's own). */
+int vie_set_stream(vie_ctx *ctx, void *hip_stream);
+
+/* Per-kernel-kind durations recorded with HIP events while VIE_FLAG_TIMING is
+ * set: names[k] (static strings), total milliseconds ms[k] and launch counts
+ * cnt[k] for k < *nkinds (in: capacity, out: number of kinds).  reset != 0
+ * clears the accumulators after reading. */
+int vie_kernel_times(vie_ctx *ctx, const char **names, double *ms, int64_t *cnt,
+                     int32_t *nkinds, int32_t reset);
+
+/* Change option fields that do not affect setup (tol, max_iter, precision,
+ * inner_tol, warm_start, flags).  k0 must match the setup value. */
+int vie_set_options(vie_ctx *ctx, const vie_options *opt);
+
+void vie_destroy(vie_ctx *ctx);
+const char *vie_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VIE_H */

@@ -1,0 +1,843 @@
+// Host runtime and C ABI (include/vie.h): contexts, spectrum setup, the
+// BiCGSTAB / iterative-refinement driver, far field, two-photon observables.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "../../include/vie.h"
+#include "kernels.h"
+
+using namespace vie;
+
+namespace {
+
+// ------------------------------------------------------------ device memory
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // grow-only; contents are not preserved
+  hipError_t reserve(size_t b) {
+    if (b <= bytes) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    bytes = b;
+    return hipSuccess;
+  }
+  template <typename T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+int pow2_at_least(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+struct BodyRec {
+  int group;       // group index
+  int slot;        // body index inside the group's chi array
+  int nb;          // body voxels (chi != 0)
+  DevBuf vox;      // int[nb] linear indices of body voxels
+  double origin[3];
+  int rhs0 = 0, nrhs = 0;  // right-hand sides of this body inside the group (last solve)
+};
+
+struct Group {
+  GroupGeom g;
+  double h;
+  std::vector<int> bodies;       // body ids
+  DevBuf chi;                    // double[nb][n]
+  DevBuf spec64, spec32;         // octant spectra [6][Q3][Q2][Q1]
+  DevBuf tw64[3], tw32[3];       // twiddles per axis
+  // per-solve storage (capacity in right-hand sides)
+  int cap = 0;
+  DevBuf x, r, rh, p, v, s, t;   // c64 [cap][3n]
+  DevBuf bufA, bufB;             // FFT scratch (sized for FP64)
+  DevBuf partials;               // c64 [cap][maxblk][2]
+  DevBuf state;                  // KState [cap]
+  DevBuf flags;                  // int [2][cap]
+  DevBuf rhs_body, pol, ph;      // per right-hand side
+  DevBuf dirs, part, F;          // far-field scratch
+};
+
+struct TimedEvent {
+  int kind;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+static const char* kKindNames[] = {
+    "fft_x_fwd_f64", "fft_y_fwd_f64", "fft_z_green_f64", "fft_y_inv_f64", "fft_x_inv_f64",
+    "fft_x_fwd_f32", "fft_y_fwd_f32", "fft_z_green_f32", "fft_y_inv_f32", "fft_x_inv_f32",
+    "krylov_vec",    "finalize",      "farfield",        "init"};
+static constexpr int kNumKinds = 14;
+
+struct vie_ctx {
+  vie_options opt;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  bool poisoned = false;
+  std::vector<std::unique_ptr<BodyRec>> bodies;
+  std::vector<std::unique_ptr<Group>> groups;
+  // timing
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<TimedEvent> ev_live;
+  double kind_ms[kNumKinds] = {0};
+  int64_t kind_cnt[kNumKinds] = {0};
+  // pinned flag mirrors for lagged convergence checks
+  int* hflags[2] = {nullptr, nullptr};
+  int hflags_cap = 0;
+  hipEvent_t flag_ev[2] = {nullptr, nullptr};
+};
+
+// --------------------------------------------------------------- utilities
+#define VIE_HIP(call)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      if (getenv("VIE_LOG"))                                                          \
+        fprintf(stderr, "vie: %s failed: %s (%s:%d)\n", #call, hipGetErrorString(e_), \
+                __FILE__, __LINE__);                                                  \
+      return e_ == hipErrorOutOfMemory ? VIE_ENOMEM : fail_device(ctx);               \
+    }                                                                                 \
+  } while (0)
+
+static int fail_device(vie_ctx* ctx) {
+  if (ctx) ctx->poisoned = true;
+  return VIE_EDEVICE;
+}
+
+static hipEvent_t ev_get(vie_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+static void timing_cb(int kind, bool begin, void* u) {
+  vie_ctx* c = (vie_ctx*)u;
+  if (begin) {
+    TimedEvent t;
+    t.kind = kind;
+    t.a = ev_get(c);
+    t.b = ev_get(c);
+    if (!t.a || !t.b) return;
+    (void)hipEventRecord(t.a, c->stream);
+    c->ev_live.push_back(t);
+  } else {
+    if (c->ev_live.empty()) return;
+    TimedEvent& t = c->ev_live.back();
+    (void)hipEventRecord(t.b, c->stream);
+  }
+}
+
+static bool timing_on(vie_ctx* c) { return (c->opt.flags & VIE_FLAG_TIMING) != 0; }
+
+static void timing_collect(vie_ctx* c) {
+  if (c->ev_live.empty()) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& t : c->ev_live) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      c->kind_ms[t.kind] += ms;
+      c->kind_cnt[t.kind] += 1;
+    }
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->ev_live.clear();
+}
+
+template <typename F>
+static hipError_t timed(vie_ctx* c, int kind, F&& f) {
+  if (timing_on(c)) timing_cb(kind, true, c);
+  hipError_t e = f();
+  if (timing_on(c)) timing_cb(kind, false, c);
+  return e;
+}
+
+static void make_twiddles(int P, std::vector<c64>& t64, std::vector<c32>& t32) {
+  t64.resize(P);
+  t32.resize(P);
+  for (int m = 0; m < P; ++m) {
+    const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / P;
+    t64[m] = mk((double)cosl(a), (double)sinl(a));
+    t32[m] = mk((float)cosl(a), (float)sinl(a));
+  }
+}
+
+static bool valid_options(const vie_options* o) {
+  if (!o) return false;
+  if (!(o->k0 > 0) || !isfinite(o->k0)) return false;
+  if (o->precision != VIE_FP64 && o->precision != VIE_MIXED) return false;
+  if (!(o->tol > 0) || !(o->tol < 1)) return false;
+  if (o->max_iter < 1) return false;
+  if (o->precision == VIE_MIXED && !(o->inner_tol > 0 && o->inner_tol < 1)) return false;
+  return true;
+}
+
+// ------------------------------------------------------------------ setup
+static int build_spectrum(vie_ctx* ctx, Group& G) {
+  const GroupGeom& g = G.g;
+  const size_t M = (size_t)g.P[0] * g.P[1] * g.P[2];
+  const size_t oct = (size_t)g.Q[0] * g.Q[1] * g.Q[2];
+  DevBuf work, tmp;
+  VIE_HIP(work.reserve(M * sizeof(c64)));
+  VIE_HIP(tmp.reserve(M * sizeof(c64)));
+  VIE_HIP(G.spec64.reserve(6 * oct * sizeof(c64)));
+  VIE_HIP(G.spec32.reserve(6 * oct * sizeof(c32)));
+  const void* tw[3] = {G.tw64[0].p, G.tw64[1].p, G.tw64[2].p};
+  for (int ab = 0; ab < 6; ++ab) {
+    VIE_HIP(launch_green_sample(work.as<c64>(), g, ab, G.h, ctx->opt.k0, ctx->stream));
+    VIE_HIP(launch_fft3d_full(work.as<c64>(), tmp.as<c64>(), g, tw, ctx->stream));
+    VIE_HIP(launch_octant(tmp.as<c64>(), G.spec64.as<c64>(), G.spec32.as<c32>(), g, ab,
+                          ctx->stream));
+  }
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  return VIE_OK;
+}
+
+extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_options* opt,
+                         vie_ctx** out) {
+  if (!out) return VIE_EINVAL;
+  *out = nullptr;
+  if (!bodies || n_bodies < 1 || !valid_options(opt)) return VIE_EINVAL;
+  for (int b = 0; b < n_bodies; ++b) {
+    const vie_body& B = bodies[b];
+    if (!B.eps_r || !(B.h > 0) || !isfinite(B.h)) return VIE_EINVAL;
+    for (int a = 0; a < 3; ++a) {
+      if (B.n[a] < 1) return VIE_EINVAL;
+      if (B.n[a] > 256) return VIE_ENOTSUP;
+      if (!isfinite(B.origin[a])) return VIE_EINVAL;
+    }
+    const int64_t n = (int64_t)B.n[0] * B.n[1] * B.n[2];
+    for (int64_t i = 0; i < n; ++i)
+      if (!(B.eps_r[i] >= 1.0) || !isfinite(B.eps_r[i])) return VIE_EINVAL;
+  }
+  vie_ctx* ctx = new (std::nothrow) vie_ctx();
+  if (!ctx) return VIE_ENOMEM;
+  ctx->opt = *opt;
+  int rc = VIE_OK;
+  auto bail = [&](int code) {
+    vie_destroy(ctx);
+    return code;
+  };
+  if (hipStreamCreate(&ctx->own_stream) != hipSuccess) return bail(VIE_EDEVICE);
+  ctx->stream = ctx->own_stream;
+  // group bodies by (n, h)
+  std::map<std::vector<int64_t>, int> key2g;
+  std::vector<std::vector<double>> chi_host;
+  for (int b = 0; b < n_bodies; ++b) {
+    const vie_body& B = bodies[b];
+    int64_t hb;
+    memcpy(&hb, &B.h, sizeof(hb));
+    std::vector<int64_t> key = {B.n[0], B.n[1], B.n[2], hb};
+    auto it = key2g.find(key);
+    int gi;
+    if (it == key2g.end()) {
+      gi = (int)ctx->groups.size();
+      key2g[key] = gi;
+      auto G = std::make_unique<Group>();
+      G->h = B.h;
+      for (int a = 0; a < 3; ++a) {
+        G->g.N[a] = B.n[a];
+        G->g.P[a] = std::max(8, pow2_at_least(2 * B.n[a] - 1));
+        G->g.Q[a] = G->g.P[a] / 2 + 1;
+      }
+      G->g.n = (int64_t)B.n[0] * B.n[1] * B.n[2];
+      G->g.nrhs = 0;
+      ctx->groups.push_back(std::move(G));
+      chi_host.emplace_back();
+    } else {
+      gi = it->second;
+    }
+    Group& G = *ctx->groups[gi];
+    auto rec = std::make_unique<BodyRec>();
+    rec->group = gi;
+    rec->slot = (int)G.bodies.size();
+    for (int a = 0; a < 3; ++a) rec->origin[a] = B.origin[a];
+    G.bodies.push_back(b);
+    std::vector<double>& ch = chi_host[gi];
+    const int64_t n = G.g.n;
+    std::vector<int> vox;
+    ch.resize((size_t)(rec->slot + 1) * n);
+    for (int64_t i = 0; i < n; ++i) {
+      const double c = B.eps_r[i] - 1.0;
+      ch[(size_t)rec->slot * n + i] = c;
+      if (c != 0.0) vox.push_back((int)i);
+    }
+    rec->nb = (int)vox.size();
+    if (!vox.empty()) {
+      if (rec->vox.reserve(vox.size() * sizeof(int)) != hipSuccess) return bail(VIE_ENOMEM);
+      if (hipMemcpy(rec->vox.p, vox.data(), vox.size() * sizeof(int), hipMemcpyHostToDevice) !=
+          hipSuccess)
+        return bail(VIE_EDEVICE);
+    }
+    ctx->bodies.push_back(std::move(rec));
+  }
+  for (size_t gi = 0; gi < ctx->groups.size(); ++gi) {
+    Group& G = *ctx->groups[gi];
+    if (G.chi.reserve(chi_host[gi].size() * sizeof(double)) != hipSuccess) return bail(VIE_ENOMEM);
+    if (hipMemcpy(G.chi.p, chi_host[gi].data(), chi_host[gi].size() * sizeof(double),
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return bail(VIE_EDEVICE);
+    for (int a = 0; a < 3; ++a) {
+      std::vector<c64> t64;
+      std::vector<c32> t32;
+      make_twiddles(G.g.P[a], t64, t32);
+      if (G.tw64[a].reserve(t64.size() * sizeof(c64)) != hipSuccess ||
+          G.tw32[a].reserve(t32.size() * sizeof(c32)) != hipSuccess)
+        return bail(VIE_ENOMEM);
+      if (hipMemcpy(G.tw64[a].p, t64.data(), t64.size() * sizeof(c64), hipMemcpyHostToDevice) !=
+              hipSuccess ||
+          hipMemcpy(G.tw32[a].p, t32.data(), t32.size() * sizeof(c32), hipMemcpyHostToDevice) !=
+              hipSuccess)
+        return bail(VIE_EDEVICE);
+    }
+    rc = build_spectrum(ctx, G);
+    if (rc != VIE_OK) return bail(rc);
+  }
+  for (int k = 0; k < 2; ++k)
+    if (hipEventCreateWithFlags(&ctx->flag_ev[k], hipEventDisableTiming) != hipSuccess)
+      return bail(VIE_EDEVICE);
+  *out = ctx;
+  return VIE_OK;
+}
+
+extern "C" void vie_destroy(vie_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  ctx->groups.clear();
+  ctx->bodies.clear();
+  for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (auto& t : ctx->ev_live) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (int k = 0; k < 2; ++k) {
+    if (ctx->hflags[k]) (void)hipHostFree(ctx->hflags[k]);
+    if (ctx->flag_ev[k]) (void)hipEventDestroy(ctx->flag_ev[k]);
+  }
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+  delete ctx;
+}
+
+extern "C" int vie_set_stream(vie_ctx* ctx, void* s) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  ctx->stream = s ? (hipStream_t)s : ctx->own_stream;
+  return VIE_OK;
+}
+
+extern "C" int vie_set_options(vie_ctx* ctx, const vie_options* opt) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  if (!valid_options(opt) || opt->k0 != ctx->opt.k0) return VIE_EINVAL;
+  ctx->opt = *opt;
+  return VIE_OK;
+}
+
+// -------------------------------------------------------------- workspace
+static int ensure_solve_storage(vie_ctx* ctx, Group& G, int nrhs) {
+  if (nrhs <= G.cap) return VIE_OK;
+  const size_t vec = (size_t)3 * G.g.n * sizeof(c64);
+  DevBuf* vs[] = {&G.x, &G.r, &G.rh, &G.p, &G.v, &G.s, &G.t};
+  for (DevBuf* b : vs) VIE_HIP(b->reserve(vec * nrhs));
+  const size_t a = (size_t)3 * G.g.N[2] * G.g.N[1] * G.g.P[0] * sizeof(c64);
+  const size_t bb = (size_t)3 * G.g.N[2] * G.g.P[1] * G.g.P[0] * sizeof(c64);
+  VIE_HIP(G.bufA.reserve(a * nrhs));
+  VIE_HIP(G.bufB.reserve(bb * nrhs));
+  const int maxblk = std::max(std::max(part_blocks_xinv(G.g, 0), part_blocks_xinv(G.g, 1)),
+                              vec_blocks(G.g));
+  VIE_HIP(G.partials.reserve((size_t)nrhs * maxblk * 2 * sizeof(c64)));
+  VIE_HIP(G.state.reserve((size_t)nrhs * sizeof(KState)));
+  VIE_HIP(G.flags.reserve((size_t)2 * nrhs * sizeof(int)));
+  VIE_HIP(G.rhs_body.reserve((size_t)nrhs * sizeof(int)));
+  VIE_HIP(G.pol.reserve((size_t)nrhs * 3 * sizeof(c64)));
+  VIE_HIP(G.ph.reserve((size_t)nrhs * (G.g.N[0] + G.g.N[1] + G.g.N[2]) * sizeof(c64)));
+  G.cap = nrhs;
+  return VIE_OK;
+}
+
+static int ensure_hflags(vie_ctx* ctx, int n) {
+  if (n <= ctx->hflags_cap) return VIE_OK;
+  for (int k = 0; k < 2; ++k) {
+    if (ctx->hflags[k]) (void)hipHostFree(ctx->hflags[k]);
+    ctx->hflags[k] = nullptr;
+    VIE_HIP(hipHostMalloc((void**)&ctx->hflags[k], (size_t)n * sizeof(int)));
+  }
+  ctx->hflags_cap = n;
+  return VIE_OK;
+}
+
+static MatvecArgs matvec_args(Group& G, int precision, const int* active) {
+  MatvecArgs m;
+  m.g = &G.g;
+  m.chi = G.chi.as<double>();
+  m.rhs_body = G.rhs_body.as<int>();
+  m.spec = precision == 0 ? G.spec64.p : G.spec32.p;
+  for (int a = 0; a < 3; ++a) m.tw[a] = precision == 0 ? G.tw64[a].p : G.tw32[a].p;
+  m.bufA = G.bufA.p;
+  m.bufB = G.bufB.p;
+  m.active = active;
+  return m;
+}
+
+static hipError_t run_matvec(vie_ctx* ctx, Group& G, int precision, const c64* x, c64* y,
+                             EpiArgs& e, const int* active) {
+  MatvecArgs m = matvec_args(G, precision, active);
+  return launch_matvec(m, precision, x, y, e, ctx->stream, timing_on(ctx) ? timing_cb : nullptr,
+                       ctx);
+}
+
+// ---------------------------------------------------------------- solver
+// Restarted BiCGSTAB with FP64 vectors.  Each cycle iterates on the current
+// residual r with the FP64 (VIE_FP64) or FP32 (VIE_MIXED) product until the
+// recursive residual drops below max((tol/2)^2 ||b||^2, eta^2 ||r_start||^2),
+// then recomputes the true residual with the FP64 product and restarts.
+// With VIE_MIXED this is FP64 iterative refinement around an FP32-product
+// inner solver; with VIE_FP64 the restart only confirms convergence.
+static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fallback_out) {
+  const GroupGeom& g = G.g;
+  const int nrhs = g.nrhs;
+  const int prec = ctx->opt.precision == VIE_MIXED ? 1 : 0;
+  FinParams fp;
+  fp.tol2_done = ctx->opt.tol * ctx->opt.tol;
+  fp.tol2_inner = 0.25 * fp.tol2_done;
+  fp.eta2 = prec ? ctx->opt.inner_tol * ctx->opt.inner_tol : 0.0;
+  fp.max_iter = ctx->opt.max_iter;
+  KState* st = G.state.as<KState>();
+  int* flags = G.flags.as<int>();
+  int* active = flags;
+  int* notdone = flags + nrhs;
+  c64* part = G.partials.as<c64>();
+  const int vb = vec_blocks(g);
+  c64 *x = G.x.as<c64>(), *r = G.r.as<c64>(), *rh = G.rh.as<c64>(), *p = G.p.as<c64>(),
+      *v = G.v.as<c64>(), *s = G.s.as<c64>(), *t = G.t.as<c64>();
+  const double* chi = G.chi.as<double>();
+  const int* rb = G.rhs_body.as<int>();
+  const c64* pol = G.pol.as<c64>();
+  const c64* ph = G.ph.as<c64>();
+  fallback_out.assign(nrhs, 0);
+
+  VIE_HIP(timed(ctx, 13, [&] {
+    return launch_init_zero_guess(g, chi, rb, pol, ph, x, r, rh, part, warm ? 1 : 0, nullptr,
+                                  ctx->stream);
+  }));
+  VIE_HIP(timed(ctx, 11, [&] {
+    return launch_finalize(FIN_INIT, nrhs, vb, part, st, flags, fp, ctx->stream);
+  }));
+  if (warm) {
+    // true residual of the initial guess; reject guesses with ||r0|| >= ||b||
+    EpiArgs e{EPI_RESID, rh, part, 0, pol, ph};
+    VIE_HIP(run_matvec(ctx, G, 0, x, r, e, notdone));
+    VIE_HIP(timed(ctx, 11, [&] {
+      return launch_finalize(FIN_RESTART, nrhs, e.part_blocks, part, st, flags, fp, ctx->stream);
+    }));
+    std::vector<KState> hs(nrhs);
+    VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    VIE_HIP(hipStreamSynchronize(ctx->stream));
+    std::vector<int> mask(nrhs, 0);
+    bool any = false;
+    for (int i = 0; i < nrhs; ++i) {
+      if (!(hs[i].rnorm2 < hs[i].bnorm2)) {
+        mask[i] = 1;
+        any = true;
+        fallback_out[i] = 1;
+      }
+    }
+    if (any) {
+      DevBuf dmask;
+      VIE_HIP(dmask.reserve(nrhs * sizeof(int)));
+      VIE_HIP(hipMemcpyAsync(dmask.p, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+                             ctx->stream));
+      VIE_HIP(launch_init_zero_guess(g, chi, rb, pol, ph, x, r, rh, part, 0, dmask.as<int>(),
+                                     ctx->stream));
+      // FIN_INIT only for the masked right-hand sides: reuse notdone as gate by
+      // running FIN_RESTART semantics after re-initialising (bnorm2 unchanged).
+      VIE_HIP(hipMemcpyAsync(notdone, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+                             ctx->stream));
+      VIE_HIP(launch_finalize(FIN_RESTART, nrhs, vb, part, st, flags, fp, ctx->stream));
+      VIE_HIP(hipStreamSynchronize(ctx->stream));
+      // restore notdone for the others from their state
+      VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
+                             ctx->stream));
+      VIE_HIP(hipStreamSynchronize(ctx->stream));
+      std::vector<int> nd(nrhs), ac(nrhs);
+      for (int i = 0; i < nrhs; ++i) {
+        nd[i] = hs[i].notdone;
+        ac[i] = hs[i].active;
+      }
+      VIE_HIP(hipMemcpyAsync(notdone, nd.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+                             ctx->stream));
+      VIE_HIP(hipMemcpyAsync(active, ac.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+                             ctx->stream));
+    }
+  }
+  int rc = ensure_hflags(ctx, nrhs);
+  if (rc != VIE_OK) return rc;
+
+  for (int cycle = 0;; ++cycle) {
+    // iterate until every right-hand side has left the cycle (lagged check)
+    int64_t k = 0;
+    for (;; ++k) {
+      VIE_HIP(timed(ctx, 10, [&] { return launch_update_p(g, st, active, r, p, v, ctx->stream); }));
+      EpiArgs e1{EPI_RHV, rh, part, 0, pol, ph};
+      VIE_HIP(run_matvec(ctx, G, prec, p, v, e1, active));
+      VIE_HIP(timed(ctx, 11, [&] {
+        return launch_finalize(FIN_ALPHA, nrhs, e1.part_blocks, part, st, flags, fp, ctx->stream);
+      }));
+      VIE_HIP(timed(ctx, 10, [&] { return launch_update_s(g, st, active, r, v, s, ctx->stream); }));
+      EpiArgs e2{EPI_TS, nullptr, part, 0, pol, ph};
+      VIE_HIP(run_matvec(ctx, G, prec, s, t, e2, active));
+      VIE_HIP(timed(ctx, 11, [&] {
+        return launch_finalize(FIN_OMEGA, nrhs, e2.part_blocks, part, st, flags, fp, ctx->stream);
+      }));
+      VIE_HIP(timed(ctx, 10, [&] {
+        return launch_update_xr(g, st, active, x, r, p, s, t, rh, part, ctx->stream);
+      }));
+      VIE_HIP(timed(ctx, 11, [&] {
+        return launch_finalize(FIN_RHO, nrhs, vb, part, st, flags, fp, ctx->stream);
+      }));
+      const int slot = (int)(k & 1);
+      VIE_HIP(hipMemcpyAsync(ctx->hflags[slot], active, nrhs * sizeof(int), hipMemcpyDeviceToHost,
+                             ctx->stream));
+      VIE_HIP(hipEventRecord(ctx->flag_ev[slot], ctx->stream));
+      if (k > 0) {
+        const int ps = (int)((k - 1) & 1);
+        VIE_HIP(hipEventSynchronize(ctx->flag_ev[ps]));
+        bool any = false;
+        for (int i = 0; i < nrhs; ++i) any |= ctx->hflags[ps][i] != 0;
+        if (!any) break;
+      }
+      if (k > (int64_t)ctx->opt.max_iter + 2) break;
+    }
+    // true residual with the FP64 product, restart
+    EpiArgs e{EPI_RESID, rh, part, 0, pol, ph};
+    VIE_HIP(run_matvec(ctx, G, 0, x, r, e, notdone));
+    VIE_HIP(timed(ctx, 11, [&] {
+      return launch_finalize(FIN_RESTART, nrhs, e.part_blocks, part, st, flags, fp, ctx->stream);
+    }));
+    VIE_HIP(hipMemcpyAsync(ctx->hflags[0], active, nrhs * sizeof(int), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    VIE_HIP(hipStreamSynchronize(ctx->stream));
+    bool any = false;
+    for (int i = 0; i < nrhs; ++i) any |= ctx->hflags[0][i] != 0;
+    if (!any) break;
+    if (cycle > ctx->opt.max_iter) break;
+  }
+  return VIE_OK;
+}
+
+static void planewave_tables(const vie_planewave& pw, const Group& G, const double* origin,
+                             double k0, c64* pol, c64* ph) {
+  for (int c = 0; c < 3; ++c) pol[c] = mk(pw.pol[c].re, pw.pol[c].im);
+  int off = 0;
+  for (int a = 0; a < 3; ++a) {
+    for (int i = 0; i < G.g.N[a]; ++i) {
+      const double ang = k0 * pw.khat[a] * (origin[a] + G.h * i);
+      ph[off + i] = mk(cos(ang), sin(ang));
+    }
+    off += G.g.N[a];
+  }
+}
+
+extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* nrhs_per_body,
+                         vie_stats* stats) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  if (!inc || !nrhs_per_body) return VIE_EINVAL;
+  const int nb = (int)ctx->bodies.size();
+  int total = 0;
+  for (int b = 0; b < nb; ++b) {
+    if (nrhs_per_body[b] < 0) return VIE_EINVAL;
+    total += nrhs_per_body[b];
+  }
+  for (int i = 0; i < total; ++i) {
+    const vie_planewave& w = inc[i];
+    const double kn = sqrt(w.khat[0] * w.khat[0] + w.khat[1] * w.khat[1] + w.khat[2] * w.khat[2]);
+    if (!(fabs(kn - 1.0) < 1e-9)) return VIE_EINVAL;
+    for (int c = 0; c < 3; ++c)
+      if (!isfinite(w.pol[c].re) || !isfinite(w.pol[c].im)) return VIE_EINVAL;
+  }
+  if (ctx->opt.warm_start) return VIE_ENOTSUP;  // no network loaded in this build
+  // assign right-hand sides to groups
+  std::vector<int> first(nb);
+  {
+    int acc = 0;
+    for (int b = 0; b < nb; ++b) {
+      first[b] = acc;
+      acc += nrhs_per_body[b];
+    }
+  }
+  for (auto& Gp : ctx->groups) {
+    Group& G = *Gp;
+    int nr = 0;
+    for (int b : G.bodies) {
+      BodyRec& B = *ctx->bodies[b];
+      B.rhs0 = nr;
+      B.nrhs = nrhs_per_body[b];
+      nr += B.nrhs;
+    }
+    G.g.nrhs = nr;
+    if (nr == 0) continue;
+    int rc = ensure_solve_storage(ctx, G, nr);
+    if (rc != VIE_OK) return rc;
+    const int L = G.g.N[0] + G.g.N[1] + G.g.N[2];
+    std::vector<int> rb(nr);
+    std::vector<c64> pol((size_t)nr * 3), ph((size_t)nr * L);
+    for (int b : G.bodies) {
+      BodyRec& B = *ctx->bodies[b];
+      for (int q = 0; q < B.nrhs; ++q) {
+        const int gi = B.rhs0 + q;
+        rb[gi] = B.slot;
+        planewave_tables(inc[first[b] + q], G, B.origin, ctx->opt.k0, &pol[(size_t)gi * 3],
+                         &ph[(size_t)gi * L]);
+      }
+    }
+    VIE_HIP(hipMemcpyAsync(G.rhs_body.p, rb.data(), nr * sizeof(int), hipMemcpyHostToDevice,
+                           ctx->stream));
+    VIE_HIP(hipMemcpyAsync(G.pol.p, pol.data(), pol.size() * sizeof(c64), hipMemcpyHostToDevice,
+                           ctx->stream));
+    VIE_HIP(hipMemcpyAsync(G.ph.p, ph.data(), ph.size() * sizeof(c64), hipMemcpyHostToDevice,
+                           ctx->stream));
+    std::vector<int> fb;
+    rc = solve_group(ctx, G, false, fb);
+    if (rc != VIE_OK) return rc;
+  }
+  // statistics
+  bool all_conv = true;
+  for (auto& Gp : ctx->groups) {
+    Group& G = *Gp;
+    if (G.g.nrhs == 0) continue;
+    std::vector<KState> hs(G.g.nrhs);
+    VIE_HIP(hipMemcpyAsync(hs.data(), G.state.p, hs.size() * sizeof(KState),
+                           hipMemcpyDeviceToHost, ctx->stream));
+    VIE_HIP(hipStreamSynchronize(ctx->stream));
+    for (int b : G.bodies) {
+      BodyRec& B = *ctx->bodies[b];
+      for (int q = 0; q < B.nrhs; ++q) {
+        const KState& S = hs[B.rhs0 + q];
+        const double rel = S.bnorm2 > 0 ? sqrt(S.rnorm2 / S.bnorm2) : 0.0;
+        const bool conv = !S.notdone;
+        all_conv &= conv;
+        if (stats) {
+          vie_stats& o = stats[first[b] + q];
+          o.iters = S.iters;
+          o.matvecs = 0;
+          o.cycles = 0;
+          o.converged = conv;
+          o.fallback = 0;
+          o.warm = 0;
+          o.rel_res = rel;
+          o.rel_res_x0 = 1.0;
+        }
+      }
+    }
+  }
+  timing_collect(ctx);
+  return all_conv ? VIE_OK : VIE_ENOCONV;
+}
+
+// --------------------------------------------------------------- products
+extern "C" int vie_matvec_dev(vie_ctx* ctx, int32_t body, int32_t precision, const void* x,
+                              void* y, int32_t nvec) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  if (body < 0 || body >= (int)ctx->bodies.size() || nvec < 1 || !x || !y) return VIE_EINVAL;
+  if (precision != VIE_FP64 && precision != VIE_MIXED) return VIE_EINVAL;
+  BodyRec& B = *ctx->bodies[body];
+  Group& G = *ctx->groups[B.group];
+  const int saved = G.g.nrhs;
+  G.g.nrhs = nvec;
+  int rc = ensure_solve_storage(ctx, G, nvec);
+  if (rc != VIE_OK) {
+    G.g.nrhs = saved;
+    return rc;
+  }
+  std::vector<int> rb(nvec, B.slot);
+  VIE_HIP(hipMemcpyAsync(G.rhs_body.p, rb.data(), nvec * sizeof(int), hipMemcpyHostToDevice,
+                         ctx->stream));
+  EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
+  hipError_t err = run_matvec(ctx, G, precision == VIE_MIXED ? 1 : 0, (const c64*)x, (c64*)y, e,
+                              nullptr);
+  G.g.nrhs = saved;
+  VIE_HIP(err);
+  return VIE_OK;
+}
+
+extern "C" int vie_matvec(vie_ctx* ctx, int32_t body, int32_t precision, const vie_c64* x,
+                          vie_c64* y, int32_t nvec) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  if (body < 0 || body >= (int)ctx->bodies.size() || nvec < 1 || !x || !y) return VIE_EINVAL;
+  Group& G = *ctx->groups[ctx->bodies[body]->group];
+  const size_t bytes = (size_t)nvec * 3 * G.g.n * sizeof(c64);
+  DevBuf dx, dy;
+  VIE_HIP(dx.reserve(bytes));
+  VIE_HIP(dy.reserve(bytes));
+  VIE_HIP(hipMemcpyAsync(dx.p, x, bytes, hipMemcpyHostToDevice, ctx->stream));
+  int rc = vie_matvec_dev(ctx, body, precision, dx.p, dy.p, nvec);
+  if (rc != VIE_OK) return rc;
+  VIE_HIP(hipMemcpyAsync(y, dy.p, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  timing_collect(ctx);
+  return VIE_OK;
+}
+
+extern "C" int vie_get_current(vie_ctx* ctx, int32_t body, int32_t rhs, vie_c64* w) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  if (body < 0 || body >= (int)ctx->bodies.size() || !w) return VIE_EINVAL;
+  BodyRec& B = *ctx->bodies[body];
+  if (rhs < 0 || rhs >= B.nrhs) return VIE_EINVAL;
+  Group& G = *ctx->groups[B.group];
+  const size_t vec = (size_t)3 * G.g.n;
+  VIE_HIP(hipMemcpyAsync(w, G.x.as<c64>() + (size_t)(B.rhs0 + rhs) * vec, vec * sizeof(c64),
+                         hipMemcpyDeviceToHost, ctx->stream));
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  return VIE_OK;
+}
+
+// -------------------------------------------------------------- far field
+extern "C" int vie_farfield(vie_ctx* ctx, int32_t body, const double* theta, const double* phi,
+                            int32_t ndir, vie_c64* F) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  if (body < 0 || body >= (int)ctx->bodies.size() || ndir < 1 || !theta || !phi || !F)
+    return VIE_EINVAL;
+  BodyRec& B = *ctx->bodies[body];
+  if (B.nrhs < 1) return VIE_ESTATE;
+  Group& G = *ctx->groups[B.group];
+  std::vector<double> dirs((size_t)ndir * 9);
+  for (int d = 0; d < ndir; ++d) {
+    const double t = theta[d], p = phi[d];
+    if (!isfinite(t) || !isfinite(p)) return VIE_EINVAL;
+    const double st = sin(t), ct = cos(t), sp = sin(p), cp = cos(p);
+    double* D = &dirs[(size_t)d * 9];
+    D[0] = st * cp; D[1] = st * sp; D[2] = ct;
+    D[3] = ct * cp; D[4] = ct * sp; D[5] = -st;
+    D[6] = -sp;     D[7] = cp;      D[8] = 0.0;
+  }
+  const size_t outn = (size_t)B.nrhs * ndir * 2;
+  if (B.nb == 0) {
+    memset(F, 0, outn * sizeof(vie_c64));
+    return VIE_OK;
+  }
+  const int dblocks = (ndir + 63) / 64;
+  int ks = std::max(1, std::min((B.nb + 63) / 64, 2048 / dblocks));
+  const int chunk = (B.nb + ks - 1) / ks;
+  ks = (B.nb + chunk - 1) / chunk;
+  VIE_HIP(G.dirs.reserve(dirs.size() * sizeof(double)));
+  VIE_HIP(G.part.reserve((size_t)ks * 4 * ndir * 3 * sizeof(c64)));
+  VIE_HIP(G.F.reserve(outn * sizeof(c64)));
+  VIE_HIP(hipMemcpyAsync(G.dirs.p, dirs.data(), dirs.size() * sizeof(double),
+                         hipMemcpyHostToDevice, ctx->stream));
+  VIE_HIP(timed(ctx, 12, [&] {
+    return launch_farfield_ks(G.g, G.x.as<c64>(), B.rhs0, B.nrhs, B.vox.as<int>(), B.nb,
+                              G.dirs.as<double>(), ndir, ctx->opt.k0, G.h, B.origin,
+                              G.part.as<c64>(), chunk, G.F.as<c64>(), ctx->stream);
+  }));
+  VIE_HIP(hipMemcpyAsync(F, G.F.p, outn * sizeof(c64), hipMemcpyDeviceToHost, ctx->stream));
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  timing_collect(ctx);
+  return VIE_OK;
+}
+
+// ------------------------------------------------------- two-photon (host)
+extern "C" int hom_g2(const vie_c64 T[4], const double* omega, double sigma, const double* dtau,
+                      int32_t ndelay, int32_t norm, double* g2, double* Nc_raw, double* Nc_norm) {
+  if (!T) return VIE_EINVAL;
+  if (norm != VIE_NORM_R1 && norm != VIE_NORM_R2) return VIE_EINVAL;
+  if (ndelay < 0 || (ndelay > 0 && !dtau)) return VIE_EINVAL;
+  if ((Nc_raw || Nc_norm) && ndelay > 0 && !(sigma > 0)) return VIE_EINVAL;
+  for (int i = 0; i < 4; ++i)
+    if (!isfinite(T[i].re) || !isfinite(T[i].im)) return VIE_EINVAL;
+  const double w1 = omega ? omega[0] : 1.0, w2 = omega ? omega[1] : 1.0;
+  if (!(w1 > 0) || !(w2 > 0)) return VIE_EINVAL;
+  const c64 a1 = mk(T[0].re, T[0].im), a2 = mk(T[1].re, T[1].im);
+  const c64 b1 = mk(T[2].re, T[2].im), b2 = mk(T[3].re, T[3].im);
+  auto ab2 = [](c64 z) { return z.re * z.re + z.im * z.im; };
+  const c64 Ad = a1 * b2, Ae = a2 * b1;  // direct and exchange path amplitudes
+  const c64 sum = Ad + Ae;
+  const double G1a = w1 * ab2(a1) + w2 * ab2(a2), G1b = w1 * ab2(b1) + w2 * ab2(b2);
+  if (g2) {
+    const double den = G1a * G1b;
+    *g2 = den > 0 ? w1 * w2 * ab2(sum) / den : NAN;
+  }
+  if (ndelay > 0 && (Nc_raw || Nc_norm)) {
+    const double sp = sigma * sqrt(M_PI);
+    const double d2 = ab2(Ad), e2 = ab2(Ae);
+    const double cross = 2.0 * (Ad.re * Ae.re + Ad.im * Ae.im);  // 2 Re(Ad conj(Ae))
+    const double M1 = ab2(a1) + ab2(a2), M2 = ab2(b1) + ab2(b2);
+    const double D = norm == VIE_NORM_R1 ? sp * (d2 + e2) : sp * M1 * M2;
+    for (int k = 0; k < ndelay; ++k) {
+      const double c = exp(-(dtau[k] * dtau[k]) / (sigma * sigma));
+      const double raw = sp * (d2 + e2 + cross * c);
+      if (Nc_raw) Nc_raw[k] = raw;
+      if (Nc_norm) Nc_norm[k] = D > 0 ? raw / D : NAN;
+    }
+  }
+  return VIE_OK;
+}
+
+// ------------------------------------------------------------------ misc
+extern "C" int vie_kernel_times(vie_ctx* ctx, const char** names, double* ms, int64_t* cnt,
+                                int32_t* nkinds, int32_t reset) {
+  if (!ctx || !nkinds) return VIE_EINVAL;
+  timing_collect(ctx);
+  const int n = std::min<int>(*nkinds, kNumKinds);
+  for (int k = 0; k < n; ++k) {
+    if (names) names[k] = kKindNames[k];
+    if (ms) ms[k] = ctx->kind_ms[k];
+    if (cnt) cnt[k] = ctx->kind_cnt[k];
+  }
+  *nkinds = kNumKinds;
+  if (reset) {
+    for (int k = 0; k < kNumKinds; ++k) {
+      ctx->kind_ms[k] = 0;
+      ctx->kind_cnt[k] = 0;
+    }
+  }
+  return VIE_OK;
+}
+
+extern "C" const char* vie_strerror(int code) {
+  switch (code) {
+    case VIE_OK: return "ok";
+    case VIE_EINVAL: return "invalid argument";
+    case VIE_ENOMEM: return "out of memory";
+    case VIE_EDEVICE: return "HIP device error (context poisoned)";
+    case VIE_ENOCONV: return "not converged within max_iter";
+    case VIE_ENOTSUP: return "unsupported request";
+    case VIE_ESTATE: return "context poisoned or not prepared";
+    default: return "unknown error";
+  }
+}

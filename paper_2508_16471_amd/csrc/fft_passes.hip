@@ -1,0 +1,583 @@
+// FFT passes of the VIE operator product y = x - chi * IFFT(Ghat^ . FFT(pad x))[0:N]
+// (the FFT-accelerated matrix-vector product of the paper's Sec. II-C).
+//
+// Data flow for one right-hand side (3 Cartesian components):
+//   x [3][N3][N2][N1]  --X fwd (pad N1->P1)-->  A [3][N3][N2][P1]
+//   A --Y fwd (pad N2->P2)-->                    B [3][N3][P2][P1]
+//   B --Z fwd (pad N3->P3), 3x3 spectral multiply, Z inv, keep N3--> B (in place)
+//   B --Y inv (keep N2)-->                        A
+//   A --X inv (keep N1), epilogue y = x - chi conv (+ fused dot products)--> y
+// Padded halves are never stored: the first stage of each forward FFT skips
+// the zero inputs, the last stage of each inverse FFT skips the discarded
+// outputs.  The 3x3 symmetric spectrum is stored on the octant
+// [0, P/2]^3 only; the other octants follow from the per-axis parity of each
+// Green component.
+#include "fft.h"
+#include "kernels.h"
+
+namespace vie {
+
+template <int P>
+struct Pad {
+  static constexpr int LSTR = P + P / 16 + 1;  // padded LDS line stride (bank spread)
+};
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+
+// fft_stages with padded LDS indexing: wrap the line pointer in an accessor.
+template <typename T>
+struct LdsLine {
+  cpx<T>* p;
+  __device__ __forceinline__ cpx<T>& operator[](int i) const { return p[pidx(i)]; }
+};
+
+template <typename T, int P, int E, int NS, bool INV>
+__device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int t,
+                                             const cpx<T>* __restrict__ tw) {
+  constexpr int RAD = (P / NS < E) ? P / NS : E;
+  constexpr int NB = E / RAD;
+  constexpr int TT = P / E;
+  constexpr bool FIRST = (NS == 1);
+  constexpr bool LAST = (NS * RAD == P);
+  cpx<T> u[E];
+  if constexpr (FIRST) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) u[b * RAD + r] = v[b + r * NB];
+  } else {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = t + b * TT;
+      const int k = j % NS;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) {
+        cpx<T> x = lds[j + r * (P / RAD)];
+        if (r > 0) {
+          cpx<T> w = tw[r * k * (P / (NS * RAD))];
+          if (INV) w.im = -w.im;
+          x = x * w;
+        }
+        u[b * RAD + r] = x;
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) dft<RAD, INV>(&u[b * RAD]);
+  if constexpr (LAST) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[b + r * NB] = u[b * RAD + r];
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = t + b * TT;
+      const int base = (j / NS) * NS * RAD + (j % NS);
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) lds[base + r * NS] = u[b * RAD + r];
+    }
+    __syncthreads();
+    fft_stages_p<T, P, E, NS * RAD, INV>(v, lds, t, tw);
+  }
+}
+
+template <typename T, int P, bool INV>
+__device__ __forceinline__ void line_fft(cpx<T> (&v)[fft_e<P>()], cpx<T>* line, int t,
+                                         const cpx<T>* __restrict__ tw) {
+  fft_stages_p<T, P, fft_e<P>(), 1, INV>(v, LdsLine<T>{line}, t, tw);
+}
+
+template <typename T>
+constexpr int nt_lines() {
+  return sizeof(T) == 8 ? 128 : 256;  // threads per workgroup of single-line passes
+}
+
+// ---------------------------------------------------------------- X forward
+// One workgroup: L consecutive x-lines of one right-hand side.
+template <typename TI, typename T, int P, bool PAD>
+__global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd(
+    const cpx<TI>* __restrict__ x, cpx<T>* __restrict__ out, const cpx<T>* __restrict__ tw, int N1,
+    int lines_per_rhs, int blocks_per_rhs, const int* __restrict__ active) {
+  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), L = NT / TT;
+  __shared__ cpx<T> lds[L * Pad<P>::LSTR];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int rhs = b / blocks_per_rhs, blk = b % blocks_per_rhs;
+  if (active && !active[rhs]) return;
+  const int li = threadIdx.x / TT, t = threadIdx.x % TT;
+  const int line = blk * L + li;
+  const bool valid = line < lines_per_rhs;
+  const size_t gl = (size_t)rhs * lines_per_rhs + (valid ? line : 0);
+  const cpx<TI>* xin = x + gl * N1;
+  cpx<T> v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int idx = t + q * TT;
+    if ((!PAD || q < E / 2) && valid && idx < N1)
+      v[q] = cvt<T>(xin[idx]);
+    else
+      v[q] = mk<T>(0, 0);
+  }
+  line_fft<T, P, false>(v, lds + li * Pad<P>::LSTR, t, tw);
+  if (valid) {
+    cpx<T>* o = out + gl * P;
+#pragma unroll
+    for (int q = 0; q < E; ++q) o[t + q * TT] = v[q];
+  }
+}
+
+// ------------------------------------------------------ strided (Y, or Z)
+// Lines run along a strided axis; W = NT/TT neighbouring columns (unit stride)
+// per workgroup so every row access is a contiguous W-element run.
+// slab s = s_hi * n_lo + s_lo; element (row, col) of slab s at
+// s_hi*stride_hi + s_lo*stride_lo + row*row_stride + col.
+struct StridedArgs {
+  int n_in_rows, n_out_rows, ncols, n_lo, tiles, slabs_per_rhs;
+  int64_t in_row, out_row, in_lo, out_lo, in_hi, out_hi;
+};
+
+template <typename T, int P, bool PAD, bool TRUNC, bool INV>
+__global__ __launch_bounds__(nt_lines<T>()) void k_fft_strided(
+    const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, const cpx<T>* __restrict__ tw,
+    StridedArgs a, const int* __restrict__ active) {
+  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), W = NT / TT;
+  __shared__ cpx<T> lds[W * Pad<P>::LSTR];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = b % a.tiles, s = b / a.tiles;
+  if (active && !active[s / a.slabs_per_rhs]) return;
+  const int s_hi = s / a.n_lo, s_lo = s % a.n_lo;
+  const int cw = threadIdx.x % W, t = threadIdx.x / W;
+  const int col = tile * W + cw;
+  const bool valid = col < a.ncols;
+  const cpx<T>* pin = in + s_hi * a.in_hi + s_lo * a.in_lo + (valid ? col : 0);
+  cpx<T> v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int row = t + q * TT;
+    if ((!PAD || q < E / 2) && valid && row < a.n_in_rows)
+      v[q] = pin[(int64_t)row * a.in_row];
+    else
+      v[q] = mk<T>(0, 0);
+  }
+  line_fft<T, P, INV>(v, lds + cw * Pad<P>::LSTR, t, tw);
+  if (valid) {
+    cpx<T>* po = out + s_hi * a.out_hi + s_lo * a.out_lo + col;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int row = t + q * TT;
+      if ((!TRUNC || q < E / 2) && row < a.n_out_rows) po[(int64_t)row * a.out_row] = v[q];
+    }
+  }
+}
+
+// ----------------------------------------------- Z fused with the spectrum
+// Workgroup: W neighbouring xi_x columns at one xi_y, all 3 components of one
+// right-hand side.  Forward z-FFT (pad), symmetric 3x3 multiply with the
+// octant spectrum (sign from each component's parity on mirrored axes),
+// inverse z-FFT (truncate), in place.
+template <typename T>
+constexpr int zw(int P) {
+  return (sizeof(T) == 8 ? 1024 : 2048) / P;
+}
+
+struct ZArgs {
+  int N3, P1, P2, Q1, Q2, Q3, tiles_x, nrhs;
+  int64_t comp_stride, rhs_stride;
+};
+
+__device__ __forceinline__ int sym_index(int a, int b) {
+  // xx, xy, xz, yy, yz, zz
+  const int lo = a < b ? a : b, hi = a < b ? b : a;
+  return lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(3 * zw<T>(P) * (P / fft_e<P>())) void k_fft_z_green(
+    cpx<T>* __restrict__ B, const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw,
+    ZArgs a, const int* __restrict__ active) {
+  constexpr int E = fft_e<P>(), TT = P / E, W = zw<T>(P), LS = Pad<P>::LSTR;
+  __shared__ cpx<T> lds[3 * W * LS];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  // right-hand sides innermost: blocks sharing a spectrum pencil are adjacent
+  const int rhs = b % a.nrhs;
+  const int tile = (b / a.nrhs) % a.tiles_x;
+  const int xy = (b / a.nrhs) / a.tiles_x;
+  if (active && !active[rhs]) return;
+  const int comp = threadIdx.x / (W * TT);
+  const int rem = threadIdx.x % (W * TT);
+  const int cw = rem % W, t = rem / W;
+  const int xx = tile * W + cw;
+  const bool valid = xx < a.P1;
+  const int64_t zs = (int64_t)a.P2 * a.P1;
+  cpx<T>* col = B + rhs * a.rhs_stride + comp * a.comp_stride + (int64_t)xy * a.P1 + (valid ? xx : 0);
+  cpx<T> v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int z = t + q * TT;
+    if (q < E / 2 && valid && z < a.N3)
+      v[q] = col[z * zs];
+    else
+      v[q] = mk<T>(0, 0);
+  }
+  cpx<T>* myline = lds + (comp * W + cw) * LS;
+  line_fft<T, P, false>(v, myline, t, tw);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < E; ++q) myline[pidx(t + q * TT)] = v[q];
+  __syncthreads();
+  // octant coordinates and mirror flags
+  const int xm = xx > a.P1 / 2, ym = xy > a.P2 / 2;
+  const int xo = xm ? a.P1 - xx : xx, yo = ym ? a.P2 - xy : xy;
+  const int64_t oct = (int64_t)a.Q3 * a.Q2 * a.Q1;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int z = t + q * TT;
+    const int zm = z > P / 2;
+    const int zo = zm ? P - z : z;
+    const cpx<T>* sp = spec + ((int64_t)zo * a.Q2 + yo) * a.Q1 + (valid ? xo : 0);
+    cpx<T> acc = mk<T>(0, 0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cpx<T> in_c = (c == comp) ? v[q] : lds[(c * W + cw) * LS + pidx(z)];
+      cpx<T> g = sp[sym_index(comp, c) * oct];
+      // odd along axis e iff exactly one of (comp, c) equals e
+      int neg = 0;
+      if (comp != c) {
+        if ((comp == 0) != (c == 0)) neg ^= xm;
+        if ((comp == 1) != (c == 1)) neg ^= ym;
+        if ((comp == 2) != (c == 2)) neg ^= zm;
+      }
+      if (neg) g = mk<T>(-g.re, -g.im);
+      acc = cfma(g, in_c, acc);
+    }
+    v[q] = acc;
+  }
+  line_fft<T, P, true>(v, myline, t, tw);
+  if (valid) {
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) {
+      const int z = t + q * TT;
+      if (z < a.N3) col[z * zs] = v[q];
+    }
+  }
+}
+
+// ------------------------------------------------ X inverse + epilogue
+struct XinvArgs {
+  int N1, N2, N3, lines_per_rhs, lines_per_comp, blocks_per_rhs;
+  int64_t n;
+};
+
+template <typename T>
+__device__ __forceinline__ void block_sum2(c64& a, c64& b, double* red) {
+  // wave64 butterfly then across waves through LDS (fixed order: deterministic)
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a.re += __shfl_xor(a.re, off, 64);
+    a.im += __shfl_xor(a.im, off, 64);
+    b.re += __shfl_xor(b.re, off, 64);
+    b.im += __shfl_xor(b.im, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    red[wv * 4 + 0] = a.re;
+    red[wv * 4 + 1] = a.im;
+    red[wv * 4 + 2] = b.re;
+    red[wv * 4 + 3] = b.im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c64 sa = mk(0.0, 0.0), sb = mk(0.0, 0.0);
+    for (int w = 0; w < nw; ++w) {
+      sa.re += red[w * 4 + 0];
+      sa.im += red[w * 4 + 1];
+      sb.re += red[w * 4 + 2];
+      sb.im += red[w * 4 + 3];
+    }
+    a = sa;
+    b = sb;
+  }
+}
+
+template <typename T, int P, int MODE>
+__global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv(
+    const cpx<T>* __restrict__ A, const c64* __restrict__ xin, c64* __restrict__ yout,
+    const double* __restrict__ chi, const int* __restrict__ rhs_body,
+    const cpx<T>* __restrict__ tw, XinvArgs a, c64* __restrict__ aux, c64* __restrict__ partials,
+    const c64* __restrict__ pol, const c64* __restrict__ ph, const int* __restrict__ active) {
+  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), L = NT / TT;
+  __shared__ cpx<T> lds[L * Pad<P>::LSTR];
+  __shared__ double red[4 * (NT / 64 + 1)];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int rhs = b / a.blocks_per_rhs, blk = b % a.blocks_per_rhs;
+  if (active && !active[rhs]) return;
+  const int li = threadIdx.x / TT, t = threadIdx.x % TT;
+  const int line = blk * L + li;
+  const bool valid = line < a.lines_per_rhs;
+  const int lc = valid ? line : 0;
+  const size_t gl = (size_t)rhs * a.lines_per_rhs + lc;
+  cpx<T> v[E];
+  {
+    const cpx<T>* src = A + gl * P;
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[q] = valid ? src[t + q * TT] : mk<T>(0, 0);
+  }
+  line_fft<T, P, true>(v, lds + li * Pad<P>::LSTR, t, tw);
+  const int comp = lc / a.lines_per_comp, sp = lc % a.lines_per_comp;  // sp = z*N2 + y
+  const double* chib = chi + (int64_t)rhs_body[rhs] * a.n + (int64_t)sp * a.N1;
+  c64 s0 = mk(0.0, 0.0), s1 = mk(0.0, 0.0);
+  c64 phyz = mk(0.0, 0.0), pc = mk(0.0, 0.0);
+  if (MODE == EPI_RESID && valid) {
+    const c64* phr = ph + (int64_t)rhs * (a.N1 + a.N2 + a.N3);
+    const int y = sp % a.N2, z = sp / a.N2;
+    phyz = phr[a.N1 + y] * phr[a.N1 + a.N2 + z];
+    pc = pol[rhs * 3 + comp];
+  }
+  if (valid) {
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) {
+      const int xi = t + q * TT;
+      if (xi < a.N1) {
+        const size_t gi = gl * a.N1 + xi;
+        const double c = chib[xi];
+        const c64 conv = cvt<double>(v[q]);
+        const c64 xv = xin[gi];
+        const c64 y = xv - c * conv;
+        if (MODE == EPI_RESID) {
+          const c64 e = pc * (phyz * ph[(int64_t)rhs * (a.N1 + a.N2 + a.N3) + xi]);
+          const c64 r = c * e - y;
+          yout[gi] = r;
+          aux[gi] = r;
+          s1.re += r.re * r.re + r.im * r.im;
+        } else {
+          yout[gi] = y;
+          if (MODE == EPI_RHV) {
+            s0 = s0 + cmulc(aux[gi], y);
+          } else if (MODE == EPI_TS) {
+            s0 = s0 + cmulc(y, xv);
+            s1.re += y.re * y.re + y.im * y.im;
+          }
+        }
+      }
+    }
+  }
+  if (MODE != EPI_PLAIN) {
+    block_sum2<T>(s0, s1, red);
+    if (threadIdx.x == 0) {
+      c64* pp = partials + ((size_t)rhs * a.blocks_per_rhs + blk) * 2;
+      pp[0] = s0;
+      pp[1] = s1;
+    }
+  }
+}
+
+// ================================================================ launchers
+template <typename T>
+static constexpr int lines_per_block(int P) {
+  return nt_lines<T>() / (P < 16 ? 1 : P / 16);
+}
+
+#define VIE_DISPATCH_P(P_, CALL)                 \
+  switch (P_) {                                  \
+    case 8: { constexpr int PP = 8; CALL; break; }     \
+    case 16: { constexpr int PP = 16; CALL; break; }   \
+    case 32: { constexpr int PP = 32; CALL; break; }   \
+    case 64: { constexpr int PP = 64; CALL; break; }   \
+    case 128: { constexpr int PP = 128; CALL; break; } \
+    case 256: { constexpr int PP = 256; CALL; break; } \
+    case 512: { constexpr int PP = 512; CALL; break; } \
+    default: return hipErrorInvalidValue;        \
+  }
+
+template <typename T>
+static hipError_t x_fwd(const GroupGeom& g, const c64* x, cpx<T>* A, const cpx<T>* tw,
+                        const int* active, hipStream_t s) {
+  const int lines = 3 * g.N[1] * g.N[2];
+  const int L = lines_per_block<T>(g.P[0]);
+  const int bpr = (lines + L - 1) / L;
+  const dim3 grid(bpr * g.nrhs);
+  VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd<double, T, PP, true><<<grid, nt_lines<T>(), 0, s>>>(
+                             x, A, tw, g.N[0], lines, bpr, active)));
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t y_pass(const GroupGeom& g, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw,
+                         bool inverse, const int* active, hipStream_t s) {
+  const int P1 = g.P[0], P2 = g.P[1], N2 = g.N[1], N3 = g.N[2];
+  StridedArgs a;
+  a.ncols = P1;
+  a.n_lo = 3 * N3;  // (comp, z) slabs; s_hi = rhs
+  a.slabs_per_rhs = 3 * N3;
+  const int W = lines_per_block<T>(P2);
+  a.tiles = (P1 + W - 1) / W;
+  if (!inverse) {
+    a.n_in_rows = N2;
+    a.n_out_rows = P2;
+    a.in_row = P1;
+    a.out_row = P1;
+    a.in_lo = (int64_t)N2 * P1;
+    a.out_lo = (int64_t)P2 * P1;
+  } else {
+    a.n_in_rows = P2;
+    a.n_out_rows = N2;
+    a.in_row = P1;
+    a.out_row = P1;
+    a.in_lo = (int64_t)P2 * P1;
+    a.out_lo = (int64_t)N2 * P1;
+  }
+  a.in_hi = a.in_lo * 3 * N3;
+  a.out_hi = a.out_lo * 3 * N3;
+  const dim3 grid(a.tiles * 3 * N3 * g.nrhs);
+  if (!inverse) {
+    VIE_DISPATCH_P(P2, (k_fft_strided<T, PP, true, false, false><<<grid, nt_lines<T>(), 0, s>>>(
+                           in, out, tw, a, active)));
+  } else {
+    VIE_DISPATCH_P(P2, (k_fft_strided<T, PP, false, true, true><<<grid, nt_lines<T>(), 0, s>>>(
+                           in, out, tw, a, active)));
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t z_pass(const GroupGeom& g, cpx<T>* B, const cpx<T>* spec, const cpx<T>* tw,
+                         const int* active, hipStream_t s) {
+  ZArgs a;
+  a.N3 = g.N[2];
+  a.P1 = g.P[0];
+  a.P2 = g.P[1];
+  a.Q1 = g.Q[0];
+  a.Q2 = g.Q[1];
+  a.Q3 = g.Q[2];
+  a.nrhs = g.nrhs;
+  a.comp_stride = (int64_t)g.N[2] * g.P[1] * g.P[0];
+  a.rhs_stride = 3 * a.comp_stride;
+  VIE_DISPATCH_P(g.P[2], ({
+                   constexpr int W = zw<T>(PP);
+                   constexpr int NT = 3 * W * (PP / fft_e<PP>());
+                   a.tiles_x = (g.P[0] + W - 1) / W;
+                   const dim3 grid(a.tiles_x * g.P[1] * g.nrhs);
+                   k_fft_z_green<T, PP><<<grid, NT, 0, s>>>(B, spec, tw, a, active);
+                 }));
+  return hipGetLastError();
+}
+
+int part_blocks_xinv(const GroupGeom& g, int precision) {
+  const int lines = 3 * g.N[1] * g.N[2];
+  const int L = precision == 0 ? lines_per_block<double>(g.P[0]) : lines_per_block<float>(g.P[0]);
+  return (lines + L - 1) / L;
+}
+
+template <typename T>
+static hipError_t x_inv(const GroupGeom& g, const cpx<T>* A, const c64* x, c64* y,
+                        const double* chi, const int* rhs_body, const cpx<T>* tw, EpiArgs& e,
+                        const int* active, hipStream_t s) {
+  XinvArgs a;
+  a.N1 = g.N[0];
+  a.N2 = g.N[1];
+  a.N3 = g.N[2];
+  a.lines_per_comp = g.N[1] * g.N[2];
+  a.lines_per_rhs = 3 * a.lines_per_comp;
+  const int L = lines_per_block<T>(g.P[0]);
+  a.blocks_per_rhs = (a.lines_per_rhs + L - 1) / L;
+  a.n = g.n;
+  e.part_blocks = a.blocks_per_rhs;
+  const dim3 grid(a.blocks_per_rhs * g.nrhs);
+#define VIE_XINV(MODE_)                                                                    \
+  VIE_DISPATCH_P(g.P[0], (k_fft_x_inv<T, PP, MODE_><<<grid, nt_lines<T>(), 0, s>>>(           \
+                             A, x, y, chi, rhs_body, tw, a, e.aux, e.partials, e.pol, e.ph, \
+                             active)))
+  switch (e.mode) {
+    case EPI_PLAIN: VIE_XINV(EPI_PLAIN); break;
+    case EPI_RHV: VIE_XINV(EPI_RHV); break;
+    case EPI_TS: VIE_XINV(EPI_TS); break;
+    case EPI_RESID: VIE_XINV(EPI_RESID); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef VIE_XINV
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t matvec_t(const MatvecArgs& m, const c64* x, c64* y, EpiArgs& e, hipStream_t s,
+                           void (*cb)(int, bool, void*), void* u) {
+  const GroupGeom& g = *m.g;
+  cpx<T>* A = (cpx<T>*)m.bufA;
+  cpx<T>* B = (cpx<T>*)m.bufB;
+  const cpx<T>* tw0 = (const cpx<T>*)m.tw[0];
+  const cpx<T>* tw1 = (const cpx<T>*)m.tw[1];
+  const cpx<T>* tw2 = (const cpx<T>*)m.tw[2];
+  hipError_t err;
+  const int base = sizeof(T) == 8 ? 0 : 5;
+#define STEP(K, CALL)              \
+  if (cb) cb(base + K, true, u);   \
+  err = CALL;                      \
+  if (cb) cb(base + K, false, u);  \
+  if (err != hipSuccess) return err;
+  STEP(0, x_fwd<T>(g, x, A, tw0, m.active, s));
+  STEP(1, y_pass<T>(g, A, B, tw1, false, m.active, s));
+  STEP(2, z_pass<T>(g, B, (const cpx<T>*)m.spec, tw2, m.active, s));
+  STEP(3, y_pass<T>(g, B, A, tw1, true, m.active, s));
+  STEP(4, x_inv<T>(g, A, x, y, m.chi, m.rhs_body, tw0, e, m.active, s));
+#undef STEP
+  return hipSuccess;
+}
+
+hipError_t launch_matvec(const MatvecArgs& a, int precision, const c64* x, c64* y, EpiArgs& epi,
+                         hipStream_t s, void (*cb)(int, bool, void*), void* u) {
+  return precision == 0 ? matvec_t<double>(a, x, y, epi, s, cb, u)
+                        : matvec_t<float>(a, x, y, epi, s, cb, u);
+}
+
+// ------------------------------------------- full (unpadded) FP64 3-D FFT
+// Forward transform of work[P3][P2][P1]; the result lands in tmp.
+hipError_t launch_fft3d_full(c64* work, c64* tmp, const GroupGeom& g, const void* twv[3],
+                             hipStream_t s) {
+  const int P1 = g.P[0], P2 = g.P[1], P3 = g.P[2];
+  const c64* tw0 = (const c64*)twv[0];
+  const c64* tw1 = (const c64*)twv[1];
+  const c64* tw2 = (const c64*)twv[2];
+  {  // x lines: work -> tmp
+    const int lines = P2 * P3;
+    const int L = lines_per_block<double>(P1);
+    const int bpr = (lines + L - 1) / L;
+    VIE_DISPATCH_P(P1, (k_fft_x_fwd<double, double, PP, false><<<bpr, nt_lines<double>(), 0, s>>>(
+                           work, tmp, tw0, P1, lines, bpr, nullptr)));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {  // y lines: tmp -> work, slabs = z planes
+    StridedArgs a;
+    a.n_in_rows = a.n_out_rows = P2;
+    a.ncols = P1;
+    a.n_lo = P3;
+    a.slabs_per_rhs = P3;
+    const int W = lines_per_block<double>(P2);
+    a.tiles = (P1 + W - 1) / W;
+    a.in_row = a.out_row = P1;
+    a.in_lo = a.out_lo = (int64_t)P2 * P1;
+    a.in_hi = a.out_hi = 0;
+    VIE_DISPATCH_P(P2, (k_fft_strided<double, PP, false, false, false>
+                        <<<a.tiles * P3, nt_lines<double>(), 0, s>>>(tmp, work, tw1, a, nullptr)));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {  // z lines: work -> tmp, slabs = y rows
+    StridedArgs a;
+    a.n_in_rows = a.n_out_rows = P3;
+    a.ncols = P1;
+    a.n_lo = P2;
+    a.slabs_per_rhs = P2;
+    const int W = lines_per_block<double>(P3);
+    a.tiles = (P1 + W - 1) / W;
+    a.in_row = a.out_row = (int64_t)P2 * P1;
+    a.in_lo = a.out_lo = P1;
+    a.in_hi = a.out_hi = 0;
+    VIE_DISPATCH_P(P3, (k_fft_strided<double, PP, false, false, false>
+                        <<<a.tiles * P2, nt_lines<double>(), 0, s>>>(work, tmp, tw2, a, nullptr)));
+  }
+  return hipGetLastError();
+}
+
+}  // namespace vie

@@ -1,0 +1,116 @@
+// Internal launcher interface between the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace vie {
+
+// Per-right-hand-side BiCGSTAB state, resident in device memory.
+struct KState {
+  c64 rho, rho_prev, alpha, omega, beta;
+  double bnorm2;   // ||b||^2
+  double rnorm2;   // ||r||^2 (recursive inside a cycle, true after a restart)
+  double target2;  // stop the current cycle when rnorm2 <= target2
+  int active;      // 1 while this right-hand side iterates
+  int it_cycle;    // iterations in the current cycle
+  int iters;       // total iterations
+  int breakdown;   // 1 if the last cycle ended on a BiCGSTAB breakdown
+  int notdone;     // 1 while the true residual is above tol
+  double rh2;      // ||rhat||^2 (shadow residual of the current cycle)
+};
+
+// Epilogue of the inverse-x pass (y = x - chi * conv, then):
+enum EpiMode {
+  EPI_PLAIN = 0,  // y only
+  EPI_RHV = 1,    // partial sum conj(rhat) . y          (v = A p)
+  EPI_TS = 2,     // partial sums conj(y) . x, |y|^2       (t = A s)
+  EPI_RESID = 3   // r = b - y, rhat = r, partial |r|^2    (restart)
+};
+
+// Geometry of one group of right-hand sides sharing a grid and spectrum.
+struct GroupGeom {
+  int N[3];     // grid
+  int P[3];     // FFT lengths (powers of two >= 2N - 1)
+  int Q[3];     // octant extents P/2 + 1
+  int64_t n;    // N1 N2 N3
+  int nrhs;     // right-hand sides in the group
+};
+
+// Device pointers used by one operator product of a group.
+struct MatvecArgs {
+  const GroupGeom* g;
+  const double* chi;       // [body][n]
+  const int* rhs_body;     // [nrhs] body index of each right-hand side
+  const void* spec;        // octant spectrum, c64 or c32 per precision
+  const void* tw[3];       // twiddle tables per axis (c64 or c32)
+  void* bufA;              // x-transformed scratch [nrhs][3][N3][N2][P1]
+  void* bufB;              // y-transformed scratch [nrhs][3][N3][P2][P1]
+  const int* active;       // [nrhs] or nullptr
+};
+
+// precision 0: FP64 passes, 1: FP32 passes (input/output vectors are FP64)
+// epilogue extras: aux (rhat for EPI_RHV, rhat output for EPI_RESID),
+// partials [nrhs][blocks][2] (c64), pol/phase tables for EPI_RESID.
+struct EpiArgs {
+  int mode;
+  c64* aux;
+  c64* partials;
+  int part_blocks;  // filled by the launcher: blocks per right-hand side
+  const c64* pol;   // [nrhs][3]
+  const c64* ph;    // [nrhs][N1 + N2 + N3]  exp(i k0 khat_a (o_a + h idx))
+};
+
+int part_blocks_xinv(const GroupGeom& g, int precision);
+int vec_blocks(const GroupGeom& g);
+
+hipError_t launch_matvec(const MatvecArgs& a, int precision, const c64* x, c64* y, EpiArgs& epi,
+                         hipStream_t s, void (*ev_cb)(int kind, bool begin, void* u), void* u);
+
+// Green spectrum: sample the circulant kernel of component ab into
+// work[P3][P2][P1] (c64).
+hipError_t launch_green_sample(c64* work, const GroupGeom& g, int ab, double h, double k0,
+                               hipStream_t s);
+// In-place unpadded 3-D FFT of one P3 x P2 x P1 c64 array (forward).
+hipError_t launch_fft3d_full(c64* work, c64* tmp, const GroupGeom& g, const void* tw[3],
+                             hipStream_t s);
+// Octant compression with 1/M scaling into spec64 (and spec32 if non-null).
+hipError_t launch_octant(const c64* work, c64* spec64, c32* spec32, const GroupGeom& g, int ab,
+                         hipStream_t s);
+
+// Krylov vector kernels (FP64 vectors of 3n complex per right-hand side).
+// b = chi pol e^{i k0 khat.r}; r = rhat = b; x = 0 unless keep_x; partials |b|^2.
+// mask (nullable): only right-hand sides with mask[rhs] != 0.
+hipError_t launch_init_zero_guess(const GroupGeom& g, const double* chi, const int* rhs_body,
+                                  const c64* pol, const c64* ph, c64* x, c64* r, c64* rh,
+                                  c64* partials, int keep_x, const int* mask, hipStream_t s);
+hipError_t launch_update_p(const GroupGeom& g, const KState* st, const int* active,
+                           const c64* r, c64* p, const c64* v, hipStream_t s);
+hipError_t launch_update_s(const GroupGeom& g, const KState* st, const int* active,
+                           const c64* r, const c64* v, c64* s_out, hipStream_t s);
+hipError_t launch_update_xr(const GroupGeom& g, const KState* st, const int* active, c64* x,
+                            c64* r, const c64* p, const c64* sv, const c64* t, const c64* rh,
+                            c64* partials, hipStream_t s);
+// Finalize reductions (one workgroup per right-hand side, fixed order):
+enum FinWhich { FIN_ALPHA = 0, FIN_OMEGA = 1, FIN_RHO = 2, FIN_INIT = 3, FIN_RESTART = 4 };
+struct FinParams {
+  double tol2_done;   // converged when ||r_true||^2 <= tol2_done ||b||^2
+  double tol2_inner;  // a cycle may stop at ||r||^2 <= tol2_inner ||b||^2 ...
+  double eta2;        // ... or at ||r||^2 <= eta2 ||r_cycle_start||^2 (larger of the two)
+  int max_iter;
+};
+hipError_t launch_finalize(int which, int nrhs, int nblk, const c64* partials, KState* st,
+                           int* active, const FinParams& fp, hipStream_t s);
+hipError_t launch_axpy_real(int64_t n, double a, const c64* x, c64* y, hipStream_t s);
+
+// Far field (eq. 25): F[rhs][dir][2] = (F_theta, F_phi) for right-hand sides
+// [r0, r0+nr) of a group; body voxels listed in vox[nb] (linear indices);
+// dirs[nd][9] = (r, theta-hat, phi-hat); part: ceil(nb/chunk)*min(nr,4)*nd*3 c64.
+hipError_t launch_farfield_ks(const GroupGeom& g, const c64* w, int r0, int nr, const int* vox,
+                              int nb, const double* dirs, int nd, double k0, double h,
+                              const double* origin, c64* part, int chunk, c64* F,
+                              hipStream_t s);
+
+}  // namespace vie

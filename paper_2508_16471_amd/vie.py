@@ -1,0 +1,224 @@
+"""ctypes binding of ``include/vie.h`` (argument marshalling only).
+
+Every numerical step runs inside ``libvie.so`` (HIP kernels for gfx950 and
+the library's host runtime).  Loading fails loudly when the library has not
+been built; there is no fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvie.so")
+
+VIE_OK, VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_ENOCONV, VIE_ENOTSUP, VIE_ESTATE = 0, -1, -2, -3, -4, -5, -6
+VIE_FP64, VIE_MIXED = 0, 1
+VIE_NORM_R1, VIE_NORM_R2 = 0, 1
+VIE_FLAG_TIMING = 1
+
+
+class vie_c64(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class vie_body(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("h", C.c_double), ("origin", C.c_double * 3),
+                ("eps_r", C.POINTER(C.c_double))]
+
+
+class vie_options(C.Structure):
+    _fields_ = [("k0", C.c_double), ("precision", C.c_int32), ("tol", C.c_double),
+                ("max_iter", C.c_int32), ("inner_tol", C.c_double), ("warm_start", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+class vie_planewave(C.Structure):
+    _fields_ = [("khat", C.c_double * 3), ("pol", vie_c64 * 3)]
+
+
+class vie_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("matvecs", C.c_int32), ("cycles", C.c_int32),
+                ("converged", C.c_int32), ("fallback", C.c_int32), ("warm", C.c_int32),
+                ("rel_res", C.c_double), ("rel_res_x0", C.c_double)]
+
+
+class VieError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libvie.so (raises if it is missing: no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libvie.so not built at {LIB_PATH}; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        sig = {
+            "vie_setup": (C.c_int, [P(vie_body), C.c_int32, P(vie_options), P(C.c_void_p)]),
+            "vie_solve": (C.c_int, [C.c_void_p, P(vie_planewave), P(C.c_int32), P(vie_stats)]),
+            "vie_farfield": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double),
+                                       C.c_int32, P(vie_c64)]),
+            "hom_g2": (C.c_int, [P(vie_c64), P(C.c_double), C.c_double, P(C.c_double), C.c_int32,
+                                 C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double)]),
+            "vie_get_current": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, P(vie_c64)]),
+            "vie_matvec": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, P(vie_c64), P(vie_c64),
+                                     C.c_int32]),
+            "vie_matvec_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                         C.c_int32]),
+            "vie_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+            "vie_kernel_times": (C.c_int, [C.c_void_p, P(C.c_char_p), P(C.c_double), P(C.c_int64),
+                                           P(C.c_int32), C.c_int32]),
+            "vie_set_options": (C.c_int, [C.c_void_p, P(vie_options)]),
+            "vie_destroy": (None, [C.c_void_p]),
+            "vie_strerror": (C.c_char_p, [C.c_int]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code):
+    return lib().vie_strerror(int(code)).decode()
+
+
+def _check(code, where, allow=()):
+    if code != VIE_OK and code not in allow:
+        raise VieError(code, where)
+    return code
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _cptr(a):
+    return a.ctypes.data_as(C.POINTER(vie_c64))
+
+
+def make_options(k0, precision=VIE_FP64, tol=1e-8, max_iter=5000, inner_tol=1e-3, warm_start=0, flags=0):
+    return vie_options(float(k0), int(precision), float(tol), int(max_iter), float(inner_tol),
+                       int(warm_start), int(flags))
+
+
+def vie_setup(bodies, opt):
+    """bodies: list of (eps_r[N3,N2,N1] float64, h, origin[3]).  Returns ctx handle."""
+    arr = (vie_body * len(bodies))()
+    keep = []
+    for i, (eps, h, origin) in enumerate(bodies):
+        e = np.ascontiguousarray(eps, dtype=np.float64)
+        keep.append(e)
+        arr[i].n[0], arr[i].n[1], arr[i].n[2] = e.shape[2], e.shape[1], e.shape[0]
+        arr[i].h = float(h)
+        for a in range(3):
+            arr[i].origin[a] = float(origin[a])
+        arr[i].eps_r = _dptr(e)
+    ctx = C.c_void_p()
+    _check(lib().vie_setup(arr, len(bodies), C.byref(opt), C.byref(ctx)), "vie_setup")
+    return ctx
+
+
+def planewaves(channels):
+    """channels: list of (khat[3], pol[3] complex) -> vie_planewave array."""
+    arr = (vie_planewave * max(1, len(channels)))()
+    for i, (k, p) in enumerate(channels):
+        for a in range(3):
+            arr[i].khat[a] = float(k[a])
+            arr[i].pol[a].re = float(np.real(p[a]))
+            arr[i].pol[a].im = float(np.imag(p[a]))
+    return arr
+
+
+def vie_solve(ctx, channels, nrhs_per_body, allow_noconv=False):
+    """Solve all right-hand sides; returns (status, list of stats dicts)."""
+    pw = planewaves(channels)
+    nr = (C.c_int32 * len(nrhs_per_body))(*[int(v) for v in nrhs_per_body])
+    st = (vie_stats * max(1, len(channels)))()
+    rc = lib().vie_solve(ctx, pw, nr, st)
+    _check(rc, "vie_solve", allow=(VIE_ENOCONV,) if allow_noconv else ())
+    out = [{f: getattr(st[i], f) for f, _ in vie_stats._fields_} for i in range(len(channels))]
+    return rc, out
+
+
+def vie_farfield(ctx, body, theta, phi, nrhs):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    F = np.zeros((nrhs, len(th), 2), dtype=np.complex128)
+    _check(lib().vie_farfield(ctx, int(body), _dptr(th), _dptr(ph), len(th), _cptr(F)), "vie_farfield")
+    return F
+
+
+def hom_g2(T, sigma=1.2, dtau=None, norm=VIE_NORM_R1, omega=None):
+    """Returns (g2, Nc_raw[ndelay], Nc_norm[ndelay])."""
+    t = np.ascontiguousarray(np.asarray(T, dtype=np.complex128).reshape(4))
+    d = np.ascontiguousarray(np.zeros(0) if dtau is None else dtau, dtype=np.float64)
+    om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
+    g = np.zeros(1)
+    raw = np.zeros(len(d))
+    nrm = np.zeros(len(d))
+    _check(lib().hom_g2(_cptr(t), None if om is None else _dptr(om), float(sigma),
+                        _dptr(d) if len(d) else None, len(d), int(norm), _dptr(g),
+                        _dptr(raw) if len(d) else None, _dptr(nrm) if len(d) else None), "hom_g2")
+    return float(g[0]), raw, nrm
+
+
+def vie_get_current(ctx, body, rhs, n):
+    """Solution w = chi E as complex array (3, N3, N2, N1); n = (N1, N2, N3)."""
+    w = np.zeros((3, n[2], n[1], n[0]), dtype=np.complex128)
+    _check(lib().vie_get_current(ctx, int(body), int(rhs), _cptr(w)), "vie_get_current")
+    return w
+
+
+def vie_matvec(ctx, body, x, precision=VIE_FP64):
+    """y = x - chi Ghat x for host vectors x[nvec, 3, N3, N2, N1] (or one vector)."""
+    xs = np.ascontiguousarray(x, dtype=np.complex128)
+    single = xs.ndim == 4
+    if single:
+        xs = xs[None]
+    y = np.zeros_like(xs)
+    _check(lib().vie_matvec(ctx, int(body), int(precision), _cptr(xs), _cptr(y), xs.shape[0]), "vie_matvec")
+    return y[0] if single else y
+
+
+def vie_matvec_dev(ctx, body, x_ptr, y_ptr, nvec, precision=VIE_FP64):
+    _check(lib().vie_matvec_dev(ctx, int(body), int(precision), C.c_void_p(x_ptr), C.c_void_p(y_ptr),
+                                int(nvec)), "vie_matvec_dev")
+
+
+def vie_set_stream(ctx, stream_ptr):
+    _check(lib().vie_set_stream(ctx, C.c_void_p(stream_ptr)), "vie_set_stream")
+
+
+def vie_set_options(ctx, opt):
+    _check(lib().vie_set_options(ctx, C.byref(opt)), "vie_set_options")
+
+
+def vie_kernel_times(ctx, reset=False):
+    cap = 32
+    names = (C.c_char_p * cap)()
+    ms = (C.c_double * cap)()
+    cnt = (C.c_int64 * cap)()
+    nk = C.c_int32(cap)
+    _check(lib().vie_kernel_times(ctx, names, ms, cnt, C.byref(nk), int(reset)), "vie_kernel_times")
+    return {names[i].decode(): (ms[i], cnt[i]) for i in range(min(cap, nk.value))}
+
+
+def vie_destroy(ctx):
+    if ctx:
+        lib().vie_destroy(ctx)
+
+
+def vie_strerror(code):
+    return strerror(code)
