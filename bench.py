@@ -1,0 +1,387 @@
+#!/usr/bin/env python3
+"""Benchmark of the FFT-VIE hot path on one MI355X.
+
+Workload (W128): held-out bodies of the Pancharatnam-Berry fin-metasurface
+family on a 128^3 grid (h = lambda/32, FFT 256^3), two plane-wave channels
+per body (directions in a 20 deg cap about +z, random elliptical
+polarisation), solved to a true relative residual of 1e-6 (FP64 operator).
+One step = the whole path for one batch: batched solve of every
+(body, channel) -> far field on a 181-point detector scan per body ->
+circular (L/R) transfer coefficients -> g2 scan and coincidence curve.
+
+value  = solves/s of the fast path (FP32 FFT product inside FP64 iterative
+         refinement, all right-hand sides batched per launch);
+plain  = solves/s of the plain path (FP64 product, FP64 BiCGSTAB, x0 = 0,
+         one right-hand side per call), reported beside it.
+roofline: the dominant kernel's algorithmic bytes (per right-hand-side
+         execution, counted from the solver's own product counts) over its
+         HIP-event time inside the timed region.
+cpu_baseline: the CPU oracle's direct FP64 operator rows (O(N_b) each) timed
+         on the host, extrapolated to a full product and scaled by the plain
+         path's measured product count per solve.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+K0 = 2 * np.pi
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--bodies", type=int, default=4)
+    ap.add_argument("--channels", type=int, default=2)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--inner-tol", type=float, default=1e-3)
+    ap.add_argument("--plain-solves", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--mode", choices=["solve", "matvec"], default="solve",
+                    help="matvec: time device-resident operator products only (profiling)")
+    ap.add_argument("--nrhs", type=int, default=1, help="matvec mode: vectors per product")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32")
+    return ap.parse_args()
+
+
+def make_workload(nb, nch, n):
+    from synth import metasurface_family, random_planewave
+
+    rng = np.random.default_rng(55)  # held-out seed of the metasurface family
+    bodies, chans = [], []
+    for _ in range(nb):
+        g, eps = metasurface_family(rng, n, 1.0 / 32 * 128 / n)
+        bodies.append((eps, g.h, g.origin, g))
+        for _ in range(nch):
+            chans.append(random_planewave(rng, cap_deg=20.0, elliptical=True))
+    return bodies, chans
+
+
+def detector_scan():
+    psi = np.deg2rad(np.linspace(-90.0, 90.0, 181))
+    theta = np.abs(psi)
+    phi = np.where(psi < 0, np.pi, 0.0)
+    return psi, theta, phi
+
+
+def post_process(V, ctx, nb, nch, theta, phi, dtau):
+    """Far field -> circular transfer coefficients -> g2 scan + Nc curve."""
+    out = []
+    i_m10 = 80  # psi = -10 deg
+    i_p10 = 100  # psi = +10 deg
+    for b in range(nb):
+        F = V.vie_farfield(ctx, b, theta, phi, nch)  # [nch][181][2]
+        EL = (F[..., 0] + 1j * F[..., 1]) / np.sqrt(2)
+        ER = (F[..., 0] - 1j * F[..., 1]) / np.sqrt(2)
+        g2s = []
+        for j in range(len(theta)):
+            T = (ER[0, i_m10], ER[1, i_m10], EL[0, j], EL[1, j])
+            g, _, _ = V.hom_g2(T)
+            g2s.append(g)
+        T = (ER[0, i_m10], ER[1, i_m10], EL[0, i_p10], EL[1, i_p10])
+        _, raw, nrm = V.hom_g2(T, 1.2, dtau, V.VIE_NORM_R1)
+        out.append((np.array(g2s), nrm))
+    return out
+
+
+# ------------------------------------------------------------ byte model
+def kernel_bytes(kind, N, P, Q, epi_extra=0):
+    """Algorithmic HBM bytes of one right-hand-side execution of a pass
+    (spectrum excluded; it is charged once per launch)."""
+    N1, N2, N3 = N
+    P1, P2, P3 = P
+    n = N1 * N2 * N3
+    c = 16 if kind.endswith("f64") else 8
+    A = 3 * N3 * N2 * P1
+    B = 3 * N3 * P2 * P1
+    if kind.startswith("fft_x_fwd"):
+        return 3 * n * 16 + A * c
+    if kind.startswith("fft_y_fwd"):
+        return A * c + B * c
+    if kind.startswith("fft_z_green"):
+        return 2 * B * c
+    if kind.startswith("fft_y_inv"):
+        return B * c + A * c
+    if kind.startswith("fft_x_inv"):
+        return A * c + 3 * n * 16 * 2 + n * 8 + epi_extra
+    raise KeyError(kind)
+
+
+def spectrum_bytes(kind, Q):
+    c = 16 if kind.endswith("f64") else 8
+    return 6 * Q[0] * Q[1] * Q[2] * c
+
+
+def roofline_from_times(times, stats, N, P, Q, mixed):
+    """Achieved GB/s of every FFT pass over the timed region."""
+    n = N[0] * N[1] * N[2]
+    iters = np.array([s["iters"] for s in stats])
+    cyc = np.array([s["cycles"] for s in stats])
+    rows = {}
+    for kind, (ms, cnt) in times.items():
+        if not kind.startswith("fft_") or cnt == 0 or ms <= 0:
+            continue
+        f32 = kind.endswith("f32")
+        if mixed:
+            execs = int((2 * iters).sum()) if f32 else int(cyc.sum())
+            launches_active = int(2 * iters.max()) if f32 else int(cyc.max())
+        else:
+            execs = int((2 * iters + cyc).sum())
+            launches_active = int(2 * iters.max() + cyc.max())
+        extra = 0
+        if kind.startswith("fft_x_inv"):
+            extra = 3 * n * 16 // 2  # rhat read (v = A p) or written (restart), on average
+        by = execs * kernel_bytes(kind, N, P, Q, extra)
+        if kind.startswith("fft_z_green"):
+            by += launches_active * spectrum_bytes(kind, Q)
+        rows[kind] = {"ms_total": ms, "launches": int(cnt), "rhs_execs": execs,
+                      "bytes": float(by), "GBps": by / (ms * 1e-3) / 1e9,
+                      "avg_launch_ms": ms / cnt}
+    return rows
+
+
+# ------------------------------------------------------------ CPU oracle
+_G = {}
+
+
+def _oracle_rows(idx):
+    from oracle import vie_dense as vd
+
+    return vd.matvec_rows(_G["chi"], _G["pos"], _G["h"], K0, _G["x"], idx)
+
+
+def cpu_product_time(body, seconds):
+    """Oracle rows of the FP64 product on the host (before any GPU use),
+    extrapolated to one full product.  Returns (seconds, info)."""
+    import multiprocessing as mp
+
+    from oracle import vie_dense as vd
+
+    eps, h, origin, g = body
+    chi = (eps - 1).ravel()
+    pos = vd.voxel_centres(g.n, g.h, g.origin)
+    rng = np.random.default_rng(1)
+    bodyvox = np.nonzero(chi)[0]
+    x = np.zeros((3, chi.size), complex)
+    x[:, bodyvox] = rng.standard_normal((3, len(bodyvox))) + 1j * rng.standard_normal((3, len(bodyvox)))
+    _G.update(chi=chi, pos=pos, h=h, x=x)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    # calibrate on one chunk in this process
+    t0 = time.perf_counter()
+    _oracle_rows(bodyvox[:8])
+    per_row = (time.perf_counter() - t0) / 8
+    nrows = int(max(workers * 8, min(len(bodyvox), seconds * workers / max(per_row, 1e-6))))
+    sel = rng.choice(bodyvox, size=nrows, replace=False)
+    chunks = np.array_split(sel, workers * 4)
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_rows, chunks)
+    wall = time.perf_counter() - t0
+    t_product = wall / nrows * len(bodyvox)  # rows off the body are the identity
+    return t_product, {"workers": workers, "rows": nrows, "body_rows": len(bodyvox), "wall": wall}
+
+
+def cpu_baseline(t_product, info, plain_products):
+    solve_s = t_product * plain_products
+    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": info["workers"], "kind": "oracle",
+            "sample": (f"{info['rows']} of {info['body_rows']} body rows of the FP64 product (direct "
+                       f"O(N_b) sum per row) on one held-out 128^3 body in {info['wall']:.1f} s wall; "
+                       f"extrapolated to a full product ({t_product:.1f} s) x {plain_products:.0f} "
+                       f"products per plain solve (the GPU plain path's measured count)")}
+
+
+# ------------------------------------------------------- product timing
+def matvec_mode(args):
+    """Time `steps` device-resident operator products of one W128 body."""
+    import torch
+
+    from paper_2508_16471_amd import vie as V
+
+    torch.cuda.set_device(0)
+    bodies, _ = make_workload(1, 1, args.grid)
+    eps, h, o, g = bodies[0]
+    N = g.n
+    P = tuple(max(8, 1 << int(np.ceil(np.log2(2 * v - 1)))) for v in N)
+    Q = tuple(p // 2 + 1 for p in P)
+    prec = V.VIE_MIXED if args.precision == "fp32" else V.VIE_FP64
+    ctx = V.vie_setup([(eps, h, o)], V.make_options(K0, flags=V.VIE_FLAG_TIMING))
+    n = N[0] * N[1] * N[2]
+    x = torch.randn(args.nrhs, 3 * n, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream().cuda_stream
+    V.vie_set_stream(ctx, stream)
+    for _ in range(max(1, args.warmup)):
+        V.vie_matvec_dev(ctx, 0, x.data_ptr(), y.data_ptr(), args.nrhs, prec)
+    torch.cuda.synchronize()
+    V.vie_kernel_times(ctx, reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        V.vie_matvec_dev(ctx, 0, x.data_ptr(), y.data_ptr(), args.nrhs, prec)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    times = V.vie_kernel_times(ctx, reset=True)
+    V.vie_destroy(ctx)
+    # plain device copy of known size: calibrates FETCH_SIZE / WRITE_SIZE counters
+    cbytes = 512 << 20
+    ca = torch.empty(cbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        cb.copy_(ca)
+    torch.cuda.synchronize()
+    rows = {}
+    for kind, (ms, cnt) in times.items():
+        if not kind.startswith("fft_") or cnt == 0:
+            continue
+        by = args.steps * args.nrhs * kernel_bytes(kind, N, P, Q)
+        if kind.startswith("fft_z_green"):
+            by += args.steps * spectrum_bytes(kind, Q)
+        rows[kind] = {"avg_launch_ms": ms / cnt, "GBps": by / (ms * 1e-3) / 1e9, "launches": cnt}
+    total = sum(v["avg_launch_ms"] for v in rows.values())
+    print(json.dumps({"mode": "matvec", "precision": args.precision, "nrhs": args.nrhs,
+                      "copy_calibration": {"bytes_read": cbytes, "bytes_written": cbytes, "launches": 3},
+                      "grid": list(N), "fft": list(P), "ms_per_product": dt / args.steps * 1e3,
+                      "kernel_ms_per_product": total, "kernels": rows}))
+
+
+# ------------------------------------------------------------------ main
+def main():
+    args = parse()
+    if args.mode == "matvec":
+        if args.gpus != 1:
+            sys.exit(2)
+        return matvec_mode(args)
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the path shards by "
+                          "right-hand side / body (see DESIGN.md), --gpus must be 1"}))
+        sys.exit(2)
+    bodies, chans = make_workload(args.bodies, args.channels, args.grid)
+    cpu_t = None
+    if not args.no_cpu:  # host oracle first, before this process touches the GPU
+        cpu_t = cpu_product_time(bodies[0], args.cpu_seconds)
+    import torch
+
+    from paper_2508_16471_amd import vie as V
+
+    torch.cuda.set_device(0)
+    V.lib()
+    N = bodies[0][3].n
+    P = tuple(max(8, 1 << int(np.ceil(np.log2(2 * v - 1)))) for v in N)
+    Q = tuple(p // 2 + 1 for p in P)
+    nb, nch = args.bodies, args.channels
+    psi, theta, phi = detector_scan()
+    dtau = np.linspace(-5, 5, 200)
+
+    fast = V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
+                          inner_tol=args.inner_tol, flags=V.VIE_FLAG_TIMING)
+    t0 = time.perf_counter()
+    ctx = V.vie_setup([(e, h, o) for e, h, o, _ in bodies], fast)
+    setup_s = time.perf_counter() - t0
+
+    def step():
+        rc, st = V.vie_solve(ctx, chans, [nch] * nb)
+        post_process(V, ctx, nb, nch, theta, phi, dtau)
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    V.vie_kernel_times(ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_stats = []
+    for _ in range(args.steps):
+        all_stats += step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    times = V.vie_kernel_times(ctx, reset=True)
+    solves = args.steps * nb * nch
+    value = solves / dt
+    fast_rows = roofline_from_times(times, all_stats, N, P, Q, mixed=True)
+    dom = max(fast_rows, key=lambda k: fast_rows[k]["ms_total"])
+    d = fast_rows[dom]
+    conv = all(s["converged"] for s in all_stats)
+    max_res = max(s["rel_res"] for s in all_stats)
+    prod_fast = np.mean([s["matvecs"] for s in all_stats])
+
+    plain = None
+    if not args.no_plain:
+        popt = V.make_options(K0, precision=V.VIE_FP64, tol=args.tol, max_iter=20000,
+                              flags=V.VIE_FLAG_TIMING)
+        V.vie_set_options(ctx, popt)
+        ps = []
+        V.vie_solve(ctx, [chans[0]], [1] + [0] * (nb - 1))  # warm
+        V.vie_kernel_times(ctx, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.plain_solves):
+            b, q = divmod(i % (nb * nch), nch)
+            cnt = [0] * nb
+            cnt[b] = 1
+            _, st = V.vie_solve(ctx, [chans[b * nch + q]], cnt)
+            ps += st
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t0
+        ptimes = V.vie_kernel_times(ctx, reset=True)
+        prow = roofline_from_times(ptimes, ps, N, P, Q, mixed=False)
+        plain = {"solves_per_s": args.plain_solves / pdt,
+                 "iters_mean": float(np.mean([s["iters"] for s in ps])),
+                 "products_mean": float(np.mean([s["matvecs"] for s in ps])),
+                 "max_rel_res": max(s["rel_res"] for s in ps),
+                 "kernels": prow}
+    V.vie_destroy(ctx)
+
+    cpu = None
+    if cpu_t is not None:
+        prods = plain["products_mean"] if plain else prod_fast
+        cpu = cpu_baseline(cpu_t[0], cpu_t[1], prods)
+
+    line = {
+        "metric": "VIE solves/s at rel. residual 1e-6 (128^3 grid), plain FP64 vs mixed+learned",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 FFT product / f64 Krylov",
+        "data": "synthetic",
+        "config": {"workload": (f"W128: {nb} held-out PB-phase fin-metasurface bodies (seed 55) on "
+                                f"{N[0]}x{N[1]}x{N[2]} voxels, h=lambda/32, FFT {P[0]}x{P[1]}x{P[2]}, "
+                                f"{nch} channels each, true rel. residual <= {args.tol:g}, far field "
+                                f"on a 181-point detector scan, circular g2 scan + 200-delay Nc"),
+                   "bodies": nb, "channels_per_body": nch, "grid": list(N), "fft": list(P),
+                   "tol": args.tol, "precision": "mixed (FP32 product, FP64 refinement)",
+                   "inner_tol": args.inner_tol, "warm_start": False},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": d["avg_launch_ms"]},
+        "cpu_baseline": cpu,
+        "fast": {"converged": conv, "max_rel_res": max_res, "products_mean": float(prod_fast),
+                 "iters_mean": float(np.mean([s["iters"] for s in all_stats])),
+                 "kernels": fast_rows},
+        "plain_fp64": plain,
+        "speedup_vs_plain": (value / plain["solves_per_s"]) if plain else None,
+        "setup_s": setup_s,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

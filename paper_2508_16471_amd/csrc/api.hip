@@ -79,6 +79,8 @@ struct Group {
   DevBuf flags;                  // int [2][cap]
   DevBuf rhs_body, pol, ph;      // per right-hand side
   DevBuf dirs, part, F;          // far-field scratch
+  int zvar[2] = {-1, -1};        // autotuned z-pass shape per precision (-1: not yet)
+  int zvar_nrhs[2] = {0, 0};     // right-hand-side count it was tuned for
 };
 
 struct TimedEvent {
@@ -370,7 +372,7 @@ static int ensure_solve_storage(vie_ctx* ctx, Group& G, int nrhs) {
   DevBuf* vs[] = {&G.x, &G.r, &G.rh, &G.p, &G.v, &G.s, &G.t};
   for (DevBuf* b : vs) VIE_HIP(b->reserve(vec * nrhs));
   const size_t a = (size_t)3 * G.g.N[2] * G.g.N[1] * G.g.P[0] * sizeof(c64);
-  const size_t bb = (size_t)3 * G.g.N[2] * G.g.P[1] * G.g.P[0] * sizeof(c64);
+  const size_t bb = (size_t)bufB_elems(G.g) * sizeof(c64);
   VIE_HIP(G.bufA.reserve(a * nrhs));
   VIE_HIP(G.bufB.reserve(bb * nrhs));
   const int maxblk = std::max(std::max(part_blocks_xinv(G.g, 0), part_blocks_xinv(G.g, 1)),
@@ -398,6 +400,7 @@ static int ensure_hflags(vie_ctx* ctx, int n) {
 
 static MatvecArgs matvec_args(Group& G, int precision, const int* active) {
   MatvecArgs m;
+  m.zvar = G.zvar[precision] < 0 ? 0 : G.zvar[precision];
   m.g = &G.g;
   m.chi = G.chi.as<double>();
   m.rhs_body = G.rhs_body.as<int>();
@@ -409,8 +412,58 @@ static MatvecArgs matvec_args(Group& G, int precision, const int* active) {
   return m;
 }
 
+// Autotuner: time every z-pass launch shape on this group's scratch with the
+// current right-hand-side count and keep the fastest (VIE_ZVAR=<k> forces one).
+static hipError_t tune_z(vie_ctx* ctx, Group& G, int precision) {
+  if (G.zvar[precision] >= 0 && G.zvar_nrhs[precision] == G.g.nrhs) return hipSuccess;
+  const char* force = getenv("VIE_ZVAR");
+  if (force) {
+    G.zvar[precision] = std::max(0, std::min(z_variants() - 1, atoi(force)));
+    G.zvar_nrhs[precision] = G.g.nrhs;
+    return hipSuccess;
+  }
+  hipError_t e = hipMemsetAsync(G.bufB.p, 0, G.bufB.bytes, ctx->stream);
+  if (e != hipSuccess) return e;
+  hipEvent_t a = nullptr, b = nullptr;
+  if ((e = hipEventCreate(&a)) != hipSuccess) return e;
+  if ((e = hipEventCreate(&b)) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return e;
+  }
+  float best = 1e30f;
+  int bestv = 0;
+  for (int v = 0; v < z_variants() && e == hipSuccess; ++v) {
+    MatvecArgs m = matvec_args(G, precision, nullptr);
+    m.zvar = v;
+    e = launch_z_only(m, precision, ctx->stream);  // warm-up
+    if (e != hipSuccess) break;
+    (void)hipEventRecord(a, ctx->stream);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_z_only(m, precision, ctx->stream);
+    (void)hipEventRecord(b, ctx->stream);
+    if (e != hipSuccess) break;
+    e = hipEventSynchronize(b);
+    float ms = 0;
+    if (e == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess && ms < best) {
+      best = ms;
+      bestv = v;
+    }
+    if (getenv("VIE_LOG"))
+      fprintf(stderr, "vie: tune z pass P=%dx%dx%d prec=%d nrhs=%d variant %d: %.4f ms\n",
+              G.g.P[0], G.g.P[1], G.g.P[2], precision, G.g.nrhs, v, ms / 3);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e == hipSuccess) {
+    G.zvar[precision] = bestv;
+    G.zvar_nrhs[precision] = G.g.nrhs;
+  }
+  return e;
+}
+
 static hipError_t run_matvec(vie_ctx* ctx, Group& G, int precision, const c64* x, c64* y,
                              EpiArgs& e, const int* active) {
+  hipError_t te = tune_z(ctx, G, precision);
+  if (te != hipSuccess) return te;
   MatvecArgs m = matvec_args(G, precision, active);
   return launch_matvec(m, precision, x, y, e, ctx->stream, timing_on(ctx) ? timing_cb : nullptr,
                        ctx);
@@ -651,8 +704,8 @@ extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* 
         if (stats) {
           vie_stats& o = stats[first[b] + q];
           o.iters = S.iters;
-          o.matvecs = 0;
-          o.cycles = 0;
+          o.matvecs = 2 * S.iters + S.cycles;
+          o.cycles = S.cycles;
           o.converged = conv;
           o.fallback = 0;
           o.warm = 0;

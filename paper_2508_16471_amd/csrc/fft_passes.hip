@@ -30,14 +30,55 @@ struct LdsLine {
   __device__ __forceinline__ cpx<T>& operator[](int i) const { return p[pidx(i)]; }
 };
 
-template <typename T, int P, int E, int NS, bool INV>
+// Twiddles of a thread's butterflies, loaded once per kernel into registers
+// and reused by every line the thread transforms (forward and inverse).
+// Stage with sub-length NS and radix RAD (not the first): butterfly b of
+// thread t has j = t + b TT, k = j % NS and multiplies input r by
+// W_{NS RAD}^{r k} = tw[r k P / (NS RAD)].
+template <int P, int E, int NS>
+constexpr int tw_count() {
+  constexpr int RAD = (P / NS < E) ? P / NS : E;
+  constexpr int here = (NS == 1) ? 0 : (E / RAD) * (RAD - 1);
+  if constexpr (NS * RAD == P)
+    return here;
+  else
+    return here + tw_count<P, E, NS * RAD>();
+}
+
+template <typename T, int P, int E, int NS, int OFF>
+__device__ __forceinline__ void tw_load(cpx<T>* w, int t, const cpx<T>* __restrict__ tw) {
+  constexpr int RAD = (P / NS < E) ? P / NS : E;
+  constexpr int NB = E / RAD, TT = P / E;
+  constexpr int here = (NS == 1) ? 0 : NB * (RAD - 1);
+  if constexpr (NS != 1) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int k = (t + b * TT) % NS;
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) w[OFF + b * (RAD - 1) + r - 1] = tw[r * k * (P / (NS * RAD))];
+    }
+  }
+  if constexpr (NS * RAD != P) tw_load<T, P, E, NS * RAD, OFF + here>(w, t, tw);
+}
+
+template <typename T, int P, int E>
+struct TwReg {
+  static constexpr int N = tw_count<P, E, 1>() > 0 ? tw_count<P, E, 1>() : 1;
+  cpx<T> w[N];
+  __device__ __forceinline__ void load(int t, const cpx<T>* __restrict__ tw) {
+    tw_load<T, P, E, 1, 0>(w, t, tw);
+  }
+};
+
+template <typename T, int P, int E, int NS, bool INV, int OFF>
 __device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int t,
-                                             const cpx<T>* __restrict__ tw) {
+                                             const cpx<T>* __restrict__ w) {
   constexpr int RAD = (P / NS < E) ? P / NS : E;
   constexpr int NB = E / RAD;
   constexpr int TT = P / E;
   constexpr bool FIRST = (NS == 1);
   constexpr bool LAST = (NS * RAD == P);
+  constexpr int here = FIRST ? 0 : NB * (RAD - 1);
   cpx<T> u[E];
   if constexpr (FIRST) {
 #pragma unroll
@@ -48,14 +89,13 @@ __device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int j = t + b * TT;
-      const int k = j % NS;
 #pragma unroll
       for (int r = 0; r < RAD; ++r) {
         cpx<T> x = lds[j + r * (P / RAD)];
         if (r > 0) {
-          cpx<T> w = tw[r * k * (P / (NS * RAD))];
-          if (INV) w.im = -w.im;
-          x = x * w;
+          cpx<T> ww = w[OFF + b * (RAD - 1) + r - 1];
+          if (INV) ww.im = -ww.im;
+          x = x * ww;
         }
         u[b * RAD + r] = x;
       }
@@ -78,14 +118,14 @@ __device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int
       for (int r = 0; r < RAD; ++r) lds[base + r * NS] = u[b * RAD + r];
     }
     __syncthreads();
-    fft_stages_p<T, P, E, NS * RAD, INV>(v, lds, t, tw);
+    fft_stages_p<T, P, E, NS * RAD, INV, OFF + here>(v, lds, t, w);
   }
 }
 
 template <typename T, int P, bool INV>
 __device__ __forceinline__ void line_fft(cpx<T> (&v)[fft_e<P>()], cpx<T>* line, int t,
-                                         const cpx<T>* __restrict__ tw) {
-  fft_stages_p<T, P, fft_e<P>(), 1, INV>(v, LdsLine<T>{line}, t, tw);
+                                         const TwReg<T, P, fft_e<P>()>& tr) {
+  fft_stages_p<T, P, fft_e<P>(), 1, INV, 0>(v, LdsLine<T>{line}, t, tr.w);
 }
 
 template <typename T>
@@ -109,6 +149,8 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd(
   const bool valid = line < lines_per_rhs;
   const size_t gl = (size_t)rhs * lines_per_rhs + (valid ? line : 0);
   const cpx<TI>* xin = x + gl * N1;
+  TwReg<T, P, E> tr;
+  tr.load(t, tw);
   cpx<T> v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
@@ -118,7 +160,7 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd(
     else
       v[q] = mk<T>(0, 0);
   }
-  line_fft<T, P, false>(v, lds + li * Pad<P>::LSTR, t, tw);
+  line_fft<T, P, false>(v, lds + li * Pad<P>::LSTR, t, tr);
   if (valid) {
     cpx<T>* o = out + gl * P;
 #pragma unroll
@@ -129,12 +171,23 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd(
 // ------------------------------------------------------ strided (Y, or Z)
 // Lines run along a strided axis; W = NT/TT neighbouring columns (unit stride)
 // per workgroup so every row access is a contiguous W-element run.
-// slab s = s_hi * n_lo + s_lo; element (row, col) of slab s at
-// s_hi*stride_hi + s_lo*stride_lo + row*row_stride + col.
-struct StridedArgs {
-  int n_in_rows, n_out_rows, ncols, n_lo, tiles, slabs_per_rhs;
-  int64_t in_row, out_row, in_lo, out_lo, in_hi, out_hi;
+// Slab s = (rhs, comp, z) with z split as (z / zl, z % zl); each side
+// addresses element (row, col) of a slab at
+//   rhs*rs + comp*cs + (z/zl)*zhs + (z%zl)*zls + row*row_stride + col.
+// The z split lets a buffer keep zl consecutive z planes next to each other
+// (blocked layout), so that both the y pass and the z pass touch only a few
+// memory pages per workgroup.
+struct SideAddr {
+  int64_t rs, cs, zhs, zls, row;
 };
+struct StridedArgs {
+  int n_in_rows, n_out_rows, ncols, tiles, ncomp, nz, zl;
+  SideAddr in, out;
+};
+
+__device__ __forceinline__ int64_t slab_base(const SideAddr& a, int rhs, int comp, int z, int zl) {
+  return rhs * a.rs + comp * a.cs + (z / zl) * a.zhs + (z % zl) * a.zls;
+}
 
 template <typename T, int P, bool PAD, bool TRUNC, bool INV>
 __global__ __launch_bounds__(nt_lines<T>()) void k_fft_strided(
@@ -144,120 +197,155 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_strided(
   __shared__ cpx<T> lds[W * Pad<P>::LSTR];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = b % a.tiles, s = b / a.tiles;
-  if (active && !active[s / a.slabs_per_rhs]) return;
-  const int s_hi = s / a.n_lo, s_lo = s % a.n_lo;
+  const int per_rhs = a.ncomp * a.nz;
+  const int rhs = s / per_rhs, cz = s % per_rhs;
+  if (active && !active[rhs]) return;
+  const int comp = cz / a.nz, z = cz % a.nz;
   const int cw = threadIdx.x % W, t = threadIdx.x / W;
   const int col = tile * W + cw;
   const bool valid = col < a.ncols;
-  const cpx<T>* pin = in + s_hi * a.in_hi + s_lo * a.in_lo + (valid ? col : 0);
+  const cpx<T>* pin = in + slab_base(a.in, rhs, comp, z, a.zl) + (valid ? col : 0);
+  TwReg<T, P, E> tr;
+  tr.load(t, tw);
   cpx<T> v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int row = t + q * TT;
     if ((!PAD || q < E / 2) && valid && row < a.n_in_rows)
-      v[q] = pin[(int64_t)row * a.in_row];
+      v[q] = pin[(int64_t)row * a.in.row];
     else
       v[q] = mk<T>(0, 0);
   }
-  line_fft<T, P, INV>(v, lds + cw * Pad<P>::LSTR, t, tw);
+  line_fft<T, P, INV>(v, lds + cw * Pad<P>::LSTR, t, tr);
   if (valid) {
-    cpx<T>* po = out + s_hi * a.out_hi + s_lo * a.out_lo + col;
+    cpx<T>* po = out + slab_base(a.out, rhs, comp, z, a.zl) + col;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int row = t + q * TT;
-      if ((!TRUNC || q < E / 2) && row < a.n_out_rows) po[(int64_t)row * a.out_row] = v[q];
+      if ((!TRUNC || q < E / 2) && row < a.n_out_rows) po[(int64_t)row * a.out.row] = v[q];
     }
   }
 }
 
 // ----------------------------------------------- Z fused with the spectrum
-// Workgroup: W neighbouring xi_x columns at one xi_y, all 3 components of one
-// right-hand side.  Forward z-FFT (pad), symmetric 3x3 multiply with the
-// octant spectrum (sign from each component's parity on mirrored axes),
-// inverse z-FFT (truncate), in place.
+// Workgroup: W neighbouring xi_x columns at one xi_y of one right-hand side.
+// Each thread owns one column's points t + q TT for all three Cartesian
+// components (registers), transforms them one after another through the
+// column's LDS line (forward, pad N3 -> P), applies the symmetric 3x3
+// spectrum point by point in registers (six unique entries per point, sign
+// from each component's parity on mirrored axes), transforms back and keeps
+// z < N3.  In place on B.
+// Launch shapes tried by the autotuner: (points per thread E, threads NT).
+// W = NT E / P columns per workgroup; LDS = W padded lines.
+struct ZShape {
+  int e, nt;
+};
 template <typename T>
-constexpr int zw(int P) {
-  return (sizeof(T) == 8 ? 1024 : 2048) / P;
+constexpr ZShape zshape(int v) {
+  // FP32: 3 x 16 complex in registers / 3 x 8; FP64: 3 x 8 / 3 x 4
+  return sizeof(T) == 4 ? (v == 0 ? ZShape{16, 256} : v == 1 ? ZShape{8, 512} : ZShape{8, 256})
+                        : (v == 0 ? ZShape{8, 256} : v == 1 ? ZShape{4, 512} : ZShape{4, 256});
+}
+static constexpr int kZVariants = 3;
+template <int P, int E0>
+constexpr int zcap() {
+  return E0 < P ? E0 : P;
 }
 
 struct ZArgs {
-  int N3, P1, P2, Q1, Q2, Q3, tiles_x, nrhs;
-  int64_t comp_stride, rhs_stride;
+  int N3, P1, P2, Q1, Q2, Q3, tiles_x, nrhs, zl;
+  int64_t comp_stride, rhs_stride, zhs, zls;  // blocked layout of B (see StridedArgs)
 };
 
-__device__ __forceinline__ int sym_index(int a, int b) {
-  // xx, xy, xz, yy, yz, zz
-  const int lo = a < b ? a : b, hi = a < b ? b : a;
-  return lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+// Stockham stages with an explicit points-per-thread E (may differ from fft_e<P>).
+template <typename T, int P, int E, bool INV>
+__device__ __forceinline__ void line_fft_e(cpx<T> (&v)[E], cpx<T>* line, int t,
+                                           const TwReg<T, P, E>& tr) {
+  fft_stages_p<T, P, E, 1, INV, 0>(v, LdsLine<T>{line}, t, tr.w);
 }
 
-template <typename T, int P>
-__global__ __launch_bounds__(3 * zw<T>(P) * (P / fft_e<P>())) void k_fft_z_green(
+template <typename T, int P, int E, int NT>
+__global__ __launch_bounds__(NT) void k_fft_z_green(
     cpx<T>* __restrict__ B, const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw,
     ZArgs a, const int* __restrict__ active) {
-  constexpr int E = fft_e<P>(), TT = P / E, W = zw<T>(P), LS = Pad<P>::LSTR;
-  __shared__ cpx<T> lds[3 * W * LS];
+  constexpr int TT = P / E, W = NT / TT, LS = Pad<P>::LSTR;
+  __shared__ cpx<T> lds[W * LS];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  // right-hand sides innermost: blocks sharing a spectrum pencil are adjacent
+  // Block order (innermost first): right-hand side, +-xi_y mirror, x tile
+  // taken in mirror pairs (k, tiles-1-k), y octant row.  Blocks that read the
+  // same spectrum slice are adjacent, hence resident on one XCD together.
   const int rhs = b % a.nrhs;
-  const int tile = (b / a.nrhs) % a.tiles_x;
-  const int xy = (b / a.nrhs) / a.tiles_x;
+  const int u = b / a.nrhs;
+  const int m = u & 1;
+  const int it = (u >> 1) % a.tiles_x;
+  const int yp = (u >> 1) / a.tiles_x;
+  if (m && (yp == 0 || 2 * yp == a.P2)) return;  // self-mirrored row: one block only
+  const int xy = m ? a.P2 - yp : yp;
+  const int tile = (it & 1) ? a.tiles_x - 1 - (it >> 1) : (it >> 1);
   if (active && !active[rhs]) return;
-  const int comp = threadIdx.x / (W * TT);
-  const int rem = threadIdx.x % (W * TT);
-  const int cw = rem % W, t = rem / W;
+  const int cw = threadIdx.x % W, t = threadIdx.x / W;
   const int xx = tile * W + cw;
   const bool valid = xx < a.P1;
-  const int64_t zs = (int64_t)a.P2 * a.P1;
-  cpx<T>* col = B + rhs * a.rhs_stride + comp * a.comp_stride + (int64_t)xy * a.P1 + (valid ? xx : 0);
-  cpx<T> v[E];
+  // B[rhs][comp][z / zl][xi_y][z % zl][xi_x]
+  cpx<T>* col = B + rhs * a.rhs_stride + (int64_t)xy * a.zl * a.P1 + (valid ? xx : 0);
+  int64_t zoff[E / 2];
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int z = t + q * TT;
+    zoff[q] = (z / a.zl) * a.zhs + (z % a.zl) * a.zls;
+  }
+  TwReg<T, P, E> tr;
+  tr.load(t, tw);
+  cpx<T> v0[E], v1[E], v2[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int z = t + q * TT;
-    if (q < E / 2 && valid && z < a.N3)
-      v[q] = col[z * zs];
-    else
-      v[q] = mk<T>(0, 0);
+    if (q < E / 2 && valid && z < a.N3) {
+      v0[q] = col[zoff[q]];
+      v1[q] = col[a.comp_stride + zoff[q]];
+      v2[q] = col[2 * a.comp_stride + zoff[q]];
+    } else {
+      v0[q] = v1[q] = v2[q] = mk<T>(0, 0);
+    }
   }
-  cpx<T>* myline = lds + (comp * W + cw) * LS;
-  line_fft<T, P, false>(v, myline, t, tw);
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < E; ++q) myline[pidx(t + q * TT)] = v[q];
-  __syncthreads();
-  // octant coordinates and mirror flags
+  cpx<T>* line = lds + cw * LS;
+  line_fft_e<T, P, E, false>(v0, line, t, tr);
+  line_fft_e<T, P, E, false>(v1, line, t, tr);
+  line_fft_e<T, P, E, false>(v2, line, t, tr);
+  // octant coordinates and mirror flags; spectrum layout [yo][ab][zo][xo]
   const int xm = xx > a.P1 / 2, ym = xy > a.P2 / 2;
   const int xo = xm ? a.P1 - xx : xx, yo = ym ? a.P2 - xy : xy;
-  const int64_t oct = (int64_t)a.Q3 * a.Q2 * a.Q1;
+  const int64_t oct = (int64_t)a.Q3 * a.Q1;
+  const cpx<T>* sxy = spec + (int64_t)yo * 6 * oct + (valid ? xo : 0);
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int z = t + q * TT;
     const int zm = z > P / 2;
     const int zo = zm ? P - z : z;
-    const cpx<T>* sp = spec + ((int64_t)zo * a.Q2 + yo) * a.Q1 + (valid ? xo : 0);
-    cpx<T> acc = mk<T>(0, 0);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const cpx<T> in_c = (c == comp) ? v[q] : lds[(c * W + cw) * LS + pidx(z)];
-      cpx<T> g = sp[sym_index(comp, c) * oct];
-      // odd along axis e iff exactly one of (comp, c) equals e
-      int neg = 0;
-      if (comp != c) {
-        if ((comp == 0) != (c == 0)) neg ^= xm;
-        if ((comp == 1) != (c == 1)) neg ^= ym;
-        if ((comp == 2) != (c == 2)) neg ^= zm;
-      }
-      if (neg) g = mk<T>(-g.re, -g.im);
-      acc = cfma(g, in_c, acc);
-    }
-    v[q] = acc;
+    const cpx<T>* sp = sxy + (int64_t)zo * a.Q1;
+    const cpx<T> gxx = sp[0], gyy = sp[3 * oct], gzz = sp[5 * oct];
+    cpx<T> gxy = sp[oct], gxz = sp[2 * oct], gyz = sp[4 * oct];
+    // G_ab is odd along axis e iff exactly one of a, b equals e
+    if (xm ^ ym) gxy = mk<T>(-gxy.re, -gxy.im);
+    if (xm ^ zm) gxz = mk<T>(-gxz.re, -gxz.im);
+    if (ym ^ zm) gyz = mk<T>(-gyz.re, -gyz.im);
+    const cpx<T> ix = v0[q], iy = v1[q], iz = v2[q];
+    v0[q] = cfma(gxz, iz, cfma(gxy, iy, gxx * ix));
+    v1[q] = cfma(gyz, iz, cfma(gyy, iy, gxy * ix));
+    v2[q] = cfma(gzz, iz, cfma(gyz, iy, gxz * ix));
   }
-  line_fft<T, P, true>(v, myline, t, tw);
+  line_fft_e<T, P, E, true>(v0, line, t, tr);
+  line_fft_e<T, P, E, true>(v1, line, t, tr);
+  line_fft_e<T, P, E, true>(v2, line, t, tr);
   if (valid) {
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
       const int z = t + q * TT;
-      if (z < a.N3) col[z * zs] = v[q];
+      if (z < a.N3) {
+        col[zoff[q]] = v0[q];
+        col[a.comp_stride + zoff[q]] = v1[q];
+        col[2 * a.comp_stride + zoff[q]] = v2[q];
+      }
     }
   }
 }
@@ -317,13 +405,15 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv(
   const bool valid = line < a.lines_per_rhs;
   const int lc = valid ? line : 0;
   const size_t gl = (size_t)rhs * a.lines_per_rhs + lc;
+  TwReg<T, P, E> tr;
+  tr.load(t, tw);
   cpx<T> v[E];
   {
     const cpx<T>* src = A + gl * P;
 #pragma unroll
     for (int q = 0; q < E; ++q) v[q] = valid ? src[t + q * TT] : mk<T>(0, 0);
   }
-  line_fft<T, P, true>(v, lds + li * Pad<P>::LSTR, t, tw);
+  line_fft<T, P, true>(v, lds + li * Pad<P>::LSTR, t, tr);
   const int comp = lc / a.lines_per_comp, sp = lc % a.lines_per_comp;  // sp = z*N2 + y
   const double* chib = chi + (int64_t)rhs_body[rhs] * a.n + (int64_t)sp * a.N1;
   c64 s0 = mk(0.0, 0.0), s1 = mk(0.0, 0.0);
@@ -402,33 +492,58 @@ static hipError_t x_fwd(const GroupGeom& g, const c64* x, cpx<T>* A, const cpx<T
   return hipGetLastError();
 }
 
+// Scratch layouts: A[rhs][comp][z][y][xi_x] (x pass side),
+// B[rhs][comp][z / zl][xi_y][z % zl][xi_x] (z pass side).
+static SideAddr side_A(const GroupGeom& g, int zl) {
+  SideAddr s;
+  const int64_t plane = (int64_t)g.N[1] * g.P[0];
+  s.row = g.P[0];
+  s.zls = plane;
+  s.zhs = plane * zl;
+  s.cs = plane * g.N[2];
+  s.rs = s.cs * 3;
+  return s;
+}
+static SideAddr side_B(const GroupGeom& g, int zl) {
+  SideAddr s;
+  const int nzh = (g.N[2] + zl - 1) / zl;
+  s.row = (int64_t)zl * g.P[0];
+  s.zls = g.P[0];
+  s.zhs = (int64_t)g.P[1] * zl * g.P[0];
+  s.cs = s.zhs * nzh;
+  s.rs = s.cs * 3;
+  return s;
+}
+int z_block(const GroupGeom& g) { return g.N[2] < 16 ? g.N[2] : 16; }
+int64_t bufB_elems(const GroupGeom& g) {
+  const int zl = z_block(g);
+  return side_B(g, zl).rs;  // per right-hand side
+}
+
 template <typename T>
 static hipError_t y_pass(const GroupGeom& g, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw,
                          bool inverse, const int* active, hipStream_t s) {
   const int P1 = g.P[0], P2 = g.P[1], N2 = g.N[1], N3 = g.N[2];
+  const int zl = z_block(g);
   StridedArgs a;
   a.ncols = P1;
-  a.n_lo = 3 * N3;  // (comp, z) slabs; s_hi = rhs
-  a.slabs_per_rhs = 3 * N3;
+  a.ncomp = 3;
+  a.nz = N3;
+  a.zl = zl;
   const int W = lines_per_block<T>(P2);
   a.tiles = (P1 + W - 1) / W;
+  const SideAddr A = side_A(g, zl), B = side_B(g, zl);
   if (!inverse) {
     a.n_in_rows = N2;
     a.n_out_rows = P2;
-    a.in_row = P1;
-    a.out_row = P1;
-    a.in_lo = (int64_t)N2 * P1;
-    a.out_lo = (int64_t)P2 * P1;
+    a.in = A;
+    a.out = B;
   } else {
     a.n_in_rows = P2;
     a.n_out_rows = N2;
-    a.in_row = P1;
-    a.out_row = P1;
-    a.in_lo = (int64_t)P2 * P1;
-    a.out_lo = (int64_t)N2 * P1;
+    a.in = B;
+    a.out = A;
   }
-  a.in_hi = a.in_lo * 3 * N3;
-  a.out_hi = a.out_lo * 3 * N3;
   const dim3 grid(a.tiles * 3 * N3 * g.nrhs);
   if (!inverse) {
     VIE_DISPATCH_P(P2, (k_fft_strided<T, PP, true, false, false><<<grid, nt_lines<T>(), 0, s>>>(
@@ -440,9 +555,20 @@ static hipError_t y_pass(const GroupGeom& g, const cpx<T>* in, cpx<T>* out, cons
   return hipGetLastError();
 }
 
+template <typename T, int PP, int V>
+static void z_launch(const GroupGeom& g, ZArgs a, cpx<T>* B, const cpx<T>* spec,
+                     const cpx<T>* tw, const int* active, hipStream_t s) {
+  constexpr ZShape sh = zshape<T>(V);
+  constexpr int E = zcap<PP, sh.e>();
+  constexpr int W = sh.nt / (PP / E);
+  a.tiles_x = (g.P[0] + W - 1) / W;
+  const dim3 grid((g.P[1] / 2 + 1) * 2 * a.tiles_x * g.nrhs);
+  k_fft_z_green<T, PP, E, sh.nt><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
+}
+
 template <typename T>
 static hipError_t z_pass(const GroupGeom& g, cpx<T>* B, const cpx<T>* spec, const cpx<T>* tw,
-                         const int* active, hipStream_t s) {
+                         const int* active, hipStream_t s, int variant) {
   ZArgs a;
   a.N3 = g.N[2];
   a.P1 = g.P[0];
@@ -451,14 +577,18 @@ static hipError_t z_pass(const GroupGeom& g, cpx<T>* B, const cpx<T>* spec, cons
   a.Q2 = g.Q[1];
   a.Q3 = g.Q[2];
   a.nrhs = g.nrhs;
-  a.comp_stride = (int64_t)g.N[2] * g.P[1] * g.P[0];
-  a.rhs_stride = 3 * a.comp_stride;
+  a.zl = z_block(g);
+  const SideAddr sb = side_B(g, a.zl);
+  a.comp_stride = sb.cs;
+  a.rhs_stride = sb.rs;
+  a.zhs = sb.zhs;
+  a.zls = sb.zls;
   VIE_DISPATCH_P(g.P[2], ({
-                   constexpr int W = zw<T>(PP);
-                   constexpr int NT = 3 * W * (PP / fft_e<PP>());
-                   a.tiles_x = (g.P[0] + W - 1) / W;
-                   const dim3 grid(a.tiles_x * g.P[1] * g.nrhs);
-                   k_fft_z_green<T, PP><<<grid, NT, 0, s>>>(B, spec, tw, a, active);
+                   switch (variant) {
+                     case 1: z_launch<T, PP, 1>(g, a, B, spec, tw, active, s); break;
+                     case 2: z_launch<T, PP, 2>(g, a, B, spec, tw, active, s); break;
+                     default: z_launch<T, PP, 0>(g, a, B, spec, tw, active, s); break;
+                   }
                  }));
   return hipGetLastError();
 }
@@ -517,11 +647,22 @@ static hipError_t matvec_t(const MatvecArgs& m, const c64* x, c64* y, EpiArgs& e
   if (err != hipSuccess) return err;
   STEP(0, x_fwd<T>(g, x, A, tw0, m.active, s));
   STEP(1, y_pass<T>(g, A, B, tw1, false, m.active, s));
-  STEP(2, z_pass<T>(g, B, (const cpx<T>*)m.spec, tw2, m.active, s));
+  STEP(2, z_pass<T>(g, B, (const cpx<T>*)m.spec, tw2, m.active, s, m.zvar));
   STEP(3, y_pass<T>(g, B, A, tw1, true, m.active, s));
   STEP(4, x_inv<T>(g, A, x, y, m.chi, m.rhs_body, tw0, e, m.active, s));
 #undef STEP
   return hipSuccess;
+}
+
+int z_variants() { return kZVariants; }
+
+hipError_t launch_z_only(const MatvecArgs& m, int precision, hipStream_t s) {
+  const GroupGeom& g = *m.g;
+  if (precision == 0)
+    return z_pass<double>(g, (c64*)m.bufB, (const c64*)m.spec, (const c64*)m.tw[2], m.active, s,
+                          m.zvar);
+  return z_pass<float>(g, (c32*)m.bufB, (const c32*)m.spec, (const c32*)m.tw[2], m.active, s,
+                       m.zvar);
 }
 
 hipError_t launch_matvec(const MatvecArgs& a, int precision, const c64* x, c64* y, EpiArgs& epi,
@@ -551,13 +692,14 @@ hipError_t launch_fft3d_full(c64* work, c64* tmp, const GroupGeom& g, const void
     StridedArgs a;
     a.n_in_rows = a.n_out_rows = P2;
     a.ncols = P1;
-    a.n_lo = P3;
-    a.slabs_per_rhs = P3;
+    a.ncomp = 1;
+    a.nz = P3;
+    a.zl = 1;
     const int W = lines_per_block<double>(P2);
     a.tiles = (P1 + W - 1) / W;
-    a.in_row = a.out_row = P1;
-    a.in_lo = a.out_lo = (int64_t)P2 * P1;
-    a.in_hi = a.out_hi = 0;
+    a.in.row = a.out.row = P1;
+    a.in.zhs = a.out.zhs = (int64_t)P2 * P1;
+    a.in.zls = a.out.zls = a.in.cs = a.out.cs = a.in.rs = a.out.rs = 0;
     VIE_DISPATCH_P(P2, (k_fft_strided<double, PP, false, false, false>
                         <<<a.tiles * P3, nt_lines<double>(), 0, s>>>(tmp, work, tw1, a, nullptr)));
     hipError_t e = hipGetLastError();
@@ -567,13 +709,14 @@ hipError_t launch_fft3d_full(c64* work, c64* tmp, const GroupGeom& g, const void
     StridedArgs a;
     a.n_in_rows = a.n_out_rows = P3;
     a.ncols = P1;
-    a.n_lo = P2;
-    a.slabs_per_rhs = P2;
+    a.ncomp = 1;
+    a.nz = P2;
+    a.zl = 1;
     const int W = lines_per_block<double>(P3);
     a.tiles = (P1 + W - 1) / W;
-    a.in_row = a.out_row = (int64_t)P2 * P1;
-    a.in_lo = a.out_lo = P1;
-    a.in_hi = a.out_hi = 0;
+    a.in.row = a.out.row = (int64_t)P2 * P1;
+    a.in.zhs = a.out.zhs = P1;
+    a.in.zls = a.out.zls = a.in.cs = a.out.cs = a.in.rs = a.out.rs = 0;
     VIE_DISPATCH_P(P3, (k_fft_strided<double, PP, false, false, false>
                         <<<a.tiles * P2, nt_lines<double>(), 0, s>>>(work, tmp, tw2, a, nullptr)));
   }

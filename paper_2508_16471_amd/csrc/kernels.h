@@ -20,6 +20,8 @@ struct KState {
   int breakdown;   // 1 if the last cycle ended on a BiCGSTAB breakdown
   int notdone;     // 1 while the true residual is above tol
   double rh2;      // ||rhat||^2 (shadow residual of the current cycle)
+  int cycles;      // FP64 true-residual products (restarts) so far
+  int pad_;
 };
 
 // Epilogue of the inverse-x pass (y = x - chi * conv, then):
@@ -47,8 +49,9 @@ struct MatvecArgs {
   const void* spec;        // octant spectrum, c64 or c32 per precision
   const void* tw[3];       // twiddle tables per axis (c64 or c32)
   void* bufA;              // x-transformed scratch [nrhs][3][N3][N2][P1]
-  void* bufB;              // y-transformed scratch [nrhs][3][N3][P2][P1]
+  void* bufB;              // y-transformed scratch [nrhs][3][N3/zl][P2][zl][P1]
   const int* active;       // [nrhs] or nullptr
+  int zvar = 0;            // launch shape of the z pass (autotuned per group/precision)
 };
 
 // precision 0: FP64 passes, 1: FP32 passes (input/output vectors are FP64)
@@ -64,10 +67,15 @@ struct EpiArgs {
 };
 
 int part_blocks_xinv(const GroupGeom& g, int precision);
+int z_block(const GroupGeom& g);        // z planes kept adjacent in the y/z scratch
+int64_t bufB_elems(const GroupGeom& g);  // y/z scratch elements per right-hand side
 int vec_blocks(const GroupGeom& g);
 
 hipError_t launch_matvec(const MatvecArgs& a, int precision, const c64* x, c64* y, EpiArgs& epi,
                          hipStream_t s, void (*ev_cb)(int kind, bool begin, void* u), void* u);
+int z_variants();
+// z pass alone on bufB (autotuning; contents are scratch)
+hipError_t launch_z_only(const MatvecArgs& a, int precision, hipStream_t s);
 
 // Green spectrum: sample the circulant kernel of component ab into
 // work[P3][P2][P1] (c64).

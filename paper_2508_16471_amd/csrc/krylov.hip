@@ -219,6 +219,9 @@ __global__ __launch_bounds__(VT) void k_finalize(int which, int nrhs, int nblk,
       if (which == FIN_INIT) {
         S.bnorm2 = b.re;
         S.iters = 0;
+        S.cycles = 0;
+      } else {
+        S.cycles += 1;  // one FP64 residual product ran for this right-hand side
       }
       S.rnorm2 = b.re;
       S.rh2 = b.re;
