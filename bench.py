@@ -99,9 +99,11 @@ def post_process(V, ctx, nb, nch, theta, phi, dtau):
 
 
 # ------------------------------------------------------------ byte model
-def kernel_bytes(kind, N, P, Q, epi_extra=0):
+def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None):
     """Algorithmic HBM bytes of one right-hand-side execution of a pass
-    (spectrum excluded; it is charged once per launch)."""
+    (spectrum excluded; it is charged once per launch).  nb: body voxels when
+    the solver's vectors are body-compressed (x passes read/write 3 nb
+    values plus the voxel index and line pointers), None for box vectors."""
     N1, N2, N3 = N
     P1, P2, P3 = P
     n = N1 * N2 * N3
@@ -109,6 +111,8 @@ def kernel_bytes(kind, N, P, Q, epi_extra=0):
     A = 3 * N3 * N2 * P1
     B = 3 * N3 * P2 * P1
     if kind.startswith("fft_x_fwd"):
+        if nb is not None:
+            return 3 * nb * (16 + 4) + 3 * (N2 * N3 + 1) * 4 + A * c
         return 3 * n * 16 + A * c
     if kind.startswith("fft_y_fwd"):
         return A * c + B * c
@@ -117,6 +121,8 @@ def kernel_bytes(kind, N, P, Q, epi_extra=0):
     if kind.startswith("fft_y_inv"):
         return B * c + A * c
     if kind.startswith("fft_x_inv"):
+        if nb is not None:
+            return A * c + 3 * nb * (16 * 2 + 8 + 4) + 3 * (N2 * N3 + 1) * 4 + epi_extra
         return A * c + 3 * n * 16 * 2 + n * 8 + epi_extra
     raise KeyError(kind)
 
@@ -126,9 +132,9 @@ def spectrum_bytes(kind, Q):
     return 6 * Q[0] * Q[1] * Q[2] * c
 
 
-def roofline_from_times(times, stats, N, P, Q, mixed):
-    """Achieved GB/s of every FFT pass over the timed region."""
-    n = N[0] * N[1] * N[2]
+def roofline_from_times(times, stats, N, P, Q, mixed, nb):
+    """Achieved GB/s of every FFT pass over the timed region (nb: mean body
+    voxels per right-hand side; the solver's vectors are body-compressed)."""
     iters = np.array([s["iters"] for s in stats])
     cyc = np.array([s["cycles"] for s in stats])
     rows = {}
@@ -144,8 +150,8 @@ def roofline_from_times(times, stats, N, P, Q, mixed):
             launches_active = int(2 * iters.max() + cyc.max())
         extra = 0
         if kind.startswith("fft_x_inv"):
-            extra = 3 * n * 16 // 2  # rhat read (v = A p) or written (restart), on average
-        by = execs * kernel_bytes(kind, N, P, Q, extra)
+            extra = 3 * nb * 16 // 2  # rhat read (v = A p) or written (restart), on average
+        by = execs * kernel_bytes(kind, N, P, Q, extra, nb=nb)
         if kind.startswith("fft_z_green"):
             by += launches_active * spectrum_bytes(kind, Q)
         rows[kind] = {"ms_total": ms, "launches": int(cnt), "rhs_execs": execs,
@@ -310,7 +316,8 @@ def main():
     times = V.vie_kernel_times(ctx, reset=True)
     solves = args.steps * nb * nch
     value = solves / dt
-    fast_rows = roofline_from_times(times, all_stats, N, P, Q, mixed=True)
+    nb_mean = float(np.mean([(e > 1).sum() for e, _, _, _ in bodies]))
+    fast_rows = roofline_from_times(times, all_stats, N, P, Q, mixed=True, nb=nb_mean)
     dom = max(fast_rows, key=lambda k: fast_rows[k]["ms_total"])
     d = fast_rows[dom]
     conv = all(s["converged"] for s in all_stats)
@@ -336,7 +343,7 @@ def main():
         torch.cuda.synchronize()
         pdt = time.perf_counter() - t0
         ptimes = V.vie_kernel_times(ctx, reset=True)
-        prow = roofline_from_times(ptimes, ps, N, P, Q, mixed=False)
+        prow = roofline_from_times(ptimes, ps, N, P, Q, mixed=False, nb=nb_mean)
         plain = {"solves_per_s": args.plain_solves / pdt,
                  "iters_mean": float(np.mean([s["iters"] for s in ps])),
                  "products_mean": float(np.mean([s["matvecs"] for s in ps])),

@@ -56,9 +56,8 @@ int pow2_at_least(int v) {
 
 struct BodyRec {
   int group;       // group index
-  int slot;        // body index inside the group's chi array
+  int slot;        // body index inside the group
   int nb;          // body voxels (chi != 0)
-  DevBuf vox;      // int[nb] linear indices of body voxels
   double origin[3];
   int rhs0 = 0, nrhs = 0;  // right-hand sides of this body inside the group (last solve)
 };
@@ -70,9 +69,17 @@ struct Group {
   DevBuf chi;                    // double[nb][n]
   DevBuf spec64, spec32;         // octant spectra [6][Q3][Q2][Q1]
   DevBuf tw64[3], tw32[3];       // twiddles per axis
-  // per-solve storage (capacity in right-hand sides)
+  // body-compressed index data of every body of the group (see BodyIdx)
+  DevBuf vox_all, chic_all, line_ptr_all, nb_arr, voff_arr;
+  std::vector<int> vox_host, nb_host, voff_host;
+  int max_nb = 0;
+  // per-solve storage (capacity in right-hand sides / compressed elements)
   int cap = 0;
-  DevBuf x, r, rh, p, v, s, t;   // c64 [cap][3n]
+  int64_t vec_cap = 0;
+  DevBuf roff;                   // int64 [cap] vector offset of each right-hand side
+  std::vector<int64_t> roff_host;
+  BodyIdx bi;
+  DevBuf x, r, rh, p, v, s, t;   // c64, body-compressed, all right-hand sides
   DevBuf bufA, bufB;             // FFT scratch (sized for FP64)
   DevBuf partials;               // c64 [cap][maxblk][2]
   DevBuf state;                  // KState [cap]
@@ -295,16 +302,41 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
       if (c != 0.0) vox.push_back((int)i);
     }
     rec->nb = (int)vox.size();
-    if (!vox.empty()) {
-      if (rec->vox.reserve(vox.size() * sizeof(int)) != hipSuccess) return bail(VIE_ENOMEM);
-      if (hipMemcpy(rec->vox.p, vox.data(), vox.size() * sizeof(int), hipMemcpyHostToDevice) !=
-          hipSuccess)
-        return bail(VIE_EDEVICE);
-    }
+    G.voff_host.push_back((int)G.vox_host.size());
+    G.nb_host.push_back(rec->nb);
+    G.max_nb = std::max(G.max_nb, rec->nb);
+    G.vox_host.insert(G.vox_host.end(), vox.begin(), vox.end());
     ctx->bodies.push_back(std::move(rec));
   }
   for (size_t gi = 0; gi < ctx->groups.size(); ++gi) {
     Group& G = *ctx->groups[gi];
+    // compressed index data: line pointers and chi at body voxels
+    const int nl = G.g.N[1] * G.g.N[2];
+    const int nbod = (int)G.bodies.size();
+    std::vector<int> lp((size_t)nbod * (nl + 1), 0);
+    std::vector<double> chic(G.vox_host.size());
+    for (int sl = 0; sl < nbod; ++sl) {
+      const int* vx = G.vox_host.data() + G.voff_host[sl];
+      int* L = lp.data() + (size_t)sl * (nl + 1);
+      for (int k = 0; k < G.nb_host[sl]; ++k) {
+        L[vx[k] / G.g.N[0] + 1] += 1;
+        chic[G.voff_host[sl] + k] = chi_host[gi][(size_t)sl * G.g.n + vx[k]];
+      }
+      for (int z = 0; z < nl; ++z) L[z + 1] += L[z];
+    }
+    auto up = [&](DevBuf& d, const void* src, size_t bytes) {
+      if (d.reserve(std::max<size_t>(bytes, 8)) != hipSuccess) return VIE_ENOMEM;
+      if (bytes && hipMemcpy(d.p, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+        return VIE_EDEVICE;
+      return VIE_OK;
+    };
+    int urc;
+    if ((urc = up(G.vox_all, G.vox_host.data(), G.vox_host.size() * sizeof(int))) != VIE_OK ||
+        (urc = up(G.chic_all, chic.data(), chic.size() * sizeof(double))) != VIE_OK ||
+        (urc = up(G.line_ptr_all, lp.data(), lp.size() * sizeof(int))) != VIE_OK ||
+        (urc = up(G.nb_arr, G.nb_host.data(), G.nb_host.size() * sizeof(int))) != VIE_OK ||
+        (urc = up(G.voff_arr, G.voff_host.data(), G.voff_host.size() * sizeof(int))) != VIE_OK)
+      return bail(urc);
     if (G.chi.reserve(chi_host[gi].size() * sizeof(double)) != hipSuccess) return bail(VIE_ENOMEM);
     if (hipMemcpy(G.chi.p, chi_host[gi].data(), chi_host[gi].size() * sizeof(double),
                   hipMemcpyHostToDevice) != hipSuccess)
@@ -366,23 +398,33 @@ extern "C" int vie_set_options(vie_ctx* ctx, const vie_options* opt) {
 }
 
 // -------------------------------------------------------------- workspace
+static int vec_blocks_group(const Group& G) { return vec_blocks_n(3 * (int64_t)G.max_nb); }
+
+// Krylov vectors of all right-hand sides (body-compressed, vec_len elements).
+static int ensure_vectors(vie_ctx* ctx, Group& G, int64_t vec_len) {
+  if (vec_len <= G.vec_cap) return VIE_OK;
+  DevBuf* vs[] = {&G.x, &G.r, &G.rh, &G.p, &G.v, &G.s, &G.t};
+  for (DevBuf* b : vs) VIE_HIP(b->reserve((size_t)vec_len * sizeof(c64)));
+  G.vec_cap = vec_len;
+  return VIE_OK;
+}
+
+// Scratch and per-right-hand-side arrays for nrhs right-hand sides.
 static int ensure_solve_storage(vie_ctx* ctx, Group& G, int nrhs) {
   if (nrhs <= G.cap) return VIE_OK;
-  const size_t vec = (size_t)3 * G.g.n * sizeof(c64);
-  DevBuf* vs[] = {&G.x, &G.r, &G.rh, &G.p, &G.v, &G.s, &G.t};
-  for (DevBuf* b : vs) VIE_HIP(b->reserve(vec * nrhs));
   const size_t a = (size_t)3 * G.g.N[2] * G.g.N[1] * G.g.P[0] * sizeof(c64);
   const size_t bb = (size_t)bufB_elems(G.g) * sizeof(c64);
   VIE_HIP(G.bufA.reserve(a * nrhs));
   VIE_HIP(G.bufB.reserve(bb * nrhs));
   const int maxblk = std::max(std::max(part_blocks_xinv(G.g, 0), part_blocks_xinv(G.g, 1)),
-                              vec_blocks(G.g));
+                              vec_blocks_group(G));
   VIE_HIP(G.partials.reserve((size_t)nrhs * maxblk * 2 * sizeof(c64)));
   VIE_HIP(G.state.reserve((size_t)nrhs * sizeof(KState)));
   VIE_HIP(G.flags.reserve((size_t)2 * nrhs * sizeof(int)));
   VIE_HIP(G.rhs_body.reserve((size_t)nrhs * sizeof(int)));
   VIE_HIP(G.pol.reserve((size_t)nrhs * 3 * sizeof(c64)));
   VIE_HIP(G.ph.reserve((size_t)nrhs * (G.g.N[0] + G.g.N[1] + G.g.N[2]) * sizeof(c64)));
+  VIE_HIP(G.roff.reserve((size_t)nrhs * sizeof(int64_t)));
   G.cap = nrhs;
   return VIE_OK;
 }
@@ -461,10 +503,11 @@ static hipError_t tune_z(vie_ctx* ctx, Group& G, int precision) {
 }
 
 static hipError_t run_matvec(vie_ctx* ctx, Group& G, int precision, const c64* x, c64* y,
-                             EpiArgs& e, const int* active) {
+                             EpiArgs& e, const int* active, bool compressed = true) {
   hipError_t te = tune_z(ctx, G, precision);
   if (te != hipSuccess) return te;
   MatvecArgs m = matvec_args(G, precision, active);
+  if (compressed) m.bi = &G.bi;
   return launch_matvec(m, precision, x, y, e, ctx->stream, timing_on(ctx) ? timing_cb : nullptr,
                        ctx);
 }
@@ -490,17 +533,16 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
   int* active = flags;
   int* notdone = flags + nrhs;
   c64* part = G.partials.as<c64>();
-  const int vb = vec_blocks(g);
+  const int vb = vec_blocks_group(G);
+  const BodyIdx& bi = G.bi;
   c64 *x = G.x.as<c64>(), *r = G.r.as<c64>(), *rh = G.rh.as<c64>(), *p = G.p.as<c64>(),
       *v = G.v.as<c64>(), *s = G.s.as<c64>(), *t = G.t.as<c64>();
-  const double* chi = G.chi.as<double>();
-  const int* rb = G.rhs_body.as<int>();
   const c64* pol = G.pol.as<c64>();
   const c64* ph = G.ph.as<c64>();
   fallback_out.assign(nrhs, 0);
 
   VIE_HIP(timed(ctx, 13, [&] {
-    return launch_init_zero_guess(g, chi, rb, pol, ph, x, r, rh, part, warm ? 1 : 0, nullptr,
+    return launch_init_zero_guess(g, bi, vb, pol, ph, x, r, rh, part, warm ? 1 : 0, nullptr,
                                   ctx->stream);
   }));
   VIE_HIP(timed(ctx, 11, [&] {
@@ -531,7 +573,7 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
       VIE_HIP(dmask.reserve(nrhs * sizeof(int)));
       VIE_HIP(hipMemcpyAsync(dmask.p, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
                              ctx->stream));
-      VIE_HIP(launch_init_zero_guess(g, chi, rb, pol, ph, x, r, rh, part, 0, dmask.as<int>(),
+      VIE_HIP(launch_init_zero_guess(g, bi, vb, pol, ph, x, r, rh, part, 0, dmask.as<int>(),
                                      ctx->stream));
       // FIN_INIT only for the masked right-hand sides: reuse notdone as gate by
       // running FIN_RESTART semantics after re-initialising (bnorm2 unchanged).
@@ -561,20 +603,22 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
     // iterate until every right-hand side has left the cycle (lagged check)
     int64_t k = 0;
     for (;; ++k) {
-      VIE_HIP(timed(ctx, 10, [&] { return launch_update_p(g, st, active, r, p, v, ctx->stream); }));
+      VIE_HIP(timed(ctx, 10,
+                    [&] { return launch_update_p(g, bi, vb, st, active, r, p, v, ctx->stream); }));
       EpiArgs e1{EPI_RHV, rh, part, 0, pol, ph};
       VIE_HIP(run_matvec(ctx, G, prec, p, v, e1, active));
       VIE_HIP(timed(ctx, 11, [&] {
         return launch_finalize(FIN_ALPHA, nrhs, e1.part_blocks, part, st, flags, fp, ctx->stream);
       }));
-      VIE_HIP(timed(ctx, 10, [&] { return launch_update_s(g, st, active, r, v, s, ctx->stream); }));
+      VIE_HIP(timed(ctx, 10,
+                    [&] { return launch_update_s(g, bi, vb, st, active, r, v, s, ctx->stream); }));
       EpiArgs e2{EPI_TS, nullptr, part, 0, pol, ph};
       VIE_HIP(run_matvec(ctx, G, prec, s, t, e2, active));
       VIE_HIP(timed(ctx, 11, [&] {
         return launch_finalize(FIN_OMEGA, nrhs, e2.part_blocks, part, st, flags, fp, ctx->stream);
       }));
       VIE_HIP(timed(ctx, 10, [&] {
-        return launch_update_xr(g, st, active, x, r, p, s, t, rh, part, ctx->stream);
+        return launch_update_xr(g, bi, vb, st, active, x, r, p, s, t, rh, part, ctx->stream);
       }));
       VIE_HIP(timed(ctx, 11, [&] {
         return launch_finalize(FIN_RHO, nrhs, vb, part, st, flags, fp, ctx->stream);
@@ -663,6 +707,26 @@ extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* 
     if (nr == 0) continue;
     int rc = ensure_solve_storage(ctx, G, nr);
     if (rc != VIE_OK) return rc;
+    G.roff_host.assign(nr, 0);
+    int64_t vlen = 0;
+    for (int b : G.bodies) {
+      BodyRec& B = *ctx->bodies[b];
+      for (int q = 0; q < B.nrhs; ++q) {
+        G.roff_host[B.rhs0 + q] = vlen;
+        vlen += 3 * (int64_t)B.nb;
+      }
+    }
+    rc = ensure_vectors(ctx, G, std::max<int64_t>(vlen, 1));
+    if (rc != VIE_OK) return rc;
+    VIE_HIP(hipMemcpyAsync(G.roff.p, G.roff_host.data(), nr * sizeof(int64_t),
+                           hipMemcpyHostToDevice, ctx->stream));
+    G.bi.vox = G.vox_all.as<int>();
+    G.bi.line_ptr = G.line_ptr_all.as<int>();
+    G.bi.chic = G.chic_all.as<double>();
+    G.bi.nb = G.nb_arr.as<int>();
+    G.bi.voff = G.voff_arr.as<int>();
+    G.bi.roff = G.roff.as<int64_t>();
+    G.bi.rhs_body = G.rhs_body.as<int>();
     const int L = G.g.N[0] + G.g.N[1] + G.g.N[2];
     std::vector<int> rb(nr);
     std::vector<c64> pol((size_t)nr * 3), ph((size_t)nr * L);
@@ -740,7 +804,7 @@ extern "C" int vie_matvec_dev(vie_ctx* ctx, int32_t body, int32_t precision, con
                          ctx->stream));
   EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
   hipError_t err = run_matvec(ctx, G, precision == VIE_MIXED ? 1 : 0, (const c64*)x, (c64*)y, e,
-                              nullptr);
+                              nullptr, false);
   G.g.nrhs = saved;
   VIE_HIP(err);
   return VIE_OK;
@@ -772,10 +836,20 @@ extern "C" int vie_get_current(vie_ctx* ctx, int32_t body, int32_t rhs, vie_c64*
   BodyRec& B = *ctx->bodies[body];
   if (rhs < 0 || rhs >= B.nrhs) return VIE_EINVAL;
   Group& G = *ctx->groups[B.group];
-  const size_t vec = (size_t)3 * G.g.n;
-  VIE_HIP(hipMemcpyAsync(w, G.x.as<c64>() + (size_t)(B.rhs0 + rhs) * vec, vec * sizeof(c64),
-                         hipMemcpyDeviceToHost, ctx->stream));
-  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  const int64_t n = G.g.n;
+  std::vector<c64> c((size_t)3 * B.nb);
+  if (B.nb > 0) {
+    VIE_HIP(hipMemcpyAsync(c.data(), G.x.as<c64>() + G.roff_host[B.rhs0 + rhs],
+                           c.size() * sizeof(c64), hipMemcpyDeviceToHost, ctx->stream));
+    VIE_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  memset(w, 0, (size_t)3 * n * sizeof(vie_c64));
+  const int* vx = G.vox_host.data() + G.voff_host[B.slot];
+  for (int comp = 0; comp < 3; ++comp)
+    for (int k = 0; k < B.nb; ++k) {
+      w[comp * n + vx[k]].re = c[(size_t)comp * B.nb + k].re;
+      w[comp * n + vx[k]].im = c[(size_t)comp * B.nb + k].im;
+    }
   return VIE_OK;
 }
 
@@ -814,7 +888,8 @@ extern "C" int vie_farfield(vie_ctx* ctx, int32_t body, const double* theta, con
   VIE_HIP(hipMemcpyAsync(G.dirs.p, dirs.data(), dirs.size() * sizeof(double),
                          hipMemcpyHostToDevice, ctx->stream));
   VIE_HIP(timed(ctx, 12, [&] {
-    return launch_farfield_ks(G.g, G.x.as<c64>(), B.rhs0, B.nrhs, B.vox.as<int>(), B.nb,
+    return launch_farfield_ks(G.g, G.x.as<c64>(), G.roff_host.data() + B.rhs0, B.nrhs,
+                              G.vox_all.as<int>() + G.voff_host[B.slot], B.nb,
                               G.dirs.as<double>(), ndir, ctx->opt.k0, G.h, B.origin,
                               G.part.as<c64>(), chunk, G.F.as<c64>(), ctx->stream);
   }));

@@ -14,8 +14,12 @@ static constexpr int FF_S = 4;    // voxel sub-lanes per direction
 static constexpr int FF_NR = 4;   // right-hand sides per pass
 static constexpr int FF_CH = 64;  // voxels staged in LDS per step
 
+struct RoffArg {
+  int64_t r[FF_NR];
+};
+
 __global__ __launch_bounds__(FF_D* FF_S) void k_farfield_sum(
-    const c64* __restrict__ w, int64_t n, int r0, int nr, const int* __restrict__ vox, int nb,
+    const c64* __restrict__ w, RoffArg ro, int nr, const int* __restrict__ vox, int nb,
     int chunk, const double* __restrict__ dirs, int nd, double k0, double h, double o0, double o1,
     double o2, int N1, int N2, c64* __restrict__ part) {
   __shared__ int sidx[FF_CH][3];
@@ -48,7 +52,7 @@ __global__ __launch_bounds__(FF_D* FF_S) void k_farfield_sum(
         sidx[k][2] = lin / (N1 * N2);
         for (int q = 0; q < FF_NR; ++q)
           for (int c = 0; c < 3; ++c)
-            sw[k][q][c] = (q < nr) ? w[(int64_t)(r0 + q) * 3 * n + c * n + lin] : mk(0.0, 0.0);
+            sw[k][q][c] = (q < nr) ? w[ro.r[q] + (int64_t)c * nb + vi] : mk(0.0, 0.0);
       } else {
         sidx[k][0] = sidx[k][1] = sidx[k][2] = 0;
         for (int q = 0; q < FF_NR; ++q)
@@ -103,17 +107,19 @@ __global__ void k_farfield_project(const c64* __restrict__ part, int ksplit, int
   F[(int64_t)e * 2 + 1] = scale * fp;
 }
 
-hipError_t launch_farfield_ks(const GroupGeom& g, const c64* w, int r0, int nr, const int* vox,
-                              int nb, const double* dirs, int nd, double k0, double h,
-                              const double* origin, c64* part, int chunk, c64* F,
-                              hipStream_t s) {
+hipError_t launch_farfield_ks(const GroupGeom& g, const c64* w, const int64_t* roff_host,
+                              int nr, const int* vox, int nb, const double* dirs, int nd,
+                              double k0, double h, const double* origin, c64* part, int chunk,
+                              c64* F, hipStream_t s) {
   const int ks = (nb + chunk - 1) / chunk;
   for (int q0 = 0; q0 < nr; q0 += FF_NR) {
     const int nq = nr - q0 < FF_NR ? nr - q0 : FF_NR;
+    RoffArg ro;
+    for (int q = 0; q < FF_NR; ++q) ro.r[q] = q < nq ? roff_host[q0 + q] : 0;
     dim3 grid((nd + FF_D - 1) / FF_D, ks);
-    k_farfield_sum<<<grid, FF_D * FF_S, 0, s>>>(w, g.n, r0 + q0, nq, vox, nb, chunk, dirs, nd, k0,
-                                                h, origin[0], origin[1], origin[2], g.N[0],
-                                                g.N[1], part);
+    k_farfield_sum<<<grid, FF_D * FF_S, 0, s>>>(w, ro, nq, vox, nb, chunk, dirs, nd, k0, h,
+                                                origin[0], origin[1], origin[2], g.N[0], g.N[1],
+                                                part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double scale = k0 * k0 * h * h * h / (4.0 * M_PI);

@@ -12,126 +12,10 @@
 // outputs.  The 3x3 symmetric spectrum is stored on the octant
 // [0, P/2]^3 only; the other octants follow from the per-axis parity of each
 // Green component.
-#include "fft.h"
+#include "fft_common.h"
 #include "kernels.h"
 
 namespace vie {
-
-template <int P>
-struct Pad {
-  static constexpr int LSTR = P + P / 16 + 1;  // padded LDS line stride (bank spread)
-};
-__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
-
-// fft_stages with padded LDS indexing: wrap the line pointer in an accessor.
-template <typename T>
-struct LdsLine {
-  cpx<T>* p;
-  __device__ __forceinline__ cpx<T>& operator[](int i) const { return p[pidx(i)]; }
-};
-
-// Twiddles of a thread's butterflies, loaded once per kernel into registers
-// and reused by every line the thread transforms (forward and inverse).
-// Stage with sub-length NS and radix RAD (not the first): butterfly b of
-// thread t has j = t + b TT, k = j % NS and multiplies input r by
-// W_{NS RAD}^{r k} = tw[r k P / (NS RAD)].
-template <int P, int E, int NS>
-constexpr int tw_count() {
-  constexpr int RAD = (P / NS < E) ? P / NS : E;
-  constexpr int here = (NS == 1) ? 0 : (E / RAD) * (RAD - 1);
-  if constexpr (NS * RAD == P)
-    return here;
-  else
-    return here + tw_count<P, E, NS * RAD>();
-}
-
-template <typename T, int P, int E, int NS, int OFF>
-__device__ __forceinline__ void tw_load(cpx<T>* w, int t, const cpx<T>* __restrict__ tw) {
-  constexpr int RAD = (P / NS < E) ? P / NS : E;
-  constexpr int NB = E / RAD, TT = P / E;
-  constexpr int here = (NS == 1) ? 0 : NB * (RAD - 1);
-  if constexpr (NS != 1) {
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int k = (t + b * TT) % NS;
-#pragma unroll
-      for (int r = 1; r < RAD; ++r) w[OFF + b * (RAD - 1) + r - 1] = tw[r * k * (P / (NS * RAD))];
-    }
-  }
-  if constexpr (NS * RAD != P) tw_load<T, P, E, NS * RAD, OFF + here>(w, t, tw);
-}
-
-template <typename T, int P, int E>
-struct TwReg {
-  static constexpr int N = tw_count<P, E, 1>() > 0 ? tw_count<P, E, 1>() : 1;
-  cpx<T> w[N];
-  __device__ __forceinline__ void load(int t, const cpx<T>* __restrict__ tw) {
-    tw_load<T, P, E, 1, 0>(w, t, tw);
-  }
-};
-
-template <typename T, int P, int E, int NS, bool INV, int OFF>
-__device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int t,
-                                             const cpx<T>* __restrict__ w) {
-  constexpr int RAD = (P / NS < E) ? P / NS : E;
-  constexpr int NB = E / RAD;
-  constexpr int TT = P / E;
-  constexpr bool FIRST = (NS == 1);
-  constexpr bool LAST = (NS * RAD == P);
-  constexpr int here = FIRST ? 0 : NB * (RAD - 1);
-  cpx<T> u[E];
-  if constexpr (FIRST) {
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int r = 0; r < RAD; ++r) u[b * RAD + r] = v[b + r * NB];
-  } else {
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int j = t + b * TT;
-#pragma unroll
-      for (int r = 0; r < RAD; ++r) {
-        cpx<T> x = lds[j + r * (P / RAD)];
-        if (r > 0) {
-          cpx<T> ww = w[OFF + b * (RAD - 1) + r - 1];
-          if (INV) ww.im = -ww.im;
-          x = x * ww;
-        }
-        u[b * RAD + r] = x;
-      }
-    }
-  }
-#pragma unroll
-  for (int b = 0; b < NB; ++b) dft<RAD, INV>(&u[b * RAD]);
-  if constexpr (LAST) {
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int r = 0; r < RAD; ++r) v[b + r * NB] = u[b * RAD + r];
-  } else {
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int j = t + b * TT;
-      const int base = (j / NS) * NS * RAD + (j % NS);
-#pragma unroll
-      for (int r = 0; r < RAD; ++r) lds[base + r * NS] = u[b * RAD + r];
-    }
-    __syncthreads();
-    fft_stages_p<T, P, E, NS * RAD, INV, OFF + here>(v, lds, t, w);
-  }
-}
-
-template <typename T, int P, bool INV>
-__device__ __forceinline__ void line_fft(cpx<T> (&v)[fft_e<P>()], cpx<T>* line, int t,
-                                         const TwReg<T, P, fft_e<P>()>& tr) {
-  fft_stages_p<T, P, fft_e<P>(), 1, INV, 0>(v, LdsLine<T>{line}, t, tr.w);
-}
-
-template <typename T>
-constexpr int nt_lines() {
-  return sizeof(T) == 8 ? 128 : 256;  // threads per workgroup of single-line passes
-}
 
 // ---------------------------------------------------------------- X forward
 // One workgroup: L consecutive x-lines of one right-hand side.
@@ -356,38 +240,6 @@ struct XinvArgs {
   int64_t n;
 };
 
-template <typename T>
-__device__ __forceinline__ void block_sum2(c64& a, c64& b, double* red) {
-  // wave64 butterfly then across waves through LDS (fixed order: deterministic)
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    a.re += __shfl_xor(a.re, off, 64);
-    a.im += __shfl_xor(a.im, off, 64);
-    b.re += __shfl_xor(b.re, off, 64);
-    b.im += __shfl_xor(b.im, off, 64);
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  __syncthreads();
-  if (lane == 0) {
-    red[wv * 4 + 0] = a.re;
-    red[wv * 4 + 1] = a.im;
-    red[wv * 4 + 2] = b.re;
-    red[wv * 4 + 3] = b.im;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    c64 sa = mk(0.0, 0.0), sb = mk(0.0, 0.0);
-    for (int w = 0; w < nw; ++w) {
-      sa.re += red[w * 4 + 0];
-      sa.im += red[w * 4 + 1];
-      sb.re += red[w * 4 + 2];
-      sb.im += red[w * 4 + 3];
-    }
-    a = sa;
-    b = sb;
-  }
-}
-
 template <typename T, int P, int MODE>
 __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv(
     const cpx<T>* __restrict__ A, const c64* __restrict__ xin, c64* __restrict__ yout,
@@ -453,7 +305,7 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv(
     }
   }
   if (MODE != EPI_PLAIN) {
-    block_sum2<T>(s0, s1, red);
+    block_sum2(s0, s1, red);
     if (threadIdx.x == 0) {
       c64* pp = partials + ((size_t)rhs * a.blocks_per_rhs + blk) * 2;
       pp[0] = s0;
@@ -463,23 +315,6 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv(
 }
 
 // ================================================================ launchers
-template <typename T>
-static constexpr int lines_per_block(int P) {
-  return nt_lines<T>() / (P < 16 ? 1 : P / 16);
-}
-
-#define VIE_DISPATCH_P(P_, CALL)                 \
-  switch (P_) {                                  \
-    case 8: { constexpr int PP = 8; CALL; break; }     \
-    case 16: { constexpr int PP = 16; CALL; break; }   \
-    case 32: { constexpr int PP = 32; CALL; break; }   \
-    case 64: { constexpr int PP = 64; CALL; break; }   \
-    case 128: { constexpr int PP = 128; CALL; break; } \
-    case 256: { constexpr int PP = 256; CALL; break; } \
-    case 512: { constexpr int PP = 512; CALL; break; } \
-    default: return hipErrorInvalidValue;        \
-  }
-
 template <typename T>
 static hipError_t x_fwd(const GroupGeom& g, const c64* x, cpx<T>* A, const cpx<T>* tw,
                         const int* active, hipStream_t s) {
@@ -630,6 +465,13 @@ static hipError_t x_inv(const GroupGeom& g, const cpx<T>* A, const c64* x, c64* 
 }
 
 template <typename T>
+hipError_t x_fwd_c(const GroupGeom& g, const c64* xc, cpx<T>* A, const cpx<T>* tw,
+                   const BodyIdx& bi, const int* active, hipStream_t s);
+template <typename T>
+hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const c64* x, c64* y, const cpx<T>* tw,
+                   const BodyIdx& bi, EpiArgs& e, const int* active, hipStream_t s);
+
+template <typename T>
 static hipError_t matvec_t(const MatvecArgs& m, const c64* x, c64* y, EpiArgs& e, hipStream_t s,
                            void (*cb)(int, bool, void*), void* u) {
   const GroupGeom& g = *m.g;
@@ -645,11 +487,19 @@ static hipError_t matvec_t(const MatvecArgs& m, const c64* x, c64* y, EpiArgs& e
   err = CALL;                      \
   if (cb) cb(base + K, false, u);  \
   if (err != hipSuccess) return err;
-  STEP(0, x_fwd<T>(g, x, A, tw0, m.active, s));
+  if (m.bi) {
+    STEP(0, x_fwd_c<T>(g, x, A, tw0, *m.bi, m.active, s));
+  } else {
+    STEP(0, x_fwd<T>(g, x, A, tw0, m.active, s));
+  }
   STEP(1, y_pass<T>(g, A, B, tw1, false, m.active, s));
   STEP(2, z_pass<T>(g, B, (const cpx<T>*)m.spec, tw2, m.active, s, m.zvar));
   STEP(3, y_pass<T>(g, B, A, tw1, true, m.active, s));
-  STEP(4, x_inv<T>(g, A, x, y, m.chi, m.rhs_body, tw0, e, m.active, s));
+  if (m.bi) {
+    STEP(4, x_inv_c<T>(g, A, x, y, tw0, *m.bi, e, m.active, s));
+  } else {
+    STEP(4, x_inv<T>(g, A, x, y, m.chi, m.rhs_body, tw0, e, m.active, s));
+  }
 #undef STEP
   return hipSuccess;
 }

@@ -1,0 +1,194 @@
+// x passes of the operator product for body-compressed vectors.
+//
+// The unknowns of the discrete system are the contrast currents of the body
+// voxels (3 N_b values; chi = 0 elsewhere, where the solution vanishes).  The
+// solver stores its vectors over those unknowns only, component-major,
+// voxels in ascending box order: v[rhs][comp][k], k < N_b(body).  An x-line
+// (y, z) owns the contiguous range line_ptr[zy] .. line_ptr[zy+1] of a body's
+// voxels, so the forward x pass scatters a line's voxels into its LDS line
+// (zeros elsewhere) before transforming, and the inverse x pass gathers the
+// convolution at the line's voxels after transforming.  The y and z passes
+// and their scratch are unchanged (full FFT box).
+#include "fft_common.h"
+#include "kernels.h"
+
+namespace vie {
+
+// ---------------------------------------------------------------- X forward
+template <typename T, int P>
+__global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd_c(
+    const c64* __restrict__ xc, cpx<T>* __restrict__ out, const cpx<T>* __restrict__ tw,
+    BodyIdx bi, int N1, int N2, int N3, int blocks_per_rhs, const int* __restrict__ active) {
+  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), L = NT / TT,
+                LS = Pad<P>::LSTR;
+  __shared__ cpx<T> lds[L * LS];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int rhs = b / blocks_per_rhs, blk = b % blocks_per_rhs;
+  if (active && !active[rhs]) return;
+  const int lines_per_rhs = 3 * N2 * N3, lpc = N2 * N3;
+  const int li = threadIdx.x / TT, t = threadIdx.x % TT;
+  const int line = blk * L + li;
+  const bool valid = line < lines_per_rhs;
+  const int lc = valid ? line : 0;
+  const int comp = lc / lpc, zy = lc % lpc;
+  const int body = bi.rhs_body[rhs];
+  const int nb = bi.nb[body];
+  const int* vox = bi.vox + bi.voff[body];
+  const int* lp = bi.line_ptr + (int64_t)body * (lpc + 1);
+  const c64* xv = xc + bi.roff[rhs] + (int64_t)comp * nb;
+  TwReg<T, P, E> tr;
+  tr.load(t, tw);
+  cpx<T>* myl = lds + li * LS;
+  // zero the line's first P/2 points (the padded half is never read)
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) myl[pidx(t + q * TT)] = mk<T>(0, 0);
+  __syncthreads();
+  if (valid) {
+    const int k1 = lp[zy + 1];
+    const int base = zy * N1;
+    for (int k = lp[zy] + t; k < k1; k += TT) myl[pidx(vox[k] - base)] = cvt<T>(xv[k]);
+  }
+  __syncthreads();
+  cpx<T> v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) v[q] = (q < E / 2) ? myl[pidx(t + q * TT)] : mk<T>(0, 0);
+  line_fft<T, P, false>(v, myl, t, tr);
+  if (valid) {
+    cpx<T>* o = out + ((size_t)rhs * lines_per_rhs + line) * P;
+#pragma unroll
+    for (int q = 0; q < E; ++q) o[t + q * TT] = v[q];
+  }
+}
+
+// ------------------------------------------------ X inverse + epilogue
+template <typename T, int P, int MODE>
+__global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv_c(
+    const cpx<T>* __restrict__ A, const c64* __restrict__ xin, c64* __restrict__ yout,
+    const cpx<T>* __restrict__ tw, BodyIdx bi, int N1, int N2, int N3, int blocks_per_rhs,
+    c64* __restrict__ aux, c64* __restrict__ partials, const c64* __restrict__ pol,
+    const c64* __restrict__ ph, const int* __restrict__ active) {
+  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), L = NT / TT,
+                LS = Pad<P>::LSTR;
+  __shared__ cpx<T> lds[L * LS];
+  __shared__ double red[4 * (NT / 64 + 1)];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int rhs = b / blocks_per_rhs, blk = b % blocks_per_rhs;
+  if (active && !active[rhs]) return;
+  const int lines_per_rhs = 3 * N2 * N3, lpc = N2 * N3;
+  const int li = threadIdx.x / TT, t = threadIdx.x % TT;
+  const int line = blk * L + li;
+  const bool valid = line < lines_per_rhs;
+  const int lc = valid ? line : 0;
+  const size_t gl = (size_t)rhs * lines_per_rhs + lc;
+  TwReg<T, P, E> tr;
+  tr.load(t, tw);
+  cpx<T> v[E];
+  {
+    const cpx<T>* src = A + gl * P;
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[q] = valid ? src[t + q * TT] : mk<T>(0, 0);
+  }
+  cpx<T>* myl = lds + li * LS;
+  line_fft<T, P, true>(v, myl, t, tr);
+  __syncthreads();  // every thread has left the FFT's last LDS read
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) myl[pidx(t + q * TT)] = v[q];
+  __syncthreads();
+  const int comp = lc / lpc, zy = lc % lpc;
+  const int body = bi.rhs_body[rhs];
+  const int nb = bi.nb[body];
+  const int* vox = bi.vox + bi.voff[body];
+  const double* chic = bi.chic + bi.voff[body];
+  const int* lp = bi.line_ptr + (int64_t)body * (lpc + 1);
+  const int64_t vb = bi.roff[rhs] + (int64_t)comp * nb;
+  c64 s0 = mk(0.0, 0.0), s1 = mk(0.0, 0.0);
+  if (valid) {
+    const int k1 = lp[zy + 1];
+    const int base = zy * N1;
+    c64 phyz = mk(0.0, 0.0), pc = mk(0.0, 0.0);
+    const c64* phr = ph + (int64_t)rhs * (N1 + N2 + N3);
+    if (MODE == EPI_RESID) {
+      const int y = zy % N2, z = zy / N2;
+      phyz = phr[N1 + y] * phr[N1 + N2 + z];
+      pc = pol[rhs * 3 + comp];
+    }
+    for (int k = lp[zy] + t; k < k1; k += TT) {
+      const int xi = vox[k] - base;
+      const c64 conv = cvt<double>(myl[pidx(xi)]);
+      const double c = chic[k];
+      const int64_t gi = vb + k;
+      const c64 xv = xin[gi];
+      const c64 y = xv - c * conv;
+      if (MODE == EPI_RESID) {
+        const c64 e = pc * (phyz * phr[xi]);
+        const c64 r = c * e - y;
+        yout[gi] = r;
+        aux[gi] = r;
+        s1.re += r.re * r.re + r.im * r.im;
+      } else {
+        yout[gi] = y;
+        if (MODE == EPI_RHV) {
+          s0 = s0 + cmulc(aux[gi], y);
+        } else if (MODE == EPI_TS) {
+          s0 = s0 + cmulc(y, xv);
+          s1.re += y.re * y.re + y.im * y.im;
+        }
+      }
+    }
+  }
+  if (MODE != EPI_PLAIN) {
+    block_sum2(s0, s1, red);
+    if (threadIdx.x == 0) {
+      c64* pp = partials + ((size_t)rhs * blocks_per_rhs + blk) * 2;
+      pp[0] = s0;
+      pp[1] = s1;
+    }
+  }
+}
+
+// ================================================================ launchers
+template <typename T>
+hipError_t x_fwd_c(const GroupGeom& g, const c64* xc, cpx<T>* A, const cpx<T>* tw,
+                   const BodyIdx& bi, const int* active, hipStream_t s) {
+  const int lines = 3 * g.N[1] * g.N[2];
+  const int L = lines_per_block<T>(g.P[0]);
+  const int bpr = (lines + L - 1) / L;
+  const dim3 grid(bpr * g.nrhs);
+  VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd_c<T, PP><<<grid, nt_lines<T>(), 0, s>>>(
+                             xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active)));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const c64* x, c64* y, const cpx<T>* tw,
+                   const BodyIdx& bi, EpiArgs& e, const int* active, hipStream_t s) {
+  const int lines = 3 * g.N[1] * g.N[2];
+  const int L = lines_per_block<T>(g.P[0]);
+  const int bpr = (lines + L - 1) / L;
+  e.part_blocks = bpr;
+  const dim3 grid(bpr * g.nrhs);
+#define VIE_XINVC(MODE_)                                                                      \
+  VIE_DISPATCH_P(g.P[0], (k_fft_x_inv_c<T, PP, MODE_><<<grid, nt_lines<T>(), 0, s>>>(           \
+                             A, x, y, tw, bi, g.N[0], g.N[1], g.N[2], bpr, e.aux, e.partials, \
+                             e.pol, e.ph, active)))
+  switch (e.mode) {
+    case EPI_PLAIN: VIE_XINVC(EPI_PLAIN); break;
+    case EPI_RHV: VIE_XINVC(EPI_RHV); break;
+    case EPI_TS: VIE_XINVC(EPI_TS); break;
+    case EPI_RESID: VIE_XINVC(EPI_RESID); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef VIE_XINVC
+  return hipGetLastError();
+}
+
+template hipError_t x_fwd_c<double>(const GroupGeom&, const c64*, c64*, const c64*,
+                                    const BodyIdx&, const int*, hipStream_t);
+template hipError_t x_fwd_c<float>(const GroupGeom&, const c64*, c32*, const c32*,
+                                   const BodyIdx&, const int*, hipStream_t);
+template hipError_t x_inv_c<double>(const GroupGeom&, const c64*, const c64*, c64*, const c64*,
+                                    const BodyIdx&, EpiArgs&, const int*, hipStream_t);
+template hipError_t x_inv_c<float>(const GroupGeom&, const c32*, const c64*, c64*, const c32*,
+                                   const BodyIdx&, EpiArgs&, const int*, hipStream_t);
+
+}  // namespace vie

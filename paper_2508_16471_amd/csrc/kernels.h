@@ -41,6 +41,18 @@ struct GroupGeom {
   int nrhs;     // right-hand sides in the group
 };
 
+// Body-compressed vectors: the solver stores each right-hand side's vectors
+// over its body's voxels only, v[rhs][comp][k] at roff[rhs] + comp nb + k.
+struct BodyIdx {
+  const int* vox;        // concatenated body-voxel linear indices (ascending per body)
+  const int* line_ptr;   // [body][N2 N3 + 1] start of each x-line in the body's list
+  const double* chic;    // chi at the body voxels (same order as vox)
+  const int* nb;         // [body] body voxels
+  const int* voff;       // [body] offset of the body's lists in vox / chic
+  const int64_t* roff;   // [rhs] offset of the right-hand side's vector
+  const int* rhs_body;   // [rhs] body of each right-hand side
+};
+
 // Device pointers used by one operator product of a group.
 struct MatvecArgs {
   const GroupGeom* g;
@@ -52,6 +64,7 @@ struct MatvecArgs {
   void* bufB;              // y-transformed scratch [nrhs][3][N3/zl][P2][zl][P1]
   const int* active;       // [nrhs] or nullptr
   int zvar = 0;            // launch shape of the z pass (autotuned per group/precision)
+  const BodyIdx* bi = nullptr;  // non-null: x and y are body-compressed
 };
 
 // precision 0: FP64 passes, 1: FP32 passes (input/output vectors are FP64)
@@ -88,19 +101,22 @@ hipError_t launch_fft3d_full(c64* work, c64* tmp, const GroupGeom& g, const void
 hipError_t launch_octant(const c64* work, c64* spec64, c32* spec32, const GroupGeom& g, int ab,
                          hipStream_t s);
 
-// Krylov vector kernels (FP64 vectors of 3n complex per right-hand side).
+// Krylov vector kernels on body-compressed FP64 vectors (3 nb per rhs).
+// vb = vec_blocks(max 3 nb) workgroups per right-hand side.
+int vec_blocks_n(int64_t max_len);
 // b = chi pol e^{i k0 khat.r}; r = rhat = b; x = 0 unless keep_x; partials |b|^2.
 // mask (nullable): only right-hand sides with mask[rhs] != 0.
-hipError_t launch_init_zero_guess(const GroupGeom& g, const double* chi, const int* rhs_body,
+hipError_t launch_init_zero_guess(const GroupGeom& g, const BodyIdx& bi, int vb,
                                   const c64* pol, const c64* ph, c64* x, c64* r, c64* rh,
                                   c64* partials, int keep_x, const int* mask, hipStream_t s);
-hipError_t launch_update_p(const GroupGeom& g, const KState* st, const int* active,
-                           const c64* r, c64* p, const c64* v, hipStream_t s);
-hipError_t launch_update_s(const GroupGeom& g, const KState* st, const int* active,
-                           const c64* r, const c64* v, c64* s_out, hipStream_t s);
-hipError_t launch_update_xr(const GroupGeom& g, const KState* st, const int* active, c64* x,
-                            c64* r, const c64* p, const c64* sv, const c64* t, const c64* rh,
-                            c64* partials, hipStream_t s);
+hipError_t launch_update_p(const GroupGeom& g, const BodyIdx& bi, int vb, const KState* st,
+                           const int* active, const c64* r, c64* p, const c64* v, hipStream_t s);
+hipError_t launch_update_s(const GroupGeom& g, const BodyIdx& bi, int vb, const KState* st,
+                           const int* active, const c64* r, const c64* v, c64* s_out,
+                           hipStream_t s);
+hipError_t launch_update_xr(const GroupGeom& g, const BodyIdx& bi, int vb, const KState* st,
+                            const int* active, c64* x, c64* r, const c64* p, const c64* sv,
+                            const c64* t, const c64* rh, c64* partials, hipStream_t s);
 // Finalize reductions (one workgroup per right-hand side, fixed order):
 enum FinWhich { FIN_ALPHA = 0, FIN_OMEGA = 1, FIN_RHO = 2, FIN_INIT = 3, FIN_RESTART = 4 };
 struct FinParams {
@@ -114,11 +130,15 @@ hipError_t launch_finalize(int which, int nrhs, int nblk, const c64* partials, K
 hipError_t launch_axpy_real(int64_t n, double a, const c64* x, c64* y, hipStream_t s);
 
 // Far field (eq. 25): F[rhs][dir][2] = (F_theta, F_phi) for right-hand sides
-// [r0, r0+nr) of a group; body voxels listed in vox[nb] (linear indices);
+// [r0, r0+nr) of one body; w body-compressed with per-rhs offsets roff (host
+// values for the nr right-hand sides), body voxels vox[nb] (linear indices);
 // dirs[nd][9] = (r, theta-hat, phi-hat); part: ceil(nb/chunk)*min(nr,4)*nd*3 c64.
-hipError_t launch_farfield_ks(const GroupGeom& g, const c64* w, int r0, int nr, const int* vox,
-                              int nb, const double* dirs, int nd, double k0, double h,
-                              const double* origin, c64* part, int chunk, c64* F,
-                              hipStream_t s);
+hipError_t launch_farfield_ks(const GroupGeom& g, const c64* w, const int64_t* roff_host,
+                              int nr, const int* vox, int nb, const double* dirs, int nd,
+                              double k0, double h, const double* origin, c64* part, int chunk,
+                              c64* F, hipStream_t s);
+// Gather a box-layout vector [3][n] into body-compressed storage [3][nb].
+hipError_t launch_compress(const c64* box, c64* comp, const int* vox, int nb, int64_t n,
+                           hipStream_t s);
 
 }  // namespace vie

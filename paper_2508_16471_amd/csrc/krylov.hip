@@ -13,8 +13,7 @@ namespace vie {
 
 static constexpr int VT = 256;  // threads per vector-kernel workgroup
 
-int vec_blocks(const GroupGeom& g) {
-  const int64_t m = 3 * g.n;
+int vec_blocks_n(int64_t m) {
   int64_t b = (m + 4 * VT - 1) / (4 * VT);
   if (b > 1024) b = 1024;
   if (b < 1) b = 1;
@@ -51,9 +50,23 @@ __device__ __forceinline__ void block_reduce2(c64& a, c64& b) {
   }
 }
 
+// Vectors are body-compressed: right-hand side r holds 3 nb values at roff[r],
+// component-major.  Each kernel strides its workgroups over that range.
+struct VecRange {
+  int64_t base, len;
+  int nb, body;
+};
+__device__ __forceinline__ VecRange vrange(const BodyIdx& bi, int rhs) {
+  VecRange v;
+  v.body = bi.rhs_body[rhs];
+  v.nb = bi.nb[v.body];
+  v.base = bi.roff[rhs];
+  v.len = 3 * (int64_t)v.nb;
+  return v;
+}
+
 // x = 0, r = rhat = b = chi pol exp(i k0 khat.r); partials (rhat.r, |r|^2)
-__global__ __launch_bounds__(VT) void k_init_zero(GroupGeom g, const double* __restrict__ chi,
-                                                  const int* __restrict__ rhs_body,
+__global__ __launch_bounds__(VT) void k_init_zero(GroupGeom g, BodyIdx bi,
                                                   const c64* __restrict__ pol,
                                                   const c64* __restrict__ ph, c64* __restrict__ x,
                                                   c64* __restrict__ r, c64* __restrict__ rh,
@@ -61,22 +74,23 @@ __global__ __launch_bounds__(VT) void k_init_zero(GroupGeom g, const double* __r
                                                   int keep_x, const int* __restrict__ mask) {
   const int rhs = blockIdx.x / vb, blk = blockIdx.x % vb;
   if (mask && !mask[rhs]) return;
-  const int64_t m = 3 * g.n;
-  const int64_t off = (int64_t)rhs * m;
-  const double* c = chi + (int64_t)rhs_body[rhs] * g.n;
+  const VecRange R = vrange(bi, rhs);
+  const int* vox = bi.vox + bi.voff[R.body];
+  const double* chic = bi.chic + bi.voff[R.body];
   const c64* p = ph + (int64_t)rhs * (g.N[0] + g.N[1] + g.N[2]);
   c64 s1 = mk(0.0, 0.0), s0 = mk(0.0, 0.0);
-  for (int64_t e = (int64_t)blk * VT + threadIdx.x; e < m; e += (int64_t)vb * VT) {
-    const int comp = (int)(e / g.n);
-    const int64_t v = e - comp * g.n;
-    const int i = (int)(v % g.N[0]);
-    const int j = (int)((v / g.N[0]) % g.N[1]);
-    const int l = (int)(v / ((int64_t)g.N[0] * g.N[1]));
+  for (int64_t e = (int64_t)blk * VT + threadIdx.x; e < R.len; e += (int64_t)vb * VT) {
+    const int comp = (int)(e / R.nb);
+    const int k = (int)(e - (int64_t)comp * R.nb);
+    const int v = vox[k];
+    const int i = v % g.N[0];
+    const int j = (v / g.N[0]) % g.N[1];
+    const int l = v / (g.N[0] * g.N[1]);
     const c64 phase = p[i] * p[g.N[0] + j] * p[g.N[0] + g.N[1] + l];
-    const c64 b = c[v] * (pol[rhs * 3 + comp] * phase);
-    if (!keep_x) x[off + e] = mk(0.0, 0.0);
-    r[off + e] = b;
-    rh[off + e] = b;
+    const c64 b = chic[k] * (pol[rhs * 3 + comp] * phase);
+    if (!keep_x) x[R.base + e] = mk(0.0, 0.0);
+    r[R.base + e] = b;
+    rh[R.base + e] = b;
     s1.re += b.re * b.re + b.im * b.im;
   }
   s0 = s1;
@@ -88,39 +102,39 @@ __global__ __launch_bounds__(VT) void k_init_zero(GroupGeom g, const double* __r
 }
 
 // p = r + beta (p - omega v); p = r at the start of a cycle
-__global__ __launch_bounds__(VT) void k_update_p(GroupGeom g, const KState* __restrict__ st,
+__global__ __launch_bounds__(VT) void k_update_p(BodyIdx bi, const KState* __restrict__ st,
                                                  const int* __restrict__ active,
                                                  const c64* __restrict__ r, c64* __restrict__ p,
                                                  const c64* __restrict__ v, int vb) {
   const int rhs = blockIdx.x / vb, blk = blockIdx.x % vb;
   if (!active[rhs]) return;
-  const int64_t m = 3 * g.n, off = (int64_t)rhs * m;
+  const VecRange R = vrange(bi, rhs);
   const bool first = st[rhs].it_cycle == 0;
   const c64 beta = st[rhs].beta, om = st[rhs].omega;
-  for (int64_t e = (int64_t)blk * VT + threadIdx.x; e < m; e += (int64_t)vb * VT) {
-    const int64_t k = off + e;
+  for (int64_t e = (int64_t)blk * VT + threadIdx.x; e < R.len; e += (int64_t)vb * VT) {
+    const int64_t k = R.base + e;
     p[k] = first ? r[k] : r[k] + beta * (p[k] - om * v[k]);
   }
 }
 
 // s = r - alpha v
-__global__ __launch_bounds__(VT) void k_update_s(GroupGeom g, const KState* __restrict__ st,
+__global__ __launch_bounds__(VT) void k_update_s(BodyIdx bi, const KState* __restrict__ st,
                                                  const int* __restrict__ active,
                                                  const c64* __restrict__ r,
                                                  const c64* __restrict__ v, c64* __restrict__ s,
                                                  int vb) {
   const int rhs = blockIdx.x / vb, blk = blockIdx.x % vb;
   if (!active[rhs]) return;
-  const int64_t m = 3 * g.n, off = (int64_t)rhs * m;
+  const VecRange R = vrange(bi, rhs);
   const c64 al = st[rhs].alpha;
-  for (int64_t e = (int64_t)blk * VT + threadIdx.x; e < m; e += (int64_t)vb * VT) {
-    const int64_t k = off + e;
+  for (int64_t e = (int64_t)blk * VT + threadIdx.x; e < R.len; e += (int64_t)vb * VT) {
+    const int64_t k = R.base + e;
     s[k] = r[k] - al * v[k];
   }
 }
 
 // x += alpha p + omega s; r = s - omega t; partials (rhat.r, |r|^2)
-__global__ __launch_bounds__(VT) void k_update_xr(GroupGeom g, const KState* __restrict__ st,
+__global__ __launch_bounds__(VT) void k_update_xr(BodyIdx bi, const KState* __restrict__ st,
                                                   const int* __restrict__ active,
                                                   c64* __restrict__ x, c64* __restrict__ r,
                                                   const c64* __restrict__ p,
@@ -130,11 +144,11 @@ __global__ __launch_bounds__(VT) void k_update_xr(GroupGeom g, const KState* __r
                                                   c64* __restrict__ partials, int vb) {
   const int rhs = blockIdx.x / vb, blk = blockIdx.x % vb;
   if (!active[rhs]) return;
-  const int64_t m = 3 * g.n, off = (int64_t)rhs * m;
+  const VecRange R = vrange(bi, rhs);
   const c64 al = st[rhs].alpha, om = st[rhs].omega;
   c64 s0 = mk(0.0, 0.0), s1 = mk(0.0, 0.0);
-  for (int64_t e = (int64_t)blk * VT + threadIdx.x; e < m; e += (int64_t)vb * VT) {
-    const int64_t k = off + e;
+  for (int64_t e = (int64_t)blk * VT + threadIdx.x; e < R.len; e += (int64_t)vb * VT) {
+    const int64_t k = R.base + e;
     const c64 sk = s[k];
     x[k] = x[k] + al * p[k] + om * sk;
     const c64 rk = sk - om * t[k];
@@ -146,6 +160,17 @@ __global__ __launch_bounds__(VT) void k_update_xr(GroupGeom g, const KState* __r
   if (threadIdx.x == 0) {
     partials[((size_t)rhs * vb + blk) * 2 + 0] = s0;
     partials[((size_t)rhs * vb + blk) * 2 + 1] = s1;
+  }
+}
+
+// body-compressed gather of a box-layout vector
+__global__ __launch_bounds__(VT) void k_compress(const c64* __restrict__ box, c64* __restrict__ out,
+                                                 const int* __restrict__ vox, int nb, int64_t n) {
+  const int64_t m = 3 * (int64_t)nb;
+  for (int64_t e = (int64_t)blockIdx.x * VT + threadIdx.x; e < m; e += (int64_t)gridDim.x * VT) {
+    const int comp = (int)(e / nb);
+    const int k = (int)(e - (int64_t)comp * nb);
+    out[e] = box[comp * n + vox[k]];
   }
 }
 
@@ -247,31 +272,35 @@ __global__ __launch_bounds__(VT) void k_axpy_real(int64_t n, double a, const c64
     y[e] = y[e] + a * x[e];
 }
 
-hipError_t launch_init_zero_guess(const GroupGeom& g, const double* chi, const int* rhs_body,
+hipError_t launch_init_zero_guess(const GroupGeom& g, const BodyIdx& bi, int vb,
                                   const c64* pol, const c64* ph, c64* x, c64* r, c64* rh,
                                   c64* partials, int keep_x, const int* mask, hipStream_t s) {
-  const int vb = vec_blocks(g);
-  k_init_zero<<<vb * g.nrhs, VT, 0, s>>>(g, chi, rhs_body, pol, ph, x, r, rh, partials, vb,
-                                         keep_x, mask);
+  k_init_zero<<<vb * g.nrhs, VT, 0, s>>>(g, bi, pol, ph, x, r, rh, partials, vb, keep_x, mask);
   return hipGetLastError();
 }
-hipError_t launch_update_p(const GroupGeom& g, const KState* st, const int* active, const c64* r,
-                           c64* p, const c64* v, hipStream_t s) {
-  const int vb = vec_blocks(g);
-  k_update_p<<<vb * g.nrhs, VT, 0, s>>>(g, st, active, r, p, v, vb);
+hipError_t launch_update_p(const GroupGeom& g, const BodyIdx& bi, int vb, const KState* st,
+                           const int* active, const c64* r, c64* p, const c64* v, hipStream_t s) {
+  k_update_p<<<vb * g.nrhs, VT, 0, s>>>(bi, st, active, r, p, v, vb);
   return hipGetLastError();
 }
-hipError_t launch_update_s(const GroupGeom& g, const KState* st, const int* active, const c64* r,
-                           const c64* v, c64* so, hipStream_t s) {
-  const int vb = vec_blocks(g);
-  k_update_s<<<vb * g.nrhs, VT, 0, s>>>(g, st, active, r, v, so, vb);
+hipError_t launch_update_s(const GroupGeom& g, const BodyIdx& bi, int vb, const KState* st,
+                           const int* active, const c64* r, const c64* v, c64* so,
+                           hipStream_t s) {
+  k_update_s<<<vb * g.nrhs, VT, 0, s>>>(bi, st, active, r, v, so, vb);
   return hipGetLastError();
 }
-hipError_t launch_update_xr(const GroupGeom& g, const KState* st, const int* active, c64* x,
-                            c64* r, const c64* p, const c64* sv, const c64* t, const c64* rh,
-                            c64* partials, hipStream_t s) {
-  const int vb = vec_blocks(g);
-  k_update_xr<<<vb * g.nrhs, VT, 0, s>>>(g, st, active, x, r, p, sv, t, rh, partials, vb);
+hipError_t launch_update_xr(const GroupGeom& g, const BodyIdx& bi, int vb, const KState* st,
+                            const int* active, c64* x, c64* r, const c64* p, const c64* sv,
+                            const c64* t, const c64* rh, c64* partials, hipStream_t s) {
+  k_update_xr<<<vb * g.nrhs, VT, 0, s>>>(bi, st, active, x, r, p, sv, t, rh, partials, vb);
+  return hipGetLastError();
+}
+hipError_t launch_compress(const c64* box, c64* comp, const int* vox, int nb, int64_t n,
+                           hipStream_t s) {
+  int64_t b = (3 * (int64_t)nb + VT - 1) / VT;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  k_compress<<<(int)b, VT, 0, s>>>(box, comp, vox, nb, n);
   return hipGetLastError();
 }
 hipError_t launch_finalize(int which, int nrhs, int nblk, const c64* partials, KState* st,
