@@ -170,6 +170,52 @@ int vie_kernel_times(vie_ctx *ctx, const char **names, double *ms, int64_t *cnt,
  * inner_tol, warm_start, flags).  k0 must match the setup value. */
 int vie_set_options(vie_ctx *ctx, const vie_options *opt);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start (a data-driven initial guess for the BiCGSTAB solve of
+ * eq. 24; the paper's own acceleration is a block preconditioner, Sec. II-C).
+ * A 4-layer 3x3x3 convolutional network (16 -> 32 -> 32 -> 32 -> 16 channels,
+ * ReLU between layers, bf16 weights and activations, fp32 accumulation)
+ * evaluated on each body's bounding box plus a 4-voxel halo, channels-last.
+ * Input channels: chi/4, b/s (re, im of x, y, z), (b - A b)/s (same order),
+ * zeros; b = chi e, s = rms of |b| over the body voxels, A b with the FP32
+ * product.  Outputs 0..5: the predicted w/s (re, im of x, y, z).  The solver
+ * uses x0 = s * output only if ||b - A x0|| < ||b|| (FP64 operator), else
+ * x0 = 0 (vie_stats.fallback).
+ * Parameters (fp32, host): per layer W[27][Cout][Cin] (tap (dz+1)*9 +
+ * (dy+1)*3 + (dx+1)) followed by b[Cout].  Device tensors: features
+ * [d2][d1][d0][16] bf16, targets [d2][d1][d0][6] fp32, outputs
+ * [d2][d1][d0][16] fp32 (dims = (d0, d1, d2)).  Loss: masked relative L2
+ * sum_body |out - t|^2 / sum_body |t|^2 over outputs 0..5 (mask: chi > 0).
+ * ------------------------------------------------------------------------ */
+typedef struct vie_cnn vie_cnn;
+
+/* Number of fp32 parameters of the network. */
+int64_t vie_cnn_num_params(void);
+/* Create a network with seeded He-normal weights on the current device. */
+int vie_cnn_create(uint64_t seed, vie_cnn **out);
+void vie_cnn_destroy(vie_cnn *net);
+/* set != 0: load n = vie_cnn_num_params() host fp32 parameters (resets the
+ * optimiser state); set == 0: read them back. */
+int vie_cnn_params(vie_cnn *net, float *params, int64_t n, int32_t set);
+/* Use net for warm starts of ctx (vie_options.warm_start = 1); NULL detaches.
+ * The network must outlive its use by ctx. */
+int vie_attach_cnn(vie_ctx *ctx, vie_cnn *net);
+/* Training sample of (body, rhs) from the last vie_solve: writes the box dims
+ * to dims[3]; when feat / target are non-NULL, fills the device tensors with
+ * the input features and the solution w/s (the target). */
+int vie_cnn_sample_dev(vie_ctx *ctx, int32_t body, int32_t rhs, void *feat_dev,
+                       void *target_dev, int32_t *dims);
+/* Forward pass on device tensors (stream: hipStream_t or NULL). */
+int vie_cnn_infer_dev(vie_cnn *net, const int32_t *dims, const void *feat_dev, void *out_dev,
+                      void *stream);
+/* Forward + backward: loss and the gradient of every parameter (host fp32
+ * array of vie_cnn_num_params(); may be NULL); parameters unchanged. */
+int vie_cnn_grad_dev(vie_cnn *net, const int32_t *dims, const void *feat_dev,
+                     const void *target_dev, float *grad_host, float *loss, void *stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) with learning rate lr. */
+int vie_cnn_train_step_dev(vie_cnn *net, const int32_t *dims, const void *feat_dev,
+                           const void *target_dev, float lr, float *loss, void *stream);
+
 void vie_destroy(vie_ctx *ctx);
 const char *vie_strerror(int code);
 

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/vie.h"
+#include "cnn.h"
 #include "kernels.h"
 
 using namespace vie;
@@ -80,6 +81,12 @@ struct Group {
   std::vector<int64_t> roff_host;
   BodyIdx bi;
   DevBuf x, r, rh, p, v, s, t;   // c64, body-compressed, all right-hand sides
+  DevBuf mask;                   // int [cap] scratch mask
+  // learned warm start: per body, network box = bounding box + 4-voxel halo
+  std::vector<int> box_lo, box_d;        // [slot][3]
+  std::vector<double> res_x0;            // per rhs: relative residual of the initial guess
+  std::vector<int> fallback, warm_used;  // per rhs
+  bool samples_ready = false;            // r = b and v = A b hold for every rhs
   DevBuf bufA, bufB;             // FFT scratch (sized for FP64)
   DevBuf partials;               // c64 [cap][maxblk][2]
   DevBuf state;                  // KState [cap]
@@ -100,11 +107,17 @@ struct TimedEvent {
 static const char* kKindNames[] = {
     "fft_x_fwd_f64", "fft_y_fwd_f64", "fft_z_green_f64", "fft_y_inv_f64", "fft_x_inv_f64",
     "fft_x_fwd_f32", "fft_y_fwd_f32", "fft_z_green_f32", "fft_y_inv_f32", "fft_x_inv_f32",
-    "krylov_vec",    "finalize",      "farfield",        "init"};
-static constexpr int kNumKinds = 14;
+    "krylov_vec",    "finalize",      "farfield",        "init",          "cnn_forward"};
+static constexpr int kNumKinds = 15;
+
+struct vie_cnn {
+  vie::Cnn c;
+};
 
 struct vie_ctx {
   vie_options opt;
+  vie_cnn* cnn = nullptr;  // warm-start network (not owned)
+  DevBuf feat;             // network input workspace (bf16)
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
   bool poisoned = false;
@@ -306,6 +319,26 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
     G.nb_host.push_back(rec->nb);
     G.max_nb = std::max(G.max_nb, rec->nb);
     G.vox_host.insert(G.vox_host.end(), vox.begin(), vox.end());
+    {  // network box: bounding box of the body voxels, 4-voxel halo, clipped
+      int lo[3] = {B.n[0], B.n[1], B.n[2]}, hi[3] = {0, 0, 0};
+      for (int v : vox) {
+        const int c[3] = {v % B.n[0], (v / B.n[0]) % B.n[1], v / (B.n[0] * B.n[1])};
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = std::min(lo[a], c[a]);
+          hi[a] = std::max(hi[a], c[a] + 1);
+        }
+      }
+      for (int a = 0; a < 3; ++a) {
+        if (vox.empty()) {
+          lo[a] = 0;
+          hi[a] = 1;
+        }
+        lo[a] = std::max(0, lo[a] - 4);
+        hi[a] = std::min(B.n[a], hi[a] + 4);
+        G.box_lo.push_back(lo[a]);
+        G.box_d.push_back(hi[a] - lo[a]);
+      }
+    }
     ctx->bodies.push_back(std::move(rec));
   }
   for (size_t gi = 0; gi < ctx->groups.size(); ++gi) {
@@ -425,6 +458,7 @@ static int ensure_solve_storage(vie_ctx* ctx, Group& G, int nrhs) {
   VIE_HIP(G.pol.reserve((size_t)nrhs * 3 * sizeof(c64)));
   VIE_HIP(G.ph.reserve((size_t)nrhs * (G.g.N[0] + G.g.N[1] + G.g.N[2]) * sizeof(c64)));
   VIE_HIP(G.roff.reserve((size_t)nrhs * sizeof(int64_t)));
+  VIE_HIP(G.mask.reserve((size_t)nrhs * sizeof(int)));
   G.cap = nrhs;
   return VIE_OK;
 }
@@ -512,6 +546,66 @@ static hipError_t run_matvec(vie_ctx* ctx, Group& G, int precision, const c64* x
                        ctx);
 }
 
+// ------------------------------------------------------ learned warm start
+// v = A_32 r for every right-hand side (r holds b after the init kernel).
+static int born_products(vie_ctx* ctx, Group& G) {
+  EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
+  VIE_HIP(run_matvec(ctx, G, 1, G.r.as<c64>(), G.v.as<c64>(), e, nullptr));
+  return VIE_OK;
+}
+
+static int ensure_feat(vie_ctx* ctx, size_t vox) {
+  VIE_HIP(ctx->feat.reserve(vox * 16 * sizeof(uint16_t)));
+  return VIE_OK;
+}
+
+// Features of right-hand side q (body slot sl) into feat (bf16 [box][16]).
+static int build_features(vie_ctx* ctx, Group& G, int q, int sl, double bnorm2, void* feat) {
+  const int* d = &G.box_d[3 * sl];
+  const int* lo = &G.box_lo[3 * sl];
+  const int nb = G.nb_host[sl];
+  const double s = nb > 0 && bnorm2 > 0 ? sqrt(bnorm2 / nb) : 0.0;
+  const c64* b = G.r.as<c64>() + G.roff_host[q];
+  const c64* Ab = G.v.as<c64>() + G.roff_host[q];
+  VIE_HIP(launch_cnn_features((bf16raw*)feat, d, lo, G.g.N, G.vox_all.as<int>() + G.voff_host[sl],
+                              G.chic_all.as<double>() + G.voff_host[sl], nb, b, Ab, s,
+                              ctx->stream));
+  return VIE_OK;
+}
+
+static int predict_x0(vie_ctx* ctx, Group& G) {
+  if (!ctx->cnn) return VIE_ESTATE;
+  int rc = born_products(ctx, G);
+  if (rc != VIE_OK) return rc;
+  const int nrhs = G.g.nrhs;
+  std::vector<KState> hs(nrhs);
+  VIE_HIP(hipMemcpyAsync(hs.data(), G.state.p, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  std::vector<int> slot_of(nrhs, 0);
+  for (int b : G.bodies) {
+    BodyRec& B = *ctx->bodies[b];
+    for (int q = 0; q < B.nrhs; ++q) slot_of[B.rhs0 + q] = B.slot;
+  }
+  Cnn& net = ctx->cnn->c;
+  for (int q = 0; q < nrhs; ++q) {
+    const int sl = slot_of[q];
+    const int* d = &G.box_d[3 * sl];
+    const size_t nv = (size_t)d[0] * d[1] * d[2];
+    if ((rc = ensure_feat(ctx, nv)) != VIE_OK) return rc;
+    VIE_HIP(cnn_ensure_ws(net, nv));
+    if ((rc = build_features(ctx, G, q, sl, hs[q].bnorm2, ctx->feat.p)) != VIE_OK) return rc;
+    VIE_HIP(timed(ctx, 14, [&] {
+      return cnn_forward(net, d, (const bf16raw*)ctx->feat.p, net.out, ctx->stream);
+    }));
+    const int nb = G.nb_host[sl];
+    const double s = nb > 0 && hs[q].bnorm2 > 0 ? sqrt(hs[q].bnorm2 / nb) : 0.0;
+    VIE_HIP(launch_cnn_gather(G.x.as<c64>() + G.roff_host[q], net.out, d, &G.box_lo[3 * sl],
+                              G.g.N, G.vox_all.as<int>() + G.voff_host[sl], nb, s, ctx->stream));
+  }
+  return VIE_OK;
+}
+
 // ---------------------------------------------------------------- solver
 // Restarted BiCGSTAB with FP64 vectors.  Each cycle iterates on the current
 // residual r with the FP64 (VIE_FP64) or FP32 (VIE_MIXED) product until the
@@ -548,7 +642,13 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
   VIE_HIP(timed(ctx, 11, [&] {
     return launch_finalize(FIN_INIT, nrhs, vb, part, st, flags, fp, ctx->stream);
   }));
+  G.res_x0.assign(nrhs, 1.0);
+  G.fallback.assign(nrhs, 0);
+  G.warm_used.assign(nrhs, 0);
   if (warm) {
+    // network prediction x0 for every right-hand side (r = b after init)
+    int rc0 = predict_x0(ctx, G);
+    if (rc0 != VIE_OK) return rc0;
     // true residual of the initial guess; reject guesses with ||r0|| >= ||b||
     EpiArgs e{EPI_RESID, rh, part, 0, pol, ph};
     VIE_HIP(run_matvec(ctx, G, 0, x, r, e, notdone));
@@ -562,26 +662,24 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
     std::vector<int> mask(nrhs, 0);
     bool any = false;
     for (int i = 0; i < nrhs; ++i) {
-      if (!(hs[i].rnorm2 < hs[i].bnorm2)) {
+      G.warm_used[i] = 1;
+      G.res_x0[i] = hs[i].bnorm2 > 0 ? sqrt(hs[i].rnorm2 / hs[i].bnorm2) : 0.0;
+      if (hs[i].bnorm2 > 0 && !(hs[i].rnorm2 < hs[i].bnorm2)) {
         mask[i] = 1;
         any = true;
+        G.fallback[i] = 1;
         fallback_out[i] = 1;
       }
     }
     if (any) {
-      DevBuf dmask;
-      VIE_HIP(dmask.reserve(nrhs * sizeof(int)));
-      VIE_HIP(hipMemcpyAsync(dmask.p, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+      // fall back to x0 = 0 for the rejected right-hand sides only
+      int* dmask = G.mask.as<int>();
+      VIE_HIP(hipMemcpyAsync(dmask, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
                              ctx->stream));
-      VIE_HIP(launch_init_zero_guess(g, bi, vb, pol, ph, x, r, rh, part, 0, dmask.as<int>(),
-                                     ctx->stream));
-      // FIN_INIT only for the masked right-hand sides: reuse notdone as gate by
-      // running FIN_RESTART semantics after re-initialising (bnorm2 unchanged).
+      VIE_HIP(launch_init_zero_guess(g, bi, vb, pol, ph, x, r, rh, part, 0, dmask, ctx->stream));
       VIE_HIP(hipMemcpyAsync(notdone, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
                              ctx->stream));
       VIE_HIP(launch_finalize(FIN_RESTART, nrhs, vb, part, st, flags, fp, ctx->stream));
-      VIE_HIP(hipStreamSynchronize(ctx->stream));
-      // restore notdone for the others from their state
       VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
                              ctx->stream));
       VIE_HIP(hipStreamSynchronize(ctx->stream));
@@ -684,7 +782,7 @@ extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* 
     for (int c = 0; c < 3; ++c)
       if (!isfinite(w.pol[c].re) || !isfinite(w.pol[c].im)) return VIE_EINVAL;
   }
-  if (ctx->opt.warm_start) return VIE_ENOTSUP;  // no network loaded in this build
+  if (ctx->opt.warm_start && !ctx->cnn) return VIE_EINVAL;  // warm start needs vie_attach_cnn
   // assign right-hand sides to groups
   std::vector<int> first(nb);
   {
@@ -746,7 +844,8 @@ extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* 
     VIE_HIP(hipMemcpyAsync(G.ph.p, ph.data(), ph.size() * sizeof(c64), hipMemcpyHostToDevice,
                            ctx->stream));
     std::vector<int> fb;
-    rc = solve_group(ctx, G, false, fb);
+    G.samples_ready = false;
+    rc = solve_group(ctx, G, ctx->opt.warm_start != 0, fb);
     if (rc != VIE_OK) return rc;
   }
   // statistics
@@ -771,10 +870,10 @@ extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* 
           o.matvecs = 2 * S.iters + S.cycles;
           o.cycles = S.cycles;
           o.converged = conv;
-          o.fallback = 0;
-          o.warm = 0;
+          o.fallback = G.fallback.empty() ? 0 : G.fallback[B.rhs0 + q];
+          o.warm = G.warm_used.empty() ? 0 : G.warm_used[B.rhs0 + q];
           o.rel_res = rel;
-          o.rel_res_x0 = 1.0;
+          o.rel_res_x0 = G.res_x0.empty() ? 1.0 : G.res_x0[B.rhs0 + q];
         }
       }
     }
@@ -933,6 +1032,169 @@ extern "C" int hom_g2(const vie_c64 T[4], const double* omega, double sigma, con
       if (Nc_norm) Nc_norm[k] = D > 0 ? raw / D : NAN;
     }
   }
+  return VIE_OK;
+}
+
+// ------------------------------------------------------- network (C ABI)
+extern "C" int64_t vie_cnn_num_params(void) { return cnn_offsets().total; }
+
+extern "C" int vie_cnn_create(uint64_t seed, vie_cnn** out) {
+  if (!out) return VIE_EINVAL;
+  *out = nullptr;
+  vie_cnn* net = new (std::nothrow) vie_cnn();
+  if (!net) return VIE_ENOMEM;
+  if (cnn_alloc(net->c) != hipSuccess) {
+    cnn_free(net->c);
+    delete net;
+    return VIE_ENOMEM;
+  }
+  // He-normal weights (last layer x0.1, unused output channels zero), zero biases
+  const CnnLayerOffsets o = cnn_offsets();
+  std::vector<float> p((size_t)o.total, 0.f);
+  uint64_t st = seed * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  auto next = [&]() {  // splitmix64
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  auto unif = [&]() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); };
+  for (int l = 0; l < kCnnLayers; ++l) {
+    const int ci = kCnnCh[l], co = kCnnCh[l + 1];
+    const double sd = sqrt(2.0 / (27.0 * ci)) * (l + 1 == kCnnLayers ? 0.1 : 1.0);
+    for (int t = 0; t < 27; ++t)
+      for (int a = 0; a < co; ++a)
+        for (int b = 0; b < ci; ++b) {
+          const double g = sqrt(-2.0 * log(unif())) * cos(6.283185307179586 * unif());
+          const bool dead = (l + 1 == kCnnLayers && a >= kCnnOut) || (l == 0 && b >= kCnnFeat);
+          p[o.w[l] + ((size_t)t * co + a) * ci + b] = dead ? 0.f : (float)(sd * g);
+        }
+  }
+  if (hipMemcpy(net->c.p, p.data(), p.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      cnn_refresh_bf16(net->c, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    cnn_free(net->c);
+    delete net;
+    return VIE_EDEVICE;
+  }
+  *out = net;
+  return VIE_OK;
+}
+
+extern "C" void vie_cnn_destroy(vie_cnn* net) {
+  if (!net) return;
+  (void)hipDeviceSynchronize();
+  cnn_free(net->c);
+  delete net;
+}
+
+extern "C" int vie_cnn_params(vie_cnn* net, float* host, int64_t n, int32_t set) {
+  if (!net || !host || n != cnn_offsets().total) return VIE_EINVAL;
+  vie_ctx* ctx = nullptr;
+  if (set) {
+    for (int64_t i = 0; i < n; ++i)
+      if (!isfinite(host[i])) return VIE_EINVAL;
+    VIE_HIP(hipMemcpy(net->c.p, host, n * 4, hipMemcpyHostToDevice));
+    VIE_HIP(hipMemset(net->c.m, 0, n * 4));
+    VIE_HIP(hipMemset(net->c.v, 0, n * 4));
+    net->c.step = 0;
+    VIE_HIP(cnn_refresh_bf16(net->c, nullptr));
+    VIE_HIP(hipDeviceSynchronize());
+  } else {
+    VIE_HIP(hipDeviceSynchronize());
+    VIE_HIP(hipMemcpy(host, net->c.p, n * 4, hipMemcpyDeviceToHost));
+  }
+  return VIE_OK;
+}
+
+extern "C" int vie_attach_cnn(vie_ctx* ctx, vie_cnn* net) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  ctx->cnn = net;
+  return VIE_OK;
+}
+
+static bool valid_dims(const int32_t* d) {
+  return d && d[0] > 0 && d[1] > 0 && d[2] > 0 && d[0] <= 512 && d[1] <= 512 && d[2] <= 512;
+}
+
+extern "C" int vie_cnn_sample_dev(vie_ctx* ctx, int32_t body, int32_t rhs, void* feat,
+                                  void* target, int32_t* dims) {
+  if (!ctx || !dims) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  if (body < 0 || body >= (int)ctx->bodies.size()) return VIE_EINVAL;
+  BodyRec& B = *ctx->bodies[body];
+  if (rhs < 0 || rhs >= B.nrhs) return VIE_EINVAL;
+  Group& G = *ctx->groups[B.group];
+  for (int a = 0; a < 3; ++a) dims[a] = G.box_d[3 * B.slot + a];
+  if (!feat && !target) return VIE_OK;
+  const int q = B.rhs0 + rhs;
+  std::vector<KState> hs(G.g.nrhs);
+  VIE_HIP(hipMemcpyAsync(hs.data(), G.state.p, hs.size() * sizeof(KState), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  if (!G.samples_ready) {
+    // r = b (solution x kept), v = A_32 b for every right-hand side
+    const int vb = vec_blocks_group(G);
+    VIE_HIP(launch_init_zero_guess(G.g, G.bi, vb, G.pol.as<c64>(), G.ph.as<c64>(), G.x.as<c64>(),
+                                   G.r.as<c64>(), G.rh.as<c64>(), G.partials.as<c64>(), 1,
+                                   nullptr, ctx->stream));
+    int rc = born_products(ctx, G);
+    if (rc != VIE_OK) return rc;
+    G.samples_ready = true;
+  }
+  const double bn2 = hs[q].bnorm2;
+  if (feat) {
+    int rc = build_features(ctx, G, q, B.slot, bn2, feat);
+    if (rc != VIE_OK) return rc;
+  }
+  if (target) {
+    const int nb = B.nb;
+    const double s = nb > 0 && bn2 > 0 ? sqrt(bn2 / nb) : 0.0;
+    VIE_HIP(launch_cnn_target((float*)target, dims, &G.box_lo[3 * B.slot], G.g.N,
+                              G.vox_all.as<int>() + G.voff_host[B.slot], nb,
+                              G.x.as<c64>() + G.roff_host[q], s, ctx->stream));
+  }
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  return VIE_OK;
+}
+
+extern "C" int vie_cnn_infer_dev(vie_cnn* net, const int32_t* dims, const void* feat, void* out,
+                                 void* stream) {
+  if (!net || !valid_dims(dims) || !feat || !out) return VIE_EINVAL;
+  vie_ctx* ctx = nullptr;
+  const int d[3] = {dims[0], dims[1], dims[2]};
+  VIE_HIP(cnn_forward(net->c, d, (const bf16raw*)feat, (float*)out, (hipStream_t)stream));
+  return VIE_OK;
+}
+
+extern "C" int vie_cnn_grad_dev(vie_cnn* net, const int32_t* dims, const void* feat,
+                                const void* target, float* grad_host, float* loss,
+                                void* stream) {
+  if (!net || !valid_dims(dims) || !feat || !target) return VIE_EINVAL;
+  vie_ctx* ctx = nullptr;
+  const int d[3] = {dims[0], dims[1], dims[2]};
+  hipStream_t s = (hipStream_t)stream;
+  VIE_HIP(cnn_forward(net->c, d, (const bf16raw*)feat, nullptr, s));
+  float l = 0.f;
+  VIE_HIP(cnn_backward(net->c, d, (const float*)target, &l, s));
+  if (loss) *loss = l;
+  if (grad_host) {
+    VIE_HIP(hipMemcpyAsync(grad_host, net->c.g, net->c.off.total * 4, hipMemcpyDeviceToHost, s));
+    VIE_HIP(hipStreamSynchronize(s));
+  }
+  return VIE_OK;
+}
+
+extern "C" int vie_cnn_train_step_dev(vie_cnn* net, const int32_t* dims, const void* feat,
+                                      const void* target, float lr, float* loss, void* stream) {
+  if (!net || !valid_dims(dims) || !feat || !target || !(lr > 0)) return VIE_EINVAL;
+  vie_ctx* ctx = nullptr;
+  const int d[3] = {dims[0], dims[1], dims[2]};
+  hipStream_t s = (hipStream_t)stream;
+  VIE_HIP(cnn_forward(net->c, d, (const bf16raw*)feat, nullptr, s));
+  VIE_HIP(cnn_backward(net->c, d, (const float*)target, loss, s));
+  VIE_HIP(cnn_adam(net->c, lr, s));
   return VIE_OK;
 }
 

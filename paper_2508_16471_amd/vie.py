@@ -81,6 +81,19 @@ def lib():
             "vie_set_options": (C.c_int, [C.c_void_p, P(vie_options)]),
             "vie_destroy": (None, [C.c_void_p]),
             "vie_strerror": (C.c_char_p, [C.c_int]),
+            "vie_cnn_num_params": (C.c_int64, []),
+            "vie_cnn_create": (C.c_int, [C.c_uint64, P(C.c_void_p)]),
+            "vie_cnn_destroy": (None, [C.c_void_p]),
+            "vie_cnn_params": (C.c_int, [C.c_void_p, P(C.c_float), C.c_int64, C.c_int32]),
+            "vie_attach_cnn": (C.c_int, [C.c_void_p, C.c_void_p]),
+            "vie_cnn_sample_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                             C.c_void_p, P(C.c_int32)]),
+            "vie_cnn_infer_dev": (C.c_int, [C.c_void_p, P(C.c_int32), C.c_void_p, C.c_void_p,
+                                            C.c_void_p]),
+            "vie_cnn_grad_dev": (C.c_int, [C.c_void_p, P(C.c_int32), C.c_void_p, C.c_void_p,
+                                           P(C.c_float), P(C.c_float), C.c_void_p]),
+            "vie_cnn_train_step_dev": (C.c_int, [C.c_void_p, P(C.c_int32), C.c_void_p, C.c_void_p,
+                                                 C.c_float, P(C.c_float), C.c_void_p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -213,6 +226,89 @@ def vie_kernel_times(ctx, reset=False):
     nk = C.c_int32(cap)
     _check(lib().vie_kernel_times(ctx, names, ms, cnt, C.byref(nk), int(reset)), "vie_kernel_times")
     return {names[i].decode(): (ms[i], cnt[i]) for i in range(min(cap, nk.value))}
+
+
+# ------------------------------------------------------------ network
+def vie_cnn_num_params():
+    return int(lib().vie_cnn_num_params())
+
+
+def vie_cnn_create(seed=0):
+    net = C.c_void_p()
+    _check(lib().vie_cnn_create(C.c_uint64(seed), C.byref(net)), "vie_cnn_create")
+    return net
+
+
+def vie_cnn_destroy(net):
+    if net:
+        lib().vie_cnn_destroy(net)
+
+
+def vie_cnn_params(net, params=None):
+    """Get (params None) or set the fp32 parameter vector."""
+    n = vie_cnn_num_params()
+    if params is None:
+        out = np.zeros(n, dtype=np.float32)
+        _check(lib().vie_cnn_params(net, out.ctypes.data_as(C.POINTER(C.c_float)), n, 0), "vie_cnn_params")
+        return out
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().vie_cnn_params(net, p.ctypes.data_as(C.POINTER(C.c_float)), n, 1), "vie_cnn_params")
+    return p
+
+
+def vie_attach_cnn(ctx, net):
+    _check(lib().vie_attach_cnn(ctx, net), "vie_attach_cnn")
+
+
+def _dims(d):
+    return (C.c_int32 * 3)(*[int(v) for v in d])
+
+
+def vie_cnn_sample_dev(ctx, body, rhs, feat_ptr=0, target_ptr=0):
+    """Returns box dims (d0, d1, d2); fills device tensors when pointers given."""
+    d = (C.c_int32 * 3)()
+    _check(lib().vie_cnn_sample_dev(ctx, int(body), int(rhs), C.c_void_p(feat_ptr or None),
+                                    C.c_void_p(target_ptr or None), d), "vie_cnn_sample_dev")
+    return tuple(d)
+
+
+def vie_cnn_infer_dev(net, dims, feat_ptr, out_ptr, stream=0):
+    _check(lib().vie_cnn_infer_dev(net, _dims(dims), C.c_void_p(feat_ptr), C.c_void_p(out_ptr),
+                                   C.c_void_p(stream or None)), "vie_cnn_infer_dev")
+
+
+def vie_cnn_grad_dev(net, dims, feat_ptr, target_ptr, stream=0):
+    n = vie_cnn_num_params()
+    g = np.zeros(n, dtype=np.float32)
+    loss = C.c_float()
+    _check(lib().vie_cnn_grad_dev(net, _dims(dims), C.c_void_p(feat_ptr), C.c_void_p(target_ptr),
+                                  g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss),
+                                  C.c_void_p(stream or None)), "vie_cnn_grad_dev")
+    return float(loss.value), g
+
+
+def vie_cnn_train_step_dev(net, dims, feat_ptr, target_ptr, lr, stream=0):
+    loss = C.c_float()
+    _check(lib().vie_cnn_train_step_dev(net, _dims(dims), C.c_void_p(feat_ptr), C.c_void_p(target_ptr),
+                                        C.c_float(lr), C.byref(loss), C.c_void_p(stream or None)),
+           "vie_cnn_train_step_dev")
+    return float(loss.value)
+
+
+def cnn_param_shapes():
+    """[(W shape (27, Cout, Cin), b shape (Cout,))] of the network layers."""
+    ch = [16, 32, 32, 32, 16]
+    return [((27, co, ci), (co,)) for ci, co in zip(ch[:-1], ch[1:])]
+
+
+def cnn_unpack(p):
+    """Split the flat parameter vector into [(W, b)] (views)."""
+    out, at = [], 0
+    for ws, bs in cnn_param_shapes():
+        nw = int(np.prod(ws))
+        out.append((p[at:at + nw].reshape(ws), p[at + nw:at + nw + bs[0]]))
+        at += nw + bs[0]
+    return out
 
 
 def vie_destroy(ctx):

@@ -13,7 +13,7 @@ LIB = os.path.join(ROOT, "paper_2508_16471_amd", "libvie.so")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:int64_t|int|void|const char)\s+\**\s*(\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
