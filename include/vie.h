@@ -173,17 +173,18 @@ int vie_set_options(vie_ctx *ctx, const vie_options *opt);
 /* ------------------------------------------------------------------------
  * Learned warm start (a data-driven initial guess for the BiCGSTAB solve of
  * eq. 24; the paper's own acceleration is a block preconditioner, Sec. II-C).
- * A 4-layer 3x3x3 convolutional network (16 -> 32 -> 32 -> 32 -> 16 channels,
+ * A 4-layer 3x3x3 convolutional network (32 -> 32 -> 32 -> 32 -> 16 channels,
  * ReLU between layers, bf16 weights and activations, fp32 accumulation)
  * evaluated on each body's bounding box plus a 4-voxel halo, channels-last.
- * Input channels: chi/4, b/s (re, im of x, y, z), (b - A b)/s (same order),
- * zeros; b = chi e, s = rms of |b| over the body voxels, A b with the FP32
- * product.  Outputs 0..5: the predicted w/s (re, im of x, y, z).  The solver
+ * Input channels: chi/4, then the Krylov vectors b, A b, A^2 b, A^3 b (FP32
+ * products), each divided by its own rms over the body voxels (re, im of x, y,
+ * z, six channels per vector), zeros; b = chi e.  Outputs 0..5: the predicted
+ * w/s (re, im of x, y, z), s = rms of |b| over the body voxels.  The solver
  * uses x0 = s * output only if ||b - A x0|| < ||b|| (FP64 operator), else
  * x0 = 0 (vie_stats.fallback).
  * Parameters (fp32, host): per layer W[27][Cout][Cin] (tap (dz+1)*9 +
  * (dy+1)*3 + (dx+1)) followed by b[Cout].  Device tensors: features
- * [d2][d1][d0][16] bf16, targets [d2][d1][d0][6] fp32, outputs
+ * [d2][d1][d0][32] bf16, targets [d2][d1][d0][6] fp32, outputs
  * [d2][d1][d0][16] fp32 (dims = (d0, d1, d2)).  Loss: masked relative L2
  * sum_body |out - t|^2 / sum_body |t|^2 over outputs 0..5 (mask: chi > 0).
  * ------------------------------------------------------------------------ */

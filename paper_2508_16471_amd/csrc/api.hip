@@ -82,6 +82,8 @@ struct Group {
   BodyIdx bi;
   DevBuf x, r, rh, p, v, s, t;   // c64, body-compressed, all right-hand sides
   DevBuf mask;                   // int [cap] scratch mask
+  DevBuf knorm;                  // double [4][cap] norms of the network's Krylov inputs
+  std::vector<double> knorm_host;
   // learned warm start: per body, network box = bounding box + 4-voxel halo
   std::vector<int> box_lo, box_d;        // [slot][3]
   std::vector<double> res_x0;            // per rhs: relative residual of the initial guess
@@ -459,6 +461,7 @@ static int ensure_solve_storage(vie_ctx* ctx, Group& G, int nrhs) {
   VIE_HIP(G.ph.reserve((size_t)nrhs * (G.g.N[0] + G.g.N[1] + G.g.N[2]) * sizeof(c64)));
   VIE_HIP(G.roff.reserve((size_t)nrhs * sizeof(int64_t)));
   VIE_HIP(G.mask.reserve((size_t)nrhs * sizeof(int)));
+  VIE_HIP(G.knorm.reserve((size_t)4 * nrhs * sizeof(double)));
   G.cap = nrhs;
   return VIE_OK;
 }
@@ -547,35 +550,53 @@ static hipError_t run_matvec(vie_ctx* ctx, Group& G, int precision, const c64* x
 }
 
 // ------------------------------------------------------ learned warm start
-// v = A_32 r for every right-hand side (r holds b after the init kernel).
-static int born_products(vie_ctx* ctx, Group& G) {
-  EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
-  VIE_HIP(run_matvec(ctx, G, 1, G.r.as<c64>(), G.v.as<c64>(), e, nullptr));
+// Krylov inputs of the network for every right-hand side, r holding b after
+// the init kernel: v = A r, s = A v, t = A s (FP32 products), and the squared
+// norm of each of r, v, s, t (host copy in knorm_host[k * nrhs + q]).
+static int krylov_inputs(vie_ctx* ctx, Group& G) {
+  const int nrhs = G.g.nrhs;
+  c64* vec[4] = {G.r.as<c64>(), G.v.as<c64>(), G.s.as<c64>(), G.t.as<c64>()};
+  for (int k = 0; k < 3; ++k) {
+    EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
+    VIE_HIP(run_matvec(ctx, G, 1, vec[k], vec[k + 1], e, nullptr));
+  }
+  for (int k = 0; k < 4; ++k)
+    VIE_HIP(launch_vec_norm2(nrhs, G.bi, vec[k], G.knorm.as<double>() + (size_t)k * nrhs,
+                             ctx->stream));
+  G.knorm_host.resize((size_t)4 * nrhs);
+  VIE_HIP(hipMemcpyAsync(G.knorm_host.data(), G.knorm.p, G.knorm_host.size() * sizeof(double),
+                         hipMemcpyDeviceToHost, ctx->stream));
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
   return VIE_OK;
 }
 
 static int ensure_feat(vie_ctx* ctx, size_t vox) {
-  VIE_HIP(ctx->feat.reserve(vox * 16 * sizeof(uint16_t)));
+  VIE_HIP(ctx->feat.reserve(vox * kCnnIn * sizeof(uint16_t)));
   return VIE_OK;
 }
 
-// Features of right-hand side q (body slot sl) into feat (bf16 [box][16]).
-static int build_features(vie_ctx* ctx, Group& G, int q, int sl, double bnorm2, void* feat) {
+// Features of right-hand side q (body slot sl) into feat (bf16 [box][32]).
+static int build_features(vie_ctx* ctx, Group& G, int q, int sl, void* feat) {
   const int* d = &G.box_d[3 * sl];
   const int* lo = &G.box_lo[3 * sl];
   const int nb = G.nb_host[sl];
-  const double s = nb > 0 && bnorm2 > 0 ? sqrt(bnorm2 / nb) : 0.0;
-  const c64* b = G.r.as<c64>() + G.roff_host[q];
-  const c64* Ab = G.v.as<c64>() + G.roff_host[q];
+  const int nrhs = G.g.nrhs;
+  const c64* vec[4] = {G.r.as<c64>() + G.roff_host[q], G.v.as<c64>() + G.roff_host[q],
+                       G.s.as<c64>() + G.roff_host[q], G.t.as<c64>() + G.roff_host[q]};
+  double inv[4];
+  for (int k = 0; k < 4; ++k) {
+    const double n2 = G.knorm_host[(size_t)k * nrhs + q];
+    inv[k] = nb > 0 && n2 > 0 ? 1.0 / sqrt(n2 / nb) : 0.0;
+  }
   VIE_HIP(launch_cnn_features((bf16raw*)feat, d, lo, G.g.N, G.vox_all.as<int>() + G.voff_host[sl],
-                              G.chic_all.as<double>() + G.voff_host[sl], nb, b, Ab, s,
+                              G.chic_all.as<double>() + G.voff_host[sl], nb, vec, inv,
                               ctx->stream));
   return VIE_OK;
 }
 
 static int predict_x0(vie_ctx* ctx, Group& G) {
   if (!ctx->cnn) return VIE_ESTATE;
-  int rc = born_products(ctx, G);
+  int rc = krylov_inputs(ctx, G);
   if (rc != VIE_OK) return rc;
   const int nrhs = G.g.nrhs;
   std::vector<KState> hs(nrhs);
@@ -594,7 +615,7 @@ static int predict_x0(vie_ctx* ctx, Group& G) {
     const size_t nv = (size_t)d[0] * d[1] * d[2];
     if ((rc = ensure_feat(ctx, nv)) != VIE_OK) return rc;
     VIE_HIP(cnn_ensure_ws(net, nv));
-    if ((rc = build_features(ctx, G, q, sl, hs[q].bnorm2, ctx->feat.p)) != VIE_OK) return rc;
+    if ((rc = build_features(ctx, G, q, sl, ctx->feat.p)) != VIE_OK) return rc;
     VIE_HIP(timed(ctx, 14, [&] {
       return cnn_forward(net, d, (const bf16raw*)ctx->feat.p, net.out, ctx->stream);
     }));
@@ -1139,13 +1160,13 @@ extern "C" int vie_cnn_sample_dev(vie_ctx* ctx, int32_t body, int32_t rhs, void*
     VIE_HIP(launch_init_zero_guess(G.g, G.bi, vb, G.pol.as<c64>(), G.ph.as<c64>(), G.x.as<c64>(),
                                    G.r.as<c64>(), G.rh.as<c64>(), G.partials.as<c64>(), 1,
                                    nullptr, ctx->stream));
-    int rc = born_products(ctx, G);
+    int rc = krylov_inputs(ctx, G);
     if (rc != VIE_OK) return rc;
     G.samples_ready = true;
   }
   const double bn2 = hs[q].bnorm2;
   if (feat) {
-    int rc = build_features(ctx, G, q, B.slot, bn2, feat);
+    int rc = build_features(ctx, G, q, B.slot, feat);
     if (rc != VIE_OK) return rc;
   }
   if (target) {

@@ -14,12 +14,15 @@ namespace vie {
 
 using bf16raw = uint16_t;
 
-// Architecture: 16 -> 32 -> 32 -> 32 -> 16 channels, ReLU between layers.
-// Input features (13 used): chi/4, b/s (re,im x 3), (b - A b)/s (re,im x 3)
-// with s = rms of |b| over the body; outputs 0..5 = w/s (re,im x 3).
+// Architecture: 32 -> 32 -> 32 -> 32 -> 16 channels, ReLU between layers.
+// Input features (25 used): chi/4 and the Krylov vectors b, A b, A^2 b, A^3 b
+// (FP32 products), each divided by its rms over the body (re, im of x, y, z);
+// outputs 0..5 = w/s (re,im x 3) with s = rms of |b| over the body.
 constexpr int kCnnLayers = 4;
-constexpr int kCnnCh[kCnnLayers + 1] = {16, 32, 32, 32, 16};
-constexpr int kCnnFeat = 13;
+constexpr int kCnnCh[kCnnLayers + 1] = {32, 32, 32, 32, 16};
+constexpr int kCnnKrylov = 4;
+constexpr int kCnnFeat = 1 + 6 * kCnnKrylov;
+constexpr int kCnnIn = 32;  // feature channels (padded)
 constexpr int kCnnOut = 6;
 
 struct CnnLayerOffsets {
@@ -58,11 +61,13 @@ hipError_t cnn_backward(Cnn& c, const int d[3], const float* target, float* loss
                         hipStream_t s);
 hipError_t cnn_adam(Cnn& c, float lr, hipStream_t s);
 
-// features of one right-hand side on its body's box: b and Ab body-compressed
-// (component-major, nb voxels), scale s; box origin lo[3] and dims d[3].
+// features of one right-hand side on its body's box: Krylov vectors vec[k]
+// body-compressed (component-major, nb voxels) with scales inv[k] (1/rms);
+// box origin lo[3] and dims d[3].
 hipError_t launch_cnn_features(bf16raw* feat, const int d[3], const int lo[3], const int N[3],
-                               const int* vox, const double* chic, int nb, const c64* b,
-                               const c64* Ab, double s, hipStream_t st);
+                               const int* vox, const double* chic, int nb,
+                               const c64* const vec[kCnnKrylov], const double inv[kCnnKrylov],
+                               hipStream_t st);
 hipError_t launch_cnn_target(float* tgt, const int d[3], const int lo[3], const int N[3],
                              const int* vox, int nb, const c64* w, double s, hipStream_t st);
 hipError_t launch_cnn_gather(c64* x, const float* out, const int d[3], const int lo[3],

@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void k_loss_partial(const float* __restrict__ 
   __shared__ float sn[256], sd[256];
   float num = 0.f, den = 0.f;
   for (size_t v = (size_t)blockIdx.x * 256 + threadIdx.x; v < nvox; v += (size_t)gridDim.x * 256) {
-    if (bf2f(feat[v * 16]) > 0.f) {
+    if (bf2f(feat[v * kCnnIn]) > 0.f) {
 #pragma unroll
       for (int c = 0; c < kCnnOut; ++c) {
         const float t = tgt[v * kCnnOut + c], d = out[v * 16 + c] - t;
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(256) void k_loss_grad(const float* __restrict__ out
     const size_t v = e / 16;
     const int c = (int)(e % 16);
     float val = 0.f;
-    if (c < kCnnOut && bf2f(feat[v * 16]) > 0.f) val = inv * (out[e] - tgt[v * kCnnOut + c]);
+    if (c < kCnnOut && bf2f(feat[v * kCnnIn]) > 0.f) val = inv * (out[e] - tgt[v * kCnnOut + c]);
     g[e] = f2bf(val);
   }
 }
@@ -359,22 +359,25 @@ struct Box {
   int d[3], lo[3], N[3];
 };
 
+struct KrylovIn {
+  const c64* v[kCnnKrylov];
+  double inv[kCnnKrylov];
+};
+
 __global__ void k_cnn_features(bf16raw* __restrict__ feat, Box bx, const int* __restrict__ vox,
-                               const double* __restrict__ chic, int nb,
-                               const c64* __restrict__ b, const c64* __restrict__ Ab,
-                               double inv_s) {
+                               const double* __restrict__ chic, int nb, KrylovIn kin) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += gridDim.x * blockDim.x) {
     const size_t v = box_index(vox[k], bx.N, bx.lo, bx.d);
-    bf16raw* f = feat + v * 16;
+    bf16raw* f = feat + v * kCnnIn;
     f[0] = f2bf((float)(chic[k] * 0.25));
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const c64 bv = b[(size_t)c * nb + k], av = Ab[(size_t)c * nb + k];
-      f[1 + 2 * c] = f2bf((float)(bv.re * inv_s));
-      f[2 + 2 * c] = f2bf((float)(bv.im * inv_s));
-      f[7 + 2 * c] = f2bf((float)((bv.re - av.re) * inv_s));
-      f[8 + 2 * c] = f2bf((float)((bv.im - av.im) * inv_s));
-    }
+    for (int q = 0; q < kCnnKrylov; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const c64 bv = kin.v[q][(size_t)c * nb + k];
+        f[1 + 6 * q + 2 * c] = f2bf((float)(bv.re * kin.inv[q]));
+        f[2 + 6 * q + 2 * c] = f2bf((float)(bv.im * kin.inv[q]));
+      }
   }
 }
 
@@ -419,13 +422,18 @@ static int grid_for(int64_t n, int per = 256) {
 }
 
 hipError_t launch_cnn_features(bf16raw* feat, const int d[3], const int lo[3], const int N[3],
-                               const int* vox, const double* chic, int nb, const c64* b,
-                               const c64* Ab, double s, hipStream_t st) {
+                               const int* vox, const double* chic, int nb,
+                               const c64* const vec[kCnnKrylov], const double inv[kCnnKrylov],
+                               hipStream_t st) {
   const size_t nv = (size_t)d[0] * d[1] * d[2];
-  hipError_t e = hipMemsetAsync(feat, 0, nv * 16 * sizeof(bf16raw), st);
+  hipError_t e = hipMemsetAsync(feat, 0, nv * kCnnIn * sizeof(bf16raw), st);
   if (e != hipSuccess || nb == 0) return e;
-  k_cnn_features<<<grid_for(nb), 256, 0, st>>>(feat, mkbox(d, lo, N), vox, chic, nb, b, Ab,
-                                               s > 0 ? 1.0 / s : 0.0);
+  KrylovIn kin;
+  for (int q = 0; q < kCnnKrylov; ++q) {
+    kin.v[q] = vec[q];
+    kin.inv[q] = inv[q];
+  }
+  k_cnn_features<<<grid_for(nb), 256, 0, st>>>(feat, mkbox(d, lo, N), vox, chic, nb, kin);
   return hipGetLastError();
 }
 
@@ -534,7 +542,7 @@ hipError_t cnn_forward(Cnn& c, const int d[3], const bf16raw* feat, float* out, 
   hipError_t e = cnn_ensure_ws(c, (size_t)d[0] * d[1] * d[2]);
   if (e != hipSuccess) return e;
   c.act[0] = const_cast<bf16raw*>(feat);
-  conv<16, 32, 0>(cd, feat, c.wf + bf16_weight_offset(0), c.p + c.off.b[0], c.act[1], nullptr,
+  conv<32, 32, 0>(cd, feat, c.wf + bf16_weight_offset(0), c.p + c.off.b[0], c.act[1], nullptr,
                   nullptr, s);
   conv<32, 32, 0>(cd, c.act[1], c.wf + bf16_weight_offset(1), c.p + c.off.b[1], c.act[2],
                   nullptr, nullptr, s);
@@ -564,7 +572,7 @@ hipError_t cnn_backward(Cnn& c, const int d[3], const float* target, float* loss
   wgrad<32, 32>(cd, c.act[1], c.gbuf[0], c.wpart, c.g + c.off.w[1], s);
   conv<32, 32, 2>(cd, c.gbuf[0], c.wb + bf16_weight_offset(1), nullptr, c.gbuf[1], nullptr,
                   c.act[1], s);
-  wgrad<16, 32>(cd, c.act[0], c.gbuf[1], c.wpart, c.g + c.off.w[0], s);
+  wgrad<32, 32>(cd, c.act[0], c.gbuf[1], c.wpart, c.g + c.off.w[0], s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (loss_host) {

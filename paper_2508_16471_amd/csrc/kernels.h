@@ -137,6 +137,9 @@ hipError_t launch_farfield_ks(const GroupGeom& g, const c64* w, const int64_t* r
                               int nr, const int* vox, int nb, const double* dirs, int nd,
                               double k0, double h, const double* origin, c64* part, int chunk,
                               c64* F, hipStream_t s);
+// ||v_rhs||^2 of body-compressed vectors into out[nrhs] (device).
+hipError_t launch_vec_norm2(int nrhs, const BodyIdx& bi, const c64* v, double* out,
+                            hipStream_t s);
 // Gather a box-layout vector [3][n] into body-compressed storage [3][nb].
 hipError_t launch_compress(const c64* box, c64* comp, const int* vox, int nb, int64_t n,
                            hipStream_t s);

@@ -163,6 +163,20 @@ __global__ __launch_bounds__(VT) void k_update_xr(BodyIdx bi, const KState* __re
   }
 }
 
+// squared norm of every right-hand side's vector (one workgroup each)
+__global__ __launch_bounds__(VT) void k_vec_norm2(BodyIdx bi, const c64* __restrict__ v,
+                                                  double* __restrict__ out) {
+  const int rhs = blockIdx.x;
+  const VecRange R = vrange(bi, rhs);
+  c64 a = mk(0.0, 0.0), b = mk(0.0, 0.0);
+  for (int64_t e = threadIdx.x; e < R.len; e += VT) {
+    const c64 x = v[R.base + e];
+    a.re += x.re * x.re + x.im * x.im;
+  }
+  block_reduce2(a, b);
+  if (threadIdx.x == 0) out[rhs] = a.re;
+}
+
 // body-compressed gather of a box-layout vector
 __global__ __launch_bounds__(VT) void k_compress(const c64* __restrict__ box, c64* __restrict__ out,
                                                  const int* __restrict__ vox, int nb, int64_t n) {
@@ -293,6 +307,11 @@ hipError_t launch_update_xr(const GroupGeom& g, const BodyIdx& bi, int vb, const
                             const int* active, c64* x, c64* r, const c64* p, const c64* sv,
                             const c64* t, const c64* rh, c64* partials, hipStream_t s) {
   k_update_xr<<<vb * g.nrhs, VT, 0, s>>>(bi, st, active, x, r, p, sv, t, rh, partials, vb);
+  return hipGetLastError();
+}
+hipError_t launch_vec_norm2(int nrhs, const BodyIdx& bi, const c64* v, double* out,
+                           hipStream_t s) {
+  k_vec_norm2<<<nrhs, VT, 0, s>>>(bi, v, out);
   return hipGetLastError();
 }
 hipError_t launch_compress(const c64* box, c64* comp, const int* vox, int nb, int64_t n,

@@ -297,7 +297,7 @@ def vie_cnn_train_step_dev(net, dims, feat_ptr, target_ptr, lr, stream=0):
 
 def cnn_param_shapes():
     """[(W shape (27, Cout, Cin), b shape (Cout,))] of the network layers."""
-    ch = [16, 32, 32, 32, 16]
+    ch = [32, 32, 32, 32, 16]
     return [((27, co, ci), (co,)) for ci, co in zip(ch[:-1], ch[1:])]
 
 

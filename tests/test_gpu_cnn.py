@@ -41,8 +41,8 @@ def _oracle_params(V, p):
 
 
 def _features(rng, d):
-    f = np.zeros((d[2], d[1], d[0], 16))
-    f[..., :13] = rng.standard_normal((d[2], d[1], d[0], 13))
+    f = np.zeros((d[2], d[1], d[0], 32))
+    f[..., :25] = rng.standard_normal((d[2], d[1], d[0], 25))
     body = rng.random((d[2], d[1], d[0])) < 0.4
     f[..., 0] = np.where(body, rng.uniform(0.2, 1.5, body.shape), 0.0)
     return cr.bf16_round(f), body
@@ -121,7 +121,7 @@ def test_sample_tensors_and_warm_started_solve(env):
         V.vie_solve(ctx, chans, [2])
         w = V.vie_get_current(ctx, 0, 1, g.n)
         d = V.vie_cnn_sample_dev(ctx, 0, 1)
-        ft = torch.zeros((d[2], d[1], d[0], 16), dtype=torch.bfloat16, device="cuda")
+        ft = torch.zeros((d[2], d[1], d[0], 32), dtype=torch.bfloat16, device="cuda")
         tt = torch.zeros((d[2], d[1], d[0], 6), dtype=torch.float32, device="cuda")
         V.vie_cnn_sample_dev(ctx, 0, 1, ft.data_ptr(), tt.data_ptr())
         f = ft.float().cpu().numpy()
