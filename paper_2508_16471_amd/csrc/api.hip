@@ -94,7 +94,13 @@ struct Group {
   DevBuf state;                  // KState [cap]
   DevBuf flags;                  // int [2][cap]
   DevBuf rhs_body, pol, ph;      // per right-hand side
-  DevBuf dirs, part, F;          // far-field scratch
+  DevBuf dirs, part, F, wd;      // far-field scratch
+  // far-field voxel blocks per body (built on first use; the body never changes)
+  struct Far {
+    FarBlocks fb;
+    DevBuf vi, org;
+  };
+  std::vector<std::unique_ptr<Far>> far;  // [slot]
   int zvar[2] = {-1, -1};        // autotuned z-pass shape per precision (-1: not yet)
   int zvar_nrhs[2] = {0, 0};     // right-hand-side count it was tuned for
 };
@@ -998,20 +1004,31 @@ extern "C" int vie_farfield(vie_ctx* ctx, int32_t body, const double* theta, con
     memset(F, 0, outn * sizeof(vie_c64));
     return VIE_OK;
   }
-  const int dblocks = (ndir + 63) / 64;
-  int ks = std::max(1, std::min((B.nb + 63) / 64, 2048 / dblocks));
-  const int chunk = (B.nb + ks - 1) / ks;
-  ks = (B.nb + chunk - 1) / chunk;
+  if (G.far.size() < G.bodies.size()) G.far.resize(G.bodies.size());
+  if (!G.far[B.slot]) {
+    std::unique_ptr<Group::Far> fr(new Group::Far);
+    far_blocks_build(G.vox_host.data() + G.voff_host[B.slot], B.nb, G.g.N, fr->fb);
+    VIE_HIP(fr->vi.reserve(fr->fb.vi.size() * sizeof(int)));
+    VIE_HIP(fr->org.reserve(fr->fb.org.size() * sizeof(int)));
+    VIE_HIP(hipMemcpyAsync(fr->vi.p, fr->fb.vi.data(), fr->fb.vi.size() * sizeof(int),
+                           hipMemcpyHostToDevice, ctx->stream));
+    VIE_HIP(hipMemcpyAsync(fr->org.p, fr->fb.org.data(), fr->fb.org.size() * sizeof(int),
+                           hipMemcpyHostToDevice, ctx->stream));
+    G.far[B.slot] = std::move(fr);
+  }
+  const Group::Far& fr = *G.far[B.slot];
+  const int ks = far_split(fr.fb.ntiles, ndir);
   VIE_HIP(G.dirs.reserve(dirs.size() * sizeof(double)));
-  VIE_HIP(G.part.reserve((size_t)ks * 4 * ndir * 3 * sizeof(c64)));
+  VIE_HIP(G.part.reserve((size_t)ks * 2 * ndir * 3 * sizeof(c64)));
+  VIE_HIP(G.wd.reserve(far_pack_elems(fr.fb.ntiles) * sizeof(c64)));
   VIE_HIP(G.F.reserve(outn * sizeof(c64)));
   VIE_HIP(hipMemcpyAsync(G.dirs.p, dirs.data(), dirs.size() * sizeof(double),
                          hipMemcpyHostToDevice, ctx->stream));
   VIE_HIP(timed(ctx, 12, [&] {
-    return launch_farfield_ks(G.g, G.x.as<c64>(), G.roff_host.data() + B.rhs0, B.nrhs,
-                              G.vox_all.as<int>() + G.voff_host[B.slot], B.nb,
-                              G.dirs.as<double>(), ndir, ctx->opt.k0, G.h, B.origin,
-                              G.part.as<c64>(), chunk, G.F.as<c64>(), ctx->stream);
+    return launch_farfield_mfma(G.x.as<c64>(), G.roff_host.data() + B.rhs0, B.nrhs, B.nb, fr.fb,
+                                fr.vi.as<int>(), fr.org.as<int>(), G.dirs.as<double>(), ndir,
+                                ctx->opt.k0, G.h, B.origin, G.wd.as<c64>(), G.part.as<c64>(),
+                                G.F.as<c64>(), ctx->stream);
   }));
   VIE_HIP(hipMemcpyAsync(F, G.F.p, outn * sizeof(c64), hipMemcpyDeviceToHost, ctx->stream));
   VIE_HIP(hipStreamSynchronize(ctx->stream));

@@ -2,88 +2,261 @@
 //   F(r) = k0^2 h^3 / (4 pi) (I - r r) sum_n w_n exp(-i k0 r . r_n),
 // reported as (F_theta, F_phi) = (theta-hat . F, phi-hat . F).
 //
-// Contraction over the body voxels n, split across workgroups (K-split) and
-// reduced in fixed order by a second kernel that also projects onto
-// theta-hat / phi-hat and applies the constant.
+// The sum over voxels is a dense complex contraction [directions x voxels] x
+// [voxels x 3R] run on FP64 MFMA (v_mfma_f64_16x16x4f64).  The phase matrix is
+// never stored: the body voxels are grouped into aligned blocks of 16 voxels
+// (shape bx x by x bz, chosen per body to minimise padding), and for a voxel
+// at block origin o_b plus offset u the phase factors as
+//   exp(-i k0 r.(o + h(o_b + u))) = S(r, b) A(r, u),
+// S(r, b) = exp(-i k0 r.(o + h o_b)),   A(r, u) = exp(-i k0 h r.u).
+// A is the same for every block, so it stays in registers as the MFMA's left
+// operand for the whole kernel; each block contributes
+//   G(r, b, qc) = sum_u A(r, u) W(b, u, qc)   (16x16x16 complex tiles on MFMA)
+// and is scaled by S(r, b) (one sincos per direction and block) and summed.
+// The accumulation over blocks is split across workgroups (K-split) and
+// reduced in fixed order by a second kernel that projects onto theta-hat /
+// phi-hat and applies the constant.
+#include <algorithm>
+#include <vector>
+
 #include "kernels.h"
 
 namespace vie {
 
-static constexpr int FF_D = 64;   // directions per workgroup
-static constexpr int FF_S = 4;    // voxel sub-lanes per direction
-static constexpr int FF_NR = 4;   // right-hand sides per pass
-static constexpr int FF_CH = 64;  // voxels staged in LDS per step
+typedef double d4 __attribute__((ext_vector_type(4)));
 
+static constexpr int FF_RB = 2;          // right-hand sides per pass
+static constexpr int FF_QC = 3 * FF_RB;  // complex columns per block (rhs x component)
+static constexpr int FF_BS = 16;         // voxels per block (MFMA K = 4 per step, 4 steps)
+static constexpr int FF_TB = 16;         // blocks per tile (MFMA N)
+static constexpr int FF_WAVES = 4;       // waves per workgroup, 16 directions each
+static constexpr int FF_DIRS = 16 * FF_WAVES;
+static constexpr int FF_TILE = FF_QC * FF_BS * FF_TB;  // c64 per packed tile
+
+// ------------------------------------------------------------ host: blocks
+void far_blocks_build(const int* vox, int nb, const int N[3], FarBlocks& fb) {
+  static const int shapes[][3] = {{16, 1, 1}, {8, 2, 1}, {4, 4, 1}, {4, 2, 2}, {2, 4, 2},
+                                  {2, 2, 4}, {1, 4, 4}, {2, 8, 1}, {1, 16, 1}, {1, 1, 16}};
+  int best = 0;
+  int64_t best_cnt = -1;
+  std::vector<uint8_t> mark;
+  for (int s = 0; s < (int)(sizeof(shapes) / sizeof(shapes[0])); ++s) {
+    const int bx = shapes[s][0], by = shapes[s][1], bz = shapes[s][2];
+    const int gx = (N[0] + bx - 1) / bx, gy = (N[1] + by - 1) / by, gz = (N[2] + bz - 1) / bz;
+    mark.assign((size_t)gx * gy * gz, 0);
+    int64_t cnt = 0;
+    for (int k = 0; k < nb; ++k) {
+      const int lin = vox[k];
+      const int i = lin % N[0], j = (lin / N[0]) % N[1], z = lin / (N[0] * N[1]);
+      const size_t key = ((size_t)(z / bz) * gy + j / by) * gx + i / bx;
+      if (!mark[key]) {
+        mark[key] = 1;
+        ++cnt;
+      }
+    }
+    if (best_cnt < 0 || cnt < best_cnt) {
+      best_cnt = cnt;
+      best = s;
+    }
+  }
+  const int bx = shapes[best][0], by = shapes[best][1], bz = shapes[best][2];
+  fb.shape[0] = bx;
+  fb.shape[1] = by;
+  fb.shape[2] = bz;
+  const int gx = (N[0] + bx - 1) / bx, gy = (N[1] + by - 1) / by, gz = (N[2] + bz - 1) / bz;
+  // number the non-empty blocks in (z, y, x) block order
+  std::vector<int> id((size_t)gx * gy * gz, -1);
+  for (int k = 0; k < nb; ++k) {
+    const int lin = vox[k];
+    const int i = lin % N[0], j = (lin / N[0]) % N[1], z = lin / (N[0] * N[1]);
+    id[((size_t)(z / bz) * gy + j / by) * gx + i / bx] = 0;
+  }
+  int nblk = 0;
+  fb.org.clear();
+  for (int zb = 0; zb < gz; ++zb)
+    for (int yb = 0; yb < gy; ++yb)
+      for (int xb = 0; xb < gx; ++xb) {
+        int& e = id[((size_t)zb * gy + yb) * gx + xb];
+        if (e < 0) continue;
+        e = nblk++;
+        fb.org.insert(fb.org.end(), {xb * bx, yb * by, zb * bz, 0});
+      }
+  fb.nblk = nblk;
+  const int padded = (nblk + FF_TB - 1) / FF_TB * FF_TB;
+  fb.org.resize((size_t)padded * 4, 0);
+  fb.vi.assign((size_t)padded * FF_BS, -1);
+  for (int k = 0; k < nb; ++k) {
+    const int lin = vox[k];
+    const int i = lin % N[0], j = (lin / N[0]) % N[1], z = lin / (N[0] * N[1]);
+    const int b = id[((size_t)(z / bz) * gy + j / by) * gx + i / bx];
+    const int u = i % bx + bx * (j % by + by * (z % bz));
+    fb.vi[(size_t)b * FF_BS + u] = k;
+  }
+  fb.ntiles = padded / FF_TB;
+}
+
+// ------------------------------------------------------------ kernels
 struct RoffArg {
-  int64_t r[FF_NR];
+  int64_t r[FF_RB];
 };
 
-__global__ __launch_bounds__(FF_D* FF_S) void k_farfield_sum(
-    const c64* __restrict__ w, RoffArg ro, int nr, const int* __restrict__ vox, int nb,
-    int chunk, const double* __restrict__ dirs, int nd, double k0, double h, double o0, double o1,
-    double o2, int N1, int N2, c64* __restrict__ part) {
-  __shared__ int sidx[FF_CH][3];
-  __shared__ c64 sw[FF_CH][FF_NR][3];
-  const int dl = threadIdx.x % FF_D, sl = threadIdx.x / FF_D;
-  const int d = blockIdx.x * FF_D + dl;
-  const int ks = blockIdx.y;
-  const int v0 = ks * chunk, v1 = min(nb, v0 + chunk);
-  double rx = 0, ry = 0, rz = 0;
-  if (d < nd) {
-    rx = dirs[d * 9 + 0];
-    ry = dirs[d * 9 + 1];
-    rz = dirs[d * 9 + 2];
-  }
-  const double ph0 = -k0 * (rx * o0 + ry * o1 + rz * o2);
-  const double ax = -k0 * h * rx, ay = -k0 * h * ry, az = -k0 * h * rz;
-  c64 acc[FF_NR][3];
-#pragma unroll
-  for (int q = 0; q < FF_NR; ++q)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[q][c] = mk(0.0, 0.0);
-  for (int base = v0; base < v1; base += FF_CH) {
-    __syncthreads();
-    for (int k = threadIdx.x; k < FF_CH; k += blockDim.x) {
-      const int vi = base + k;
-      if (vi < v1) {
-        const int lin = vox[vi];
-        sidx[k][0] = lin % N1;
-        sidx[k][1] = (lin / N1) % N2;
-        sidx[k][2] = lin / (N1 * N2);
-        for (int q = 0; q < FF_NR; ++q)
-          for (int c = 0; c < 3; ++c)
-            sw[k][q][c] = (q < nr) ? w[ro.r[q] + (int64_t)c * nb + vi] : mk(0.0, 0.0);
-      } else {
-        sidx[k][0] = sidx[k][1] = sidx[k][2] = 0;
-        for (int q = 0; q < FF_NR; ++q)
-          for (int c = 0; c < 3; ++c) sw[k][q][c] = mk(0.0, 0.0);
-      }
+// Wd[tile][qc][u][s] = w of right-hand side q, component c at offset u of
+// block tile*16 + s (zero where the block has no body voxel).
+__global__ void k_ff_pack(const c64* __restrict__ w, RoffArg ro, int nq, int nb,
+                          const int* __restrict__ blk_vi, int ntiles, c64* __restrict__ Wd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)ntiles * FF_TILE) return;
+  const int s = (int)(e % FF_TB);
+  const int u = (int)((e / FF_TB) % FF_BS);
+  const int qc = (int)((e / (FF_TB * FF_BS)) % FF_QC);
+  const int64_t tile = e / FF_TILE;
+  const int q = qc / 3, c = qc % 3;
+  const int vi = blk_vi[(tile * FF_TB + s) * FF_BS + u];
+  c64 v = mk(0.0, 0.0);
+  if (vi >= 0 && q < nq) v = w[ro.r[q] + (int64_t)c * nb + vi];
+  Wd[e] = v;
+}
+
+struct FfGeom {
+  double k0, h, o[3];
+  int bx, by;
+};
+
+__global__ __launch_bounds__(FF_DIRS * 4) void k_ff_mfma(
+    const c64* __restrict__ Wd, const int4* __restrict__ org, int ntiles, int tiles_per_split,
+    const double* __restrict__ dirs, int nd, FfGeom fg, int nq, c64* __restrict__ part) {
+  __shared__ c64 sW[FF_TILE];
+  __shared__ int4 sOrg[FF_TB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int dbase = blockIdx.x * FF_DIRS + wave * 16;
+  const int t0 = blockIdx.y * tiles_per_split;
+  const int t1 = min(ntiles, t0 + tiles_per_split);
+
+  // left operand A(r, u): direction dbase + lane%16, offsets u = 4 ks + lane/16
+  double aR[4], aI[4], aIn[4];
+  {
+    const int d = dbase + (lane & 15);
+    double rx = 0, ry = 0, rz = 0;
+    if (d < nd) {
+      rx = dirs[d * 9 + 0];
+      ry = dirs[d * 9 + 1];
+      rz = dirs[d * 9 + 2];
     }
-    __syncthreads();
-    for (int k = sl; k < FF_CH; k += FF_S) {
-      const double ang = ph0 + ax * sidx[k][0] + ay * sidx[k][1] + az * sidx[k][2];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int u = 4 * ks + (lane >> 4);
+      const int du = u % fg.bx, dv = (u / fg.bx) % fg.by, dw = u / (fg.bx * fg.by);
+      const double ang = -fg.k0 * fg.h * (rx * du + ry * dv + rz * dw);
       double sn, cs;
       sincos(ang, &sn, &cs);
-      const c64 e = mk(cs, sn);
-#pragma unroll
-      for (int q = 0; q < FF_NR; ++q)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) acc[q][c] = cfma(e, sw[k][q][c], acc[q][c]);
+      aR[ks] = cs;
+      aI[ks] = sn;
+      aIn[ks] = -sn;
     }
   }
-  // reduce the FF_S sub-lanes through LDS (reuse sw)
-  __syncthreads();
-  c64* red = &sw[0][0][0];  // FF_CH*FF_NR*3 = 768 >= FF_D*FF_S? use two rounds per q
-  for (int q = 0; q < FF_NR; ++q) {
-    for (int c = 0; c < 3; ++c) {
-      red[threadIdx.x] = acc[q][c];
-      __syncthreads();
-      if (sl == 0 && d < nd && q < nr) {
-        c64 s = red[dl];
-        for (int u = 1; u < FF_S; ++u) s = s + red[u * FF_D + dl];
-        part[(((int64_t)ks * nr + q) * nd + d) * 3 + c] = s;
+  // output rows of this lane (FP64 16x16x4 result layout: row lane/16 + 4 r,
+  // column lane % 16): directions dbase + lane/16 + 4 r
+  double p0[4], cx[4], cy[4], cz[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int d = dbase + (lane >> 4) + 4 * r;
+    double rx = 0, ry = 0, rz = 0;
+    if (d < nd) {
+      rx = dirs[d * 9 + 0];
+      ry = dirs[d * 9 + 1];
+      rz = dirs[d * 9 + 2];
+    }
+    p0[r] = -fg.k0 * (rx * fg.o[0] + ry * fg.o[1] + rz * fg.o[2]);
+    cx[r] = -fg.k0 * fg.h * rx;
+    cy[r] = -fg.k0 * fg.h * ry;
+    cz[r] = -fg.k0 * fg.h * rz;
+  }
+  c64 acc[4][FF_QC];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int qc = 0; qc < FF_QC; ++qc) acc[r][qc] = mk(0.0, 0.0);
+
+  // register prefetch of the next tile (FF_TILE / 256 c64 per thread)
+  constexpr int PER = FF_TILE / (FF_DIRS * 4);
+  c64 pre[PER];
+  int4 preo = make_int4(0, 0, 0, 0);
+  auto fetch = [&](int t) {
+    const c64* src = Wd + (int64_t)t * FF_TILE;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) pre[k] = src[k * FF_DIRS * 4 + threadIdx.x];
+    if (threadIdx.x < FF_TB) preo = org[(int64_t)t * FF_TB + threadIdx.x];
+  };
+  if (t0 < t1) fetch(t0);
+  for (int t = t0; t < t1; ++t) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) sW[k * FF_DIRS * 4 + threadIdx.x] = pre[k];
+    if (threadIdx.x < FF_TB) sOrg[threadIdx.x] = preo;
+    __syncthreads();
+    if (t + 1 < t1) fetch(t + 1);
+
+    // block scale S(r, b) for this lane's column block b = lane % 16
+    const int4 ob = sOrg[lane & 15];
+    c64 S[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double ang = p0[r] + cx[r] * ob.x + cy[r] * ob.y + cz[r] * ob.z;
+      double sn, cs;
+      sincos(ang, &sn, &cs);
+      S[r] = mk(cs, sn);
+    }
+    d4 gR[FF_QC], gI[FF_QC];
+#pragma unroll
+    for (int qc = 0; qc < FF_QC; ++qc) {
+      gR[qc] = d4{0.0, 0.0, 0.0, 0.0};
+      gI[qc] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      c64 b[FF_QC];
+#pragma unroll
+      for (int qc = 0; qc < FF_QC; ++qc)
+        b[qc] = sW[(qc * FF_BS + 4 * ks + (lane >> 4)) * FF_TB + (lane & 15)];
+#pragma unroll
+      for (int qc = 0; qc < FF_QC; ++qc) {
+        gR[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aR[ks], b[qc].re, gR[qc], 0, 0, 0);
+        gI[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aR[ks], b[qc].im, gI[qc], 0, 0, 0);
       }
-      __syncthreads();
+#pragma unroll
+      for (int qc = 0; qc < FF_QC; ++qc) {
+        gR[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aIn[ks], b[qc].im, gR[qc], 0, 0, 0);
+        gI[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aI[ks], b[qc].re, gI[qc], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int qc = 0; qc < FF_QC; ++qc)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r][qc] = cfma(S[r], mk(gR[qc][r], gI[qc][r]), acc[r][qc]);
+  }
+  // sum over the 16 column blocks (lanes sharing lane / 16), fixed pattern
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int qc = 0; qc < FF_QC; ++qc) {
+      double re = acc[r][qc].re, im = acc[r][qc].im;
+#pragma unroll
+      for (int m = 8; m >= 1; m >>= 1) {
+        re += __shfl_xor(re, m, 64);
+        im += __shfl_xor(im, m, 64);
+      }
+      acc[r][qc] = mk(re, im);
+    }
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int d = dbase + (lane >> 4) + 4 * r;
+      if (d >= nd) continue;
+#pragma unroll
+      for (int qc = 0; qc < FF_QC; ++qc) {
+        const int q = qc / 3, c = qc % 3;
+        if (q < nq) part[(((int64_t)blockIdx.y * nq + q) * nd + d) * 3 + c] = acc[r][qc];
+      }
     }
   }
 }
@@ -107,22 +280,46 @@ __global__ void k_farfield_project(const c64* __restrict__ part, int ksplit, int
   F[(int64_t)e * 2 + 1] = scale * fp;
 }
 
-hipError_t launch_farfield_ks(const GroupGeom& g, const c64* w, const int64_t* roff_host,
-                              int nr, const int* vox, int nb, const double* dirs, int nd,
-                              double k0, double h, const double* origin, c64* part, int chunk,
-                              c64* F, hipStream_t s) {
-  const int ks = (nb + chunk - 1) / chunk;
-  for (int q0 = 0; q0 < nr; q0 += FF_NR) {
-    const int nq = nr - q0 < FF_NR ? nr - q0 : FF_NR;
+int far_split(int ntiles, int nd) {
+  const int dblocks = (nd + FF_DIRS - 1) / FF_DIRS;
+  const int want = std::max(1, 1024 / dblocks);
+  const int ks = std::min(ntiles, want);
+  const int tps = (ntiles + ks - 1) / ks;
+  return (ntiles + tps - 1) / tps;
+}
+
+size_t far_pack_elems(int ntiles) { return (size_t)ntiles * FF_TILE; }
+
+hipError_t launch_farfield_mfma(const c64* w, const int64_t* roff_host, int nr, int nb,
+                                const FarBlocks& fb, const int* blk_vi, const int* blk_org,
+                                const double* dirs, int nd, double k0, double h,
+                                const double* origin, c64* Wd, c64* part, c64* F,
+                                hipStream_t s) {
+  const int ntiles = fb.ntiles;
+  const int ks = far_split(ntiles, nd);
+  const int tps = (ntiles + ks - 1) / ks;
+  FfGeom fg;
+  fg.k0 = k0;
+  fg.h = h;
+  fg.o[0] = origin[0];
+  fg.o[1] = origin[1];
+  fg.o[2] = origin[2];
+  fg.bx = fb.shape[0];
+  fg.by = fb.shape[1];
+  const double scale = k0 * k0 * h * h * h / (4.0 * M_PI);
+  for (int q0 = 0; q0 < nr; q0 += FF_RB) {
+    const int nq = std::min(FF_RB, nr - q0);
     RoffArg ro;
-    for (int q = 0; q < FF_NR; ++q) ro.r[q] = q < nq ? roff_host[q0 + q] : 0;
-    dim3 grid((nd + FF_D - 1) / FF_D, ks);
-    k_farfield_sum<<<grid, FF_D * FF_S, 0, s>>>(w, ro, nq, vox, nb, chunk, dirs, nd, k0, h,
-                                                origin[0], origin[1], origin[2], g.N[0], g.N[1],
-                                                part);
+    for (int q = 0; q < FF_RB; ++q) ro.r[q] = q < nq ? roff_host[q0 + q] : 0;
+    const int64_t tot = (int64_t)ntiles * FF_TILE;
+    k_ff_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(w, ro, nq, nb, blk_vi, ntiles, Wd);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const double scale = k0 * k0 * h * h * h / (4.0 * M_PI);
+    dim3 grid((nd + FF_DIRS - 1) / FF_DIRS, ks);
+    k_ff_mfma<<<grid, FF_DIRS * 4, 0, s>>>(Wd, (const int4*)blk_org, ntiles, tps, dirs, nd, fg,
+                                           nq, part);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     k_farfield_project<<<(nq * nd + 255) / 256, 256, 0, s>>>(part, ks, nq, nd, dirs, scale,
                                                               F + (int64_t)q0 * nd * 2);
     e = hipGetLastError();

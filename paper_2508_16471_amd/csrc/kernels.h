@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "common.h"
 
 namespace vie {
@@ -129,14 +131,28 @@ hipError_t launch_finalize(int which, int nrhs, int nblk, const c64* partials, K
                            int* active, const FinParams& fp, hipStream_t s);
 hipError_t launch_axpy_real(int64_t n, double a, const c64* x, c64* y, hipStream_t s);
 
-// Far field (eq. 25): F[rhs][dir][2] = (F_theta, F_phi) for right-hand sides
-// [r0, r0+nr) of one body; w body-compressed with per-rhs offsets roff (host
-// values for the nr right-hand sides), body voxels vox[nb] (linear indices);
-// dirs[nd][9] = (r, theta-hat, phi-hat); part: ceil(nb/chunk)*min(nr,4)*nd*3 c64.
-hipError_t launch_farfield_ks(const GroupGeom& g, const c64* w, const int64_t* roff_host,
-                              int nr, const int* vox, int nb, const double* dirs, int nd,
-                              double k0, double h, const double* origin, c64* part, int chunk,
-                              c64* F, hipStream_t s);
+// Far field (eq. 25) on FP64 MFMA.  The body voxels are grouped into aligned
+// blocks of 16 voxels (shape bx x by x bz, picked per body to minimise empty
+// slots); blocks are padded to whole tiles of 16.
+struct FarBlocks {
+  int shape[3] = {16, 1, 1};
+  int nblk = 0, ntiles = 0;
+  std::vector<int> org;  // [ntiles*16][4] block origin (i, j, k, 0) in voxels
+  std::vector<int> vi;   // [ntiles*16][16] compressed voxel index at offset u, -1 empty
+};
+void far_blocks_build(const int* vox, int nb, const int N[3], FarBlocks& fb);
+// K-split count and packed-operand size (c64) for a launch.
+int far_split(int ntiles, int nd);
+size_t far_pack_elems(int ntiles);
+// F[rhs][dir][2] = (F_theta, F_phi) for nr right-hand sides of one body; w
+// body-compressed with per-rhs offsets roff (host values), blk_vi / blk_org the
+// device copies of fb.vi / fb.org; dirs[nd][9] = (r, theta-hat, phi-hat).
+// Scratch: Wd far_pack_elems(ntiles) c64, part far_split(..)*min(nr,2)*nd*3 c64.
+hipError_t launch_farfield_mfma(const c64* w, const int64_t* roff_host, int nr, int nb,
+                                const FarBlocks& fb, const int* blk_vi, const int* blk_org,
+                                const double* dirs, int nd, double k0, double h,
+                                const double* origin, c64* Wd, c64* part, c64* F,
+                                hipStream_t s);
 // ||v_rhs||^2 of body-compressed vectors into out[nrhs] (device).
 hipError_t launch_vec_norm2(int nrhs, const BodyIdx& bi, const c64* v, double* out,
                             hipStream_t s);
