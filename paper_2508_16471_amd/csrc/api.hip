@@ -761,6 +761,18 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
       }
       if (k > (int64_t)ctx->opt.max_iter + 2) break;
     }
+    if (getenv("VIE_LOG")) {
+      std::vector<KState> hs(nrhs);
+      VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
+                             ctx->stream));
+      VIE_HIP(hipStreamSynchronize(ctx->stream));
+      for (int i = 0; i < nrhs; ++i)
+        fprintf(stderr,
+                "vie: cycle %d rhs %d: %d iterations, recursive rel res %.3e, breakdown %d, "
+                "|omega| %.3e\n",
+                cycle, i, hs[i].it_cycle, hs[i].bnorm2 > 0 ? sqrt(hs[i].rnorm2 / hs[i].bnorm2) : 0.0,
+                hs[i].breakdown, std::hypot(hs[i].omega.re, hs[i].omega.im));
+    }
     // true residual with the FP64 product, restart
     EpiArgs e{EPI_RESID, rh, part, 0, pol, ph};
     VIE_HIP(run_matvec(ctx, G, 0, x, r, e, notdone));
@@ -770,6 +782,15 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
     VIE_HIP(hipMemcpyAsync(ctx->hflags[0], active, nrhs * sizeof(int), hipMemcpyDeviceToHost,
                            ctx->stream));
     VIE_HIP(hipStreamSynchronize(ctx->stream));
+    if (getenv("VIE_LOG")) {
+      std::vector<KState> hs(nrhs);
+      VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
+                             ctx->stream));
+      VIE_HIP(hipStreamSynchronize(ctx->stream));
+      for (int i = 0; i < nrhs; ++i)
+        fprintf(stderr, "vie: restart %d rhs %d: true rel res %.3e after %d iterations\n", cycle,
+                i, hs[i].bnorm2 > 0 ? sqrt(hs[i].rnorm2 / hs[i].bnorm2) : 0.0, hs[i].iters);
+    }
     bool any = false;
     for (int i = 0; i < nrhs; ++i) any |= ctx->hflags[0][i] != 0;
     if (!any) break;

@@ -25,7 +25,7 @@ namespace vie {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-static constexpr int FF_RB = 2;          // right-hand sides per pass
+static constexpr int FF_RB = 1;          // right-hand sides per pass
 static constexpr int FF_QC = 3 * FF_RB;  // complex columns per block (rhs x component)
 static constexpr int FF_BS = 16;         // voxels per block (MFMA K = 4 per step, 4 steps)
 static constexpr int FF_TB = 16;         // blocks per tile (MFMA N)
@@ -122,12 +122,154 @@ struct FfGeom {
   int bx, by;
 };
 
-__global__ __launch_bounds__(FF_DIRS * 4) void k_ff_mfma(
+// sin and cos of x for |x| < 1e9: Cody-Waite reduction by pi/2 with a two-part
+// constant (FMA), then Taylor polynomials on |r| <= pi/4 through r^17 (sin)
+// and r^16 (cos); absolute error about 2e-16.  Branch-free, so it schedules
+// between the matrix instructions.
+__device__ __forceinline__ void ff_sincos(double x, double& sn, double& cs) {
+  const double n = rint(x * 0.63661977236758134308);
+  double r = fma(-n, 1.5707963267948966192, x);
+  r = fma(-n, 6.123233995736766036e-17, r);
+  const int q = (int)n;
+  const double r2 = r * r;
+  double ps = 2.8114572543455207632e-15;    // 1/17!
+  ps = fma(ps, r2, -7.6471637318198164759e-13);  // -1/15!
+  ps = fma(ps, r2, 1.6059043836821614599e-10);   // 1/13!
+  ps = fma(ps, r2, -2.5052108385441718775e-08);  // -1/11!
+  ps = fma(ps, r2, 2.7557319223985890653e-06);   // 1/9!
+  ps = fma(ps, r2, -1.9841269841269841270e-04);  // -1/7!
+  ps = fma(ps, r2, 8.3333333333333333333e-03);   // 1/5!
+  ps = fma(ps, r2, -1.6666666666666666667e-01);  // -1/3!
+  const double s0 = fma(r * r2, ps, r);
+  double pc = 4.7794773323873852974e-14;    // 1/16!
+  pc = fma(pc, r2, -1.1470745597729724714e-11);  // -1/14!
+  pc = fma(pc, r2, 2.0876756987868098979e-09);   // 1/12!
+  pc = fma(pc, r2, -2.7557319223985890653e-07);  // -1/10!
+  pc = fma(pc, r2, 2.4801587301587301587e-05);   // 1/8!
+  pc = fma(pc, r2, -1.3888888888888888889e-03);  // -1/6!
+  pc = fma(pc, r2, 4.1666666666666666667e-02);   // 1/4!
+  pc = fma(pc, r2, -0.5);
+  const double c0 = fma(r2, pc, 1.0);
+  const bool swap = q & 1;
+  const double s1 = swap ? c0 : s0, c1 = swap ? s0 : c0;
+  sn = (q & 2) ? -s1 : s1;
+  cs = ((q + 1) & 2) ? -c1 : c1;
+}
+
+// exp(i x) from a 256-entry table of exp(2 pi i k / 256) in LDS: x = k pi/128
+// + e with |e| <= pi/256 (two-part FMA reduction), then Taylor polynomials of
+// cos e through e^6 and sin e through e^7 (truncation below 1e-19) and one
+// complex product with the table entry.
+constexpr int FF_NT = 256;
+__device__ __forceinline__ c64 ff_expi(double x, const c64* sT) {
+  const double kf = rint(x * 40.743665431525205957);  // 128 / pi
+  double e = fma(-kf, 2.4543692606170259375e-02, x);  // fl(pi) / 128
+  e = fma(-kf, 9.5675531183386971e-19, e);            // (pi - fl(pi)) / 128
+  const c64 t = sT[(int)kf & (FF_NT - 1)];
+  const double e2 = e * e;
+  double pc = fma(e2, -1.3888888888888888889e-03, 4.1666666666666666667e-02);
+  pc = fma(e2, pc, -0.5);
+  const double c = fma(e2, pc, 1.0);
+  double ps = fma(e2, -1.9841269841269841270e-04, 8.3333333333333333333e-03);
+  ps = fma(e2, ps, -1.6666666666666666667e-01);
+  const double sn = fma(e * e2, ps, e);
+  return mk(t.re * c - t.im * sn, fma(t.re, sn, t.im * c));
+}
+
+// packed tile t -> registers (FF_TILE / 256 c64 and one block origin per thread)
+constexpr int FF_PER = FF_TILE / (FF_DIRS * 4);
+struct FfPre {
+  c64 v[FF_PER];
+  int4 o;
+};
+
+__device__ __forceinline__ FfPre ff_fetch(const c64* __restrict__ Wd,
+                                          const int4* __restrict__ org, int t) {
+  FfPre p;
+  const c64* src = Wd + (int64_t)t * FF_TILE;
+#pragma unroll
+  for (int k = 0; k < FF_PER; ++k) p.v[k] = src[k * FF_DIRS * 4 + threadIdx.x];
+  p.o = threadIdx.x < FF_TB ? org[(int64_t)t * FF_TB + threadIdx.x] : make_int4(0, 0, 0, 0);
+  return p;
+}
+
+__device__ __forceinline__ void ff_store(c64* sW, int4* sOrg, const FfPre& p) {
+#pragma unroll
+  for (int k = 0; k < FF_PER; ++k) sW[k * FF_DIRS * 4 + threadIdx.x] = p.v[k];
+  if (threadIdx.x < FF_TB) sOrg[threadIdx.x] = p.o;
+}
+
+struct FfRows {
+  double p0[4], cx[4], cy[4], cz[4];
+};
+
+// G(r, b, qc) = sum_u A(r, u) W(b, u, qc) for one staged tile (complex as
+// four real products), and the block scale S(r, b) of this lane's column.
+__device__ __forceinline__ void ff_tile(const c64* sW, const int4* sOrg, const c64* sT,
+                                        const double (&aR)[4],
+                                        const double (&aI)[4], const double (&aIn)[4],
+                                        const FfRows& rw, int lane, d4 (&gR)[FF_QC],
+                                        d4 (&gI)[FF_QC], c64 (&S)[4]) {
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    c64 b[FF_QC];
+#pragma unroll
+    for (int qc = 0; qc < FF_QC; ++qc)
+      b[qc] = sW[(qc * FF_BS + 4 * ks + (lane >> 4)) * FF_TB + (lane & 15)];
+    if (ks == 0) {
+#pragma unroll
+      for (int qc = 0; qc < FF_QC; ++qc) {
+        gR[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aR[ks], b[qc].re, d4{0.0, 0.0, 0.0, 0.0},
+                                                      0, 0, 0);
+        gI[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aR[ks], b[qc].im, d4{0.0, 0.0, 0.0, 0.0},
+                                                      0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int qc = 0; qc < FF_QC; ++qc) {
+        gR[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aR[ks], b[qc].re, gR[qc], 0, 0, 0);
+        gI[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aR[ks], b[qc].im, gI[qc], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int qc = 0; qc < FF_QC; ++qc) {
+      gR[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aIn[ks], b[qc].im, gR[qc], 0, 0, 0);
+      gI[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aI[ks], b[qc].re, gI[qc], 0, 0, 0);
+    }
+  }
+  const int4 ob = sOrg[lane & 15];
+  const double ox = ob.x, oy = ob.y, oz = ob.z;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double ang = fma(rw.cz[r], oz, fma(rw.cy[r], oy, fma(rw.cx[r], ox, rw.p0[r])));
+    S[r] = ff_expi(ang, sT);
+  }
+}
+
+__device__ __forceinline__ void ff_accum(const d4 (&gR)[FF_QC], const d4 (&gI)[FF_QC],
+                                         const c64 (&S)[4], c64 (&acc)[4][FF_QC]) {
+#pragma unroll
+  for (int qc = 0; qc < FF_QC; ++qc)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r][qc] = cfma(S[r], mk(gR[qc][r], gI[qc][r]), acc[r][qc]);
+}
+
+// One workgroup: 64 directions (16 per wave) against the blocks of tiles
+// [t0, t1).  Tiles are double-buffered in LDS (one barrier per tile) with a
+// register prefetch; two waves per SIMD so that one wave's scale-and-
+// accumulate and phase work runs while the other's matrix products execute.
+__global__ __launch_bounds__(FF_DIRS * 4) __attribute__((amdgpu_waves_per_eu(2))) void k_ff_mfma(
     const c64* __restrict__ Wd, const int4* __restrict__ org, int ntiles, int tiles_per_split,
     const double* __restrict__ dirs, int nd, FfGeom fg, int nq, c64* __restrict__ part) {
-  __shared__ c64 sW[FF_TILE];
-  __shared__ int4 sOrg[FF_TB];
+  __shared__ c64 sW[2][FF_TILE];
+  __shared__ int4 sOrg[2][FF_TB];
+  __shared__ c64 sT[FF_NT];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = threadIdx.x; k < FF_NT; k += FF_DIRS * 4) {
+    double sn, cs;
+    ff_sincos(k * (2.0 * M_PI / FF_NT), sn, cs);
+    sT[k] = mk(cs, sn);
+  }  // visible after the first barrier of the tile loop
   const int dbase = blockIdx.x * FF_DIRS + wave * 16;
   const int t0 = blockIdx.y * tiles_per_split;
   const int t1 = min(ntiles, t0 + tiles_per_split);
@@ -148,7 +290,7 @@ __global__ __launch_bounds__(FF_DIRS * 4) void k_ff_mfma(
       const int du = u % fg.bx, dv = (u / fg.bx) % fg.by, dw = u / (fg.bx * fg.by);
       const double ang = -fg.k0 * fg.h * (rx * du + ry * dv + rz * dw);
       double sn, cs;
-      sincos(ang, &sn, &cs);
+      ff_sincos(ang, sn, cs);
       aR[ks] = cs;
       aI[ks] = sn;
       aIn[ks] = -sn;
@@ -156,7 +298,7 @@ __global__ __launch_bounds__(FF_DIRS * 4) void k_ff_mfma(
   }
   // output rows of this lane (FP64 16x16x4 result layout: row lane/16 + 4 r,
   // column lane % 16): directions dbase + lane/16 + 4 r
-  double p0[4], cx[4], cy[4], cz[4];
+  FfRows rw;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int d = dbase + (lane >> 4) + 4 * r;
@@ -166,10 +308,10 @@ __global__ __launch_bounds__(FF_DIRS * 4) void k_ff_mfma(
       ry = dirs[d * 9 + 1];
       rz = dirs[d * 9 + 2];
     }
-    p0[r] = -fg.k0 * (rx * fg.o[0] + ry * fg.o[1] + rz * fg.o[2]);
-    cx[r] = -fg.k0 * fg.h * rx;
-    cy[r] = -fg.k0 * fg.h * ry;
-    cz[r] = -fg.k0 * fg.h * rz;
+    rw.p0[r] = -fg.k0 * (rx * fg.o[0] + ry * fg.o[1] + rz * fg.o[2]);
+    rw.cx[r] = -fg.k0 * fg.h * rx;
+    rw.cy[r] = -fg.k0 * fg.h * ry;
+    rw.cz[r] = -fg.k0 * fg.h * rz;
   }
   c64 acc[4][FF_QC];
 #pragma unroll
@@ -177,62 +319,17 @@ __global__ __launch_bounds__(FF_DIRS * 4) void k_ff_mfma(
 #pragma unroll
     for (int qc = 0; qc < FF_QC; ++qc) acc[r][qc] = mk(0.0, 0.0);
 
-  // register prefetch of the next tile (FF_TILE / 256 c64 per thread)
-  constexpr int PER = FF_TILE / (FF_DIRS * 4);
-  c64 pre[PER];
-  int4 preo = make_int4(0, 0, 0, 0);
-  auto fetch = [&](int t) {
-    const c64* src = Wd + (int64_t)t * FF_TILE;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) pre[k] = src[k * FF_DIRS * 4 + threadIdx.x];
-    if (threadIdx.x < FF_TB) preo = org[(int64_t)t * FF_TB + threadIdx.x];
-  };
-  if (t0 < t1) fetch(t0);
+  d4 gR[FF_QC], gI[FF_QC];
+  c64 S[4];
+  FfPre pre;
+  if (t0 < t1) pre = ff_fetch(Wd, org, t0);
   for (int t = t0; t < t1; ++t) {
+    const int cb = (t - t0) & 1;
+    ff_store(sW[cb], sOrg[cb], pre);
+    if (t + 1 < t1) pre = ff_fetch(Wd, org, t + 1);
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PER; ++k) sW[k * FF_DIRS * 4 + threadIdx.x] = pre[k];
-    if (threadIdx.x < FF_TB) sOrg[threadIdx.x] = preo;
-    __syncthreads();
-    if (t + 1 < t1) fetch(t + 1);
-
-    // block scale S(r, b) for this lane's column block b = lane % 16
-    const int4 ob = sOrg[lane & 15];
-    c64 S[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const double ang = p0[r] + cx[r] * ob.x + cy[r] * ob.y + cz[r] * ob.z;
-      double sn, cs;
-      sincos(ang, &sn, &cs);
-      S[r] = mk(cs, sn);
-    }
-    d4 gR[FF_QC], gI[FF_QC];
-#pragma unroll
-    for (int qc = 0; qc < FF_QC; ++qc) {
-      gR[qc] = d4{0.0, 0.0, 0.0, 0.0};
-      gI[qc] = d4{0.0, 0.0, 0.0, 0.0};
-    }
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      c64 b[FF_QC];
-#pragma unroll
-      for (int qc = 0; qc < FF_QC; ++qc)
-        b[qc] = sW[(qc * FF_BS + 4 * ks + (lane >> 4)) * FF_TB + (lane & 15)];
-#pragma unroll
-      for (int qc = 0; qc < FF_QC; ++qc) {
-        gR[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aR[ks], b[qc].re, gR[qc], 0, 0, 0);
-        gI[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aR[ks], b[qc].im, gI[qc], 0, 0, 0);
-      }
-#pragma unroll
-      for (int qc = 0; qc < FF_QC; ++qc) {
-        gR[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aIn[ks], b[qc].im, gR[qc], 0, 0, 0);
-        gI[qc] = __builtin_amdgcn_mfma_f64_16x16x4f64(aI[ks], b[qc].re, gI[qc], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int qc = 0; qc < FF_QC; ++qc)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r][qc] = cfma(S[r], mk(gR[qc][r], gI[qc][r]), acc[r][qc]);
+    ff_tile(sW[cb], sOrg[cb], sT, aR, aI, aIn, rw, lane, gR, gI, S);
+    ff_accum(gR, gI, S, acc);
   }
   // sum over the 16 column blocks (lanes sharing lane / 16), fixed pattern
 #pragma unroll

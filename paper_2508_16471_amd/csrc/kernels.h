@@ -19,7 +19,7 @@ struct KState {
   int active;      // 1 while this right-hand side iterates
   int it_cycle;    // iterations in the current cycle
   int iters;       // total iterations
-  int breakdown;   // 1 if the last cycle ended on a BiCGSTAB breakdown
+  int breakdown;   // why the last cycle broke down: 0 no, 1 rhat.Ap, 2 rhat.r, 3 omega, 4 overflow
   int notdone;     // 1 while the true residual is above tol
   double rh2;      // ||rhat||^2 (shadow residual of the current cycle)
   int cycles;      // FP64 true-residual products (restarts) so far

@@ -213,8 +213,13 @@ __global__ __launch_bounds__(VT) void k_finalize(int which, int nrhs, int nblk,
   switch (which) {
     case FIN_ALPHA: {
       const c64 rhv = a;
-      if (cabs2(rhv) <= 1e-28 * S.rh2 * S.rnorm2 || !(cabs2(rhv) < 1e300)) {
-        S.breakdown = 1;
+      // Only an exact zero (or overflow) is a breakdown: rhat . A p and
+      // rhat . r carry the product of the omegas, so their ratio to
+      // |rhat| |r| decays geometrically in a healthy iteration and any fixed
+      // relative threshold would restart it (losing the Krylov space) for
+      // no reason on slowly converging problems.
+      if (cabs2(rhv) == 0.0 || !(cabs2(rhv) < 1e300)) {
+        S.breakdown = 1;  // rhat . A p vanished
         S.active = 0;
         flags[rhs] = 0;
       } else {
@@ -236,14 +241,14 @@ __global__ __launch_bounds__(VT) void k_finalize(int which, int nrhs, int nblk,
       int stop = 0;
       if (!(S.rnorm2 <= 1e300)) {  // NaN / overflow: end the cycle, restart from x
         stop = 1;
-        S.breakdown = 1;
+        S.breakdown = 4;
       } else if (S.rnorm2 <= S.target2) {
         stop = 1;
       } else if (S.iters >= fp.max_iter) {
         stop = 1;
-      } else if (cabs2(S.rho) <= 1e-28 * S.rh2 * S.rnorm2 || cabs2(S.omega) == 0.0) {
+      } else if (cabs2(S.rho) == 0.0 || cabs2(S.omega) == 0.0) {
         stop = 1;
-        S.breakdown = 1;
+        S.breakdown = cabs2(S.omega) == 0.0 ? 3 : 2;  // omega = 0 / rhat . r vanished
       } else {
         S.beta = cdiv(S.rho, S.rho_prev) * cdiv(S.alpha, S.omega);
       }

@@ -251,3 +251,43 @@ def test_matvec_sampled_rows_large(V, n, rows):
     print(n, _relerr(y64, ref), _relerr(y32, ref))
     assert _relerr(y64, ref) < 1e-12
     assert _relerr(y32, ref) < 5e-6
+
+
+@pytest.mark.parametrize("zvar", [0, 1, 2])
+@pytest.mark.parametrize("n", [(64, 64, 64), (24, 20, 17)])
+def test_every_z_pass_shape_matches_oracle(V, zvar, n):
+    """Each fused z-pass shape the autotuner may pick (forced through
+    VIE_ZVAR), FP64 and FP32, two vectors per call, against the oracle's
+    direct sum on sampled rows."""
+    import os
+
+    rng = np.random.default_rng(7 * zvar + n[0])
+    h = 1.0 / 32
+    g = Grid.centred(n, h)
+    eps = sphere(g, 0.45 * n[0] * h, 4.0)
+    chi = (eps - 1).ravel()
+    body = np.nonzero(chi)[0]
+    xs = np.stack([_rand_vec(rng, n) * (chi.reshape(eps.shape) != 0)[None] for _ in range(2)])
+    pos = vd.voxel_centres(g.n, g.h, g.origin)
+    sel = np.concatenate([rng.choice(body, 28, replace=False), [0, len(chi) - 1, body[0], body[-1]]])
+    refs = [vd.matvec_rows(chi, pos, h, K0, x.reshape(3, -1), sel) for x in xs]
+    old = os.environ.get("VIE_ZVAR")
+    os.environ["VIE_ZVAR"] = str(zvar)
+    try:
+        ctx = V.vie_setup([(eps, h, g.origin)], V.make_options(K0))
+        try:
+            y64 = V.vie_matvec(ctx, 0, xs, V.VIE_FP64)
+            y32 = V.vie_matvec(ctx, 0, xs, V.VIE_MIXED)
+        finally:
+            V.vie_destroy(ctx)
+    finally:
+        if old is None:
+            del os.environ["VIE_ZVAR"]
+        else:
+            os.environ["VIE_ZVAR"] = old
+    for q in range(2):
+        e64 = _relerr(y64[q].reshape(3, -1)[:, sel], refs[q])
+        e32 = _relerr(y32[q].reshape(3, -1)[:, sel], refs[q])
+        print("zvar", zvar, n, q, e64, e32)
+        assert e64 < 1e-12
+        assert e32 < 5e-6
