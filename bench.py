@@ -51,8 +51,15 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--mode", choices=["solve", "matvec"], default="solve",
-                    help="matvec: time device-resident operator products only (profiling)")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with 512 MiB fill / sum kernels (HBM counter calibration)")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2508_16471_amd", "weights",
+                                                      "warmstart_metasurface128.npy"))
+    ap.add_argument("--mode", choices=["solve", "matvec", "farfield"], default="solve",
+                    help="matvec: time device-resident operator products only; farfield: "
+                         "the 64,800-direction sweep of one body only (profiling)")
     ap.add_argument("--nrhs", type=int, default=1, help="matvec mode: vectors per product")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32")
     return ap.parse_args()
@@ -242,13 +249,7 @@ def matvec_mode(args):
     dt = time.perf_counter() - t0
     times = V.vie_kernel_times(ctx, reset=True)
     V.vie_destroy(ctx)
-    # plain device copy of known size: calibrates FETCH_SIZE / WRITE_SIZE counters
-    cbytes = 512 << 20
-    ca = torch.empty(cbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
-    cb = torch.empty_like(ca)
-    for _ in range(3):
-        cb.copy_(ca)
-    torch.cuda.synchronize()
+    calib_copy(torch)  # FETCH_SIZE / WRITE_SIZE calibration kernels
     rows = {}
     for kind, (ms, cnt) in times.items():
         if not kind.startswith("fft_") or cnt == 0:
@@ -259,18 +260,137 @@ def matvec_mode(args):
         rows[kind] = {"avg_launch_ms": ms / cnt, "GBps": by / (ms * 1e-3) / 1e9, "launches": cnt}
     total = sum(v["avg_launch_ms"] for v in rows.values())
     print(json.dumps({"mode": "matvec", "precision": args.precision, "nrhs": args.nrhs,
-                      "copy_calibration": {"bytes_read": cbytes, "bytes_written": cbytes, "launches": 3},
+                      "calibration": {"fill_bytes_written": 512 << 20, "sum_bytes_read": 512 << 20},
                       "grid": list(N), "fft": list(P), "ms_per_product": dt / args.steps * 1e3,
                       "kernel_ms_per_product": total, "kernels": rows}))
+
+
+# ------------------------------------------------------- HBM counters
+def calib_copy(torch):
+    """Kernels of known HBM traffic for the FETCH_SIZE / WRITE_SIZE counters:
+    a device fill writes 512 MiB, a device sum reads 512 MiB (three each)."""
+    cbytes = 512 << 20
+    ca = torch.empty(cbytes // 4, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        ca.fill_(1.0)
+    for _ in range(3):
+        float(ca.sum())
+    torch.cuda.synchronize()
+
+
+def measured_traffic(kind, avg_launch_ms):
+    """HBM bytes per launch of `kind` from the committed counter summary
+    (profiles/traffic_<kind>.json, written by profsum traffic), or None when
+    it is missing or the product sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kind}.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2508_16471_amd.profsum import sources_sha
+
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("sources_sha256") != sources_sha():
+        return None
+    return {"bytes_per_launch": rec["bytes_per_dispatch"],
+            "GBps": rec["bytes_per_dispatch"] / (avg_launch_ms * 1e-3) / 1e9,
+            "fetch_scale": rec["fetch_scale"], "write_scale": rec["write_scale"],
+            "source": os.path.relpath(path, ROOT)}
+
+
+# ------------------------------------------------------- extra legs
+def other_rows(times):
+    """Time of the non-FFT kernel kinds over the timed region."""
+    return {k: {"ms_total": ms, "launches": int(cnt)} for k, (ms, cnt) in times.items()
+            if not k.startswith("fft_") and cnt > 0}
+
+
+def learned_leg(V, torch, ctx, args, chans, nb, nch, theta, phi, dtau, fast_value):
+    """The fast path with the trained warm-start network attached (same
+    bodies, same step); the plain start stays the fallback."""
+    net = V.vie_cnn_create(0)
+    try:
+        V.vie_cnn_params(net, np.load(args.weights))
+        V.vie_attach_cnn(ctx, net)
+        V.vie_set_options(ctx, V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol,
+                                              max_iter=20000, inner_tol=args.inner_tol,
+                                              warm_start=1, flags=V.VIE_FLAG_TIMING))
+        V.vie_solve(ctx, chans, [nch] * nb)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = []
+        for _ in range(args.steps):
+            _, s = V.vie_solve(ctx, chans, [nch] * nb)
+            post_process(V, ctx, nb, nch, theta, phi, dtau)
+            st += s
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        val = args.steps * nb * nch / dt
+        return {"solves_per_s": val, "vs_fast": val / fast_value,
+                "iters_mean": float(np.mean([x["iters"] for x in st])),
+                "fallback_rate": float(np.mean([x["fallback"] for x in st])),
+                "rel_res_x0_mean": float(np.mean([x["rel_res_x0"] for x in st])),
+                "converged": all(x["converged"] for x in st),
+                "max_rel_res": max(x["rel_res"] for x in st),
+                "weights": os.path.relpath(args.weights, ROOT)}
+    finally:
+        V.vie_attach_cnn(ctx, None)
+        V.vie_cnn_destroy(net)
+
+
+def farfield_sweep(V, torch, ctx, args, chans, nch, nbv, reps=3):
+    """360 x 180 far-field sweep (64,800 directions) of body 0's channels on
+    the FP64-MFMA contraction; achieved rate from the kernel-kind time."""
+    V.vie_set_options(ctx, V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
+                                          inner_tol=args.inner_tol, flags=V.VIE_FLAG_TIMING))
+    V.vie_solve(ctx, chans[:nch], [nch] + [0] * (len(chans) // nch - 1))
+    th1 = (np.arange(180) + 0.5) * np.pi / 180
+    ph1 = np.arange(360) * 2 * np.pi / 360 - np.pi
+    TH, PH = np.meshgrid(th1, ph1, indexing="ij")
+    V.vie_farfield(ctx, 0, TH.ravel(), PH.ravel(), nch)
+    V.vie_kernel_times(ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        V.vie_farfield(ctx, 0, TH.ravel(), PH.ravel(), nch)
+    wall = (time.perf_counter() - t0) / reps
+    ms, cnt = V.vie_kernel_times(ctx, reset=True).get("farfield", (0.0, 0))
+    flop = 8.0 * TH.size * nbv * 3 * nch  # complex multiply-adds of the voxel sum
+    dev_s = ms / max(cnt, 1) * 1e-3
+    return {"directions": int(TH.size), "channels": nch, "body_voxels": nbv,
+            "device_ms": dev_s * 1e3, "wall_ms": wall * 1e3,
+            "tflops": flop / dev_s / 1e12 if dev_s > 0 else None,
+            "frac_fp64_peak": flop / dev_s / 78.6e12 if dev_s > 0 else None}
+
+
+def farfield_mode(args):
+    """Solve body 0 of the workload (its channels), then time the far-field
+    sweep alone (`steps` sweeps)."""
+    import torch
+
+    from paper_2508_16471_amd import vie as V
+
+    torch.cuda.set_device(0)
+    V.lib()
+    bodies, chans = make_workload(1, args.channels, args.grid)
+    eps, h, o, g = bodies[0]
+    ctx = V.vie_setup([(eps, h, o)], V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol,
+                                                   max_iter=20000, inner_tol=args.inner_tol,
+                                                   flags=V.VIE_FLAG_TIMING))
+    try:
+        sweep = farfield_sweep(V, torch, ctx, args, chans, args.channels, int((eps != 1.0).sum()),
+                               reps=max(1, args.steps))
+    finally:
+        V.vie_destroy(ctx)
+    print(json.dumps({"mode": "farfield", "grid": list(g.n), "farfield_sweep": sweep}))
 
 
 # ------------------------------------------------------------------ main
 def main():
     args = parse()
-    if args.mode == "matvec":
+    if args.mode in ("matvec", "farfield"):
         if args.gpus != 1:
             sys.exit(2)
-        return matvec_mode(args)
+        return matvec_mode(args) if args.mode == "matvec" else farfield_mode(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the path shards by "
                           "right-hand side / body (see DESIGN.md), --gpus must be 1"}))
@@ -349,7 +469,15 @@ def main():
                  "products_mean": float(np.mean([s["matvecs"] for s in ps])),
                  "max_rel_res": max(s["rel_res"] for s in ps),
                  "kernels": prow}
+    learned = None
+    if not args.no_learned and os.path.exists(args.weights):
+        learned = learned_leg(V, torch, ctx, args, chans, nb, nch, theta, phi, dtau, value)
+    sweep = None
+    if not args.no_sweep:
+        sweep = farfield_sweep(V, torch, ctx, args, chans, nch, int((bodies[0][0] != 1.0).sum()))
     V.vie_destroy(ctx)
+    if args.calib_copy:
+        calib_copy(torch)
 
     cpu = None
     if cpu_t is not None:
@@ -377,14 +505,19 @@ def main():
                    "tol": args.tol, "precision": "mixed (FP32 product, FP64 refinement)",
                    "inner_tol": args.inner_tol, "warm_start": False},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, d["avg_launch_ms"]),
+                     "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
                      "avg_launch_ms": d["avg_launch_ms"]},
         "cpu_baseline": cpu,
         "fast": {"converged": conv, "max_rel_res": max_res, "products_mean": float(prod_fast),
                  "iters_mean": float(np.mean([s["iters"] for s in all_stats])),
                  "kernels": fast_rows},
+        "other_kernels": other_rows(times),
         "plain_fp64": plain,
         "speedup_vs_plain": (value / plain["solves_per_s"]) if plain else None,
+        "learned": learned,
+        "farfield_sweep": sweep,
         "setup_s": setup_s,
     }
     print(json.dumps(line))
