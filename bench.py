@@ -57,9 +57,10 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2508_16471_amd", "weights",
                                                       "warmstart_metasurface128.npy"))
-    ap.add_argument("--mode", choices=["solve", "matvec", "farfield"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "matvec", "farfield", "uneven"], default="solve",
                     help="matvec: time device-resident operator products only; farfield: "
-                         "the 64,800-direction sweep of one body only (profiling)")
+                         "the 64,800-direction sweep of one body only (profiling); uneven: "
+                         "random ellipsoid-union bodies on mixed grids, batched per grid")
     ap.add_argument("--nrhs", type=int, default=1, help="matvec mode: vectors per product")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32")
     return ap.parse_args()
@@ -384,13 +385,85 @@ def farfield_mode(args):
     print(json.dumps({"mode": "farfield", "grid": list(g.n), "farfield_sweep": sweep}))
 
 
+def uneven_mode(args):
+    """Uneven batch: `bodies` random ellipsoid unions (1-6 ellipsoids, semi-axes
+    U[0.2, 1], eps U[1.5, 6]) on grids drawn from {32, 48, 64, 96}^3 (h = 1/16),
+    4 channels each (k uniform on the sphere, random linear polarisation).
+    Bodies sharing a grid form one batched group; groups are solved in grid
+    order, one call each, and a solve's latency is the time from the first
+    call's start to the end of its group's call.  Run with replayed graphs
+    and, for comparison, with eager launches."""
+    import torch
+
+    from paper_2508_16471_amd import vie as V
+    from synth import Grid, random_ellipsoid_body
+
+    torch.cuda.set_device(0)
+    V.lib()
+    rng = np.random.default_rng(4)
+    sizes = [32, 48, 64, 96]
+    nb = args.bodies
+    nch = 4
+    grid_of = [int(rng.choice(sizes)) for _ in range(nb)]
+    bodies, chans = [], []
+    for n in grid_of:
+        g = Grid.centred(n, 1.0 / 16)
+        bodies.append((random_ellipsoid_body(rng, g), g.h, g.origin))
+        for _ in range(nch):
+            k = rng.standard_normal(3)
+            k /= np.linalg.norm(k)
+            p = np.cross(k, rng.standard_normal(3))
+            chans.append((k, p / np.linalg.norm(p)))
+    out = {"mode": "uneven", "bodies": nb, "channels_per_body": nch,
+           "grids": {str(n): grid_of.count(n) for n in sizes}, "tol": args.tol}
+    for label, flags in (("graph", 0), ("eager", V.VIE_FLAG_NO_GRAPH)):
+        opt = V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
+                             inner_tol=args.inner_tol, flags=flags)
+        t0 = time.perf_counter()
+        ctx = V.vie_setup(bodies, opt)
+        setup = time.perf_counter() - t0
+        try:
+            for n in sizes:  # warm-up: tuning and graph capture per group
+                cnt = [nch if grid_of[b] == n else 0 for b in range(nb)]
+                if sum(cnt):
+                    V.vie_solve(ctx, [c for b, c in enumerate(chans) if cnt[b // nch]], cnt)
+                    print(f"uneven {label} warm-up grid {n} done", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            lat, groups, iters = [], {}, []
+            t0 = time.perf_counter()
+            for n in sizes:
+                cnt = [nch if grid_of[b] == n else 0 for b in range(nb)]
+                if not sum(cnt):
+                    continue
+                tg = time.perf_counter()
+                _, st = V.vie_solve(ctx, [c for b, c in enumerate(chans) if cnt[b // nch]], cnt)
+                now = time.perf_counter()
+                groups[str(n)] = {"rhs": sum(cnt), "seconds": now - tg,
+                                  "iters_mean": float(np.mean([x["iters"] for x in st])),
+                                  "converged": all(x["converged"] for x in st)}
+                lat += [now - t0] * len(st)
+                iters += [x["iters"] for x in st]
+                print(f"uneven {label} grid {n}: {groups[str(n)]}", file=sys.stderr, flush=True)
+            total = time.perf_counter() - t0
+        finally:
+            V.vie_destroy(ctx)
+        lat = np.array(lat)
+        out[label] = {"solves_per_s": len(lat) / total, "seconds": total, "setup_s": setup,
+                      "latency_s": {"p50": float(np.percentile(lat, 50)),
+                                    "p90": float(np.percentile(lat, 90)),
+                                    "p99": float(np.percentile(lat, 99))},
+                      "iters_mean": float(np.mean(iters)), "groups": groups}
+        print(json.dumps({label: out[label]}), file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
 # ------------------------------------------------------------------ main
 def main():
     args = parse()
-    if args.mode in ("matvec", "farfield"):
+    if args.mode in ("matvec", "farfield", "uneven"):
         if args.gpus != 1:
             sys.exit(2)
-        return matvec_mode(args) if args.mode == "matvec" else farfield_mode(args)
+        return {"matvec": matvec_mode, "farfield": farfield_mode, "uneven": uneven_mode}[args.mode](args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the path shards by "
                           "right-hand side / body (see DESIGN.md), --gpus must be 1"}))

@@ -61,7 +61,13 @@ enum vie_status {
 
 enum { VIE_FP64 = 0, VIE_MIXED = 1 };
 enum { VIE_NORM_R1 = 0, VIE_NORM_R2 = 1 };
-enum { VIE_FLAG_TIMING = 1 }; /* record per-kernel HIP-event durations */
+enum {
+  VIE_FLAG_TIMING = 1,  /* record per-kernel HIP-event durations (disables graphs) */
+  VIE_FLAG_NO_GRAPH = 2 /* launch every BiCGSTAB iteration eagerly instead of     */
+                        /* replaying a captured hipGraph of VIE_GRAPH_ITERS        */
+                        /* iterations (results are identical either way)           */
+};
+enum { VIE_GRAPH_ITERS = 8 };
 
 /* One body on its own uniform grid (eq. 24's volume V, discretised). */
 typedef struct {

@@ -101,6 +101,15 @@ struct Group {
     DevBuf vi, org;
   };
   std::vector<std::unique_ptr<Far>> far;  // [slot]
+  // captured BiCGSTAB iterations (replayed while every pointer and the shape
+  // they were captured with are unchanged)
+  struct IterGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void*> key;
+    ~IterGraph() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+    }
+  } iter_graph;
   int zvar[2] = {-1, -1};        // autotuned z-pass shape per precision (-1: not yet)
   int zvar_nrhs[2] = {0, 0};     // right-hand-side count it was tuned for
 };
@@ -724,30 +733,84 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
   int rc = ensure_hflags(ctx, nrhs);
   if (rc != VIE_OK) return rc;
 
+  // one BiCGSTAB iteration for every active right-hand side
+  auto iteration = [&]() -> hipError_t {
+    hipError_t he;
+    if ((he = timed(ctx, 10, [&] {
+           return launch_update_p(g, bi, vb, st, active, r, p, v, ctx->stream);
+         })) != hipSuccess)
+      return he;
+    EpiArgs e1{EPI_RHV, rh, part, 0, pol, ph};
+    if ((he = run_matvec(ctx, G, prec, p, v, e1, active)) != hipSuccess) return he;
+    if ((he = timed(ctx, 11, [&] {
+           return launch_finalize(FIN_ALPHA, nrhs, e1.part_blocks, part, st, flags, fp,
+                                  ctx->stream);
+         })) != hipSuccess)
+      return he;
+    if ((he = timed(ctx, 10, [&] {
+           return launch_update_s(g, bi, vb, st, active, r, v, s, ctx->stream);
+         })) != hipSuccess)
+      return he;
+    EpiArgs e2{EPI_TS, nullptr, part, 0, pol, ph};
+    if ((he = run_matvec(ctx, G, prec, s, t, e2, active)) != hipSuccess) return he;
+    if ((he = timed(ctx, 11, [&] {
+           return launch_finalize(FIN_OMEGA, nrhs, e2.part_blocks, part, st, flags, fp,
+                                  ctx->stream);
+         })) != hipSuccess)
+      return he;
+    if ((he = timed(ctx, 10, [&] {
+           return launch_update_xr(g, bi, vb, st, active, x, r, p, s, t, rh, part, ctx->stream);
+         })) != hipSuccess)
+      return he;
+    return timed(ctx, 11, [&] {
+      return launch_finalize(FIN_RHO, nrhs, vb, part, st, flags, fp, ctx->stream);
+    });
+  };
+  // Graph mode: capture VIE_GRAPH_ITERS iterations once and replay them.  Every
+  // launch reads its scalars from device state and skips inactive right-hand
+  // sides, so replaying past convergence changes nothing.  The capture holds
+  // only kernel launches (the autotuner, which clears memory, runs first).
+  const bool use_graph = !timing_on(ctx) && !(ctx->opt.flags & VIE_FLAG_NO_GRAPH);
+  const int per_launch = use_graph ? VIE_GRAPH_ITERS : 1;
+  if (use_graph) {
+    VIE_HIP(tune_z(ctx, G, prec));
+    std::vector<const void*> key = {x, r, rh, p, v, s, t, part, st, flags, pol, ph,
+                                    G.bufA.p, G.bufB.p, G.roff.p, G.rhs_body.p,
+                                    (const void*)ctx->stream,
+                                    (const void*)(intptr_t)nrhs, (const void*)(intptr_t)prec,
+                                    (const void*)(intptr_t)G.zvar[prec],
+                                    (const void*)(intptr_t)fp.max_iter};
+    double fpd[3] = {fp.tol2_done, fp.tol2_inner, fp.eta2};
+    for (double d : fpd) {
+      intptr_t bits = 0;
+      memcpy(&bits, &d, sizeof(d) < sizeof(bits) ? sizeof(d) : sizeof(bits));
+      key.push_back((const void*)bits);
+    }
+    if (!G.iter_graph.exec || G.iter_graph.key != key) {
+      if (G.iter_graph.exec) (void)hipGraphExecDestroy(G.iter_graph.exec);
+      G.iter_graph.exec = nullptr;
+      hipGraph_t graph = nullptr;
+      VIE_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = hipSuccess;
+      for (int i = 0; i < VIE_GRAPH_ITERS && ce == hipSuccess; ++i) ce = iteration();
+      hipError_t ee = hipStreamEndCapture(ctx->stream, &graph);
+      if (ce == hipSuccess) ce = ee;
+      if (ce == hipSuccess) ce = hipGraphInstantiate(&G.iter_graph.exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      VIE_HIP(ce);
+      G.iter_graph.key = key;
+    }
+  }
+
   for (int cycle = 0;; ++cycle) {
     // iterate until every right-hand side has left the cycle (lagged check)
     int64_t k = 0;
     for (;; ++k) {
-      VIE_HIP(timed(ctx, 10,
-                    [&] { return launch_update_p(g, bi, vb, st, active, r, p, v, ctx->stream); }));
-      EpiArgs e1{EPI_RHV, rh, part, 0, pol, ph};
-      VIE_HIP(run_matvec(ctx, G, prec, p, v, e1, active));
-      VIE_HIP(timed(ctx, 11, [&] {
-        return launch_finalize(FIN_ALPHA, nrhs, e1.part_blocks, part, st, flags, fp, ctx->stream);
-      }));
-      VIE_HIP(timed(ctx, 10,
-                    [&] { return launch_update_s(g, bi, vb, st, active, r, v, s, ctx->stream); }));
-      EpiArgs e2{EPI_TS, nullptr, part, 0, pol, ph};
-      VIE_HIP(run_matvec(ctx, G, prec, s, t, e2, active));
-      VIE_HIP(timed(ctx, 11, [&] {
-        return launch_finalize(FIN_OMEGA, nrhs, e2.part_blocks, part, st, flags, fp, ctx->stream);
-      }));
-      VIE_HIP(timed(ctx, 10, [&] {
-        return launch_update_xr(g, bi, vb, st, active, x, r, p, s, t, rh, part, ctx->stream);
-      }));
-      VIE_HIP(timed(ctx, 11, [&] {
-        return launch_finalize(FIN_RHO, nrhs, vb, part, st, flags, fp, ctx->stream);
-      }));
+      if (use_graph) {
+        VIE_HIP(hipGraphLaunch(G.iter_graph.exec, ctx->stream));
+      } else {
+        VIE_HIP(iteration());
+      }
       const int slot = (int)(k & 1);
       VIE_HIP(hipMemcpyAsync(ctx->hflags[slot], active, nrhs * sizeof(int), hipMemcpyDeviceToHost,
                              ctx->stream));
@@ -759,7 +822,7 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
         for (int i = 0; i < nrhs; ++i) any |= ctx->hflags[ps][i] != 0;
         if (!any) break;
       }
-      if (k > (int64_t)ctx->opt.max_iter + 2) break;
+      if (k * per_launch > (int64_t)ctx->opt.max_iter + 2) break;
     }
     if (getenv("VIE_LOG")) {
       std::vector<KState> hs(nrhs);

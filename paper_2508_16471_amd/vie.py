@@ -19,6 +19,7 @@ VIE_OK, VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_ENOCONV, VIE_ENOTSUP, VIE_ESTAT
 VIE_FP64, VIE_MIXED = 0, 1
 VIE_NORM_R1, VIE_NORM_R2 = 0, 1
 VIE_FLAG_TIMING = 1
+VIE_FLAG_NO_GRAPH = 2
 
 
 class vie_c64(C.Structure):
