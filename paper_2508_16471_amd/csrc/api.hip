@@ -68,7 +68,7 @@ struct Group {
   double h;
   std::vector<int> bodies;       // body ids
   DevBuf chi;                    // double[nb][n]
-  DevBuf spec64, spec32;         // octant spectra [6][Q3][Q2][Q1]
+  DevBuf spec64, spec32;         // octant spectra [Q2][Q3][Q1][6] (see k_octant)
   DevBuf tw64[3], tw32[3];       // twiddles per axis
   // body-compressed index data of every body of the group (see BodyIdx)
   DevBuf vox_all, chic_all, line_ptr_all, nb_arr, voff_arr;

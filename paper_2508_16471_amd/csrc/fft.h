@@ -58,25 +58,47 @@ __device__ __forceinline__ cpx<T> twc(cpx<T> a, int m) {
 }
 
 // In-register DFT of R points (R in {1,2,4,8,16}), natural order in and out.
-template <int R, bool INV, typename T>
+// HIN: inputs a[R/2..R) are known to be zero (zero-padded line);
+// HOUT: only outputs a[0..R/2) are needed (truncated line; the others are
+// left unspecified).  Both prune work without changing the needed values.
+template <int R, bool INV, bool HIN = false, bool HOUT = false, typename T>
 __device__ __forceinline__ void dft(cpx<T>* a) {
   if constexpr (R == 1) {
     return;
   } else if constexpr (R == 2) {
-    cpx<T> t = a[0];
-    a[0] = t + a[1];
-    a[1] = t - a[1];
+    if constexpr (HIN) {
+      a[1] = a[0];
+    } else {
+      cpx<T> t = a[0];
+      a[0] = t + a[1];
+      if constexpr (!HOUT) a[1] = t - a[1];
+    }
   } else if constexpr (R == 4) {
-    cpx<T> s0 = a[0] + a[2], d0 = a[0] - a[2];
-    cpx<T> s1 = a[1] + a[3], d1 = a[1] - a[3];
-    // d1 * W4^1 = d1 * (-i) forward, (+i) inverse
-    cpx<T> e1 = INV ? mk(-d1.im, d1.re) : mk(d1.im, -d1.re);
-    a[0] = s0 + s1;
-    a[2] = s0 - s1;
-    a[1] = d0 + e1;
-    a[3] = d0 - e1;
+    if constexpr (HIN) {
+      // d1 * W4^1 = d1 * (-i) forward, (+i) inverse; a2 = a3 = 0
+      const cpx<T> a0 = a[0], a1 = a[1];
+      const cpx<T> e1 = INV ? mk(-a1.im, a1.re) : mk(a1.im, -a1.re);
+      a[0] = a0 + a1;
+      a[1] = a0 + e1;
+      if constexpr (!HOUT) {
+        a[2] = a0 - a1;
+        a[3] = a0 - e1;
+      }
+    } else {
+      cpx<T> s0 = a[0] + a[2], d0 = a[0] - a[2];
+      cpx<T> s1 = a[1] + a[3], d1 = a[1] - a[3];
+      cpx<T> e1 = INV ? mk(-d1.im, d1.re) : mk(d1.im, -d1.re);
+      a[0] = s0 + s1;
+      a[1] = d0 + e1;
+      if constexpr (!HOUT) {
+        a[2] = s0 - s1;
+        a[3] = d0 - e1;
+      }
+    }
   } else {
-    // R = R1 * R2, input index n = R2 n1 + n2, output k = k1 + R1 k2
+    // R = R1 * R2, input index n = R2 n1 + n2, output k = k1 + R1 k2.
+    // Inputs n >= R/2 are those with n1 >= R1/2; outputs k < R/2 those with
+    // k2 < R2/2.
     constexpr int R1 = (R == 8) ? 2 : 4;
     constexpr int R2 = R / R1;
     cpx<T> y[R];
@@ -85,7 +107,7 @@ __device__ __forceinline__ void dft(cpx<T>* a) {
       cpx<T> u[R1];
 #pragma unroll
       for (int n1 = 0; n1 < R1; ++n1) u[n1] = a[R2 * n1 + n2];
-      dft<R1, INV>(u);
+      dft<R1, INV, HIN, false>(u);
 #pragma unroll
       for (int k1 = 0; k1 < R1; ++k1) y[n2 * R1 + k1] = twc<R, INV>(u[k1], n2 * k1);
     }
@@ -94,9 +116,9 @@ __device__ __forceinline__ void dft(cpx<T>* a) {
       cpx<T> u[R2];
 #pragma unroll
       for (int n2 = 0; n2 < R2; ++n2) u[n2] = y[n2 * R1 + k1];
-      dft<R2, INV>(u);
+      dft<R2, INV, false, HOUT>(u);
 #pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2) a[k1 + R1 * k2] = u[k2];
+      for (int k2 = 0; k2 < (HOUT ? R2 / 2 : R2); ++k2) a[k1 + R1 * k2] = u[k2];
     }
   }
 }

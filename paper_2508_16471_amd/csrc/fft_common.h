@@ -60,7 +60,10 @@ struct TwReg {
   }
 };
 
-template <typename T, int P, int E, int NS, bool INV, int OFF>
+// HIN: the line's upper half (points P/2..P) is zero on entry (every thread
+// holds it as v[E/2..E)); HOUT: only the lower half is needed on exit.  The
+// first / last stage's DFTs are pruned accordingly.
+template <typename T, int P, int E, int NS, bool INV, int OFF, bool HIN = false, bool HOUT = false>
 __device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int t,
                                              const cpx<T>* __restrict__ w) {
   constexpr int RAD = (P / NS < E) ? P / NS : E;
@@ -91,8 +94,14 @@ __device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int
       }
     }
   }
+  // the first stage has one DFT per thread (RAD = E) holding points t + q P/E:
+  // its inputs q >= E/2 are the zero half; in the last stage the needed
+  // outputs q = b + r NB < E/2 are the DFT outputs r < RAD/2
+  static_assert(!FIRST || NB == 1, "first stage: one DFT per thread");
+  constexpr bool PIN = HIN && FIRST;
+  constexpr bool POUT = HOUT && LAST;
 #pragma unroll
-  for (int b = 0; b < NB; ++b) dft<RAD, INV>(&u[b * RAD]);
+  for (int b = 0; b < NB; ++b) dft<RAD, INV, PIN, POUT>(&u[b * RAD]);
   if constexpr (LAST) {
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -108,14 +117,14 @@ __device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int
       for (int r = 0; r < RAD; ++r) lds[base + r * NS] = u[b * RAD + r];
     }
     __syncthreads();
-    fft_stages_p<T, P, E, NS * RAD, INV, OFF + here>(v, lds, t, w);
+    fft_stages_p<T, P, E, NS * RAD, INV, OFF + here, HIN, HOUT>(v, lds, t, w);
   }
 }
 
-template <typename T, int P, bool INV>
+template <typename T, int P, bool INV, bool HIN = false, bool HOUT = false>
 __device__ __forceinline__ void line_fft(cpx<T> (&v)[fft_e<P>()], cpx<T>* line, int t,
                                          const TwReg<T, P, fft_e<P>()>& tr) {
-  fft_stages_p<T, P, fft_e<P>(), 1, INV, 0>(v, LdsLine<T>{line}, t, tr.w);
+  fft_stages_p<T, P, fft_e<P>(), 1, INV, 0, HIN, HOUT>(v, LdsLine<T>{line}, t, tr.w);
 }
 
 template <typename T>

@@ -25,7 +25,10 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd(
     int lines_per_rhs, int blocks_per_rhs, const int* __restrict__ active) {
   constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), L = NT / TT;
   __shared__ cpx<T> lds[L * Pad<P>::LSTR];
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  // Hardware order (consecutive blocks go to consecutive XCDs): the lines of
+  // one right-hand side spread over every XCD, so inactive right-hand sides
+  // leave none idle, and concurrently running blocks touch neighbouring lines.
+  const int b = blockIdx.x;
   const int rhs = b / blocks_per_rhs, blk = b % blocks_per_rhs;
   if (active && !active[rhs]) return;
   const int li = threadIdx.x / TT, t = threadIdx.x % TT;
@@ -44,7 +47,7 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd(
     else
       v[q] = mk<T>(0, 0);
   }
-  line_fft<T, P, false>(v, lds + li * Pad<P>::LSTR, t, tr);
+  line_fft<T, P, false, PAD>(v, lds + li * Pad<P>::LSTR, t, tr);
   if (valid) {
     cpx<T>* o = out + gl * P;
 #pragma unroll
@@ -79,10 +82,15 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_strided(
     StridedArgs a, const int* __restrict__ active) {
   constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), W = NT / TT;
   __shared__ cpx<T> lds[W * Pad<P>::LSTR];
+  // XCD-contiguous ranges of the logical order below (neighbouring column
+  // tiles of one slab share an XCD), with the right-hand side innermost so
+  // that every XCD holds an equal share of each right-hand side and
+  // inactive ones leave no XCD idle.
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int tile = b % a.tiles, s = b / a.tiles;
   const int per_rhs = a.ncomp * a.nz;
-  const int rhs = s / per_rhs, cz = s % per_rhs;
+  const int nrhs_l = gridDim.x / (a.tiles * per_rhs);
+  const int rhs = b % nrhs_l, rest = b / nrhs_l;
+  const int tile = rest % a.tiles, cz = rest / a.tiles;
   if (active && !active[rhs]) return;
   const int comp = cz / a.nz, z = cz % a.nz;
   const int cw = threadIdx.x % W, t = threadIdx.x / W;
@@ -100,7 +108,7 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_strided(
     else
       v[q] = mk<T>(0, 0);
   }
-  line_fft<T, P, INV>(v, lds + cw * Pad<P>::LSTR, t, tr);
+  line_fft<T, P, INV, PAD, TRUNC>(v, lds + cw * Pad<P>::LSTR, t, tr);
   if (valid) {
     cpx<T>* po = out + slab_base(a.out, rhs, comp, z, a.zl) + col;
 #pragma unroll
@@ -142,13 +150,33 @@ struct ZArgs {
 };
 
 // Stockham stages with an explicit points-per-thread E (may differ from fft_e<P>).
-template <typename T, int P, int E, bool INV>
+template <typename T, int P, int E, bool INV, bool HIN = false, bool HOUT = false>
 __device__ __forceinline__ void line_fft_e(cpx<T> (&v)[E], cpx<T>* line, int t,
                                            const TwReg<T, P, E>& tr) {
-  fft_stages_p<T, P, E, 1, INV, 0>(v, LdsLine<T>{line}, t, tr.w);
+  fft_stages_p<T, P, E, 1, INV, 0, HIN, HOUT>(v, LdsLine<T>{line}, t, tr.w);
 }
 
-template <typename T, int P, int E, int NT>
+// The six spectrum components of one frequency: one contiguous record.
+template <typename T>
+__device__ __forceinline__ void load_g6(const cpx<T>* __restrict__ sp, cpx<T> (&g)[6]) {
+  if constexpr (sizeof(T) == 4) {
+    const float4* p4 = reinterpret_cast<const float4*>(sp);
+    const float4 a = p4[0], b = p4[1], c = p4[2];
+    g[0] = mk<T>(a.x, a.y);
+    g[1] = mk<T>(a.z, a.w);
+    g[2] = mk<T>(b.x, b.y);
+    g[3] = mk<T>(b.z, b.w);
+    g[4] = mk<T>(c.x, c.y);
+    g[5] = mk<T>(c.z, c.w);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) g[k] = sp[k];
+  }
+}
+
+// FAST: the z block is 16 and N3 = P/2 (every stored z is a body row), so the
+// blocked offsets are shifts and no row needs a bounds test.
+template <typename T, int P, int E, int NT, bool FAST>
 __global__ __launch_bounds__(NT) void k_fft_z_green(
     cpx<T>* __restrict__ B, const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw,
     ZArgs a, const int* __restrict__ active) {
@@ -170,13 +198,18 @@ __global__ __launch_bounds__(NT) void k_fft_z_green(
   const int cw = threadIdx.x % W, t = threadIdx.x / W;
   const int xx = tile * W + cw;
   const bool valid = xx < a.P1;
-  // B[rhs][comp][z / zl][xi_y][z % zl][xi_x]
+  // B[rhs][comp][z / zl][xi_y][z % zl][xi_x]; offsets within one right-hand
+  // side fit in 32 bits (3 N3 P2 P1 < 2^31 for P <= 512)
   cpx<T>* col = B + rhs * a.rhs_stride + (int64_t)xy * a.zl * a.P1 + (valid ? xx : 0);
-  int64_t zoff[E / 2];
+  const int cs = (int)a.comp_stride;
+  int zoff[E / 2];
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int z = t + q * TT;
-    zoff[q] = (z / a.zl) * a.zhs + (z % a.zl) * a.zls;
+    if constexpr (FAST)
+      zoff[q] = (z >> 4) * (int)a.zhs + (z & 15) * (int)a.zls;
+    else
+      zoff[q] = (z / a.zl) * (int)a.zhs + (z % a.zl) * (int)a.zls;
   }
   TwReg<T, P, E> tr;
   tr.load(t, tw);
@@ -184,31 +217,33 @@ __global__ __launch_bounds__(NT) void k_fft_z_green(
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int z = t + q * TT;
-    if (q < E / 2 && valid && z < a.N3) {
+    if (q < E / 2 && valid && (FAST || z < a.N3)) {
       v0[q] = col[zoff[q]];
-      v1[q] = col[a.comp_stride + zoff[q]];
-      v2[q] = col[2 * a.comp_stride + zoff[q]];
+      v1[q] = col[cs + zoff[q]];
+      v2[q] = col[2 * cs + zoff[q]];
     } else {
       v0[q] = v1[q] = v2[q] = mk<T>(0, 0);
     }
   }
   cpx<T>* line = lds + cw * LS;
-  line_fft_e<T, P, E, false>(v0, line, t, tr);
-  line_fft_e<T, P, E, false>(v1, line, t, tr);
-  line_fft_e<T, P, E, false>(v2, line, t, tr);
-  // octant coordinates and mirror flags; spectrum layout [yo][ab][zo][xo]
+  // z < N3 <= P/2: the upper half of every line is zero padding
+  line_fft_e<T, P, E, false, true, false>(v0, line, t, tr);
+  line_fft_e<T, P, E, false, true, false>(v1, line, t, tr);
+  line_fft_e<T, P, E, false, true, false>(v2, line, t, tr);
+  // octant coordinates and mirror flags; spectrum layout [yo][zo][xo][ab]
   const int xm = xx > a.P1 / 2, ym = xy > a.P2 / 2;
   const int xo = xm ? a.P1 - xx : xx, yo = ym ? a.P2 - xy : xy;
-  const int64_t oct = (int64_t)a.Q3 * a.Q1;
-  const cpx<T>* sxy = spec + (int64_t)yo * 6 * oct + (valid ? xo : 0);
+  const cpx<T>* sxy = spec + ((int64_t)yo * a.Q3 * a.Q1 + (valid ? xo : 0)) * 6;
+  const int zstep = 6 * a.Q1;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int z = t + q * TT;
     const int zm = z > P / 2;
     const int zo = zm ? P - z : z;
-    const cpx<T>* sp = sxy + (int64_t)zo * a.Q1;
-    const cpx<T> gxx = sp[0], gyy = sp[3 * oct], gzz = sp[5 * oct];
-    cpx<T> gxy = sp[oct], gxz = sp[2 * oct], gyz = sp[4 * oct];
+    cpx<T> gg[6];
+    load_g6<T>(sxy + zo * zstep, gg);
+    const cpx<T> gxx = gg[0], gyy = gg[3], gzz = gg[5];
+    cpx<T> gxy = gg[1], gxz = gg[2], gyz = gg[4];
     // G_ab is odd along axis e iff exactly one of a, b equals e
     if (xm ^ ym) gxy = mk<T>(-gxy.re, -gxy.im);
     if (xm ^ zm) gxz = mk<T>(-gxz.re, -gxz.im);
@@ -218,17 +253,18 @@ __global__ __launch_bounds__(NT) void k_fft_z_green(
     v1[q] = cfma(gyz, iz, cfma(gyy, iy, gxy * ix));
     v2[q] = cfma(gzz, iz, cfma(gyz, iy, gxz * ix));
   }
-  line_fft_e<T, P, E, true>(v0, line, t, tr);
-  line_fft_e<T, P, E, true>(v1, line, t, tr);
-  line_fft_e<T, P, E, true>(v2, line, t, tr);
+  // only z < N3 <= P/2 is stored
+  line_fft_e<T, P, E, true, false, true>(v0, line, t, tr);
+  line_fft_e<T, P, E, true, false, true>(v1, line, t, tr);
+  line_fft_e<T, P, E, true, false, true>(v2, line, t, tr);
   if (valid) {
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
       const int z = t + q * TT;
-      if (z < a.N3) {
+      if (FAST || z < a.N3) {
         col[zoff[q]] = v0[q];
-        col[a.comp_stride + zoff[q]] = v1[q];
-        col[2 * a.comp_stride + zoff[q]] = v2[q];
+        col[cs + zoff[q]] = v1[q];
+        col[2 * cs + zoff[q]] = v2[q];
       }
     }
   }
@@ -249,7 +285,8 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv(
   constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), L = NT / TT;
   __shared__ cpx<T> lds[L * Pad<P>::LSTR];
   __shared__ double red[4 * (NT / 64 + 1)];
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  // hardware order (see the forward x pass)
+  const int b = blockIdx.x;
   const int rhs = b / a.blocks_per_rhs, blk = b % a.blocks_per_rhs;
   if (active && !active[rhs]) return;
   const int li = threadIdx.x / TT, t = threadIdx.x % TT;
@@ -265,7 +302,7 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv(
 #pragma unroll
     for (int q = 0; q < E; ++q) v[q] = valid ? src[t + q * TT] : mk<T>(0, 0);
   }
-  line_fft<T, P, true>(v, lds + li * Pad<P>::LSTR, t, tr);
+  line_fft<T, P, true, false, true>(v, lds + li * Pad<P>::LSTR, t, tr);  // only x < N1 kept
   const int comp = lc / a.lines_per_comp, sp = lc % a.lines_per_comp;  // sp = z*N2 + y
   const double* chib = chi + (int64_t)rhs_body[rhs] * a.n + (int64_t)sp * a.N1;
   c64 s0 = mk(0.0, 0.0), s1 = mk(0.0, 0.0);
@@ -398,7 +435,13 @@ static void z_launch(const GroupGeom& g, ZArgs a, cpx<T>* B, const cpx<T>* spec,
   constexpr int W = sh.nt / (PP / E);
   a.tiles_x = (g.P[0] + W - 1) / W;
   const dim3 grid((g.P[1] / 2 + 1) * 2 * a.tiles_x * g.nrhs);
-  k_fft_z_green<T, PP, E, sh.nt><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
+  if constexpr (PP >= 32) {
+    if (a.zl == 16 && 2 * a.N3 == PP) {
+      k_fft_z_green<T, PP, E, sh.nt, true><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
+      return;
+    }
+  }
+  k_fft_z_green<T, PP, E, sh.nt, false><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
 }
 
 template <typename T>

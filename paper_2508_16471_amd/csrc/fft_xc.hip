@@ -22,7 +22,10 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd_c(
   constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), L = NT / TT,
                 LS = Pad<P>::LSTR;
   __shared__ cpx<T> lds[L * LS];
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  // Hardware order (consecutive blocks go to consecutive XCDs): the lines of
+  // one right-hand side spread over every XCD, so inactive right-hand sides
+  // leave none idle, and concurrently running blocks touch neighbouring lines.
+  const int b = blockIdx.x;
   const int rhs = b / blocks_per_rhs, blk = b % blocks_per_rhs;
   if (active && !active[rhs]) return;
   const int lines_per_rhs = 3 * N2 * N3, lpc = N2 * N3;
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd_c(
   cpx<T> v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) v[q] = (q < E / 2) ? myl[pidx(t + q * TT)] : mk<T>(0, 0);
-  line_fft<T, P, false>(v, myl, t, tr);
+  line_fft<T, P, false, true>(v, myl, t, tr);  // upper half is zero padding
   if (valid) {
     cpx<T>* o = out + ((size_t)rhs * lines_per_rhs + line) * P;
 #pragma unroll
@@ -71,7 +74,10 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv_c(
                 LS = Pad<P>::LSTR;
   __shared__ cpx<T> lds[L * LS];
   __shared__ double red[4 * (NT / 64 + 1)];
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  // Hardware order (consecutive blocks go to consecutive XCDs): the lines of
+  // one right-hand side spread over every XCD, so inactive right-hand sides
+  // leave none idle, and concurrently running blocks touch neighbouring lines.
+  const int b = blockIdx.x;
   const int rhs = b / blocks_per_rhs, blk = b % blocks_per_rhs;
   if (active && !active[rhs]) return;
   const int lines_per_rhs = 3 * N2 * N3, lpc = N2 * N3;
@@ -89,7 +95,7 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv_c(
     for (int q = 0; q < E; ++q) v[q] = valid ? src[t + q * TT] : mk<T>(0, 0);
   }
   cpx<T>* myl = lds + li * LS;
-  line_fft<T, P, true>(v, myl, t, tr);
+  line_fft<T, P, true, false, true>(v, myl, t, tr);  // only x < N1 is used
   __syncthreads();  // every thread has left the FFT's last LDS read
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) myl[pidx(t + q * TT)] = v[q];

@@ -60,8 +60,8 @@ __global__ void k_green_sample(c64* __restrict__ work, GroupGeom g, int ab, doub
   }
 }
 
-// spec[y][ab][z][x] over the octant (one y-slice holds all six components, so
-// the z pass reads one contiguous region per workgroup), scaled by 1/M.
+// spec[y][z][x][ab] over the octant: the six components of a frequency are
+// one contiguous record (the z pass reads it with wide loads), scaled by 1/M.
 __global__ void k_octant(const c64* __restrict__ work, c64* __restrict__ s64,
                          c32* __restrict__ s32, GroupGeom g, int ab) {
   const int64_t oct = (int64_t)g.Q[0] * g.Q[1] * g.Q[2];
@@ -73,7 +73,7 @@ __global__ void k_octant(const c64* __restrict__ work, c64* __restrict__ s64,
     const int z = (int)(e / ((int64_t)g.Q[0] * g.Q[1]));
     const c64 v = work[((int64_t)z * g.P[1] + y) * g.P[0] + x];
     const c64 w = mk(v.re * inv, v.im * inv);
-    const int64_t o = (((int64_t)y * 6 + ab) * g.Q[2] + z) * g.Q[0] + x;
+    const int64_t o = (((int64_t)y * g.Q[2] + z) * g.Q[0] + x) * 6 + ab;
     s64[o] = w;
     if (s32) s32[o] = mk((float)w.re, (float)w.im);
   }
