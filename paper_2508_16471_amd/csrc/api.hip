@@ -513,7 +513,7 @@ static hipError_t tune_z(vie_ctx* ctx, Group& G, int precision) {
   if (G.zvar[precision] >= 0 && G.zvar_nrhs[precision] == G.g.nrhs) return hipSuccess;
   const char* force = getenv("VIE_ZVAR");
   if (force) {
-    G.zvar[precision] = std::max(0, std::min(z_variants() - 1, atoi(force)));
+    G.zvar[precision] = std::max(0, std::min(z_variants(precision) - 1, atoi(force)));
     G.zvar_nrhs[precision] = G.g.nrhs;
     return hipSuccess;
   }
@@ -527,7 +527,7 @@ static hipError_t tune_z(vie_ctx* ctx, Group& G, int precision) {
   }
   float best = 1e30f;
   int bestv = 0;
-  for (int v = 0; v < z_variants() && e == hipSuccess; ++v) {
+  for (int v = 0; v < z_variants(precision) && e == hipSuccess; ++v) {
     MatvecArgs m = matvec_args(G, precision, nullptr);
     m.zvar = v;
     e = launch_z_only(m, precision, ctx->stream);  // warm-up

@@ -131,14 +131,21 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_strided(
 // W = NT E / P columns per workgroup; LDS = W padded lines.
 struct ZShape {
   int e, nt;
+  bool occ3;  // register budget capped for three waves per SIMD
 };
 template <typename T>
 constexpr ZShape zshape(int v) {
   // FP32: 3 x 16 complex in registers / 3 x 8; FP64: 3 x 8 / 3 x 4
-  return sizeof(T) == 4 ? (v == 0 ? ZShape{16, 256} : v == 1 ? ZShape{8, 512} : ZShape{8, 256})
-                        : (v == 0 ? ZShape{8, 256} : v == 1 ? ZShape{4, 512} : ZShape{4, 256});
+  return sizeof(T) == 4
+             ? (v == 0 ? ZShape{16, 256, false}
+                       : v == 1 ? ZShape{8, 512, false}
+                                : v == 2 ? ZShape{8, 256, false} : ZShape{16, 256, true})
+             : (v == 0 ? ZShape{8, 256, false}
+                       : v == 1 ? ZShape{4, 512, false} : ZShape{4, 256, false});
 }
-static constexpr int kZVariants = 3;
+// FP32 has a fourth shape (16 points per thread at three waves per SIMD, a few
+// registers spilled); FP64 would spill too much for it.
+static constexpr int kZVariants32 = 4, kZVariants64 = 3;
 template <int P, int E0>
 constexpr int zcap() {
   return E0 < P ? E0 : P;
@@ -177,9 +184,10 @@ __device__ __forceinline__ void load_g6(const cpx<T>* __restrict__ sp, cpx<T> (&
 // FAST: the z block is 16 and N3 = P/2 (every stored z is a body row), so the
 // blocked offsets are shifts and no row needs a bounds test.
 template <typename T, int P, int E, int NT, bool FAST>
-__global__ __launch_bounds__(NT) void k_fft_z_green(
-    cpx<T>* __restrict__ B, const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw,
-    ZArgs a, const int* __restrict__ active) {
+__device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
+                                             const cpx<T>* __restrict__ spec,
+                                             const cpx<T>* __restrict__ tw, const ZArgs& a,
+                                             const int* __restrict__ active) {
   constexpr int TT = P / E, W = NT / TT, LS = Pad<P>::LSTR;
   __shared__ cpx<T> lds[W * LS];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -268,6 +276,19 @@ __global__ __launch_bounds__(NT) void k_fft_z_green(
       }
     }
   }
+}
+
+template <typename T, int P, int E, int NT, bool FAST>
+__global__ __launch_bounds__(NT) void k_fft_z_green(
+    cpx<T>* __restrict__ B, const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw,
+    ZArgs a, const int* __restrict__ active) {
+  z_green_body<T, P, E, NT, FAST>(B, spec, tw, a, active);
+}
+template <typename T, int P, int E, int NT, bool FAST>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_fft_z_green_o3(
+    cpx<T>* __restrict__ B, const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw,
+    ZArgs a, const int* __restrict__ active) {
+  z_green_body<T, P, E, NT, FAST>(B, spec, tw, a, active);
 }
 
 // ------------------------------------------------ X inverse + epilogue
@@ -435,13 +456,23 @@ static void z_launch(const GroupGeom& g, ZArgs a, cpx<T>* B, const cpx<T>* spec,
   constexpr int W = sh.nt / (PP / E);
   a.tiles_x = (g.P[0] + W - 1) / W;
   const dim3 grid((g.P[1] / 2 + 1) * 2 * a.tiles_x * g.nrhs);
-  if constexpr (PP >= 32) {
-    if (a.zl == 16 && 2 * a.N3 == PP) {
-      k_fft_z_green<T, PP, E, sh.nt, true><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
-      return;
+  if constexpr (sh.occ3) {
+    if constexpr (PP >= 32) {
+      if (a.zl == 16 && 2 * a.N3 == PP) {
+        k_fft_z_green_o3<T, PP, E, sh.nt, true><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
+        return;
+      }
     }
+    k_fft_z_green_o3<T, PP, E, sh.nt, false><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
+  } else {
+    if constexpr (PP >= 32) {
+      if (a.zl == 16 && 2 * a.N3 == PP) {
+        k_fft_z_green<T, PP, E, sh.nt, true><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
+        return;
+      }
+    }
+    k_fft_z_green<T, PP, E, sh.nt, false><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
   }
-  k_fft_z_green<T, PP, E, sh.nt, false><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
 }
 
 template <typename T>
@@ -465,6 +496,12 @@ static hipError_t z_pass(const GroupGeom& g, cpx<T>* B, const cpx<T>* spec, cons
                    switch (variant) {
                      case 1: z_launch<T, PP, 1>(g, a, B, spec, tw, active, s); break;
                      case 2: z_launch<T, PP, 2>(g, a, B, spec, tw, active, s); break;
+                     case 3:
+                       if constexpr (sizeof(T) == 4) {
+                         z_launch<T, PP, 3>(g, a, B, spec, tw, active, s);
+                         break;
+                       }
+                       [[fallthrough]];
                      default: z_launch<T, PP, 0>(g, a, B, spec, tw, active, s); break;
                    }
                  }));
@@ -547,7 +584,7 @@ static hipError_t matvec_t(const MatvecArgs& m, const c64* x, c64* y, EpiArgs& e
   return hipSuccess;
 }
 
-int z_variants() { return kZVariants; }
+int z_variants(int precision) { return precision == 0 ? kZVariants64 : kZVariants32; }
 
 hipError_t launch_z_only(const MatvecArgs& m, int precision, hipStream_t s) {
   const GroupGeom& g = *m.g;

@@ -88,7 +88,7 @@ int vec_blocks(const GroupGeom& g);
 
 hipError_t launch_matvec(const MatvecArgs& a, int precision, const c64* x, c64* y, EpiArgs& epi,
                          hipStream_t s, void (*ev_cb)(int kind, bool begin, void* u), void* u);
-int z_variants();
+int z_variants(int precision);  // z-pass launch shapes (0 = FP64, 1 = FP32)
 // z pass alone on bufB (autotuning; contents are scratch)
 hipError_t launch_z_only(const MatvecArgs& a, int precision, hipStream_t s);
 
