@@ -107,6 +107,18 @@ def post_process(V, ctx, nb, nch, theta, phi, dtau):
 
 
 # ------------------------------------------------------------ byte model
+def fft_length(n):
+    """The library's circulant length per axis: the smallest 2^k >= 8 or
+    3 * 2^k >= 12 that is >= 2n - 1."""
+    need = max(8, 2 * n - 1)
+    p2, p3 = 8, 12
+    while p2 < need:
+        p2 *= 2
+    while p3 < need:
+        p3 *= 2
+    return min(p2, p3)
+
+
 def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None):
     """Algorithmic HBM bytes of one right-hand-side execution of a pass
     (spectrum excluded; it is charged once per launch).  nb: body voxels when
@@ -230,7 +242,7 @@ def matvec_mode(args):
     bodies, _ = make_workload(1, 1, args.grid)
     eps, h, o, g = bodies[0]
     N = g.n
-    P = tuple(max(8, 1 << int(np.ceil(np.log2(2 * v - 1)))) for v in N)
+    P = tuple(fft_length(v) for v in N)
     Q = tuple(p // 2 + 1 for p in P)
     prec = V.VIE_MIXED if args.precision == "fp32" else V.VIE_FP64
     ctx = V.vie_setup([(eps, h, o)], V.make_options(K0, flags=V.VIE_FLAG_TIMING))
@@ -479,7 +491,7 @@ def main():
     torch.cuda.set_device(0)
     V.lib()
     N = bodies[0][3].n
-    P = tuple(max(8, 1 << int(np.ceil(np.log2(2 * v - 1)))) for v in N)
+    P = tuple(fft_length(v) for v in N)
     Q = tuple(p // 2 + 1 for p in P)
     nb, nch = args.bodies, args.channels
     psi, theta, phi = detector_scan()

@@ -49,10 +49,16 @@ struct DevBuf {
   }
 };
 
-int pow2_at_least(int v) {
-  int p = 1;
-  while (p < v) p <<= 1;
-  return p;
+// Circulant length of an axis with n voxels: the smallest supported FFT
+// length (2^k >= 8, or 3 * 2^k >= 12) that holds every displacement,
+// P >= 2n - 1.
+int fft_length(int n) {
+  const int need = std::max(8, 2 * n - 1);
+  int p2 = 8;
+  while (p2 < need) p2 <<= 1;
+  int p3 = 12;
+  while (p3 < need) p3 <<= 1;
+  return std::min(p2, p3);
 }
 
 struct BodyRec {
@@ -306,7 +312,7 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
       G->h = B.h;
       for (int a = 0; a < 3; ++a) {
         G->g.N[a] = B.n[a];
-        G->g.P[a] = std::max(8, pow2_at_least(2 * B.n[a] - 1));
+        G->g.P[a] = fft_length(B.n[a]);
         G->g.Q[a] = G->g.P[a] / 2 + 1;
       }
       G->g.n = (int64_t)B.n[0] * B.n[1] * B.n[2];

@@ -27,7 +27,7 @@ struct LdsLine {
 // W_{NS RAD}^{r k} = tw[r k P / (NS RAD)].
 template <int P, int E, int NS>
 constexpr int tw_count() {
-  constexpr int RAD = (P / NS < E) ? P / NS : E;
+  constexpr int RAD = fft_radix<P, E, NS>();
   constexpr int here = (NS == 1) ? 0 : (E / RAD) * (RAD - 1);
   if constexpr (NS * RAD == P)
     return here;
@@ -37,7 +37,7 @@ constexpr int tw_count() {
 
 template <typename T, int P, int E, int NS, int OFF>
 __device__ __forceinline__ void tw_load(cpx<T>* w, int t, const cpx<T>* __restrict__ tw) {
-  constexpr int RAD = (P / NS < E) ? P / NS : E;
+  constexpr int RAD = fft_radix<P, E, NS>();
   constexpr int NB = E / RAD, TT = P / E;
   constexpr int here = (NS == 1) ? 0 : NB * (RAD - 1);
   if constexpr (NS != 1) {
@@ -66,7 +66,7 @@ struct TwReg {
 template <typename T, int P, int E, int NS, bool INV, int OFF, bool HIN = false, bool HOUT = false>
 __device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int t,
                                              const cpx<T>* __restrict__ w) {
-  constexpr int RAD = (P / NS < E) ? P / NS : E;
+  constexpr int RAD = fft_radix<P, E, NS>();
   constexpr int NB = E / RAD;
   constexpr int TT = P / E;
   constexpr bool FIRST = (NS == 1);
@@ -167,19 +167,26 @@ __device__ __forceinline__ void block_sum2(c64& a, c64& b, double* red) {
 
 template <typename T>
 constexpr int lines_per_block(int P) {
-  return nt_lines<T>() / (P < 16 ? 1 : P / 16);
+  return nt_lines<T>() / (P / fft_e_of(P));
 }
 
-#define VIE_DISPATCH_P(P_, CALL)                 \
-  switch (P_) {                                  \
+// Supported line lengths: 2^k (8..512) and 3 * 2^k (12..384).
+#define VIE_DISPATCH_P(P_, CALL)                       \
+  switch (P_) {                                        \
     case 8: { constexpr int PP = 8; CALL; break; }     \
+    case 12: { constexpr int PP = 12; CALL; break; }   \
     case 16: { constexpr int PP = 16; CALL; break; }   \
+    case 24: { constexpr int PP = 24; CALL; break; }   \
     case 32: { constexpr int PP = 32; CALL; break; }   \
+    case 48: { constexpr int PP = 48; CALL; break; }   \
     case 64: { constexpr int PP = 64; CALL; break; }   \
+    case 96: { constexpr int PP = 96; CALL; break; }   \
     case 128: { constexpr int PP = 128; CALL; break; } \
+    case 192: { constexpr int PP = 192; CALL; break; } \
     case 256: { constexpr int PP = 256; CALL; break; } \
+    case 384: { constexpr int PP = 384; CALL; break; } \
     case 512: { constexpr int PP = 512; CALL; break; } \
-    default: return hipErrorInvalidValue;        \
+    default: return hipErrorInvalidValue;              \
   }
 
 

@@ -146,9 +146,12 @@ constexpr ZShape zshape(int v) {
 // FP32 has a fourth shape (16 points per thread at three waves per SIMD, a few
 // registers spilled); FP64 would spill too much for it.
 static constexpr int kZVariants32 = 4, kZVariants64 = 3;
+// Points per thread of a z shape: E0 (capped at P) for P = 2^k; for
+// P = 3 * 2^k, 12 (or 6 for the small shapes, which keeps the LDS of the
+// 512-thread shapes within 64 KB).
 template <int P, int E0>
 constexpr int zcap() {
-  return E0 < P ? E0 : P;
+  return (P % 3 == 0) ? (E0 >= 8 ? 12 : 6) : (E0 < P ? E0 : P);
 }
 
 struct ZArgs {

@@ -225,10 +225,13 @@ def test_error_paths(V):
         V.vie_destroy(ctx)
 
 
-@pytest.mark.parametrize("n,rows", [((64, 64, 64), 48), ((128, 128, 128), 24)])
+@pytest.mark.parametrize("n,rows", [((64, 64, 64), 48), ((128, 128, 128), 24), ((48, 48, 48), 32),
+                                    ((96, 96, 96), 24), ((256, 256, 48), 16)])
 def test_matvec_sampled_rows_large(V, n, rows):
     """Full-size grids: sampled rows of the FP64/FP32 product against the
-    oracle's O(M)-per-row direct sum (x supported on a metasurface-like body)."""
+    oracle's O(M)-per-row direct sum (x supported on a metasurface-like body).
+    FFT lengths: 128, 256 (2^k); 96, 192 (3 x 2^k); 512 x 512 x 96 (the
+    256 x 256 x 48 metasurface grid, mixed)."""
     rng = np.random.default_rng(n[0])
     h = 1.0 / 32
     g = Grid.centred(n, h)
