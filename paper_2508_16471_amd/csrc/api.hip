@@ -1110,9 +1110,9 @@ extern "C" int vie_farfield(vie_ctx* ctx, int32_t body, const double* theta, con
     G.far[B.slot] = std::move(fr);
   }
   const Group::Far& fr = *G.far[B.slot];
-  const int ks = far_split(fr.fb.ntiles, ndir);
+  const int ks = far_split_total(fr.fb, ndir);
   VIE_HIP(G.dirs.reserve(dirs.size() * sizeof(double)));
-  VIE_HIP(G.part.reserve((size_t)ks * 2 * ndir * 3 * sizeof(c64)));
+  VIE_HIP(G.part.reserve((size_t)ks * ndir * 3 * sizeof(c64)));
   VIE_HIP(G.wd.reserve(far_pack_elems(fr.fb.ntiles) * sizeof(c64)));
   VIE_HIP(G.F.reserve(outn * sizeof(c64)));
   VIE_HIP(hipMemcpyAsync(G.dirs.p, dirs.data(), dirs.size() * sizeof(double),

@@ -34,65 +34,115 @@ static constexpr int FF_DIRS = 16 * FF_WAVES;
 static constexpr int FF_TILE = FF_QC * FF_BS * FF_TB;  // c64 per packed tile
 
 // ------------------------------------------------------------ host: blocks
+namespace {
+const int kShapes[][3] = {{16, 1, 1}, {8, 2, 1}, {4, 4, 1}, {4, 2, 2}, {2, 4, 2},
+                          {2, 2, 4}, {1, 4, 4}, {2, 8, 1}, {1, 16, 1}, {1, 1, 16}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+struct VoxIJK {
+  int i, j, z;
+};
+}  // namespace
+
 void far_blocks_build(const int* vox, int nb, const int N[3], FarBlocks& fb) {
-  static const int shapes[][3] = {{16, 1, 1}, {8, 2, 1}, {4, 4, 1}, {4, 2, 2}, {2, 4, 2},
-                                  {2, 2, 4}, {1, 4, 4}, {2, 8, 1}, {1, 16, 1}, {1, 1, 16}};
-  int best = 0;
-  int64_t best_cnt = -1;
-  std::vector<uint8_t> mark;
-  for (int s = 0; s < (int)(sizeof(shapes) / sizeof(shapes[0])); ++s) {
-    const int bx = shapes[s][0], by = shapes[s][1], bz = shapes[s][2];
-    const int gx = (N[0] + bx - 1) / bx, gy = (N[1] + by - 1) / by, gz = (N[2] + bz - 1) / bz;
-    mark.assign((size_t)gx * gy * gz, 0);
-    int64_t cnt = 0;
-    for (int k = 0; k < nb; ++k) {
-      const int lin = vox[k];
-      const int i = lin % N[0], j = (lin / N[0]) % N[1], z = lin / (N[0] * N[1]);
-      const size_t key = ((size_t)(z / bz) * gy + j / by) * gx + i / bx;
-      if (!mark[key]) {
-        mark[key] = 1;
-        ++cnt;
-      }
-    }
-    if (best_cnt < 0 || cnt < best_cnt) {
-      best_cnt = cnt;
-      best = s;
-    }
-  }
-  const int bx = shapes[best][0], by = shapes[best][1], bz = shapes[best][2];
-  fb.shape[0] = bx;
-  fb.shape[1] = by;
-  fb.shape[2] = bz;
-  const int gx = (N[0] + bx - 1) / bx, gy = (N[1] + by - 1) / by, gz = (N[2] + bz - 1) / bz;
-  // number the non-empty blocks in (z, y, x) block order
-  std::vector<int> id((size_t)gx * gy * gz, -1);
+  std::vector<VoxIJK> p(nb);
   for (int k = 0; k < nb; ++k) {
     const int lin = vox[k];
-    const int i = lin % N[0], j = (lin / N[0]) % N[1], z = lin / (N[0] * N[1]);
-    id[((size_t)(z / bz) * gy + j / by) * gx + i / bx] = 0;
+    p[k] = {lin % N[0], (lin / N[0]) % N[1], lin / (N[0] * N[1])};
   }
-  int nblk = 0;
+  // blocks per band of H z layers for every shape with bz dividing H
+  // (aligned blocks of such shapes never cross a band boundary)
+  auto count_bands = [&](int H, std::vector<std::vector<int64_t>>& cnt) {
+    const int nbands = (N[2] + H - 1) / H;
+    cnt.assign(kNumShapes, std::vector<int64_t>(nbands, -1));
+    std::vector<uint8_t> mark;
+    for (int s = 0; s < kNumShapes; ++s) {
+      const int bx = kShapes[s][0], by = kShapes[s][1], bz = kShapes[s][2];
+      if (H % bz) continue;
+      const int gx = (N[0] + bx - 1) / bx, gy = (N[1] + by - 1) / by, gz = (N[2] + bz - 1) / bz;
+      mark.assign((size_t)gx * gy * gz, 0);
+      std::fill(cnt[s].begin(), cnt[s].end(), 0);
+      for (const VoxIJK& v : p) {
+        const size_t key = ((size_t)(v.z / bz) * gy + v.j / by) * gx + v.i / bx;
+        if (!mark[key]) {
+          mark[key] = 1;
+          ++cnt[s][v.z / H];
+        }
+      }
+    }
+    return nbands;
+  };
+  // pick the band height (4 or 16 layers) and per-band shape with the fewest blocks
+  int bestH = 16;
+  std::vector<int> best_choice;
+  int64_t best_total = -1;
+  for (int H : {4, 16}) {
+    std::vector<std::vector<int64_t>> cnt;
+    const int nbands = count_bands(H, cnt);
+    std::vector<int> choice(nbands, 0);
+    int64_t total = 0;
+    for (int band = 0; band < nbands; ++band) {
+      int64_t bc = -1;
+      for (int s = 0; s < kNumShapes; ++s)
+        if (cnt[s][band] >= 0 && (bc < 0 || cnt[s][band] < bc)) {
+          bc = cnt[s][band];
+          choice[band] = s;
+        }
+      total += bc;
+    }
+    if (best_total < 0 || total < best_total) {
+      best_total = total;
+      bestH = H;
+      best_choice = choice;
+    }
+  }
+  // one group per shape in use; blocks numbered in (z, y, x) block order
+  fb.groups.clear();
   fb.org.clear();
-  for (int zb = 0; zb < gz; ++zb)
-    for (int yb = 0; yb < gy; ++yb)
-      for (int xb = 0; xb < gx; ++xb) {
-        int& e = id[((size_t)zb * gy + yb) * gx + xb];
-        if (e < 0) continue;
-        e = nblk++;
-        fb.org.insert(fb.org.end(), {xb * bx, yb * by, zb * bz, 0});
-      }
-  fb.nblk = nblk;
-  const int padded = (nblk + FF_TB - 1) / FF_TB * FF_TB;
-  fb.org.resize((size_t)padded * 4, 0);
-  fb.vi.assign((size_t)padded * FF_BS, -1);
-  for (int k = 0; k < nb; ++k) {
-    const int lin = vox[k];
-    const int i = lin % N[0], j = (lin / N[0]) % N[1], z = lin / (N[0] * N[1]);
-    const int b = id[((size_t)(z / bz) * gy + j / by) * gx + i / bx];
-    const int u = i % bx + bx * (j % by + by * (z % bz));
-    fb.vi[(size_t)b * FF_BS + u] = k;
+  fb.vi.clear();
+  fb.nblk = 0;
+  int tiles = 0;
+  for (int s = 0; s < kNumShapes; ++s) {
+    bool used = false;
+    for (int c : best_choice) used |= (c == s);
+    if (!used) continue;
+    const int bx = kShapes[s][0], by = kShapes[s][1], bz = kShapes[s][2];
+    const int gx = (N[0] + bx - 1) / bx, gy = (N[1] + by - 1) / by, gz = (N[2] + bz - 1) / bz;
+    std::vector<int> id((size_t)gx * gy * gz, -1);
+    for (const VoxIJK& v : p)
+      if (best_choice[v.z / bestH] == s) id[((size_t)(v.z / bz) * gy + v.j / by) * gx + v.i / bx] = 0;
+    const size_t base = fb.org.size() / 4;
+    int nblk = 0;
+    for (int zb = 0; zb < gz; ++zb)
+      for (int yb = 0; yb < gy; ++yb)
+        for (int xb = 0; xb < gx; ++xb) {
+          int& e = id[((size_t)zb * gy + yb) * gx + xb];
+          if (e < 0) continue;
+          e = nblk++;
+          fb.org.insert(fb.org.end(), {xb * bx, yb * by, zb * bz, 0});
+        }
+    if (nblk == 0) continue;  // a shape chosen only for empty bands
+    const int padded = (nblk + FF_TB - 1) / FF_TB * FF_TB;
+    fb.org.resize((base + padded) * 4, 0);
+    fb.vi.resize((base + padded) * FF_BS, -1);
+    for (int k = 0; k < nb; ++k) {
+      const VoxIJK& v = p[k];
+      if (best_choice[v.z / bestH] != s) continue;
+      const int b = id[((size_t)(v.z / bz) * gy + v.j / by) * gx + v.i / bx];
+      const int u = v.i % bx + bx * (v.j % by + by * (v.z % bz));
+      fb.vi[(base + b) * FF_BS + u] = k;
+    }
+    FarGroup gr;
+    gr.shape[0] = bx;
+    gr.shape[1] = by;
+    gr.shape[2] = bz;
+    gr.tile0 = tiles;
+    gr.ntiles = padded / FF_TB;
+    fb.groups.push_back(gr);
+    tiles += gr.ntiles;
+    fb.nblk += nblk;
   }
-  fb.ntiles = padded / FF_TB;
+  fb.ntiles = tiles;
 }
 
 // ------------------------------------------------------------ kernels
@@ -377,12 +427,19 @@ __global__ void k_farfield_project(const c64* __restrict__ part, int ksplit, int
   F[(int64_t)e * 2 + 1] = scale * fp;
 }
 
-int far_split(int ntiles, int nd) {
+static int far_split(int ntiles, int nd) {
+  if (ntiles <= 0) return 0;
   const int dblocks = (nd + FF_DIRS - 1) / FF_DIRS;
   const int want = std::max(1, 1024 / dblocks);
   const int ks = std::min(ntiles, want);
   const int tps = (ntiles + ks - 1) / ks;
   return (ntiles + tps - 1) / tps;
+}
+
+int far_split_total(const FarBlocks& fb, int nd) {
+  int ks = 0;
+  for (const FarGroup& gr : fb.groups) ks += far_split(gr.ntiles, nd);
+  return ks;
 }
 
 size_t far_pack_elems(int ntiles) { return (size_t)ntiles * FF_TILE; }
@@ -393,16 +450,13 @@ hipError_t launch_farfield_mfma(const c64* w, const int64_t* roff_host, int nr, 
                                 const double* origin, c64* Wd, c64* part, c64* F,
                                 hipStream_t s) {
   const int ntiles = fb.ntiles;
-  const int ks = far_split(ntiles, nd);
-  const int tps = (ntiles + ks - 1) / ks;
+  const int kst = far_split_total(fb, nd);
   FfGeom fg;
   fg.k0 = k0;
   fg.h = h;
   fg.o[0] = origin[0];
   fg.o[1] = origin[1];
   fg.o[2] = origin[2];
-  fg.bx = fb.shape[0];
-  fg.by = fb.shape[1];
   const double scale = k0 * k0 * h * h * h / (4.0 * M_PI);
   for (int q0 = 0; q0 < nr; q0 += FF_RB) {
     const int nq = std::min(FF_RB, nr - q0);
@@ -412,12 +466,23 @@ hipError_t launch_farfield_mfma(const c64* w, const int64_t* roff_host, int nr, 
     k_ff_pack<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(w, ro, nq, nb, blk_vi, ntiles, Wd);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 grid((nd + FF_DIRS - 1) / FF_DIRS, ks);
-    k_ff_mfma<<<grid, FF_DIRS * 4, 0, s>>>(Wd, (const int4*)blk_org, ntiles, tps, dirs, nd, fg,
-                                           nq, part);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_farfield_project<<<(nq * nd + 255) / 256, 256, 0, s>>>(part, ks, nq, nd, dirs, scale,
+    // one launch per block shape; each writes its own range of K-split partials
+    int ks0 = 0;
+    for (const FarGroup& gr : fb.groups) {
+      const int ks = far_split(gr.ntiles, nd);
+      if (ks == 0) continue;
+      const int tps = (gr.ntiles + ks - 1) / ks;
+      fg.bx = gr.shape[0];
+      fg.by = gr.shape[1];
+      dim3 grid((nd + FF_DIRS - 1) / FF_DIRS, ks);
+      k_ff_mfma<<<grid, FF_DIRS * 4, 0, s>>>(
+          Wd + (int64_t)gr.tile0 * FF_TILE, (const int4*)blk_org + (int64_t)gr.tile0 * FF_TB,
+          gr.ntiles, tps, dirs, nd, fg, nq, part + (int64_t)ks0 * nq * nd * 3);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      ks0 += ks;
+    }
+    k_farfield_project<<<(nq * nd + 255) / 256, 256, 0, s>>>(part, kst, nq, nd, dirs, scale,
                                                               F + (int64_t)q0 * nd * 2);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

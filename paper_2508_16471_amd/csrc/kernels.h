@@ -132,22 +132,27 @@ hipError_t launch_finalize(int which, int nrhs, int nblk, const c64* partials, K
 hipError_t launch_axpy_real(int64_t n, double a, const c64* x, c64* y, hipStream_t s);
 
 // Far field (eq. 25) on FP64 MFMA.  The body voxels are grouped into aligned
-// blocks of 16 voxels (shape bx x by x bz, picked per body to minimise empty
-// slots); blocks are padded to whole tiles of 16.
+// blocks of 16 voxels.  The block shape (bx x by x bz) is chosen per band of
+// z layers to minimise empty slots (a slab and the fins on it want different
+// shapes); bands with the same shape form one group of whole tiles of 16.
+struct FarGroup {
+  int shape[3];
+  int tile0, ntiles;
+};
 struct FarBlocks {
-  int shape[3] = {16, 1, 1};
+  std::vector<FarGroup> groups;
   int nblk = 0, ntiles = 0;
   std::vector<int> org;  // [ntiles*16][4] block origin (i, j, k, 0) in voxels
   std::vector<int> vi;   // [ntiles*16][16] compressed voxel index at offset u, -1 empty
 };
 void far_blocks_build(const int* vox, int nb, const int N[3], FarBlocks& fb);
-// K-split count and packed-operand size (c64) for a launch.
-int far_split(int ntiles, int nd);
+// Total K-split count over the groups, and packed-operand size (c64).
+int far_split_total(const FarBlocks& fb, int nd);
 size_t far_pack_elems(int ntiles);
 // F[rhs][dir][2] = (F_theta, F_phi) for nr right-hand sides of one body; w
 // body-compressed with per-rhs offsets roff (host values), blk_vi / blk_org the
 // device copies of fb.vi / fb.org; dirs[nd][9] = (r, theta-hat, phi-hat).
-// Scratch: Wd far_pack_elems(ntiles) c64, part far_split(..)*min(nr,2)*nd*3 c64.
+// Scratch: Wd far_pack_elems(ntiles) c64, part far_split_total(..)*nd*3 c64.
 hipError_t launch_farfield_mfma(const c64* w, const int64_t* roff_host, int nr, int nb,
                                 const FarBlocks& fb, const int* blk_vi, const int* blk_org,
                                 const double* dirs, int nd, double k0, double h,
