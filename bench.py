@@ -466,6 +466,28 @@ def uneven_mode(args):
                                     "p99": float(np.percentile(lat, 99))},
                       "iters_mean": float(np.mean(iters)), "groups": groups}
         print(json.dumps({label: out[label]}), file=sys.stderr, flush=True)
+    # launch-bound case: one 16^3 sphere (r = lambda/2, eps 2.25), one channel
+    g = Grid.centred(16, 1.0 / 16)
+    from synth import sphere
+
+    body = [(sphere(g, 0.5, 2.25), g.h, g.origin)]
+    small = {}
+    for label, flags in (("graph", 0), ("eager", V.VIE_FLAG_NO_GRAPH)):
+        ctx = V.vie_setup(body, V.make_options(K0, precision=V.VIE_FP64, tol=1e-8, max_iter=5000,
+                                               flags=flags))
+        try:
+            V.vie_solve(ctx, [((0, 0, 1.0), (1.0, 0, 0))], [1])
+            ts = []
+            for _ in range(20):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st = V.vie_solve(ctx, [((0, 0, 1.0), (1.0, 0, 0))], [1])
+                ts.append(time.perf_counter() - t0)
+        finally:
+            V.vie_destroy(ctx)
+        small[label] = {"median_ms": float(np.median(ts)) * 1e3, "iters": st[0]["iters"]}
+    out["small_single_solve"] = {"workload": "16^3 sphere r=0.5, eps 2.25, 1 channel, FP64, tol 1e-8",
+                                 **small}
     print(json.dumps(out))
 
 

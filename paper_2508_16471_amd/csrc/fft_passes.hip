@@ -131,24 +131,16 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_strided(
 // W = NT E / P columns per workgroup; LDS = W padded lines.
 struct ZShape {
   int e, nt;
-  bool occ3;  // register budget capped for three waves per SIMD
 };
 template <typename T>
 constexpr ZShape zshape(int v) {
-  // FP32: 3 x 16 complex in registers / 3 x 8; FP64: 3 x 8 / 3 x 4
-  return sizeof(T) == 4
-             ? (v == 0 ? ZShape{16, 256, false}
-                       : v == 1 ? ZShape{8, 512, false}
-                                : v == 2 ? ZShape{8, 256, false} : ZShape{16, 256, true})
-             : (v == 0 ? ZShape{8, 256, false}
-                       : v == 1 ? ZShape{4, 512, false} : ZShape{4, 256, false});
+  // FP32: 3 x 16 complex in registers / 3 x 8; FP64: 3 x 8 / 3 x 4.  Every
+  // shape keeps W = NT E / P >= 16 (FP32) or 8 (FP64) columns per workgroup,
+  // so each row access is a full 128-byte run.
+  return sizeof(T) == 4 ? (v == 0 ? ZShape{16, 256} : ZShape{8, 512})
+                        : (v == 0 ? ZShape{8, 256} : ZShape{4, 512});
 }
-// FP32 has a fourth shape (16 points per thread at three waves per SIMD, a few
-// registers spilled); FP64 would spill too much for it.
-static constexpr int kZVariants32 = 4, kZVariants64 = 3;
-// Points per thread of a z shape: E0 (capped at P) for P = 2^k; for
-// P = 3 * 2^k, 12 (or 6 for the small shapes, which keeps the LDS of the
-// 512-thread shapes within 64 KB).
+static constexpr int kZVariants = 2;
 template <int P, int E0>
 constexpr int zcap() {
   return (P % 3 == 0) ? (E0 >= 8 ? 12 : 6) : (E0 < P ? E0 : P);
@@ -283,12 +275,6 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
 
 template <typename T, int P, int E, int NT, bool FAST>
 __global__ __launch_bounds__(NT) void k_fft_z_green(
-    cpx<T>* __restrict__ B, const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw,
-    ZArgs a, const int* __restrict__ active) {
-  z_green_body<T, P, E, NT, FAST>(B, spec, tw, a, active);
-}
-template <typename T, int P, int E, int NT, bool FAST>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_fft_z_green_o3(
     cpx<T>* __restrict__ B, const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw,
     ZArgs a, const int* __restrict__ active) {
   z_green_body<T, P, E, NT, FAST>(B, spec, tw, a, active);
@@ -459,23 +445,13 @@ static void z_launch(const GroupGeom& g, ZArgs a, cpx<T>* B, const cpx<T>* spec,
   constexpr int W = sh.nt / (PP / E);
   a.tiles_x = (g.P[0] + W - 1) / W;
   const dim3 grid((g.P[1] / 2 + 1) * 2 * a.tiles_x * g.nrhs);
-  if constexpr (sh.occ3) {
-    if constexpr (PP >= 32) {
-      if (a.zl == 16 && 2 * a.N3 == PP) {
-        k_fft_z_green_o3<T, PP, E, sh.nt, true><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
-        return;
-      }
+  if constexpr (PP >= 32) {
+    if (a.zl == 16 && 2 * a.N3 == PP) {
+      k_fft_z_green<T, PP, E, sh.nt, true><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
+      return;
     }
-    k_fft_z_green_o3<T, PP, E, sh.nt, false><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
-  } else {
-    if constexpr (PP >= 32) {
-      if (a.zl == 16 && 2 * a.N3 == PP) {
-        k_fft_z_green<T, PP, E, sh.nt, true><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
-        return;
-      }
-    }
-    k_fft_z_green<T, PP, E, sh.nt, false><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
   }
+  k_fft_z_green<T, PP, E, sh.nt, false><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
 }
 
 template <typename T>
@@ -498,13 +474,6 @@ static hipError_t z_pass(const GroupGeom& g, cpx<T>* B, const cpx<T>* spec, cons
   VIE_DISPATCH_P(g.P[2], ({
                    switch (variant) {
                      case 1: z_launch<T, PP, 1>(g, a, B, spec, tw, active, s); break;
-                     case 2: z_launch<T, PP, 2>(g, a, B, spec, tw, active, s); break;
-                     case 3:
-                       if constexpr (sizeof(T) == 4) {
-                         z_launch<T, PP, 3>(g, a, B, spec, tw, active, s);
-                         break;
-                       }
-                       [[fallthrough]];
                      default: z_launch<T, PP, 0>(g, a, B, spec, tw, active, s); break;
                    }
                  }));
@@ -587,7 +556,7 @@ static hipError_t matvec_t(const MatvecArgs& m, const c64* x, c64* y, EpiArgs& e
   return hipSuccess;
 }
 
-int z_variants(int precision) { return precision == 0 ? kZVariants64 : kZVariants32; }
+int z_variants(int) { return kZVariants; }
 
 hipError_t launch_z_only(const MatvecArgs& m, int precision, hipStream_t s) {
   const GroupGeom& g = *m.g;

@@ -256,7 +256,7 @@ def test_matvec_sampled_rows_large(V, n, rows):
     assert _relerr(y32, ref) < 5e-6
 
 
-@pytest.mark.parametrize("zvar", [0, 1, 2, 3])
+@pytest.mark.parametrize("zvar", [0, 1])
 @pytest.mark.parametrize("n", [(64, 64, 64), (24, 20, 17)])
 def test_every_z_pass_shape_matches_oracle(V, zvar, n):
     """Each fused z-pass shape the autotuner may pick (forced through
