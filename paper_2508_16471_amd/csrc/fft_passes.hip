@@ -176,8 +176,32 @@ __device__ __forceinline__ void load_g6(const cpx<T>* __restrict__ sp, cpx<T> (&
   }
 }
 
-// FAST: the z block is 16 and N3 = P/2 (every stored z is a body row), so the
-// blocked offsets are shifts and no row needs a bounds test.
+// FP32 column pairs: lanes 2i (column c) and 2i+1 (column c+1) of one row
+// of threads move 16-byte row segments [c, c+1] -- the even lane the row of
+// its point 2k, the odd lane the row of its point 2k+1 -- and one lane swap
+// hands each lane its own column's two points.  Half the memory
+// instructions of one 8-byte access per point.
+__device__ __forceinline__ float swap_pair(float x) {
+  // lanes 2i <-> 2i+1 (DPP quad_perm [1,0,3,2])
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ void pair_in(const float4 f, int odd, cpx<float>& a, cpx<float>& b) {
+  const float sr = odd ? f.x : f.z, si = odd ? f.y : f.w;  // the partner's point
+  const float kr = odd ? f.z : f.x, ki = odd ? f.w : f.y;  // this lane's point
+  const float rr = swap_pair(sr), ri = swap_pair(si);
+  a = odd ? mk<float>(rr, ri) : mk<float>(kr, ki);
+  b = odd ? mk<float>(kr, ki) : mk<float>(rr, ri);
+}
+__device__ __forceinline__ float4 pair_out(int odd, const cpx<float>& a, const cpx<float>& b) {
+  const cpx<float> sd = odd ? a : b;
+  const float rr = swap_pair(sd.re), ri = swap_pair(sd.im);
+  const cpx<float> own = odd ? b : a;
+  return odd ? make_float4(rr, ri, own.re, own.im) : make_float4(own.re, own.im, rr, ri);
+}
+
+// FAST: the z block is 16, N3 = P/2 (every stored z is a body row) and the
+// column tiles cover P1 exactly, so the blocked offsets are shifts and no row
+// or column needs a bounds test.
 template <typename T, int P, int E, int NT, bool FAST>
 __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
                                              const cpx<T>* __restrict__ spec,
@@ -200,7 +224,11 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
   if (active && !active[rhs]) return;
   const int cw = threadIdx.x % W, t = threadIdx.x / W;
   const int xx = tile * W + cw;
-  const bool valid = xx < a.P1;
+  // FP32 with shift addressing, 16 points per thread: rows move as 16-byte
+  // column-pair segments; every column of such a launch is valid (FAST
+  // launches need P1 % W == 0)
+  constexpr bool PAIR = FAST && sizeof(T) == 4 && E == 16;
+  const bool valid = PAIR || xx < a.P1;
   // B[rhs][comp][z / zl][xi_y][z % zl][xi_x]; offsets within one right-hand
   // side fit in 32 bits (3 N3 P2 P1 < 2^31 for P <= 512)
   cpx<T>* col = B + rhs * a.rhs_stride + (int64_t)xy * a.zl * a.P1 + (valid ? xx : 0);
@@ -216,26 +244,53 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
   }
   TwReg<T, P, E> tr;
   tr.load(t, tw);
+  const int odd = cw & 1;
   cpx<T> v0[E], v1[E], v2[E];
+  if constexpr (PAIR) {
+    const float* cp = reinterpret_cast<const float*>(col - odd);
 #pragma unroll
-  for (int q = 0; q < E; ++q) {
-    const int z = t + q * TT;
-    if (q < E / 2 && valid && (FAST || z < a.N3)) {
-      v0[q] = col[zoff[q]];
-      v1[q] = col[cs + zoff[q]];
-      v2[q] = col[2 * cs + zoff[q]];
-    } else {
-      v0[q] = v1[q] = v2[q] = mk<T>(0, 0);
+    for (int k = 0; k < E / 4; ++k) {
+      const int zr = t + (2 * k + odd) * TT;  // this lane's row: point 2k (even) or 2k+1 (odd)
+      const int off = 2 * ((zr >> 4) * (int)a.zhs + (zr & 15) * (int)a.zls);
+      pair_in(*reinterpret_cast<const float4*>(cp + off), odd, v0[2 * k], v0[2 * k + 1]);
+      pair_in(*reinterpret_cast<const float4*>(cp + 2 * cs + off), odd, v1[2 * k], v1[2 * k + 1]);
+      pair_in(*reinterpret_cast<const float4*>(cp + 4 * cs + off), odd, v2[2 * k], v2[2 * k + 1]);
+    }
+#pragma unroll
+    for (int q = E / 2; q < E; ++q) v0[q] = v1[q] = v2[q] = mk<T>(0, 0);
+  } else {
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int z = t + q * TT;
+      if (q < E / 2 && valid && (FAST || z < a.N3)) {
+        v0[q] = col[zoff[q]];
+        v1[q] = col[cs + zoff[q]];
+        v2[q] = col[2 * cs + zoff[q]];
+      } else {
+        v0[q] = v1[q] = v2[q] = mk<T>(0, 0);
+      }
     }
   }
   cpx<T>* line = lds + cw * LS;
   // z < N3 <= P/2: the upper half of every line is zero padding
   line_fft_e<T, P, E, false, true, false>(v0, line, t, tr);
   line_fft_e<T, P, E, false, true, false>(v1, line, t, tr);
-  line_fft_e<T, P, E, false, true, false>(v2, line, t, tr);
   // octant coordinates and mirror flags; spectrum layout [yo][zo][xo][ab]
   const int xm = xx > a.P1 / 2, ym = xy > a.P2 / 2;
   const int xo = xm ? a.P1 - xx : xx, yo = ym ? a.P2 - xy : xy;
+  // paired FP32 launches up to P = 256: the first ZPF spectrum records are
+  // requested before the last forward transform, so their latency overlaps it
+  constexpr int ZPF = (PAIR && P <= 256) ? 2 : 0;
+  cpx<T> gpre[ZPF > 0 ? ZPF : 1][6];
+  {
+    const cpx<T>* s0 = spec + ((int64_t)yo * a.Q3 * a.Q1 + (valid ? xo : 0)) * 6;
+#pragma unroll
+    for (int q = 0; q < ZPF; ++q) {
+      const int z = t + q * TT;
+      load_g6<T>(s0 + (z > P / 2 ? P - z : z) * 6 * a.Q1, gpre[q]);
+    }
+  }
+  line_fft_e<T, P, E, false, true, false>(v2, line, t, tr);
   const cpx<T>* sxy = spec + ((int64_t)yo * a.Q3 * a.Q1 + (valid ? xo : 0)) * 6;
   const int zstep = 6 * a.Q1;
 #pragma unroll
@@ -244,7 +299,12 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
     const int zm = z > P / 2;
     const int zo = zm ? P - z : z;
     cpx<T> gg[6];
-    load_g6<T>(sxy + zo * zstep, gg);
+    if (q < ZPF) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) gg[k] = gpre[q < ZPF ? q : 0][k];
+    } else {
+      load_g6<T>(sxy + zo * zstep, gg);
+    }
     const cpx<T> gxx = gg[0], gyy = gg[3], gzz = gg[5];
     cpx<T> gxy = gg[1], gxz = gg[2], gyz = gg[4];
     // G_ab is odd along axis e iff exactly one of a, b equals e
@@ -260,6 +320,18 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
   line_fft_e<T, P, E, true, false, true>(v0, line, t, tr);
   line_fft_e<T, P, E, true, false, true>(v1, line, t, tr);
   line_fft_e<T, P, E, true, false, true>(v2, line, t, tr);
+  if constexpr (PAIR) {
+    float* cp = reinterpret_cast<float*>(col - odd);
+#pragma unroll
+    for (int k = 0; k < E / 4; ++k) {
+      const int zr = t + (2 * k + odd) * TT;
+      const int off = 2 * ((zr >> 4) * (int)a.zhs + (zr & 15) * (int)a.zls);
+      *reinterpret_cast<float4*>(cp + off) = pair_out(odd, v0[2 * k], v0[2 * k + 1]);
+      *reinterpret_cast<float4*>(cp + 2 * cs + off) = pair_out(odd, v1[2 * k], v1[2 * k + 1]);
+      *reinterpret_cast<float4*>(cp + 4 * cs + off) = pair_out(odd, v2[2 * k], v2[2 * k + 1]);
+    }
+    return;
+  }
   if (valid) {
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
@@ -446,7 +518,7 @@ static void z_launch(const GroupGeom& g, ZArgs a, cpx<T>* B, const cpx<T>* spec,
   a.tiles_x = (g.P[0] + W - 1) / W;
   const dim3 grid((g.P[1] / 2 + 1) * 2 * a.tiles_x * g.nrhs);
   if constexpr (PP >= 32) {
-    if (a.zl == 16 && 2 * a.N3 == PP) {
+    if (a.zl == 16 && 2 * a.N3 == PP && g.P[0] % W == 0) {
       k_fft_z_green<T, PP, E, sh.nt, true><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
       return;
     }
