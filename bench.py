@@ -57,11 +57,14 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2508_16471_amd", "weights",
                                                       "warmstart_metasurface128.npy"))
-    ap.add_argument("--mode", choices=["solve", "matvec", "farfield", "uneven"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "matvec", "farfield", "uneven", "metasurface"],
+                    default="solve",
                     help="matvec: time device-resident operator products only; farfield: "
                          "the 64,800-direction sweep of one body only (profiling); uneven: "
                          "random ellipsoid-union bodies on mixed grids, batched per grid")
     ap.add_argument("--nrhs", type=int, default=1, help="matvec mode: vectors per product")
+    ap.add_argument("--directions", type=int, default=64,
+                    help="metasurface mode: incident directions (x 2 circular polarisations)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32")
     return ap.parse_args()
 
@@ -491,13 +494,79 @@ def uneven_mode(args):
     print(json.dumps(out))
 
 
+def metasurface_mode(args):
+    """PB metasurface on the 256 x 256 x 48 grid (h = lambda/32, 8 x 8 fins of
+    eps 5.8 on an eps 2.1 slab): `directions` incident directions spread over
+    a 20 deg cap about +z, each with both circular polarisations, solved as
+    one batched call (FP32 product inside FP64 refinement, replayed graphs;
+    the call includes the one-off z-shape tuning and graph capture), then a
+    362-direction far-field scan (theta in [0, 180] deg in the phi = 0 and
+    phi = 90 deg planes) of every right-hand side."""
+    import torch
+
+    from paper_2508_16471_amd import vie as V
+    from synth import cap_directions, circular_pol_basis, pb_metasurface
+
+    torch.cuda.set_device(0)
+    V.lib()
+    g, eps = pb_metasurface()
+    chans = []
+    for k in cap_directions(args.directions, 20.0):
+        _, _, L, R = circular_pol_basis(k)
+        chans += [(k, L), (k, R)]
+    nrhs = len(chans)
+    nb = int((eps != 1.0).sum())
+    N = g.n
+    P = tuple(fft_length(v) for v in N)
+    free0 = torch.cuda.mem_get_info()[0]
+    opt = V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
+                         inner_tol=args.inner_tol)
+    t0 = time.perf_counter()
+    ctx = V.vie_setup([(eps, g.h, g.origin)], opt)
+    setup = time.perf_counter() - t0
+    print(f"metasurface: setup {setup:.2f} s, {nrhs} right-hand sides, {nb} body voxels",
+          file=sys.stderr, flush=True)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = V.vie_solve(ctx, chans, [nrhs], allow_noconv=True)
+        torch.cuda.synchronize()
+        solve_s = time.perf_counter() - t0
+        used = (free0 - torch.cuda.mem_get_info()[0]) / 1e9
+        print(f"metasurface: solve {solve_s:.2f} s rc {rc}", file=sys.stderr, flush=True)
+        th = np.deg2rad(np.linspace(0.0, 180.0, 181))
+        theta = np.concatenate([th, th])
+        phi = np.concatenate([np.zeros(181), np.full(181, np.pi / 2)])
+        V.vie_farfield(ctx, 0, theta, phi, nrhs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        V.vie_farfield(ctx, 0, theta, phi, nrhs)
+        torch.cuda.synchronize()
+        ff_s = time.perf_counter() - t0
+    finally:
+        V.vie_destroy(ctx)
+    it = [x["iters"] for x in st]
+    flops = 8.0 * theta.size * nb * 3 * nrhs
+    print(json.dumps({
+        "mode": "metasurface", "workload": "PB metasurface 256x256x48, h=lambda/32, 8x8 fins eps 5.8, "
+        "slab eps 2.1", "grid": list(N), "fft": list(P), "body_voxels": nb, "rhs": nrhs,
+        "tol": args.tol, "precision": "fp32 product + fp64 refinement", "setup_s": setup,
+        "solve_s": solve_s, "solves_per_s": nrhs / solve_s, "rc": rc,
+        "iters_mean": float(np.mean(it)), "iters_max": int(np.max(it)),
+        "all_converged": all(x["converged"] for x in st),
+        "max_rel_res": float(max(x["rel_res"] for x in st)), "device_mem_GB": used,
+        "farfield": {"directions": int(theta.size), "seconds": ff_s,
+                     "TFLOPs": flops / ff_s / 1e12}}))
+
+
 # ------------------------------------------------------------------ main
 def main():
     args = parse()
-    if args.mode in ("matvec", "farfield", "uneven"):
+    if args.mode in ("matvec", "farfield", "uneven", "metasurface"):
         if args.gpus != 1:
             sys.exit(2)
-        return {"matvec": matvec_mode, "farfield": farfield_mode, "uneven": uneven_mode}[args.mode](args)
+        return {"matvec": matvec_mode, "farfield": farfield_mode, "uneven": uneven_mode,
+                "metasurface": metasurface_mode}[args.mode](args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the path shards by "
                           "right-hand side / body (see DESIGN.md), --gpus must be 1"}))

@@ -17,6 +17,8 @@ from .geometry import (  # noqa: F401
     random_ellipsoid_body,
     metasurface_fins,
     metasurface_family,
+    pb_metasurface,
+    cap_directions,
     pb_rotation_step,
     planewave,
     random_planewave,

@@ -170,6 +170,36 @@ def metasurface_family(rng, n=128, h=1.0 / 32):
     return grid, body
 
 
+def pb_metasurface(n=(256, 256, 48), h=1.0 / 32, count=8):
+    """The benchmark Pancharatnam-Berry metasurface (lengths in wavelengths):
+    a ``count x count`` array of 0.15 x 0.4 x 0.6 fins (eps 5.8) on a lossless
+    slab 0.2 thick (eps 2.1), lateral period ``n[0] h / count``, fin rotation
+    stepped linearly through [0, pi) across x (angle pi a / count in column
+    a), slab and fins centred in z on an ``n`` grid of spacing ``h``."""
+    grid = Grid.centred(n, h)
+    fin_cells = int(round(0.6 / h))
+    slab_cells = max(1, int(round(0.2 / h)))
+    if slab_cells + fin_cells > n[2]:
+        raise ValueError("grid too thin for slab and fins")
+    z0 = (n[2] - slab_cells - fin_cells) // 2
+    ang = np.tile(np.pi * np.arange(count) / count, (count, 1))
+    body = metasurface_fins(grid, slab_eps=2.1, slab_cells=slab_cells, fin_eps=5.8, fin_len=0.4,
+                            fin_wid=0.15, fin_cells=fin_cells, period=n[0] * h / count, count=count,
+                            angles=ang, z0_cells=z0)
+    return grid, body
+
+
+def cap_directions(count, cap_deg):
+    """``count`` directions spread evenly (Fibonacci spiral in cos theta) over
+    the cap of half-angle ``cap_deg`` about +z."""
+    cmin = np.cos(np.deg2rad(cap_deg))
+    i = np.arange(count) + 0.5
+    ct = 1.0 - (1.0 - cmin) * i / count
+    ph = np.pi * (3.0 - np.sqrt(5.0)) * i
+    st = np.sqrt(1.0 - ct * ct)
+    return np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=1)
+
+
 def planewave(khat, pol):
     """Normalised plane-wave channel ``(khat[3] real, pol[3] complex)``;
     ``pol`` is projected orthogonal to ``khat`` and normalised."""
