@@ -150,6 +150,35 @@ int vie_farfield(vie_ctx *ctx, int32_t body, const double *theta, const double *
 int hom_g2(const vie_c64 T[4], const double *omega, double sigma, const double *dtau,
            int32_t ndelay, int32_t norm, double *g2, double *Nc_raw, double *Nc_norm);
 
+/* Detector with a finite aperture (the aperture-collected field operator,
+ * eq. NAfield).  Under the narrowband approximation of Sec. II the collected
+ * field of channel j is a transfer coefficient like the point detector's
+ * (eq. Eproj), averaged over the aperture:
+ *   T_NA = (1 / Omega) * integral over the cone of p . F(r) dOmega(r),
+ * with a uniform angular sensitivity W = 1 / Omega on the cone of half-angle
+ * `alpha` (radians, 0 <= alpha <= pi; Omega = 2 pi (1 - cos alpha)) about the
+ * axis direction (theta0, phi0), and a fixed detection polarisation `pol`
+ * (complex Cartesian 3-vector, taken unconjugated like c_theta, c_phi of the
+ * point detector).  F is the Cartesian far field of eq. 25.  alpha = 0 is the
+ * point detector on the axis, with c_theta = pol . theta0-hat and
+ * c_phi = pol . phi0-hat.  The g2 and coincidences of such detectors follow
+ * from hom_g2 with these coefficients. */
+typedef struct {
+  double theta0, phi0; /* cone axis */
+  double alpha;        /* cone half-angle; NA = sin(alpha) in vacuum */
+  vie_c64 pol[3];      /* detection polarisation */
+} vie_na_detector;
+
+/* T[rhs * ndet + a] for every right-hand side of `body` and every detector
+ * det[a].  Quadrature: n_rad Gauss-Legendre nodes in the cosine of the angle
+ * from the axis on [cos alpha, 1] times n_az equally spaced azimuths (exact
+ * for a single dipole with n_rad >= 2, n_az >= 3); the far field at all
+ * nodes comes from the same MFMA projection as vie_farfield.  Host arrays.
+ * VIE_EINVAL for non-finite input, alpha outside [0, pi], n_rad outside
+ * [1, 256] or n_az outside [1, 1024]; VIE_ESTATE before a solve. */
+int vie_transfer_na(vie_ctx *ctx, int32_t body, const vie_na_detector *det, int32_t ndet,
+                    int32_t n_rad, int32_t n_az, vie_c64 *T);
+
 /* Copy the solution w = chi E of (body, rhs) to host memory w[3*N1*N2*N3]. */
 int vie_get_current(vie_ctx *ctx, int32_t body, int32_t rhs, vie_c64 *w);
 

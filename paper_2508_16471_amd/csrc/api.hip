@@ -1073,25 +1073,12 @@ extern "C" int vie_get_current(vie_ctx* ctx, int32_t body, int32_t rhs, vie_c64*
 }
 
 // -------------------------------------------------------------- far field
-extern "C" int vie_farfield(vie_ctx* ctx, int32_t body, const double* theta, const double* phi,
-                            int32_t ndir, vie_c64* F) {
-  if (!ctx) return VIE_EINVAL;
-  if (ctx->poisoned) return VIE_ESTATE;
-  if (body < 0 || body >= (int)ctx->bodies.size() || ndir < 1 || !theta || !phi || !F)
-    return VIE_EINVAL;
-  BodyRec& B = *ctx->bodies[body];
-  if (B.nrhs < 1) return VIE_ESTATE;
+// Far field of every right-hand side of body B at ndir directions given as
+// (r-hat, e1, e2) triples (9 doubles each, e1 and e2 orthonormal and
+// perpendicular to r-hat): F[(rhs * ndir + d) * 2 + {0,1}] = (e1.F, e2.F).
+static int far_project(vie_ctx* ctx, BodyRec& B, const std::vector<double>& dirs, int ndir,
+                       vie_c64* F) {
   Group& G = *ctx->groups[B.group];
-  std::vector<double> dirs((size_t)ndir * 9);
-  for (int d = 0; d < ndir; ++d) {
-    const double t = theta[d], p = phi[d];
-    if (!isfinite(t) || !isfinite(p)) return VIE_EINVAL;
-    const double st = sin(t), ct = cos(t), sp = sin(p), cp = cos(p);
-    double* D = &dirs[(size_t)d * 9];
-    D[0] = st * cp; D[1] = st * sp; D[2] = ct;
-    D[3] = ct * cp; D[4] = ct * sp; D[5] = -st;
-    D[6] = -sp;     D[7] = cp;      D[8] = 0.0;
-  }
   const size_t outn = (size_t)B.nrhs * ndir * 2;
   if (B.nb == 0) {
     memset(F, 0, outn * sizeof(vie_c64));
@@ -1126,6 +1113,130 @@ extern "C" int vie_farfield(vie_ctx* ctx, int32_t body, const double* theta, con
   VIE_HIP(hipMemcpyAsync(F, G.F.p, outn * sizeof(c64), hipMemcpyDeviceToHost, ctx->stream));
   VIE_HIP(hipStreamSynchronize(ctx->stream));
   timing_collect(ctx);
+  return VIE_OK;
+}
+
+// r-hat, theta-hat, phi-hat of the direction (t, p) into D[0..8]
+static void sph_frame(double t, double p, double* D) {
+  const double st = sin(t), ct = cos(t), sp = sin(p), cp = cos(p);
+  D[0] = st * cp; D[1] = st * sp; D[2] = ct;
+  D[3] = ct * cp; D[4] = ct * sp; D[5] = -st;
+  D[6] = -sp;     D[7] = cp;      D[8] = 0.0;
+}
+
+extern "C" int vie_farfield(vie_ctx* ctx, int32_t body, const double* theta, const double* phi,
+                            int32_t ndir, vie_c64* F) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  if (body < 0 || body >= (int)ctx->bodies.size() || ndir < 1 || !theta || !phi || !F)
+    return VIE_EINVAL;
+  BodyRec& B = *ctx->bodies[body];
+  if (B.nrhs < 1) return VIE_ESTATE;
+  std::vector<double> dirs((size_t)ndir * 9);
+  for (int d = 0; d < ndir; ++d) {
+    if (!isfinite(theta[d]) || !isfinite(phi[d])) return VIE_EINVAL;
+    sph_frame(theta[d], phi[d], &dirs[(size_t)d * 9]);
+  }
+  return far_project(ctx, B, dirs, ndir, F);
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton iteration on P_n from
+// the cosine initial guess, P_n and P_n' by the three-term recurrence.
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;  // P_0, P_1
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double pn = n == 0 ? 1.0 : (n == 1 ? z : p1);
+      const double pm = n == 1 ? 1.0 : p0;  // P_{n-1}
+      dp = n * (z * pn - pm) / (z * z - 1.0);
+      const double dz = pn / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+extern "C" int vie_transfer_na(vie_ctx* ctx, int32_t body, const vie_na_detector* det,
+                               int32_t ndet, int32_t n_rad, int32_t n_az, vie_c64* T) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  if (body < 0 || body >= (int)ctx->bodies.size() || ndet < 1 || !det || !T || n_rad < 1 ||
+      n_az < 1 || n_rad > 256 || n_az > 1024)
+    return VIE_EINVAL;
+  BodyRec& B = *ctx->bodies[body];
+  if (B.nrhs < 1) return VIE_ESTATE;
+  std::vector<double> gx, gw;
+  gauss_legendre(n_rad, gx, gw);
+  // quadrature directions of every detector: (r-hat, theta-hat, phi-hat) and
+  // the weight times (p . theta-hat, p . phi-hat)
+  std::vector<double> dirs;
+  std::vector<vie_c64> cw;  // per direction: weight * p.theta-hat, weight * p.phi-hat
+  std::vector<int> first(ndet + 1, 0);
+  for (int a = 0; a < ndet; ++a) {
+    const vie_na_detector& D = det[a];
+    if (!isfinite(D.theta0) || !isfinite(D.phi0) || !(D.alpha >= 0.0) || D.alpha > M_PI)
+      return VIE_EINVAL;
+    for (int c = 0; c < 3; ++c)
+      if (!isfinite(D.pol[c].re) || !isfinite(D.pol[c].im)) return VIE_EINVAL;
+    double ax[9];
+    sph_frame(D.theta0, D.phi0, ax);  // local frame: u = r0, e1 = theta0-hat, e2 = phi0-hat
+    auto add = [&](double ca, double beta, double wt) {
+      const double sa = sqrt(fmax(0.0, 1.0 - ca * ca)), cb = cos(beta), sb = sin(beta);
+      double r[3];
+      for (int k = 0; k < 3; ++k) r[k] = ca * ax[k] + sa * (cb * ax[3 + k] + sb * ax[6 + k]);
+      const double t = acos(fmax(-1.0, fmin(1.0, r[2]))), p = atan2(r[1], r[0]);
+      double F9[9];
+      sph_frame(t, p, F9);
+      // sph_frame rebuilt r-hat from (t, p); keep the exact node direction
+      F9[0] = r[0]; F9[1] = r[1]; F9[2] = r[2];
+      dirs.insert(dirs.end(), F9, F9 + 9);
+      vie_c64 pt{0, 0}, pp{0, 0};
+      for (int k = 0; k < 3; ++k) {
+        pt.re += D.pol[k].re * F9[3 + k]; pt.im += D.pol[k].im * F9[3 + k];
+        pp.re += D.pol[k].re * F9[6 + k]; pp.im += D.pol[k].im * F9[6 + k];
+      }
+      cw.push_back({wt * pt.re, wt * pt.im});
+      cw.push_back({wt * pp.re, wt * pp.im});
+    };
+    if (D.alpha == 0.0) {
+      add(1.0, 0.0, 1.0);  // point detector on the axis
+    } else {
+      const double c0 = cos(D.alpha), omega = 2.0 * M_PI * (1.0 - c0);
+      for (int i = 0; i < n_rad; ++i) {
+        const double ca = 0.5 * (1.0 - c0) * gx[i] + 0.5 * (1.0 + c0);  // [-1,1] -> [cos alpha, 1]
+        const double wr = 0.5 * (1.0 - c0) * gw[i];
+        for (int j = 0; j < n_az; ++j)
+          add(ca, 2.0 * M_PI * (j + 0.5) / n_az, wr * (2.0 * M_PI / n_az) / omega);
+      }
+    }
+    first[a + 1] = (int)(dirs.size() / 9);
+  }
+  const int nd = first[ndet];
+  std::vector<vie_c64> F((size_t)B.nrhs * nd * 2);
+  const int rc = far_project(ctx, B, dirs, nd, F.data());
+  if (rc != VIE_OK) return rc;
+  for (int q = 0; q < B.nrhs; ++q)
+    for (int a = 0; a < ndet; ++a) {
+      double re = 0.0, im = 0.0;
+      for (int d = first[a]; d < first[a + 1]; ++d)
+        for (int k = 0; k < 2; ++k) {
+          const vie_c64 f = F[((size_t)q * nd + d) * 2 + k], c = cw[(size_t)d * 2 + k];
+          re += c.re * f.re - c.im * f.im;
+          im += c.re * f.im + c.im * f.re;
+        }
+      T[(size_t)q * ndet + a] = {re, im};
+    }
   return VIE_OK;
 }
 

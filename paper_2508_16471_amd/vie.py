@@ -41,6 +41,11 @@ class vie_planewave(C.Structure):
     _fields_ = [("khat", C.c_double * 3), ("pol", vie_c64 * 3)]
 
 
+class vie_na_detector(C.Structure):
+    _fields_ = [("theta0", C.c_double), ("phi0", C.c_double), ("alpha", C.c_double),
+                ("pol", vie_c64 * 3)]
+
+
 class vie_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("matvecs", C.c_int32), ("cycles", C.c_int32),
                 ("converged", C.c_int32), ("fallback", C.c_int32), ("warm", C.c_int32),
@@ -69,6 +74,8 @@ def lib():
             "vie_solve": (C.c_int, [C.c_void_p, P(vie_planewave), P(C.c_int32), P(vie_stats)]),
             "vie_farfield": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double),
                                        C.c_int32, P(vie_c64)]),
+            "vie_transfer_na": (C.c_int, [C.c_void_p, C.c_int32, P(vie_na_detector), C.c_int32,
+                                          C.c_int32, C.c_int32, P(vie_c64)]),
             "hom_g2": (C.c_int, [P(vie_c64), P(C.c_double), C.c_double, P(C.c_double), C.c_int32,
                                  C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double)]),
             "vie_get_current": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, P(vie_c64)]),
@@ -172,6 +179,21 @@ def vie_farfield(ctx, body, theta, phi, nrhs):
     F = np.zeros((nrhs, len(th), 2), dtype=np.complex128)
     _check(lib().vie_farfield(ctx, int(body), _dptr(th), _dptr(ph), len(th), _cptr(F)), "vie_farfield")
     return F
+
+
+def vie_transfer_na(ctx, body, detectors, nrhs, n_rad=8, n_az=16):
+    """Aperture-averaged transfer coefficients T[nrhs, ndet]; detectors: list of
+    (theta0, phi0, alpha, pol[3] complex)."""
+    arr = (vie_na_detector * max(1, len(detectors)))()
+    for i, (t0, p0, al, pol) in enumerate(detectors):
+        arr[i].theta0, arr[i].phi0, arr[i].alpha = float(t0), float(p0), float(al)
+        for a in range(3):
+            arr[i].pol[a].re = float(np.real(pol[a]))
+            arr[i].pol[a].im = float(np.imag(pol[a]))
+    T = np.zeros((nrhs, len(detectors)), dtype=np.complex128)
+    _check(lib().vie_transfer_na(ctx, int(body), arr, len(detectors), int(n_rad), int(n_az),
+                                 _cptr(T)), "vie_transfer_na")
+    return T
 
 
 def hom_g2(T, sigma=1.2, dtau=None, norm=VIE_NORM_R1, omega=None):
