@@ -378,6 +378,29 @@ def farfield_sweep(V, torch, ctx, args, chans, nch, nbv, reps=3):
             "frac_fp64_peak": flop / dev_s / 78.6e12 if dev_s > 0 else None}
 
 
+def na_detection(V, torch, ctx, nch):
+    """Finite-aperture detection on body 0: detector a (R circular, psi = -10 deg)
+    and detector b (L circular, psi = +10 deg) in the xz plane, uniform cones of
+    NA = sin(alpha) (12 x 24 quadrature nodes each), g2 of the two channels per NA."""
+    rows = []
+    for na in (0.0, 0.05, 0.1, 0.2, 0.3, 0.5):
+        al = float(np.arcsin(na))
+        dets = []
+        for psi, sgn in ((-10.0, -1.0), (10.0, 1.0)):
+            t0, p0 = np.deg2rad(abs(psi)), (np.pi if psi < 0 else 0.0)
+            th = np.array([np.cos(t0) * np.cos(p0), np.cos(t0) * np.sin(p0), -np.sin(t0)])
+            ph = np.array([-np.sin(p0), np.cos(p0), 0.0])
+            dets.append((t0, p0, al, (th + 1j * sgn * ph) / np.sqrt(2)))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        T = V.vie_transfer_na(ctx, 0, dets, nch, 12, 24)
+        sec = time.perf_counter() - t1
+        g2 = V.hom_g2((T[0, 0], T[1, 0], T[0, 1], T[1, 1]))[0] if nch >= 2 else None
+        rows.append({"NA": na, "g2": g2, "seconds": sec})
+    return {"detectors": "R at psi=-10 deg, L at psi=+10 deg, uniform cone, 12x24 nodes",
+            "body": 0, "rows": rows}
+
+
 def farfield_mode(args):
     """Solve body 0 of the workload (its channels), then time the far-field
     sweep alone (`steps` sweeps)."""
@@ -651,6 +674,7 @@ def main():
     sweep = None
     if not args.no_sweep:
         sweep = farfield_sweep(V, torch, ctx, args, chans, nch, int((bodies[0][0] != 1.0).sum()))
+    na = na_detection(V, torch, ctx, nch)
     V.vie_destroy(ctx)
     if args.calib_copy:
         calib_copy(torch)
@@ -694,6 +718,7 @@ def main():
         "speedup_vs_plain": (value / plain["solves_per_s"]) if plain else None,
         "learned": learned,
         "farfield_sweep": sweep,
+        "na_detection": na,
         "setup_s": setup_s,
     }
     print(json.dumps(line))
