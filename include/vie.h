@@ -175,7 +175,8 @@ typedef struct {
  * for a single dipole with n_rad >= 2, n_az >= 3); the far field at all
  * nodes comes from the same MFMA projection as vie_farfield.  Host arrays.
  * VIE_EINVAL for non-finite input, alpha outside [0, pi], n_rad outside
- * [1, 256] or n_az outside [1, 1024]; VIE_ESTATE before a solve. */
+ * [1, 256], n_az outside [1, 1024] or more than 2^22 nodes in all;
+ * VIE_ESTATE before a solve. */
 int vie_transfer_na(vie_ctx *ctx, int32_t body, const vie_na_detector *det, int32_t ndet,
                     int32_t n_rad, int32_t n_az, vie_c64 *T);
 

@@ -1172,7 +1172,7 @@ extern "C" int vie_transfer_na(vie_ctx* ctx, int32_t body, const vie_na_detector
   if (!ctx) return VIE_EINVAL;
   if (ctx->poisoned) return VIE_ESTATE;
   if (body < 0 || body >= (int)ctx->bodies.size() || ndet < 1 || !det || !T || n_rad < 1 ||
-      n_az < 1 || n_rad > 256 || n_az > 1024)
+      n_az < 1 || n_rad > 256 || n_az > 1024 || (int64_t)ndet * n_rad * n_az > (1 << 22))
     return VIE_EINVAL;
   BodyRec& B = *ctx->bodies[body];
   if (B.nrhs < 1) return VIE_ESTATE;
