@@ -90,7 +90,8 @@ def detector_scan():
 
 
 def post_process(V, ctx, nb, nch, theta, phi, dtau):
-    """Far field -> circular transfer coefficients -> g2 scan + Nc curve."""
+    """Far field -> circular transfer coefficients -> g2 scan, classical
+    intensity-product scan (eq. 27) and Nc curve."""
     out = []
     i_m10 = 80  # psi = -10 deg
     i_p10 = 100  # psi = +10 deg
@@ -98,14 +99,15 @@ def post_process(V, ctx, nb, nch, theta, phi, dtau):
         F = V.vie_farfield(ctx, b, theta, phi, nch)  # [nch][181][2]
         EL = (F[..., 0] + 1j * F[..., 1]) / np.sqrt(2)
         ER = (F[..., 0] - 1j * F[..., 1]) / np.sqrt(2)
-        g2s = []
+        g2s, p2s = [], []
         for j in range(len(theta)):
             T = (ER[0, i_m10], ER[1, i_m10], EL[0, j], EL[1, j])
             g, _, _ = V.hom_g2(T)
             g2s.append(g)
+            p2s.append(V.hom_classical_p2(T))
         T = (ER[0, i_m10], ER[1, i_m10], EL[0, i_p10], EL[1, i_p10])
         _, raw, nrm = V.hom_g2(T, 1.2, dtau, V.VIE_NORM_R1)
-        out.append((np.array(g2s), nrm))
+        out.append((np.array(g2s), np.array(p2s), nrm))
     return out
 
 

@@ -150,6 +150,13 @@ int vie_farfield(vie_ctx *ctx, int32_t body, const double *theta, const double *
 int hom_g2(const vie_c64 T[4], const double *omega, double sigma, const double *dtau,
            int32_t ndelay, int32_t norm, double *g2, double *Nc_raw, double *Nc_norm);
 
+/* Classical comparison observable (eq. 27): for deterministic fields, the
+ * product of the two detectors' intensities of the coherent superposition of
+ * both channels' responses, P2 = |T_a1 + T_a2|^2 |T_b1 + T_b2|^2 (T ordered
+ * as in hom_g2, unit channel amplitudes).  VIE_EINVAL for NULL or non-finite
+ * input.  Host arrays. */
+int hom_classical_p2(const vie_c64 T[4], double *p2);
+
 /* Detector with a finite aperture (the aperture-collected field operator,
  * eq. NAfield).  Under the narrowband approximation of Sec. II the collected
  * field of channel j is a transfer coefficient like the point detector's

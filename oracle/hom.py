@@ -15,6 +15,7 @@ two-channel transfer relation, eqs. field_transfer1/2).
   Normalisation R1: D_c = sigma sqrt(pi) (|A_dir|^2 + |A_ex|^2), so that
   Nc~ -> 1 at large delay.  R2: D_c = sigma sqrt(pi) G1_a G1_b (product of
   marginal intensities), so that Nc~(0) = g2 and single-path zeros stay zero.
+* Classical comparison (eq. 27): P2 = |T_a1 + T_a2|^2 |T_b1 + T_b2|^2.
 """
 
 from __future__ import annotations
@@ -34,6 +35,14 @@ def g2(T, omega=(1.0, 1.0)):
     num = w1 * w2 * abs(Ta1 * Tb2 + Ta2 * Tb1) ** 2
     den = (w1 * abs(Ta1) ** 2 + w2 * abs(Ta2) ** 2) * (w1 * abs(Tb1) ** 2 + w2 * abs(Tb2) ** 2)
     return num / den if den > 0 else float("nan")
+
+
+def classical_p2(T):
+    """Classical fourth-order correlation (eq. 27): intensity product
+    |E(r1)|^2 |E(r2)|^2 of the coherent superposition E = E_k1 + E_k2 of the
+    two channels' responses, projected on the detectors."""
+    Ta1, Ta2, Tb1, Tb2 = (complex(v) for v in T)
+    return abs(Ta1 + Ta2) ** 2 * abs(Tb1 + Tb2) ** 2
 
 
 def g2_fock(T, omega=(1.0, 1.0), nmax=2):

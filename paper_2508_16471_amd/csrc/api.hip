@@ -1277,6 +1277,18 @@ extern "C" int hom_g2(const vie_c64 T[4], const double* omega, double sigma, con
   return VIE_OK;
 }
 
+// Classical fourth-order correlation (eq. 27) of the coherent superposition
+// of the two channels' responses: |T_a1 + T_a2|^2 |T_b1 + T_b2|^2.
+extern "C" int hom_classical_p2(const vie_c64 T[4], double* p2) {
+  if (!T || !p2) return VIE_EINVAL;
+  for (int i = 0; i < 4; ++i)
+    if (!isfinite(T[i].re) || !isfinite(T[i].im)) return VIE_EINVAL;
+  const double ar = T[0].re + T[1].re, ai = T[0].im + T[1].im;
+  const double br = T[2].re + T[3].re, bi = T[2].im + T[3].im;
+  *p2 = (ar * ar + ai * ai) * (br * br + bi * bi);
+  return VIE_OK;
+}
+
 // ------------------------------------------------------- network (C ABI)
 extern "C" int64_t vie_cnn_num_params(void) { return cnn_offsets().total; }
 

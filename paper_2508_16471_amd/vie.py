@@ -74,6 +74,7 @@ def lib():
             "vie_solve": (C.c_int, [C.c_void_p, P(vie_planewave), P(C.c_int32), P(vie_stats)]),
             "vie_farfield": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double),
                                        C.c_int32, P(vie_c64)]),
+            "hom_classical_p2": (C.c_int, [P(vie_c64), P(C.c_double)]),
             "vie_transfer_na": (C.c_int, [C.c_void_p, C.c_int32, P(vie_na_detector), C.c_int32,
                                           C.c_int32, C.c_int32, P(vie_c64)]),
             "hom_g2": (C.c_int, [P(vie_c64), P(C.c_double), C.c_double, P(C.c_double), C.c_int32,
@@ -179,6 +180,14 @@ def vie_farfield(ctx, body, theta, phi, nrhs):
     F = np.zeros((nrhs, len(th), 2), dtype=np.complex128)
     _check(lib().vie_farfield(ctx, int(body), _dptr(th), _dptr(ph), len(th), _cptr(F)), "vie_farfield")
     return F
+
+
+def hom_classical_p2(T):
+    """Classical intensity product of the superposed channels (eq. 27)."""
+    t = np.ascontiguousarray(np.asarray(T, dtype=np.complex128).reshape(4))
+    p = np.zeros(1)
+    _check(lib().hom_classical_p2(_cptr(t), _dptr(p)), "hom_classical_p2")
+    return float(p[0])
 
 
 def vie_transfer_na(ctx, body, detectors, nrhs, n_rad=8, n_az=16):

@@ -187,6 +187,17 @@ def test_hom_g2_matches_oracle(V):
     assert abs(g) < 1e-15
 
 
+def test_hom_classical_p2_matches_oracle(V):
+    rng = np.random.default_rng(27)
+    for _ in range(20):
+        T = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+        want = hom.classical_p2(T)
+        assert abs(V.hom_classical_p2(T) - want) < 1e-13 * want
+    with pytest.raises(V.VieError) as e:
+        V.hom_classical_p2([np.nan, 0, 1, 1])
+    assert e.value.code == V.VIE_EINVAL
+
+
 def test_error_paths(V):
     g = Grid.centred(4, 0.1)
     eps = np.full((4, 4, 4), 2.0)

@@ -184,3 +184,28 @@ def test_paper_printed_numbers():
     fr = gold["fraunhofer"]
     assert abs(2 * fr["aperture_wavelengths"] ** 2 - fr["distance_wavelengths"]) < 1e-9
     assert abs(fr["distance_wavelengths"] * fr["wavelength_nm"] * 1e-6 - fr["distance_mm"]) < 0.01
+
+
+def test_classical_p2_is_intensity_product_of_superposed_response():
+    """eq. 27: P2 from the transfer coefficients equals the intensity product of
+    the far field of the superposed current w1 + w2 (linearity of eq. 25),
+    with z-detection c = (-sin theta, 0); beam splitter: |t + r|^4."""
+    rng = np.random.default_rng(27)
+    n = (4, 3, 5)
+    h = 0.1
+    pos = vd.voxel_centres(n, h, -h * (np.array(n) - 1) / 2)
+    w1, w2 = (rng.standard_normal((3, pos.shape[0])) + 1j * rng.standard_normal((3, pos.shape[0]))
+              for _ in range(2))
+    th = np.array([0.6, 2.2])
+    ph = np.array([0.3, -1.9])
+    T = []
+    for w in (w1, w2):
+        Ft, _ = vd.farfield(w, pos, h, 2 * np.pi, th, ph)
+        T.append(-np.sin(th) * Ft)
+    Tv = (T[0][0], T[1][0], T[0][1], T[1][1])
+    Fs, _ = vd.farfield(w1 + w2, pos, h, 2 * np.pi, th, ph)
+    Es = -np.sin(th) * Fs
+    want = abs(Es[0]) ** 2 * abs(Es[1]) ** 2
+    assert abs(hom.classical_p2(Tv) - want) < 1e-12 * want
+    t, r = 1 / np.sqrt(2), 1j / np.sqrt(2)
+    assert abs(hom.classical_p2((t, r, r, t)) - abs(t + r) ** 4) < 1e-15
