@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2508_16471_amd", "weights",
                                                       "warmstart_metasurface128.npy"))
-    ap.add_argument("--mode", choices=["solve", "matvec", "farfield", "uneven", "metasurface"],
+    ap.add_argument("--mode", choices=["solve", "matvec", "farfield", "uneven", "metasurface",
+                                       "sphere"],
                     default="solve",
                     help="matvec: time device-resident operator products only; farfield: "
                          "the 64,800-direction sweep of one body only (profiling); uneven: "
@@ -584,14 +585,86 @@ def metasurface_mode(args):
                      "TFLOPs": flops / ff_s / 1e12}}))
 
 
+def sphere_mode(args):
+    """The paper's sphere study at full size: r = 1 lambda, eps 4, 64^3 voxels
+    (h = 2.05/64), two channels at theta = +-30 deg (y-polarised), both
+    precisions.  Far-field sweep 360 x 180 per channel, z-detection
+    (c = (-sin theta, 0)) transfer coefficients, the g2 map (eq. 10) and the
+    classical intensity-product map (eq. 27) over (phi1, phi2) in 1 deg steps at
+    theta1 = 45, theta2 = 135 deg, and coincidence curves (200 delays) at the
+    map's minimum, median and maximum g2."""
+    import torch
+
+    from paper_2508_16471_amd import vie as V
+    from synth import Grid, sphere
+
+    torch.cuda.set_device(0)
+    V.lib()
+    g = Grid.centred((64, 64, 64), 2.05 / 64)
+    eps = sphere(g, 1.0, 4.0)
+    a = np.deg2rad(30.0)
+    chans = [((np.sin(a), 0, np.cos(a)), (0, 1.0, 0)), ((-np.sin(a), 0, np.cos(a)), (0, 1.0, 0))]
+    out = {"mode": "sphere", "workload": "sphere r=1 lambda, eps 4, 64^3, h=2.05/64, channels "
+           "theta=+-30 deg (y-pol), z-detection", "body_voxels": int((eps != 1.0).sum())}
+    th1 = (np.arange(180) + 0.5) * np.pi / 180
+    ph1 = np.arange(360) * 2 * np.pi / 360 - np.pi
+    TH, PH = np.meshgrid(th1, ph1, indexing="ij")
+    for label, prec in (("fp64", V.VIE_FP64), ("mixed", V.VIE_MIXED)):
+        ctx = V.vie_setup([(eps, g.h, g.origin)], V.make_options(K0, precision=prec, tol=1e-6,
+                                                                max_iter=20000))
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = V.vie_solve(ctx, chans, [2])
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            V.vie_farfield(ctx, 0, TH.ravel(), PH.ravel(), 2)
+            tf = time.perf_counter() - t0
+            phis = np.deg2rad(np.arange(360.0))
+            t0 = time.perf_counter()
+            Fa = V.vie_farfield(ctx, 0, np.full(360, np.pi / 4), phis, 2)[..., 0]
+            Fb = V.vie_farfield(ctx, 0, np.full(360, 3 * np.pi / 4), phis, 2)[..., 0]
+            Ta = -np.sin(np.pi / 4) * Fa  # [channel][phi1]
+            Tb = -np.sin(3 * np.pi / 4) * Fb
+            g2 = np.empty((360, 360))
+            p2 = np.empty((360, 360))
+            for i in range(360):
+                for j in range(360):
+                    T = (Ta[0, i], Ta[1, i], Tb[0, j], Tb[1, j])
+                    g2[i, j] = V.hom_g2(T)[0]
+                    p2[i, j] = V.hom_classical_p2(T)
+            tm = time.perf_counter() - t0
+        finally:
+            V.vie_destroy(ctx)
+        flat = np.argsort(g2, axis=None)
+        picks = {"min": flat[0], "median": flat[len(flat) // 2], "max": flat[-1]}
+        dtau = np.linspace(-5, 5, 200)
+        curves = {}
+        for k, idx in picks.items():
+            i, j = divmod(int(idx), 360)
+            T = (Ta[0, i], Ta[1, i], Tb[0, j], Tb[1, j])
+            _, _, nrm = V.hom_g2(T, 1.2, dtau, V.VIE_NORM_R2)
+            curves[k] = {"phi1_deg": i, "phi2_deg": j, "g2": float(g2[i, j]),
+                         "Nc_R2_near_0": float(nrm[int(np.argmin(np.abs(dtau)))]),
+                         "Nc_R2_at_5sigma": float(nrm[-1])}
+        out[label] = {"solve_s": ts, "iters": [x["iters"] for x in st],
+                      "rel_res": [x["rel_res"] for x in st],
+                      "sweep_64800_s": tf, "maps_s": tm,
+                      "g2_min": float(np.nanmin(g2)), "g2_max": float(np.nanmax(g2)),
+                      "p2_norm_min": float(np.nanmin(p2) / np.nanmax(p2)), "coincidence": curves}
+        print(json.dumps({label: out[label]}), file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
 # ------------------------------------------------------------------ main
 def main():
     args = parse()
-    if args.mode in ("matvec", "farfield", "uneven", "metasurface"):
+    if args.mode in ("matvec", "farfield", "uneven", "metasurface", "sphere"):
         if args.gpus != 1:
             sys.exit(2)
         return {"matvec": matvec_mode, "farfield": farfield_mode, "uneven": uneven_mode,
-                "metasurface": metasurface_mode}[args.mode](args)
+                "metasurface": metasurface_mode, "sphere": sphere_mode}[args.mode](args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the path shards by "
                           "right-hand side / body (see DESIGN.md), --gpus must be 1"}))
