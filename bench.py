@@ -769,6 +769,7 @@ def main():
         prods = plain["products_mean"] if plain else prod_fast
         cpu = cpu_baseline(cpu_t[0], cpu_t[1], prods)
 
+    mt = measured_traffic(dom, d["avg_launch_ms"])
     line = {
         "metric": "VIE solves/s at rel. residual 1e-6 (128^3 grid), plain FP64 vs mixed+learned",
         "value": value,
@@ -791,7 +792,8 @@ def main():
                    "inner_tol": args.inner_tol, "warm_start": False},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, d["avg_launch_ms"]),
+                     "traffic": (mt or {}).get("bytes_per_launch"),
+                     "traffic_detail": mt,
                      "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
                      "avg_launch_ms": d["avg_launch_ms"]},
         "matvec": matvec,
