@@ -76,11 +76,11 @@ __device__ __forceinline__ int64_t slab_base(const SideAddr& a, int rhs, int com
   return rhs * a.rs + comp * a.cs + (z / zl) * a.zhs + (z % zl) * a.zls;
 }
 
-template <typename T, int P, bool PAD, bool TRUNC, bool INV>
-__global__ __launch_bounds__(nt_lines<T>()) void k_fft_strided(
+template <typename T, int P, bool PAD, bool TRUNC, bool INV, int NTB = nt_lines<T>()>
+__global__ __launch_bounds__(NTB) void k_fft_strided(
     const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, const cpx<T>* __restrict__ tw,
     StridedArgs a, const int* __restrict__ active) {
-  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), W = NT / TT;
+  constexpr int E = fft_e<P>(), TT = P / E, NT = NTB, W = NT / TT;
   __shared__ cpx<T> lds[W * Pad<P>::LSTR];
   // XCD-contiguous ranges of the logical order below (neighbouring column
   // tiles of one slab share an XCD), with the right-hand side innermost so
@@ -474,6 +474,14 @@ int64_t bufB_elems(const GroupGeom& g) {
   return side_B(g, zl).rs;  // per right-hand side
 }
 
+// Workgroup size of the y passes (the host's ntY in y_pass computes the same).
+template <typename T, int P>
+constexpr int y_threads() {
+  constexpr int tt = P / fft_e<P>();
+  constexpr int nt = (int)(128 / sizeof(cpx<T>)) * tt;
+  return nt > nt_lines<T>() ? nt : nt_lines<T>();
+}
+
 template <typename T>
 static hipError_t y_pass(const GroupGeom& g, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw,
                          bool inverse, const int* active, hipStream_t s) {
@@ -484,7 +492,11 @@ static hipError_t y_pass(const GroupGeom& g, const cpx<T>* in, cpx<T>* out, cons
   a.ncomp = 3;
   a.nz = N3;
   a.zl = zl;
-  const int W = lines_per_block<T>(P2);
+  // enough threads per workgroup that each row access is a 128-byte run
+  // (long lines have more threads per line)
+  const int TTy = P2 / fft_e_of(P2);
+  const int ntY = std::max(nt_lines<T>(), (int)(128 / sizeof(cpx<T>)) * TTy);
+  const int W = ntY / TTy;
   a.tiles = (P1 + W - 1) / W;
   const SideAddr A = side_A(g, zl), B = side_B(g, zl);
   if (!inverse) {
@@ -500,10 +512,10 @@ static hipError_t y_pass(const GroupGeom& g, const cpx<T>* in, cpx<T>* out, cons
   }
   const dim3 grid(a.tiles * 3 * N3 * g.nrhs);
   if (!inverse) {
-    VIE_DISPATCH_P(P2, (k_fft_strided<T, PP, true, false, false><<<grid, nt_lines<T>(), 0, s>>>(
+    VIE_DISPATCH_P(P2, (k_fft_strided<T, PP, true, false, false, y_threads<T, PP>()><<<grid, ntY, 0, s>>>(
                            in, out, tw, a, active)));
   } else {
-    VIE_DISPATCH_P(P2, (k_fft_strided<T, PP, false, true, true><<<grid, nt_lines<T>(), 0, s>>>(
+    VIE_DISPATCH_P(P2, (k_fft_strided<T, PP, false, true, true, y_threads<T, PP>()><<<grid, ntY, 0, s>>>(
                            in, out, tw, a, active)));
   }
   return hipGetLastError();
