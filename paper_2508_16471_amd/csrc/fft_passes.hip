@@ -227,7 +227,7 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
   // FP32 with shift addressing, 16 points per thread: rows move as 16-byte
   // column-pair segments; every column of such a launch is valid (FAST
   // launches need P1 % W == 0)
-  constexpr bool PAIR = FAST && sizeof(T) == 4 && E == 16;
+  constexpr bool PAIR = FAST && sizeof(T) == 4 && (E == 16 || E == 12);
   const bool valid = PAIR || xx < a.P1;
   // B[rhs][comp][z / zl][xi_y][z % zl][xi_x]; offsets within one right-hand
   // side fit in 32 bits (3 N3 P2 P1 < 2^31 for P <= 512)
