@@ -237,12 +237,15 @@ def test_error_paths(V):
 
 
 @pytest.mark.parametrize("n,rows", [((64, 64, 64), 48), ((128, 128, 128), 24), ((48, 48, 48), 32),
-                                    ((96, 96, 96), 24), ((256, 256, 48), 16)])
+                                    ((96, 96, 96), 24), ((256, 256, 48), 16), ((256, 256, 256), 12),
+                                    ((48, 40, 192), 16)])
 def test_matvec_sampled_rows_large(V, n, rows):
     """Full-size grids: sampled rows of the FP64/FP32 product against the
     oracle's O(M)-per-row direct sum (x supported on a metasurface-like body).
     FFT lengths: 128, 256 (2^k); 96, 192 (3 x 2^k); 512 x 512 x 96 (the
-    256 x 256 x 48 metasurface grid, mixed)."""
+    256 x 256 x 48 metasurface grid, mixed); 512^3 (the largest grid, every
+    axis at its maximum line length); 96 x 96 x 384 (the longest 3 x 2^k
+    z line)."""
     rng = np.random.default_rng(n[0])
     h = 1.0 / 32
     g = Grid.centred(n, h)
