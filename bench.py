@@ -65,7 +65,7 @@ def parse():
                          "random ellipsoid-union bodies on mixed grids, batched per grid")
     ap.add_argument("--nrhs", type=int, default=1, help="matvec mode: vectors per product")
     ap.add_argument("--directions", type=int, default=64,
-                    help="metasurface mode: incident directions (x 2 circular polarisations)")
+                    help="metasurface mode: incident directions of the 64-point (u, v) grid (x 2 circular polarisations)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32")
     return ap.parse_args()
 
@@ -521,23 +521,28 @@ def uneven_mode(args):
 
 
 def metasurface_mode(args):
-    """PB metasurface on the 256 x 256 x 48 grid (h = lambda/32, 8 x 8 fins of
-    eps 5.8 on an eps 2.1 slab): `directions` incident directions spread over
-    a 20 deg cap about +z, each with both circular polarisations, solved as
-    one batched call (FP32 product inside FP64 refinement, replayed graphs;
-    the call includes the one-off z-shape tuning and graph capture), then a
-    362-direction far-field scan (theta in [0, 180] deg in the phi = 0 and
-    phi = 90 deg planes) of every right-hand side."""
+    """PB metasurface on the 256 x 256 x 48 grid (h = lambda/60, 8 x 8 fins of
+    eps 5.8 on an eps 2.1 slab, 1.28 M body voxels): incident directions
+    (u, v, sqrt(1 - u^2 - v^2)) with u, v in {-0.3, ..., 0.4} (64, normal
+    incidence included; `directions` < 64 takes an evenly strided subset),
+    each with both circular polarisations, solved as one batched call (FP32
+    product inside FP64 refinement, replayed graphs; the call includes the
+    one-off z-shape tuning and graph capture), then a 362-direction far-field
+    scan (theta in [0, 180] deg in the phi = 0 and phi = 90 deg planes) of
+    every right-hand side."""
     import torch
 
     from paper_2508_16471_amd import vie as V
-    from synth import cap_directions, circular_pol_basis, pb_metasurface
+    from synth import circular_pol_basis, pb_metasurface, uv_directions
 
     torch.cuda.set_device(0)
     V.lib()
     g, eps = pb_metasurface()
     chans = []
-    for k in cap_directions(args.directions, 20.0):
+    dirs = uv_directions()
+    if args.directions < len(dirs):
+        dirs = dirs[np.linspace(0, len(dirs) - 1, args.directions).round().astype(int)]
+    for k in dirs:
         _, _, L, R = circular_pol_basis(k)
         chans += [(k, L), (k, R)]
     nrhs = len(chans)
@@ -574,8 +579,8 @@ def metasurface_mode(args):
     it = [x["iters"] for x in st]
     flops = 8.0 * theta.size * nb * 3 * nrhs
     print(json.dumps({
-        "mode": "metasurface", "workload": "PB metasurface 256x256x48, h=lambda/32, 8x8 fins eps 5.8, "
-        "slab eps 2.1", "grid": list(N), "fft": list(P), "body_voxels": nb, "rhs": nrhs,
+        "mode": "metasurface", "workload": "PB metasurface 256x256x48, h=lambda/60, 8x8 fins eps 5.8 "
+        "(9x24x36 cells, period 32 cells), slab eps 2.1 (12 cells), directions u,v in -0.3..0.4 x L/R", "grid": list(N), "fft": list(P), "body_voxels": nb, "rhs": nrhs,
         "tol": args.tol, "precision": "fp32 product + fp64 refinement", "setup_s": setup,
         "solve_s": solve_s, "solves_per_s": nrhs / solve_s, "rc": rc,
         "iters_mean": float(np.mean(it)), "iters_max": int(np.max(it)),

@@ -19,6 +19,7 @@ from .geometry import (  # noqa: F401
     metasurface_family,
     pb_metasurface,
     cap_directions,
+    uv_directions,
     pb_rotation_step,
     planewave,
     random_planewave,

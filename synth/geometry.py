@@ -170,12 +170,14 @@ def metasurface_family(rng, n=128, h=1.0 / 32):
     return grid, body
 
 
-def pb_metasurface(n=(256, 256, 48), h=1.0 / 32, count=8):
+def pb_metasurface(n=(256, 256, 48), h=1.0 / 60, count=8):
     """The benchmark Pancharatnam-Berry metasurface (lengths in wavelengths):
     a ``count x count`` array of 0.15 x 0.4 x 0.6 fins (eps 5.8) on a lossless
     slab 0.2 thick (eps 2.1), lateral period ``n[0] h / count``, fin rotation
     stepped linearly through [0, pi) across x (angle pi a / count in column
-    a), slab and fins centred in z on an ``n`` grid of spacing ``h``."""
+    a), slab and fins centred in z on an ``n`` grid of spacing ``h``.  At the
+    defaults (h = lambda/60) the slab is 12 cells, the fins 9 x 24 x 36 cells
+    on a 32-cell period, and slab plus fins fill the 48 z cells."""
     grid = Grid.centred(n, h)
     fin_cells = int(round(0.6 / h))
     slab_cells = max(1, int(round(0.2 / h)))
@@ -187,6 +189,16 @@ def pb_metasurface(n=(256, 256, 48), h=1.0 / 32, count=8):
                             fin_wid=0.15, fin_cells=fin_cells, period=n[0] * h / count, count=count,
                             angles=ang, z0_cells=z0)
     return grid, body
+
+
+def uv_directions(values=np.arange(-0.3, 0.41, 0.1)):
+    """Incident directions (u, v, sqrt(1 - u^2 - v^2)) on the product grid of
+    transverse components ``values`` (default -0.3 ... 0.4 in steps of 0.1:
+    64 directions, normal incidence included), u fastest."""
+    vals = np.round(np.asarray(values, float), 12)
+    U, Vv = np.meshgrid(vals, vals, indexing="xy")
+    u, v = U.ravel(), Vv.ravel()
+    return np.stack([u, v, np.sqrt(1.0 - u * u - v * v)], axis=1)
 
 
 def cap_directions(count, cap_deg):
