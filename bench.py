@@ -541,7 +541,11 @@ def metasurface_mode(args):
     chans = []
     dirs = uv_directions()
     if args.directions < len(dirs):
-        dirs = dirs[np.linspace(0, len(dirs) - 1, args.directions).round().astype(int)]
+        pick = np.linspace(0, len(dirs) - 1, args.directions).round().astype(int)
+        normal = int(np.argmin(np.abs(dirs[:, 0]) + np.abs(dirs[:, 1])))
+        if normal not in pick:
+            pick[np.argmin(np.abs(pick - normal))] = normal  # keep normal incidence
+        dirs = dirs[np.unique(pick)]
     for k in dirs:
         _, _, L, R = circular_pol_basis(k)
         chans += [(k, L), (k, R)]
@@ -574,6 +578,34 @@ def metasurface_mode(args):
         V.vie_farfield(ctx, 0, theta, phi, nrhs)
         torch.cuda.synchronize()
         ff_s = time.perf_counter() - t0
+        # two photons in H and V at normal incidence (linear combinations of the
+        # L and R solutions), L detection at +psi, R detection at -psi, in the
+        # xz plane along the rotation gradient
+        i0 = int(np.argmin(np.abs(dirs[:, 0]) + np.abs(dirs[:, 1])))
+        psi = np.deg2rad(np.linspace(-90.0, 90.0, 181))
+        Fs = V.vie_farfield(ctx, 0, np.abs(psi), np.where(psi < 0, np.pi, 0.0), nrhs)
+        FL, FR = Fs[2 * i0], Fs[2 * i0 + 1]  # [psi][theta/phi component]
+        FH = (FL + FR) / np.sqrt(2)
+        FV = (FL - FR) / (1j * np.sqrt(2))
+        projL = lambda F: (F[..., 0] + 1j * F[..., 1]) / np.sqrt(2)  # noqa: E731
+        projR = lambda F: (F[..., 0] - 1j * F[..., 1]) / np.sqrt(2)  # noqa: E731
+        # first diffraction order of the 8-fin supercell (it spans the grid: n[0] h)
+        design = float(np.degrees(np.arcsin(1.0 / (g.n[0] * g.h))))
+        g2lr = {}
+        for ang in (design, 10.0):
+            a = np.deg2rad(ang)
+            Fd = V.vie_farfield(ctx, 0, np.array([a, a]), np.array([0.0, np.pi]), nrhs)
+            dH = (Fd[2 * i0] + Fd[2 * i0 + 1]) / np.sqrt(2)
+            dV = (Fd[2 * i0] - Fd[2 * i0 + 1]) / (1j * np.sqrt(2))
+            T = (projL(dH)[0], projL(dV)[0], projR(dH)[1], projR(dV)[1])
+            g2lr[f"{ang:.2f}"] = {"g2": V.hom_g2(T)[0], "P2_classical": V.hom_classical_p2(T)}
+        ia = int(np.argmin(np.abs(np.degrees(psi) - design)))
+        scan = np.array([V.hom_g2((projL(FH)[ia], projL(FV)[ia], projR(FH)[j], projR(FV)[j]))[0]
+                         for j in range(len(psi))])
+        g2_out = {"channels": "H, V at normal incidence (from the L/R solutions)",
+                  "detectors": "L at +psi, R at -psi, xz plane (scan: R detector on 1-deg steps)",
+                  "design_order_deg": design, "at": g2lr,
+                  "scan_b_min": float(np.nanmin(scan)), "scan_b_max": float(np.nanmax(scan))}
     finally:
         V.vie_destroy(ctx)
     it = [x["iters"] for x in st]
@@ -587,7 +619,8 @@ def metasurface_mode(args):
         "all_converged": all(x["converged"] for x in st),
         "max_rel_res": float(max(x["rel_res"] for x in st)), "device_mem_GB": used,
         "farfield": {"directions": int(theta.size), "seconds": ff_s,
-                     "TFLOPs": flops / ff_s / 1e12}}))
+                     "TFLOPs": flops / ff_s / 1e12},
+        "g2_LR": g2_out}))
 
 
 def sphere_mode(args):
