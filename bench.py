@@ -404,6 +404,35 @@ def na_detection(V, torch, ctx, nch):
             "body": 0, "rows": rows}
 
 
+def sphere_leg(V, torch, args):
+    """The secondary W128 body: a sphere r = 2 lambda, eps 2.25 on the same
+    128^3 grid (h = lambda/32, about 52 % fill), k = z, x-polarised, tol as the
+    main run: plain FP64 against the fast (mixed) path, one solve each after a
+    warm-up."""
+    from synth import Grid, sphere
+
+    g = Grid.centred(args.grid, 1.0 / 32 * 128 / args.grid)
+    eps = sphere(g, 2.0, 2.25)
+    ch = [((0, 0, 1.0), (1.0, 0, 0))]
+    out = {"workload": f"sphere r=2 lambda, eps 2.25, {args.grid}^3, h=lambda/32, k=z, x-pol",
+           "body_voxels": int((eps != 1.0).sum())}
+    for label, prec in (("plain_fp64", V.VIE_FP64), ("fast", V.VIE_MIXED)):
+        ctx = V.vie_setup([(eps, g.h, g.origin)], V.make_options(K0, precision=prec, tol=args.tol,
+                                                                max_iter=20000, inner_tol=args.inner_tol))
+        try:
+            V.vie_solve(ctx, ch, [1])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = V.vie_solve(ctx, ch, [1])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        finally:
+            V.vie_destroy(ctx)
+        out[label] = {"solves_per_s": 1.0 / dt, "iters": st[0]["iters"], "rel_res": st[0]["rel_res"]}
+    out["speedup"] = out["fast"]["solves_per_s"] / out["plain_fp64"]["solves_per_s"]
+    return out
+
+
 def farfield_mode(args):
     """Solve body 0 of the workload (its channels), then time the far-field
     sweep alone (`steps` sweeps)."""
@@ -799,6 +828,7 @@ def main():
         sweep = farfield_sweep(V, torch, ctx, args, chans, nch, int((bodies[0][0] != 1.0).sum()))
     na = na_detection(V, torch, ctx, nch)
     V.vie_destroy(ctx)
+    secondary = None if args.no_plain else sphere_leg(V, torch, args)
     if args.calib_copy:
         calib_copy(torch)
 
@@ -845,6 +875,7 @@ def main():
         "learned": learned,
         "farfield_sweep": sweep,
         "na_detection": na,
+        "secondary_sphere": secondary,
         "setup_s": setup_s,
     }
     print(json.dumps(line))
