@@ -658,8 +658,10 @@ def sphere_mode(args):
     precisions.  Far-field sweep 360 x 180 per channel, z-detection
     (c = (-sin theta, 0)) transfer coefficients, the g2 map (eq. 10) and the
     classical intensity-product map (eq. 27) over (phi1, phi2) in 1 deg steps at
-    theta1 = 45, theta2 = 135 deg, and coincidence curves (200 delays) at the
-    map's minimum, median and maximum g2."""
+    theta1 = 45, theta2 = 135 deg, the g2 map over (theta1, theta2) at
+    (phi1, phi2) = (0, 180 deg), and coincidence curves (200 delays) at the
+    (phi1, phi2) map's minimum, median and maximum g2 and at its pair closest
+    to a single path."""
     import torch
 
     from paper_2508_16471_amd import vie as V
@@ -701,11 +703,30 @@ def sphere_mode(args):
                     T = (Ta[0, i], Ta[1, i], Tb[0, j], Tb[1, j])
                     g2[i, j] = V.hom_g2(T)[0]
                     p2[i, j] = V.hom_classical_p2(T)
+            # (theta1, theta2) map at (phi1, phi2) = (0, 180 deg)
+            ths = (np.arange(180) + 0.5) * np.pi / 180
+            Fa2 = V.vie_farfield(ctx, 0, ths, np.zeros(180), 2)[..., 0] * -np.sin(ths)
+            Fb2 = V.vie_farfield(ctx, 0, ths, np.full(180, np.pi), 2)[..., 0] * -np.sin(ths)
+            g2t = np.array([[V.hom_g2((Fa2[0, i], Fa2[1, i], Fb2[0, j], Fb2[1, j]))[0]
+                             for j in range(180)] for i in range(180)])
             tm = time.perf_counter() - t0
         finally:
             V.vie_destroy(ctx)
+        # the (theta1, theta2) detectors see only solver-tolerance noise when the
+        # channels' fields have no theta component in the xz plane (y-polarised
+        # channels on a body symmetric under y -> -y): no physical g2 there
+        bright = float(max(np.abs(Fa2).max(), np.abs(Fb2).max()) / np.abs(Ta).max())
+        theta_map = ({"dark": True, "relative_brightness": bright} if bright < 10 * 1e-6 else
+                     {"dark": False, "relative_brightness": bright, "g2_min": float(np.nanmin(g2t)),
+                      "g2_max": float(np.nanmax(g2t))})
         flat = np.argsort(g2, axis=None)
-        picks = {"min": flat[0], "median": flat[len(flat) // 2], "max": flat[-1]}
+        # single-path point: the pair where one path amplitude is smallest
+        # relative to the other (|A_dir| = |T_a1 T_b2|, |A_ex| = |T_a2 T_b1|)
+        ad = np.abs(Ta[0][:, None] * Tb[1][None, :])
+        ae = np.abs(Ta[1][:, None] * Tb[0][None, :])
+        single = int(np.argmin(np.minimum(ad, ae) / np.maximum(np.maximum(ad, ae), 1e-300)))
+        picks = {"min": flat[0], "median": flat[len(flat) // 2], "max": flat[-1],
+                 "single_path": single}
         dtau = np.linspace(-5, 5, 200)
         curves = {}
         for k, idx in picks.items():
@@ -719,6 +740,7 @@ def sphere_mode(args):
                       "rel_res": [x["rel_res"] for x in st],
                       "sweep_64800_s": tf, "maps_s": tm,
                       "g2_min": float(np.nanmin(g2)), "g2_max": float(np.nanmax(g2)),
+                      "theta_map": theta_map,
                       "p2_norm_min": float(np.nanmin(p2) / np.nanmax(p2)), "coincidence": curves}
         print(json.dumps({label: out[label]}), file=sys.stderr, flush=True)
     print(json.dumps(out))
