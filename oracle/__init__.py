@@ -17,6 +17,9 @@ hom        Two-photon observables: g2 of two populated channels, coincidence
            number Nc(dtau) and its two normalisations, the beam-splitter model,
            brute-force Fock-space and tau-quadrature checks.
 conv_ref   Plain 3-D convolution forward/backward (learned warm start).
+detect     Finite-aperture detectors: cone quadrature of the far field.
+precond    Block-Jacobi preconditioner on a lateral partition, k-step GMRES
+           block solves, restarted flexible GMRES.
 
 Every function states the passage of the paper it follows.  Functions with
 no independent pin say "parity unpinned" in their docstring (none at
