@@ -58,15 +58,19 @@ def parse():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2508_16471_amd", "weights",
                                                       "warmstart_metasurface128.npy"))
     ap.add_argument("--mode", choices=["solve", "matvec", "farfield", "uneven", "metasurface",
-                                       "sphere"],
+                                       "sphere", "precond"],
                     default="solve",
                     help="matvec: time device-resident operator products only; farfield: "
                          "the 64,800-direction sweep of one body only (profiling); uneven: "
-                         "random ellipsoid-union bodies on mixed grids, batched per grid")
+                         "random ellipsoid-union bodies on mixed grids, batched per grid; "
+                         "precond: block-Jacobi FGMRES against GMRES and BiCGSTAB on one body")
     ap.add_argument("--nrhs", type=int, default=1, help="matvec mode: vectors per product")
     ap.add_argument("--directions", type=int, default=64,
                     help="metasurface mode: incident directions of the 64-point (u, v) grid (x 2 circular polarisations)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32")
+    ap.add_argument("--configs", default="",
+                    help="precond mode: comma-separated configuration names to run "
+                         "(the BiCGSTAB reference always runs)")
     return ap.parse_args()
 
 
@@ -747,13 +751,76 @@ def sphere_mode(args):
 
 
 # ------------------------------------------------------------------ main
+def precond_mode(args):
+    """The paper's block preconditioner (7 x 7 lateral blocks, read as block
+    Jacobi with k-step GMRES block solves) inside restarted FGMRES, against
+    plain restarted GMRES and the mixed BiCGSTAB path, on one body of the
+    benchmark family (--grid, --channels right-hand sides), mixed precision,
+    tol --tol.  Each configuration is run once untimed (sub-problem setup,
+    autotuning) and once timed."""
+    bodies, chans = make_workload(1, args.channels, args.grid)
+    import torch
+
+    from paper_2508_16471_amd import vie as V
+
+    torch.cuda.set_device(0)
+    V.lib()
+    e, h, o, g = bodies[0]
+    nch = args.channels
+    opt = V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
+                         inner_tol=args.inner_tol)
+    ctx = V.vie_setup([(e, h, o)], opt)
+    configs = [("bicgstab_mixed", None, 0)]
+    for m in (30,):
+        configs.append((f"gmres{m}", V.fgmres_options(m, (0, 0)), 0))
+        for bl, k in (((7, 7), 2), ((7, 7), 4), ((8, 8), 2), ((8, 8), 4), ((4, 4), 4),
+                      ((2, 2), 2), ((2, 2), 4), ((2, 2), 8), ((1, 1), 4)):
+            configs.append((f"fgmres{m}_bj{bl[0]}x{bl[1]}_k{k}",
+                            V.fgmres_options(m, bl, k, V.VIE_MIXED), k))
+    if args.configs:
+        keep = set(args.configs.split(","))
+        configs = [c for c in configs if c[0] in keep or c[0] == "bicgstab_mixed"]
+    res = {}
+    try:
+        for name, fo, k in configs:
+            def run():
+                if fo is None:
+                    return V.vie_solve(ctx, chans, [nch], allow_noconv=True)[1]
+                return V.vie_solve_fgmres(ctx, chans, [nch], fo, allow_noconv=True)[1]
+
+            run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = run()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            it = float(np.mean([s["iters"] for s in st]))
+            r = {"solves_per_s": nch / dt, "ms_per_solve": 1e3 * dt / nch,
+                 "iterations": it, "operator_products": float(np.mean([s["matvecs"] for s in st])),
+                 "block_products": it * k, "converged": all(s["converged"] for s in st),
+                 "max_rel_res": max(s["rel_res"] for s in st)}
+            res[name] = r
+            print(f"precond {name}: {r}", file=sys.stderr, flush=True)
+    finally:
+        V.vie_destroy(ctx)
+    base = res["bicgstab_mixed"]["solves_per_s"]
+    print(json.dumps({"metric": "VIE solves/s at rel. residual %g, one body (%d^3 grid)" % (args.tol, args.grid),
+                      "value": max(r["solves_per_s"] for r in res.values()), "unit": "solves/s",
+                      "n_gpus": 1, "mode": "precond", "data": "synthetic",
+                      "config": {"workload": f"metasurface family {args.grid}^3, h = lambda/32, "
+                                             f"{nch} channels, mixed precision"},
+                      "configs": res,
+                      "speedup_vs_bicgstab": {k: v["solves_per_s"] / base for k, v in res.items()}}))
+
+
 def main():
     args = parse()
-    if args.mode in ("matvec", "farfield", "uneven", "metasurface", "sphere"):
+    if args.mode in ("matvec", "farfield", "uneven", "metasurface", "sphere", "precond"):
         if args.gpus != 1:
             sys.exit(2)
         return {"matvec": matvec_mode, "farfield": farfield_mode, "uneven": uneven_mode,
-                "metasurface": metasurface_mode, "sphere": sphere_mode}[args.mode](args)
+                "metasurface": metasurface_mode, "sphere": sphere_mode,
+                "precond": precond_mode}[args.mode](args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the path shards by "
                           "right-hand side / body (see DESIGN.md), --gpus must be 1"}))

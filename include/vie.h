@@ -127,6 +127,44 @@ int vie_setup(const vie_body *bodies, int32_t n_bodies, const vie_options *opt,
 int vie_solve(vie_ctx *ctx, const vie_planewave *inc, const int32_t *nrhs_per_body,
               vie_stats *stats);
 
+/* Block preconditioner of the paper's large metasurface solve (Sec. IV:
+ * BiCGStab with a preconditioner over 7 x 7 blocks), here as block Jacobi
+ * over a lateral partition, with restarted flexible GMRES (Saad 1993) as the
+ * outer method because the block solves are inexact.
+ *   Partition: x part p of bx holds voxels [floor(p N1 / bx),
+ *   floor((p + 1) N1 / bx)), y alike; a block is one (x part, y part) pair over
+ *   the full z extent.  M = the operator with every coupling between two
+ *   different blocks dropped; z = M^{-1} v is approximated on every block by
+ *   inner_iters steps of GMRES from zero (the minimal-residual element of that
+ *   Krylov space of the block's own operator).
+ * blocks = {0, 0} turns the preconditioner off (plain restarted GMRES). */
+typedef struct {
+  int32_t restart;         /* Arnoldi steps per cycle, 1..128                      */
+  int32_t blocks[2];       /* bx, by: each 1..64 and at most N1 (N2); or {0, 0}    */
+  int32_t inner_iters;     /* GMRES steps of every block solve, 1..64              */
+  int32_t inner_precision; /* VIE_FP64 or VIE_MIXED: block products in FP64/FP32  */
+} vie_fgmres_options;
+
+/* Solve like vie_solve (same channels, stats, solution storage and return
+ * codes) with right-preconditioned restarted FGMRES from w = 0, for a
+ * context holding exactly one body (VIE_ENOTSUP otherwise).  The Arnoldi
+ * products use the context's precision; every cycle ends with the FP64 true
+ * residual, which alone decides convergence (tol and max_iter of the
+ * context: max_iter caps the Arnoldi steps).  stats: iters = Arnoldi steps,
+ * cycles = FP64 residual products, matvecs = iters + cycles (the block
+ * products, inner_iters per step, are not counted).  VIE_EINVAL for options
+ * out of range.  The first call with a new partition builds the block
+ * sub-problems (a spectrum for the padded block grid). */
+int vie_solve_fgmres(vie_ctx *ctx, const vie_planewave *inc, const int32_t *nrhs_per_body,
+                     const vie_fgmres_options *opt, vie_stats *stats);
+
+/* Apply the preconditioner alone: z = M^{-1} r (as defined above, blocks
+ * required) for nvec host vectors r[nvec][3][N3][N2][N1] of the context's
+ * only body; z has the same layout and is 0 off the body (entries of r off
+ * the body are ignored).  VIE_EINVAL for blocks = {0, 0} or bad options. */
+int vie_precond_apply(vie_ctx *ctx, const vie_fgmres_options *opt, const vie_c64 *r, vie_c64 *z,
+                      int32_t nvec);
+
 /* Far-field amplitude (eq. 25, normalisation above) of every right-hand
  * side of `body` at ndir directions (theta, phi in radians):
  * F[(rhs * ndir + d) * 2 + {0,1}] = (F_theta, F_phi) with

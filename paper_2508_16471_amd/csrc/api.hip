@@ -12,6 +12,7 @@
 
 #include "../../include/vie.h"
 #include "cnn.h"
+#include "gmres.h"
 #include "kernels.h"
 
 using namespace vie;
@@ -125,6 +126,90 @@ struct TimedEvent {
   hipEvent_t a, b;
 };
 
+// Device storage of one batched Arnoldi process over nseg segments: basis V
+// (m + 1 vectors), preconditioned vectors Z (flexible variant, m vectors),
+// the work vector, both Gram-Schmidt passes of every Hessenberg column
+// H[j][s][i] (i <= j; column j of all segments contiguous, so one plain copy
+// brings it to the host) and the squared norms NR[s][j] (NR[s][0] = ||r||^2).
+struct ArnoldiBufs {
+  DevBuf V, Z, w, H1, H2, NR, dpart, npart, off, len, act, nvs, coef;
+};
+
+// Block-Jacobi preconditioner of a one-body context: the body split into
+// bx x by lateral blocks, each non-empty block one body of a sub-context on a
+// common padded grid, so that the block products of every right-hand side
+// run as one batched product.
+struct BlockPrec {
+  int bx = 0, by = 0;
+  vie_ctx* sub = nullptr;       // owned; its stream is set to the parent's per use
+  int nblk = 0;                 // non-empty blocks
+  int64_t len = 0;              // 3 nb: elements of one right-hand side's vector
+  std::vector<int64_t> boff;    // element offset of each block in the permuted vector
+  std::vector<int> blen;        // elements of each block (3 nb_b)
+  DevBuf perm;                  // int [len]: permuted position -> body vector position
+  int nrhs = 0;                 // right-hand sides the segment tables are bound for
+  ArnoldiBufs ab;
+  DevBuf R, X;                  // permuted input, block solution
+  ~BlockPrec() {
+    if (sub) vie_destroy(sub);
+  }
+};
+
+// Least-squares part of GMRES for one segment: the Hessenberg matrix reduced
+// column by column by complex Givens rotations (c real, s complex).
+struct HessLS {
+  int m = 0;
+  std::vector<c64> R, sn, g;
+  std::vector<double> cs;
+  void reset(int m_, double beta) {
+    m = m_;
+    R.assign((size_t)(m + 1) * m, mk(0.0, 0.0));
+    sn.assign(m, mk(0.0, 0.0));
+    cs.assign(m, 0.0);
+    g.assign(m + 1, mk(0.0, 0.0));
+    g[0] = mk(beta, 0.0);
+  }
+  // Append column j (h[0..j], subdiagonal hn >= 0); returns the residual
+  // estimate |g[j+1]|.
+  double add(int j, const c64* h, double hn) {
+    c64* col = &R[(size_t)j * (m + 1)];
+    for (int i = 0; i <= j; ++i) col[i] = h[i];
+    for (int i = 0; i < j; ++i) {
+      const c64 a = col[i], b = col[i + 1];
+      col[i] = cs[i] * a + sn[i] * b;
+      col[i + 1] = cs[i] * b - mk(sn[i].re, -sn[i].im) * a;
+    }
+    const c64 a = col[j];
+    const double aa = std::hypot(a.re, a.im);
+    const double rho = std::hypot(aa, hn);
+    if (rho == 0.0) {
+      cs[j] = 1.0;
+      sn[j] = mk(0.0, 0.0);
+    } else if (aa == 0.0) {
+      cs[j] = 0.0;
+      sn[j] = mk(1.0, 0.0);
+    } else {
+      cs[j] = aa / rho;
+      sn[j] = mk(a.re / aa * hn / rho, a.im / aa * hn / rho);  // (a/|a|) conj(hn) / rho
+    }
+    col[j] = cs[j] * a + hn * sn[j];
+    const c64 gj = g[j];
+    g[j] = cs[j] * gj;
+    g[j + 1] = mk(0.0, 0.0) - mk(sn[j].re, -sn[j].im) * gj;
+    return std::hypot(g[j + 1].re, g[j + 1].im);
+  }
+  // y[0..k) from the triangular system R y = g.
+  void solve(int k, c64* y) const {
+    for (int i = k - 1; i >= 0; --i) {
+      c64 t = g[i];
+      for (int l = i + 1; l < k; ++l) t = t - R[(size_t)l * (m + 1) + i] * y[l];
+      const c64 d = R[(size_t)i * (m + 1) + i];
+      const double dd = d.re * d.re + d.im * d.im;
+      y[i] = dd > 0 ? (1.0 / dd) * cmulc(d, t) : mk(0.0, 0.0);
+    }
+  }
+};
+
 }  // namespace
 
 static const char* kKindNames[] = {
@@ -155,6 +240,9 @@ struct vie_ctx {
   int* hflags[2] = {nullptr, nullptr};
   int hflags_cap = 0;
   hipEvent_t flag_ev[2] = {nullptr, nullptr};
+  // flexible GMRES and its block-Jacobi preconditioner (built on first use)
+  std::unique_ptr<ArnoldiBufs> fgm;
+  std::unique_ptr<BlockPrec> bj;
 };
 
 // --------------------------------------------------------------- utilities
@@ -423,6 +511,9 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
 extern "C" void vie_destroy(vie_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->bj && ctx->bj->sub) ctx->bj->sub->stream = ctx->bj->sub->own_stream;
+  ctx->bj.reset();
+  ctx->fgm.reset();
   ctx->groups.clear();
   ctx->bodies.clear();
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
@@ -884,15 +975,16 @@ static void planewave_tables(const vie_planewave& pw, const Group& G, const doub
   }
 }
 
-extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* nrhs_per_body,
-                         vie_stats* stats) {
-  if (!ctx) return VIE_EINVAL;
-  if (ctx->poisoned) return VIE_ESTATE;
-  if (!inc || !nrhs_per_body) return VIE_EINVAL;
+// Check the incident channels of a solve; first[b] = index of body b's first
+// channel in inc.
+static int check_channels(vie_ctx* ctx, const vie_planewave* inc, const int32_t* nrhs_per_body,
+                          std::vector<int>& first) {
   const int nb = (int)ctx->bodies.size();
   int total = 0;
+  first.assign(nb, 0);
   for (int b = 0; b < nb; ++b) {
     if (nrhs_per_body[b] < 0) return VIE_EINVAL;
+    first[b] = total;
     total += nrhs_per_body[b];
   }
   for (int i = 0; i < total; ++i) {
@@ -902,67 +994,82 @@ extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* 
     for (int c = 0; c < 3; ++c)
       if (!isfinite(w.pol[c].re) || !isfinite(w.pol[c].im)) return VIE_EINVAL;
   }
-  if (ctx->opt.warm_start && !ctx->cnn) return VIE_EINVAL;  // warm start needs vie_attach_cnn
-  // assign right-hand sides to groups
-  std::vector<int> first(nb);
-  {
-    int acc = 0;
-    for (int b = 0; b < nb; ++b) {
-      first[b] = acc;
-      acc += nrhs_per_body[b];
+  return VIE_OK;
+}
+
+// Bind the right-hand sides of one solve to group G: per-body ranges,
+// storage, vector offsets, compressed-index pointers, plane-wave tables.
+static int bind_rhs(vie_ctx* ctx, Group& G, const vie_planewave* inc,
+                    const int32_t* nrhs_per_body, const std::vector<int>& first) {
+  int nr = 0;
+  for (int b : G.bodies) {
+    BodyRec& B = *ctx->bodies[b];
+    B.rhs0 = nr;
+    B.nrhs = nrhs_per_body[b];
+    nr += B.nrhs;
+  }
+  G.g.nrhs = nr;
+  if (nr == 0) return VIE_OK;
+  int rc = ensure_solve_storage(ctx, G, nr);
+  if (rc != VIE_OK) return rc;
+  G.roff_host.assign(nr, 0);
+  int64_t vlen = 0;
+  for (int b : G.bodies) {
+    BodyRec& B = *ctx->bodies[b];
+    for (int q = 0; q < B.nrhs; ++q) {
+      G.roff_host[B.rhs0 + q] = vlen;
+      vlen += 3 * (int64_t)B.nb;
     }
   }
-  for (auto& Gp : ctx->groups) {
-    Group& G = *Gp;
-    int nr = 0;
-    for (int b : G.bodies) {
-      BodyRec& B = *ctx->bodies[b];
-      B.rhs0 = nr;
-      B.nrhs = nrhs_per_body[b];
-      nr += B.nrhs;
-    }
-    G.g.nrhs = nr;
-    if (nr == 0) continue;
-    int rc = ensure_solve_storage(ctx, G, nr);
-    if (rc != VIE_OK) return rc;
-    G.roff_host.assign(nr, 0);
-    int64_t vlen = 0;
-    for (int b : G.bodies) {
-      BodyRec& B = *ctx->bodies[b];
-      for (int q = 0; q < B.nrhs; ++q) {
-        G.roff_host[B.rhs0 + q] = vlen;
-        vlen += 3 * (int64_t)B.nb;
-      }
-    }
-    rc = ensure_vectors(ctx, G, std::max<int64_t>(vlen, 1));
-    if (rc != VIE_OK) return rc;
-    VIE_HIP(hipMemcpyAsync(G.roff.p, G.roff_host.data(), nr * sizeof(int64_t),
-                           hipMemcpyHostToDevice, ctx->stream));
-    G.bi.vox = G.vox_all.as<int>();
-    G.bi.line_ptr = G.line_ptr_all.as<int>();
-    G.bi.chic = G.chic_all.as<double>();
-    G.bi.nb = G.nb_arr.as<int>();
-    G.bi.voff = G.voff_arr.as<int>();
-    G.bi.roff = G.roff.as<int64_t>();
-    G.bi.rhs_body = G.rhs_body.as<int>();
-    const int L = G.g.N[0] + G.g.N[1] + G.g.N[2];
-    std::vector<int> rb(nr);
-    std::vector<c64> pol((size_t)nr * 3), ph((size_t)nr * L);
-    for (int b : G.bodies) {
-      BodyRec& B = *ctx->bodies[b];
-      for (int q = 0; q < B.nrhs; ++q) {
-        const int gi = B.rhs0 + q;
-        rb[gi] = B.slot;
+  rc = ensure_vectors(ctx, G, std::max<int64_t>(vlen, 1));
+  if (rc != VIE_OK) return rc;
+  VIE_HIP(hipMemcpyAsync(G.roff.p, G.roff_host.data(), nr * sizeof(int64_t),
+                         hipMemcpyHostToDevice, ctx->stream));
+  G.bi.vox = G.vox_all.as<int>();
+  G.bi.line_ptr = G.line_ptr_all.as<int>();
+  G.bi.chic = G.chic_all.as<double>();
+  G.bi.nb = G.nb_arr.as<int>();
+  G.bi.voff = G.voff_arr.as<int>();
+  G.bi.roff = G.roff.as<int64_t>();
+  G.bi.rhs_body = G.rhs_body.as<int>();
+  const int L = G.g.N[0] + G.g.N[1] + G.g.N[2];
+  std::vector<int> rb(nr);
+  std::vector<c64> pol((size_t)nr * 3), ph((size_t)nr * L);
+  for (int b : G.bodies) {
+    BodyRec& B = *ctx->bodies[b];
+    for (int q = 0; q < B.nrhs; ++q) {
+      const int gi = B.rhs0 + q;
+      rb[gi] = B.slot;
+      if (inc)
         planewave_tables(inc[first[b] + q], G, B.origin, ctx->opt.k0, &pol[(size_t)gi * 3],
                          &ph[(size_t)gi * L]);
-      }
     }
-    VIE_HIP(hipMemcpyAsync(G.rhs_body.p, rb.data(), nr * sizeof(int), hipMemcpyHostToDevice,
-                           ctx->stream));
-    VIE_HIP(hipMemcpyAsync(G.pol.p, pol.data(), pol.size() * sizeof(c64), hipMemcpyHostToDevice,
-                           ctx->stream));
-    VIE_HIP(hipMemcpyAsync(G.ph.p, ph.data(), ph.size() * sizeof(c64), hipMemcpyHostToDevice,
-                           ctx->stream));
+  }
+  VIE_HIP(hipMemcpyAsync(G.rhs_body.p, rb.data(), nr * sizeof(int), hipMemcpyHostToDevice,
+                         ctx->stream));
+  VIE_HIP(hipMemcpyAsync(G.pol.p, pol.data(), pol.size() * sizeof(c64), hipMemcpyHostToDevice,
+                         ctx->stream));
+  VIE_HIP(hipMemcpyAsync(G.ph.p, ph.data(), ph.size() * sizeof(c64), hipMemcpyHostToDevice,
+                         ctx->stream));
+  // the host tables must outlive the copies
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  return VIE_OK;
+}
+
+extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* nrhs_per_body,
+                         vie_stats* stats) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  if (!inc || !nrhs_per_body) return VIE_EINVAL;
+  std::vector<int> first;
+  int rc = check_channels(ctx, inc, nrhs_per_body, first);
+  if (rc != VIE_OK) return rc;
+  if (ctx->opt.warm_start && !ctx->cnn) return VIE_EINVAL;  // warm start needs vie_attach_cnn
+  for (auto& Gp : ctx->groups) {
+    Group& G = *Gp;
+    rc = bind_rhs(ctx, G, inc, nrhs_per_body, first);
+    if (rc != VIE_OK) return rc;
+    if (G.g.nrhs == 0) continue;
     std::vector<int> fb;
     G.samples_ready = false;
     rc = solve_group(ctx, G, ctx->opt.warm_start != 0, fb);
@@ -1000,6 +1107,551 @@ extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* 
   }
   timing_collect(ctx);
   return all_conv ? VIE_OK : VIE_ENOCONV;
+}
+
+// ------------------------------------------------- flexible GMRES (FGMRES)
+// Restarted FGMRES with right preconditioning (Saad 1993) and the block
+// preconditioner of the paper's large metasurface solve (Sec. IV, 7 x 7
+// blocks), read as block Jacobi over a lateral partition with inexact block
+// solves: k steps of GMRES from zero on every block.  The block solves of all
+// blocks and right-hand sides run as one batched product on a sub-context.
+
+static bool valid_fgmres(const vie_fgmres_options* fo, const GroupGeom& g) {
+  if (!fo) return false;
+  if (fo->restart < 1 || fo->restart > 128) return false;
+  if (fo->blocks[0] == 0 && fo->blocks[1] == 0) return true;
+  for (int a = 0; a < 2; ++a)
+    if (fo->blocks[a] < 1 || fo->blocks[a] > 64 || fo->blocks[a] > g.N[a]) return false;
+  if (fo->inner_iters < 1 || fo->inner_iters > 64) return false;
+  return fo->inner_precision == VIE_FP64 || fo->inner_precision == VIE_MIXED;
+}
+
+// Storage of an Arnoldi process of m steps over nseg segments of at most
+// maxlen elements, total elements per vector.
+static int arnoldi_alloc(vie_ctx* ctx, ArnoldiBufs& A, int nseg, int maxlen, int64_t total, int m,
+                         bool flexible) {
+  const int nblk = seg_blocks(maxlen);
+  const size_t vb = (size_t)std::max<int64_t>(total, 1) * sizeof(c64);
+  VIE_HIP(A.V.reserve((size_t)(m + 1) * vb));
+  if (flexible) VIE_HIP(A.Z.reserve((size_t)m * vb));
+  VIE_HIP(A.w.reserve(vb));
+  VIE_HIP(A.H1.reserve((size_t)nseg * m * (m + 1) * sizeof(c64)));
+  VIE_HIP(A.H2.reserve((size_t)nseg * m * (m + 1) * sizeof(c64)));
+  VIE_HIP(A.NR.reserve((size_t)nseg * (m + 1) * sizeof(double)));
+  VIE_HIP(A.dpart.reserve((size_t)nseg * (m + 1) * nblk * sizeof(c64)));
+  VIE_HIP(A.npart.reserve((size_t)nseg * nblk * sizeof(double)));
+  VIE_HIP(A.off.reserve((size_t)nseg * sizeof(int64_t)));
+  VIE_HIP(A.len.reserve((size_t)nseg * sizeof(int)));
+  VIE_HIP(A.act.reserve((size_t)nseg * sizeof(int)));
+  VIE_HIP(A.nvs.reserve((size_t)nseg * sizeof(int)));
+  VIE_HIP(A.coef.reserve((size_t)nseg * (m + 1) * sizeof(c64)));
+  return VIE_OK;
+}
+
+static int arnoldi_tables(vie_ctx* ctx, ArnoldiBufs& A, const std::vector<int64_t>& off,
+                          const std::vector<int>& len) {
+  VIE_HIP(hipMemcpyAsync(A.off.p, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                         ctx->stream));
+  VIE_HIP(hipMemcpyAsync(A.len.p, len.data(), len.size() * sizeof(int), hipMemcpyHostToDevice,
+                         ctx->stream));
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  return VIE_OK;
+}
+
+// Step j of the Arnoldi process after the caller has put the product into w:
+// classical Gram-Schmidt against V_0..V_j applied twice (both coefficient
+// passes kept in H1, H2), ||w||^2 into NR[s][j+1], V_{j+1} = w / ||w||.
+static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, int64_t stride,
+                               int m, int j) {
+  c64* V = A.V.as<c64>();
+  c64* w = A.w.as<c64>();
+  const int ldh = m + 1;
+  c64* h1 = A.H1.as<c64>() + (size_t)j * S.nseg * (m + 1);
+  c64* h2 = A.H2.as<c64>() + (size_t)j * S.nseg * (m + 1);
+  double* nr = A.NR.as<double>() + j + 1;
+  hipError_t e;
+  if ((e = launch_seg_mdot(S, V, stride, j + 1, w, A.dpart.as<c64>(), h1, ldh, ctx->stream)) !=
+      hipSuccess)
+    return e;
+  if ((e = launch_seg_maxpy(S, V, stride, j + 1, nullptr, h1, ldh, w, nullptr, nullptr, 0,
+                            ctx->stream)) != hipSuccess)
+    return e;
+  if ((e = launch_seg_mdot(S, V, stride, j + 1, w, A.dpart.as<c64>(), h2, ldh, ctx->stream)) !=
+      hipSuccess)
+    return e;
+  if ((e = launch_seg_maxpy(S, V, stride, j + 1, nullptr, h2, ldh, w, A.npart.as<double>(), nr,
+                            m + 1, ctx->stream)) != hipSuccess)
+    return e;
+  return launch_seg_normalize(S, w, nr, m + 1, V + (size_t)(j + 1) * stride, ctx->stream);
+}
+
+// Block partition of the context's only body into bx x by lateral blocks:
+// x part p covers voxels [floor(p N1 / bx), floor((p + 1) N1 / bx)), y alike,
+// every block the full z extent.  Each non-empty block becomes one body of a
+// sub-context: its voxels cropped to their own bounding box and placed at the
+// origin of a common grid (the largest box extent per axis); the other voxels
+// of that grid have eps = 1.  Couplings depend on voxel offsets only, so the
+// block's operator is exactly the full operator restricted to the block, and
+// the crop keeps the ascending voxel order of the body's vector.
+static int bj_build(vie_ctx* ctx, const vie_fgmres_options* fo) {
+  const int bx = fo->blocks[0], by = fo->blocks[1];
+  if (ctx->bj && ctx->bj->bx == bx && ctx->bj->by == by) return VIE_OK;
+  if (ctx->bj && ctx->bj->sub) ctx->bj->sub->stream = ctx->bj->sub->own_stream;
+  ctx->bj.reset();
+  BodyRec& B = *ctx->bodies[0];
+  Group& G = *ctx->groups[B.group];
+  const int N1 = G.g.N[0], N2 = G.g.N[1];
+  const int nb = B.nb;
+  std::vector<double> chic(nb);
+  if (nb > 0) {
+    VIE_HIP(hipMemcpyAsync(chic.data(), G.chic_all.as<double>() + G.voff_host[B.slot],
+                           nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    VIE_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  auto parts = [](int n, int np, std::vector<int>& of, std::vector<int>& lo) {
+    lo.resize(np + 1);
+    for (int p = 0; p <= np; ++p) lo[p] = (int)((int64_t)p * n / np);
+    of.assign(n, 0);
+    for (int p = 0; p < np; ++p)
+      for (int i = lo[p]; i < lo[p + 1]; ++i) of[i] = p;
+  };
+  std::vector<int> px, py, lox, loy;
+  parts(N1, bx, px, lox);
+  parts(N2, by, py, loy);
+  const int* vx = G.vox_host.data() + G.voff_host[B.slot];
+  std::vector<std::vector<int>> members((size_t)bx * by);
+  std::vector<int> blo((size_t)bx * by * 3, INT32_MAX), bhi((size_t)bx * by * 3, -1);
+  for (int k = 0; k < nb; ++k) {
+    const int v = vx[k];
+    const int c[3] = {v % N1, (v / N1) % N2, v / (N1 * N2)};
+    const size_t id = px[c[0]] + (size_t)bx * py[c[1]];
+    members[id].push_back(k);
+    for (int a = 0; a < 3; ++a) {
+      blo[id * 3 + a] = std::min(blo[id * 3 + a], c[a]);
+      bhi[id * 3 + a] = std::max(bhi[id * 3 + a], c[a]);
+    }
+  }
+  int ext[3] = {1, 1, 1};
+  for (size_t id = 0; id < members.size(); ++id)
+    if (!members[id].empty())
+      for (int a = 0; a < 3; ++a) ext[a] = std::max(ext[a], bhi[id * 3 + a] - blo[id * 3 + a] + 1);
+  const int mx = ext[0], my = ext[1], mz = ext[2];
+  auto P = std::make_unique<BlockPrec>();
+  P->bx = bx;
+  P->by = by;
+  P->len = 3 * (int64_t)nb;
+  std::vector<std::vector<double>> eps;
+  std::vector<int> perm((size_t)P->len);
+  int64_t acc = 0;
+  for (int id = 0; id < bx * by; ++id) {
+    const std::vector<int>& mem = members[id];
+    if (mem.empty()) continue;
+    const int x0 = blo[(size_t)id * 3], y0 = blo[(size_t)id * 3 + 1], z0 = blo[(size_t)id * 3 + 2];
+    eps.emplace_back((size_t)mx * my * mz, 1.0);
+    std::vector<double>& e = eps.back();
+    const int nbb = (int)mem.size();
+    for (int t = 0; t < nbb; ++t) {
+      const int v = vx[mem[t]];
+      const int i = v % N1 - x0, j = (v / N1) % N2 - y0, kz = v / (N1 * N2) - z0;
+      e[i + (size_t)mx * (j + (size_t)my * kz)] = 1.0 + chic[mem[t]];
+      for (int c = 0; c < 3; ++c) perm[acc + (int64_t)c * nbb + t] = c * nb + mem[t];
+    }
+    P->boff.push_back(acc);
+    P->blen.push_back(3 * nbb);
+    acc += 3 * nbb;
+  }
+  P->nblk = (int)eps.size();
+  std::vector<vie_body> bodies(P->nblk);
+  for (int b = 0; b < P->nblk; ++b) {
+    bodies[b].n[0] = mx;
+    bodies[b].n[1] = my;
+    bodies[b].n[2] = mz;
+    bodies[b].h = G.h;
+    bodies[b].origin[0] = bodies[b].origin[1] = bodies[b].origin[2] = 0.0;
+    bodies[b].eps_r = eps[b].data();
+  }
+  vie_options so = ctx->opt;
+  so.precision = VIE_MIXED;
+  so.inner_tol = 1e-3;
+  so.warm_start = 0;
+  so.flags = VIE_FLAG_NO_GRAPH;
+  int rc = vie_setup(bodies.data(), P->nblk, &so, &P->sub);
+  if (rc != VIE_OK) return rc;
+  // the sub-context's compressed order must be the block order used above
+  if (P->sub->groups.size() != 1) return VIE_EDEVICE;
+  for (int b = 0; b < P->nblk; ++b)
+    if (3 * P->sub->bodies[b]->nb != P->blen[b] || P->sub->bodies[b]->slot != b) return VIE_EDEVICE;
+  VIE_HIP(P->perm.reserve(std::max<size_t>(perm.size(), 1) * sizeof(int)));
+  if (!perm.empty())
+    VIE_HIP(hipMemcpy(P->perm.p, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice));
+  ctx->bj = std::move(P);
+  return VIE_OK;
+}
+
+// Segment tables of the block solves for nrhs right-hand sides: segment
+// q * nblk + b is block b of right-hand side q.
+static int bj_bind(vie_ctx* ctx, int nrhs, int k) {
+  BlockPrec& P = *ctx->bj;
+  if (P.nrhs == nrhs) return VIE_OK;
+  vie_ctx* sub = P.sub;
+  sub->stream = ctx->stream;
+  Group& Gp = *sub->groups[0];
+  const int nseg = nrhs * P.nblk;
+  std::vector<int64_t> off(nseg);
+  std::vector<int> len(nseg), rb(nseg);
+  int maxlen = 1;
+  for (int q = 0; q < nrhs; ++q)
+    for (int b = 0; b < P.nblk; ++b) {
+      const int s = q * P.nblk + b;
+      off[s] = q * P.len + P.boff[b];
+      len[s] = P.blen[b];
+      rb[s] = b;
+      maxlen = std::max(maxlen, len[s]);
+    }
+  Gp.g.nrhs = nseg;
+  int rc = ensure_solve_storage(sub, Gp, nseg);
+  if (rc != VIE_OK) return rc;
+  Gp.roff_host = off;
+  VIE_HIP(hipMemcpyAsync(Gp.roff.p, off.data(), nseg * sizeof(int64_t), hipMemcpyHostToDevice,
+                         ctx->stream));
+  VIE_HIP(hipMemcpyAsync(Gp.rhs_body.p, rb.data(), nseg * sizeof(int), hipMemcpyHostToDevice,
+                         ctx->stream));
+  Gp.bi.vox = Gp.vox_all.as<int>();
+  Gp.bi.line_ptr = Gp.line_ptr_all.as<int>();
+  Gp.bi.chic = Gp.chic_all.as<double>();
+  Gp.bi.nb = Gp.nb_arr.as<int>();
+  Gp.bi.voff = Gp.voff_arr.as<int>();
+  Gp.bi.roff = Gp.roff.as<int64_t>();
+  Gp.bi.rhs_body = Gp.rhs_body.as<int>();
+  const int64_t tot = nrhs * P.len;
+  rc = arnoldi_alloc(ctx, P.ab, nseg, maxlen, tot, k, false);
+  if (rc != VIE_OK) return rc;
+  rc = arnoldi_tables(ctx, P.ab, off, len);
+  if (rc != VIE_OK) return rc;
+  VIE_HIP(P.R.reserve((size_t)std::max<int64_t>(tot, 1) * sizeof(c64)));
+  VIE_HIP(P.X.reserve((size_t)std::max<int64_t>(tot, 1) * sizeof(c64)));
+  P.nrhs = nrhs;
+  return VIE_OK;
+}
+
+// z = M^{-1} v for nrhs body-compressed vectors (v, z device, nrhs * 3 nb
+// elements); right-hand sides with act[q] == 0 get z = 0.
+static int bj_apply(vie_ctx* ctx, const vie_fgmres_options* fo, const c64* v, c64* z,
+                    const std::vector<int>& act, int nrhs) {
+  BlockPrec& P = *ctx->bj;
+  vie_ctx* sub = P.sub;
+  sub->stream = ctx->stream;
+  Group& Gp = *sub->groups[0];
+  ArnoldiBufs& A = P.ab;
+  const int k = fo->inner_iters;
+  const int ip = fo->inner_precision == VIE_MIXED ? 1 : 0;
+  const int nseg = nrhs * P.nblk;
+  const int64_t tot = nrhs * P.len;
+  int maxlen = 1;
+  for (int l : P.blen) maxlen = std::max(maxlen, l);
+  int rc = arnoldi_alloc(ctx, A, nseg, maxlen, tot, k, false);  // grows for a larger k
+  if (rc != VIE_OK) return rc;
+  SegSet S{A.off.as<int64_t>(), A.len.as<int>(), A.act.as<int>(), nseg, seg_blocks(maxlen)};
+  std::vector<int> act_s(nseg), nvs(nseg, 0);
+  for (int s = 0; s < nseg; ++s) act_s[s] = act[s / P.nblk] ? 1 : 0;
+  VIE_HIP(hipMemcpyAsync(A.act.p, act_s.data(), nseg * sizeof(int), hipMemcpyHostToDevice,
+                         ctx->stream));
+  c64* R = P.R.as<c64>();
+  c64* V = A.V.as<c64>();
+  double* NR = A.NR.as<double>();
+  const int ldn = k + 1;
+  VIE_HIP(launch_permute(nrhs, P.len, P.perm.as<int>(), v, R, 0, ctx->stream));
+  VIE_HIP(launch_seg_maxpy(S, nullptr, 0, 0, nullptr, nullptr, 0, R, A.npart.as<double>(), NR,
+                           ldn, ctx->stream));
+  VIE_HIP(launch_seg_normalize(S, R, NR, ldn, V, ctx->stream));
+  for (int j = 0; j < k; ++j) {
+    EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
+    VIE_HIP(run_matvec(sub, Gp, ip, V + (size_t)j * tot, A.w.as<c64>(), e, A.act.as<int>()));
+    VIE_HIP(arnoldi_orth(ctx, A, S, tot, k, j));
+  }
+  std::vector<c64> h1((size_t)k * nseg * ldn), h2((size_t)k * nseg * ldn), coef((size_t)nseg * ldn);
+  std::vector<double> nr((size_t)nseg * ldn);
+  VIE_HIP(hipMemcpyAsync(h1.data(), A.H1.p, h1.size() * sizeof(c64), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  VIE_HIP(hipMemcpyAsync(h2.data(), A.H2.p, h2.size() * sizeof(c64), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  VIE_HIP(hipMemcpyAsync(nr.data(), NR, nr.size() * sizeof(double), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  HessLS ls;
+  std::vector<c64> h(k + 1), y(k);
+  int maxst = 0;
+  for (int s = 0; s < nseg; ++s) {
+    if (!act_s[s]) continue;
+    const double beta = sqrt(std::max(nr[(size_t)s * ldn], 0.0));
+    if (!(beta > 0)) continue;
+    ls.reset(k, beta);
+    int steps = 0;
+    for (int j = 0; j < k; ++j) {
+      for (int i = 0; i <= j; ++i)
+        h[i] = h1[((size_t)j * nseg + s) * ldn + i] + h2[((size_t)j * nseg + s) * ldn + i];
+      const double hn = sqrt(std::max(nr[(size_t)s * ldn + j + 1], 0.0));
+      ls.add(j, h.data(), hn);
+      steps = j + 1;
+      if (hn <= 1e-14 * beta) break;
+    }
+    ls.solve(steps, y.data());
+    for (int i = 0; i < steps; ++i) coef[(size_t)s * ldn + i] = mk(0.0, 0.0) - y[i];
+    nvs[s] = steps;
+    maxst = std::max(maxst, steps);
+  }
+  VIE_HIP(hipMemcpyAsync(A.coef.p, coef.data(), coef.size() * sizeof(c64), hipMemcpyHostToDevice,
+                         ctx->stream));
+  VIE_HIP(hipMemcpyAsync(A.nvs.p, nvs.data(), nseg * sizeof(int), hipMemcpyHostToDevice,
+                         ctx->stream));
+  VIE_HIP(hipMemsetAsync(P.X.p, 0, (size_t)tot * sizeof(c64), ctx->stream));
+  VIE_HIP(launch_seg_maxpy(S, V, tot, maxst, A.nvs.as<int>(), A.coef.as<c64>(), ldn,
+                           P.X.as<c64>(), nullptr, nullptr, 0, ctx->stream));
+  VIE_HIP(launch_permute(nrhs, P.len, P.perm.as<int>(), P.X.as<c64>(), z, 1, ctx->stream));
+  // the host tables must outlive the copies
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  return VIE_OK;
+}
+
+// Restarted FGMRES on every right-hand side of the one-body group G (bound
+// by bind_rhs), from w = 0.  Arnoldi products in the context's precision;
+// every cycle ends with the FP64 true residual, which alone decides
+// convergence.  A cycle stops early once its residual estimate is below
+// tol / 2.
+static int fgmres_group(vie_ctx* ctx, Group& G, const vie_fgmres_options* fo,
+                        std::vector<int>& steps, std::vector<int>& cycles) {
+  const int nrhs = G.g.nrhs;
+  const int m = fo->restart;
+  const bool flex = fo->blocks[0] > 0 && ctx->bj && ctx->bj->nblk > 0;
+  const int prec = ctx->opt.precision == VIE_MIXED ? 1 : 0;
+  const int len = 3 * ctx->bodies[0]->nb;
+  const int64_t tot = (int64_t)nrhs * len;
+  if (!ctx->fgm) ctx->fgm = std::make_unique<ArnoldiBufs>();
+  ArnoldiBufs& A = *ctx->fgm;
+  int rc = arnoldi_alloc(ctx, A, nrhs, len, tot, m, flex);
+  if (rc != VIE_OK) return rc;
+  rc = arnoldi_tables(ctx, A, G.roff_host, std::vector<int>(nrhs, len));
+  if (rc != VIE_OK) return rc;
+  const SegSet S{A.off.as<int64_t>(), A.len.as<int>(), A.act.as<int>(), nrhs, seg_blocks(len)};
+  FinParams fp;
+  fp.tol2_done = ctx->opt.tol * ctx->opt.tol;
+  fp.tol2_inner = fp.tol2_done;
+  fp.eta2 = 0.0;
+  fp.max_iter = ctx->opt.max_iter;
+  KState* st = G.state.as<KState>();
+  int* flags = G.flags.as<int>();
+  int* notdone = flags + nrhs;
+  c64* part = G.partials.as<c64>();
+  c64 *x = G.x.as<c64>(), *r = G.r.as<c64>(), *rh = G.rh.as<c64>();
+  const c64* pol = G.pol.as<c64>();
+  const c64* ph = G.ph.as<c64>();
+  const int vb = vec_blocks_group(G);
+  VIE_HIP(launch_init_zero_guess(G.g, G.bi, vb, pol, ph, x, r, rh, part, 0, nullptr, ctx->stream));
+  VIE_HIP(launch_finalize(FIN_INIT, nrhs, vb, part, st, flags, fp, ctx->stream));
+  std::vector<KState> hs(nrhs);
+  VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  steps.assign(nrhs, 0);
+  cycles.assign(nrhs, 0);
+  const int maxit = ctx->opt.max_iter;
+  c64* V = A.V.as<c64>();
+  c64* Z = flex ? A.Z.as<c64>() : V;
+  double* NR = A.NR.as<double>();
+  std::vector<int> act(nrhs), nst(nrhs), mc(nrhs);
+  std::vector<HessLS> ls(nrhs);
+  std::vector<c64> h1((size_t)nrhs * (m + 1)), h2((size_t)nrhs * (m + 1)), hc(m + 1), y(m);
+  std::vector<c64> coef((size_t)nrhs * (m + 1));
+  std::vector<double> nr((size_t)nrhs * (m + 1));
+  for (;;) {
+    bool any = false;
+    for (int q = 0; q < nrhs; ++q) {
+      act[q] = (hs[q].notdone && steps[q] < maxit) ? 1 : 0;
+      any |= act[q] != 0;
+    }
+    if (!any) break;
+    VIE_HIP(hipMemcpyAsync(A.act.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+                           ctx->stream));
+    VIE_HIP(launch_seg_maxpy(S, nullptr, 0, 0, nullptr, nullptr, 0, r, A.npart.as<double>(), NR,
+                             m + 1, ctx->stream));
+    VIE_HIP(launch_seg_normalize(S, r, NR, m + 1, V, ctx->stream));
+    for (int q = 0; q < nrhs; ++q) {
+      nst[q] = 0;
+      if (!act[q]) continue;
+      ls[q].reset(m, sqrt(hs[q].rnorm2));
+      mc[q] = std::min(m, maxit - steps[q]);
+    }
+    for (int j = 0; j < m; ++j) {
+      c64* vj = V + (size_t)j * tot;
+      c64* zj = Z + (size_t)j * tot;
+      if (flex) {
+        rc = bj_apply(ctx, fo, vj, zj, act, nrhs);
+        if (rc != VIE_OK) return rc;
+      }
+      EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
+      VIE_HIP(run_matvec(ctx, G, prec, zj, A.w.as<c64>(), e, A.act.as<int>()));
+      VIE_HIP(arnoldi_orth(ctx, A, S, tot, m, j));
+      VIE_HIP(hipMemcpyAsync(h1.data(), A.H1.as<c64>() + (size_t)j * nrhs * (m + 1),
+                             h1.size() * sizeof(c64), hipMemcpyDeviceToHost, ctx->stream));
+      VIE_HIP(hipMemcpyAsync(h2.data(), A.H2.as<c64>() + (size_t)j * nrhs * (m + 1),
+                             h2.size() * sizeof(c64), hipMemcpyDeviceToHost, ctx->stream));
+      VIE_HIP(hipMemcpyAsync(nr.data(), NR, nr.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream));
+      VIE_HIP(hipStreamSynchronize(ctx->stream));
+      bool more = false, changed = false;
+      for (int q = 0; q < nrhs; ++q) {
+        if (!act[q]) continue;
+        for (int i = 0; i <= j; ++i) hc[i] = h1[(size_t)q * (m + 1) + i] + h2[(size_t)q * (m + 1) + i];
+        const double hn = sqrt(std::max(nr[(size_t)q * (m + 1) + j + 1], 0.0));
+        const double est = ls[q].add(j, hc.data(), hn);
+        nst[q] = j + 1;
+        steps[q] += 1;
+        const double beta = sqrt(hs[q].rnorm2);
+        if (est <= 0.5 * ctx->opt.tol * sqrt(hs[q].bnorm2) || nst[q] >= mc[q] ||
+            hn <= 1e-14 * beta) {
+          act[q] = 0;
+          changed = true;
+        } else {
+          more = true;
+        }
+      }
+      if (!more) break;
+      if (changed)
+        VIE_HIP(hipMemcpyAsync(A.act.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+                               ctx->stream));
+    }
+    // x += Z y for every right-hand side that took steps in this cycle
+    int maxst = 0;
+    std::fill(coef.begin(), coef.end(), mk(0.0, 0.0));
+    for (int q = 0; q < nrhs; ++q) {
+      act[q] = nst[q] > 0 ? 1 : 0;
+      if (!act[q]) continue;
+      ls[q].solve(nst[q], y.data());
+      for (int i = 0; i < nst[q]; ++i) coef[(size_t)q * (m + 1) + i] = mk(0.0, 0.0) - y[i];
+      maxst = std::max(maxst, nst[q]);
+    }
+    VIE_HIP(hipMemcpyAsync(A.act.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+                           ctx->stream));
+    VIE_HIP(hipMemcpyAsync(A.nvs.p, nst.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+                           ctx->stream));
+    VIE_HIP(hipMemcpyAsync(A.coef.p, coef.data(), coef.size() * sizeof(c64), hipMemcpyHostToDevice,
+                           ctx->stream));
+    VIE_HIP(launch_seg_maxpy(S, Z, tot, maxst, A.nvs.as<int>(), A.coef.as<c64>(), m + 1, x,
+                             nullptr, nullptr, 0, ctx->stream));
+    // true residual with the FP64 product
+    EpiArgs e{EPI_RESID, rh, part, 0, pol, ph};
+    VIE_HIP(run_matvec(ctx, G, 0, x, r, e, notdone));
+    VIE_HIP(launch_finalize(FIN_RESTART, nrhs, e.part_blocks, part, st, flags, fp, ctx->stream));
+    for (int q = 0; q < nrhs; ++q) cycles[q] += hs[q].notdone ? 1 : 0;
+    VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    VIE_HIP(hipStreamSynchronize(ctx->stream));
+    if (getenv("VIE_LOG"))
+      for (int q = 0; q < nrhs; ++q)
+        fprintf(stderr, "vie: fgmres rhs %d: %d steps, true rel res %.3e\n", q, steps[q],
+                hs[q].bnorm2 > 0 ? sqrt(hs[q].rnorm2 / hs[q].bnorm2) : 0.0);
+  }
+  return VIE_OK;
+}
+
+extern "C" int vie_solve_fgmres(vie_ctx* ctx, const vie_planewave* inc,
+                                const int32_t* nrhs_per_body, const vie_fgmres_options* fo,
+                                vie_stats* stats) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  if (!inc || !nrhs_per_body || !fo) return VIE_EINVAL;
+  if (ctx->bodies.size() != 1) return VIE_ENOTSUP;
+  BodyRec& B = *ctx->bodies[0];
+  Group& G = *ctx->groups[B.group];
+  if (!valid_fgmres(fo, G.g)) return VIE_EINVAL;
+  std::vector<int> first;
+  int rc = check_channels(ctx, inc, nrhs_per_body, first);
+  if (rc != VIE_OK) return rc;
+  rc = bind_rhs(ctx, G, inc, nrhs_per_body, first);
+  if (rc != VIE_OK) return rc;
+  const int nrhs = G.g.nrhs;
+  if (nrhs == 0) return VIE_OK;
+  G.res_x0.assign(nrhs, 1.0);
+  G.fallback.assign(nrhs, 0);
+  G.warm_used.assign(nrhs, 0);
+  G.samples_ready = false;
+  if (fo->blocks[0] > 0 && B.nb > 0) {
+    rc = bj_build(ctx, fo);
+    if (rc != VIE_OK) return rc;
+    rc = bj_bind(ctx, nrhs, fo->inner_iters);
+    if (rc != VIE_OK) return rc;
+  }
+  std::vector<int> steps, cycles;
+  rc = fgmres_group(ctx, G, fo, steps, cycles);
+  if (rc != VIE_OK) return rc;
+  std::vector<KState> hs(nrhs);
+  VIE_HIP(hipMemcpyAsync(hs.data(), G.state.p, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  bool all_conv = true;
+  for (int q = 0; q < nrhs; ++q) {
+    const bool conv = !hs[q].notdone;
+    all_conv &= conv;
+    if (stats) {
+      vie_stats& o = stats[q];
+      o.iters = steps[q];
+      o.matvecs = steps[q] + cycles[q];
+      o.cycles = cycles[q];
+      o.converged = conv;
+      o.fallback = 0;
+      o.warm = 0;
+      o.rel_res = hs[q].bnorm2 > 0 ? sqrt(hs[q].rnorm2 / hs[q].bnorm2) : 0.0;
+      o.rel_res_x0 = 1.0;
+    }
+  }
+  timing_collect(ctx);
+  return all_conv ? VIE_OK : VIE_ENOCONV;
+}
+
+extern "C" int vie_precond_apply(vie_ctx* ctx, const vie_fgmres_options* fo, const vie_c64* r,
+                                 vie_c64* z, int32_t nvec) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  if (!fo || !r || !z || nvec < 1) return VIE_EINVAL;
+  if (ctx->bodies.size() != 1) return VIE_ENOTSUP;
+  BodyRec& B = *ctx->bodies[0];
+  Group& G = *ctx->groups[B.group];
+  if (!valid_fgmres(fo, G.g) || fo->blocks[0] < 1) return VIE_EINVAL;
+  const int64_t n = G.g.n;
+  const int nb = B.nb;
+  const int64_t len = 3 * (int64_t)nb;
+  memset(z, 0, (size_t)nvec * 3 * n * sizeof(vie_c64));
+  if (nb == 0) return VIE_OK;
+  int rc = bj_build(ctx, fo);
+  if (rc != VIE_OK) return rc;
+  rc = bj_bind(ctx, nvec, fo->inner_iters);
+  if (rc != VIE_OK) return rc;
+  const int* vx = G.vox_host.data() + G.voff_host[B.slot];
+  std::vector<c64> hv((size_t)nvec * len), hz((size_t)nvec * len);
+  for (int q = 0; q < nvec; ++q)
+    for (int c = 0; c < 3; ++c)
+      for (int k = 0; k < nb; ++k) {
+        const vie_c64& a = r[(size_t)q * 3 * n + (size_t)c * n + vx[k]];
+        hv[(size_t)q * len + (size_t)c * nb + k] = mk(a.re, a.im);
+      }
+  DevBuf dv, dz;
+  VIE_HIP(dv.reserve(hv.size() * sizeof(c64)));
+  VIE_HIP(dz.reserve(hv.size() * sizeof(c64)));
+  VIE_HIP(hipMemcpyAsync(dv.p, hv.data(), hv.size() * sizeof(c64), hipMemcpyHostToDevice,
+                         ctx->stream));
+  rc = bj_apply(ctx, fo, dv.as<c64>(), dz.as<c64>(), std::vector<int>(nvec, 1), nvec);
+  if (rc != VIE_OK) return rc;
+  VIE_HIP(hipMemcpyAsync(hz.data(), dz.p, hz.size() * sizeof(c64), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  for (int q = 0; q < nvec; ++q)
+    for (int c = 0; c < 3; ++c)
+      for (int k = 0; k < nb; ++k) {
+        const c64 a = hz[(size_t)q * len + (size_t)c * nb + k];
+        z[(size_t)q * 3 * n + (size_t)c * n + vx[k]].re = a.re;
+        z[(size_t)q * 3 * n + (size_t)c * n + vx[k]].im = a.im;
+      }
+  return VIE_OK;
 }
 
 // --------------------------------------------------------------- products

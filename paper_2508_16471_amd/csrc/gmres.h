@@ -1,0 +1,51 @@
+// Launchers of the segmented multi-vector kernels used by the flexible GMRES
+// driver and its block-Jacobi preconditioner.
+//
+// A segment is one independent vector of a batched solve (one right-hand
+// side, or one block of one right-hand side): elements [off[s], off[s] +
+// len[s]) of every vector.  A multi-vector holds nv vectors at base + i *
+// stride.  Reductions go through per-workgroup partials summed in a fixed
+// order, so results do not depend on scheduling.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace vie {
+
+struct SegSet {
+  const int64_t* off;  // [nseg] first element of each segment (device)
+  const int* len;      // [nseg] elements (device)
+  const int* active;   // [nseg] (device) or nullptr: segments with 0 are skipped
+  int nseg;
+  int nblk;            // workgroups per segment, from seg_blocks()
+};
+
+int seg_blocks(int64_t max_len);
+
+// out[s * ldo + i] = sum_e conj(V_i[e]) w[e] over segment s, for i < nv
+// (zero for skipped segments).  partials: nseg * nv * nblk c64.
+hipError_t launch_seg_mdot(const SegSet& S, const c64* V, int64_t stride, int nv, const c64* w,
+                           c64* partials, c64* out, int ldo, hipStream_t st);
+
+// w[e] -= sum_{i < n_s} coef[s * ldc + i] V_i[e] with n_s = nv, or
+// min(nv, nv_seg[s]) when nv_seg is given.  With norm2 != nullptr also
+// norm2[s * ldn] = ||w_s||^2 after the update (partials: nseg * nblk doubles).
+// nv = 0 only measures the norm.
+hipError_t launch_seg_maxpy(const SegSet& S, const c64* V, int64_t stride, int nv,
+                            const int* nv_seg, const c64* coef, int ldc, c64* w,
+                            double* partials, double* norm2, int ldn, hipStream_t st);
+
+// dst = src / sqrt(norm2[s * ldn]) per segment (zero where norm2 is 0).
+hipError_t launch_seg_normalize(const SegSet& S, const c64* src, const double* norm2, int ldn,
+                                c64* dst, hipStream_t st);
+
+// nrep repetitions of a permutation of n elements:
+//   gather  (scatter == 0): dst[r * n + j] = src[r * n + perm[j]]
+//   scatter (scatter != 0): dst[r * n + perm[j]] = src[r * n + j]
+hipError_t launch_permute(int nrep, int64_t n, const int* perm, const c64* src, c64* dst,
+                          int scatter, hipStream_t st);
+
+}  // namespace vie

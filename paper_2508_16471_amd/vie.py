@@ -46,6 +46,11 @@ class vie_na_detector(C.Structure):
                 ("pol", vie_c64 * 3)]
 
 
+class vie_fgmres_options(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("blocks", C.c_int32 * 2), ("inner_iters", C.c_int32),
+                ("inner_precision", C.c_int32)]
+
+
 class vie_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("matvecs", C.c_int32), ("cycles", C.c_int32),
                 ("converged", C.c_int32), ("fallback", C.c_int32), ("warm", C.c_int32),
@@ -72,6 +77,10 @@ def lib():
         sig = {
             "vie_setup": (C.c_int, [P(vie_body), C.c_int32, P(vie_options), P(C.c_void_p)]),
             "vie_solve": (C.c_int, [C.c_void_p, P(vie_planewave), P(C.c_int32), P(vie_stats)]),
+            "vie_solve_fgmres": (C.c_int, [C.c_void_p, P(vie_planewave), P(C.c_int32),
+                                           P(vie_fgmres_options), P(vie_stats)]),
+            "vie_precond_apply": (C.c_int, [C.c_void_p, P(vie_fgmres_options), P(vie_c64),
+                                            P(vie_c64), C.c_int32]),
             "vie_farfield": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double),
                                        C.c_int32, P(vie_c64)]),
             "hom_classical_p2": (C.c_int, [P(vie_c64), P(C.c_double)]),
@@ -172,6 +181,39 @@ def vie_solve(ctx, channels, nrhs_per_body, allow_noconv=False):
     _check(rc, "vie_solve", allow=(VIE_ENOCONV,) if allow_noconv else ())
     out = [{f: getattr(st[i], f) for f, _ in vie_stats._fields_} for i in range(len(channels))]
     return rc, out
+
+
+def fgmres_options(restart=30, blocks=(7, 7), inner_iters=4, inner_precision=VIE_MIXED):
+    o = vie_fgmres_options()
+    o.restart = int(restart)
+    o.blocks[0], o.blocks[1] = int(blocks[0]), int(blocks[1])
+    o.inner_iters = int(inner_iters)
+    o.inner_precision = int(inner_precision)
+    return o
+
+
+def vie_solve_fgmres(ctx, channels, nrhs_per_body, fopt, allow_noconv=False):
+    """Preconditioned restarted FGMRES solve of a one-body context; returns
+    (status, list of stats dicts) like vie_solve."""
+    pw = planewaves(channels)
+    nr = (C.c_int32 * len(nrhs_per_body))(*[int(v) for v in nrhs_per_body])
+    st = (vie_stats * max(1, len(channels)))()
+    rc = lib().vie_solve_fgmres(ctx, pw, nr, C.byref(fopt), st)
+    _check(rc, "vie_solve_fgmres", allow=(VIE_ENOCONV,) if allow_noconv else ())
+    out = [{f: getattr(st[i], f) for f, _ in vie_stats._fields_} for i in range(len(channels))]
+    return rc, out
+
+
+def vie_precond_apply(ctx, fopt, r):
+    """z = M^{-1} r (block-Jacobi) for host vectors r[nvec, 3, N3, N2, N1] (or one)."""
+    rs = np.ascontiguousarray(r, dtype=np.complex128)
+    single = rs.ndim == 4
+    if single:
+        rs = rs[None]
+    z = np.zeros_like(rs)
+    _check(lib().vie_precond_apply(ctx, C.byref(fopt), _cptr(rs), _cptr(z), rs.shape[0]),
+           "vie_precond_apply")
+    return z[0] if single else z
 
 
 def vie_farfield(ctx, body, theta, phi, nrhs):
