@@ -754,39 +754,47 @@ def sphere_mode(args):
 def precond_mode(args):
     """The paper's block preconditioner (7 x 7 lateral blocks, read as block
     Jacobi with k-step GMRES block solves) inside restarted FGMRES, against
-    plain restarted GMRES and the mixed BiCGSTAB path, on one body of the
-    benchmark family (--grid, --channels right-hand sides), mixed precision,
-    tol --tol.  Each configuration is run once untimed (sub-problem setup,
-    autotuning) and once timed."""
-    bodies, chans = make_workload(1, args.channels, args.grid)
+    plain restarted GMRES and the mixed BiCGSTAB path, on the benchmark
+    workload (--bodies bodies of --grid^3, --channels each), mixed precision,
+    tol --tol; the best configurations also with the learned warm start.
+    Each configuration is run once untimed (sub-problem setup, autotuning)
+    and once timed."""
+    bodies, chans = make_workload(args.bodies, args.channels, args.grid)
     import torch
 
     from paper_2508_16471_amd import vie as V
 
     torch.cuda.set_device(0)
     V.lib()
-    e, h, o, g = bodies[0]
-    nch = args.channels
+    nb, nch = args.bodies, args.channels
     opt = V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
                          inner_tol=args.inner_tol)
-    ctx = V.vie_setup([(e, h, o)], opt)
-    configs = [("bicgstab_mixed", None, 0)]
-    for m in (30,):
-        configs.append((f"gmres{m}", V.fgmres_options(m, (0, 0)), 0))
-        for bl, k in (((7, 7), 2), ((7, 7), 4), ((8, 8), 2), ((8, 8), 4), ((4, 4), 4),
-                      ((2, 2), 2), ((2, 2), 4), ((2, 2), 8), ((1, 1), 4)):
-            configs.append((f"fgmres{m}_bj{bl[0]}x{bl[1]}_k{k}",
-                            V.fgmres_options(m, bl, k, V.VIE_MIXED), k))
+    opt_warm = V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
+                              inner_tol=args.inner_tol, warm_start=1)
+    ctx = V.vie_setup([(e, h, o) for e, h, o, _ in bodies], opt)
+    net = V.vie_cnn_create(0)
+    V.vie_cnn_params(net, np.load(args.weights))
+    configs = [("bicgstab_mixed", None, 0, 0), ("gmres30", V.fgmres_options(30, (0, 0)), 0, 0)]
+    for m, bl, k in ((30, (7, 7), 2), (30, (7, 7), 4), (30, (8, 8), 2), (30, (8, 8), 4),
+                     (30, (4, 4), 4), (30, (4, 4), 8), (30, (2, 2), 2), (30, (2, 2), 4),
+                     (30, (2, 2), 8), (60, (2, 2), 8), (30, (2, 2), 16), (30, (1, 1), 4)):
+        configs.append((f"fgmres{m}_bj{bl[0]}x{bl[1]}_k{k}",
+                        V.fgmres_options(m, bl, k, V.VIE_MIXED), k, 0))
+    configs += [("bicgstab_mixed_learned", None, 0, 1),
+                ("fgmres60_bj2x2_k8_learned", V.fgmres_options(60, (2, 2), 8, V.VIE_MIXED), 8, 1)]
     if args.configs:
         keep = set(args.configs.split(","))
         configs = [c for c in configs if c[0] in keep or c[0] == "bicgstab_mixed"]
     res = {}
     try:
-        for name, fo, k in configs:
+        for name, fo, k, warm in configs:
+            V.vie_set_options(ctx, opt_warm if warm else opt)
+            V.vie_attach_cnn(ctx, net if warm else None)
+
             def run():
                 if fo is None:
-                    return V.vie_solve(ctx, chans, [nch], allow_noconv=True)[1]
-                return V.vie_solve_fgmres(ctx, chans, [nch], fo, allow_noconv=True)[1]
+                    return V.vie_solve(ctx, chans, [nch] * nb, allow_noconv=True)[1]
+                return V.vie_solve_fgmres(ctx, chans, [nch] * nb, fo, allow_noconv=True)[1]
 
             run()
             torch.cuda.synchronize()
@@ -795,20 +803,24 @@ def precond_mode(args):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             it = float(np.mean([s["iters"] for s in st]))
-            r = {"solves_per_s": nch / dt, "ms_per_solve": 1e3 * dt / nch,
+            r = {"solves_per_s": nb * nch / dt, "ms_per_solve": 1e3 * dt / (nb * nch),
                  "iterations": it, "operator_products": float(np.mean([s["matvecs"] for s in st])),
                  "block_products": it * k, "converged": all(s["converged"] for s in st),
                  "max_rel_res": max(s["rel_res"] for s in st)}
+            if warm:
+                r["initial_rel_res"] = float(np.mean([s["rel_res_x0"] for s in st]))
+                r["fallbacks"] = int(sum(s["fallback"] for s in st))
             res[name] = r
             print(f"precond {name}: {r}", file=sys.stderr, flush=True)
     finally:
         V.vie_destroy(ctx)
+        V.vie_cnn_destroy(net)
     base = res["bicgstab_mixed"]["solves_per_s"]
-    print(json.dumps({"metric": "VIE solves/s at rel. residual %g, one body (%d^3 grid)" % (args.tol, args.grid),
+    print(json.dumps({"metric": "VIE solves/s at rel. residual %g (%d^3 grid)" % (args.tol, args.grid),
                       "value": max(r["solves_per_s"] for r in res.values()), "unit": "solves/s",
                       "n_gpus": 1, "mode": "precond", "data": "synthetic",
                       "config": {"workload": f"metasurface family {args.grid}^3, h = lambda/32, "
-                                             f"{nch} channels, mixed precision"},
+                                             f"{nb} bodies x {nch} channels, mixed precision"},
                       "configs": res,
                       "speedup_vs_bicgstab": {k: v["solves_per_s"] / base for k, v in res.items()}}))
 

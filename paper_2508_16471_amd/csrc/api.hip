@@ -135,21 +135,29 @@ struct ArnoldiBufs {
   DevBuf V, Z, w, H1, H2, NR, dpart, npart, off, len, act, nvs, coef;
 };
 
-// Block-Jacobi preconditioner of a one-body context: the body split into
-// bx x by lateral blocks, each non-empty block one body of a sub-context on a
-// common padded grid, so that the block products of every right-hand side
-// run as one batched product.
+// Block-Jacobi preconditioner of one group: every body split into bx x by
+// lateral blocks, each non-empty block one body of a sub-context on a common
+// cropped grid, so that the block solves of all blocks, bodies and
+// right-hand sides run as one batched product.
 struct BlockPrec {
   int bx = 0, by = 0;
-  vie_ctx* sub = nullptr;       // owned; its stream is set to the parent's per use
-  int nblk = 0;                 // non-empty blocks
-  int64_t len = 0;              // 3 nb: elements of one right-hand side's vector
-  std::vector<int64_t> boff;    // element offset of each block in the permuted vector
-  std::vector<int> blen;        // elements of each block (3 nb_b)
-  DevBuf perm;                  // int [len]: permuted position -> body vector position
-  int nrhs = 0;                 // right-hand sides the segment tables are bound for
+  vie_ctx* sub = nullptr;        // owned; its stream is set to the parent's per use
+  int nsub = 0;                  // sub-context bodies (non-empty blocks of all bodies)
+  std::vector<int> first_blk;    // [slot] first sub-context body of each body of the group
+  std::vector<int> nblk_of;      // [slot] its non-empty blocks
+  std::vector<int64_t> boff;     // [sub body] element offset in its body's permuted vector
+  std::vector<int> blen;         // [sub body] elements (3 nb of the block)
+  std::vector<int64_t> poff;     // [slot] offset of the body's permutation in perm
+  DevBuf perm;                   // int, per body: permuted position -> body vector position
+  // binding of the current right-hand sides
+  std::vector<int> bound_rb;     // body slot of every right-hand side
+  std::vector<int64_t> bound_roff;
+  std::vector<int> seg_rhs;      // [segment] right-hand side
+  int nseg = 0, maxlen = 1, maxqlen = 1;
+  int64_t tot = 0;               // elements of all right-hand sides' vectors
+  DevBuf qoff, qpoff, qlen;      // [rhs] vector offset, permutation offset, elements
   ArnoldiBufs ab;
-  DevBuf R, X;                  // permuted input, block solution
+  DevBuf R, X;                   // permuted input, block solution
   ~BlockPrec() {
     if (sub) vie_destroy(sub);
   }
@@ -242,7 +250,7 @@ struct vie_ctx {
   hipEvent_t flag_ev[2] = {nullptr, nullptr};
   // flexible GMRES and its block-Jacobi preconditioner (built on first use)
   std::unique_ptr<ArnoldiBufs> fgm;
-  std::unique_ptr<BlockPrec> bj;
+  std::vector<std::unique_ptr<BlockPrec>> bj;  // [group]
 };
 
 // --------------------------------------------------------------- utilities
@@ -511,8 +519,9 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
 extern "C" void vie_destroy(vie_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  if (ctx->bj && ctx->bj->sub) ctx->bj->sub->stream = ctx->bj->sub->own_stream;
-  ctx->bj.reset();
+  for (auto& P : ctx->bj)
+    if (P && P->sub) P->sub->stream = P->sub->own_stream;
+  ctx->bj.clear();
   ctx->fgm.reset();
   ctx->groups.clear();
   ctx->bodies.clear();
@@ -749,6 +758,75 @@ static int predict_x0(vie_ctx* ctx, Group& G) {
 // then recomputes the true residual with the FP64 product and restarts.
 // With VIE_MIXED this is FP64 iterative refinement around an FP32-product
 // inner solver; with VIE_FP64 the restart only confirms convergence.
+// Learned warm start after the zero-guess init (r = b, KState as after
+// FIN_INIT): the network's guess x0 for every right-hand side, its true
+// residual, and x0 = 0 again wherever ||b - A x0|| >= ||b||.  Leaves x, r, rhat
+// and KState / flags as after a restart; records res_x0, fallback, warm_used.
+static int warm_start_init(vie_ctx* ctx, Group& G, const FinParams& fp,
+                           std::vector<int>& fallback_out) {
+  const GroupGeom& g = G.g;
+  const int nrhs = g.nrhs;
+  KState* st = G.state.as<KState>();
+  int* flags = G.flags.as<int>();
+  int* active = flags;
+  int* notdone = flags + nrhs;
+  c64* part = G.partials.as<c64>();
+  const int vb = vec_blocks_group(G);
+  const BodyIdx& bi = G.bi;
+  c64 *x = G.x.as<c64>(), *r = G.r.as<c64>(), *rh = G.rh.as<c64>();
+  const c64* pol = G.pol.as<c64>();
+  const c64* ph = G.ph.as<c64>();
+  // network prediction x0 for every right-hand side (r = b after init)
+  int rc0 = predict_x0(ctx, G);
+  if (rc0 != VIE_OK) return rc0;
+  // true residual of the initial guess; reject guesses with ||r0|| >= ||b||
+  EpiArgs e{EPI_RESID, rh, part, 0, pol, ph};
+  VIE_HIP(run_matvec(ctx, G, 0, x, r, e, notdone));
+  VIE_HIP(timed(ctx, 11, [&] {
+    return launch_finalize(FIN_RESTART, nrhs, e.part_blocks, part, st, flags, fp, ctx->stream);
+  }));
+  std::vector<KState> hs(nrhs);
+  VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  std::vector<int> mask(nrhs, 0);
+  bool any = false;
+  for (int i = 0; i < nrhs; ++i) {
+    G.warm_used[i] = 1;
+    G.res_x0[i] = hs[i].bnorm2 > 0 ? sqrt(hs[i].rnorm2 / hs[i].bnorm2) : 0.0;
+    if (hs[i].bnorm2 > 0 && !(hs[i].rnorm2 < hs[i].bnorm2)) {
+      mask[i] = 1;
+      any = true;
+      G.fallback[i] = 1;
+      fallback_out[i] = 1;
+    }
+  }
+  if (any) {
+    // fall back to x0 = 0 for the rejected right-hand sides only
+    int* dmask = G.mask.as<int>();
+    VIE_HIP(hipMemcpyAsync(dmask, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+                           ctx->stream));
+    VIE_HIP(launch_init_zero_guess(g, bi, vb, pol, ph, x, r, rh, part, 0, dmask, ctx->stream));
+    VIE_HIP(hipMemcpyAsync(notdone, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+                           ctx->stream));
+    VIE_HIP(launch_finalize(FIN_RESTART, nrhs, vb, part, st, flags, fp, ctx->stream));
+    VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    VIE_HIP(hipStreamSynchronize(ctx->stream));
+    std::vector<int> nd(nrhs), ac(nrhs);
+    for (int i = 0; i < nrhs; ++i) {
+      nd[i] = hs[i].notdone;
+      ac[i] = hs[i].active;
+    }
+    VIE_HIP(hipMemcpyAsync(notdone, nd.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+                           ctx->stream));
+    VIE_HIP(hipMemcpyAsync(active, ac.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+                           ctx->stream));
+    VIE_HIP(hipStreamSynchronize(ctx->stream));  // nd, ac are about to go out of scope
+  }
+  return VIE_OK;
+}
+
 static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fallback_out) {
   const GroupGeom& g = G.g;
   const int nrhs = g.nrhs;
@@ -782,53 +860,8 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
   G.fallback.assign(nrhs, 0);
   G.warm_used.assign(nrhs, 0);
   if (warm) {
-    // network prediction x0 for every right-hand side (r = b after init)
-    int rc0 = predict_x0(ctx, G);
-    if (rc0 != VIE_OK) return rc0;
-    // true residual of the initial guess; reject guesses with ||r0|| >= ||b||
-    EpiArgs e{EPI_RESID, rh, part, 0, pol, ph};
-    VIE_HIP(run_matvec(ctx, G, 0, x, r, e, notdone));
-    VIE_HIP(timed(ctx, 11, [&] {
-      return launch_finalize(FIN_RESTART, nrhs, e.part_blocks, part, st, flags, fp, ctx->stream);
-    }));
-    std::vector<KState> hs(nrhs);
-    VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
-                           ctx->stream));
-    VIE_HIP(hipStreamSynchronize(ctx->stream));
-    std::vector<int> mask(nrhs, 0);
-    bool any = false;
-    for (int i = 0; i < nrhs; ++i) {
-      G.warm_used[i] = 1;
-      G.res_x0[i] = hs[i].bnorm2 > 0 ? sqrt(hs[i].rnorm2 / hs[i].bnorm2) : 0.0;
-      if (hs[i].bnorm2 > 0 && !(hs[i].rnorm2 < hs[i].bnorm2)) {
-        mask[i] = 1;
-        any = true;
-        G.fallback[i] = 1;
-        fallback_out[i] = 1;
-      }
-    }
-    if (any) {
-      // fall back to x0 = 0 for the rejected right-hand sides only
-      int* dmask = G.mask.as<int>();
-      VIE_HIP(hipMemcpyAsync(dmask, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
-                             ctx->stream));
-      VIE_HIP(launch_init_zero_guess(g, bi, vb, pol, ph, x, r, rh, part, 0, dmask, ctx->stream));
-      VIE_HIP(hipMemcpyAsync(notdone, mask.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
-                             ctx->stream));
-      VIE_HIP(launch_finalize(FIN_RESTART, nrhs, vb, part, st, flags, fp, ctx->stream));
-      VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
-                             ctx->stream));
-      VIE_HIP(hipStreamSynchronize(ctx->stream));
-      std::vector<int> nd(nrhs), ac(nrhs);
-      for (int i = 0; i < nrhs; ++i) {
-        nd[i] = hs[i].notdone;
-        ac[i] = hs[i].active;
-      }
-      VIE_HIP(hipMemcpyAsync(notdone, nd.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
-                             ctx->stream));
-      VIE_HIP(hipMemcpyAsync(active, ac.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
-                             ctx->stream));
-    }
+    int rcw = warm_start_init(ctx, G, fp, fallback_out);
+    if (rcw != VIE_OK) return rcw;
   }
   int rc = ensure_hflags(ctx, nrhs);
   if (rc != VIE_OK) return rc;
@@ -1114,7 +1147,8 @@ extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* 
 // preconditioner of the paper's large metasurface solve (Sec. IV, 7 x 7
 // blocks), read as block Jacobi over a lateral partition with inexact block
 // solves: k steps of GMRES from zero on every block.  The block solves of all
-// blocks and right-hand sides run as one batched product on a sub-context.
+// blocks, bodies and right-hand sides of a group run as one batched product
+// on a sub-context.
 
 static bool valid_fgmres(const vie_fgmres_options* fo, const GroupGeom& g) {
   if (!fo) return false;
@@ -1185,182 +1219,231 @@ static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, in
   return launch_seg_normalize(S, w, nr, m + 1, V + (size_t)(j + 1) * stride, ctx->stream);
 }
 
-// Block partition of the context's only body into bx x by lateral blocks:
+// Block partition of every body of group G into bx x by lateral blocks:
 // x part p covers voxels [floor(p N1 / bx), floor((p + 1) N1 / bx)), y alike,
 // every block the full z extent.  Each non-empty block becomes one body of a
 // sub-context: its voxels cropped to their own bounding box and placed at the
-// origin of a common grid (the largest box extent per axis); the other voxels
-// of that grid have eps = 1.  Couplings depend on voxel offsets only, so the
-// block's operator is exactly the full operator restricted to the block, and
-// the crop keeps the ascending voxel order of the body's vector.
-static int bj_build(vie_ctx* ctx, const vie_fgmres_options* fo) {
+// origin of a common grid (the largest box extent per axis over all blocks);
+// the other voxels of that grid have eps = 1.  Couplings depend on voxel
+// offsets only, so the block's operator is exactly the full operator
+// restricted to the block, and the crop keeps the ascending voxel order of
+// the body's vector.
+static int bj_build(vie_ctx* ctx, int gi, const vie_fgmres_options* fo) {
   const int bx = fo->blocks[0], by = fo->blocks[1];
-  if (ctx->bj && ctx->bj->bx == bx && ctx->bj->by == by) return VIE_OK;
-  if (ctx->bj && ctx->bj->sub) ctx->bj->sub->stream = ctx->bj->sub->own_stream;
-  ctx->bj.reset();
-  BodyRec& B = *ctx->bodies[0];
-  Group& G = *ctx->groups[B.group];
+  if ((int)ctx->bj.size() <= gi) ctx->bj.resize(gi + 1);
+  std::unique_ptr<BlockPrec>& slotp = ctx->bj[gi];
+  if (slotp && slotp->bx == bx && slotp->by == by) return VIE_OK;
+  if (slotp && slotp->sub) slotp->sub->stream = slotp->sub->own_stream;
+  slotp.reset();
+  Group& G = *ctx->groups[gi];
   const int N1 = G.g.N[0], N2 = G.g.N[1];
-  const int nb = B.nb;
-  std::vector<double> chic(nb);
-  if (nb > 0) {
-    VIE_HIP(hipMemcpyAsync(chic.data(), G.chic_all.as<double>() + G.voff_host[B.slot],
-                           nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  const int nbod = (int)G.bodies.size();
+  std::vector<double> chic(G.vox_host.size());
+  if (!chic.empty()) {
+    VIE_HIP(hipMemcpyAsync(chic.data(), G.chic_all.p, chic.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, ctx->stream));
     VIE_HIP(hipStreamSynchronize(ctx->stream));
   }
-  auto parts = [](int n, int np, std::vector<int>& of, std::vector<int>& lo) {
-    lo.resize(np + 1);
-    for (int p = 0; p <= np; ++p) lo[p] = (int)((int64_t)p * n / np);
+  auto parts = [](int n, int np, std::vector<int>& of) {
     of.assign(n, 0);
-    for (int p = 0; p < np; ++p)
-      for (int i = lo[p]; i < lo[p + 1]; ++i) of[i] = p;
+    for (int p = 0; p < np; ++p) {
+      const int lo = (int)((int64_t)p * n / np), hi = (int)((int64_t)(p + 1) * n / np);
+      for (int i = lo; i < hi; ++i) of[i] = p;
+    }
   };
-  std::vector<int> px, py, lox, loy;
-  parts(N1, bx, px, lox);
-  parts(N2, by, py, loy);
-  const int* vx = G.vox_host.data() + G.voff_host[B.slot];
-  std::vector<std::vector<int>> members((size_t)bx * by);
-  std::vector<int> blo((size_t)bx * by * 3, INT32_MAX), bhi((size_t)bx * by * 3, -1);
-  for (int k = 0; k < nb; ++k) {
-    const int v = vx[k];
-    const int c[3] = {v % N1, (v / N1) % N2, v / (N1 * N2)};
-    const size_t id = px[c[0]] + (size_t)bx * py[c[1]];
-    members[id].push_back(k);
-    for (int a = 0; a < 3; ++a) {
-      blo[id * 3 + a] = std::min(blo[id * 3 + a], c[a]);
-      bhi[id * 3 + a] = std::max(bhi[id * 3 + a], c[a]);
+  std::vector<int> px, py;
+  parts(N1, bx, px);
+  parts(N2, by, py);
+  const size_t nbl = (size_t)bx * by;
+  // members (indices into the body's voxel list) and bounding box of every block
+  std::vector<std::vector<int>> members((size_t)nbod * nbl);
+  std::vector<int> blo(members.size() * 3, INT32_MAX), bhi(members.size() * 3, -1);
+  int ext[3] = {1, 1, 1};
+  for (int sl = 0; sl < nbod; ++sl) {
+    const int* vx = G.vox_host.data() + G.voff_host[sl];
+    for (int k = 0; k < G.nb_host[sl]; ++k) {
+      const int v = vx[k];
+      const int c[3] = {v % N1, (v / N1) % N2, v / (N1 * N2)};
+      const size_t id = (size_t)sl * nbl + px[c[0]] + (size_t)bx * py[c[1]];
+      members[id].push_back(k);
+      for (int a = 0; a < 3; ++a) {
+        blo[id * 3 + a] = std::min(blo[id * 3 + a], c[a]);
+        bhi[id * 3 + a] = std::max(bhi[id * 3 + a], c[a]);
+      }
     }
   }
-  int ext[3] = {1, 1, 1};
   for (size_t id = 0; id < members.size(); ++id)
     if (!members[id].empty())
       for (int a = 0; a < 3; ++a) ext[a] = std::max(ext[a], bhi[id * 3 + a] - blo[id * 3 + a] + 1);
-  const int mx = ext[0], my = ext[1], mz = ext[2];
   auto P = std::make_unique<BlockPrec>();
   P->bx = bx;
   P->by = by;
-  P->len = 3 * (int64_t)nb;
   std::vector<std::vector<double>> eps;
-  std::vector<int> perm((size_t)P->len);
-  int64_t acc = 0;
-  for (int id = 0; id < bx * by; ++id) {
-    const std::vector<int>& mem = members[id];
-    if (mem.empty()) continue;
-    const int x0 = blo[(size_t)id * 3], y0 = blo[(size_t)id * 3 + 1], z0 = blo[(size_t)id * 3 + 2];
-    eps.emplace_back((size_t)mx * my * mz, 1.0);
-    std::vector<double>& e = eps.back();
-    const int nbb = (int)mem.size();
-    for (int t = 0; t < nbb; ++t) {
-      const int v = vx[mem[t]];
-      const int i = v % N1 - x0, j = (v / N1) % N2 - y0, kz = v / (N1 * N2) - z0;
-      e[i + (size_t)mx * (j + (size_t)my * kz)] = 1.0 + chic[mem[t]];
-      for (int c = 0; c < 3; ++c) perm[acc + (int64_t)c * nbb + t] = c * nb + mem[t];
+  std::vector<int> perm;
+  for (int sl = 0; sl < nbod; ++sl) {
+    const int nb = G.nb_host[sl];
+    const int* vx = G.vox_host.data() + G.voff_host[sl];
+    const double* ch = chic.data() + G.voff_host[sl];
+    P->first_blk.push_back((int)eps.size());
+    P->poff.push_back((int64_t)perm.size());
+    perm.resize(perm.size() + 3 * (size_t)nb);
+    int* pm = perm.data() + P->poff.back();
+    int64_t acc = 0;
+    for (size_t t = 0; t < nbl; ++t) {
+      const size_t id = (size_t)sl * nbl + t;
+      const std::vector<int>& mem = members[id];
+      if (mem.empty()) continue;
+      const int x0 = blo[id * 3], y0 = blo[id * 3 + 1], z0 = blo[id * 3 + 2];
+      eps.emplace_back((size_t)ext[0] * ext[1] * ext[2], 1.0);
+      std::vector<double>& e = eps.back();
+      const int nbb = (int)mem.size();
+      for (int u = 0; u < nbb; ++u) {
+        const int v = vx[mem[u]];
+        const int i = v % N1 - x0, j = (v / N1) % N2 - y0, kz = v / (N1 * N2) - z0;
+        e[i + (size_t)ext[0] * (j + (size_t)ext[1] * kz)] = 1.0 + ch[mem[u]];
+        for (int c = 0; c < 3; ++c) pm[acc + (int64_t)c * nbb + u] = c * nb + mem[u];
+      }
+      P->boff.push_back(acc);
+      P->blen.push_back(3 * nbb);
+      acc += 3 * nbb;
     }
-    P->boff.push_back(acc);
-    P->blen.push_back(3 * nbb);
-    acc += 3 * nbb;
+    P->nblk_of.push_back((int)eps.size() - P->first_blk.back());
   }
-  P->nblk = (int)eps.size();
-  std::vector<vie_body> bodies(P->nblk);
-  for (int b = 0; b < P->nblk; ++b) {
-    bodies[b].n[0] = mx;
-    bodies[b].n[1] = my;
-    bodies[b].n[2] = mz;
-    bodies[b].h = G.h;
-    bodies[b].origin[0] = bodies[b].origin[1] = bodies[b].origin[2] = 0.0;
-    bodies[b].eps_r = eps[b].data();
+  P->nsub = (int)eps.size();
+  if (P->nsub > 0) {
+    std::vector<vie_body> bodies(P->nsub);
+    for (int b = 0; b < P->nsub; ++b) {
+      for (int a = 0; a < 3; ++a) {
+        bodies[b].n[a] = ext[a];
+        bodies[b].origin[a] = 0.0;
+      }
+      bodies[b].h = G.h;
+      bodies[b].eps_r = eps[b].data();
+    }
+    vie_options so = ctx->opt;
+    so.precision = VIE_MIXED;
+    so.inner_tol = 1e-3;
+    so.warm_start = 0;
+    so.flags = VIE_FLAG_NO_GRAPH;
+    int rc = vie_setup(bodies.data(), P->nsub, &so, &P->sub);
+    if (rc != VIE_OK) return rc;
+    // the sub-context's compressed order must be the block order used above
+    if (P->sub->groups.size() != 1) return VIE_EDEVICE;
+    for (int b = 0; b < P->nsub; ++b)
+      if (3 * P->sub->bodies[b]->nb != P->blen[b] || P->sub->bodies[b]->slot != b)
+        return VIE_EDEVICE;
   }
-  vie_options so = ctx->opt;
-  so.precision = VIE_MIXED;
-  so.inner_tol = 1e-3;
-  so.warm_start = 0;
-  so.flags = VIE_FLAG_NO_GRAPH;
-  int rc = vie_setup(bodies.data(), P->nblk, &so, &P->sub);
-  if (rc != VIE_OK) return rc;
-  // the sub-context's compressed order must be the block order used above
-  if (P->sub->groups.size() != 1) return VIE_EDEVICE;
-  for (int b = 0; b < P->nblk; ++b)
-    if (3 * P->sub->bodies[b]->nb != P->blen[b] || P->sub->bodies[b]->slot != b) return VIE_EDEVICE;
   VIE_HIP(P->perm.reserve(std::max<size_t>(perm.size(), 1) * sizeof(int)));
   if (!perm.empty())
     VIE_HIP(hipMemcpy(P->perm.p, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice));
-  ctx->bj = std::move(P);
+  slotp = std::move(P);
   return VIE_OK;
 }
 
-// Segment tables of the block solves for nrhs right-hand sides: segment
-// q * nblk + b is block b of right-hand side q.
-static int bj_bind(vie_ctx* ctx, int nrhs, int k) {
-  BlockPrec& P = *ctx->bj;
-  if (P.nrhs == nrhs) return VIE_OK;
+// Segment tables of the block solves for right-hand sides of body slots rb[q]
+// at vector offsets roff[q]: one segment per (right-hand side, block of its
+// body).
+static int bj_bind(vie_ctx* ctx, Group& G, BlockPrec& P, const std::vector<int>& rb,
+                   const std::vector<int64_t>& roff, int k) {
+  if (P.nsub == 0) return VIE_OK;
+  if (P.bound_rb == rb && P.bound_roff == roff) return VIE_OK;
   vie_ctx* sub = P.sub;
   sub->stream = ctx->stream;
   Group& Gp = *sub->groups[0];
-  const int nseg = nrhs * P.nblk;
-  std::vector<int64_t> off(nseg);
-  std::vector<int> len(nseg), rb(nseg);
-  int maxlen = 1;
-  for (int q = 0; q < nrhs; ++q)
-    for (int b = 0; b < P.nblk; ++b) {
-      const int s = q * P.nblk + b;
-      off[s] = q * P.len + P.boff[b];
-      len[s] = P.blen[b];
-      rb[s] = b;
-      maxlen = std::max(maxlen, len[s]);
+  const int nrhs = (int)rb.size();
+  std::vector<int64_t> off, qoff(nrhs), qpoff(nrhs);
+  std::vector<int> len, srb, qlen(nrhs);
+  P.seg_rhs.clear();
+  P.maxlen = 1;
+  P.maxqlen = 1;
+  int64_t tot = 0;
+  for (int q = 0; q < nrhs; ++q) {
+    const int sl = rb[q];
+    qoff[q] = roff[q];
+    qpoff[q] = P.poff[sl];
+    qlen[q] = 3 * G.nb_host[sl];
+    P.maxqlen = std::max(P.maxqlen, qlen[q]);
+    tot = std::max<int64_t>(tot, roff[q] + qlen[q]);
+    for (int t = 0; t < P.nblk_of[sl]; ++t) {
+      const int sb = P.first_blk[sl] + t;
+      off.push_back(roff[q] + P.boff[sb]);
+      len.push_back(P.blen[sb]);
+      srb.push_back(sb);
+      P.seg_rhs.push_back(q);
+      P.maxlen = std::max(P.maxlen, P.blen[sb]);
     }
-  Gp.g.nrhs = nseg;
-  int rc = ensure_solve_storage(sub, Gp, nseg);
-  if (rc != VIE_OK) return rc;
-  Gp.roff_host = off;
-  VIE_HIP(hipMemcpyAsync(Gp.roff.p, off.data(), nseg * sizeof(int64_t), hipMemcpyHostToDevice,
+  }
+  const int nseg = (int)off.size();
+  P.nseg = nseg;
+  P.tot = tot;
+  if (nseg > 0) {
+    Gp.g.nrhs = nseg;
+    int rc = ensure_solve_storage(sub, Gp, nseg);
+    if (rc != VIE_OK) return rc;
+    Gp.roff_host = off;
+    VIE_HIP(hipMemcpyAsync(Gp.roff.p, off.data(), nseg * sizeof(int64_t), hipMemcpyHostToDevice,
+                           ctx->stream));
+    VIE_HIP(hipMemcpyAsync(Gp.rhs_body.p, srb.data(), nseg * sizeof(int), hipMemcpyHostToDevice,
+                           ctx->stream));
+    Gp.bi.vox = Gp.vox_all.as<int>();
+    Gp.bi.line_ptr = Gp.line_ptr_all.as<int>();
+    Gp.bi.chic = Gp.chic_all.as<double>();
+    Gp.bi.nb = Gp.nb_arr.as<int>();
+    Gp.bi.voff = Gp.voff_arr.as<int>();
+    Gp.bi.roff = Gp.roff.as<int64_t>();
+    Gp.bi.rhs_body = Gp.rhs_body.as<int>();
+    rc = arnoldi_alloc(ctx, P.ab, nseg, P.maxlen, tot, k, false);
+    if (rc != VIE_OK) return rc;
+    rc = arnoldi_tables(ctx, P.ab, off, len);
+    if (rc != VIE_OK) return rc;
+  }
+  VIE_HIP(P.qoff.reserve(std::max(nrhs, 1) * sizeof(int64_t)));
+  VIE_HIP(P.qpoff.reserve(std::max(nrhs, 1) * sizeof(int64_t)));
+  VIE_HIP(P.qlen.reserve(std::max(nrhs, 1) * sizeof(int)));
+  VIE_HIP(hipMemcpyAsync(P.qoff.p, qoff.data(), nrhs * sizeof(int64_t), hipMemcpyHostToDevice,
                          ctx->stream));
-  VIE_HIP(hipMemcpyAsync(Gp.rhs_body.p, rb.data(), nseg * sizeof(int), hipMemcpyHostToDevice,
+  VIE_HIP(hipMemcpyAsync(P.qpoff.p, qpoff.data(), nrhs * sizeof(int64_t), hipMemcpyHostToDevice,
                          ctx->stream));
-  Gp.bi.vox = Gp.vox_all.as<int>();
-  Gp.bi.line_ptr = Gp.line_ptr_all.as<int>();
-  Gp.bi.chic = Gp.chic_all.as<double>();
-  Gp.bi.nb = Gp.nb_arr.as<int>();
-  Gp.bi.voff = Gp.voff_arr.as<int>();
-  Gp.bi.roff = Gp.roff.as<int64_t>();
-  Gp.bi.rhs_body = Gp.rhs_body.as<int>();
-  const int64_t tot = nrhs * P.len;
-  rc = arnoldi_alloc(ctx, P.ab, nseg, maxlen, tot, k, false);
-  if (rc != VIE_OK) return rc;
-  rc = arnoldi_tables(ctx, P.ab, off, len);
-  if (rc != VIE_OK) return rc;
+  VIE_HIP(hipMemcpyAsync(P.qlen.p, qlen.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+                         ctx->stream));
   VIE_HIP(P.R.reserve((size_t)std::max<int64_t>(tot, 1) * sizeof(c64)));
   VIE_HIP(P.X.reserve((size_t)std::max<int64_t>(tot, 1) * sizeof(c64)));
-  P.nrhs = nrhs;
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  P.bound_rb = rb;
+  P.bound_roff = roff;
   return VIE_OK;
 }
 
-// z = M^{-1} v for nrhs body-compressed vectors (v, z device, nrhs * 3 nb
-// elements); right-hand sides with act[q] == 0 get z = 0.
-static int bj_apply(vie_ctx* ctx, const vie_fgmres_options* fo, const c64* v, c64* z,
-                    const std::vector<int>& act, int nrhs) {
-  BlockPrec& P = *ctx->bj;
+// z = M^{-1} v for the bound right-hand sides (v, z device vectors at the
+// bound offsets); right-hand sides with act[q] == 0 get z = 0.
+static int bj_apply(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo, const c64* v,
+                    c64* z, const std::vector<int>& act) {
+  const int nrhs = (int)P.bound_rb.size();
+  if (P.nseg == 0) {
+    VIE_HIP(hipMemsetAsync(z, 0, (size_t)std::max<int64_t>(P.tot, 0) * sizeof(c64), ctx->stream));
+    return VIE_OK;
+  }
   vie_ctx* sub = P.sub;
   sub->stream = ctx->stream;
   Group& Gp = *sub->groups[0];
   ArnoldiBufs& A = P.ab;
   const int k = fo->inner_iters;
   const int ip = fo->inner_precision == VIE_MIXED ? 1 : 0;
-  const int nseg = nrhs * P.nblk;
-  const int64_t tot = nrhs * P.len;
-  int maxlen = 1;
-  for (int l : P.blen) maxlen = std::max(maxlen, l);
-  int rc = arnoldi_alloc(ctx, A, nseg, maxlen, tot, k, false);  // grows for a larger k
+  const int nseg = P.nseg;
+  const int64_t tot = P.tot;
+  int rc = arnoldi_alloc(ctx, A, nseg, P.maxlen, tot, k, false);  // grows for a larger k
   if (rc != VIE_OK) return rc;
-  SegSet S{A.off.as<int64_t>(), A.len.as<int>(), A.act.as<int>(), nseg, seg_blocks(maxlen)};
+  SegSet S{A.off.as<int64_t>(), A.len.as<int>(), A.act.as<int>(), nseg, seg_blocks(P.maxlen)};
   std::vector<int> act_s(nseg), nvs(nseg, 0);
-  for (int s = 0; s < nseg; ++s) act_s[s] = act[s / P.nblk] ? 1 : 0;
+  for (int s = 0; s < nseg; ++s) act_s[s] = act[P.seg_rhs[s]] ? 1 : 0;
   VIE_HIP(hipMemcpyAsync(A.act.p, act_s.data(), nseg * sizeof(int), hipMemcpyHostToDevice,
                          ctx->stream));
   c64* R = P.R.as<c64>();
   c64* V = A.V.as<c64>();
   double* NR = A.NR.as<double>();
   const int ldn = k + 1;
-  VIE_HIP(launch_permute(nrhs, P.len, P.perm.as<int>(), v, R, 0, ctx->stream));
+  VIE_HIP(launch_permute(nrhs, P.qoff.as<int64_t>(), P.qpoff.as<int64_t>(), P.qlen.as<int>(),
+                         P.maxqlen, P.perm.as<int>(), v, R, 0, ctx->stream));
   VIE_HIP(launch_seg_maxpy(S, nullptr, 0, 0, nullptr, nullptr, 0, R, A.npart.as<double>(), NR,
                            ldn, ctx->stream));
   VIE_HIP(launch_seg_normalize(S, R, NR, ldn, V, ctx->stream));
@@ -1407,32 +1490,42 @@ static int bj_apply(vie_ctx* ctx, const vie_fgmres_options* fo, const c64* v, c6
   VIE_HIP(hipMemsetAsync(P.X.p, 0, (size_t)tot * sizeof(c64), ctx->stream));
   VIE_HIP(launch_seg_maxpy(S, V, tot, maxst, A.nvs.as<int>(), A.coef.as<c64>(), ldn,
                            P.X.as<c64>(), nullptr, nullptr, 0, ctx->stream));
-  VIE_HIP(launch_permute(nrhs, P.len, P.perm.as<int>(), P.X.as<c64>(), z, 1, ctx->stream));
+  VIE_HIP(launch_permute(nrhs, P.qoff.as<int64_t>(), P.qpoff.as<int64_t>(), P.qlen.as<int>(),
+                         P.maxqlen, P.perm.as<int>(), P.X.as<c64>(), z, 1, ctx->stream));
   // the host tables must outlive the copies
   VIE_HIP(hipStreamSynchronize(ctx->stream));
   return VIE_OK;
 }
 
-// Restarted FGMRES on every right-hand side of the one-body group G (bound
-// by bind_rhs), from w = 0.  Arnoldi products in the context's precision;
-// every cycle ends with the FP64 true residual, which alone decides
-// convergence.  A cycle stops early once its residual estimate is below
-// tol / 2.
-static int fgmres_group(vie_ctx* ctx, Group& G, const vie_fgmres_options* fo,
-                        std::vector<int>& steps, std::vector<int>& cycles) {
+// Restarted FGMRES on every right-hand side of group G (bound by bind_rhs),
+// from w = 0 or the learned warm start.  Arnoldi products in the context's
+// precision; every cycle ends with the FP64 true residual, which alone
+// decides convergence.  A cycle stops early once its residual estimate is
+// below tol / 2.
+static int fgmres_group(vie_ctx* ctx, Group& G, BlockPrec* P, const vie_fgmres_options* fo,
+                        bool warm, std::vector<int>& steps, std::vector<int>& cycles) {
   const int nrhs = G.g.nrhs;
   const int m = fo->restart;
-  const bool flex = fo->blocks[0] > 0 && ctx->bj && ctx->bj->nblk > 0;
+  const bool flex = P != nullptr;
   const int prec = ctx->opt.precision == VIE_MIXED ? 1 : 0;
-  const int len = 3 * ctx->bodies[0]->nb;
-  const int64_t tot = (int64_t)nrhs * len;
+  std::vector<int> len(nrhs);
+  int maxlen = 1;
+  int64_t tot = 0;
+  for (int b : G.bodies) {
+    const BodyRec& B = *ctx->bodies[b];
+    for (int q = 0; q < B.nrhs; ++q) {
+      len[B.rhs0 + q] = 3 * B.nb;
+      tot = std::max<int64_t>(tot, G.roff_host[B.rhs0 + q] + 3 * (int64_t)B.nb);
+    }
+    maxlen = std::max(maxlen, 3 * B.nb);
+  }
   if (!ctx->fgm) ctx->fgm = std::make_unique<ArnoldiBufs>();
   ArnoldiBufs& A = *ctx->fgm;
-  int rc = arnoldi_alloc(ctx, A, nrhs, len, tot, m, flex);
+  int rc = arnoldi_alloc(ctx, A, nrhs, maxlen, tot, m, flex);
   if (rc != VIE_OK) return rc;
-  rc = arnoldi_tables(ctx, A, G.roff_host, std::vector<int>(nrhs, len));
+  rc = arnoldi_tables(ctx, A, G.roff_host, len);
   if (rc != VIE_OK) return rc;
-  const SegSet S{A.off.as<int64_t>(), A.len.as<int>(), A.act.as<int>(), nrhs, seg_blocks(len)};
+  const SegSet S{A.off.as<int64_t>(), A.len.as<int>(), A.act.as<int>(), nrhs, seg_blocks(maxlen)};
   FinParams fp;
   fp.tol2_done = ctx->opt.tol * ctx->opt.tol;
   fp.tol2_inner = fp.tol2_done;
@@ -1448,6 +1541,11 @@ static int fgmres_group(vie_ctx* ctx, Group& G, const vie_fgmres_options* fo,
   const int vb = vec_blocks_group(G);
   VIE_HIP(launch_init_zero_guess(G.g, G.bi, vb, pol, ph, x, r, rh, part, 0, nullptr, ctx->stream));
   VIE_HIP(launch_finalize(FIN_INIT, nrhs, vb, part, st, flags, fp, ctx->stream));
+  if (warm) {
+    std::vector<int> fb(nrhs, 0);
+    rc = warm_start_init(ctx, G, fp, fb);
+    if (rc != VIE_OK) return rc;
+  }
   std::vector<KState> hs(nrhs);
   VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
                          ctx->stream));
@@ -1485,7 +1583,7 @@ static int fgmres_group(vie_ctx* ctx, Group& G, const vie_fgmres_options* fo,
       c64* vj = V + (size_t)j * tot;
       c64* zj = Z + (size_t)j * tot;
       if (flex) {
-        rc = bj_apply(ctx, fo, vj, zj, act, nrhs);
+        rc = bj_apply(ctx, *P, fo, vj, zj, act);
         if (rc != VIE_OK) return rc;
       }
       EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
@@ -1501,14 +1599,14 @@ static int fgmres_group(vie_ctx* ctx, Group& G, const vie_fgmres_options* fo,
       bool more = false, changed = false;
       for (int q = 0; q < nrhs; ++q) {
         if (!act[q]) continue;
-        for (int i = 0; i <= j; ++i) hc[i] = h1[(size_t)q * (m + 1) + i] + h2[(size_t)q * (m + 1) + i];
+        for (int i = 0; i <= j; ++i)
+          hc[i] = h1[(size_t)q * (m + 1) + i] + h2[(size_t)q * (m + 1) + i];
         const double hn = sqrt(std::max(nr[(size_t)q * (m + 1) + j + 1], 0.0));
         const double est = ls[q].add(j, hc.data(), hn);
         nst[q] = j + 1;
         steps[q] += 1;
-        const double beta = sqrt(hs[q].rnorm2);
         if (est <= 0.5 * ctx->opt.tol * sqrt(hs[q].bnorm2) || nst[q] >= mc[q] ||
-            hn <= 1e-14 * beta) {
+            hn <= 1e-14 * sqrt(hs[q].rnorm2)) {
           act[q] = 0;
           changed = true;
         } else {
@@ -1516,9 +1614,11 @@ static int fgmres_group(vie_ctx* ctx, Group& G, const vie_fgmres_options* fo,
         }
       }
       if (!more) break;
-      if (changed)
+      if (changed) {
         VIE_HIP(hipMemcpyAsync(A.act.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
                                ctx->stream));
+        VIE_HIP(hipStreamSynchronize(ctx->stream));
+      }
     }
     // x += Z y for every right-hand side that took steps in this cycle
     int maxst = 0;
@@ -1554,54 +1654,73 @@ static int fgmres_group(vie_ctx* ctx, Group& G, const vie_fgmres_options* fo,
   return VIE_OK;
 }
 
+// Body slot of every right-hand side of G.
+static std::vector<int> rhs_slots(vie_ctx* ctx, const Group& G) {
+  std::vector<int> rb(G.g.nrhs, 0);
+  for (int b : G.bodies) {
+    const BodyRec& B = *ctx->bodies[b];
+    for (int q = 0; q < B.nrhs; ++q) rb[B.rhs0 + q] = B.slot;
+  }
+  return rb;
+}
+
 extern "C" int vie_solve_fgmres(vie_ctx* ctx, const vie_planewave* inc,
                                 const int32_t* nrhs_per_body, const vie_fgmres_options* fo,
                                 vie_stats* stats) {
   if (!ctx) return VIE_EINVAL;
   if (ctx->poisoned) return VIE_ESTATE;
   if (!inc || !nrhs_per_body || !fo) return VIE_EINVAL;
-  if (ctx->bodies.size() != 1) return VIE_ENOTSUP;
-  BodyRec& B = *ctx->bodies[0];
-  Group& G = *ctx->groups[B.group];
-  if (!valid_fgmres(fo, G.g)) return VIE_EINVAL;
+  for (auto& Gp : ctx->groups)
+    if (!valid_fgmres(fo, Gp->g)) return VIE_EINVAL;
   std::vector<int> first;
   int rc = check_channels(ctx, inc, nrhs_per_body, first);
   if (rc != VIE_OK) return rc;
-  rc = bind_rhs(ctx, G, inc, nrhs_per_body, first);
-  if (rc != VIE_OK) return rc;
-  const int nrhs = G.g.nrhs;
-  if (nrhs == 0) return VIE_OK;
-  G.res_x0.assign(nrhs, 1.0);
-  G.fallback.assign(nrhs, 0);
-  G.warm_used.assign(nrhs, 0);
-  G.samples_ready = false;
-  if (fo->blocks[0] > 0 && B.nb > 0) {
-    rc = bj_build(ctx, fo);
-    if (rc != VIE_OK) return rc;
-    rc = bj_bind(ctx, nrhs, fo->inner_iters);
-    if (rc != VIE_OK) return rc;
-  }
-  std::vector<int> steps, cycles;
-  rc = fgmres_group(ctx, G, fo, steps, cycles);
-  if (rc != VIE_OK) return rc;
-  std::vector<KState> hs(nrhs);
-  VIE_HIP(hipMemcpyAsync(hs.data(), G.state.p, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
-                         ctx->stream));
-  VIE_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->opt.warm_start && !ctx->cnn) return VIE_EINVAL;  // warm start needs vie_attach_cnn
+  const bool blocks = fo->blocks[0] > 0;
   bool all_conv = true;
-  for (int q = 0; q < nrhs; ++q) {
-    const bool conv = !hs[q].notdone;
-    all_conv &= conv;
-    if (stats) {
-      vie_stats& o = stats[q];
-      o.iters = steps[q];
-      o.matvecs = steps[q] + cycles[q];
-      o.cycles = cycles[q];
-      o.converged = conv;
-      o.fallback = 0;
-      o.warm = 0;
-      o.rel_res = hs[q].bnorm2 > 0 ? sqrt(hs[q].rnorm2 / hs[q].bnorm2) : 0.0;
-      o.rel_res_x0 = 1.0;
+  for (int gi = 0; gi < (int)ctx->groups.size(); ++gi) {
+    Group& G = *ctx->groups[gi];
+    rc = bind_rhs(ctx, G, inc, nrhs_per_body, first);
+    if (rc != VIE_OK) return rc;
+    const int nrhs = G.g.nrhs;
+    if (nrhs == 0) continue;
+    G.res_x0.assign(nrhs, 1.0);
+    G.fallback.assign(nrhs, 0);
+    G.warm_used.assign(nrhs, 0);
+    G.samples_ready = false;
+    BlockPrec* P = nullptr;
+    if (blocks) {
+      rc = bj_build(ctx, gi, fo);
+      if (rc != VIE_OK) return rc;
+      P = ctx->bj[gi].get();
+      rc = bj_bind(ctx, G, *P, rhs_slots(ctx, G), G.roff_host, fo->inner_iters);
+      if (rc != VIE_OK) return rc;
+      if (P->nseg == 0) P = nullptr;  // no body voxels: nothing to precondition
+    }
+    std::vector<int> steps, cycles;
+    rc = fgmres_group(ctx, G, P, fo, ctx->opt.warm_start != 0, steps, cycles);
+    if (rc != VIE_OK) return rc;
+    std::vector<KState> hs(nrhs);
+    VIE_HIP(hipMemcpyAsync(hs.data(), G.state.p, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    VIE_HIP(hipStreamSynchronize(ctx->stream));
+    for (int b : G.bodies) {
+      const BodyRec& B = *ctx->bodies[b];
+      for (int q = 0; q < B.nrhs; ++q) {
+        const int gq = B.rhs0 + q;
+        const bool conv = !hs[gq].notdone;
+        all_conv &= conv;
+        if (!stats) continue;
+        vie_stats& o = stats[first[b] + q];
+        o.iters = steps[gq];
+        o.matvecs = steps[gq] + cycles[gq];
+        o.cycles = cycles[gq];
+        o.converged = conv;
+        o.fallback = G.fallback[gq];
+        o.warm = G.warm_used[gq];
+        o.rel_res = hs[gq].bnorm2 > 0 ? sqrt(hs[gq].rnorm2 / hs[gq].bnorm2) : 0.0;
+        o.rel_res_x0 = G.res_x0[gq];
+      }
     }
   }
   timing_collect(ctx);
@@ -1622,9 +1741,12 @@ extern "C" int vie_precond_apply(vie_ctx* ctx, const vie_fgmres_options* fo, con
   const int64_t len = 3 * (int64_t)nb;
   memset(z, 0, (size_t)nvec * 3 * n * sizeof(vie_c64));
   if (nb == 0) return VIE_OK;
-  int rc = bj_build(ctx, fo);
+  int rc = bj_build(ctx, B.group, fo);
   if (rc != VIE_OK) return rc;
-  rc = bj_bind(ctx, nvec, fo->inner_iters);
+  BlockPrec& P = *ctx->bj[B.group];
+  std::vector<int64_t> roff(nvec);
+  for (int q = 0; q < nvec; ++q) roff[q] = q * len;
+  rc = bj_bind(ctx, G, P, std::vector<int>(nvec, B.slot), roff, fo->inner_iters);
   if (rc != VIE_OK) return rc;
   const int* vx = G.vox_host.data() + G.voff_host[B.slot];
   std::vector<c64> hv((size_t)nvec * len), hz((size_t)nvec * len);
@@ -1639,7 +1761,7 @@ extern "C" int vie_precond_apply(vie_ctx* ctx, const vie_fgmres_options* fo, con
   VIE_HIP(dz.reserve(hv.size() * sizeof(c64)));
   VIE_HIP(hipMemcpyAsync(dv.p, hv.data(), hv.size() * sizeof(c64), hipMemcpyHostToDevice,
                          ctx->stream));
-  rc = bj_apply(ctx, fo, dv.as<c64>(), dz.as<c64>(), std::vector<int>(nvec, 1), nvec);
+  rc = bj_apply(ctx, P, fo, dv.as<c64>(), dz.as<c64>(), std::vector<int>(nvec, 1));
   if (rc != VIE_OK) return rc;
   VIE_HIP(hipMemcpyAsync(hz.data(), dz.p, hz.size() * sizeof(c64), hipMemcpyDeviceToHost,
                          ctx->stream));

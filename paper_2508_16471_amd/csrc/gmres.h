@@ -42,10 +42,12 @@ hipError_t launch_seg_maxpy(const SegSet& S, const c64* V, int64_t stride, int n
 hipError_t launch_seg_normalize(const SegSet& S, const c64* src, const double* norm2, int ldn,
                                 c64* dst, hipStream_t st);
 
-// nrep repetitions of a permutation of n elements:
-//   gather  (scatter == 0): dst[r * n + j] = src[r * n + perm[j]]
-//   scatter (scatter != 0): dst[r * n + perm[j]] = src[r * n + j]
-hipError_t launch_permute(int nrep, int64_t n, const int* perm, const c64* src, c64* dst,
-                          int scatter, hipStream_t st);
+// Permutation of each of nrep vectors (vector q: qlen[q] elements at qoff[q],
+// its permutation at perm + qpoff[q]; maxlen >= every qlen):
+//   gather  (scatter == 0): dst[qoff + j] = src[qoff + perm[j]]
+//   scatter (scatter != 0): dst[qoff + perm[j]] = src[qoff + j]
+hipError_t launch_permute(int nrep, const int64_t* qoff, const int64_t* qpoff, const int* qlen,
+                          int maxlen, const int* perm, const c64* src, c64* dst, int scatter,
+                          hipStream_t st);
 
 }  // namespace vie

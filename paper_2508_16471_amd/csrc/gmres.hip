@@ -57,16 +57,18 @@ __global__ __launch_bounds__(GT) void k_seg_mdot(SegSet S, const c64* __restrict
   }
 }
 
-__global__ void k_seg_sum_c(SegSet S, int nv, const c64* __restrict__ partials,
-                            c64* __restrict__ out, int ldo) {
-  const int s = blockIdx.x;
-  const bool skip = S.active && !S.active[s];
-  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
-    c64 t = mk(0.0, 0.0);
-    if (!skip)
-      for (int k = 0; k < S.nblk; ++k) t = t + partials[((int64_t)s * nv + i) * S.nblk + k];
-    out[(int64_t)s * ldo + i] = t;
-  }
+// One wave per (segment, coefficient): lane l sums partials l, l + 64, ...,
+// then a fixed butterfly across the wave.
+__global__ __launch_bounds__(64) void k_seg_sum_c(SegSet S, int nv,
+                                                  const c64* __restrict__ partials,
+                                                  c64* __restrict__ out, int ldo) {
+  const int i = blockIdx.x, s = blockIdx.y;
+  c64 t = mk(0.0, 0.0);
+  if (!(S.active && !S.active[s]))
+    for (int k = threadIdx.x; k < S.nblk; k += 64)
+      t = t + partials[((int64_t)s * nv + i) * S.nblk + k];
+  for (int m = 32; m >= 1; m >>= 1) t = t + shfl_xor_c(t, m);
+  if (threadIdx.x == 0) out[(int64_t)s * ldo + i] = t;
 }
 
 __global__ __launch_bounds__(GT) void k_seg_maxpy(SegSet S, const c64* __restrict__ V,
@@ -103,13 +105,14 @@ __global__ __launch_bounds__(GT) void k_seg_maxpy(SegSet S, const c64* __restric
   }
 }
 
-__global__ void k_seg_sum_r(SegSet S, const double* __restrict__ partials,
-                            double* __restrict__ out, int ldn) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S.nseg || (S.active && !S.active[s])) return;
+__global__ __launch_bounds__(64) void k_seg_sum_r(SegSet S, const double* __restrict__ partials,
+                                                  double* __restrict__ out, int ldn) {
+  const int s = blockIdx.x;
+  if (S.active && !S.active[s]) return;
   double t = 0.0;
-  for (int k = 0; k < S.nblk; ++k) t += partials[(int64_t)s * S.nblk + k];
-  out[(int64_t)s * ldn] = t;
+  for (int k = threadIdx.x; k < S.nblk; k += 64) t += partials[(int64_t)s * S.nblk + k];
+  for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m);
+  if (threadIdx.x == 0) out[(int64_t)s * ldn] = t;
 }
 
 __global__ __launch_bounds__(GT) void k_seg_normalize(SegSet S, const c64* __restrict__ src,
@@ -125,12 +128,18 @@ __global__ __launch_bounds__(GT) void k_seg_normalize(SegSet S, const c64* __res
     dst[off + e] = sc * src[off + e];
 }
 
-__global__ __launch_bounds__(GT) void k_permute(int64_t n, const int* __restrict__ perm,
+__global__ __launch_bounds__(GT) void k_permute(const int64_t* __restrict__ qoff,
+                                                const int64_t* __restrict__ qpoff,
+                                                const int* __restrict__ qlen,
+                                                const int* __restrict__ perm,
                                                 const c64* __restrict__ src,
                                                 c64* __restrict__ dst, int scatter) {
-  const int64_t base = (int64_t)blockIdx.y * n;
-  for (int64_t j = (int64_t)blockIdx.x * GT + threadIdx.x; j < n; j += (int64_t)gridDim.x * GT) {
-    const int64_t p = perm[j];
+  const int q = blockIdx.y;
+  const int64_t base = qoff[q];
+  const int* pm = perm + qpoff[q];
+  const int n = qlen[q];
+  for (int j = blockIdx.x * GT + threadIdx.x; j < n; j += gridDim.x * GT) {
+    const int p = pm[j];
     if (scatter)
       dst[base + p] = src[base + j];
     else
@@ -149,7 +158,7 @@ hipError_t launch_seg_mdot(const SegSet& S, const c64* V, int64_t stride, int nv
                            c64* partials, c64* out, int ldo, hipStream_t st) {
   if (S.nseg < 1 || nv < 1) return hipSuccess;
   k_seg_mdot<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, V, stride, nv, w, partials);
-  k_seg_sum_c<<<S.nseg, 64, 0, st>>>(S, nv, partials, out, ldo);
+  k_seg_sum_c<<<dim3(nv, S.nseg), 64, 0, st>>>(S, nv, partials, out, ldo);
   return hipGetLastError();
 }
 
@@ -160,7 +169,7 @@ hipError_t launch_seg_maxpy(const SegSet& S, const c64* V, int64_t stride, int n
   if (nv < 0 || nv > kMaxVec) return hipErrorInvalidValue;
   k_seg_maxpy<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, V, stride, nv, nv_seg, coef, ldc, w,
                                                    norm2 ? partials : nullptr);
-  if (norm2) k_seg_sum_r<<<(S.nseg + 63) / 64, 64, 0, st>>>(S, partials, norm2, ldn);
+  if (norm2) k_seg_sum_r<<<S.nseg, 64, 0, st>>>(S, partials, norm2, ldn);
   return hipGetLastError();
 }
 
@@ -171,11 +180,12 @@ hipError_t launch_seg_normalize(const SegSet& S, const c64* src, const double* n
   return hipGetLastError();
 }
 
-hipError_t launch_permute(int nrep, int64_t n, const int* perm, const c64* src, c64* dst,
-                          int scatter, hipStream_t st) {
-  if (nrep < 1 || n < 1) return hipSuccess;
-  const int gx = (int)std::min<int64_t>((n + GT - 1) / GT, 4096);
-  k_permute<<<dim3(gx, nrep), GT, 0, st>>>(n, perm, src, dst, scatter);
+hipError_t launch_permute(int nrep, const int64_t* qoff, const int64_t* qpoff, const int* qlen,
+                          int maxlen, const int* perm, const c64* src, c64* dst, int scatter,
+                          hipStream_t st) {
+  if (nrep < 1 || maxlen < 1) return hipSuccess;
+  const int gx = std::min((maxlen + GT - 1) / GT, 4096);
+  k_permute<<<dim3(gx, nrep), GT, 0, st>>>(qoff, qpoff, qlen, perm, src, dst, scatter);
   return hipGetLastError();
 }
 

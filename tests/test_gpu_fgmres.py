@@ -11,6 +11,8 @@ block solves, textbook FGMRES).
   exact arithmetic; rel. 1e-8);
 * converged solves equal the dense LU solution (FP64 to 1e-10: rel. 1e-8;
   mixed to 1e-6: rel. 1e-5), with and without the preconditioner;
+* several bodies on several grids in one call; the learned warm start with
+  its fallback;
 * option checks.
 """
 
@@ -173,29 +175,59 @@ def test_fgmres_rejects_bad_options(V):
     ctx = V.vie_setup([(eps, g.h, g.origin), (eps, g.h, g.origin)],
                       V.make_options(K0, tol=1e-6, max_iter=100))
     try:
-        with pytest.raises(V.VieError) as e:
-            V.vie_solve_fgmres(ctx, CHANS[:2], [1, 1], V.fgmres_options(blocks=(2, 2)))
+        with pytest.raises(V.VieError) as e:  # the preconditioner alone takes one body
+            V.vie_precond_apply(ctx, V.fgmres_options(blocks=(2, 2)),
+                                np.zeros((3,) + g.n[::-1], complex))
         assert e.value.code == V.VIE_ENOTSUP
     finally:
         V.vie_destroy(ctx)
 
 
-def test_fgmres_after_bicgstab_on_one_context(V):
-    """A BiCGSTAB solve, then preconditioned FGMRES, then plain GMRES on the same
-    context: each meets the tolerance and equals the LU solution."""
-    g, eps, chi, pos, A, body = _case(16)
-    ctx = _ctx(V, g, eps, V.VIE_MIXED, tol=1e-6)
-    lu = scipy.linalg.lu_factor(A)
-    want = [scipy.linalg.lu_solve(lu, _rhs(chi, pos, body, kh, p)) for kh, p in CHANS]
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-6)])
+def test_fgmres_several_bodies_and_grids(V, prec, tol):
+    """Three bodies in two grid groups (two share a grid), uneven channel
+    counts: one batched FGMRES call with the block preconditioner; every
+    solution equals its body's LU solution."""
+    cases = [_case(21), _case(22), _case(23, n=(9, 12, 6))]
+    bodies = [(c[1], c[0].h, c[0].origin) for c in cases]
+    nrhs = [2, 1, 2]
+    chans = CHANS[:2] + CHANS[:1] + CHANS[:2]
+    opt = V.make_options(K0, precision=prec, tol=tol, max_iter=2000)
+    ctx = V.vie_setup(bodies, opt)
     try:
-        runs = [lambda: V.vie_solve(ctx, CHANS, [2]),
-                lambda: V.vie_solve_fgmres(ctx, CHANS, [2], V.fgmres_options(8, (2, 2), 4)),
-                lambda: V.vie_solve_fgmres(ctx, CHANS, [2], V.fgmres_options(8, (0, 0)))]
-        for run in runs:
-            rc, st = run()
-            assert rc == 0 and all(s["converged"] and s["rel_res"] <= 1e-6 for s in st)
-            for q in range(2):
-                got = _body_vec(V.vie_get_current(ctx, 0, q, g.n), body)
-                assert np.linalg.norm(got - want[q]) < 1e-5 * np.linalg.norm(want[q])
+        rc, st = V.vie_solve_fgmres(ctx, chans, nrhs,
+                                    V.fgmres_options(6, (2, 2), 3, inner_precision=prec))
+        assert rc == 0 and all(s["converged"] and s["rel_res"] <= tol for s in st)
+        i = 0
+        for b, (g, eps, chi, pos, A, body) in enumerate(cases):
+            lu = scipy.linalg.lu_factor(A)
+            for q in range(nrhs[b]):
+                kh, p = chans[i]
+                want = scipy.linalg.lu_solve(lu, _rhs(chi, pos, body, kh, p))
+                got = _body_vec(V.vie_get_current(ctx, b, q, g.n), body)
+                err = np.linalg.norm(got - want) / np.linalg.norm(want)
+                print(b, q, st[i]["iters"], err)
+                assert err < (1e-8 if prec == 0 else 1e-5)
+                i += 1
     finally:
         V.vie_destroy(ctx)
+
+
+def test_fgmres_warm_start_fallback(V):
+    """An untrained network's guesses are checked like the BiCGSTAB path's: a
+    guess with ||b - A x0|| >= ||b|| falls back to w = 0; the solve still
+    meets the tolerance."""
+    g, eps, chi, pos, A, body = _case(24)
+    net = V.vie_cnn_create(3)
+    opt = V.make_options(K0, precision=V.VIE_MIXED, tol=1e-6, max_iter=2000, warm_start=1)
+    ctx = V.vie_setup([(eps, g.h, g.origin)], opt)
+    try:
+        V.vie_attach_cnn(ctx, net)
+        rc, st = V.vie_solve_fgmres(ctx, CHANS, [2], V.fgmres_options(8, (2, 2), 3))
+        print(st)
+        assert rc == 0 and all(s["converged"] and s["warm"] == 1 for s in st)
+        for s in st:
+            assert s["fallback"] == (1 if s["rel_res_x0"] >= 1.0 else 0)
+    finally:
+        V.vie_destroy(ctx)
+        V.vie_cnn_destroy(net)
