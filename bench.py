@@ -68,6 +68,12 @@ def parse():
     ap.add_argument("--directions", type=int, default=64,
                     help="metasurface mode: incident directions of the 64-point (u, v) grid (x 2 circular polarisations)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32")
+    ap.add_argument("--solver", choices=["fgmres", "bicgstab"], default="fgmres",
+                    help="fast leg: block-Jacobi FGMRES (vie_solve_fgmres) or BiCGSTAB with FP64 "
+                         "refinement (vie_solve)")
+    ap.add_argument("--restart", type=int, default=60, help="FGMRES steps per cycle")
+    ap.add_argument("--blocks", default="2,2", help="FGMRES lateral block partition bx,by")
+    ap.add_argument("--inner-iters", type=int, default=8, help="GMRES steps per block solve")
     ap.add_argument("--configs", default="",
                     help="precond mode: comma-separated configuration names to run "
                          "(the BiCGSTAB reference always runs)")
@@ -184,6 +190,73 @@ def roofline_from_times(times, stats, N, P, Q, mixed, nb):
         by = execs * kernel_bytes(kind, N, P, Q, extra, nb=nb)
         if kind.startswith("fft_z_green"):
             by += launches_active * spectrum_bytes(kind, Q)
+        rows[kind] = {"ms_total": ms, "launches": int(cnt), "rhs_execs": execs,
+                      "bytes": float(by), "GBps": by / (ms * 1e-3) / 1e9,
+                      "avg_launch_ms": ms / cnt}
+    return rows
+
+
+def block_geometry(bodies, blocks):
+    """The block-Jacobi sub-problem grid the library builds for these bodies
+    (same lateral partition, every non-empty block cropped to its bounding
+    box, the common grid the largest box extent per axis), the block count of
+    every body and the mean body voxels per block."""
+    bx, by = blocks
+
+    def bounds(n, parts):
+        return [(p * n) // parts for p in range(parts + 1)]
+
+    ext = [1, 1, 1]
+    nblk, nbv = [], []
+    for e, _, _, g in bodies:
+        body = e != 1.0  # (N3, N2, N1)
+        n1, n2 = g.n[0], g.n[1]
+        xb, yb = bounds(n1, bx), bounds(n2, by)
+        cnt = 0
+        for py in range(by):
+            for px in range(bx):
+                sub = body[:, yb[py]:yb[py + 1], xb[px]:xb[px + 1]]
+                if not sub.any():
+                    continue
+                cnt += 1
+                nbv.append(int(sub.sum()))
+                for a, ax in ((0, (1, 2)), (1, (0, 2)), (2, (0, 1))):
+                    idx = np.nonzero(sub.any(axis=ax))[0]
+                    ext[2 - a] = max(ext[2 - a], int(idx[-1] - idx[0] + 1))
+        nblk.append(cnt)
+    P = tuple(fft_length(v) for v in ext)
+    return {"N": tuple(ext), "P": P, "Q": tuple(p // 2 + 1 for p in P), "blocks_per_body": nblk,
+            "nb_mean": float(np.mean(nbv)) if nbv else 0.0}
+
+
+def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch):
+    """Achieved GB/s of every FFT pass of the FGMRES solve: FP32 outer
+    products (one per Arnoldi step), FP64 true-residual products (one per
+    cycle) and the FP32 block products (k per step, one execution per block
+    of the right-hand side's body)."""
+    iters = np.array([s["iters"] for s in stats])
+    cyc = np.array([s["cycles"] for s in stats])
+    per_step = len(geom["blocks_per_body"]) * nch  # stats repeat once per timed step
+    nblk = np.array([geom["blocks_per_body"][(i % per_step) // nch] for i in range(len(stats))])
+    rows = {}
+    for kind, (ms, cnt) in times.items():
+        blk = kind.startswith("block_")
+        base = kind[len("block_"):] if blk else kind
+        if not base.startswith("fft_") or cnt == 0 or ms <= 0:
+            continue
+        f32 = base.endswith("f32")
+        if blk:
+            Nk, Pk, Qk, nbk = geom["N"], geom["P"], geom["Q"], geom["nb_mean"]
+            execs = int((iters * k * nblk).sum())
+            launches_active = int(iters.max() * k)
+        else:
+            Nk, Pk, Qk, nbk = N, P, Q, nb
+            execs = int(iters.sum()) if f32 else int(cyc.sum())
+            launches_active = int(iters.max()) if f32 else int(cyc.max())
+        extra = 3 * nbk * 16 if (base.startswith("fft_x_inv") and not f32 and not blk) else 0
+        by = execs * kernel_bytes(base, Nk, Pk, Qk, extra, nb=nbk)
+        if base.startswith("fft_z_green"):
+            by += launches_active * spectrum_bytes(base, Qk)
         rows[kind] = {"ms_total": ms, "launches": int(cnt), "rhs_execs": execs,
                       "bytes": float(by), "GBps": by / (ms * 1e-3) / 1e9,
                       "avg_launch_ms": ms / cnt}
@@ -324,12 +397,12 @@ def measured_traffic(kind, avg_launch_ms):
 def other_rows(times):
     """Time of the non-FFT kernel kinds over the timed region."""
     return {k: {"ms_total": ms, "launches": int(cnt)} for k, (ms, cnt) in times.items()
-            if not k.startswith("fft_") and cnt > 0}
+            if not k.startswith(("fft_", "block_fft_")) and cnt > 0}
 
 
-def learned_leg(V, torch, ctx, args, chans, nb, nch, theta, phi, dtau, fast_value):
-    """The fast path with the trained warm-start network attached (same
-    bodies, same step); the plain start stays the fallback."""
+def learned_leg(V, torch, ctx, args, chans, nb, nch, theta, phi, dtau, fast_value, solve):
+    """The fast path (solver `solve`) with the trained warm-start network
+    attached (same bodies, same step); the plain start stays the fallback."""
     net = V.vie_cnn_create(0)
     try:
         V.vie_cnn_params(net, np.load(args.weights))
@@ -337,12 +410,12 @@ def learned_leg(V, torch, ctx, args, chans, nb, nch, theta, phi, dtau, fast_valu
         V.vie_set_options(ctx, V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol,
                                               max_iter=20000, inner_tol=args.inner_tol,
                                               warm_start=1, flags=V.VIE_FLAG_TIMING))
-        V.vie_solve(ctx, chans, [nch] * nb)  # warm-up
+        solve()  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = []
         for _ in range(args.steps):
-            _, s = V.vie_solve(ctx, chans, [nch] * nb)
+            _, s = solve()
             post_process(V, ctx, nb, nch, theta, phi, dtau)
             st += s
         torch.cuda.synchronize()
@@ -777,7 +850,8 @@ def precond_mode(args):
     configs = [("bicgstab_mixed", None, 0, 0), ("gmres30", V.fgmres_options(30, (0, 0)), 0, 0)]
     for m, bl, k in ((30, (7, 7), 2), (30, (7, 7), 4), (30, (8, 8), 2), (30, (8, 8), 4),
                      (30, (4, 4), 4), (30, (4, 4), 8), (30, (2, 2), 2), (30, (2, 2), 4),
-                     (30, (2, 2), 8), (60, (2, 2), 8), (30, (2, 2), 16), (30, (1, 1), 4)):
+                     (30, (2, 2), 8), (60, (2, 2), 8), (20, (2, 2), 8), (40, (2, 2), 8),
+                     (30, (2, 2), 16), (30, (1, 1), 4)):
         configs.append((f"fgmres{m}_bj{bl[0]}x{bl[1]}_k{k}",
                         V.fgmres_options(m, bl, k, V.VIE_MIXED), k, 0))
     configs += [("bicgstab_mixed_learned", None, 0, 1),
@@ -860,8 +934,18 @@ def main():
     ctx = V.vie_setup([(e, h, o) for e, h, o, _ in bodies], fast)
     setup_s = time.perf_counter() - t0
 
+    use_fgmres = args.solver == "fgmres"
+    blocks = tuple(int(v) for v in args.blocks.split(","))
+    fo = V.fgmres_options(args.restart, blocks, args.inner_iters, V.VIE_MIXED)
+    geom = block_geometry(bodies, blocks) if use_fgmres else None
+
+    def solve():
+        if use_fgmres:
+            return V.vie_solve_fgmres(ctx, chans, [nch] * nb, fo)
+        return V.vie_solve(ctx, chans, [nch] * nb)
+
     def step():
-        rc, st = V.vie_solve(ctx, chans, [nch] * nb)
+        rc, st = solve()
         post_process(V, ctx, nb, nch, theta, phi, dtau)
         return st
 
@@ -879,19 +963,24 @@ def main():
     solves = args.steps * nb * nch
     value = solves / dt
     nb_mean = float(np.mean([(e > 1).sum() for e, _, _, _ in bodies]))
-    fast_rows = roofline_from_times(times, all_stats, N, P, Q, mixed=True, nb=nb_mean)
+    if use_fgmres:
+        fast_rows = roofline_fgmres(times, all_stats, N, P, Q, nb_mean, geom, args.inner_iters, nch)
+    else:
+        fast_rows = roofline_from_times(times, all_stats, N, P, Q, mixed=True, nb=nb_mean)
     dom = max(fast_rows, key=lambda k: fast_rows[k]["ms_total"])
     d = fast_rows[dom]
-    # the whole FP32 operator product: its five passes' algorithmic bytes over
-    # their summed kernel time in the timed region
-    mv_rows = [v for k, v in fast_rows.items() if k.endswith("_f32")]
+    # the whole FP32 operator product of the body grid: its five passes'
+    # algorithmic bytes over their summed kernel time in the timed region
+    mv_keys = sorted(k for k in fast_rows if k.endswith("_f32") and not k.startswith("block_"))
+    mv_rows = [fast_rows[k] for k in mv_keys]
     mv_bytes = sum(v["bytes"] for v in mv_rows)
     mv_ms = sum(v["ms_total"] for v in mv_rows)
-    matvec = {"passes": sorted(k for k in fast_rows if k.endswith("_f32")),
+    zrow = fast_rows.get("fft_z_green_f32", {"rhs_execs": 0})
+    matvec = {"passes": mv_keys,
               "GBps": mv_bytes / (mv_ms * 1e-3) / 1e9 if mv_ms > 0 else None,
               "frac": mv_bytes / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if mv_ms > 0 else None,
-              "rhs_products": fast_rows[dom]["rhs_execs"],
-              "rhs_products_per_s": fast_rows[dom]["rhs_execs"] / (mv_ms * 1e-3) if mv_ms > 0 else None}
+              "rhs_products": zrow["rhs_execs"],
+              "rhs_products_per_s": zrow["rhs_execs"] / (mv_ms * 1e-3) if mv_ms > 0 else None}
     conv = all(s["converged"] for s in all_stats)
     max_res = max(s["rel_res"] for s in all_stats)
     prod_fast = np.mean([s["matvecs"] for s in all_stats])
@@ -923,7 +1012,7 @@ def main():
                  "kernels": prow}
     learned = None
     if not args.no_learned and os.path.exists(args.weights):
-        learned = learned_leg(V, torch, ctx, args, chans, nb, nch, theta, phi, dtau, value)
+        learned = learned_leg(V, torch, ctx, args, chans, nb, nch, theta, phi, dtau, value, solve)
     sweep = None
     if not args.no_sweep:
         sweep = farfield_sweep(V, torch, ctx, args, chans, nch, int((bodies[0][0] != 1.0).sum()))
@@ -958,7 +1047,14 @@ def main():
                                 f"on a 181-point detector scan, circular g2 scan + 200-delay Nc"),
                    "bodies": nb, "channels_per_body": nch, "grid": list(N), "fft": list(P),
                    "tol": args.tol, "precision": "mixed (FP32 product, FP64 refinement)",
-                   "inner_tol": args.inner_tol, "warm_start": False},
+                   "solver": ({"method": "FGMRES, block-Jacobi right preconditioner",
+                               "restart": args.restart, "blocks": list(blocks),
+                               "inner_gmres_steps": args.inner_iters,
+                               "block_grid": list(geom["N"]), "block_fft": list(geom["P"]),
+                               "blocks_per_body": geom["blocks_per_body"]}
+                              if use_fgmres else {"method": "BiCGSTAB with FP64 refinement",
+                                                  "inner_tol": args.inner_tol}),
+                   "warm_start": False},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS,
                      "traffic": (mt or {}).get("bytes_per_launch"),
@@ -969,6 +1065,8 @@ def main():
         "cpu_baseline": cpu,
         "fast": {"converged": conv, "max_rel_res": max_res, "products_mean": float(prod_fast),
                  "iters_mean": float(np.mean([s["iters"] for s in all_stats])),
+                 "block_products_mean": (float(np.mean([s["iters"] for s in all_stats]))
+                                         * args.inner_iters if use_fgmres else 0.0),
                  "kernels": fast_rows},
         "other_kernels": other_rows(times),
         "plain_fp64": plain,

@@ -146,15 +146,17 @@ typedef struct {
 } vie_fgmres_options;
 
 /* Solve like vie_solve (same channels, stats, solution storage and return
- * codes) with right-preconditioned restarted FGMRES from w = 0, for a
- * context holding exactly one body (VIE_ENOTSUP otherwise).  The Arnoldi
- * products use the context's precision; every cycle ends with the FP64 true
- * residual, which alone decides convergence (tol and max_iter of the
+ * codes, all bodies and grids of the context batched) with right-
+ * preconditioned restarted FGMRES.  Start: w = 0, or with warm_start the
+ * network's guess under the same residual check and fallback as vie_solve.
+ * The Arnoldi products use the context's precision; every cycle ends with the
+ * FP64 true residual, which alone decides convergence (tol and max_iter of the
  * context: max_iter caps the Arnoldi steps).  stats: iters = Arnoldi steps,
  * cycles = FP64 residual products, matvecs = iters + cycles (the block
  * products, inner_iters per step, are not counted).  VIE_EINVAL for options
- * out of range.  The first call with a new partition builds the block
- * sub-problems (a spectrum for the padded block grid). */
+ * out of range for any grid of the context.  The first call with a new
+ * partition builds the block sub-problems of every body (one spectrum per
+ * group on the common cropped block grid). */
 int vie_solve_fgmres(vie_ctx *ctx, const vie_planewave *inc, const int32_t *nrhs_per_body,
                      const vie_fgmres_options *opt, vie_stats *stats);
 
@@ -242,8 +244,12 @@ int vie_set_stream(vie_ctx *ctx, void *hip_stream);
 
 /* Per-kernel-kind durations recorded with HIP events while VIE_FLAG_TIMING is
  * set: names[k] (static strings), total milliseconds ms[k] and launch counts
- * cnt[k] for k < *nkinds (in: capacity, out: number of kinds).  reset != 0
- * clears the accumulators after reading. */
+ * cnt[k] for k < *nkinds (in: capacity, out: number of kinds).  Kinds: the
+ * five product passes per precision ("fft_x_fwd_f64" ... "fft_x_inv_f32"),
+ * Krylov vector work, reductions, far field, setup, network; the same five
+ * passes of the block solves of vie_solve_fgmres ("block_fft_..."), and its
+ * Arnoldi vector kernels ("arnoldi").  reset != 0 clears the accumulators
+ * after reading. */
 int vie_kernel_times(vie_ctx *ctx, const char **names, double *ms, int64_t *cnt,
                      int32_t *nkinds, int32_t reset);
 

@@ -220,11 +220,20 @@ struct HessLS {
 
 }  // namespace
 
+// Timing kinds: the product passes, vector work and setup of the context's
+// own groups (0..14), the product passes of the block solves run on a
+// block-Jacobi sub-context (15..24, same order as 0..9), and the Arnoldi
+// vector kernels of FGMRES (25).
 static const char* kKindNames[] = {
-    "fft_x_fwd_f64", "fft_y_fwd_f64", "fft_z_green_f64", "fft_y_inv_f64", "fft_x_inv_f64",
-    "fft_x_fwd_f32", "fft_y_fwd_f32", "fft_z_green_f32", "fft_y_inv_f32", "fft_x_inv_f32",
-    "krylov_vec",    "finalize",      "farfield",        "init",          "cnn_forward"};
-static constexpr int kNumKinds = 15;
+    "fft_x_fwd_f64",       "fft_y_fwd_f64",       "fft_z_green_f64",       "fft_y_inv_f64",
+    "fft_x_inv_f64",       "fft_x_fwd_f32",       "fft_y_fwd_f32",         "fft_z_green_f32",
+    "fft_y_inv_f32",       "fft_x_inv_f32",       "krylov_vec",            "finalize",
+    "farfield",            "init",                "cnn_forward",           "block_fft_x_fwd_f64",
+    "block_fft_y_fwd_f64", "block_fft_z_green_f64", "block_fft_y_inv_f64", "block_fft_x_inv_f64",
+    "block_fft_x_fwd_f32", "block_fft_y_fwd_f32", "block_fft_z_green_f32", "block_fft_y_inv_f32",
+    "block_fft_x_inv_f32", "arnoldi"};
+static constexpr int kNumKinds = 26;
+static constexpr int kBlockKind0 = 15, kArnoldiKind = 25;
 
 struct vie_cnn {
   vie::Cnn c;
@@ -1425,6 +1434,7 @@ static int bj_apply(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo, co
   }
   vie_ctx* sub = P.sub;
   sub->stream = ctx->stream;
+  sub->opt.flags = (sub->opt.flags & ~VIE_FLAG_TIMING) | (ctx->opt.flags & VIE_FLAG_TIMING);
   Group& Gp = *sub->groups[0];
   ArnoldiBufs& A = P.ab;
   const int k = fo->inner_iters;
@@ -1450,7 +1460,7 @@ static int bj_apply(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo, co
   for (int j = 0; j < k; ++j) {
     EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
     VIE_HIP(run_matvec(sub, Gp, ip, V + (size_t)j * tot, A.w.as<c64>(), e, A.act.as<int>()));
-    VIE_HIP(arnoldi_orth(ctx, A, S, tot, k, j));
+    VIE_HIP(timed(ctx, kArnoldiKind, [&] { return arnoldi_orth(ctx, A, S, tot, k, j); }));
   }
   std::vector<c64> h1((size_t)k * nseg * ldn), h2((size_t)k * nseg * ldn), coef((size_t)nseg * ldn);
   std::vector<double> nr((size_t)nseg * ldn);
@@ -1588,7 +1598,7 @@ static int fgmres_group(vie_ctx* ctx, Group& G, BlockPrec* P, const vie_fgmres_o
       }
       EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
       VIE_HIP(run_matvec(ctx, G, prec, zj, A.w.as<c64>(), e, A.act.as<int>()));
-      VIE_HIP(arnoldi_orth(ctx, A, S, tot, m, j));
+      VIE_HIP(timed(ctx, kArnoldiKind, [&] { return arnoldi_orth(ctx, A, S, tot, m, j); }));
       VIE_HIP(hipMemcpyAsync(h1.data(), A.H1.as<c64>() + (size_t)j * nrhs * (m + 1),
                              h1.size() * sizeof(c64), hipMemcpyDeviceToHost, ctx->stream));
       VIE_HIP(hipMemcpyAsync(h2.data(), A.H2.as<c64>() + (size_t)j * nrhs * (m + 1),
@@ -2231,6 +2241,16 @@ extern "C" int vie_kernel_times(vie_ctx* ctx, const char** names, double* ms, in
                                 int32_t* nkinds, int32_t reset) {
   if (!ctx || !nkinds) return VIE_EINVAL;
   timing_collect(ctx);
+  for (auto& P : ctx->bj) {  // block products of the sub-contexts
+    if (!P || !P->sub) continue;
+    timing_collect(P->sub);
+    for (int k = 0; k < 10; ++k) {
+      ctx->kind_ms[kBlockKind0 + k] += P->sub->kind_ms[k];
+      ctx->kind_cnt[kBlockKind0 + k] += P->sub->kind_cnt[k];
+      P->sub->kind_ms[k] = 0;
+      P->sub->kind_cnt[k] = 0;
+    }
+  }
   const int n = std::min<int>(*nkinds, kNumKinds);
   for (int k = 0; k < n; ++k) {
     if (names) names[k] = kKindNames[k];
