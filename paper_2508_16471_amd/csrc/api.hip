@@ -133,6 +133,7 @@ struct TimedEvent {
 // brings it to the host) and the squared norms NR[s][j] (NR[s][0] = ||r||^2).
 struct ArnoldiBufs {
   DevBuf V, Z, w, H1, H2, NR, dpart, npart, off, len, act, nvs, coef;
+  DevBuf W2, act2;  // ||w||^2 before orthogonalisation, reorthogonalisation flags
 };
 
 // Block-Jacobi preconditioner of one group: every body split into bx x by
@@ -1188,6 +1189,8 @@ static int arnoldi_alloc(vie_ctx* ctx, ArnoldiBufs& A, int nseg, int maxlen, int
   VIE_HIP(A.act.reserve((size_t)nseg * sizeof(int)));
   VIE_HIP(A.nvs.reserve((size_t)nseg * sizeof(int)));
   VIE_HIP(A.coef.reserve((size_t)nseg * (m + 1) * sizeof(c64)));
+  VIE_HIP(A.W2.reserve((size_t)nseg * sizeof(double)));
+  VIE_HIP(A.act2.reserve((size_t)nseg * sizeof(int)));
   return VIE_OK;
 }
 
@@ -1202,8 +1205,11 @@ static int arnoldi_tables(vie_ctx* ctx, ArnoldiBufs& A, const std::vector<int64_
 }
 
 // Step j of the Arnoldi process after the caller has put the product into w:
-// classical Gram-Schmidt against V_0..V_j applied twice (both coefficient
-// passes kept in H1, H2), ||w||^2 into NR[s][j+1], V_{j+1} = w / ||w||.
+// classical Gram-Schmidt against V_0..V_j (coefficients in H1), repeated
+// (coefficients in H2, zero where skipped) for the segments whose norm fell
+// below 1/sqrt(2) of its value before the pass (the "twice is enough"
+// criterion of Daniel, Gragg, Kaufman and Stewart 1976); ||w||^2 into
+// NR[s][j+1], V_{j+1} = w / ||w||.
 static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, int64_t stride,
                                int m, int j) {
   c64* V = A.V.as<c64>();
@@ -1212,18 +1218,27 @@ static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, in
   c64* h1 = A.H1.as<c64>() + (size_t)j * S.nseg * (m + 1);
   c64* h2 = A.H2.as<c64>() + (size_t)j * S.nseg * (m + 1);
   double* nr = A.NR.as<double>() + j + 1;
+  double* npart = A.npart.as<double>();
+  SegSet S2 = S;
+  S2.active = A.act2.as<int>();
   hipError_t e;
+  if ((e = launch_seg_maxpy(S, nullptr, 0, 0, nullptr, nullptr, 0, w, npart, A.W2.as<double>(), 1,
+                            ctx->stream)) != hipSuccess)
+    return e;
   if ((e = launch_seg_mdot(S, V, stride, j + 1, w, A.dpart.as<c64>(), h1, ldh, ctx->stream)) !=
       hipSuccess)
     return e;
-  if ((e = launch_seg_maxpy(S, V, stride, j + 1, nullptr, h1, ldh, w, nullptr, nullptr, 0,
+  if ((e = launch_seg_maxpy(S, V, stride, j + 1, nullptr, h1, ldh, w, npart, nr, m + 1,
                             ctx->stream)) != hipSuccess)
     return e;
-  if ((e = launch_seg_mdot(S, V, stride, j + 1, w, A.dpart.as<c64>(), h2, ldh, ctx->stream)) !=
+  if ((e = launch_seg_reorth_flags(S, A.W2.as<double>(), nr, m + 1, 0.5, A.act2.as<int>(),
+                                   ctx->stream)) != hipSuccess)
+    return e;
+  if ((e = launch_seg_mdot(S2, V, stride, j + 1, w, A.dpart.as<c64>(), h2, ldh, ctx->stream)) !=
       hipSuccess)
     return e;
-  if ((e = launch_seg_maxpy(S, V, stride, j + 1, nullptr, h2, ldh, w, A.npart.as<double>(), nr,
-                            m + 1, ctx->stream)) != hipSuccess)
+  if ((e = launch_seg_maxpy(S2, V, stride, j + 1, nullptr, h2, ldh, w, npart, nr, m + 1,
+                            ctx->stream)) != hipSuccess)
     return e;
   return launch_seg_normalize(S, w, nr, m + 1, V + (size_t)(j + 1) * stride, ctx->stream);
 }

@@ -38,6 +38,11 @@ hipError_t launch_seg_maxpy(const SegSet& S, const c64* V, int64_t stride, int n
                             const int* nv_seg, const c64* coef, int ldc, c64* w,
                             double* partials, double* norm2, int ldn, hipStream_t st);
 
+// act2[s] = 1 where segment s is active and after[s * ldn] < eta2 * before[s]
+// (too much cancellation in a Gram-Schmidt pass: orthogonalise again).
+hipError_t launch_seg_reorth_flags(const SegSet& S, const double* before, const double* after,
+                                  int ldn, double eta2, int* act2, hipStream_t st);
+
 // dst = src / sqrt(norm2[s * ldn]) per segment (zero where norm2 is 0).
 hipError_t launch_seg_normalize(const SegSet& S, const c64* src, const double* norm2, int ldn,
                                 c64* dst, hipStream_t st);

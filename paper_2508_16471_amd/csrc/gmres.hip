@@ -1,5 +1,5 @@
 // Segmented multi-vector kernels of the flexible GMRES driver (Arnoldi with
-// classical Gram-Schmidt applied twice, solution update) and the permutation
+// classical Gram-Schmidt and selective reorthogonalisation, solution update) and the permutation
 // between a body's vector and its block-ordered copy (block-Jacobi
 // preconditioner).  All work is HBM-bound streaming over FP64 complex vectors:
 // one coalesced 16-byte load per element per vector, reductions through
@@ -115,6 +115,15 @@ __global__ __launch_bounds__(64) void k_seg_sum_r(SegSet S, const double* __rest
   if (threadIdx.x == 0) out[(int64_t)s * ldn] = t;
 }
 
+__global__ void k_seg_reorth_flags(SegSet S, const double* __restrict__ before,
+                                   const double* __restrict__ after, int ldn, double eta2,
+                                   int* __restrict__ act2) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S.nseg) return;
+  const bool on = !S.active || S.active[s];
+  act2[s] = (on && after[(int64_t)s * ldn] < eta2 * before[s]) ? 1 : 0;
+}
+
 __global__ __launch_bounds__(GT) void k_seg_normalize(SegSet S, const c64* __restrict__ src,
                                                       const double* __restrict__ norm2, int ldn,
                                                       c64* __restrict__ dst) {
@@ -170,6 +179,13 @@ hipError_t launch_seg_maxpy(const SegSet& S, const c64* V, int64_t stride, int n
   k_seg_maxpy<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, V, stride, nv, nv_seg, coef, ldc, w,
                                                    norm2 ? partials : nullptr);
   if (norm2) k_seg_sum_r<<<S.nseg, 64, 0, st>>>(S, partials, norm2, ldn);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_reorth_flags(const SegSet& S, const double* before, const double* after,
+                                  int ldn, double eta2, int* act2, hipStream_t st) {
+  if (S.nseg < 1) return hipSuccess;
+  k_seg_reorth_flags<<<(S.nseg + 63) / 64, 64, 0, st>>>(S, before, after, ldn, eta2, act2);
   return hipGetLastError();
 }
 
