@@ -81,11 +81,11 @@ def rhs(chi, pos, k0, khat, pol):
     return chi[None, :] * incident_field(pos, k0, khat, pol)
 
 
-def _green_apply_rows(pos, rows, src, x_src, h, k0):
+def _green_apply_rows(pos, rows, src, x_src, h, k0, s_self=None):
     """sum_n Ghat(r_row - r_n) x_n over the sources ``src`` (indices) for the
-    given rows, including the diagonal s x_row when the row is a source.
-    Returns (3, len(rows))."""
-    s = self_term(k0, h)
+    given rows, including the diagonal s x_row when the row is a source
+    (s = self_term unless s_self is given).  Returns (3, len(rows))."""
+    s = self_term(k0, h) if s_self is None else s_self
     scale = k0 * k0 * h**3
     P = pos[src]
     out = np.zeros((3, len(rows)), complex)
@@ -115,50 +115,52 @@ def _green_apply_rows(pos, rows, src, x_src, h, k0):
     return out
 
 
-def matvec_rows(chi, pos, h, k0, x, rows):
+def matvec_rows(chi, pos, h, k0, x, rows, s_self=None):
     """Rows of y = A x = x - chi * (Ghat x), summing directly over every voxel
     where x is non-zero (O(M) per row).  chi: (M,), x: (3, M)."""
     rows = np.asarray(rows, dtype=np.int64)
     src = np.nonzero(np.any(x != 0, axis=0))[0]
-    gx = _green_apply_rows(pos, rows, src, x[:, src], h, k0) if len(src) else np.zeros((3, len(rows)), complex)
+    gx = (_green_apply_rows(pos, rows, src, x[:, src], h, k0, s_self) if len(src)
+          else np.zeros((3, len(rows)), complex))
     return x[:, rows] - chi[rows][None, :] * gx
 
 
-def matvec(chi, pos, h, k0, x):
+def matvec(chi, pos, h, k0, x, s_self=None):
     """Full direct product y = x - chi * (Ghat x) (O(M^2); rows with chi = 0
     reduce to the identity)."""
     y = x.astype(complex).copy()
     rows = np.nonzero(chi != 0)[0]
     if len(rows):
-        y[:, rows] = matvec_rows(chi, pos, h, k0, x, rows)
+        y[:, rows] = matvec_rows(chi, pos, h, k0, x, rows, s_self)
     return y
 
 
-def green_matrix(pos, h, k0):
-    """Dense Ghat over the given voxels, index ``comp * M + voxel``."""
+def green_matrix(pos, h, k0, s_self=None):
+    """Dense Ghat over the given voxels, index ``comp * M + voxel`` (diagonal
+    self_term unless s_self is given)."""
     M = len(pos)
     R = pos[:, None, :] - pos[None, :, :]
     eye = np.eye(M, dtype=bool)
     R[eye] = 1.0  # placeholder, overwritten below
     G = green_dyadic(R, k0) * (k0 * k0 * h**3)
-    G[eye] = self_term(k0, h) * np.eye(3)
+    G[eye] = (self_term(k0, h) if s_self is None else s_self) * np.eye(3)
     return G.transpose(2, 0, 3, 1).reshape(3 * M, 3 * M)
 
 
-def body_system(chi, pos, h, k0):
+def body_system(chi, pos, h, k0, s_self=None):
     """A = I - diag(chi) Ghat restricted to the body voxels (chi != 0).
     Returns (A, body_indices)."""
     body = np.nonzero(chi != 0)[0]
-    G = green_matrix(pos[body], h, k0)
+    G = green_matrix(pos[body], h, k0, s_self)
     c = np.tile(chi[body], 3)
     A = np.eye(3 * len(body), dtype=complex) - c[:, None] * G
     return A, body
 
 
-def solve_lu(chi, pos, h, k0, khat, pol):
+def solve_lu(chi, pos, h, k0, khat, pol, s_self=None):
     """Exact solution of the discrete system by dense LU (w = 0 off the body).
     Returns w (3, M)."""
-    A, body = body_system(chi, pos, h, k0)
+    A, body = body_system(chi, pos, h, k0, s_self)
     b = rhs(chi, pos, k0, khat, pol)[:, body].reshape(-1)
     wb = scipy.linalg.lu_solve(scipy.linalg.lu_factor(A), b)
     w = np.zeros((3, len(chi)), complex)
