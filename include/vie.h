@@ -15,6 +15,15 @@
  *     s = -1/3 + 2/3 (cos x + x sin x - 1) + i k0^3 h^3 / (6 pi),
  *     x = k0 h (3 / 4 pi)^(1/3),
  *
+ * or, with VIE_FLAG_CUBE_SELF, the voxel's own singular integral (the paper
+ * leaves the self-term integral open):
+ *
+ *     s_cube = -1/3 + (2 k0^2 / 3) integral over the cube of e^{i k0 r} / (4 pi r) dV
+ *
+ * (-1/3: the cube's static principal value; its imaginary part equals the
+ * radiation reaction k0^3 h^3 / (6 pi) only to leading order in k0 h, so that
+ * discrete model is not exactly lossless),
+ *
  * solves it with BiCGSTAB around an FFT-accelerated product (Sec. II-C),
  * evaluates the far-field amplitude of eq. 25,
  *     F(r) = k0^2 h^3 / (4 pi) (I - r r) sum_n w_n exp(-i k0 r . r_n)
@@ -63,9 +72,12 @@ enum { VIE_FP64 = 0, VIE_MIXED = 1 };
 enum { VIE_NORM_R1 = 0, VIE_NORM_R2 = 1 };
 enum {
   VIE_FLAG_TIMING = 1,  /* record per-kernel HIP-event durations (disables graphs) */
-  VIE_FLAG_NO_GRAPH = 2 /* launch every BiCGSTAB iteration eagerly instead of     */
-                        /* replaying a captured hipGraph of VIE_GRAPH_ITERS        */
-                        /* iterations (results are identical either way)           */
+  VIE_FLAG_NO_GRAPH = 2, /* launch every BiCGSTAB iteration eagerly instead of    */
+                         /* replaying a captured hipGraph of VIE_GRAPH_ITERS       */
+                         /* iterations (results are identical either way)          */
+  VIE_FLAG_CUBE_SELF = 4 /* self term of the exact cube cell instead of the        */
+                         /* equal-volume sphere (see below); read by vie_setup,    */
+                         /* vie_set_options may not change it                      */
 };
 enum { VIE_GRAPH_ITERS = 8 };
 
@@ -189,6 +201,12 @@ int vie_farfield(vie_ctx *ctx, int32_t body, const double *theta, const double *
  * g2, Nc_raw, Nc_norm may each be NULL. */
 int hom_g2(const vie_c64 T[4], const double *omega, double sigma, const double *dtau,
            int32_t ndelay, int32_t norm, double *g2, double *Nc_raw, double *Nc_norm);
+
+/* Diagonal coefficient s of the discrete operator for voxel edge h (host
+ * arithmetic): kind 0 = the default equal-volume-sphere term, kind 1 = the
+ * exact cube cell (VIE_FLAG_CUBE_SELF), both as defined at the top of this
+ * header.  VIE_EINVAL for another kind or non-positive / non-finite k0, h. */
+int vie_self_term(int32_t kind, double k0, double h, vie_c64 *s);
 
 /* Classical comparison observable (eq. 27): for deterministic fields, the
  * product of the two detectors' intensities of the coherent superposition of

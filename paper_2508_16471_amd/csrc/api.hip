@@ -13,6 +13,7 @@
 #include "../../include/vie.h"
 #include "cnn.h"
 #include "gmres.h"
+#include "green.h"
 #include "kernels.h"
 
 using namespace vie;
@@ -365,7 +366,14 @@ static int build_spectrum(vie_ctx* ctx, Group& G) {
   VIE_HIP(G.spec32.reserve(6 * oct * sizeof(c32)));
   const void* tw[3] = {G.tw64[0].p, G.tw64[1].p, G.tw64[2].p};
   for (int ab = 0; ab < 6; ++ab) {
-    VIE_HIP(launch_green_sample(work.as<c64>(), g, ab, G.h, ctx->opt.k0, ctx->stream));
+    if (ctx->opt.flags & VIE_FLAG_CUBE_SELF) {
+      double sr, si;
+      self_term_cube(ctx->opt.k0, G.h, &sr, &si);
+      VIE_HIP(launch_green_sample_self(work.as<c64>(), g, ab, G.h, ctx->opt.k0, sr, si,
+                                       ctx->stream));
+    } else {
+      VIE_HIP(launch_green_sample(work.as<c64>(), g, ab, G.h, ctx->opt.k0, ctx->stream));
+    }
     VIE_HIP(launch_fft3d_full(work.as<c64>(), tmp.as<c64>(), g, tw, ctx->stream));
     VIE_HIP(launch_octant(tmp.as<c64>(), G.spec64.as<c64>(), G.spec32.as<c32>(), g, ab,
                           ctx->stream));
@@ -559,6 +567,7 @@ extern "C" int vie_set_options(vie_ctx* ctx, const vie_options* opt) {
   if (!ctx) return VIE_EINVAL;
   if (ctx->poisoned) return VIE_ESTATE;
   if (!valid_options(opt) || opt->k0 != ctx->opt.k0) return VIE_EINVAL;
+  if ((opt->flags ^ ctx->opt.flags) & VIE_FLAG_CUBE_SELF) return VIE_EINVAL;  // fixed at setup
   ctx->opt = *opt;
   return VIE_OK;
 }
@@ -1348,7 +1357,7 @@ static int bj_build(vie_ctx* ctx, int gi, const vie_fgmres_options* fo) {
     so.precision = VIE_MIXED;
     so.inner_tol = 1e-3;
     so.warm_start = 0;
-    so.flags = VIE_FLAG_NO_GRAPH;
+    so.flags = VIE_FLAG_NO_GRAPH | (ctx->opt.flags & VIE_FLAG_CUBE_SELF);  // same operator
     int rc = vie_setup(bodies.data(), P->nsub, &so, &P->sub);
     if (rc != VIE_OK) return rc;
     // the sub-context's compressed order must be the block order used above
@@ -2078,6 +2087,20 @@ extern "C" int hom_g2(const vie_c64 T[4], const double* omega, double sigma, con
 
 // Classical fourth-order correlation (eq. 27) of the coherent superposition
 // of the two channels' responses: |T_a1 + T_a2|^2 |T_b1 + T_b2|^2.
+extern "C" int vie_self_term(int32_t kind, double k0, double h, vie_c64* s) {
+  if (!s || !(k0 > 0) || !(h > 0) || !isfinite(k0) || !isfinite(h)) return VIE_EINVAL;
+  double re, im;
+  if (kind == 0)
+    self_term_sphere(k0, h, &re, &im);
+  else if (kind == 1)
+    self_term_cube(k0, h, &re, &im);
+  else
+    return VIE_EINVAL;
+  s->re = re;
+  s->im = im;
+  return VIE_OK;
+}
+
 extern "C" int hom_classical_p2(const vie_c64 T[4], double* p2) {
   if (!T || !p2) return VIE_EINVAL;
   for (int i = 0; i < 4; ++i)

@@ -9,7 +9,11 @@
 // function is (I + grad grad / k0^2) e^{i k0 R} / (4 pi R), differentiated in
 // closed form.  Each component is even or odd along each axis, so its DFT
 // has the same parity and only the octant [0, P/2]^3 is stored.
-#include "kernels.h"
+#include <math.h>
+
+#include <vector>
+
+#include "green.h"
 
 namespace vie {
 
@@ -90,6 +94,80 @@ hipError_t launch_green_sample(c64* work, const GroupGeom& g, int ab, double h, 
                                hipStream_t s) {
   k_green_sample<<<2048, 256, 0, s>>>(work, g, ab, h, k0, self_term_re(k0, h),
                                       self_term_im(k0, h));
+  return hipGetLastError();
+}
+
+// Exact-cube self term: s = -1/3 + (2 k0^2 / 3) I with I the integral of
+// e^{i k0 r} / (4 pi r) over the voxel (a cube of edge h about the collocation
+// point).  The -1/3 is the cube's static principal value (depolarisation
+// I/3, by cubic symmetry); the remainder of the dyadic kernel is integrable
+// with trace 2 g.  In spherical coordinates the radial integral is
+// elementary, int_0^R r e^{ikr} dr = (e^{ikR}(1 - ikR) - 1) / k^2, and the
+// solid angle is covered through the six (equal) faces: on the face x = h/2,
+// dOmega = (h/2) dy dz / R^3.  Gauss-Legendre on a quarter face (the
+// integrand is smooth there, R >= h/2).
+static void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double t = cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+      const double dt = p1 / dp;
+      t -= dt;
+      if (fabs(dt) < 1e-16) break;
+    }
+    x[i] = 0.5 * (1.0 - t);  // on [0, 1]
+    w[i] = 1.0 / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+void self_term_cube(double k0, double h, double* re, double* im) {
+  const double c = 0.5 * h;
+  std::vector<double> x, w;
+  gauss_legendre01(40, x, w);
+  double sr = 0.0, si = 0.0;
+  for (size_t i = 0; i < x.size(); ++i)
+    for (size_t j = 0; j < x.size(); ++j) {
+      const double y = c * x[i], z = c * x[j];
+      const double R = sqrt(c * c + y * y + z * z);
+      const double t = k0 * R;
+      // e^{it}(1 - it) - 1 = (t sin t - 2 sin^2(t/2)) + i (sin t - t cos t),
+      // the imaginary part by its series where the difference would cancel
+      const double sh = sin(0.5 * t);
+      const double fr = t * sin(t) - 2.0 * sh * sh;
+      double fi;
+      if (t < 0.1) {
+        const double t2 = t * t;
+        fi = t * t2 * (1.0 / 3 - t2 * (1.0 / 30 - t2 * (1.0 / 840 - t2 * (1.0 / 45360 - t2 / 3991680))));
+      } else {
+        fi = sin(t) - t * cos(t);
+      }
+      const double wt = w[i] * w[j] * c * c * c / (R * R * R);  // quarter-face area c^2 times dOmega factor
+      sr += wt * fr;
+      si += wt * fi;
+    }
+  // six faces x four quarters, 1 / (4 pi), radial integral / k0^2, times 2 k0^2 / 3
+  const double f = 24.0 / (4.0 * M_PI) * (2.0 / 3.0);
+  *re = -1.0 / 3.0 + f * sr;
+  *im = f * si;
+}
+
+void self_term_sphere(double k0, double h, double* re, double* im) {
+  *re = self_term_re(k0, h);
+  *im = self_term_im(k0, h);
+}
+
+hipError_t launch_green_sample_self(c64* work, const GroupGeom& g, int ab, double h, double k0,
+                                    double s_re, double s_im, hipStream_t s) {
+  k_green_sample<<<2048, 256, 0, s>>>(work, g, ab, h, k0, s_re, s_im);
   return hipGetLastError();
 }
 

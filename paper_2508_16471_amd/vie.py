@@ -20,6 +20,7 @@ VIE_FP64, VIE_MIXED = 0, 1
 VIE_NORM_R1, VIE_NORM_R2 = 0, 1
 VIE_FLAG_TIMING = 1
 VIE_FLAG_NO_GRAPH = 2
+VIE_FLAG_CUBE_SELF = 4
 
 
 class vie_c64(C.Structure):
@@ -84,6 +85,7 @@ def lib():
             "vie_farfield": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), P(C.c_double),
                                        C.c_int32, P(vie_c64)]),
             "hom_classical_p2": (C.c_int, [P(vie_c64), P(C.c_double)]),
+            "vie_self_term": (C.c_int, [C.c_int32, C.c_double, C.c_double, P(vie_c64)]),
             "vie_transfer_na": (C.c_int, [C.c_void_p, C.c_int32, P(vie_na_detector), C.c_int32,
                                           C.c_int32, C.c_int32, P(vie_c64)]),
             "hom_g2": (C.c_int, [P(vie_c64), P(C.c_double), C.c_double, P(C.c_double), C.c_int32,
@@ -222,6 +224,13 @@ def vie_farfield(ctx, body, theta, phi, nrhs):
     F = np.zeros((nrhs, len(th), 2), dtype=np.complex128)
     _check(lib().vie_farfield(ctx, int(body), _dptr(th), _dptr(ph), len(th), _cptr(F)), "vie_farfield")
     return F
+
+
+def vie_self_term(kind, k0, h):
+    """Diagonal coefficient of the discrete operator: kind 0 sphere, 1 cube."""
+    out = vie_c64()
+    _check(lib().vie_self_term(int(kind), float(k0), float(h), C.byref(out)), "vie_self_term")
+    return complex(out.re, out.im)
 
 
 def hom_classical_p2(T):
