@@ -1215,12 +1215,12 @@ static int arnoldi_tables(vie_ctx* ctx, ArnoldiBufs& A, const std::vector<int64_
 
 // Step j of the Arnoldi process after the caller has put the product into w:
 // classical Gram-Schmidt against V_0..V_j (coefficients in H1), repeated
-// (coefficients in H2, zero where skipped) for the segments whose norm fell
-// below 1/sqrt(2) of its value before the pass (the "twice is enough"
-// criterion of Daniel, Gragg, Kaufman and Stewart 1976); ||w||^2 into
-// NR[s][j+1], V_{j+1} = w / ||w||.
+// (coefficients in H2, zero where skipped) for the segments whose squared norm
+// fell below eta2 times its value before the pass (eta2 = 1/2: the "twice is
+// enough" criterion of Daniel, Gragg, Kaufman and Stewart 1976; eta2 = 0: one
+// pass); ||w||^2 into NR[s][j+1], V_{j+1} = w / ||w||.
 static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, int64_t stride,
-                               int m, int j) {
+                               int m, int j, double eta2) {
   c64* V = A.V.as<c64>();
   c64* w = A.w.as<c64>();
   const int ldh = m + 1;
@@ -1231,8 +1231,8 @@ static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, in
   SegSet S2 = S;
   S2.active = A.act2.as<int>();
   hipError_t e;
-  if ((e = launch_seg_maxpy(S, nullptr, 0, 0, nullptr, nullptr, 0, w, npart, A.W2.as<double>(), 1,
-                            ctx->stream)) != hipSuccess)
+  if (eta2 > 0 && (e = launch_seg_maxpy(S, nullptr, 0, 0, nullptr, nullptr, 0, w, npart,
+                                         A.W2.as<double>(), 1, ctx->stream)) != hipSuccess)
     return e;
   if ((e = launch_seg_mdot(S, V, stride, j + 1, w, A.dpart.as<c64>(), h1, ldh, ctx->stream)) !=
       hipSuccess)
@@ -1240,7 +1240,7 @@ static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, in
   if ((e = launch_seg_maxpy(S, V, stride, j + 1, nullptr, h1, ldh, w, npart, nr, m + 1,
                             ctx->stream)) != hipSuccess)
     return e;
-  if ((e = launch_seg_reorth_flags(S, A.W2.as<double>(), nr, m + 1, 0.5, A.act2.as<int>(),
+  if ((e = launch_seg_reorth_flags(S, A.W2.as<double>(), nr, m + 1, eta2, A.act2.as<int>(),
                                    ctx->stream)) != hipSuccess)
     return e;
   if ((e = launch_seg_mdot(S2, V, stride, j + 1, w, A.dpart.as<c64>(), h2, ldh, ctx->stream)) !=
@@ -1484,7 +1484,10 @@ static int bj_apply(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo, co
   for (int j = 0; j < k; ++j) {
     EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
     VIE_HIP(run_matvec(sub, Gp, ip, V + (size_t)j * tot, A.w.as<c64>(), e, A.act.as<int>()));
-    VIE_HIP(timed(ctx, kArnoldiKind, [&] { return arnoldi_orth(ctx, A, S, tot, k, j); }));
+    // the block solves are approximations: with FP32 block products one
+    // Gram-Schmidt pass is enough
+    const double eta2 = ip ? 0.0 : 0.5;
+    VIE_HIP(timed(ctx, kArnoldiKind, [&] { return arnoldi_orth(ctx, A, S, tot, k, j, eta2); }));
   }
   std::vector<c64> h1((size_t)k * nseg * ldn), h2((size_t)k * nseg * ldn), coef((size_t)nseg * ldn);
   std::vector<double> nr((size_t)nseg * ldn);
@@ -1622,7 +1625,7 @@ static int fgmres_group(vie_ctx* ctx, Group& G, BlockPrec* P, const vie_fgmres_o
       }
       EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
       VIE_HIP(run_matvec(ctx, G, prec, zj, A.w.as<c64>(), e, A.act.as<int>()));
-      VIE_HIP(timed(ctx, kArnoldiKind, [&] { return arnoldi_orth(ctx, A, S, tot, m, j); }));
+      VIE_HIP(timed(ctx, kArnoldiKind, [&] { return arnoldi_orth(ctx, A, S, tot, m, j, 0.5); }));
       VIE_HIP(hipMemcpyAsync(h1.data(), A.H1.as<c64>() + (size_t)j * nrhs * (m + 1),
                              h1.size() * sizeof(c64), hipMemcpyDeviceToHost, ctx->stream));
       VIE_HIP(hipMemcpyAsync(h2.data(), A.H2.as<c64>() + (size_t)j * nrhs * (m + 1),

@@ -121,7 +121,7 @@ __global__ void k_seg_reorth_flags(SegSet S, const double* __restrict__ before,
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S.nseg) return;
   const bool on = !S.active || S.active[s];
-  act2[s] = (on && after[(int64_t)s * ldn] < eta2 * before[s]) ? 1 : 0;
+  act2[s] = (on && eta2 > 0.0 && after[(int64_t)s * ldn] < eta2 * before[s]) ? 1 : 0;
 }
 
 __global__ __launch_bounds__(GT) void k_seg_normalize(SegSet S, const c64* __restrict__ src,
