@@ -231,3 +231,23 @@ def test_fgmres_warm_start_fallback(V):
     finally:
         V.vie_destroy(ctx)
         V.vie_cnn_destroy(net)
+
+
+def test_fgmres_empty_body_and_silent_body(V):
+    """A body without voxels (eps = 1 everywhere) converges at once with w = 0;
+    a body given no channels is skipped; the third body still matches LU."""
+    g, eps, chi, pos, A, body = _case(25)
+    empty = np.ones_like(eps)
+    bodies = [(empty, g.h, g.origin), (eps, g.h, g.origin), (eps, g.h, g.origin)]
+    ctx = V.vie_setup(bodies, V.make_options(K0, precision=V.VIE_FP64, tol=1e-10, max_iter=2000))
+    try:
+        rc, st = V.vie_solve_fgmres(ctx, CHANS[:2], [1, 0, 1], V.fgmres_options(8, (2, 2), 3))
+        assert rc == 0 and st[0]["converged"] and st[0]["iters"] == 0 and st[0]["rel_res"] == 0
+        w0 = V.vie_get_current(ctx, 0, 0, g.n)
+        assert np.all(w0 == 0)
+        kh, p = CHANS[1]
+        want = scipy.linalg.lu_solve(scipy.linalg.lu_factor(A), _rhs(chi, pos, body, kh, p))
+        got = _body_vec(V.vie_get_current(ctx, 2, 0, g.n), body)
+        assert np.linalg.norm(got - want) < 1e-8 * np.linalg.norm(want)
+    finally:
+        V.vie_destroy(ctx)
