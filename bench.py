@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--precond-body", choices=["family", "metasurface"], default="family",
                     help="precond mode: the benchmark family (--bodies x --channels) or the "
                          "256x256x48 PB metasurface (one body, --channels uv directions x L/R)")
+    ap.add_argument("--no-window", action="store_true",
+                    help="solve and precond modes: compute on the full grid instead of the z "
+                         "window that holds the bodies (VIE_FLAG_Z_WINDOW)")
     ap.add_argument("--configs", default="",
                     help="precond mode: comma-separated configuration names to run "
                          "(the BiCGSTAB reference always runs)")
@@ -327,12 +330,11 @@ def matvec_mode(args):
     torch.cuda.set_device(0)
     bodies, _ = make_workload(1, 1, args.grid)
     eps, h, o, g = bodies[0]
-    N = g.n
-    P = tuple(fft_length(v) for v in N)
-    Q = tuple(p // 2 + 1 for p in P)
     prec = V.VIE_MIXED if args.precision == "fp32" else V.VIE_FP64
     ctx = V.vie_setup([(eps, h, o)], V.make_options(K0, flags=V.VIE_FLAG_TIMING))
-    n = N[0] * N[1] * N[2]
+    N, P, _ = V.vie_grid(ctx, 0)  # the z window the passes run on
+    Q = tuple(p // 2 + 1 for p in P)
+    n = g.n[0] * g.n[1] * g.n[2]  # box vectors stay in the body's grid
     x = torch.randn(args.nrhs, 3 * n, dtype=torch.complex128, device="cuda")
     y = torch.empty_like(x)
     stream = torch.cuda.current_stream().cuda_stream
@@ -360,7 +362,8 @@ def matvec_mode(args):
     total = sum(v["avg_launch_ms"] for v in rows.values())
     print(json.dumps({"mode": "matvec", "precision": args.precision, "nrhs": args.nrhs,
                       "calibration": {"fill_bytes_written": 512 << 20, "sum_bytes_read": 512 << 20},
-                      "grid": list(N), "fft": list(P), "ms_per_product": dt / args.steps * 1e3,
+                      "grid": list(g.n), "window": list(N), "fft": list(P),
+                      "ms_per_product": dt / args.steps * 1e3,
                       "kernel_ms_per_product": total, "kernels": rows}))
 
 
@@ -412,7 +415,8 @@ def learned_leg(V, torch, ctx, args, chans, nb, nch, theta, phi, dtau, fast_valu
         V.vie_attach_cnn(ctx, net)
         V.vie_set_options(ctx, V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol,
                                               max_iter=20000, inner_tol=args.inner_tol,
-                                              warm_start=1, flags=V.VIE_FLAG_TIMING))
+                                              warm_start=1,
+                                              flags=V.VIE_FLAG_TIMING | args.wflag))
         solve()  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -440,7 +444,8 @@ def farfield_sweep(V, torch, ctx, args, chans, nch, nbv, reps=3):
     """360 x 180 far-field sweep (64,800 directions) of body 0's channels on
     the FP64-MFMA contraction; achieved rate from the kernel-kind time."""
     V.vie_set_options(ctx, V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
-                                          inner_tol=args.inner_tol, flags=V.VIE_FLAG_TIMING))
+                                          inner_tol=args.inner_tol,
+                                          flags=V.VIE_FLAG_TIMING | args.wflag))
     V.vie_solve(ctx, chans[:nch], [nch] + [0] * (len(chans) // nch - 1))
     th1 = (np.arange(180) + 0.5) * np.pi / 180
     ph1 = np.arange(360) * 2 * np.pi / 360 - np.pi
@@ -860,10 +865,11 @@ def precond_mode(args):
 
     torch.cuda.set_device(0)
     V.lib()
+    wflag = 0 if args.no_window else V.VIE_FLAG_Z_WINDOW
     opt = V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
-                         inner_tol=args.inner_tol)
+                         inner_tol=args.inner_tol, flags=wflag)
     opt_warm = V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
-                              inner_tol=args.inner_tol, warm_start=1)
+                              inner_tol=args.inner_tol, warm_start=1, flags=wflag)
     ctx = V.vie_setup([(e, h, o) for e, h, o, _ in bodies], opt)
     net = V.vie_cnn_create(0)
     V.vie_cnn_params(net, np.load(args.weights))
@@ -941,18 +947,19 @@ def main():
 
     torch.cuda.set_device(0)
     V.lib()
-    N = bodies[0][3].n
-    P = tuple(fft_length(v) for v in N)
-    Q = tuple(p // 2 + 1 for p in P)
+    N0 = bodies[0][3].n
     nb, nch = args.bodies, args.channels
     psi, theta, phi = detector_scan()
     dtau = np.linspace(-5, 5, 200)
 
+    args.wflag = 0 if args.no_window else V.VIE_FLAG_Z_WINDOW
     fast = V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
-                          inner_tol=args.inner_tol, flags=V.VIE_FLAG_TIMING)
+                          inner_tol=args.inner_tol, flags=V.VIE_FLAG_TIMING | args.wflag)
     t0 = time.perf_counter()
     ctx = V.vie_setup([(e, h, o) for e, h, o, _ in bodies], fast)
     setup_s = time.perf_counter() - t0
+    N, P, _ = V.vie_grid(ctx, 0)  # the z window of the group (all bodies share it)
+    Q = tuple(p // 2 + 1 for p in P)
 
     use_fgmres = args.solver == "fgmres"
     blocks = tuple(int(v) for v in args.blocks.split(","))
@@ -1008,7 +1015,7 @@ def main():
     plain = None
     if not args.no_plain:
         popt = V.make_options(K0, precision=V.VIE_FP64, tol=args.tol, max_iter=20000,
-                              flags=V.VIE_FLAG_TIMING)
+                              flags=V.VIE_FLAG_TIMING | args.wflag)
         V.vie_set_options(ctx, popt)
         ps = []
         V.vie_solve(ctx, [chans[0]], [1] + [0] * (nb - 1))  # warm
@@ -1062,10 +1069,12 @@ def main():
         "dtype": "f32 FFT product / f64 Krylov",
         "data": "synthetic",
         "config": {"workload": (f"W128: {nb} held-out PB-phase fin-metasurface bodies (seed 55) on "
-                                f"{N[0]}x{N[1]}x{N[2]} voxels, h=lambda/32, FFT {P[0]}x{P[1]}x{P[2]}, "
+                                f"{N0[0]}x{N0[1]}x{N0[2]} voxels (computed on the {N[0]}x{N[1]}x{N[2]} "
+                                f"z window that holds the bodies), h=lambda/32, FFT {P[0]}x{P[1]}x{P[2]}, "
                                 f"{nch} channels each, true rel. residual <= {args.tol:g}, far field "
                                 f"on a 181-point detector scan, circular g2 scan + 200-delay Nc"),
-                   "bodies": nb, "channels_per_body": nch, "grid": list(N), "fft": list(P),
+                   "bodies": nb, "channels_per_body": nch, "grid": list(N0), "window": list(N),
+                   "fft": list(P),
                    "tol": args.tol, "precision": "mixed (FP32 product, FP64 refinement)",
                    "solver": ({"method": "FGMRES, block-Jacobi right preconditioner",
                                "restart": args.restart, "blocks": list(blocks),
@@ -1074,7 +1083,7 @@ def main():
                                "blocks_per_body": geom["blocks_per_body"]}
                               if use_fgmres else {"method": "BiCGSTAB with FP64 refinement",
                                                   "inner_tol": args.inner_tol}),
-                   "warm_start": False},
+                   "z_window": not args.no_window, "warm_start": False},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS,
                      "traffic": (mt or {}).get("bytes_per_launch"),

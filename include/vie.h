@@ -75,9 +75,12 @@ enum {
   VIE_FLAG_NO_GRAPH = 2, /* launch every BiCGSTAB iteration eagerly instead of    */
                          /* replaying a captured hipGraph of VIE_GRAPH_ITERS       */
                          /* iterations (results are identical either way)          */
-  VIE_FLAG_CUBE_SELF = 4 /* self term of the exact cube cell instead of the        */
-                         /* equal-volume sphere (see below); read by vie_setup,    */
-                         /* vie_set_options may not change it                      */
+  VIE_FLAG_CUBE_SELF = 4, /* self term of the exact cube cell instead of the       */
+                          /* equal-volume sphere (see below); read by vie_setup,   */
+                          /* vie_set_options may not change it                     */
+  VIE_FLAG_Z_WINDOW = 8   /* compute each grid group on the window of z layers     */
+                          /* that holds its bodies (see vie_grid); read by         */
+                          /* vie_setup, vie_set_options may not change it          */
 };
 enum { VIE_GRAPH_ITERS = 8 };
 
@@ -201,6 +204,19 @@ int vie_farfield(vie_ctx *ctx, int32_t body, const double *theta, const double *
  * g2, Nc_raw, Nc_norm may each be NULL. */
 int hom_g2(const vie_c64 T[4], const double *omega, double sigma, const double *dtau,
            int32_t ndelay, int32_t norm, double *g2, double *Nc_raw, double *Nc_norm);
+
+/* The grid a body is computed on.  With VIE_FLAG_Z_WINDOW a group of bodies
+ * sharing (n, h) computes on a window of z layers of their grid: the layers
+ * holding any of its bodies' voxels plus a 4-layer margin, clipped.  Voxels
+ * outside have chi = 0, so the system for the body's unknowns (and every
+ * solve, current and far field) is that of the full grid.  Box vectors at the
+ * ABI (vie_matvec, vie_get_current) stay in the body's grid; vie_matvec then
+ * applies the operator to x restricted to the window and passes the
+ * components outside it through (y = x there).  Without the flag the window
+ * is the whole grid.  grid[3] = window voxels (N1, N2, N3w), fft[3] =
+ * circulant lengths, offset[3] = (0, 0, first z layer of the window in the
+ * body's grid).  Any pointer may be NULL. */
+int vie_grid(vie_ctx *ctx, int32_t body, int32_t *grid, int32_t *fft, int32_t *offset);
 
 /* Diagonal coefficient s of the discrete operator for voxel edge h (host
  * arithmetic): kind 0 = the default equal-volume-sphere term, kind 1 = the

@@ -67,12 +67,15 @@ struct BodyRec {
   int group;       // group index
   int slot;        // body index inside the group
   int nb;          // body voxels (chi != 0)
-  double origin[3];
+  int zoff = 0;    // first z layer of the body's grid inside the group's compute window
+  double origin[3];  // centre of the compute window's voxel (0, 0, 0)
   int rhs0 = 0, nrhs = 0;  // right-hand sides of this body inside the group (last solve)
 };
 
 struct Group {
-  GroupGeom g;
+  GroupGeom g;     // compute grid: the bodies' grid cut to a window of z layers
+  int N0[3];       // the bodies' grid as given
+  int64_t n0;      // N0[0] N0[1] N0[2]
   double h;
   std::vector<int> bodies;       // body ids
   DevBuf chi;                    // double[nb][n]
@@ -98,6 +101,7 @@ struct Group {
   std::vector<int> fallback, warm_used;  // per rhs
   bool samples_ready = false;            // r = b and v = A b hold for every rhs
   DevBuf bufA, bufB;             // FFT scratch (sized for FP64)
+  DevBuf boxX, boxY;             // compute-window copies of box-layout product vectors
   DevBuf partials;               // c64 [cap][maxblk][2]
   DevBuf state;                  // KState [cap]
   DevBuf flags;                  // int [2][cap]
@@ -409,45 +413,82 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
   };
   if (hipStreamCreate(&ctx->own_stream) != hipSuccess) return bail(VIE_EDEVICE);
   ctx->stream = ctx->own_stream;
-  // group bodies by (n, h)
+  // Group bodies by (n, h).  With VIE_FLAG_Z_WINDOW a group computes on a
+  // window of its grid in z: the layers that hold body voxels of any of its
+  // bodies plus a 4-layer margin (the network box), clipped to the grid.
+  // Voxels outside the window have chi = 0 in every body, so they neither act
+  // on the body nor are acted on: the discrete system for the body's unknowns
+  // is the same, on a shorter circulant.  Each body sits in the window at its
+  // own offset zoff.  Without the flag the window is the whole grid.
   std::map<std::vector<int64_t>, int> key2g;
-  std::vector<std::vector<double>> chi_host;
+  std::vector<int> gi_of(n_bodies), zlo_of(n_bodies), zhi_of(n_bodies);
   for (int b = 0; b < n_bodies; ++b) {
     const vie_body& B = bodies[b];
     int64_t hb;
     memcpy(&hb, &B.h, sizeof(hb));
     std::vector<int64_t> key = {B.n[0], B.n[1], B.n[2], hb};
     auto it = key2g.find(key);
-    int gi;
     if (it == key2g.end()) {
-      gi = (int)ctx->groups.size();
-      key2g[key] = gi;
+      gi_of[b] = (int)ctx->groups.size();
+      key2g[key] = gi_of[b];
       auto G = std::make_unique<Group>();
       G->h = B.h;
-      for (int a = 0; a < 3; ++a) {
-        G->g.N[a] = B.n[a];
-        G->g.P[a] = fft_length(B.n[a]);
-        G->g.Q[a] = G->g.P[a] / 2 + 1;
-      }
-      G->g.n = (int64_t)B.n[0] * B.n[1] * B.n[2];
+      for (int a = 0; a < 3; ++a) G->N0[a] = B.n[a];
+      G->n0 = (int64_t)B.n[0] * B.n[1] * B.n[2];
       G->g.nrhs = 0;
       ctx->groups.push_back(std::move(G));
-      chi_host.emplace_back();
     } else {
-      gi = it->second;
+      gi_of[b] = it->second;
     }
+    const int64_t plane = (int64_t)B.n[0] * B.n[1];
+    int zmin = B.n[2], zmax = -1;
+    for (int64_t i = 0; i < (int64_t)plane * B.n[2]; ++i)
+      if (B.eps_r[i] != 1.0) {
+        const int z = (int)(i / plane);
+        zmin = std::min(zmin, z);
+        zmax = std::max(zmax, z);
+      }
+    if (zmax < 0) zmin = zmax = 0;  // no body voxel: a one-layer window
+    zlo_of[b] = std::max(0, zmin - 4);
+    zhi_of[b] = std::min(B.n[2], zmax + 1 + 4);
+    if (!(opt->flags & VIE_FLAG_Z_WINDOW)) {
+      zlo_of[b] = 0;
+      zhi_of[b] = B.n[2];
+    }
+  }
+  std::vector<int> win(ctx->groups.size(), 1);
+  for (int b = 0; b < n_bodies; ++b)
+    win[gi_of[b]] = std::max(win[gi_of[b]], zhi_of[b] - zlo_of[b]);
+  for (size_t gi = 0; gi < ctx->groups.size(); ++gi) {
+    Group& G = *ctx->groups[gi];
+    G.g.N[0] = G.N0[0];
+    G.g.N[1] = G.N0[1];
+    G.g.N[2] = win[gi];
+    for (int a = 0; a < 3; ++a) {
+      G.g.P[a] = fft_length(G.g.N[a]);
+      G.g.Q[a] = G.g.P[a] / 2 + 1;
+    }
+    G.g.n = (int64_t)G.g.N[0] * G.g.N[1] * G.g.N[2];
+  }
+  std::vector<std::vector<double>> chi_host(ctx->groups.size());
+  for (int b = 0; b < n_bodies; ++b) {
+    const vie_body& B = bodies[b];
+    const int gi = gi_of[b];
     Group& G = *ctx->groups[gi];
     auto rec = std::make_unique<BodyRec>();
     rec->group = gi;
     rec->slot = (int)G.bodies.size();
+    rec->zoff = std::max(0, std::min(zlo_of[b], G.N0[2] - G.g.N[2]));
     for (int a = 0; a < 3; ++a) rec->origin[a] = B.origin[a];
+    rec->origin[2] += B.h * rec->zoff;
     G.bodies.push_back(b);
     std::vector<double>& ch = chi_host[gi];
     const int64_t n = G.g.n;
+    const int64_t shift = (int64_t)G.g.N[0] * G.g.N[1] * rec->zoff;
     std::vector<int> vox;
     ch.resize((size_t)(rec->slot + 1) * n);
     for (int64_t i = 0; i < n; ++i) {
-      const double c = B.eps_r[i] - 1.0;
+      const double c = B.eps_r[i + shift] - 1.0;
       ch[(size_t)rec->slot * n + i] = c;
       if (c != 0.0) vox.push_back((int)i);
     }
@@ -457,9 +498,10 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
     G.max_nb = std::max(G.max_nb, rec->nb);
     G.vox_host.insert(G.vox_host.end(), vox.begin(), vox.end());
     {  // network box: bounding box of the body voxels, 4-voxel halo, clipped
-      int lo[3] = {B.n[0], B.n[1], B.n[2]}, hi[3] = {0, 0, 0};
+      const int* N = G.g.N;
+      int lo[3] = {N[0], N[1], N[2]}, hi[3] = {0, 0, 0};
       for (int v : vox) {
-        const int c[3] = {v % B.n[0], (v / B.n[0]) % B.n[1], v / (B.n[0] * B.n[1])};
+        const int c[3] = {v % N[0], (v / N[0]) % N[1], v / (N[0] * N[1])};
         for (int a = 0; a < 3; ++a) {
           lo[a] = std::min(lo[a], c[a]);
           hi[a] = std::max(hi[a], c[a] + 1);
@@ -471,7 +513,7 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
           hi[a] = 1;
         }
         lo[a] = std::max(0, lo[a] - 4);
-        hi[a] = std::min(B.n[a], hi[a] + 4);
+        hi[a] = std::min(N[a], hi[a] + 4);
         G.box_lo.push_back(lo[a]);
         G.box_d.push_back(hi[a] - lo[a]);
       }
@@ -567,7 +609,8 @@ extern "C" int vie_set_options(vie_ctx* ctx, const vie_options* opt) {
   if (!ctx) return VIE_EINVAL;
   if (ctx->poisoned) return VIE_ESTATE;
   if (!valid_options(opt) || opt->k0 != ctx->opt.k0) return VIE_EINVAL;
-  if ((opt->flags ^ ctx->opt.flags) & VIE_FLAG_CUBE_SELF) return VIE_EINVAL;  // fixed at setup
+  if ((opt->flags ^ ctx->opt.flags) & (VIE_FLAG_CUBE_SELF | VIE_FLAG_Z_WINDOW))
+    return VIE_EINVAL;  // fixed at setup
   ctx->opt = *opt;
   return VIE_OK;
 }
@@ -1836,11 +1879,38 @@ extern "C" int vie_matvec_dev(vie_ctx* ctx, int32_t body, int32_t precision, con
   std::vector<int> rb(nvec, B.slot);
   VIE_HIP(hipMemcpyAsync(G.rhs_body.p, rb.data(), nvec * sizeof(int), hipMemcpyHostToDevice,
                          ctx->stream));
+  // Box vectors come in the bodies' grid; the product runs on the compute
+  // window.  Outside the window chi = 0, so there y = x.
+  const bool window = G.g.n != G.n0;
+  const c64* xs = (const c64*)x;
+  c64* ys = (c64*)y;
+  if (window) {
+    const size_t wb = (size_t)nvec * 3 * G.g.n * sizeof(c64);
+    hipError_t re = G.boxX.reserve(wb);
+    if (re == hipSuccess) re = G.boxY.reserve(wb);
+    if (re != hipSuccess) {
+      G.g.nrhs = saved;
+      VIE_HIP(re);
+    }
+    const int64_t shift = (int64_t)G.g.N[0] * G.g.N[1] * B.zoff;
+    for (int64_t r = 0; r < (int64_t)nvec * 3; ++r)  // the window of every component
+      VIE_HIP(hipMemcpyAsync(G.boxX.as<c64>() + r * G.g.n, (const c64*)x + r * G.n0 + shift,
+                             G.g.n * sizeof(c64), hipMemcpyDeviceToDevice, ctx->stream));
+    xs = G.boxX.as<c64>();
+    ys = G.boxY.as<c64>();
+  }
   EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
-  hipError_t err = run_matvec(ctx, G, precision == VIE_MIXED ? 1 : 0, (const c64*)x, (c64*)y, e,
-                              nullptr, false);
+  hipError_t err = run_matvec(ctx, G, precision == VIE_MIXED ? 1 : 0, xs, ys, e, nullptr, false);
   G.g.nrhs = saved;
   VIE_HIP(err);
+  if (window) {
+    const int64_t shift = (int64_t)G.g.N[0] * G.g.N[1] * B.zoff;
+    VIE_HIP(hipMemcpyAsync(y, x, (size_t)nvec * 3 * G.n0 * sizeof(c64), hipMemcpyDeviceToDevice,
+                           ctx->stream));
+    for (int64_t r = 0; r < (int64_t)nvec * 3; ++r)
+      VIE_HIP(hipMemcpyAsync((c64*)y + r * G.n0 + shift, G.boxY.as<c64>() + r * G.g.n,
+                             G.g.n * sizeof(c64), hipMemcpyDeviceToDevice, ctx->stream));
+  }
   return VIE_OK;
 }
 
@@ -1850,7 +1920,7 @@ extern "C" int vie_matvec(vie_ctx* ctx, int32_t body, int32_t precision, const v
   if (ctx->poisoned) return VIE_ESTATE;
   if (body < 0 || body >= (int)ctx->bodies.size() || nvec < 1 || !x || !y) return VIE_EINVAL;
   Group& G = *ctx->groups[ctx->bodies[body]->group];
-  const size_t bytes = (size_t)nvec * 3 * G.g.n * sizeof(c64);
+  const size_t bytes = (size_t)nvec * 3 * G.n0 * sizeof(c64);
   DevBuf dx, dy;
   VIE_HIP(dx.reserve(bytes));
   VIE_HIP(dy.reserve(bytes));
@@ -1870,19 +1940,20 @@ extern "C" int vie_get_current(vie_ctx* ctx, int32_t body, int32_t rhs, vie_c64*
   BodyRec& B = *ctx->bodies[body];
   if (rhs < 0 || rhs >= B.nrhs) return VIE_EINVAL;
   Group& G = *ctx->groups[B.group];
-  const int64_t n = G.g.n;
+  const int64_t n0 = G.n0;
+  const int64_t shift = (int64_t)G.g.N[0] * G.g.N[1] * B.zoff;  // window -> body grid
   std::vector<c64> c((size_t)3 * B.nb);
   if (B.nb > 0) {
     VIE_HIP(hipMemcpyAsync(c.data(), G.x.as<c64>() + G.roff_host[B.rhs0 + rhs],
                            c.size() * sizeof(c64), hipMemcpyDeviceToHost, ctx->stream));
     VIE_HIP(hipStreamSynchronize(ctx->stream));
   }
-  memset(w, 0, (size_t)3 * n * sizeof(vie_c64));
+  memset(w, 0, (size_t)3 * n0 * sizeof(vie_c64));
   const int* vx = G.vox_host.data() + G.voff_host[B.slot];
   for (int comp = 0; comp < 3; ++comp)
     for (int k = 0; k < B.nb; ++k) {
-      w[comp * n + vx[k]].re = c[(size_t)comp * B.nb + k].re;
-      w[comp * n + vx[k]].im = c[(size_t)comp * B.nb + k].im;
+      w[comp * n0 + shift + vx[k]].re = c[(size_t)comp * B.nb + k].re;
+      w[comp * n0 + shift + vx[k]].im = c[(size_t)comp * B.nb + k].im;
     }
   return VIE_OK;
 }
@@ -2094,6 +2165,20 @@ extern "C" int hom_g2(const vie_c64 T[4], const double* omega, double sigma, con
 
 // Classical fourth-order correlation (eq. 27) of the coherent superposition
 // of the two channels' responses: |T_a1 + T_a2|^2 |T_b1 + T_b2|^2.
+extern "C" int vie_grid(vie_ctx* ctx, int32_t body, int32_t* grid, int32_t* fft,
+                        int32_t* offset) {
+  if (!ctx) return VIE_EINVAL;
+  if (body < 0 || body >= (int)ctx->bodies.size()) return VIE_EINVAL;
+  const BodyRec& B = *ctx->bodies[body];
+  const Group& G = *ctx->groups[B.group];
+  for (int a = 0; a < 3; ++a) {
+    if (grid) grid[a] = G.g.N[a];
+    if (fft) fft[a] = G.g.P[a];
+    if (offset) offset[a] = a == 2 ? B.zoff : 0;
+  }
+  return VIE_OK;
+}
+
 extern "C" int vie_self_term(int32_t kind, double k0, double h, vie_c64* s) {
   if (!s || !(k0 > 0) || !(h > 0) || !isfinite(k0) || !isfinite(h)) return VIE_EINVAL;
   double re, im;

@@ -21,6 +21,7 @@ VIE_NORM_R1, VIE_NORM_R2 = 0, 1
 VIE_FLAG_TIMING = 1
 VIE_FLAG_NO_GRAPH = 2
 VIE_FLAG_CUBE_SELF = 4
+VIE_FLAG_Z_WINDOW = 8
 
 
 class vie_c64(C.Structure):
@@ -86,6 +87,8 @@ def lib():
                                        C.c_int32, P(vie_c64)]),
             "hom_classical_p2": (C.c_int, [P(vie_c64), P(C.c_double)]),
             "vie_self_term": (C.c_int, [C.c_int32, C.c_double, C.c_double, P(vie_c64)]),
+            "vie_grid": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32), P(C.c_int32),
+                                   P(C.c_int32)]),
             "vie_transfer_na": (C.c_int, [C.c_void_p, C.c_int32, P(vie_na_detector), C.c_int32,
                                           C.c_int32, C.c_int32, P(vie_c64)]),
             "hom_g2": (C.c_int, [P(vie_c64), P(C.c_double), C.c_double, P(C.c_double), C.c_int32,
@@ -224,6 +227,13 @@ def vie_farfield(ctx, body, theta, phi, nrhs):
     F = np.zeros((nrhs, len(th), 2), dtype=np.complex128)
     _check(lib().vie_farfield(ctx, int(body), _dptr(th), _dptr(ph), len(th), _cptr(F)), "vie_farfield")
     return F
+
+
+def vie_grid(ctx, body):
+    """(window grid, FFT lengths, window offset in the body's grid) of a body."""
+    g, f, o = (C.c_int32 * 3)(), (C.c_int32 * 3)(), (C.c_int32 * 3)()
+    _check(lib().vie_grid(ctx, int(body), g, f, o), "vie_grid")
+    return tuple(g), tuple(f), tuple(o)
 
 
 def vie_self_term(kind, k0, h):
