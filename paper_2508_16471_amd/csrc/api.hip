@@ -139,6 +139,12 @@ struct TimedEvent {
 struct ArnoldiBufs {
   DevBuf V, Z, w, H1, H2, NR, dpart, npart, off, len, act, nvs, coef;
   DevBuf W2, act2;  // ||w||^2 before orthogonalisation, reorthogonalisation flags
+  DevBuf wide;      // FP64 copy of an FP32 basis vector (product input)
+  int v32 = 0;      // V and Z stored in FP32 (mixed precision) instead of FP64
+  // address of vector j of a multi-vector with `stride` elements per vector
+  void* at(const DevBuf& b, int64_t j, int64_t stride) const {
+    return (char*)b.p + (size_t)j * stride * (v32 ? sizeof(c32) : sizeof(c64));
+  }
 };
 
 // Block-Jacobi preconditioner of one group: every body split into bx x by
@@ -1243,6 +1249,7 @@ static int arnoldi_alloc(vie_ctx* ctx, ArnoldiBufs& A, int nseg, int maxlen, int
   VIE_HIP(A.coef.reserve((size_t)nseg * (m + 1) * sizeof(c64)));
   VIE_HIP(A.W2.reserve((size_t)nseg * sizeof(double)));
   VIE_HIP(A.act2.reserve((size_t)nseg * sizeof(int)));
+  VIE_HIP(A.wide.reserve(vb));
   return VIE_OK;
 }
 
@@ -1264,7 +1271,8 @@ static int arnoldi_tables(vie_ctx* ctx, ArnoldiBufs& A, const std::vector<int64_
 // pass); ||w||^2 into NR[s][j+1], V_{j+1} = w / ||w||.
 static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, int64_t stride,
                                int m, int j, double eta2) {
-  c64* V = A.V.as<c64>();
+  const void* V = A.V.p;
+  const int v32 = A.v32;
   c64* w = A.w.as<c64>();
   const int ldh = m + 1;
   c64* h1 = A.H1.as<c64>() + (size_t)j * S.nseg * (m + 1);
@@ -1274,25 +1282,25 @@ static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, in
   SegSet S2 = S;
   S2.active = A.act2.as<int>();
   hipError_t e;
-  if (eta2 > 0 && (e = launch_seg_maxpy(S, nullptr, 0, 0, nullptr, nullptr, 0, w, npart,
+  if (eta2 > 0 && (e = launch_seg_maxpy(S, nullptr, 0, 0, 0, nullptr, nullptr, 0, w, npart,
                                          A.W2.as<double>(), 1, ctx->stream)) != hipSuccess)
     return e;
-  if ((e = launch_seg_mdot(S, V, stride, j + 1, w, A.dpart.as<c64>(), h1, ldh, ctx->stream)) !=
-      hipSuccess)
+  if ((e = launch_seg_mdot(S, V, v32, stride, j + 1, w, A.dpart.as<c64>(), h1, ldh,
+                           ctx->stream)) != hipSuccess)
     return e;
-  if ((e = launch_seg_maxpy(S, V, stride, j + 1, nullptr, h1, ldh, w, npart, nr, m + 1,
+  if ((e = launch_seg_maxpy(S, V, v32, stride, j + 1, nullptr, h1, ldh, w, npart, nr, m + 1,
                             ctx->stream)) != hipSuccess)
     return e;
   if ((e = launch_seg_reorth_flags(S, A.W2.as<double>(), nr, m + 1, eta2, A.act2.as<int>(),
                                    ctx->stream)) != hipSuccess)
     return e;
-  if ((e = launch_seg_mdot(S2, V, stride, j + 1, w, A.dpart.as<c64>(), h2, ldh, ctx->stream)) !=
-      hipSuccess)
+  if ((e = launch_seg_mdot(S2, V, v32, stride, j + 1, w, A.dpart.as<c64>(), h2, ldh,
+                           ctx->stream)) != hipSuccess)
     return e;
-  if ((e = launch_seg_maxpy(S2, V, stride, j + 1, nullptr, h2, ldh, w, npart, nr, m + 1,
+  if ((e = launch_seg_maxpy(S2, V, v32, stride, j + 1, nullptr, h2, ldh, w, npart, nr, m + 1,
                             ctx->stream)) != hipSuccess)
     return e;
-  return launch_seg_normalize(S, w, nr, m + 1, V + (size_t)(j + 1) * stride, ctx->stream);
+  return launch_seg_normalize(S, w, nr, m + 1, A.at(A.V, j + 1, stride), v32, ctx->stream);
 }
 
 // Block partition of every body of group G into bx x by lateral blocks:
@@ -1492,11 +1500,12 @@ static int bj_bind(vie_ctx* ctx, Group& G, BlockPrec& P, const std::vector<int>&
 
 // z = M^{-1} v for the bound right-hand sides (v, z device vectors at the
 // bound offsets); right-hand sides with act[q] == 0 get z = 0.
-static int bj_apply(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo, const c64* v,
-                    c64* z, const std::vector<int>& act) {
+static int bj_apply(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo, const void* v,
+                    void* z, int vz32, const std::vector<int>& act) {
   const int nrhs = (int)P.bound_rb.size();
   if (P.nseg == 0) {
-    VIE_HIP(hipMemsetAsync(z, 0, (size_t)std::max<int64_t>(P.tot, 0) * sizeof(c64), ctx->stream));
+    VIE_HIP(hipMemsetAsync(z, 0, (size_t)std::max<int64_t>(P.tot, 0) * (vz32 ? sizeof(c32) : sizeof(c64)),
+                           ctx->stream));
     return VIE_OK;
   }
   vie_ctx* sub = P.sub;
@@ -1515,18 +1524,24 @@ static int bj_apply(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo, co
   for (int s = 0; s < nseg; ++s) act_s[s] = act[P.seg_rhs[s]] ? 1 : 0;
   VIE_HIP(hipMemcpyAsync(A.act.p, act_s.data(), nseg * sizeof(int), hipMemcpyHostToDevice,
                          ctx->stream));
+  // with FP32 block products the block basis is stored in FP32 too
+  A.v32 = ip;
   c64* R = P.R.as<c64>();
-  c64* V = A.V.as<c64>();
   double* NR = A.NR.as<double>();
   const int ldn = k + 1;
   VIE_HIP(launch_permute(nrhs, P.qoff.as<int64_t>(), P.qpoff.as<int64_t>(), P.qlen.as<int>(),
-                         P.maxqlen, P.perm.as<int>(), v, R, 0, ctx->stream));
-  VIE_HIP(launch_seg_maxpy(S, nullptr, 0, 0, nullptr, nullptr, 0, R, A.npart.as<double>(), NR,
+                         P.maxqlen, P.perm.as<int>(), v, vz32, R, 0, 0, ctx->stream));
+  VIE_HIP(launch_seg_maxpy(S, nullptr, 0, 0, 0, nullptr, nullptr, 0, R, A.npart.as<double>(), NR,
                            ldn, ctx->stream));
-  VIE_HIP(launch_seg_normalize(S, R, NR, ldn, V, ctx->stream));
+  VIE_HIP(launch_seg_normalize(S, R, NR, ldn, A.V.p, A.v32, ctx->stream));
   for (int j = 0; j < k; ++j) {
     EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
-    VIE_HIP(run_matvec(sub, Gp, ip, V + (size_t)j * tot, A.w.as<c64>(), e, A.act.as<int>()));
+    const c64* in = (const c64*)A.at(A.V, j, tot);
+    if (A.v32) {  // the product takes FP64 vectors
+      VIE_HIP(launch_seg_widen(S, A.at(A.V, j, tot), 1, A.wide.as<c64>(), ctx->stream));
+      in = A.wide.as<c64>();
+    }
+    VIE_HIP(run_matvec(sub, Gp, ip, in, A.w.as<c64>(), e, A.act.as<int>()));
     // the block solves are approximations: with FP32 block products one
     // Gram-Schmidt pass is enough
     const double eta2 = ip ? 0.0 : 0.5;
@@ -1568,10 +1583,10 @@ static int bj_apply(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo, co
   VIE_HIP(hipMemcpyAsync(A.nvs.p, nvs.data(), nseg * sizeof(int), hipMemcpyHostToDevice,
                          ctx->stream));
   VIE_HIP(hipMemsetAsync(P.X.p, 0, (size_t)tot * sizeof(c64), ctx->stream));
-  VIE_HIP(launch_seg_maxpy(S, V, tot, maxst, A.nvs.as<int>(), A.coef.as<c64>(), ldn,
+  VIE_HIP(launch_seg_maxpy(S, A.V.p, A.v32, tot, maxst, A.nvs.as<int>(), A.coef.as<c64>(), ldn,
                            P.X.as<c64>(), nullptr, nullptr, 0, ctx->stream));
   VIE_HIP(launch_permute(nrhs, P.qoff.as<int64_t>(), P.qpoff.as<int64_t>(), P.qlen.as<int>(),
-                         P.maxqlen, P.perm.as<int>(), P.X.as<c64>(), z, 1, ctx->stream));
+                         P.maxqlen, P.perm.as<int>(), P.X.as<c64>(), 0, z, vz32, 1, ctx->stream));
   // the host tables must outlive the copies
   VIE_HIP(hipStreamSynchronize(ctx->stream));
   return VIE_OK;
@@ -1633,8 +1648,10 @@ static int fgmres_group(vie_ctx* ctx, Group& G, BlockPrec* P, const vie_fgmres_o
   steps.assign(nrhs, 0);
   cycles.assign(nrhs, 0);
   const int maxit = ctx->opt.max_iter;
-  c64* V = A.V.as<c64>();
-  c64* Z = flex ? A.Z.as<c64>() : V;
+  // mixed precision: the basis V and the preconditioned vectors Z are stored in
+  // FP32 (their products are FP32 anyway); dots, updates and x stay FP64
+  A.v32 = prec;
+  const DevBuf& Zb = flex ? A.Z : A.V;
   double* NR = A.NR.as<double>();
   // FP32 Arnoldi products perturb the Arnoldi relation at about 1e-7, so in the
   // mixed path one Gram-Schmidt pass is enough; the FP64 true residual at the
@@ -1654,9 +1671,9 @@ static int fgmres_group(vie_ctx* ctx, Group& G, BlockPrec* P, const vie_fgmres_o
     if (!any) break;
     VIE_HIP(hipMemcpyAsync(A.act.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
                            ctx->stream));
-    VIE_HIP(launch_seg_maxpy(S, nullptr, 0, 0, nullptr, nullptr, 0, r, A.npart.as<double>(), NR,
+    VIE_HIP(launch_seg_maxpy(S, nullptr, 0, 0, 0, nullptr, nullptr, 0, r, A.npart.as<double>(), NR,
                              m + 1, ctx->stream));
-    VIE_HIP(launch_seg_normalize(S, r, NR, m + 1, V, ctx->stream));
+    VIE_HIP(launch_seg_normalize(S, r, NR, m + 1, A.V.p, A.v32, ctx->stream));
     for (int q = 0; q < nrhs; ++q) {
       nst[q] = 0;
       if (!act[q]) continue;
@@ -1664,14 +1681,19 @@ static int fgmres_group(vie_ctx* ctx, Group& G, BlockPrec* P, const vie_fgmres_o
       mc[q] = std::min(m, maxit - steps[q]);
     }
     for (int j = 0; j < m; ++j) {
-      c64* vj = V + (size_t)j * tot;
-      c64* zj = Z + (size_t)j * tot;
+      void* vj = A.at(A.V, j, tot);
+      void* zj = A.at(Zb, j, tot);
       if (flex) {
-        rc = bj_apply(ctx, *P, fo, vj, zj, act);
+        rc = bj_apply(ctx, *P, fo, vj, zj, A.v32, act);
         if (rc != VIE_OK) return rc;
       }
       EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
-      VIE_HIP(run_matvec(ctx, G, prec, zj, A.w.as<c64>(), e, A.act.as<int>()));
+      const c64* in = (const c64*)zj;
+      if (A.v32) {  // the product takes FP64 vectors
+        VIE_HIP(launch_seg_widen(S, zj, 1, A.wide.as<c64>(), ctx->stream));
+        in = A.wide.as<c64>();
+      }
+      VIE_HIP(run_matvec(ctx, G, prec, in, A.w.as<c64>(), e, A.act.as<int>()));
       VIE_HIP(timed(ctx, kArnoldiKind, [&] { return arnoldi_orth(ctx, A, S, tot, m, j, eta2); }));
       VIE_HIP(hipMemcpyAsync(h1.data(), A.H1.as<c64>() + (size_t)j * nrhs * (m + 1),
                              h1.size() * sizeof(c64), hipMemcpyDeviceToHost, ctx->stream));
@@ -1720,7 +1742,7 @@ static int fgmres_group(vie_ctx* ctx, Group& G, BlockPrec* P, const vie_fgmres_o
                            ctx->stream));
     VIE_HIP(hipMemcpyAsync(A.coef.p, coef.data(), coef.size() * sizeof(c64), hipMemcpyHostToDevice,
                            ctx->stream));
-    VIE_HIP(launch_seg_maxpy(S, Z, tot, maxst, A.nvs.as<int>(), A.coef.as<c64>(), m + 1, x,
+    VIE_HIP(launch_seg_maxpy(S, Zb.p, A.v32, tot, maxst, A.nvs.as<int>(), A.coef.as<c64>(), m + 1, x,
                              nullptr, nullptr, 0, ctx->stream));
     // true residual with the FP64 product
     EpiArgs e{EPI_RESID, rh, part, 0, pol, ph};
@@ -1845,7 +1867,7 @@ extern "C" int vie_precond_apply(vie_ctx* ctx, const vie_fgmres_options* fo, con
   VIE_HIP(dz.reserve(hv.size() * sizeof(c64)));
   VIE_HIP(hipMemcpyAsync(dv.p, hv.data(), hv.size() * sizeof(c64), hipMemcpyHostToDevice,
                          ctx->stream));
-  rc = bj_apply(ctx, P, fo, dv.as<c64>(), dz.as<c64>(), std::vector<int>(nvec, 1));
+  rc = bj_apply(ctx, P, fo, dv.p, dz.p, 0, std::vector<int>(nvec, 1));
   if (rc != VIE_OK) return rc;
   VIE_HIP(hipMemcpyAsync(hz.data(), dz.p, hz.size() * sizeof(c64), hipMemcpyDeviceToHost,
                          ctx->stream));

@@ -25,16 +25,19 @@ struct SegSet {
 
 int seg_blocks(int64_t max_len);
 
+// Multi-vectors V may be stored in FP64 (v32 = 0: c64) or FP32 (v32 = 1:
+// c32); arithmetic and the vectors w, x are FP64 either way.
+
 // out[s * ldo + i] = sum_e conj(V_i[e]) w[e] over segment s, for i < nv
 // (zero for skipped segments).  partials: nseg * nv * nblk c64.
-hipError_t launch_seg_mdot(const SegSet& S, const c64* V, int64_t stride, int nv, const c64* w,
-                           c64* partials, c64* out, int ldo, hipStream_t st);
+hipError_t launch_seg_mdot(const SegSet& S, const void* V, int v32, int64_t stride, int nv,
+                           const c64* w, c64* partials, c64* out, int ldo, hipStream_t st);
 
 // w[e] -= sum_{i < n_s} coef[s * ldc + i] V_i[e] with n_s = nv, or
 // min(nv, nv_seg[s]) when nv_seg is given.  With norm2 != nullptr also
 // norm2[s * ldn] = ||w_s||^2 after the update (partials: nseg * nblk doubles).
 // nv = 0 only measures the norm.
-hipError_t launch_seg_maxpy(const SegSet& S, const c64* V, int64_t stride, int nv,
+hipError_t launch_seg_maxpy(const SegSet& S, const void* V, int v32, int64_t stride, int nv,
                             const int* nv_seg, const c64* coef, int ldc, c64* w,
                             double* partials, double* norm2, int ldn, hipStream_t st);
 
@@ -43,16 +46,21 @@ hipError_t launch_seg_maxpy(const SegSet& S, const c64* V, int64_t stride, int n
 hipError_t launch_seg_reorth_flags(const SegSet& S, const double* before, const double* after,
                                   int ldn, double eta2, int* act2, hipStream_t st);
 
-// dst = src / sqrt(norm2[s * ldn]) per segment (zero where norm2 is 0).
+// dst = src / sqrt(norm2[s * ldn]) per segment (zero where norm2 is 0),
+// stored in FP32 when d32.
 hipError_t launch_seg_normalize(const SegSet& S, const c64* src, const double* norm2, int ldn,
-                                c64* dst, hipStream_t st);
+                                void* dst, int d32, hipStream_t st);
+
+// dst = src (FP32 when s32) as FP64, per active segment.
+hipError_t launch_seg_widen(const SegSet& S, const void* src, int s32, c64* dst, hipStream_t st);
 
 // Permutation of each of nrep vectors (vector q: qlen[q] elements at qoff[q],
 // its permutation at perm + qpoff[q]; maxlen >= every qlen):
 //   gather  (scatter == 0): dst[qoff + j] = src[qoff + perm[j]]
 //   scatter (scatter != 0): dst[qoff + perm[j]] = src[qoff + j]
+// src is FP32 when s32, dst when d32.
 hipError_t launch_permute(int nrep, const int64_t* qoff, const int64_t* qpoff, const int* qlen,
-                          int maxlen, const int* perm, const c64* src, c64* dst, int scatter,
-                          hipStream_t st);
+                          int maxlen, const int* perm, const void* src, int s32, void* dst,
+                          int d32, int scatter, hipStream_t st);
 
 }  // namespace vie

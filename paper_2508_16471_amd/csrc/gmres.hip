@@ -20,7 +20,13 @@ __device__ __forceinline__ c64 shfl_xor_c(c64 v, int m) {
   return mk(__shfl_xor(v.re, m), __shfl_xor(v.im, m));
 }
 
-__global__ __launch_bounds__(GT) void k_seg_mdot(SegSet S, const c64* __restrict__ V,
+__device__ __forceinline__ c64 ld64(const c64* p) { return *p; }
+__device__ __forceinline__ c64 ld64(const c32* p) { return cvt<double>(*p); }
+__device__ __forceinline__ void st(c64* p, c64 v) { *p = v; }
+__device__ __forceinline__ void st(c32* p, c64 v) { *p = cvt<float>(v); }
+
+template <typename TV>
+__global__ __launch_bounds__(GT) void k_seg_mdot(SegSet S, const TV* __restrict__ V,
                                                  int64_t stride, int nv,
                                                  const c64* __restrict__ w,
                                                  c64* __restrict__ partials) {
@@ -38,7 +44,7 @@ __global__ __launch_bounds__(GT) void k_seg_mdot(SegSet S, const c64* __restrict
       const c64 we = w[off + e];
 #pragma unroll
       for (int u = 0; u < GU; ++u)
-        if (i0 + u < nv) acc[u] = acc[u] + cmulc(V[(int64_t)(i0 + u) * stride + off + e], we);
+        if (i0 + u < nv) acc[u] = acc[u] + cmulc(ld64(V + (int64_t)(i0 + u) * stride + off + e), we);
     }
 #pragma unroll
     for (int u = 0; u < GU; ++u)
@@ -71,7 +77,8 @@ __global__ __launch_bounds__(64) void k_seg_sum_c(SegSet S, int nv,
   if (threadIdx.x == 0) out[(int64_t)s * ldo + i] = t;
 }
 
-__global__ __launch_bounds__(GT) void k_seg_maxpy(SegSet S, const c64* __restrict__ V,
+template <typename TV>
+__global__ __launch_bounds__(GT) void k_seg_maxpy(SegSet S, const TV* __restrict__ V,
                                                   int64_t stride, int nv,
                                                   const int* __restrict__ nv_seg,
                                                   const c64* __restrict__ coef, int ldc,
@@ -90,7 +97,7 @@ __global__ __launch_bounds__(GT) void k_seg_maxpy(SegSet S, const c64* __restric
   double nr = 0.0;
   for (int e = blk * GT + threadIdx.x; e < len; e += S.nblk * GT) {
     c64 a = w[off + e];
-    for (int i = 0; i < n; ++i) a = a - cf[i] * V[(int64_t)i * stride + off + e];
+    for (int i = 0; i < n; ++i) a = a - cf[i] * ld64(V + (int64_t)i * stride + off + e);
     if (n > 0) w[off + e] = a;
     nr += a.re * a.re + a.im * a.im;
   }
@@ -124,25 +131,36 @@ __global__ void k_seg_reorth_flags(SegSet S, const double* __restrict__ before,
   act2[s] = (on && eta2 > 0.0 && after[(int64_t)s * ldn] < eta2 * before[s]) ? 1 : 0;
 }
 
+template <typename TD>
 __global__ __launch_bounds__(GT) void k_seg_normalize(SegSet S, const c64* __restrict__ src,
                                                       const double* __restrict__ norm2, int ldn,
-                                                      c64* __restrict__ dst) {
+                                                      TD* __restrict__ dst) {
   const int s = blockIdx.y, blk = blockIdx.x;
   if (S.active && !S.active[s]) return;
   const int64_t off = S.off[s];
   const int len = S.len[s];
   const double n2 = norm2[(int64_t)s * ldn];
   const double sc = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
-  for (int e = blk * GT + threadIdx.x; e < len; e += S.nblk * GT)
-    dst[off + e] = sc * src[off + e];
+  for (int e = blk * GT + threadIdx.x; e < len; e += S.nblk * GT) st(dst + off + e, sc * src[off + e]);
 }
 
+template <typename TS>
+__global__ __launch_bounds__(GT) void k_seg_widen(SegSet S, const TS* __restrict__ src,
+                                                  c64* __restrict__ dst) {
+  const int s = blockIdx.y, blk = blockIdx.x;
+  if (S.active && !S.active[s]) return;
+  const int64_t off = S.off[s];
+  const int len = S.len[s];
+  for (int e = blk * GT + threadIdx.x; e < len; e += S.nblk * GT) dst[off + e] = ld64(src + off + e);
+}
+
+template <typename TS, typename TD>
 __global__ __launch_bounds__(GT) void k_permute(const int64_t* __restrict__ qoff,
                                                 const int64_t* __restrict__ qpoff,
                                                 const int* __restrict__ qlen,
                                                 const int* __restrict__ perm,
-                                                const c64* __restrict__ src,
-                                                c64* __restrict__ dst, int scatter) {
+                                                const TS* __restrict__ src,
+                                                TD* __restrict__ dst, int scatter) {
   const int q = blockIdx.y;
   const int64_t base = qoff[q];
   const int* pm = perm + qpoff[q];
@@ -150,9 +168,9 @@ __global__ __launch_bounds__(GT) void k_permute(const int64_t* __restrict__ qoff
   for (int j = blockIdx.x * GT + threadIdx.x; j < n; j += gridDim.x * GT) {
     const int p = pm[j];
     if (scatter)
-      dst[base + p] = src[base + j];
+      st(dst + base + p, ld64(src + base + j));
     else
-      dst[base + j] = src[base + p];
+      st(dst + base + j, ld64(src + base + p));
   }
 }
 
@@ -163,21 +181,29 @@ int seg_blocks(int64_t max_len) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 256));
 }
 
-hipError_t launch_seg_mdot(const SegSet& S, const c64* V, int64_t stride, int nv, const c64* w,
-                           c64* partials, c64* out, int ldo, hipStream_t st) {
+hipError_t launch_seg_mdot(const SegSet& S, const void* V, int v32, int64_t stride, int nv,
+                           const c64* w, c64* partials, c64* out, int ldo, hipStream_t st) {
   if (S.nseg < 1 || nv < 1) return hipSuccess;
-  k_seg_mdot<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, V, stride, nv, w, partials);
+  if (v32)
+    k_seg_mdot<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c32*)V, stride, nv, w, partials);
+  else
+    k_seg_mdot<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c64*)V, stride, nv, w, partials);
   k_seg_sum_c<<<dim3(nv, S.nseg), 64, 0, st>>>(S, nv, partials, out, ldo);
   return hipGetLastError();
 }
 
-hipError_t launch_seg_maxpy(const SegSet& S, const c64* V, int64_t stride, int nv,
+hipError_t launch_seg_maxpy(const SegSet& S, const void* V, int v32, int64_t stride, int nv,
                             const int* nv_seg, const c64* coef, int ldc, c64* w,
                             double* partials, double* norm2, int ldn, hipStream_t st) {
   if (S.nseg < 1) return hipSuccess;
   if (nv < 0 || nv > kMaxVec) return hipErrorInvalidValue;
-  k_seg_maxpy<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, V, stride, nv, nv_seg, coef, ldc, w,
-                                                   norm2 ? partials : nullptr);
+  double* pn = norm2 ? partials : nullptr;
+  if (v32)
+    k_seg_maxpy<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c32*)V, stride, nv, nv_seg, coef,
+                                                     ldc, w, pn);
+  else
+    k_seg_maxpy<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c64*)V, stride, nv, nv_seg, coef,
+                                                     ldc, w, pn);
   if (norm2) k_seg_sum_r<<<S.nseg, 64, 0, st>>>(S, partials, norm2, ldn);
   return hipGetLastError();
 }
@@ -190,18 +216,37 @@ hipError_t launch_seg_reorth_flags(const SegSet& S, const double* before, const 
 }
 
 hipError_t launch_seg_normalize(const SegSet& S, const c64* src, const double* norm2, int ldn,
-                                c64* dst, hipStream_t st) {
+                                void* dst, int d32, hipStream_t st) {
   if (S.nseg < 1) return hipSuccess;
-  k_seg_normalize<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, src, norm2, ldn, dst);
+  if (d32)
+    k_seg_normalize<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, src, norm2, ldn, (c32*)dst);
+  else
+    k_seg_normalize<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, src, norm2, ldn, (c64*)dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_widen(const SegSet& S, const void* src, int s32, c64* dst, hipStream_t st) {
+  if (S.nseg < 1) return hipSuccess;
+  if (s32)
+    k_seg_widen<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c32*)src, dst);
+  else
+    k_seg_widen<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c64*)src, dst);
   return hipGetLastError();
 }
 
 hipError_t launch_permute(int nrep, const int64_t* qoff, const int64_t* qpoff, const int* qlen,
-                          int maxlen, const int* perm, const c64* src, c64* dst, int scatter,
-                          hipStream_t st) {
+                          int maxlen, const int* perm, const void* src, int s32, void* dst,
+                          int d32, int scatter, hipStream_t st) {
   if (nrep < 1 || maxlen < 1) return hipSuccess;
-  const int gx = std::min((maxlen + GT - 1) / GT, 4096);
-  k_permute<<<dim3(gx, nrep), GT, 0, st>>>(qoff, qpoff, qlen, perm, src, dst, scatter);
+  const dim3 grid(std::min((maxlen + GT - 1) / GT, 4096), nrep);
+  if (s32 && d32)
+    k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c32*)src, (c32*)dst, scatter);
+  else if (s32)
+    k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c32*)src, (c64*)dst, scatter);
+  else if (d32)
+    k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c64*)src, (c32*)dst, scatter);
+  else
+    k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c64*)src, (c64*)dst, scatter);
   return hipGetLastError();
 }
 
