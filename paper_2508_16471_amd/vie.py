@@ -198,7 +198,7 @@ def fgmres_options(restart=30, blocks=(7, 7), inner_iters=4, inner_precision=VIE
 
 
 def vie_solve_fgmres(ctx, channels, nrhs_per_body, fopt, allow_noconv=False):
-    """Preconditioned restarted FGMRES solve of a one-body context; returns
+    """Block-Jacobi preconditioned restarted FGMRES solve of every body; returns
     (status, list of stats dicts) like vie_solve."""
     pw = planewaves(channels)
     nr = (C.c_int32 * len(nrhs_per_body))(*[int(v) for v in nrhs_per_body])
