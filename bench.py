@@ -878,7 +878,8 @@ def precond_mode(args):
                      (30, (4, 4), 4), (30, (4, 4), 8), (30, (2, 2), 2), (30, (2, 2), 4),
                      (30, (2, 2), 8), (60, (2, 2), 8), (20, (2, 2), 8), (40, (2, 2), 8),
                      (30, (2, 2), 16), (30, (1, 1), 4), (60, (2, 2), 6), (60, (2, 2), 10),
-                     (60, (3, 3), 8), (60, (2, 1), 8), (60, (1, 2), 8), (60, (3, 3), 12)):
+                     (60, (3, 3), 8), (60, (2, 1), 8), (60, (1, 2), 8), (60, (3, 3), 12),
+                     (40, (2, 2), 10), (30, (2, 2), 10), (60, (2, 2), 12)):
         configs.append((f"fgmres{m}_bj{bl[0]}x{bl[1]}_k{k}",
                         V.fgmres_options(m, bl, k, V.VIE_MIXED), k, 0))
     configs += [("bicgstab_mixed_learned", None, 0, 1),
