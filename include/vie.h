@@ -142,7 +142,7 @@ int vie_setup(const vie_body *bodies, int32_t n_bodies, const vie_options *opt,
 int vie_solve(vie_ctx *ctx, const vie_planewave *inc, const int32_t *nrhs_per_body,
               vie_stats *stats);
 
-/* Block preconditioner of the paper's large metasurface solve (Sec. IV:
+/* Block preconditioner of the paper's large metasurface solve (Sec. III-B:
  * BiCGStab with a preconditioner over 7 x 7 blocks), here as block Jacobi
  * over a lateral partition, with restarted flexible GMRES (Saad 1993) as the
  * outer method because the block solves are inexact.
@@ -193,15 +193,21 @@ int vie_farfield(vie_ctx *ctx, int32_t body, const double *theta, const double *
 /* Two-photon observables of two populated channels from the 2x2 transfer
  * coefficients T = (T_a1, T_a2, T_b1, T_b2) (eqs. field_transfer1/2; T_aj is
  * detector a's projected far-field amplitude for channel j, eq. Eproj).
- *   g2 (eq. 10) with weights omega[2] (NULL: equal);
+ * Channel weights omega[2] (NULL: equal) are the omega_kj of the field
+ * operators (eqs. 8-9): every coefficient of channel j is first multiplied by
+ * sqrt(omega[j]), t_aj = sqrt(w_j) T_aj, t_bj = sqrt(w_j) T_bj.  Then
+ *   g2 (eq. 10) = |t_a1 t_b2 + t_a2 t_b1|^2 / (G1_a G1_b),
+ *     G1_a = |t_a1|^2 + |t_a2|^2, G1_b = |t_b1|^2 + |t_b2|^2;
  *   Nc_raw[k] = sigma sqrt(pi) (|A_d|^2 + |A_e|^2 + 2 Re(A_d A_e*) c_k),
- *     A_d = T_a1 T_b2, A_e = T_a2 T_b1, c_k = exp(-dtau_k^2 / sigma^2)
+ *     A_d = t_a1 t_b2, A_e = t_a2 t_b1, c_k = exp(-dtau_k^2 / sigma^2)
  *     (eqs. 19-22 with K = 1 and baseband Gaussian wavepackets);
  *   Nc_norm = Nc_raw / D_c with D_c = sigma sqrt(pi) (|A_d|^2 + |A_e|^2)
  *     (VIE_NORM_R1, -> 1 at large delay, eq. 18) or
- *     D_c = sigma sqrt(pi) G1_a G1_b (VIE_NORM_R2, Nc_norm(0) = g2).
- * A dark detector (zero denominator) gives NaN and VIE_OK.  Host arrays;
- * g2, Nc_raw, Nc_norm may each be NULL. */
+ *     D_c = sigma sqrt(pi) G1_a G1_b (VIE_NORM_R2, Nc_norm(0) = g2 for any
+ *     weights).
+ * A dark detector (zero denominator) gives NaN and VIE_OK.  VIE_EINVAL for
+ * non-finite T, non-positive or non-finite weights, and sigma <= 0 when
+ * delays are asked for.  Host arrays; g2, Nc_raw, Nc_norm may each be NULL. */
 int hom_g2(const vie_c64 T[4], const double *omega, double sigma, const double *dtau,
            int32_t ndelay, int32_t norm, double *g2, double *Nc_raw, double *Nc_norm);
 

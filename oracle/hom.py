@@ -15,6 +15,9 @@ two-channel transfer relation, eqs. field_transfer1/2).
   Normalisation R1: D_c = sigma sqrt(pi) (|A_dir|^2 + |A_ex|^2), so that
   Nc~ -> 1 at large delay.  R2: D_c = sigma sqrt(pi) G1_a G1_b (product of
   marginal intensities), so that Nc~(0) = g2 and single-path zeros stay zero.
+  Channel weights w_j (the sqrt(omega_kj) factors of the field operators,
+  eqs. 8-9) multiply every transfer coefficient of channel j by sqrt(w_j)
+  before any of the above, exactly as they enter g2 (eq. 10).
 * Classical comparison (eq. 27): P2 = |T_a1 + T_a2|^2 |T_b1 + T_b2|^2.
 """
 
@@ -73,10 +76,19 @@ def path_amplitudes(T):
     return complex(T[0]) * complex(T[3]), complex(T[1]) * complex(T[2])
 
 
-def coincidence(T, sigma, dtau, norm="R1"):
+def weighted(T, omega=(1.0, 1.0)):
+    """Transfer coefficients with the channel weights of eqs. 8-9 folded in:
+    T_aj, T_bj -> sqrt(w_j) T_aj, sqrt(w_j) T_bj."""
+    s1, s2 = np.sqrt(omega[0]), np.sqrt(omega[1])
+    return (s1 * complex(T[0]), s2 * complex(T[1]), s1 * complex(T[2]), s2 * complex(T[3]))
+
+
+def coincidence(T, sigma, dtau, norm="R1", omega=(1.0, 1.0)):
     """Closed-form coincidence number.  Returns (Nc_raw, Nc_norm) arrays over
-    dtau (eqs. 18-22, K = 1, baseband Gaussian wavepackets)."""
+    dtau (eqs. 18-22, K = 1, baseband Gaussian wavepackets), channel weights
+    folded into the transfer coefficients (eqs. 8-9)."""
     dtau = np.asarray(dtau, float)
+    T = weighted(T, omega)
     Ad, Ae = path_amplitudes(T)
     c = np.exp(-(dtau**2) / sigma**2)
     raw = sigma * SQRT_PI * (abs(Ad) ** 2 + abs(Ae) ** 2 + 2.0 * np.real(Ad * np.conj(Ae)) * c)
@@ -92,11 +104,11 @@ def coincidence(T, sigma, dtau, norm="R1"):
     return raw, nrm
 
 
-def coincidence_quadrature(T, sigma, dtau, n=4001, span=12.0):
+def coincidence_quadrature(T, sigma, dtau, n=4001, span=12.0, omega=(1.0, 1.0)):
     """Raw Nc by direct tau quadrature of the scattering correlation
     (eq. G2_scatter) with baseband h(tau) = exp(-tau^2/(2 sigma^2)); trapezoid
     rule on a wide uniform grid (spectrally accurate for Gaussians)."""
-    Ad, Ae = path_amplitudes(T)
+    Ad, Ae = path_amplitudes(weighted(T, omega))
     out = []
     for dt in np.atleast_1d(dtau):
         lo, hi = min(0.0, 2 * dt) - span * sigma, max(0.0, 2 * dt) + span * sigma
@@ -127,11 +139,3 @@ def beam_splitter_nc_quadrature(Tbs, Rbs, sigma, dtau, n=4001, span=12.0):
         G2 = Tbs**2 * h1**2 + Rbs**2 * h2**2 - 2 * Rbs * Tbs * h1 * h2
         out.append(np.trapezoid(G2, tau))
     return np.asarray(out)
-
-
-def detector_projection(Ftheta, Fphi, c_theta, c_phi):
-    """Detector-projected amplitude T = c_theta F_theta + c_phi F_phi
-    (eq. Eproj; coefficients unconjugated; the incident plane wave has no
-    1/r far-field term and is dropped).  z-detection: c = (-sin theta, 0);
-    circular (eq. 30): L = (1, i)/sqrt2, R = (1, -i)/sqrt2."""
-    return c_theta * Ftheta + c_phi * Fphi

@@ -1,7 +1,7 @@
 """Block-Jacobi preconditioner on a lateral partition, and flexible GMRES
 (test infrastructure only).
 
-The paper accelerates its largest solve (the full-wave metasurface, Sec. IV)
+The paper accelerates its largest solve (the full-wave metasurface, Sec. III-B; the method of Sec. II-C)
 with a block preconditioner over a 7 x 7 partition of the structure and a
 parallel implementation; it gives no further detail of the block solve.  The
 reading written out here:

@@ -1212,7 +1212,7 @@ extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* 
 
 // ------------------------------------------------- flexible GMRES (FGMRES)
 // Restarted FGMRES with right preconditioning (Saad 1993) and the block
-// preconditioner of the paper's large metasurface solve (Sec. IV, 7 x 7
+// preconditioner of the paper's large metasurface solve (Sec. III-B, 7 x 7
 // blocks), read as block Jacobi over a lateral partition with inexact block
 // solves: k steps of GMRES from zero on every block.  The block solves of all
 // blocks, bodies and right-hand sides of a group run as one batched product
@@ -1842,10 +1842,13 @@ extern "C" int vie_precond_apply(vie_ctx* ctx, const vie_fgmres_options* fo, con
   BodyRec& B = *ctx->bodies[0];
   Group& G = *ctx->groups[B.group];
   if (!valid_fgmres(fo, G.g) || fo->blocks[0] < 1) return VIE_EINVAL;
-  const int64_t n = G.g.n;
+  // r and z are box vectors on the body's grid (n0 voxels); the body's voxel
+  // list indexes the compute window, which starts zoff layers up
+  const int64_t n0 = G.n0;
+  const int64_t shift = (int64_t)G.g.N[0] * G.g.N[1] * B.zoff;
   const int nb = B.nb;
   const int64_t len = 3 * (int64_t)nb;
-  memset(z, 0, (size_t)nvec * 3 * n * sizeof(vie_c64));
+  memset(z, 0, (size_t)nvec * 3 * n0 * sizeof(vie_c64));
   if (nb == 0) return VIE_OK;
   int rc = bj_build(ctx, B.group, fo);
   if (rc != VIE_OK) return rc;
@@ -1859,7 +1862,7 @@ extern "C" int vie_precond_apply(vie_ctx* ctx, const vie_fgmres_options* fo, con
   for (int q = 0; q < nvec; ++q)
     for (int c = 0; c < 3; ++c)
       for (int k = 0; k < nb; ++k) {
-        const vie_c64& a = r[(size_t)q * 3 * n + (size_t)c * n + vx[k]];
+        const vie_c64& a = r[(size_t)q * 3 * n0 + (size_t)c * n0 + shift + vx[k]];
         hv[(size_t)q * len + (size_t)c * nb + k] = mk(a.re, a.im);
       }
   DevBuf dv, dz;
@@ -1876,8 +1879,9 @@ extern "C" int vie_precond_apply(vie_ctx* ctx, const vie_fgmres_options* fo, con
     for (int c = 0; c < 3; ++c)
       for (int k = 0; k < nb; ++k) {
         const c64 a = hz[(size_t)q * len + (size_t)c * nb + k];
-        z[(size_t)q * 3 * n + (size_t)c * n + vx[k]].re = a.re;
-        z[(size_t)q * 3 * n + (size_t)c * n + vx[k]].im = a.im;
+        vie_c64& o = z[(size_t)q * 3 * n0 + (size_t)c * n0 + shift + vx[k]];
+        o.re = a.re;
+        o.im = a.im;
       }
   return VIE_OK;
 }
@@ -2158,23 +2162,25 @@ extern "C" int hom_g2(const vie_c64 T[4], const double* omega, double sigma, con
   for (int i = 0; i < 4; ++i)
     if (!isfinite(T[i].re) || !isfinite(T[i].im)) return VIE_EINVAL;
   const double w1 = omega ? omega[0] : 1.0, w2 = omega ? omega[1] : 1.0;
-  if (!(w1 > 0) || !(w2 > 0)) return VIE_EINVAL;
-  const c64 a1 = mk(T[0].re, T[0].im), a2 = mk(T[1].re, T[1].im);
-  const c64 b1 = mk(T[2].re, T[2].im), b2 = mk(T[3].re, T[3].im);
+  if (!(w1 > 0) || !(w2 > 0) || !isfinite(w1) || !isfinite(w2)) return VIE_EINVAL;
+  // the channel weights enter as sqrt(w_j) on every coefficient of channel j
+  // (the field operators of eqs. 8-9)
+  const double s1 = sqrt(w1), s2 = sqrt(w2);
+  const c64 a1 = s1 * mk(T[0].re, T[0].im), a2 = s2 * mk(T[1].re, T[1].im);
+  const c64 b1 = s1 * mk(T[2].re, T[2].im), b2 = s2 * mk(T[3].re, T[3].im);
   auto ab2 = [](c64 z) { return z.re * z.re + z.im * z.im; };
   const c64 Ad = a1 * b2, Ae = a2 * b1;  // direct and exchange path amplitudes
   const c64 sum = Ad + Ae;
-  const double G1a = w1 * ab2(a1) + w2 * ab2(a2), G1b = w1 * ab2(b1) + w2 * ab2(b2);
+  const double G1a = ab2(a1) + ab2(a2), G1b = ab2(b1) + ab2(b2);  // marginal intensities
   if (g2) {
     const double den = G1a * G1b;
-    *g2 = den > 0 ? w1 * w2 * ab2(sum) / den : NAN;
+    *g2 = den > 0 ? ab2(sum) / den : NAN;
   }
   if (ndelay > 0 && (Nc_raw || Nc_norm)) {
     const double sp = sigma * sqrt(M_PI);
     const double d2 = ab2(Ad), e2 = ab2(Ae);
     const double cross = 2.0 * (Ad.re * Ae.re + Ad.im * Ae.im);  // 2 Re(Ad conj(Ae))
-    const double M1 = ab2(a1) + ab2(a2), M2 = ab2(b1) + ab2(b2);
-    const double D = norm == VIE_NORM_R1 ? sp * (d2 + e2) : sp * M1 * M2;
+    const double D = norm == VIE_NORM_R1 ? sp * (d2 + e2) : sp * G1a * G1b;
     for (int k = 0; k < ndelay; ++k) {
       const double c = exp(-(dtau[k] * dtau[k]) / (sigma * sigma));
       const double raw = sp * (d2 + e2 + cross * c);
@@ -2185,8 +2191,8 @@ extern "C" int hom_g2(const vie_c64 T[4], const double* omega, double sigma, con
   return VIE_OK;
 }
 
-// Classical fourth-order correlation (eq. 27) of the coherent superposition
-// of the two channels' responses: |T_a1 + T_a2|^2 |T_b1 + T_b2|^2.
+// The grid a body is computed on: its compute window, the circulant lengths
+// and the window's z offset.
 extern "C" int vie_grid(vie_ctx* ctx, int32_t body, int32_t* grid, int32_t* fft,
                         int32_t* offset) {
   if (!ctx) return VIE_EINVAL;
@@ -2215,6 +2221,8 @@ extern "C" int vie_self_term(int32_t kind, double k0, double h, vie_c64* s) {
   return VIE_OK;
 }
 
+// Classical fourth-order correlation (eq. 27) of the coherent superposition
+// of the two channels' responses: |T_a1 + T_a2|^2 |T_b1 + T_b2|^2.
 extern "C" int hom_classical_p2(const vie_c64 T[4], double* p2) {
   if (!T || !p2) return VIE_EINVAL;
   for (int i = 0; i < 4; ++i)

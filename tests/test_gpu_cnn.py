@@ -62,7 +62,7 @@ def test_network_forward_matches_oracle(env, d):
         ref, _ = cr.forward(_oracle_params(V, p), feat, round_bf16=True)
         err = _relerr(out.cpu().numpy(), ref)
         print(d, "forward rel err", err)
-        assert err < 1e-2
+        assert err < 1e-3  # rel-L2 bar of the learned-part parity
     finally:
         V.vie_cnn_destroy(net)
 
@@ -86,7 +86,7 @@ def test_network_gradients_match_oracle(env):
         for (gW, gb), (W_gpu, b_gpu) in zip(grads, V.cnn_unpack(g)):
             ew, eb = _relerr(W_gpu, gW), _relerr(b_gpu, gb)
             print("grad rel err W", ew, "b", eb)
-            assert ew < 3e-2 and eb < 3e-2
+            assert ew < 1e-3 and eb < 1e-3
     finally:
         V.vie_cnn_destroy(net)
 

@@ -1,5 +1,5 @@
 """GPU parity of the block-Jacobi preconditioner and restarted flexible GMRES
-(the block preconditioner of the large metasurface solve, Sec. IV; FGMRES
+(the block preconditioner of the large metasurface solve, Sec. III-B; FGMRES
 after Saad 1993) against the oracle (dense block systems, k-step GMRES
 block solves, textbook FGMRES).
 

@@ -176,15 +176,21 @@ def test_hom_g2_matches_oracle(V):
         om = rng.uniform(0.5, 2, 2)
         g, raw, n1 = V.hom_g2(T, 1.2, dt, V.VIE_NORM_R1, omega=om)
         assert abs(g - hom.g2(T, tuple(om))) < 1e-12
-        r_raw, r_n1 = hom.coincidence(T, 1.2, dt, "R1")
+        r_raw, r_n1 = hom.coincidence(T, 1.2, dt, "R1", omega=tuple(om))
         assert np.abs(raw - r_raw).max() < 1e-12 * np.abs(r_raw).max()
         assert np.abs(n1 - r_n1).max() < 1e-12
         _, _, n2 = V.hom_g2(T, 1.2, dt, V.VIE_NORM_R2)
         assert np.abs(n2 - hom.coincidence(T, 1.2, dt, "R2")[1]).max() < 1e-12
+        # unequal weights: R2 against the oracle, and its zero-delay value is g2
+        g, _, n2w = V.hom_g2(T, 1.2, np.r_[0.0, dt], V.VIE_NORM_R2, omega=om)
+        assert np.abs(n2w[1:] - hom.coincidence(T, 1.2, dt, "R2", omega=tuple(om))[1]).max() < 1e-12
+        assert abs(n2w[0] - g) < 1e-12
     g, _, n = V.hom_g2([0, 0, 1, 1j], 1.2, dt[:3])
     assert np.isnan(g) and np.all(np.isnan(n))
     g, _, _ = V.hom_g2(hom.beam_splitter_T(0.5, 0.5))
     assert abs(g) < 1e-15
+    g, _, _ = V.hom_g2(hom.beam_splitter_T(0.5, 0.5), omega=(2.0, 1.0))
+    assert abs(g - hom.g2_fock(hom.beam_splitter_T(0.5, 0.5), (2.0, 1.0))) < 1e-12
 
 
 def test_hom_classical_p2_matches_oracle(V):

@@ -9,6 +9,9 @@ unknowns is unchanged; the checks are against the oracle on the full grid.
 * BiCGSTAB and block-Jacobi FGMRES solves, currents and far fields equal the
   dense LU solution (rel. 1e-10), for two bodies at different heights sharing
   one window, and equal the solves of a context without the window;
+* the block-Jacobi preconditioner applied alone (vie_precond_apply) on box
+  vectors of the body's grid equals the oracle's block Jacobi on the full
+  grid (rel. 1e-9), and is zero off the body;
 * the flag is fixed at setup.
 """
 
@@ -16,6 +19,7 @@ import numpy as np
 import pytest
 import scipy.linalg
 
+from oracle import precond as pc
 from oracle import vie_dense as vd
 from synth import Grid
 
@@ -114,6 +118,34 @@ def test_window_solves_match_lu(V, solver):
             e_full = _relerr(ws[q], res[0][b][0][q])
             print(solver, b, q, e_w, e_f, e_full)
             assert e_w < 1e-10 and e_f < 1e-10 and e_full < 1e-10
+
+
+def test_window_precond_apply_matches_oracle(V):
+    rng = np.random.default_rng(4)
+    g = Grid.centred(N, H)
+    eps = _slab_body(rng, 15, 23)
+    chi = (eps - 1).ravel()
+    pos = vd.voxel_centres(g.n, g.h, g.origin)
+    A, body = vd.body_system(chi, pos, H, K0)
+    r = rng.standard_normal((2, 3) + N[::-1]) + 1j * rng.standard_normal((2, 3) + N[::-1])
+    blocks, k = (3, 2), 3
+    bset = pc.block_index_sets(pc.lateral_blocks(g.n, *blocks)[body])
+    ctx = V.vie_setup([(eps, H, g.origin)], V.make_options(K0, flags=V.VIE_FLAG_Z_WINDOW))
+    try:
+        assert V.vie_grid(ctx, 0)[2] == (0, 0, 11)
+        z = V.vie_precond_apply(ctx, V.fgmres_options(blocks=blocks, inner_iters=k,
+                                                      inner_precision=V.VIE_FP64), r)
+    finally:
+        V.vie_destroy(ctx)
+    off = np.ones(int(np.prod(g.n)), bool)
+    off[body] = False
+    for q in range(2):
+        want = pc.block_jacobi(A, bset, r[q].reshape(3, -1)[:, body].reshape(-1), k=k)
+        got = z[q].reshape(3, -1)[:, body].reshape(-1)
+        err = _relerr(got, want)
+        print("window precond", q, err)
+        assert err < 1e-9
+        assert np.all(z[q].reshape(3, -1)[:, off] == 0)
 
 
 def test_window_flag_fixed_at_setup(V):

@@ -147,6 +147,28 @@ def test_coincidence_normalisation_identities():
     assert np.all(r2 == 0.0)  # single path stays suppressed at every delay
 
 
+def test_coincidence_channel_weights():
+    """Unequal channel weights (the sqrt(omega) factors of eqs. 8-9): the
+    R2-normalised dip at zero delay equals the Fock-space g2 computed
+    independently with the same weights, R1 does not depend on them, and the
+    raw count equals the tau quadrature of the weighted path amplitudes."""
+    rng = np.random.default_rng(16)
+    dt = np.linspace(-5, 5, 11)
+    for _ in range(6):
+        T = _rand_T(rng)
+        om = tuple(rng.uniform(0.3, 3.0, 2))
+        _, r2 = hom.coincidence(T, 1.2, [0.0], "R2", omega=om)
+        assert abs(r2[0] - hom.g2_fock(T, om)) < 1e-12
+        _, r1w = hom.coincidence(T, 1.2, dt, "R1", omega=om)
+        _, r1 = hom.coincidence(T, 1.2, dt, "R1")
+        assert np.abs(r1w - r1).max() < 1e-12
+        raw, _ = hom.coincidence(T, 1.2, dt, omega=om)
+        quad = hom.coincidence_quadrature(T, 1.2, dt, omega=om)
+        assert np.abs(raw - quad).max() < 1e-10 * np.abs(raw).max()
+        raw1, _ = hom.coincidence(T, 1.2, dt)
+        assert np.abs(raw - om[0] * om[1] * raw1).max() < 1e-12 * np.abs(raw).max()
+
+
 # ------------------------------------------------------- VIE + HOM chain ---
 def test_rayleigh_sphere_g2zz_is_sin2_sum_of_azimuths():
     """Small sphere, channels k1 = k x (y-pol), k2 = k y (x-pol), z-detection at

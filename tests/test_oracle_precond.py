@@ -1,5 +1,5 @@
 """Pins of the block-Jacobi / flexible-GMRES oracle (block preconditioner of
-the full-wave metasurface solve, Sec. IV; FGMRES after Saad 1993).
+the full-wave metasurface solve, Sec. III-B; FGMRES after Saad 1993).
 
 Each check compares against something the oracle does not contain:
 
