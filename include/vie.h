@@ -279,6 +279,31 @@ int vie_matvec(vie_ctx *ctx, int32_t body, int32_t precision, const vie_c64 *x, 
 int vie_matvec_dev(vie_ctx *ctx, int32_t body, int32_t precision, const void *x_dev,
                    void *y_dev, int32_t nvec);
 
+/* Allocation-free variant of vie_matvec_dev, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same arguments, layout and result (the
+ * same kernels; the z-pass launch shape is the one the context has tuned for
+ * this grid, else the default).  The call allocates nothing, copies nothing
+ * from host memory and records no memset: its scratch (FFT work arrays, a
+ * table of nvec ints and, with the z window, two window copies of the
+ * vectors) lives in a static device array of VIE_STATIC_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on until the process ends.  Bytes
+ * needed, each term rounded up to 256, with c = 16 (VIE_FP64) or 8
+ * (VIE_MIXED), window grid (N1, N2, N3) and FFT lengths (P1, P2, P3) as
+ * reported by vie_grid, and n the window's voxel count:
+ *   nvec * 3 * N3 * N2 * P1 * c  +  nvec * 3 * Z * P2 * P1 * c  +  4 nvec
+ *   [+ 2 * nvec * 3 * n * 16 when the window is smaller than the grid],
+ * Z = N3 rounded up to a multiple of min(16, N3).
+ * VIE_ENOTSUP when that exceeds the limit (nothing is launched).  Every call
+ * on one GPU, from any context or thread, shares that GPU's array: calls
+ * whose work overlaps in time on one GPU (different streams, or different
+ * host threads) race and give wrong results; calls on one stream are ordered
+ * and safe.  Nothing in the array must start at zero (every element a call
+ * reads, it has written first). */
+#define VIE_STATIC_SCRATCH_BYTES 268435456
+int vie_matvec_dev_static(vie_ctx *ctx, int32_t body, int32_t precision, const void *x_dev,
+                          void *y_dev, int32_t nvec);
+
 /* Use the given hipStream_t for all later device work (NULL: library's own). */
 int vie_set_stream(vie_ctx *ctx, void *hip_stream);
 

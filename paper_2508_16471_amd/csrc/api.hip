@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -253,6 +254,7 @@ struct vie_cnn {
 
 struct vie_ctx {
   vie_options opt;
+  int dev = 0;             // HIP device current at setup
   vie_cnn* cnn = nullptr;  // warm-start network (not owned)
   DevBuf feat;             // network input workspace (bf16)
   hipStream_t own_stream = nullptr;
@@ -273,6 +275,33 @@ struct vie_ctx {
   std::unique_ptr<ArnoldiBufs> fgm;
   std::vector<std::unique_ptr<BlockPrec>> bj;  // [group]
 };
+
+// ------------------------------------------------ allocation-free scratch
+// Scratch of vie_matvec_dev_static: a file-scope device array, one copy per
+// GPU, that exists from the code object's load to the end of the process.
+// Host code never passes `scratch` itself to a kernel (on the host it is a
+// stand-in, not a device address): vie_setup looks up each device's address
+// of it once, with that device current, and the entry point uses that.
+static __device__ __align__(256) unsigned char scratch[VIE_STATIC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices];      // device address per device
+static hipError_t g_scratch_err[kMaxDevices];  // result of the look-up
+static bool g_scratch_done[kMaxDevices];
+
+// Look up the current device's address of `scratch` (first call per device).
+static hipError_t scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    void* ptr = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+    g_scratch_done[dev] = true;
+  }
+  return g_scratch_err[dev];
+}
 
 // --------------------------------------------------------------- utilities
 #define VIE_HIP(call)                                                                 \
@@ -417,8 +446,18 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
     vie_destroy(ctx);
     return code;
   };
+  if (hipGetDevice(&ctx->dev) != hipSuccess) return bail(VIE_EDEVICE);
   if (hipStreamCreate(&ctx->own_stream) != hipSuccess) return bail(VIE_EDEVICE);
   ctx->stream = ctx->own_stream;
+  {
+    const hipError_t se = scratch_init(ctx->dev);
+    if (se != hipSuccess) {
+      if (getenv("VIE_LOG"))
+        fprintf(stderr, "vie: hipGetSymbolAddress(scratch) failed on device %d: %s\n", ctx->dev,
+                hipGetErrorString(se));
+      return bail(VIE_EDEVICE);
+    }
+  }
   // Group bodies by (n, h).  With VIE_FLAG_Z_WINDOW a group computes on a
   // window of its grid in z: the layers that hold body voxels of any of its
   // bodies plus a 4-layer margin (the network box), clipped to the grid.
@@ -1936,6 +1975,73 @@ extern "C" int vie_matvec_dev(vie_ctx* ctx, int32_t body, int32_t precision, con
     for (int64_t r = 0; r < (int64_t)nvec * 3; ++r)
       VIE_HIP(hipMemcpyAsync((c64*)y + r * G.n0 + shift, G.boxY.as<c64>() + r * G.g.n,
                              G.g.n * sizeof(c64), hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  return VIE_OK;
+}
+
+// The product of vie_matvec_dev with every scratch buffer (FFT work arrays,
+// the right-hand-side table, window copies) carved out of the static scratch
+// array instead of memory the context allocates: no allocation, no host
+// copy, no memset.  Layout, each part 256-byte aligned: bufA, bufB, the
+// body table, then the two window copies.  The z-pass shape is the one tuned
+// for this group if any, else the default.
+extern "C" int vie_matvec_dev_static(vie_ctx* ctx, int32_t body, int32_t precision,
+                                     const void* x, void* y, int32_t nvec) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->poisoned) return VIE_ESTATE;
+  if (body < 0 || body >= (int)ctx->bodies.size() || nvec < 1 || !x || !y) return VIE_EINVAL;
+  if (precision != VIE_FP64 && precision != VIE_MIXED) return VIE_EINVAL;
+  BodyRec& B = *ctx->bodies[body];
+  Group& G = *ctx->groups[B.group];
+  const int prec = precision == VIE_MIXED ? 1 : 0;
+  const size_t cb = prec ? sizeof(c32) : sizeof(c64);
+  const bool window = G.g.n != G.n0;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t a_b = al((size_t)nvec * 3 * G.g.N[2] * G.g.N[1] * G.g.P[0] * cb);
+  const size_t b_b = al((size_t)nvec * (size_t)bufB_elems(G.g) * cb);
+  const size_t r_b = al((size_t)nvec * sizeof(int));
+  const size_t w_b = window ? al((size_t)nvec * 3 * G.g.n * sizeof(c64)) : 0;
+  const size_t need = a_b + b_b + r_b + 2 * w_b;
+  if (need > (size_t)VIE_STATIC_SCRATCH_BYTES) {
+    if (getenv("VIE_LOG"))
+      fprintf(stderr, "vie: vie_matvec_dev_static needs %zu bytes of scratch, the limit is %zu\n",
+              need, (size_t)VIE_STATIC_SCRATCH_BYTES);
+    return VIE_ENOTSUP;
+  }
+  char* base = (char*)g_scratch_ptr[ctx->dev];
+  if (!base) return VIE_ESTATE;  // the look-up at setup failed (vie_setup would have said so)
+  int* rb = (int*)(base + a_b + b_b);
+  c64* boxX = (c64*)(base + a_b + b_b + r_b);
+  c64* boxY = (c64*)(base + a_b + b_b + r_b + w_b);
+  const int saved = G.g.nrhs;
+  G.g.nrhs = nvec;
+  MatvecArgs m = matvec_args(G, prec, nullptr);
+  m.bufA = base;
+  m.bufB = base + a_b;
+  m.rhs_body = rb;
+  m.zvar = G.zvar[prec] >= 0 ? G.zvar[prec] : 0;
+  hipError_t err = launch_fill_int(rb, nvec, B.slot, ctx->stream);
+  const c64* xs = (const c64*)x;
+  c64* ys = (c64*)y;
+  const int64_t shift = (int64_t)G.g.N[0] * G.g.N[1] * B.zoff;
+  if (window && err == hipSuccess) {
+    // the window of every component: nvec * 3 rows of n from rows of n0
+    err = hipMemcpy2DAsync(boxX, G.g.n * sizeof(c64), (const c64*)x + shift, G.n0 * sizeof(c64),
+                           G.g.n * sizeof(c64), (size_t)nvec * 3, hipMemcpyDeviceToDevice,
+                           ctx->stream);
+    xs = boxX;
+    ys = boxY;
+  }
+  EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
+  if (err == hipSuccess) err = launch_matvec(m, prec, xs, ys, e, ctx->stream, nullptr, nullptr);
+  G.g.nrhs = saved;
+  VIE_HIP(err);
+  if (window) {
+    VIE_HIP(hipMemcpyAsync(y, x, (size_t)nvec * 3 * G.n0 * sizeof(c64), hipMemcpyDeviceToDevice,
+                           ctx->stream));
+    VIE_HIP(hipMemcpy2DAsync((c64*)y + shift, G.n0 * sizeof(c64), boxY, G.g.n * sizeof(c64),
+                             G.g.n * sizeof(c64), (size_t)nvec * 3, hipMemcpyDeviceToDevice,
+                             ctx->stream));
   }
   return VIE_OK;
 }

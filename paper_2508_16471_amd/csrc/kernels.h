@@ -161,6 +161,8 @@ hipError_t launch_farfield_mfma(const c64* w, const int64_t* roff_host, int nr, 
 // ||v_rhs||^2 of body-compressed vectors into out[nrhs] (device).
 hipError_t launch_vec_norm2(int nrhs, const BodyIdx& bi, const c64* v, double* out,
                             hipStream_t s);
+// p[i] = v for i < n (device ints), by a kernel (no memset node when captured).
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
 // Gather a box-layout vector [3][n] into body-compressed storage [3][nb].
 hipError_t launch_compress(const c64* box, c64* comp, const int* vox, int nb, int64_t n,
                            hipStream_t s);

@@ -319,6 +319,17 @@ hipError_t launch_vec_norm2(int nrhs, const BodyIdx& bi, const c64* v, double* o
   k_vec_norm2<<<nrhs, VT, 0, s>>>(bi, v, out);
   return hipGetLastError();
 }
+__global__ void k_fill_int(int* __restrict__ p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s) {
+  if (n < 1) return hipSuccess;
+  k_fill_int<<<(n + VT - 1) / VT, VT, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_compress(const c64* box, c64* comp, const int* vox, int nb, int64_t n,
                            hipStream_t s) {
   int64_t b = (3 * (int64_t)nb + VT - 1) / VT;

@@ -22,6 +22,7 @@ VIE_FLAG_TIMING = 1
 VIE_FLAG_NO_GRAPH = 2
 VIE_FLAG_CUBE_SELF = 4
 VIE_FLAG_Z_WINDOW = 8
+VIE_STATIC_SCRATCH_BYTES = 268435456  # size of the static scratch of vie_matvec_dev_static
 
 
 class vie_c64(C.Structure):
@@ -98,6 +99,8 @@ def lib():
                                      C.c_int32]),
             "vie_matvec_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                          C.c_int32]),
+            "vie_matvec_dev_static": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                                C.c_void_p, C.c_int32]),
             "vie_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
             "vie_kernel_times": (C.c_int, [C.c_void_p, P(C.c_char_p), P(C.c_double), P(C.c_int64),
                                            P(C.c_int32), C.c_int32]),
@@ -301,6 +304,13 @@ def vie_matvec(ctx, body, x, precision=VIE_FP64):
 def vie_matvec_dev(ctx, body, x_ptr, y_ptr, nvec, precision=VIE_FP64):
     _check(lib().vie_matvec_dev(ctx, int(body), int(precision), C.c_void_p(x_ptr), C.c_void_p(y_ptr),
                                 int(nvec)), "vie_matvec_dev")
+
+
+def vie_matvec_dev_static(ctx, body, x_ptr, y_ptr, nvec, precision=VIE_FP64):
+    """vie_matvec_dev with its scratch in the library's static device array
+    (allocates nothing); raises VieError(VIE_ENOTSUP) beyond that array's size."""
+    _check(lib().vie_matvec_dev_static(ctx, int(body), int(precision), C.c_void_p(x_ptr),
+                                       C.c_void_p(y_ptr), int(nvec)), "vie_matvec_dev_static")
 
 
 def vie_set_stream(ctx, stream_ptr):
