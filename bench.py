@@ -269,6 +269,28 @@ def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch):
     return rows
 
 
+def arnoldi_bytes(stats, nbv, nch, restart, k):
+    """Algorithmic HBM bytes of the FGMRES Gram-Schmidt kernels (timing kind
+    "arnoldi": one classical Gram-Schmidt pass per step in the mixed path,
+    FP32 basis and work vector): at step j of a cycle, per vector element,
+    the multi-dot reads V_0..V_j and w, the multi-axpy reads V_0..V_j and w
+    and writes w, the normalisation reads w and writes V_{j+1}:
+    (16 j + 56) bytes.  Outer process: every cycle's steps; block solves:
+    k steps per outer step over the same elements (the blocks partition the
+    body).  nbv: body voxels of each body, stats in body-major order."""
+    total = 0.0
+    per = len(nbv) * nch
+    for i, st in enumerate(stats):
+        n = 3 * nbv[(i % per) // nch]
+        steps = st["iters"]
+        full, rem = divmod(steps, restart)
+        cyc = [restart] * full + ([rem] if rem else [])
+        outer = sum(8 * c * (c - 1) + 56 * c for c in cyc)
+        inner = steps * (8 * k * (k - 1) + 56 * k)
+        total += n * (outer + inner)
+    return total
+
+
 # ------------------------------------------------------------ CPU oracle
 _G = {}
 
@@ -311,13 +333,57 @@ def cpu_product_time(body, seconds):
     return t_product, {"workers": workers, "rows": nrows, "body_rows": len(bodyvox), "wall": wall}
 
 
-def cpu_baseline(t_product, info, plain_products):
+def host_info():
+    """CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def cpu_c1_solve():
+    """The oracle's dense LU solve of C1 (16^3 sphere, r = lambda/2, eps 2.25,
+    6,528 unknowns), timed whole on the host: matrix assembly + LU + solve,
+    and one dense product (no extrapolation)."""
+    from oracle import vie_dense as vd
+    from synth import Grid, sphere
+
+    g = Grid.centred(16, 1.0 / 16)
+    chi = (sphere(g, 0.5, 2.25) - 1.0).ravel()
+    pos = vd.voxel_centres(g.n, g.h, g.origin)
+    t0 = time.perf_counter()
+    vd.solve_lu(chi, pos, g.h, K0, (0.0, 0.0, 1.0), (1.0, 0.0, 0.0))
+    t_lu = time.perf_counter() - t0
+    x = np.zeros((3, chi.size), complex)
+    x[:, chi != 0] = 1.0
+    t0 = time.perf_counter()
+    vd.matvec(chi, pos, g.h, K0, x)
+    t_mv = time.perf_counter() - t0
+    return {"workload": "C1: 16^3 sphere r=lambda/2, eps 2.25 (2,176 body voxels, 6,528 unknowns)",
+            "lu_solve_s": t_lu, "lu_solves_per_s": 1.0 / t_lu, "dense_product_s": t_mv}
+
+
+def cpu_baseline(t_product, info, plain_products, c1=None):
     solve_s = t_product * plain_products
-    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": info["workers"], "kind": "oracle",
-            "sample": (f"{info['rows']} of {info['body_rows']} body rows of the FP64 product (direct "
-                       f"O(N_b) sum per row) on one held-out 128^3 body in {info['wall']:.1f} s wall; "
-                       f"extrapolated to a full product ({t_product:.1f} s) x {plain_products:.0f} "
-                       f"products per plain solve (the GPU plain path's measured count)")}
+    out = {"value": 1.0 / solve_s, "unit": "solves/s", "cores": info["workers"], "kind": "oracle",
+           "sample": (f"{info['rows']} of {info['body_rows']} body rows of the FP64 product (direct "
+                      f"O(N_b) sum per row) on one held-out 128^3 body in {info['wall']:.1f} s wall; "
+                      f"scaled to a full product ({t_product:.1f} s) x {plain_products:.0f} "
+                      f"products per plain solve (the GPU plain path's measured count)"),
+           "host": host_info()}
+    if c1 is not None:
+        out["c1_measured"] = c1
+    return out
 
 
 # ------------------------------------------------------- product timing
@@ -415,8 +481,7 @@ def learned_leg(V, torch, ctx, args, chans, nb, nch, theta, phi, dtau, fast_valu
         V.vie_attach_cnn(ctx, net)
         V.vie_set_options(ctx, V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol,
                                               max_iter=20000, inner_tol=args.inner_tol,
-                                              warm_start=1,
-                                              flags=V.VIE_FLAG_TIMING | args.wflag))
+                                              warm_start=1, flags=args.wflag))
         solve()  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -939,9 +1004,10 @@ def main():
                           "right-hand side / body (see DESIGN.md), --gpus must be 1"}))
         sys.exit(2)
     bodies, chans = make_workload(args.bodies, args.channels, args.grid)
-    cpu_t = None
+    cpu_t = c1 = None
     if not args.no_cpu:  # host oracle first, before this process touches the GPU
         cpu_t = cpu_product_time(bodies[0], args.cpu_seconds)
+        c1 = cpu_c1_solve()
     import torch
 
     from paper_2508_16471_amd import vie as V
@@ -954,8 +1020,11 @@ def main():
     dtau = np.linspace(-5, 5, 200)
 
     args.wflag = 0 if args.no_window else V.VIE_FLAG_Z_WINDOW
+    # timed as shipped: graphs on, no timing events
     fast = V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
-                          inner_tol=args.inner_tol, flags=V.VIE_FLAG_TIMING | args.wflag)
+                          inner_tol=args.inner_tol, flags=args.wflag)
+    fast_timed = V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
+                                inner_tol=args.inner_tol, flags=V.VIE_FLAG_TIMING | args.wflag)
     t0 = time.perf_counter()
     ctx = V.vie_setup([(e, h, o) for e, h, o, _ in bodies], fast)
     setup_s = time.perf_counter() - t0
@@ -979,7 +1048,6 @@ def main():
 
     for _ in range(args.warmup):
         step()
-    V.vie_kernel_times(ctx, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     all_stats = []
@@ -987,14 +1055,30 @@ def main():
         all_stats += step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    times = V.vie_kernel_times(ctx, reset=True)
     solves = args.steps * nb * nch
     value = solves / dt
+    # Per-kernel times: the same steps again with HIP events around every
+    # launch on the library's stream (instrumented: graphs off, events between
+    # launches); the kernels and their launches are the same as in the timed
+    # region above.
+    V.vie_set_options(ctx, fast_timed)
+    step()
+    V.vie_kernel_times(ctx, reset=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    inst_stats = []
+    for _ in range(args.steps):
+        inst_stats += step()
+    torch.cuda.synchronize()
+    dt_inst = time.perf_counter() - t1
+    times = V.vie_kernel_times(ctx, reset=True)
+    V.vie_set_options(ctx, fast)
+    iters_match = [s["iters"] for s in inst_stats] == [s["iters"] for s in all_stats]
     nb_mean = float(np.mean([(e > 1).sum() for e, _, _, _ in bodies]))
     if use_fgmres:
-        fast_rows = roofline_fgmres(times, all_stats, N, P, Q, nb_mean, geom, args.inner_iters, nch)
+        fast_rows = roofline_fgmres(times, inst_stats, N, P, Q, nb_mean, geom, args.inner_iters, nch)
     else:
-        fast_rows = roofline_from_times(times, all_stats, N, P, Q, mixed=True, nb=nb_mean)
+        fast_rows = roofline_from_times(times, inst_stats, N, P, Q, mixed=True, nb=nb_mean)
     dom = max(fast_rows, key=lambda k: fast_rows[k]["ms_total"])
     d = fast_rows[dom]
     # the whole FP32 operator product of the body grid: its five passes'
@@ -1009,30 +1093,44 @@ def main():
               "frac": mv_bytes / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if mv_ms > 0 else None,
               "rhs_products": zrow["rhs_execs"],
               "rhs_products_per_s": zrow["rhs_execs"] / (mv_ms * 1e-3) if mv_ms > 0 else None}
+    arn = None
+    if use_fgmres and "arnoldi" in times:
+        a_ms = times["arnoldi"][0]
+        a_by = arnoldi_bytes(inst_stats, [int((e != 1.0).sum()) for e, _, _, _ in bodies], nch,
+                             args.restart, args.inner_iters)
+        arn = {"ms_total": a_ms, "launches": int(times["arnoldi"][1]), "bytes": a_by,
+               "GBps": a_by / (a_ms * 1e-3) / 1e9, "frac": a_by / (a_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "model": "16 j + 56 bytes per element at Gram-Schmidt step j (FP32 basis and w)"}
     conv = all(s["converged"] for s in all_stats)
     max_res = max(s["rel_res"] for s in all_stats)
     prod_fast = np.mean([s["matvecs"] for s in all_stats])
 
     plain = None
     if not args.no_plain:
-        popt = V.make_options(K0, precision=V.VIE_FP64, tol=args.tol, max_iter=20000,
-                              flags=V.VIE_FLAG_TIMING | args.wflag)
-        V.vie_set_options(ctx, popt)
-        ps = []
+        def plain_solves():
+            ps = []
+            for i in range(args.plain_solves):
+                b, q = divmod(i % (nb * nch), nch)
+                cnt = [0] * nb
+                cnt[b] = 1
+                _, st = V.vie_solve(ctx, [chans[b * nch + q]], cnt)
+                ps += st
+            return ps
+
+        popt = dict(precision=V.VIE_FP64, tol=args.tol, max_iter=20000)
+        V.vie_set_options(ctx, V.make_options(K0, flags=args.wflag, **popt))
         V.vie_solve(ctx, [chans[0]], [1] + [0] * (nb - 1))  # warm
-        V.vie_kernel_times(ctx, reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(args.plain_solves):
-            b, q = divmod(i % (nb * nch), nch)
-            cnt = [0] * nb
-            cnt[b] = 1
-            _, st = V.vie_solve(ctx, [chans[b * nch + q]], cnt)
-            ps += st
+        ps = plain_solves()
         torch.cuda.synchronize()
         pdt = time.perf_counter() - t0
+        # per-kernel times from an instrumented re-run of the same solves
+        V.vie_set_options(ctx, V.make_options(K0, flags=V.VIE_FLAG_TIMING | args.wflag, **popt))
+        V.vie_kernel_times(ctx, reset=True)
+        ps_inst = plain_solves()
         ptimes = V.vie_kernel_times(ctx, reset=True)
-        prow = roofline_from_times(ptimes, ps, N, P, Q, mixed=False, nb=nb_mean)
+        prow = roofline_from_times(ptimes, ps_inst, N, P, Q, mixed=False, nb=nb_mean)
         plain = {"solves_per_s": args.plain_solves / pdt,
                  "iters_mean": float(np.mean([s["iters"] for s in ps])),
                  "products_mean": float(np.mean([s["matvecs"] for s in ps])),
@@ -1047,13 +1145,14 @@ def main():
     na = na_detection(V, torch, ctx, nch)
     V.vie_destroy(ctx)
     secondary = None if args.no_plain else sphere_leg(V, torch, args)
+    probe = V.vie_hbm_probe(4 << 30, 10)  # achievable HBM on this device
     if args.calib_copy:
         calib_copy(torch)
 
     cpu = None
     if cpu_t is not None:
         prods = plain["products_mean"] if plain else prod_fast
-        cpu = cpu_baseline(cpu_t[0], cpu_t[1], prods)
+        cpu = cpu_baseline(cpu_t[0], cpu_t[1], prods, c1)
 
     mt = measured_traffic(dom, d["avg_launch_ms"])
     line = {
@@ -1090,7 +1189,14 @@ def main():
                      "traffic": (mt or {}).get("bytes_per_launch"),
                      "traffic_detail": mt,
                      "algorithmic_bytes_per_launch": d["bytes"] / d["launches"],
-                     "avg_launch_ms": d["avg_launch_ms"]},
+                     "avg_launch_ms": d["avg_launch_ms"],
+                     "timing": ("HIP events around every launch on the library's stream, over "
+                                "an instrumented re-run of the timed steps (graphs off)"),
+                     "instrumented_ms_per_step": dt_inst / args.steps * 1e3,
+                     "instrumented_iters_match": iters_match,
+                     "achievable_GBps": probe,
+                     "frac_of_achievable_copy": d["GBps"] / probe["copy"]},
+        "arnoldi": arn,
         "matvec": matvec,
         "cpu_baseline": cpu,
         "fast": {"converged": conv, "max_rel_res": max_res, "products_mean": float(prod_fast),

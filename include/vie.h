@@ -318,6 +318,15 @@ int vie_set_stream(vie_ctx *ctx, void *hip_stream);
 int vie_kernel_times(vie_ctx *ctx, const char **names, double *ms, int64_t *cnt,
                      int32_t *nkinds, int32_t reset);
 
+/* Achievable HBM bandwidth of the current device (measurement aid): streaming
+ * read, write and copy kernels over a buffer of `bytes` (1 MiB .. 64 GiB; the
+ * copy uses two such buffers), each timed over `reps` launches after one
+ * warm-up with HIP events on the null stream.  gbps[0] = read, gbps[1] =
+ * write, gbps[2] = copy (read + write bytes), in 1e9 bytes/s.  Allocates and
+ * frees its buffers; VIE_EINVAL for out-of-range sizes, VIE_ENOMEM when the
+ * buffers do not fit. */
+int vie_hbm_probe(int64_t bytes, int32_t reps, double *gbps);
+
 /* Change option fields that do not affect setup (tol, max_iter, precision,
  * inner_tol, warm_start, flags).  k0 must match the setup value. */
 int vie_set_options(vie_ctx *ctx, const vie_options *opt);

@@ -140,11 +140,34 @@ struct TimedEvent {
 struct ArnoldiBufs {
   DevBuf V, Z, w, H1, H2, NR, dpart, npart, off, len, act, nvs, coef;
   DevBuf W2, act2;  // ||w||^2 before orthogonalisation, reorthogonalisation flags
-  DevBuf wide;      // FP64 copy of an FP32 basis vector (product input)
+  // least squares on the device (LsBufs) and the per-segment step counters
+  DevBuf lsR, lscs, lssn, lsg, lsnst, mc, steps, cycles, anyf;
+  int ls_m = 0;     // columns the least-squares buffers hold
   int v32 = 0;      // V and Z stored in FP32 (mixed precision) instead of FP64
+  // captured step chunks of the outer FGMRES (graph per first step, valid
+  // while `key` matches every pointer and size the capture used)
+  std::vector<hipGraphExec_t> chunk_exec;
+  std::vector<const void*> chunk_key;
+  ~ArnoldiBufs() { clear_graphs(); }
+  void clear_graphs() {
+    for (auto e : chunk_exec)
+      if (e) (void)hipGraphExecDestroy(e);
+    chunk_exec.clear();
+  }
   // address of vector j of a multi-vector with `stride` elements per vector
   void* at(const DevBuf& b, int64_t j, int64_t stride) const {
     return (char*)b.p + (size_t)j * stride * (v32 ? sizeof(c32) : sizeof(c64));
+  }
+  LsBufs ls() const {
+    LsBufs L;
+    L.R = lsR.as<c64>();
+    L.cs = lscs.as<double>();
+    L.sn = lssn.as<c64>();
+    L.g = lsg.as<c64>();
+    L.nst = lsnst.as<int>();
+    L.m = ls_m;
+    L.ldr = ls_m + 1;
+    return L;
   }
 };
 
@@ -166,6 +189,7 @@ struct BlockPrec {
   std::vector<int> bound_rb;     // body slot of every right-hand side
   std::vector<int64_t> bound_roff;
   std::vector<int> seg_rhs;      // [segment] right-hand side
+  DevBuf seg_rhs_dev, ones;      // device copy of seg_rhs; [rhs] all-active flags
   int nseg = 0, maxlen = 1, maxqlen = 1;
   int64_t tot = 0;               // elements of all right-hand sides' vectors
   DevBuf qoff, qpoff, qlen;      // [rhs] vector offset, permutation offset, elements
@@ -173,61 +197,6 @@ struct BlockPrec {
   DevBuf R, X;                   // permuted input, block solution
   ~BlockPrec() {
     if (sub) vie_destroy(sub);
-  }
-};
-
-// Least-squares part of GMRES for one segment: the Hessenberg matrix reduced
-// column by column by complex Givens rotations (c real, s complex).
-struct HessLS {
-  int m = 0;
-  std::vector<c64> R, sn, g;
-  std::vector<double> cs;
-  void reset(int m_, double beta) {
-    m = m_;
-    R.assign((size_t)(m + 1) * m, mk(0.0, 0.0));
-    sn.assign(m, mk(0.0, 0.0));
-    cs.assign(m, 0.0);
-    g.assign(m + 1, mk(0.0, 0.0));
-    g[0] = mk(beta, 0.0);
-  }
-  // Append column j (h[0..j], subdiagonal hn >= 0); returns the residual
-  // estimate |g[j+1]|.
-  double add(int j, const c64* h, double hn) {
-    c64* col = &R[(size_t)j * (m + 1)];
-    for (int i = 0; i <= j; ++i) col[i] = h[i];
-    for (int i = 0; i < j; ++i) {
-      const c64 a = col[i], b = col[i + 1];
-      col[i] = cs[i] * a + sn[i] * b;
-      col[i + 1] = cs[i] * b - mk(sn[i].re, -sn[i].im) * a;
-    }
-    const c64 a = col[j];
-    const double aa = std::hypot(a.re, a.im);
-    const double rho = std::hypot(aa, hn);
-    if (rho == 0.0) {
-      cs[j] = 1.0;
-      sn[j] = mk(0.0, 0.0);
-    } else if (aa == 0.0) {
-      cs[j] = 0.0;
-      sn[j] = mk(1.0, 0.0);
-    } else {
-      cs[j] = aa / rho;
-      sn[j] = mk(a.re / aa * hn / rho, a.im / aa * hn / rho);  // (a/|a|) conj(hn) / rho
-    }
-    col[j] = cs[j] * a + hn * sn[j];
-    const c64 gj = g[j];
-    g[j] = cs[j] * gj;
-    g[j + 1] = mk(0.0, 0.0) - mk(sn[j].re, -sn[j].im) * gj;
-    return std::hypot(g[j + 1].re, g[j + 1].im);
-  }
-  // y[0..k) from the triangular system R y = g.
-  void solve(int k, c64* y) const {
-    for (int i = k - 1; i >= 0; --i) {
-      c64 t = g[i];
-      for (int l = i + 1; l < k; ++l) t = t - R[(size_t)l * (m + 1) + i] * y[l];
-      const c64 d = R[(size_t)i * (m + 1) + i];
-      const double dd = d.re * d.re + d.im * d.im;
-      y[i] = dd > 0 ? (1.0 / dd) * cmulc(d, t) : mk(0.0, 0.0);
-    }
   }
 };
 
@@ -446,8 +415,14 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
     vie_destroy(ctx);
     return code;
   };
-  if (hipGetDevice(&ctx->dev) != hipSuccess) return bail(VIE_EDEVICE);
-  if (hipStreamCreate(&ctx->own_stream) != hipSuccess) return bail(VIE_EDEVICE);
+  auto hip_fail = [&](hipError_t e, const char* what) {
+    if (getenv("VIE_LOG"))
+      fprintf(stderr, "vie: vie_setup: %s failed: %s\n", what, hipGetErrorString(e));
+    return bail(e == hipErrorOutOfMemory ? VIE_ENOMEM : VIE_EDEVICE);
+  };
+  hipError_t he;
+  if ((he = hipGetDevice(&ctx->dev)) != hipSuccess) return hip_fail(he, "hipGetDevice");
+  if ((he = hipStreamCreate(&ctx->own_stream)) != hipSuccess) return hip_fail(he, "hipStreamCreate");
   ctx->stream = ctx->own_stream;
   {
     const hipError_t se = scratch_init(ctx->dev);
@@ -583,8 +558,12 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
     }
     auto up = [&](DevBuf& d, const void* src, size_t bytes) {
       if (d.reserve(std::max<size_t>(bytes, 8)) != hipSuccess) return VIE_ENOMEM;
-      if (bytes && hipMemcpy(d.p, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+      hipError_t ue;
+      if (bytes && (ue = hipMemcpy(d.p, src, bytes, hipMemcpyHostToDevice)) != hipSuccess) {
+        if (getenv("VIE_LOG"))
+          fprintf(stderr, "vie: vie_setup: hipMemcpy failed: %s\n", hipGetErrorString(ue));
         return VIE_EDEVICE;
+      }
       return VIE_OK;
     };
     int urc;
@@ -595,9 +574,9 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
         (urc = up(G.voff_arr, G.voff_host.data(), G.voff_host.size() * sizeof(int))) != VIE_OK)
       return bail(urc);
     if (G.chi.reserve(chi_host[gi].size() * sizeof(double)) != hipSuccess) return bail(VIE_ENOMEM);
-    if (hipMemcpy(G.chi.p, chi_host[gi].data(), chi_host[gi].size() * sizeof(double),
-                  hipMemcpyHostToDevice) != hipSuccess)
-      return bail(VIE_EDEVICE);
+    if ((he = hipMemcpy(G.chi.p, chi_host[gi].data(), chi_host[gi].size() * sizeof(double),
+                        hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(he, "hipMemcpy");
     for (int a = 0; a < 3; ++a) {
       std::vector<c64> t64;
       std::vector<c32> t32;
@@ -605,18 +584,18 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
       if (G.tw64[a].reserve(t64.size() * sizeof(c64)) != hipSuccess ||
           G.tw32[a].reserve(t32.size() * sizeof(c32)) != hipSuccess)
         return bail(VIE_ENOMEM);
-      if (hipMemcpy(G.tw64[a].p, t64.data(), t64.size() * sizeof(c64), hipMemcpyHostToDevice) !=
-              hipSuccess ||
-          hipMemcpy(G.tw32[a].p, t32.data(), t32.size() * sizeof(c32), hipMemcpyHostToDevice) !=
-              hipSuccess)
-        return bail(VIE_EDEVICE);
+      if ((he = hipMemcpy(G.tw64[a].p, t64.data(), t64.size() * sizeof(c64),
+                          hipMemcpyHostToDevice)) != hipSuccess ||
+          (he = hipMemcpy(G.tw32[a].p, t32.data(), t32.size() * sizeof(c32),
+                          hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(he, "hipMemcpy");
     }
     rc = build_spectrum(ctx, G);
     if (rc != VIE_OK) return bail(rc);
   }
   for (int k = 0; k < 2; ++k)
-    if (hipEventCreateWithFlags(&ctx->flag_ev[k], hipEventDisableTiming) != hipSuccess)
-      return bail(VIE_EDEVICE);
+    if ((he = hipEventCreateWithFlags(&ctx->flag_ev[k], hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(he, "hipEventCreateWithFlags");
   *out = ctx;
   return VIE_OK;
 }
@@ -770,12 +749,15 @@ static hipError_t tune_z(vie_ctx* ctx, Group& G, int precision) {
   return e;
 }
 
-static hipError_t run_matvec(vie_ctx* ctx, Group& G, int precision, const c64* x, c64* y,
-                             EpiArgs& e, const int* active, bool compressed = true) {
+// x, y: c64 vectors, or c32 with io32 (FP32 product, compressed, plain).
+static hipError_t run_matvec(vie_ctx* ctx, Group& G, int precision, const void* x, void* y,
+                             EpiArgs& e, const int* active, bool compressed = true,
+                             int io32 = 0) {
   hipError_t te = tune_z(ctx, G, precision);
   if (te != hipSuccess) return te;
   MatvecArgs m = matvec_args(G, precision, active);
   if (compressed) m.bi = &G.bi;
+  m.io32 = io32;
   return launch_matvec(m, precision, x, y, e, ctx->stream, timing_on(ctx) ? timing_cb : nullptr,
                        ctx);
 }
@@ -1288,7 +1270,16 @@ static int arnoldi_alloc(vie_ctx* ctx, ArnoldiBufs& A, int nseg, int maxlen, int
   VIE_HIP(A.coef.reserve((size_t)nseg * (m + 1) * sizeof(c64)));
   VIE_HIP(A.W2.reserve((size_t)nseg * sizeof(double)));
   VIE_HIP(A.act2.reserve((size_t)nseg * sizeof(int)));
-  VIE_HIP(A.wide.reserve(vb));
+  VIE_HIP(A.lsR.reserve((size_t)nseg * m * (m + 1) * sizeof(c64)));
+  VIE_HIP(A.lscs.reserve((size_t)nseg * m * sizeof(double)));
+  VIE_HIP(A.lssn.reserve((size_t)nseg * m * sizeof(c64)));
+  VIE_HIP(A.lsg.reserve((size_t)nseg * (m + 1) * sizeof(c64)));
+  VIE_HIP(A.lsnst.reserve((size_t)nseg * sizeof(int)));
+  VIE_HIP(A.mc.reserve((size_t)nseg * sizeof(int)));
+  VIE_HIP(A.steps.reserve((size_t)nseg * sizeof(int)));
+  VIE_HIP(A.cycles.reserve((size_t)nseg * sizeof(int)));
+  VIE_HIP(A.anyf.reserve(sizeof(int)));
+  A.ls_m = m;
   return VIE_OK;
 }
 
@@ -1304,7 +1295,8 @@ static int arnoldi_tables(vie_ctx* ctx, ArnoldiBufs& A, const std::vector<int64_
 
 // Step j of the Arnoldi process after the caller has put the product into w:
 // classical Gram-Schmidt against V_0..V_j (coefficients in H1), repeated
-// (coefficients in H2, zero where skipped) for the segments whose squared norm
+// (coefficients in H2, zero where skipped; only when eta2 > 0, otherwise H2 is
+// neither written nor read) for the segments whose squared norm
 // fell below eta2 times its value before the pass (eta2 = 1/2: the "twice is
 // enough" criterion of Daniel, Gragg, Kaufman and Stewart 1976; eta2 = 0: one
 // pass); ||w||^2 into NR[s][j+1], V_{j+1} = w / ||w||.
@@ -1312,7 +1304,7 @@ static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, in
                                int m, int j, double eta2) {
   const void* V = A.V.p;
   const int v32 = A.v32;
-  c64* w = A.w.as<c64>();
+  void* w = A.w.p;  // FP32 when the basis is (the products then write FP32)
   const int ldh = m + 1;
   c64* h1 = A.H1.as<c64>() + (size_t)j * S.nseg * (m + 1);
   c64* h2 = A.H2.as<c64>() + (size_t)j * S.nseg * (m + 1);
@@ -1321,25 +1313,27 @@ static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, in
   SegSet S2 = S;
   S2.active = A.act2.as<int>();
   hipError_t e;
-  if (eta2 > 0 && (e = launch_seg_maxpy(S, nullptr, 0, 0, 0, nullptr, nullptr, 0, w, npart,
+  if (eta2 > 0 && (e = launch_seg_maxpy(S, nullptr, 0, 0, 0, nullptr, nullptr, 0, w, v32, npart,
                                          A.W2.as<double>(), 1, ctx->stream)) != hipSuccess)
     return e;
-  if ((e = launch_seg_mdot(S, V, v32, stride, j + 1, w, A.dpart.as<c64>(), h1, ldh,
+  if ((e = launch_seg_mdot(S, V, v32, stride, j + 1, w, v32, A.dpart.as<c64>(), h1, ldh,
                            ctx->stream)) != hipSuccess)
     return e;
-  if ((e = launch_seg_maxpy(S, V, v32, stride, j + 1, nullptr, h1, ldh, w, npart, nr, m + 1,
+  if ((e = launch_seg_maxpy(S, V, v32, stride, j + 1, nullptr, h1, ldh, w, v32, npart, nr, m + 1,
                             ctx->stream)) != hipSuccess)
     return e;
-  if ((e = launch_seg_reorth_flags(S, A.W2.as<double>(), nr, m + 1, eta2, A.act2.as<int>(),
-                                   ctx->stream)) != hipSuccess)
-    return e;
-  if ((e = launch_seg_mdot(S2, V, v32, stride, j + 1, w, A.dpart.as<c64>(), h2, ldh,
-                           ctx->stream)) != hipSuccess)
-    return e;
-  if ((e = launch_seg_maxpy(S2, V, v32, stride, j + 1, nullptr, h2, ldh, w, npart, nr, m + 1,
-                            ctx->stream)) != hipSuccess)
-    return e;
-  return launch_seg_normalize(S, w, nr, m + 1, A.at(A.V, j + 1, stride), v32, ctx->stream);
+  if (eta2 > 0) {  // otherwise there is no second pass (and H2 is not read)
+    if ((e = launch_seg_reorth_flags(S, A.W2.as<double>(), nr, m + 1, eta2, A.act2.as<int>(),
+                                     ctx->stream)) != hipSuccess)
+      return e;
+    if ((e = launch_seg_mdot(S2, V, v32, stride, j + 1, w, v32, A.dpart.as<c64>(), h2, ldh,
+                             ctx->stream)) != hipSuccess)
+      return e;
+    if ((e = launch_seg_maxpy(S2, V, v32, stride, j + 1, nullptr, h2, ldh, w, v32, npart, nr, m + 1,
+                              ctx->stream)) != hipSuccess)
+      return e;
+  }
+  return launch_seg_normalize(S, w, v32, nr, m + 1, A.at(A.V, j + 1, stride), v32, ctx->stream);
 }
 
 // Block partition of every body of group G into bx x by lateral blocks:
@@ -1531,6 +1525,12 @@ static int bj_bind(vie_ctx* ctx, Group& G, BlockPrec& P, const std::vector<int>&
                          ctx->stream));
   VIE_HIP(P.R.reserve((size_t)std::max<int64_t>(tot, 1) * sizeof(c64)));
   VIE_HIP(P.X.reserve((size_t)std::max<int64_t>(tot, 1) * sizeof(c64)));
+  VIE_HIP(P.seg_rhs_dev.reserve((size_t)std::max(nseg, 1) * sizeof(int)));
+  VIE_HIP(P.ones.reserve((size_t)std::max(nrhs, 1) * sizeof(int)));
+  if (nseg > 0)
+    VIE_HIP(hipMemcpyAsync(P.seg_rhs_dev.p, P.seg_rhs.data(), nseg * sizeof(int),
+                           hipMemcpyHostToDevice, ctx->stream));
+  VIE_HIP(launch_fill_int(P.ones.as<int>(), nrhs, 1, ctx->stream));
   VIE_HIP(hipStreamSynchronize(ctx->stream));
   P.bound_rb = rb;
   P.bound_roff = roff;
@@ -1538,15 +1538,14 @@ static int bj_bind(vie_ctx* ctx, Group& G, BlockPrec& P, const std::vector<int>&
 }
 
 // z = M^{-1} v for the bound right-hand sides (v, z device vectors at the
-// bound offsets); right-hand sides with act[q] == 0 get z = 0.
+// bound offsets) whose device flag act_rhs[q] is set; z of the others is left
+// as it is.  Device work only (no host copy, no synchronisation, no memset),
+// so a caller may capture it in a graph once the block storage is sized
+// (bj_prepare).
 static int bj_apply(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo, const void* v,
-                    void* z, int vz32, const std::vector<int>& act) {
+                    void* z, int vz32, const int* act_rhs) {
   const int nrhs = (int)P.bound_rb.size();
-  if (P.nseg == 0) {
-    VIE_HIP(hipMemsetAsync(z, 0, (size_t)std::max<int64_t>(P.tot, 0) * (vz32 ? sizeof(c32) : sizeof(c64)),
-                           ctx->stream));
-    return VIE_OK;
-  }
+  if (P.nseg == 0) return VIE_OK;  // no block holds a voxel: the callers never get here
   vie_ctx* sub = P.sub;
   sub->stream = ctx->stream;
   sub->opt.flags = (sub->opt.flags & ~VIE_FLAG_TIMING) | (ctx->opt.flags & VIE_FLAG_TIMING);
@@ -1556,88 +1555,94 @@ static int bj_apply(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo, co
   const int ip = fo->inner_precision == VIE_MIXED ? 1 : 0;
   const int nseg = P.nseg;
   const int64_t tot = P.tot;
-  int rc = arnoldi_alloc(ctx, A, nseg, P.maxlen, tot, k, false);  // grows for a larger k
-  if (rc != VIE_OK) return rc;
+  if (A.ls_m < k) return VIE_ESTATE;  // bj_prepare sizes the storage first
   SegSet S{A.off.as<int64_t>(), A.len.as<int>(), A.act.as<int>(), nseg, seg_blocks(P.maxlen)};
-  std::vector<int> act_s(nseg), nvs(nseg, 0);
-  for (int s = 0; s < nseg; ++s) act_s[s] = act[P.seg_rhs[s]] ? 1 : 0;
-  VIE_HIP(hipMemcpyAsync(A.act.p, act_s.data(), nseg * sizeof(int), hipMemcpyHostToDevice,
-                         ctx->stream));
+  VIE_HIP(launch_seg_act_map(nseg, P.seg_rhs_dev.as<int>(), act_rhs, A.act.as<int>(),
+                             ctx->stream));
   // with FP32 block products the block basis is stored in FP32 too
   A.v32 = ip;
   c64* R = P.R.as<c64>();
   double* NR = A.NR.as<double>();
   const int ldn = k + 1;
   VIE_HIP(launch_permute(nrhs, P.qoff.as<int64_t>(), P.qpoff.as<int64_t>(), P.qlen.as<int>(),
-                         P.maxqlen, P.perm.as<int>(), v, vz32, R, 0, 0, ctx->stream));
-  VIE_HIP(launch_seg_maxpy(S, nullptr, 0, 0, 0, nullptr, nullptr, 0, R, A.npart.as<double>(), NR,
+                         P.maxqlen, P.perm.as<int>(), v, vz32, R, 0, 0, act_rhs, ctx->stream));
+  VIE_HIP(launch_seg_maxpy(S, nullptr, 0, 0, 0, nullptr, nullptr, 0, R, 0, A.npart.as<double>(), NR,
                            ldn, ctx->stream));
-  VIE_HIP(launch_seg_normalize(S, R, NR, ldn, A.V.p, A.v32, ctx->stream));
+  VIE_HIP(launch_seg_normalize(S, R, 0, NR, ldn, A.V.p, A.v32, ctx->stream));
+  // the block solves are approximations: with FP32 block products one
+  // Gram-Schmidt pass is enough
+  const double eta2 = ip ? 0.0 : 0.5;
   for (int j = 0; j < k; ++j) {
+    // with an FP32 basis the FP32 product reads V_j and writes w in FP32
     EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
-    const c64* in = (const c64*)A.at(A.V, j, tot);
-    if (A.v32) {  // the product takes FP64 vectors
-      VIE_HIP(launch_seg_widen(S, A.at(A.V, j, tot), 1, A.wide.as<c64>(), ctx->stream));
-      in = A.wide.as<c64>();
-    }
-    VIE_HIP(run_matvec(sub, Gp, ip, in, A.w.as<c64>(), e, A.act.as<int>()));
-    // the block solves are approximations: with FP32 block products one
-    // Gram-Schmidt pass is enough
-    const double eta2 = ip ? 0.0 : 0.5;
+    VIE_HIP(run_matvec(sub, Gp, ip, A.at(A.V, j, tot), A.w.p, e, A.act.as<int>(), true, A.v32));
     VIE_HIP(timed(ctx, kArnoldiKind, [&] { return arnoldi_orth(ctx, A, S, tot, k, j, eta2); }));
   }
-  std::vector<c64> h1((size_t)k * nseg * ldn), h2((size_t)k * nseg * ldn), coef((size_t)nseg * ldn);
-  std::vector<double> nr((size_t)nseg * ldn);
-  VIE_HIP(hipMemcpyAsync(h1.data(), A.H1.p, h1.size() * sizeof(c64), hipMemcpyDeviceToHost,
+  // least squares of every block solve on the device, then X = V y
+  VIE_HIP(launch_ls_full(nseg, k, A.H1.as<c64>(), A.H2.as<c64>(), eta2 > 0 ? 1 : 0, ldn, NR, ldn,
+                         A.act.as<int>(), A.ls(), A.coef.as<c64>(), ldn, A.nvs.as<int>(),
                          ctx->stream));
-  VIE_HIP(hipMemcpyAsync(h2.data(), A.H2.p, h2.size() * sizeof(c64), hipMemcpyDeviceToHost,
-                         ctx->stream));
-  VIE_HIP(hipMemcpyAsync(nr.data(), NR, nr.size() * sizeof(double), hipMemcpyDeviceToHost,
-                         ctx->stream));
-  VIE_HIP(hipStreamSynchronize(ctx->stream));
-  HessLS ls;
-  std::vector<c64> h(k + 1), y(k);
-  int maxst = 0;
-  for (int s = 0; s < nseg; ++s) {
-    if (!act_s[s]) continue;
-    const double beta = sqrt(std::max(nr[(size_t)s * ldn], 0.0));
-    if (!(beta > 0)) continue;
-    ls.reset(k, beta);
-    int steps = 0;
-    for (int j = 0; j < k; ++j) {
-      for (int i = 0; i <= j; ++i)
-        h[i] = h1[((size_t)j * nseg + s) * ldn + i] + h2[((size_t)j * nseg + s) * ldn + i];
-      const double hn = sqrt(std::max(nr[(size_t)s * ldn + j + 1], 0.0));
-      ls.add(j, h.data(), hn);
-      steps = j + 1;
-      if (hn <= 1e-14 * beta) break;
-    }
-    ls.solve(steps, y.data());
-    for (int i = 0; i < steps; ++i) coef[(size_t)s * ldn + i] = mk(0.0, 0.0) - y[i];
-    nvs[s] = steps;
-    maxst = std::max(maxst, steps);
-  }
-  VIE_HIP(hipMemcpyAsync(A.coef.p, coef.data(), coef.size() * sizeof(c64), hipMemcpyHostToDevice,
-                         ctx->stream));
-  VIE_HIP(hipMemcpyAsync(A.nvs.p, nvs.data(), nseg * sizeof(int), hipMemcpyHostToDevice,
-                         ctx->stream));
-  VIE_HIP(hipMemsetAsync(P.X.p, 0, (size_t)tot * sizeof(c64), ctx->stream));
-  VIE_HIP(launch_seg_maxpy(S, A.V.p, A.v32, tot, maxst, A.nvs.as<int>(), A.coef.as<c64>(), ldn,
-                           P.X.as<c64>(), nullptr, nullptr, 0, ctx->stream));
+  VIE_HIP(launch_seg_lincomb(S, A.V.p, A.v32, tot, k, A.nvs.as<int>(), A.coef.as<c64>(), ldn,
+                             P.X.as<c64>(), ctx->stream));
   VIE_HIP(launch_permute(nrhs, P.qoff.as<int64_t>(), P.qpoff.as<int64_t>(), P.qlen.as<int>(),
-                         P.maxqlen, P.perm.as<int>(), P.X.as<c64>(), 0, z, vz32, 1, ctx->stream));
-  // the host tables must outlive the copies
-  VIE_HIP(hipStreamSynchronize(ctx->stream));
+                         P.maxqlen, P.perm.as<int>(), P.X.as<c64>(), 0, z, vz32, 1, act_rhs,
+                         ctx->stream));
   return VIE_OK;
+}
+
+// Size the block solves' storage for k steps and tune the block products'
+// z pass (both allocate or clear memory, so they run before any capture).
+static int bj_prepare(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo) {
+  if (P.nseg == 0) return VIE_OK;
+  int rc = arnoldi_alloc(ctx, P.ab, P.nseg, P.maxlen, P.tot, fo->inner_iters, false);
+  if (rc != VIE_OK) return rc;
+  vie_ctx* sub = P.sub;
+  sub->stream = ctx->stream;
+  VIE_HIP(tune_z(sub, *sub->groups[0], fo->inner_precision == VIE_MIXED ? 1 : 0));
+  return VIE_OK;
+}
+
+// Pointers and sizes the captured FGMRES step chunks depend on.
+static void key_bufs(std::vector<const void*>& k, std::initializer_list<const DevBuf*> bs) {
+  for (const DevBuf* b : bs) {
+    k.push_back(b->p);
+    k.push_back((const void*)(uintptr_t)b->bytes);
+  }
+}
+static void key_group(std::vector<const void*>& k, const Group& G) {
+  key_bufs(k, {&G.chi, &G.spec64, &G.spec32, &G.tw64[0], &G.tw64[1], &G.tw64[2], &G.tw32[0],
+               &G.tw32[1], &G.tw32[2], &G.vox_all, &G.chic_all, &G.line_ptr_all, &G.nb_arr,
+               &G.voff_arr, &G.roff, &G.x, &G.r, &G.rh, &G.state, &G.flags, &G.bufA, &G.bufB,
+               &G.rhs_body, &G.partials});
+  const int ints[] = {G.g.nrhs, G.zvar[0], G.zvar[1], G.g.N[0], G.g.N[1], G.g.N[2], G.g.P[0],
+                      G.g.P[1], G.g.P[2]};
+  for (int v : ints) k.push_back((const void*)(intptr_t)v);
+}
+static void key_arnoldi(std::vector<const void*>& k, const ArnoldiBufs& A) {
+  key_bufs(k, {&A.V, &A.Z, &A.w, &A.H1, &A.H2, &A.NR, &A.dpart, &A.npart, &A.off, &A.len, &A.act,
+               &A.nvs, &A.coef, &A.W2, &A.act2, &A.lsR, &A.lscs, &A.lssn, &A.lsg,
+               &A.lsnst, &A.mc, &A.steps, &A.cycles, &A.anyf});
+  k.push_back((const void*)(intptr_t)A.ls_m);
+  k.push_back((const void*)(intptr_t)A.v32);
 }
 
 // Restarted FGMRES on every right-hand side of group G (bound by bind_rhs),
 // from w = 0 or the learned warm start.  Arnoldi products in the context's
 // precision; every cycle ends with the FP64 true residual, which alone
-// decides convergence.  A cycle stops early once its residual estimate is
-// below tol / 2.
+// decides convergence.  A right-hand side leaves a cycle early once its
+// residual estimate is below tol / 2.
+//
+// The whole cycle runs on the device: the Givens rotations and the small
+// triangular solves of the outer process and of every block solve are device
+// kernels, and each right-hand side's activity is a device flag that every
+// kernel reads.  The host launches the steps in chunks of kChunk (replayed
+// from a captured graph unless VIE_FLAG_TIMING or VIE_FLAG_NO_GRAPH is set)
+// and stops launching once the flag copied after the previous chunk says that
+// no right-hand side is active (a lagged check: the GPU never waits for the
+// host inside a cycle).  The host waits once per cycle, for the convergence
+// flag after the FP64 residual.
 static int fgmres_group(vie_ctx* ctx, Group& G, BlockPrec* P, const vie_fgmres_options* fo,
-                        bool warm, std::vector<int>& steps, std::vector<int>& cycles) {
+                        bool warm, std::vector<int>& steps_out, std::vector<int>& cycles_out) {
   const int nrhs = G.g.nrhs;
   const int m = fo->restart;
   const bool flex = P != nullptr;
@@ -1680,12 +1685,21 @@ static int fgmres_group(vie_ctx* ctx, Group& G, BlockPrec* P, const vie_fgmres_o
     rc = warm_start_init(ctx, G, fp, fb);
     if (rc != VIE_OK) return rc;
   }
-  std::vector<KState> hs(nrhs);
-  VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
-                         ctx->stream));
-  VIE_HIP(hipStreamSynchronize(ctx->stream));
-  steps.assign(nrhs, 0);
-  cycles.assign(nrhs, 0);
+  int* steps = A.steps.as<int>();
+  int* cycles = A.cycles.as<int>();
+  int* mc = A.mc.as<int>();
+  int* anyf = A.anyf.as<int>();
+  VIE_HIP(launch_fill_int(steps, nrhs, 0, ctx->stream));
+  VIE_HIP(launch_fill_int(cycles, nrhs, 0, ctx->stream));
+  // everything that allocates or clears memory happens before any capture
+  if (flex) {
+    rc = bj_prepare(ctx, *P, fo);
+    if (rc != VIE_OK) return rc;
+  }
+  VIE_HIP(tune_z(ctx, G, prec));
+  VIE_HIP(tune_z(ctx, G, 0));
+  rc = ensure_hflags(ctx, std::max(nrhs, 1));
+  if (rc != VIE_OK) return rc;
   const int maxit = ctx->opt.max_iter;
   // mixed precision: the basis V and the preconditioned vectors Z are stored in
   // FP32 (their products are FP32 anyway); dots, updates and x stay FP64
@@ -1696,106 +1710,134 @@ static int fgmres_group(vie_ctx* ctx, Group& G, BlockPrec* P, const vie_fgmres_o
   // mixed path one Gram-Schmidt pass is enough; the FP64 true residual at the
   // end of every cycle decides convergence either way
   const double eta2 = prec ? 0.0 : 0.5;
-  std::vector<int> act(nrhs), nst(nrhs), mc(nrhs);
-  std::vector<HessLS> ls(nrhs);
-  std::vector<c64> h1((size_t)nrhs * (m + 1)), h2((size_t)nrhs * (m + 1)), hc(m + 1), y(m);
-  std::vector<c64> coef((size_t)nrhs * (m + 1));
-  std::vector<double> nr((size_t)nrhs * (m + 1));
-  for (;;) {
-    bool any = false;
-    for (int q = 0; q < nrhs; ++q) {
-      act[q] = (hs[q].notdone && steps[q] < maxit) ? 1 : 0;
-      any |= act[q] != 0;
+  const LsBufs L = A.ls();
+  const double half_tol = 0.5 * ctx->opt.tol;
+  const bool use_graph = !timing_on(ctx) && !(ctx->opt.flags & VIE_FLAG_NO_GRAPH);
+  constexpr int kChunk = 4;
+
+  // Arnoldi step j: z_j = M^{-1} v_j, w = A z_j, Gram-Schmidt, least squares
+  auto step = [&](int j) -> int {
+    void* vj = A.at(A.V, j, tot);
+    void* zj = A.at(Zb, j, tot);
+    if (flex) {
+      const int r2 = bj_apply(ctx, *P, fo, vj, zj, A.v32, A.act.as<int>());
+      if (r2 != VIE_OK) return r2;
     }
-    if (!any) break;
-    VIE_HIP(hipMemcpyAsync(A.act.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
+    // mixed: the FP32 product reads z_j and writes w in FP32
+    EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
+    VIE_HIP(run_matvec(ctx, G, prec, zj, A.w.p, e, A.act.as<int>(), true, A.v32));
+    VIE_HIP(timed(ctx, kArnoldiKind, [&] { return arnoldi_orth(ctx, A, S, tot, m, j, eta2); }));
+    VIE_HIP(launch_ls_step(nrhs, j, A.H1.as<c64>(), A.H2.as<c64>(), eta2 > 0 ? 1 : 0, m + 1, NR,
+                           m + 1, st, half_tol, A.act.as<int>(), steps, mc, L, anyf,
                            ctx->stream));
-    VIE_HIP(launch_seg_maxpy(S, nullptr, 0, 0, 0, nullptr, nullptr, 0, r, A.npart.as<double>(), NR,
-                             m + 1, ctx->stream));
-    VIE_HIP(launch_seg_normalize(S, r, NR, m + 1, A.V.p, A.v32, ctx->stream));
-    for (int q = 0; q < nrhs; ++q) {
-      nst[q] = 0;
-      if (!act[q]) continue;
-      ls[q].reset(m, sqrt(hs[q].rnorm2));
-      mc[q] = std::min(m, maxit - steps[q]);
+    return VIE_OK;
+  };
+  std::vector<const void*> key;
+  if (use_graph) {
+    key_group(key, G);
+    key_arnoldi(key, A);
+    if (flex) {
+      key_group(key, *P->sub->groups[0]);
+      key_arnoldi(key, P->ab);
+      key_bufs(key, {&P->R, &P->X, &P->perm, &P->qoff, &P->qpoff, &P->qlen, &P->seg_rhs_dev});
+      const int64_t pv[] = {P->nseg, P->tot, P->maxlen, P->maxqlen, (int64_t)P->bound_rb.size(),
+                            fo->inner_iters, fo->inner_precision};
+      for (int64_t v : pv) key.push_back((const void*)(intptr_t)v);
     }
-    for (int j = 0; j < m; ++j) {
-      void* vj = A.at(A.V, j, tot);
-      void* zj = A.at(Zb, j, tot);
-      if (flex) {
-        rc = bj_apply(ctx, *P, fo, vj, zj, A.v32, act);
-        if (rc != VIE_OK) return rc;
+    const int64_t cv[] = {nrhs, m, prec, flex ? 1 : 0, tot, maxlen};
+    for (int64_t v : cv) key.push_back((const void*)(intptr_t)v);
+    int64_t tb = 0;
+    memcpy(&tb, &half_tol, sizeof(tb));
+    key.push_back((const void*)(intptr_t)tb);
+    key.push_back((const void*)ctx->stream);
+    if (A.chunk_key != key) {
+      A.clear_graphs();
+      A.chunk_key = key;
+    }
+  }
+  // steps j0 .. j0 + jn - 1: eager, or one replay of the chunk's graph
+  auto run_chunk = [&](int j0, int jn) -> int {
+    if (!use_graph) {
+      for (int j = j0; j < j0 + jn; ++j) {
+        const int r2 = step(j);
+        if (r2 != VIE_OK) return r2;
       }
-      EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
-      const c64* in = (const c64*)zj;
-      if (A.v32) {  // the product takes FP64 vectors
-        VIE_HIP(launch_seg_widen(S, zj, 1, A.wide.as<c64>(), ctx->stream));
-        in = A.wide.as<c64>();
+      return VIE_OK;
+    }
+    const size_t idx = (size_t)(j0 / kChunk);
+    if (A.chunk_exec.size() <= idx) A.chunk_exec.resize(idx + 1, nullptr);
+    if (!A.chunk_exec[idx]) {
+      hipGraph_t graph = nullptr;
+      VIE_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+      int r2 = VIE_OK;
+      for (int j = j0; j < j0 + jn && r2 == VIE_OK; ++j) r2 = step(j);
+      const hipError_t ee = hipStreamEndCapture(ctx->stream, &graph);
+      if (r2 != VIE_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r2;
       }
-      VIE_HIP(run_matvec(ctx, G, prec, in, A.w.as<c64>(), e, A.act.as<int>()));
-      VIE_HIP(timed(ctx, kArnoldiKind, [&] { return arnoldi_orth(ctx, A, S, tot, m, j, eta2); }));
-      VIE_HIP(hipMemcpyAsync(h1.data(), A.H1.as<c64>() + (size_t)j * nrhs * (m + 1),
-                             h1.size() * sizeof(c64), hipMemcpyDeviceToHost, ctx->stream));
-      VIE_HIP(hipMemcpyAsync(h2.data(), A.H2.as<c64>() + (size_t)j * nrhs * (m + 1),
-                             h2.size() * sizeof(c64), hipMemcpyDeviceToHost, ctx->stream));
-      VIE_HIP(hipMemcpyAsync(nr.data(), NR, nr.size() * sizeof(double), hipMemcpyDeviceToHost,
+      VIE_HIP(ee);
+      hipGraphExec_t ex = nullptr;
+      const hipError_t ie = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      VIE_HIP(ie);
+      A.chunk_exec[idx] = ex;
+    }
+    VIE_HIP(hipGraphLaunch(A.chunk_exec[idx], ctx->stream));
+    return VIE_OK;
+  };
+  for (int cycle = 0;; ++cycle) {
+    // one host wait per cycle: is any right-hand side left to iterate?
+    VIE_HIP(launch_any_notdone(nrhs, st, steps, maxit, anyf, ctx->stream));
+    VIE_HIP(hipMemcpyAsync(ctx->hflags[0], anyf, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    VIE_HIP(hipStreamSynchronize(ctx->stream));
+    if (!ctx->hflags[0][0] || cycle > maxit) break;
+    VIE_HIP(launch_ls_cycle_init(nrhs, maxit, st, A.act.as<int>(), steps, mc, cycles, L,
+                                 ctx->stream));
+    VIE_HIP(launch_seg_maxpy(S, nullptr, 0, 0, 0, nullptr, nullptr, 0, r, 0, A.npart.as<double>(), NR,
+                             m + 1, ctx->stream));
+    VIE_HIP(launch_seg_normalize(S, r, 0, NR, m + 1, A.V.p, A.v32, ctx->stream));
+    for (int j0 = 0, c = 0; j0 < m; j0 += kChunk, ++c) {
+      rc = run_chunk(j0, std::min(kChunk, m - j0));
+      if (rc != VIE_OK) return rc;
+      const int slot = c & 1;
+      VIE_HIP(hipMemcpyAsync(ctx->hflags[slot], anyf, sizeof(int), hipMemcpyDeviceToHost,
                              ctx->stream));
-      VIE_HIP(hipStreamSynchronize(ctx->stream));
-      bool more = false, changed = false;
-      for (int q = 0; q < nrhs; ++q) {
-        if (!act[q]) continue;
-        for (int i = 0; i <= j; ++i)
-          hc[i] = h1[(size_t)q * (m + 1) + i] + h2[(size_t)q * (m + 1) + i];
-        const double hn = sqrt(std::max(nr[(size_t)q * (m + 1) + j + 1], 0.0));
-        const double est = ls[q].add(j, hc.data(), hn);
-        nst[q] = j + 1;
-        steps[q] += 1;
-        if (est <= 0.5 * ctx->opt.tol * sqrt(hs[q].bnorm2) || nst[q] >= mc[q] ||
-            hn <= 1e-14 * sqrt(hs[q].rnorm2)) {
-          act[q] = 0;
-          changed = true;
-        } else {
-          more = true;
-        }
-      }
-      if (!more) break;
-      if (changed) {
-        VIE_HIP(hipMemcpyAsync(A.act.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
-                               ctx->stream));
-        VIE_HIP(hipStreamSynchronize(ctx->stream));
+      VIE_HIP(hipEventRecord(ctx->flag_ev[slot], ctx->stream));
+      if (c > 0) {  // the previous chunk's flag: stop launching once nothing is active
+        VIE_HIP(hipEventSynchronize(ctx->flag_ev[slot ^ 1]));
+        if (!ctx->hflags[slot ^ 1][0]) break;
       }
     }
     // x += Z y for every right-hand side that took steps in this cycle
-    int maxst = 0;
-    std::fill(coef.begin(), coef.end(), mk(0.0, 0.0));
-    for (int q = 0; q < nrhs; ++q) {
-      act[q] = nst[q] > 0 ? 1 : 0;
-      if (!act[q]) continue;
-      ls[q].solve(nst[q], y.data());
-      for (int i = 0; i < nst[q]; ++i) coef[(size_t)q * (m + 1) + i] = mk(0.0, 0.0) - y[i];
-      maxst = std::max(maxst, nst[q]);
-    }
-    VIE_HIP(hipMemcpyAsync(A.act.p, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
-                           ctx->stream));
-    VIE_HIP(hipMemcpyAsync(A.nvs.p, nst.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
-                           ctx->stream));
-    VIE_HIP(hipMemcpyAsync(A.coef.p, coef.data(), coef.size() * sizeof(c64), hipMemcpyHostToDevice,
-                           ctx->stream));
-    VIE_HIP(launch_seg_maxpy(S, Zb.p, A.v32, tot, maxst, A.nvs.as<int>(), A.coef.as<c64>(), m + 1, x,
-                             nullptr, nullptr, 0, ctx->stream));
+    VIE_HIP(launch_ls_solve(nrhs, L, A.coef.as<c64>(), m + 1, A.nvs.as<int>(), A.act.as<int>(),
+                            ctx->stream));
+    VIE_HIP(launch_seg_maxpy(S, Zb.p, A.v32, tot, m, A.nvs.as<int>(), A.coef.as<c64>(), m + 1, x,
+                             0, nullptr, nullptr, 0, ctx->stream));
     // true residual with the FP64 product
     EpiArgs e{EPI_RESID, rh, part, 0, pol, ph};
     VIE_HIP(run_matvec(ctx, G, 0, x, r, e, notdone));
     VIE_HIP(launch_finalize(FIN_RESTART, nrhs, e.part_blocks, part, st, flags, fp, ctx->stream));
-    for (int q = 0; q < nrhs; ++q) cycles[q] += hs[q].notdone ? 1 : 0;
-    VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
-                           ctx->stream));
-    VIE_HIP(hipStreamSynchronize(ctx->stream));
-    if (getenv("VIE_LOG"))
+    if (getenv("VIE_LOG")) {
+      std::vector<KState> hs(nrhs);
+      std::vector<int> hst(nrhs);
+      VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
+                             ctx->stream));
+      VIE_HIP(hipMemcpyAsync(hst.data(), steps, nrhs * sizeof(int), hipMemcpyDeviceToHost,
+                             ctx->stream));
+      VIE_HIP(hipStreamSynchronize(ctx->stream));
       for (int q = 0; q < nrhs; ++q)
-        fprintf(stderr, "vie: fgmres rhs %d: %d steps, true rel res %.3e\n", q, steps[q],
+        fprintf(stderr, "vie: fgmres rhs %d: %d steps, true rel res %.3e\n", q, hst[q],
                 hs[q].bnorm2 > 0 ? sqrt(hs[q].rnorm2 / hs[q].bnorm2) : 0.0);
+    }
   }
+  steps_out.assign(nrhs, 0);
+  cycles_out.assign(nrhs, 0);
+  VIE_HIP(hipMemcpyAsync(steps_out.data(), steps, nrhs * sizeof(int), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  VIE_HIP(hipMemcpyAsync(cycles_out.data(), cycles, nrhs * sizeof(int), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  VIE_HIP(hipStreamSynchronize(ctx->stream));
   return VIE_OK;
 }
 
@@ -1909,7 +1951,9 @@ extern "C" int vie_precond_apply(vie_ctx* ctx, const vie_fgmres_options* fo, con
   VIE_HIP(dz.reserve(hv.size() * sizeof(c64)));
   VIE_HIP(hipMemcpyAsync(dv.p, hv.data(), hv.size() * sizeof(c64), hipMemcpyHostToDevice,
                          ctx->stream));
-  rc = bj_apply(ctx, P, fo, dv.p, dz.p, 0, std::vector<int>(nvec, 1));
+  rc = bj_prepare(ctx, P, fo);
+  if (rc != VIE_OK) return rc;
+  rc = bj_apply(ctx, P, fo, dv.p, dz.p, 0, P.ones.as<int>());
   if (rc != VIE_OK) return rc;
   VIE_HIP(hipMemcpyAsync(hz.data(), dz.p, hz.size() * sizeof(c64), hipMemcpyDeviceToHost,
                          ctx->stream));

@@ -199,10 +199,12 @@ __device__ __forceinline__ float4 pair_out(int odd, const cpx<float>& a, const c
   return odd ? make_float4(rr, ri, own.re, own.im) : make_float4(own.re, own.im, rr, ri);
 }
 
-// FAST: the z block is 16, N3 = P/2 (every stored z is a body row) and the
-// column tiles cover P1 exactly, so the blocked offsets are shifts and no row
-// or column needs a bounds test.
-template <typename T, int P, int E, int NT, bool FAST>
+// FAST: the z block is 16, the blocked layout holds exactly P/2 rows (N3
+// rounded up to a multiple of 16 equals P/2) and the column tiles cover P1
+// exactly, so the blocked offsets are shifts and no column needs a bounds
+// test.  ZP (FAST with N3 < P/2): rows N3 .. P/2-1 of the layout are padding
+// that nothing else reads; they are loaded as zeros and written freely.
+template <typename T, int P, int E, int NT, bool FAST, bool ZP>
 __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
                                              const cpx<T>* __restrict__ spec,
                                              const cpx<T>* __restrict__ tw, const ZArgs& a,
@@ -252,9 +254,13 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
     for (int k = 0; k < E / 4; ++k) {
       const int zr = t + (2 * k + odd) * TT;  // this lane's row: point 2k (even) or 2k+1 (odd)
       const int off = 2 * ((zr >> 4) * (int)a.zhs + (zr & 15) * (int)a.zls);
-      pair_in(*reinterpret_cast<const float4*>(cp + off), odd, v0[2 * k], v0[2 * k + 1]);
-      pair_in(*reinterpret_cast<const float4*>(cp + 2 * cs + off), odd, v1[2 * k], v1[2 * k + 1]);
-      pair_in(*reinterpret_cast<const float4*>(cp + 4 * cs + off), odd, v2[2 * k], v2[2 * k + 1]);
+      float4 f0 = *reinterpret_cast<const float4*>(cp + off);
+      float4 f1 = *reinterpret_cast<const float4*>(cp + 2 * cs + off);
+      float4 f2 = *reinterpret_cast<const float4*>(cp + 4 * cs + off);
+      if (ZP && zr >= a.N3) f0 = f1 = f2 = make_float4(0.f, 0.f, 0.f, 0.f);
+      pair_in(f0, odd, v0[2 * k], v0[2 * k + 1]);
+      pair_in(f1, odd, v1[2 * k], v1[2 * k + 1]);
+      pair_in(f2, odd, v2[2 * k], v2[2 * k + 1]);
     }
 #pragma unroll
     for (int q = E / 2; q < E; ++q) v0[q] = v1[q] = v2[q] = mk<T>(0, 0);
@@ -262,7 +268,7 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int z = t + q * TT;
-      if (q < E / 2 && valid && (FAST || z < a.N3)) {
+      if (q < E / 2 && valid && ((FAST && !ZP) || z < a.N3)) {
         v0[q] = col[zoff[q]];
         v1[q] = col[cs + zoff[q]];
         v2[q] = col[2 * cs + zoff[q]];
@@ -345,11 +351,11 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
   }
 }
 
-template <typename T, int P, int E, int NT, bool FAST>
+template <typename T, int P, int E, int NT, bool FAST, bool ZP = false>
 __global__ __launch_bounds__(NT) void k_fft_z_green(
     cpx<T>* __restrict__ B, const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw,
     ZArgs a, const int* __restrict__ active) {
-  z_green_body<T, P, E, NT, FAST>(B, spec, tw, a, active);
+  z_green_body<T, P, E, NT, FAST, ZP>(B, spec, tw, a, active);
 }
 
 // ------------------------------------------------ X inverse + epilogue
@@ -530,8 +536,12 @@ static void z_launch(const GroupGeom& g, ZArgs a, cpx<T>* B, const cpx<T>* spec,
   a.tiles_x = (g.P[0] + W - 1) / W;
   const dim3 grid((g.P[1] / 2 + 1) * 2 * a.tiles_x * g.nrhs);
   if constexpr (PP >= 32) {
-    if (a.zl == 16 && 2 * a.N3 == PP && g.P[0] % W == 0) {
-      k_fft_z_green<T, PP, E, sh.nt, true><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
+    // FAST: the blocked layout holds exactly PP/2 rows (see z_green_body)
+    if (a.zl == 16 && 2 * ((a.N3 + 15) / 16) * 16 == PP && g.P[0] % W == 0) {
+      if (2 * a.N3 == PP)
+        k_fft_z_green<T, PP, E, sh.nt, true, false><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
+      else
+        k_fft_z_green<T, PP, E, sh.nt, true, true><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
       return;
     }
   }
@@ -601,15 +611,20 @@ static hipError_t x_inv(const GroupGeom& g, const cpx<T>* A, const c64* x, c64* 
 }
 
 template <typename T>
-hipError_t x_fwd_c(const GroupGeom& g, const c64* xc, cpx<T>* A, const cpx<T>* tw,
+hipError_t x_fwd_c(const GroupGeom& g, const void* xc, int in32, cpx<T>* A, const cpx<T>* tw,
                    const BodyIdx& bi, const int* active, hipStream_t s);
 template <typename T>
-hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const c64* x, c64* y, const cpx<T>* tw,
-                   const BodyIdx& bi, EpiArgs& e, const int* active, hipStream_t s);
+hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const void* x, void* y, int io32,
+                   const cpx<T>* tw, const BodyIdx& bi, EpiArgs& e, const int* active,
+                   hipStream_t s);
 
 template <typename T>
-static hipError_t matvec_t(const MatvecArgs& m, const c64* x, c64* y, EpiArgs& e, hipStream_t s,
-                           void (*cb)(int, bool, void*), void* u) {
+static hipError_t matvec_t(const MatvecArgs& m, const void* xv, void* yv, EpiArgs& e,
+                           hipStream_t s, void (*cb)(int, bool, void*), void* u) {
+  // FP32 vectors only with body-compressed FP32 passes and the plain epilogue
+  if (m.io32 && (!m.bi || sizeof(T) != 4 || e.mode != EPI_PLAIN)) return hipErrorInvalidValue;
+  const c64* x = (const c64*)xv;
+  c64* y = (c64*)yv;
   const GroupGeom& g = *m.g;
   cpx<T>* A = (cpx<T>*)m.bufA;
   cpx<T>* B = (cpx<T>*)m.bufB;
@@ -624,7 +639,7 @@ static hipError_t matvec_t(const MatvecArgs& m, const c64* x, c64* y, EpiArgs& e
   if (cb) cb(base + K, false, u);  \
   if (err != hipSuccess) return err;
   if (m.bi) {
-    STEP(0, x_fwd_c<T>(g, x, A, tw0, *m.bi, m.active, s));
+    STEP(0, x_fwd_c<T>(g, xv, m.io32, A, tw0, *m.bi, m.active, s));
   } else {
     STEP(0, x_fwd<T>(g, x, A, tw0, m.active, s));
   }
@@ -632,7 +647,7 @@ static hipError_t matvec_t(const MatvecArgs& m, const c64* x, c64* y, EpiArgs& e
   STEP(2, z_pass<T>(g, B, (const cpx<T>*)m.spec, tw2, m.active, s, m.zvar));
   STEP(3, y_pass<T>(g, B, A, tw1, true, m.active, s));
   if (m.bi) {
-    STEP(4, x_inv_c<T>(g, A, x, y, tw0, *m.bi, e, m.active, s));
+    STEP(4, x_inv_c<T>(g, A, xv, yv, m.io32, tw0, *m.bi, e, m.active, s));
   } else {
     STEP(4, x_inv<T>(g, A, x, y, m.chi, m.rhs_body, tw0, e, m.active, s));
   }
@@ -651,7 +666,7 @@ hipError_t launch_z_only(const MatvecArgs& m, int precision, hipStream_t s) {
                        m.zvar);
 }
 
-hipError_t launch_matvec(const MatvecArgs& a, int precision, const c64* x, c64* y, EpiArgs& epi,
+hipError_t launch_matvec(const MatvecArgs& a, int precision, const void* x, void* y, EpiArgs& epi,
                          hipStream_t s, void (*cb)(int, bool, void*), void* u) {
   return precision == 0 ? matvec_t<double>(a, x, y, epi, s, cb, u)
                         : matvec_t<float>(a, x, y, epi, s, cb, u);

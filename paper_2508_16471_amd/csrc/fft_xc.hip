@@ -15,9 +15,9 @@
 namespace vie {
 
 // ---------------------------------------------------------------- X forward
-template <typename T, int P>
+template <typename T, int P, typename TI>
 __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd_c(
-    const c64* __restrict__ xc, cpx<T>* __restrict__ out, const cpx<T>* __restrict__ tw,
+    const cpx<TI>* __restrict__ xc, cpx<T>* __restrict__ out, const cpx<T>* __restrict__ tw,
     BodyIdx bi, int N1, int N2, int N3, int blocks_per_rhs, const int* __restrict__ active) {
   constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), L = NT / TT,
                 LS = Pad<P>::LSTR;
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd_c(
   const int nb = bi.nb[body];
   const int* vox = bi.vox + bi.voff[body];
   const int* lp = bi.line_ptr + (int64_t)body * (lpc + 1);
-  const c64* xv = xc + bi.roff[rhs] + (int64_t)comp * nb;
+  const cpx<TI>* xv = xc + bi.roff[rhs] + (int64_t)comp * nb;
   TwReg<T, P, E> tr;
   tr.load(t, tw);
   cpx<T>* myl = lds + li * LS;
@@ -64,9 +64,9 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd_c(
 }
 
 // ------------------------------------------------ X inverse + epilogue
-template <typename T, int P, int MODE>
+template <typename T, int P, int MODE, typename TIO>
 __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv_c(
-    const cpx<T>* __restrict__ A, const c64* __restrict__ xin, c64* __restrict__ yout,
+    const cpx<T>* __restrict__ A, const cpx<TIO>* __restrict__ xin, cpx<TIO>* __restrict__ yout,
     const cpx<T>* __restrict__ tw, BodyIdx bi, int N1, int N2, int N3, int blocks_per_rhs,
     c64* __restrict__ aux, c64* __restrict__ partials, const c64* __restrict__ pol,
     const c64* __restrict__ ph, const int* __restrict__ active) {
@@ -123,16 +123,16 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv_c(
       const c64 conv = cvt<double>(myl[pidx(xi)]);
       const double c = chic[k];
       const int64_t gi = vb + k;
-      const c64 xv = xin[gi];
+      const c64 xv = cvt<double>(xin[gi]);
       const c64 y = xv - c * conv;
       if (MODE == EPI_RESID) {
         const c64 e = pc * (phyz * phr[xi]);
         const c64 r = c * e - y;
-        yout[gi] = r;
+        yout[gi] = cvt<TIO>(r);
         aux[gi] = r;
         s1.re += r.re * r.re + r.im * r.im;
       } else {
-        yout[gi] = y;
+        yout[gi] = cvt<TIO>(y);
         if (MODE == EPI_RHV) {
           s0 = s0 + cmulc(aux[gi], y);
         } else if (MODE == EPI_TS) {
@@ -154,29 +154,42 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv_c(
 
 // ================================================================ launchers
 template <typename T>
-hipError_t x_fwd_c(const GroupGeom& g, const c64* xc, cpx<T>* A, const cpx<T>* tw,
+hipError_t x_fwd_c(const GroupGeom& g, const void* xc, int in32, cpx<T>* A, const cpx<T>* tw,
                    const BodyIdx& bi, const int* active, hipStream_t s) {
   const int lines = 3 * g.N[1] * g.N[2];
   const int L = lines_per_block<T>(g.P[0]);
   const int bpr = (lines + L - 1) / L;
   const dim3 grid(bpr * g.nrhs);
-  VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd_c<T, PP><<<grid, nt_lines<T>(), 0, s>>>(
-                             xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active)));
+  if (in32) {
+    VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd_c<T, PP, float><<<grid, nt_lines<T>(), 0, s>>>(
+                               (const c32*)xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active)));
+  } else {
+    VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd_c<T, PP, double><<<grid, nt_lines<T>(), 0, s>>>(
+                               (const c64*)xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active)));
+  }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const c64* x, c64* y, const cpx<T>* tw,
-                   const BodyIdx& bi, EpiArgs& e, const int* active, hipStream_t s) {
+hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const void* x, void* y, int io32,
+                   const cpx<T>* tw, const BodyIdx& bi, EpiArgs& e, const int* active,
+                   hipStream_t s) {
   const int lines = 3 * g.N[1] * g.N[2];
   const int L = lines_per_block<T>(g.P[0]);
   const int bpr = (lines + L - 1) / L;
   e.part_blocks = bpr;
   const dim3 grid(bpr * g.nrhs);
+  if (io32) {  // FP32 vectors: the plain product only
+    if (e.mode != EPI_PLAIN) return hipErrorInvalidValue;
+    VIE_DISPATCH_P(g.P[0], (k_fft_x_inv_c<T, PP, EPI_PLAIN, float><<<grid, nt_lines<T>(), 0, s>>>(
+                               A, (const c32*)x, (c32*)y, tw, bi, g.N[0], g.N[1], g.N[2], bpr,
+                               e.aux, e.partials, e.pol, e.ph, active)));
+    return hipGetLastError();
+  }
 #define VIE_XINVC(MODE_)                                                                      \
-  VIE_DISPATCH_P(g.P[0], (k_fft_x_inv_c<T, PP, MODE_><<<grid, nt_lines<T>(), 0, s>>>(           \
-                             A, x, y, tw, bi, g.N[0], g.N[1], g.N[2], bpr, e.aux, e.partials, \
-                             e.pol, e.ph, active)))
+  VIE_DISPATCH_P(g.P[0], (k_fft_x_inv_c<T, PP, MODE_, double><<<grid, nt_lines<T>(), 0, s>>>(   \
+                             A, (const c64*)x, (c64*)y, tw, bi, g.N[0], g.N[1], g.N[2], bpr,  \
+                             e.aux, e.partials, e.pol, e.ph, active)))
   switch (e.mode) {
     case EPI_PLAIN: VIE_XINVC(EPI_PLAIN); break;
     case EPI_RHV: VIE_XINVC(EPI_RHV); break;
@@ -188,13 +201,13 @@ hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const c64* x, c64* y, co
   return hipGetLastError();
 }
 
-template hipError_t x_fwd_c<double>(const GroupGeom&, const c64*, c64*, const c64*,
+template hipError_t x_fwd_c<double>(const GroupGeom&, const void*, int, c64*, const c64*,
                                     const BodyIdx&, const int*, hipStream_t);
-template hipError_t x_fwd_c<float>(const GroupGeom&, const c64*, c32*, const c32*,
+template hipError_t x_fwd_c<float>(const GroupGeom&, const void*, int, c32*, const c32*,
                                    const BodyIdx&, const int*, hipStream_t);
-template hipError_t x_inv_c<double>(const GroupGeom&, const c64*, const c64*, c64*, const c64*,
-                                    const BodyIdx&, EpiArgs&, const int*, hipStream_t);
-template hipError_t x_inv_c<float>(const GroupGeom&, const c32*, const c64*, c64*, const c32*,
-                                   const BodyIdx&, EpiArgs&, const int*, hipStream_t);
+template hipError_t x_inv_c<double>(const GroupGeom&, const c64*, const void*, void*, int,
+                                    const c64*, const BodyIdx&, EpiArgs&, const int*, hipStream_t);
+template hipError_t x_inv_c<float>(const GroupGeom&, const c32*, const void*, void*, int,
+                                   const c32*, const BodyIdx&, EpiArgs&, const int*, hipStream_t);
 
 }  // namespace vie

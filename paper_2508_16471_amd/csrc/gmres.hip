@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "gmres.h"
+#include "kernels.h"
 
 namespace vie {
 
@@ -25,10 +26,10 @@ __device__ __forceinline__ c64 ld64(const c32* p) { return cvt<double>(*p); }
 __device__ __forceinline__ void st(c64* p, c64 v) { *p = v; }
 __device__ __forceinline__ void st(c32* p, c64 v) { *p = cvt<float>(v); }
 
-template <typename TV>
+template <typename TV, typename TW>
 __global__ __launch_bounds__(GT) void k_seg_mdot(SegSet S, const TV* __restrict__ V,
                                                  int64_t stride, int nv,
-                                                 const c64* __restrict__ w,
+                                                 const TW* __restrict__ w,
                                                  c64* __restrict__ partials) {
   const int s = blockIdx.y, blk = blockIdx.x;
   if (S.active && !S.active[s]) return;
@@ -41,7 +42,7 @@ __global__ __launch_bounds__(GT) void k_seg_mdot(SegSet S, const TV* __restrict_
 #pragma unroll
     for (int u = 0; u < GU; ++u) acc[u] = mk(0.0, 0.0);
     for (int e = blk * GT + threadIdx.x; e < len; e += S.nblk * GT) {
-      const c64 we = w[off + e];
+      const c64 we = ld64(w + off + e);
 #pragma unroll
       for (int u = 0; u < GU; ++u)
         if (i0 + u < nv) acc[u] = acc[u] + cmulc(ld64(V + (int64_t)(i0 + u) * stride + off + e), we);
@@ -77,12 +78,12 @@ __global__ __launch_bounds__(64) void k_seg_sum_c(SegSet S, int nv,
   if (threadIdx.x == 0) out[(int64_t)s * ldo + i] = t;
 }
 
-template <typename TV>
+template <typename TV, typename TW>
 __global__ __launch_bounds__(GT) void k_seg_maxpy(SegSet S, const TV* __restrict__ V,
                                                   int64_t stride, int nv,
                                                   const int* __restrict__ nv_seg,
                                                   const c64* __restrict__ coef, int ldc,
-                                                  c64* __restrict__ w,
+                                                  TW* __restrict__ w,
                                                   double* __restrict__ partials) {
   const int s = blockIdx.y, blk = blockIdx.x;
   if (S.active && !S.active[s]) return;
@@ -96,9 +97,12 @@ __global__ __launch_bounds__(GT) void k_seg_maxpy(SegSet S, const TV* __restrict
   __syncthreads();
   double nr = 0.0;
   for (int e = blk * GT + threadIdx.x; e < len; e += S.nblk * GT) {
-    c64 a = w[off + e];
+    c64 a = ld64(w + off + e);
     for (int i = 0; i < n; ++i) a = a - cf[i] * ld64(V + (int64_t)i * stride + off + e);
-    if (n > 0) w[off + e] = a;
+    if (n > 0) {
+      st(w + off + e, a);
+      a = ld64(w + off + e);  // the norm of what is stored (rounded when w is FP32)
+    }
     nr += a.re * a.re + a.im * a.im;
   }
   if (!partials) return;
@@ -131,8 +135,8 @@ __global__ void k_seg_reorth_flags(SegSet S, const double* __restrict__ before,
   act2[s] = (on && eta2 > 0.0 && after[(int64_t)s * ldn] < eta2 * before[s]) ? 1 : 0;
 }
 
-template <typename TD>
-__global__ __launch_bounds__(GT) void k_seg_normalize(SegSet S, const c64* __restrict__ src,
+template <typename TS, typename TD>
+__global__ __launch_bounds__(GT) void k_seg_normalize(SegSet S, const TS* __restrict__ src,
                                                       const double* __restrict__ norm2, int ldn,
                                                       TD* __restrict__ dst) {
   const int s = blockIdx.y, blk = blockIdx.x;
@@ -141,17 +145,36 @@ __global__ __launch_bounds__(GT) void k_seg_normalize(SegSet S, const c64* __res
   const int len = S.len[s];
   const double n2 = norm2[(int64_t)s * ldn];
   const double sc = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
-  for (int e = blk * GT + threadIdx.x; e < len; e += S.nblk * GT) st(dst + off + e, sc * src[off + e]);
+  for (int e = blk * GT + threadIdx.x; e < len; e += S.nblk * GT)
+    st(dst + off + e, sc * ld64(src + off + e));
 }
 
-template <typename TS>
-__global__ __launch_bounds__(GT) void k_seg_widen(SegSet S, const TS* __restrict__ src,
-                                                  c64* __restrict__ dst) {
+template <typename TV>
+__global__ __launch_bounds__(GT) void k_seg_lincomb(SegSet S, const TV* __restrict__ V,
+                                                    int64_t stride, int nv,
+                                                    const int* __restrict__ nv_seg,
+                                                    const c64* __restrict__ coef, int ldc,
+                                                    c64* __restrict__ x) {
   const int s = blockIdx.y, blk = blockIdx.x;
   if (S.active && !S.active[s]) return;
   const int64_t off = S.off[s];
   const int len = S.len[s];
-  for (int e = blk * GT + threadIdx.x; e < len; e += S.nblk * GT) dst[off + e] = ld64(src + off + e);
+  int n = nv;
+  if (nv_seg) n = min(n, nv_seg[s]);
+  __shared__ c64 cf[kMaxVec];
+  for (int i = threadIdx.x; i < n; i += GT) cf[i] = coef[(int64_t)s * ldc + i];
+  __syncthreads();
+  for (int e = blk * GT + threadIdx.x; e < len; e += S.nblk * GT) {
+    c64 a = mk(0.0, 0.0);
+    for (int i = 0; i < n; ++i) a = a - cf[i] * ld64(V + (int64_t)i * stride + off + e);
+    x[off + e] = a;
+  }
+}
+
+__global__ void k_seg_act_map(int nseg, const int* __restrict__ seg_rhs,
+                              const int* __restrict__ act_rhs, int* __restrict__ act_seg) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nseg) act_seg[s] = act_rhs[seg_rhs[s]] ? 1 : 0;
 }
 
 template <typename TS, typename TD>
@@ -160,8 +183,10 @@ __global__ __launch_bounds__(GT) void k_permute(const int64_t* __restrict__ qoff
                                                 const int* __restrict__ qlen,
                                                 const int* __restrict__ perm,
                                                 const TS* __restrict__ src,
-                                                TD* __restrict__ dst, int scatter) {
+                                                TD* __restrict__ dst, int scatter,
+                                                const int* __restrict__ act) {
   const int q = blockIdx.y;
+  if (act && !act[q]) return;
   const int64_t base = qoff[q];
   const int* pm = perm + qpoff[q];
   const int n = qlen[q];
@@ -174,6 +199,149 @@ __global__ __launch_bounds__(GT) void k_permute(const int64_t* __restrict__ qoff
   }
 }
 
+// ------------------------------------------------ GMRES least squares
+__device__ __forceinline__ c64 conjc(c64 a) { return mk(a.re, -a.im); }
+__device__ __forceinline__ double cabs2(c64 a) { return hypot(a.re, a.im); }
+
+// Apply the previous j rotations to column j (col[0..j]), form the rotation
+// that annihilates the subdiagonal hn, update g; returns |g[j+1]|.
+__device__ double ls_add(int j, c64* col, double* cs, c64* sn, c64* g, double hn) {
+  for (int i = 0; i < j; ++i) {
+    const c64 a = col[i], b = col[i + 1];
+    col[i] = cs[i] * a + sn[i] * b;
+    col[i + 1] = cs[i] * b - conjc(sn[i]) * a;
+  }
+  const c64 a = col[j];
+  const double aa = cabs2(a);
+  const double rho = hypot(aa, hn);
+  double c;
+  c64 sv;
+  if (rho == 0.0) {
+    c = 1.0;
+    sv = mk(0.0, 0.0);
+  } else if (aa == 0.0) {
+    c = 0.0;
+    sv = mk(1.0, 0.0);
+  } else {
+    c = aa / rho;
+    sv = mk(a.re / aa * hn / rho, a.im / aa * hn / rho);  // (a / |a|) hn / rho
+  }
+  cs[j] = c;
+  sn[j] = sv;
+  col[j] = c * a + hn * sv;
+  const c64 gj = g[j];
+  g[j] = c * gj;
+  g[j + 1] = mk(0.0, 0.0) - conjc(sv) * gj;
+  return cabs2(g[j + 1]);
+}
+
+// y[0..k) from R y = g (columns of R at stride ldr), written as -y into out.
+__device__ void ls_backsolve(int k, const c64* R, int ldr, const c64* g, c64* out) {
+  for (int i = k - 1; i >= 0; --i) {
+    c64 t = g[i];
+    for (int l = i + 1; l < k; ++l) t = t + R[(size_t)l * ldr + i] * out[l];  // out = -y
+    const c64 d = R[(size_t)i * ldr + i];
+    const double dd = d.re * d.re + d.im * d.im;
+    const c64 y = dd > 0 ? (1.0 / dd) * cmulc(d, t) : mk(0.0, 0.0);
+    out[i] = mk(-y.re, -y.im);
+  }
+}
+
+__global__ void k_ls_cycle_init(int nseg, int maxit, const KState* __restrict__ st,
+                                int* __restrict__ act, int* __restrict__ steps,
+                                int* __restrict__ mc, int* __restrict__ cycles, LsBufs L) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nseg) return;
+  const int nd = st[q].notdone;
+  act[q] = (nd && steps[q] < maxit) ? 1 : 0;
+  if (nd) cycles[q] += 1;
+  L.nst[q] = 0;
+  mc[q] = min(L.m, maxit - steps[q]);
+  L.g[(size_t)q * L.ldr] = mk(sqrt(fmax(st[q].rnorm2, 0.0)), 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_ls_step(int nseg, int j, const c64* __restrict__ H1,
+                                                 const c64* __restrict__ H2, int use_h2, int ldh,
+                                                 const double* __restrict__ NR, int ldn,
+                                                 const KState* __restrict__ st, double half_tol,
+                                                 int* __restrict__ act, int* __restrict__ steps,
+                                                 const int* __restrict__ mc, LsBufs L,
+                                                 int* __restrict__ any) {
+  int live = 0;
+  for (int q = threadIdx.x; q < nseg; q += blockDim.x) {
+    if (!act[q]) continue;
+    c64* col = L.R + ((size_t)q * L.m + j) * L.ldr;
+    const c64* h1 = H1 + ((size_t)j * nseg + q) * ldh;
+    const c64* h2 = H2 + ((size_t)j * nseg + q) * ldh;
+    for (int i = 0; i <= j; ++i) col[i] = use_h2 ? h1[i] + h2[i] : h1[i];
+    const double hn = sqrt(fmax(NR[(size_t)q * ldn + j + 1], 0.0));
+    const double est = ls_add(j, col, L.cs + (size_t)q * L.m, L.sn + (size_t)q * L.m,
+                              L.g + (size_t)q * L.ldr, hn);
+    L.nst[q] = j + 1;
+    steps[q] += 1;
+    const bool stop = est <= half_tol * sqrt(fmax(st[q].bnorm2, 0.0)) || j + 1 >= mc[q] ||
+                      hn <= 1e-14 * sqrt(fmax(st[q].rnorm2, 0.0));
+    if (stop)
+      act[q] = 0;
+    else
+      live = 1;
+  }
+  live = __syncthreads_or(live);
+  if (threadIdx.x == 0) any[0] = live;
+}
+
+__global__ void k_ls_solve(int nseg, LsBufs L, c64* __restrict__ coef, int ldc,
+                           int* __restrict__ nvs, int* __restrict__ act) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nseg) return;
+  const int n = L.nst[q];
+  nvs[q] = n;
+  act[q] = n > 0 ? 1 : 0;
+  if (n > 0)
+    ls_backsolve(n, L.R + (size_t)q * L.m * L.ldr, L.ldr, L.g + (size_t)q * L.ldr,
+                 coef + (size_t)q * ldc);
+}
+
+__global__ void k_ls_full(int nseg, int k, const c64* __restrict__ H1, const c64* __restrict__ H2,
+                          int use_h2, int ldh, const double* __restrict__ NR, int ldn,
+                          const int* __restrict__ act, LsBufs L, c64* __restrict__ coef, int ldc,
+                          int* __restrict__ nvs) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  nvs[s] = 0;
+  if (!act[s]) return;
+  const double beta = sqrt(fmax(NR[(size_t)s * ldn], 0.0));
+  if (!(beta > 0)) return;
+  c64* R = L.R + (size_t)s * L.m * L.ldr;
+  c64* g = L.g + (size_t)s * L.ldr;
+  double* cs = L.cs + (size_t)s * L.m;
+  c64* sn = L.sn + (size_t)s * L.m;
+  g[0] = mk(beta, 0.0);
+  int steps = 0;
+  for (int j = 0; j < k; ++j) {
+    c64* col = R + (size_t)j * L.ldr;
+    const c64* h1 = H1 + ((size_t)j * nseg + s) * ldh;
+    const c64* h2 = H2 + ((size_t)j * nseg + s) * ldh;
+    for (int i = 0; i <= j; ++i) col[i] = use_h2 ? h1[i] + h2[i] : h1[i];
+    const double hn = sqrt(fmax(NR[(size_t)s * ldn + j + 1], 0.0));
+    ls_add(j, col, cs, sn, g, hn);
+    steps = j + 1;
+    if (hn <= 1e-14 * beta) break;
+  }
+  ls_backsolve(steps, R, L.ldr, g, coef + (size_t)s * ldc);
+  nvs[s] = steps;
+}
+
+__global__ __launch_bounds__(256) void k_any_notdone(int n, const KState* __restrict__ st,
+                                                     const int* __restrict__ steps, int maxit,
+                                                     int* __restrict__ any) {
+  int live = 0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x)
+    if (st[q].notdone && steps[q] < maxit) live = 1;
+  live = __syncthreads_or(live);
+  if (threadIdx.x == 0) any[0] = live;
+}
+
 }  // namespace
 
 int seg_blocks(int64_t max_len) {
@@ -182,28 +350,37 @@ int seg_blocks(int64_t max_len) {
 }
 
 hipError_t launch_seg_mdot(const SegSet& S, const void* V, int v32, int64_t stride, int nv,
-                           const c64* w, c64* partials, c64* out, int ldo, hipStream_t st) {
+                           const void* w, int w32, c64* partials, c64* out, int ldo,
+                           hipStream_t st) {
   if (S.nseg < 1 || nv < 1) return hipSuccess;
-  if (v32)
-    k_seg_mdot<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c32*)V, stride, nv, w, partials);
+  const dim3 grid(S.nblk, S.nseg);
+  if (v32 && w32)
+    k_seg_mdot<<<grid, GT, 0, st>>>(S, (const c32*)V, stride, nv, (const c32*)w, partials);
+  else if (v32)
+    k_seg_mdot<<<grid, GT, 0, st>>>(S, (const c32*)V, stride, nv, (const c64*)w, partials);
+  else if (w32)
+    k_seg_mdot<<<grid, GT, 0, st>>>(S, (const c64*)V, stride, nv, (const c32*)w, partials);
   else
-    k_seg_mdot<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c64*)V, stride, nv, w, partials);
+    k_seg_mdot<<<grid, GT, 0, st>>>(S, (const c64*)V, stride, nv, (const c64*)w, partials);
   k_seg_sum_c<<<dim3(nv, S.nseg), 64, 0, st>>>(S, nv, partials, out, ldo);
   return hipGetLastError();
 }
 
 hipError_t launch_seg_maxpy(const SegSet& S, const void* V, int v32, int64_t stride, int nv,
-                            const int* nv_seg, const c64* coef, int ldc, c64* w,
+                            const int* nv_seg, const c64* coef, int ldc, void* w, int w32,
                             double* partials, double* norm2, int ldn, hipStream_t st) {
   if (S.nseg < 1) return hipSuccess;
   if (nv < 0 || nv > kMaxVec) return hipErrorInvalidValue;
   double* pn = norm2 ? partials : nullptr;
-  if (v32)
-    k_seg_maxpy<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c32*)V, stride, nv, nv_seg, coef,
-                                                     ldc, w, pn);
+  const dim3 grid(S.nblk, S.nseg);
+  if (v32 && w32)
+    k_seg_maxpy<<<grid, GT, 0, st>>>(S, (const c32*)V, stride, nv, nv_seg, coef, ldc, (c32*)w, pn);
+  else if (v32)
+    k_seg_maxpy<<<grid, GT, 0, st>>>(S, (const c32*)V, stride, nv, nv_seg, coef, ldc, (c64*)w, pn);
+  else if (w32)
+    k_seg_maxpy<<<grid, GT, 0, st>>>(S, (const c64*)V, stride, nv, nv_seg, coef, ldc, (c32*)w, pn);
   else
-    k_seg_maxpy<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c64*)V, stride, nv, nv_seg, coef,
-                                                     ldc, w, pn);
+    k_seg_maxpy<<<grid, GT, 0, st>>>(S, (const c64*)V, stride, nv, nv_seg, coef, ldc, (c64*)w, pn);
   if (norm2) k_seg_sum_r<<<S.nseg, 64, 0, st>>>(S, partials, norm2, ldn);
   return hipGetLastError();
 }
@@ -215,38 +392,96 @@ hipError_t launch_seg_reorth_flags(const SegSet& S, const double* before, const 
   return hipGetLastError();
 }
 
-hipError_t launch_seg_normalize(const SegSet& S, const c64* src, const double* norm2, int ldn,
-                                void* dst, int d32, hipStream_t st) {
+hipError_t launch_seg_normalize(const SegSet& S, const void* src, int s32, const double* norm2,
+                                int ldn, void* dst, int d32, hipStream_t st) {
   if (S.nseg < 1) return hipSuccess;
-  if (d32)
-    k_seg_normalize<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, src, norm2, ldn, (c32*)dst);
+  const dim3 grid(S.nblk, S.nseg);
+  if (s32 && d32)
+    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c32*)src, norm2, ldn, (c32*)dst);
+  else if (s32)
+    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c32*)src, norm2, ldn, (c64*)dst);
+  else if (d32)
+    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c64*)src, norm2, ldn, (c32*)dst);
   else
-    k_seg_normalize<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, src, norm2, ldn, (c64*)dst);
-  return hipGetLastError();
-}
-
-hipError_t launch_seg_widen(const SegSet& S, const void* src, int s32, c64* dst, hipStream_t st) {
-  if (S.nseg < 1) return hipSuccess;
-  if (s32)
-    k_seg_widen<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c32*)src, dst);
-  else
-    k_seg_widen<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c64*)src, dst);
+    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c64*)src, norm2, ldn, (c64*)dst);
   return hipGetLastError();
 }
 
 hipError_t launch_permute(int nrep, const int64_t* qoff, const int64_t* qpoff, const int* qlen,
                           int maxlen, const int* perm, const void* src, int s32, void* dst,
-                          int d32, int scatter, hipStream_t st) {
+                          int d32, int scatter, const int* act, hipStream_t st) {
   if (nrep < 1 || maxlen < 1) return hipSuccess;
   const dim3 grid(std::min((maxlen + GT - 1) / GT, 4096), nrep);
   if (s32 && d32)
-    k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c32*)src, (c32*)dst, scatter);
+    k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c32*)src, (c32*)dst, scatter, act);
   else if (s32)
-    k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c32*)src, (c64*)dst, scatter);
+    k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c32*)src, (c64*)dst, scatter, act);
   else if (d32)
-    k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c64*)src, (c32*)dst, scatter);
+    k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c64*)src, (c32*)dst, scatter, act);
   else
-    k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c64*)src, (c64*)dst, scatter);
+    k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c64*)src, (c64*)dst, scatter, act);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_lincomb(const SegSet& S, const void* V, int v32, int64_t stride, int nv,
+                              const int* nv_seg, const c64* coef, int ldc, c64* x,
+                              hipStream_t st) {
+  if (S.nseg < 1) return hipSuccess;
+  if (nv < 0 || nv > kMaxVec) return hipErrorInvalidValue;
+  if (v32)
+    k_seg_lincomb<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c32*)V, stride, nv, nv_seg, coef,
+                                                       ldc, x);
+  else
+    k_seg_lincomb<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c64*)V, stride, nv, nv_seg, coef,
+                                                       ldc, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_act_map(int nseg, const int* seg_rhs, const int* act_rhs, int* act_seg,
+                              hipStream_t st) {
+  if (nseg < 1) return hipSuccess;
+  k_seg_act_map<<<(nseg + 255) / 256, 256, 0, st>>>(nseg, seg_rhs, act_rhs, act_seg);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_cycle_init(int nseg, int maxit, const KState* st, int* act, int* steps,
+                                int* mc, int* cycles, const LsBufs& L, hipStream_t s) {
+  if (nseg < 1) return hipSuccess;
+  k_ls_cycle_init<<<(nseg + 255) / 256, 256, 0, s>>>(nseg, maxit, st, act, steps, mc, cycles, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_step(int nseg, int j, const c64* H1, const c64* H2, int use_h2, int ldh,
+                          const double* NR, int ldn, const KState* st, double half_tol,
+                          int* act, int* steps, const int* mc, const LsBufs& L, int* any,
+                          hipStream_t s) {
+  if (nseg < 1) return hipSuccess;
+  if (j < 0 || j >= L.m) return hipErrorInvalidValue;
+  k_ls_step<<<1, 256, 0, s>>>(nseg, j, H1, H2, use_h2, ldh, NR, ldn, st, half_tol, act, steps, mc,
+                              L, any);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_solve(int nseg, const LsBufs& L, c64* coef, int ldc, int* nvs, int* act,
+                           hipStream_t s) {
+  if (nseg < 1) return hipSuccess;
+  k_ls_solve<<<(nseg + 63) / 64, 64, 0, s>>>(nseg, L, coef, ldc, nvs, act);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_full(int nseg, int k, const c64* H1, const c64* H2, int use_h2, int ldh,
+                          const double* NR, int ldn, const int* act, const LsBufs& L, c64* coef,
+                          int ldc, int* nvs, hipStream_t s) {
+  if (nseg < 1) return hipSuccess;
+  if (k < 1 || k > L.m) return hipErrorInvalidValue;
+  k_ls_full<<<(nseg + 63) / 64, 64, 0, s>>>(nseg, k, H1, H2, use_h2, ldh, NR, ldn, act, L, coef,
+                                             ldc, nvs);
+  return hipGetLastError();
+}
+
+hipError_t launch_any_notdone(int n, const KState* st, const int* steps, int maxit, int* any,
+                              hipStream_t s) {
+  k_any_notdone<<<1, 256, 0, s>>>(n, st, steps, maxit, any);
   return hipGetLastError();
 }
 

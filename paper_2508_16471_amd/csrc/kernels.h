@@ -67,6 +67,7 @@ struct MatvecArgs {
   const int* active;       // [nrhs] or nullptr
   int zvar = 0;            // launch shape of the z pass (autotuned per group/precision)
   const BodyIdx* bi = nullptr;  // non-null: x and y are body-compressed
+  int io32 = 0;  // compressed x and y stored in FP32 (FP32 passes, plain epilogue only)
 };
 
 // precision 0: FP64 passes, 1: FP32 passes (input/output vectors are FP64)
@@ -86,7 +87,8 @@ int z_block(const GroupGeom& g);        // z planes kept adjacent in the y/z scr
 int64_t bufB_elems(const GroupGeom& g);  // y/z scratch elements per right-hand side
 int vec_blocks(const GroupGeom& g);
 
-hipError_t launch_matvec(const MatvecArgs& a, int precision, const c64* x, c64* y, EpiArgs& epi,
+// x, y: c64 vectors, or c32 when a.io32.
+hipError_t launch_matvec(const MatvecArgs& a, int precision, const void* x, void* y, EpiArgs& epi,
                          hipStream_t s, void (*ev_cb)(int kind, bool begin, void* u), void* u);
 int z_variants(int precision);  // z-pass launch shapes (0 = FP64, 1 = FP32)
 // z pass alone on bufB (autotuning; contents are scratch)

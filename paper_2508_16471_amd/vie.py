@@ -102,6 +102,7 @@ def lib():
             "vie_matvec_dev_static": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                                 C.c_void_p, C.c_int32]),
             "vie_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+            "vie_hbm_probe": (C.c_int, [C.c_int64, C.c_int32, P(C.c_double)]),
             "vie_kernel_times": (C.c_int, [C.c_void_p, P(C.c_char_p), P(C.c_double), P(C.c_int64),
                                            P(C.c_int32), C.c_int32]),
             "vie_set_options": (C.c_int, [C.c_void_p, P(vie_options)]),
@@ -311,6 +312,13 @@ def vie_matvec_dev_static(ctx, body, x_ptr, y_ptr, nvec, precision=VIE_FP64):
     (allocates nothing); raises VieError(VIE_ENOTSUP) beyond that array's size."""
     _check(lib().vie_matvec_dev_static(ctx, int(body), int(precision), C.c_void_p(x_ptr),
                                        C.c_void_p(y_ptr), int(nvec)), "vie_matvec_dev_static")
+
+
+def vie_hbm_probe(nbytes=4 << 30, reps=10):
+    """Achievable HBM bandwidth (GB/s): dict(read=, write=, copy=)."""
+    g = np.zeros(3)
+    _check(lib().vie_hbm_probe(int(nbytes), int(reps), _dptr(g)), "vie_hbm_probe")
+    return {"read": float(g[0]), "write": float(g[1]), "copy": float(g[2])}
 
 
 def vie_set_stream(ctx, stream_ptr):

@@ -1,7 +1,7 @@
-"""Captured-graph execution of the BiCGSTAB iterations equals eager
-execution bit for bit (same kernels, same order, same device state), over
-repeated solves on one context with eager work in between, for mixed sizes
-and both precisions.  The z-pass shape is pinned (VIE_ZVAR) on both sides:
+"""Captured-graph execution of the BiCGSTAB iterations and of the FGMRES step
+chunks equals eager execution bit for bit (same kernels, same order, same
+device state), over repeated solves on one context with eager work in
+between, for mixed sizes and both precisions.  The z-pass shape is pinned (VIE_ZVAR) on both sides:
 the autotuner picks by timing, and two shapes round differently."""
 
 import numpy as np
@@ -91,4 +91,44 @@ def test_graph_replay_equals_eager(V, precision, pinned_zvar):
             assert np.array_equal(a, b)
         assert np.array_equal(fe, fg)
     # repeated identical solves on one context agree with each other too
+    assert all(np.array_equal(a, b) for a, b in zip(res[0][0][0], res[0][1][0]))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fgmres_chunk_graphs_equal_eager(V, precision, pinned_zvar):
+    """Block-Jacobi FGMRES with its step chunks replayed from captured graphs
+    equals eager launches bit for bit: restart 10 (chunks of 4, 4 and 2
+    steps, several cycles), two grid groups, repeated solves with eager work
+    between, a changed tolerance and a changed channel count (new captures)."""
+    bodies = _bodies()
+    chans = _chans(8)
+    plans = [([2, 1, 3, 2], 1e-9), ([2, 1, 3, 2], 1e-9), ([2, 1, 3, 2], 1e-7), ([1, 2, 1, 1], 1e-9)]
+    fo = V.fgmres_options(10, (2, 2), 3, V.VIE_MIXED if precision else V.VIE_FP64)
+    res = {}
+    for flags in (V.VIE_FLAG_NO_GRAPH, 0):
+        ctx = V.vie_setup([(e, g.h, g.origin) for e, g in bodies],
+                          V.make_options(K0, precision=precision, tol=1e-9, max_iter=4000,
+                                         flags=flags))
+        try:
+            runs = []
+            for nr, tol in plans:
+                V.vie_set_options(ctx, V.make_options(K0, precision=precision, tol=tol,
+                                                      max_iter=4000, flags=flags))
+                rc, st = V.vie_solve_fgmres(ctx, chans[:sum(nr)], nr, fo)
+                assert rc == 0
+                w = [V.vie_get_current(ctx, b, q, g.n) for b, (_, g) in enumerate(bodies)
+                     for q in range(nr[b])]
+                F = V.vie_farfield(ctx, 2, [0.3, 1.2], [0.0, 2.0], nr[2])  # eager work between
+                runs.append((w, [(s["iters"], s["cycles"], s["converged"]) for s in st], F))
+            res[flags] = runs
+        finally:
+            V.vie_destroy(ctx)
+    for rep in range(len(plans)):
+        we, se, fe = res[V.VIE_FLAG_NO_GRAPH][rep]
+        wg, sg, fg = res[0][rep]
+        print("fgmres rep", rep, "eager", se, "graph", sg)
+        assert se == sg
+        for a, b in zip(we, wg):
+            assert np.array_equal(a, b)
+        assert np.array_equal(fe, fg)
     assert all(np.array_equal(a, b) for a, b in zip(res[0][0][0], res[0][1][0]))
