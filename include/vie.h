@@ -86,7 +86,8 @@ enum { VIE_GRAPH_ITERS = 8 };
 
 /* One body on its own uniform grid (eq. 24's volume V, discretised). */
 typedef struct {
-  int32_t n[3];        /* voxels per axis, each 1..256                          */
+  int32_t n[3];        /* voxels per axis: N1, N2 in 1..3072, N3 in 1..256,      */
+                       /* N1 N2 N3 < 2^31                                       */
   double h;            /* voxel edge > 0                                        */
   double origin[3];    /* centre of voxel (0,0,0)                               */
   const double *eps_r; /* host, N1*N2*N3 relative permittivities, x fastest,   */
@@ -128,7 +129,9 @@ typedef struct {
  * the device, builds the FP64 (and FP32) octant spectrum of the circulant
  * embedding of Ghat for each distinct (grid, h, k0), allocates Krylov and FFT
  * workspaces.  Returns VIE_EINVAL on bad shapes/values, VIE_ENOTSUP if a
- * grid exceeds 256 per axis. */
+ * grid exceeds the limits of vie_body.n (FFT lines of up to 6144 points
+ * along x and y, 512 along z) or one component of the y/z scratch would
+ * exceed 2^31 elements. */
 int vie_setup(const vie_body *bodies, int32_t n_bodies, const vie_options *opt,
               vie_ctx **out);
 

@@ -52,6 +52,8 @@ struct DevBuf {
   }
 };
 
+constexpr int kMaxNxy = 3072, kMaxNz = 256;  // voxels per axis (FFT lines 6144 / 512)
+
 // Circulant length of an axis with n voxels: the smallest supported FFT
 // length (2^k >= 8, or 3 * 2^k >= 12) that holds every displacement,
 // P >= 2n - 1.
@@ -400,10 +402,12 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
     if (!B.eps_r || !(B.h > 0) || !isfinite(B.h)) return VIE_EINVAL;
     for (int a = 0; a < 3; ++a) {
       if (B.n[a] < 1) return VIE_EINVAL;
-      if (B.n[a] > 256) return VIE_ENOTSUP;
       if (!isfinite(B.origin[a])) return VIE_EINVAL;
     }
+    // x and y lines up to 6144 points (3072 voxels), z lines up to 512 (256)
+    if (B.n[0] > kMaxNxy || B.n[1] > kMaxNxy || B.n[2] > kMaxNz) return VIE_ENOTSUP;
     const int64_t n = (int64_t)B.n[0] * B.n[1] * B.n[2];
+    if (n >= ((int64_t)1 << 31)) return VIE_ENOTSUP;  // voxel indices are 32-bit
     for (int64_t i = 0; i < n; ++i)
       if (!(B.eps_r[i] >= 1.0) || !isfinite(B.eps_r[i])) return VIE_EINVAL;
   }
@@ -489,6 +493,12 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
       G.g.Q[a] = G.g.P[a] / 2 + 1;
     }
     G.g.n = (int64_t)G.g.N[0] * G.g.N[1] * G.g.N[2];
+    // one component of the y/z scratch must be addressable with 32-bit offsets
+    const int64_t zl = G.g.N[2] < 16 ? G.g.N[2] : 16;
+    if (((G.g.N[2] + zl - 1) / zl) * zl * G.g.P[1] * G.g.P[0] >= ((int64_t)1 << 31)) {
+      vie_destroy(ctx);
+      return VIE_ENOTSUP;
+    }
   }
   std::vector<std::vector<double>> chi_host(ctx->groups.size());
   for (int b = 0; b < n_bodies; ++b) {
@@ -1045,6 +1055,14 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
         if (!any) break;
       }
       if (k * per_launch > (int64_t)ctx->opt.max_iter + 2) break;
+      if ((k & 63) == 63 && getenv("VIE_LOG")) {
+        KState h0;
+        VIE_HIP(hipMemcpyAsync(&h0, st, sizeof(KState), hipMemcpyDeviceToHost, ctx->stream));
+        VIE_HIP(hipStreamSynchronize(ctx->stream));
+        fprintf(stderr, "vie: cycle %d: %lld iterations launched, rhs 0 recursive rel res %.3e\n",
+                cycle, (long long)((k + 1) * per_launch),
+                h0.bnorm2 > 0 ? sqrt(h0.rnorm2 / h0.bnorm2) : 0.0);
+      }
     }
     if (getenv("VIE_LOG")) {
       std::vector<KState> hs(nrhs);
@@ -1807,6 +1825,8 @@ static int fgmres_group(vie_ctx* ctx, Group& G, BlockPrec* P, const vie_fgmres_o
       if (c > 0) {  // the previous chunk's flag: stop launching once nothing is active
         VIE_HIP(hipEventSynchronize(ctx->flag_ev[slot ^ 1]));
         if (!ctx->hflags[slot ^ 1][0]) break;
+        if (getenv("VIE_LOG"))
+          fprintf(stderr, "vie: fgmres cycle %d: steps < %d done\n", cycle, j0);
       }
     }
     // x += Z y for every right-hand side that took steps in this cycle

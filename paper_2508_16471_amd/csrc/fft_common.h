@@ -51,7 +51,14 @@ __device__ __forceinline__ void tw_load(cpx<T>* w, int t, const cpx<T>* __restri
   if constexpr (NS * RAD != P) tw_load<T, P, E, NS * RAD, OFF + here>(w, t, tw);
 }
 
-template <typename T, int P, int E>
+// Lines longer than 512 points read their twiddles from the global table at
+// every stage instead (too many to keep in registers; the table is small and
+// stays in cache).
+template <int P>
+constexpr bool tw_global() {
+  return P > 512;
+}
+template <typename T, int P, int E, bool G = tw_global<P>()>
 struct TwReg {
   static constexpr int N = tw_count<P, E, 1>() > 0 ? tw_count<P, E, 1>() : 1;
   cpx<T> w[N];
@@ -59,11 +66,19 @@ struct TwReg {
     tw_load<T, P, E, 1, 0>(w, t, tw);
   }
 };
+template <typename T, int P, int E>
+struct TwReg<T, P, E, true> {
+  const cpx<T>* w;
+  __device__ __forceinline__ void load(int, const cpx<T>* __restrict__ tw) { w = tw; }
+};
 
 // HIN: the line's upper half (points P/2..P) is zero on entry (every thread
 // holds it as v[E/2..E)); HOUT: only the lower half is needed on exit.  The
 // first / last stage's DFTs are pruned accordingly.
-template <typename T, int P, int E, int NS, bool INV, int OFF, bool HIN = false, bool HOUT = false>
+// GTW: w is the global twiddle table (tw[m] = W_P^m) instead of the
+// thread's register twiddles.
+template <typename T, int P, int E, int NS, bool INV, int OFF, bool HIN = false, bool HOUT = false,
+          bool GTW = false>
 __device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int t,
                                              const cpx<T>* __restrict__ w) {
   constexpr int RAD = fft_radix<P, E, NS>();
@@ -86,7 +101,11 @@ __device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int
       for (int r = 0; r < RAD; ++r) {
         cpx<T> x = lds[j + r * (P / RAD)];
         if (r > 0) {
-          cpx<T> ww = w[OFF + b * (RAD - 1) + r - 1];
+          cpx<T> ww;
+          if constexpr (GTW)
+            ww = w[r * (j % NS) * (P / (NS * RAD))];
+          else
+            ww = w[OFF + b * (RAD - 1) + r - 1];
           if (INV) ww.im = -ww.im;
           x = x * ww;
         }
@@ -117,19 +136,26 @@ __device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int
       for (int r = 0; r < RAD; ++r) lds[base + r * NS] = u[b * RAD + r];
     }
     __syncthreads();
-    fft_stages_p<T, P, E, NS * RAD, INV, OFF + here, HIN, HOUT>(v, lds, t, w);
+    fft_stages_p<T, P, E, NS * RAD, INV, OFF + here, HIN, HOUT, GTW>(v, lds, t, w);
   }
 }
 
 template <typename T, int P, bool INV, bool HIN = false, bool HOUT = false>
 __device__ __forceinline__ void line_fft(cpx<T> (&v)[fft_e<P>()], cpx<T>* line, int t,
                                          const TwReg<T, P, fft_e<P>()>& tr) {
-  fft_stages_p<T, P, fft_e<P>(), 1, INV, 0, HIN, HOUT>(v, LdsLine<T>{line}, t, tr.w);
+  fft_stages_p<T, P, fft_e<P>(), 1, INV, 0, HIN, HOUT, tw_global<P>()>(v, LdsLine<T>{line}, t,
+                                                                       tr.w);
 }
 
 template <typename T>
 constexpr int nt_lines() {
   return sizeof(T) == 8 ? 128 : 256;  // threads per workgroup of single-line passes
+}
+// Threads per workgroup of a single-line pass of length P: nt_lines, or one
+// whole line when its P / E threads are more than that (lines above 512).
+template <typename T>
+constexpr int nt_lines_p(int P) {
+  return nt_lines<T>() > P / fft_e_of(P) ? nt_lines<T>() : P / fft_e_of(P);
 }
 
 
@@ -167,11 +193,37 @@ __device__ __forceinline__ void block_sum2(c64& a, c64& b, double* red) {
 
 template <typename T>
 constexpr int lines_per_block(int P) {
-  return nt_lines<T>() / (P / fft_e_of(P));
+  return nt_lines_p<T>(P) / (P / fft_e_of(P));
 }
 
-// Supported line lengths: 2^k (8..512) and 3 * 2^k (12..384).
-#define VIE_DISPATCH_P(P_, CALL)                       \
+// Line lengths of the x and y passes: 2^k (8..4096) and 3 * 2^k (12..6144).
+#define VIE_DISPATCH_P(P_, CALL)                         \
+  switch (P_) {                                          \
+    case 8: { constexpr int PP = 8; CALL; break; }       \
+    case 12: { constexpr int PP = 12; CALL; break; }     \
+    case 16: { constexpr int PP = 16; CALL; break; }     \
+    case 24: { constexpr int PP = 24; CALL; break; }     \
+    case 32: { constexpr int PP = 32; CALL; break; }     \
+    case 48: { constexpr int PP = 48; CALL; break; }     \
+    case 64: { constexpr int PP = 64; CALL; break; }     \
+    case 96: { constexpr int PP = 96; CALL; break; }     \
+    case 128: { constexpr int PP = 128; CALL; break; }   \
+    case 192: { constexpr int PP = 192; CALL; break; }   \
+    case 256: { constexpr int PP = 256; CALL; break; }   \
+    case 384: { constexpr int PP = 384; CALL; break; }   \
+    case 512: { constexpr int PP = 512; CALL; break; }   \
+    case 768: { constexpr int PP = 768; CALL; break; }   \
+    case 1024: { constexpr int PP = 1024; CALL; break; } \
+    case 1536: { constexpr int PP = 1536; CALL; break; } \
+    case 2048: { constexpr int PP = 2048; CALL; break; } \
+    case 3072: { constexpr int PP = 3072; CALL; break; } \
+    case 4096: { constexpr int PP = 4096; CALL; break; } \
+    case 6144: { constexpr int PP = 6144; CALL; break; } \
+    default: return hipErrorInvalidValue;                \
+  }
+
+// Line lengths of the z passes: 2^k (8..512) and 3 * 2^k (12..384).
+#define VIE_DISPATCH_PZ(P_, CALL)                      \
   switch (P_) {                                        \
     case 8: { constexpr int PP = 8; CALL; break; }     \
     case 12: { constexpr int PP = 12; CALL; break; }   \

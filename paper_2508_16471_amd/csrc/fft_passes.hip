@@ -20,10 +20,10 @@ namespace vie {
 // ---------------------------------------------------------------- X forward
 // One workgroup: L consecutive x-lines of one right-hand side.
 template <typename TI, typename T, int P, bool PAD>
-__global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd(
+__global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_fwd(
     const cpx<TI>* __restrict__ x, cpx<T>* __restrict__ out, const cpx<T>* __restrict__ tw, int N1,
     int lines_per_rhs, int blocks_per_rhs, const int* __restrict__ active) {
-  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), L = NT / TT;
+  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines_p<T>(P), L = NT / TT;
   __shared__ cpx<T> lds[L * Pad<P>::LSTR];
   // Hardware order (consecutive blocks go to consecutive XCDs): the lines of
   // one right-hand side spread over every XCD, so inactive right-hand sides
@@ -231,10 +231,12 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
   // launches need P1 % W == 0)
   constexpr bool PAIR = FAST && sizeof(T) == 4 && (E == 16 || E == 12);
   const bool valid = PAIR || xx < a.P1;
-  // B[rhs][comp][z / zl][xi_y][z % zl][xi_x]; offsets within one right-hand
-  // side fit in 32 bits (3 N3 P2 P1 < 2^31 for P <= 512)
+  // B[rhs][comp][z / zl][xi_y][z % zl][xi_x]; one base pointer per component,
+  // offsets within a component fit in 32 bits (the setup checks that a
+  // component of B has fewer than 2^31 elements)
   cpx<T>* col = B + rhs * a.rhs_stride + (int64_t)xy * a.zl * a.P1 + (valid ? xx : 0);
-  const int cs = (int)a.comp_stride;
+  cpx<T>* col1 = col + a.comp_stride;
+  cpx<T>* col2 = col1 + a.comp_stride;
   int zoff[E / 2];
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
@@ -250,13 +252,15 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
   cpx<T> v0[E], v1[E], v2[E];
   if constexpr (PAIR) {
     const float* cp = reinterpret_cast<const float*>(col - odd);
+    const float* cp1 = reinterpret_cast<const float*>(col1 - odd);
+    const float* cp2 = reinterpret_cast<const float*>(col2 - odd);
 #pragma unroll
     for (int k = 0; k < E / 4; ++k) {
       const int zr = t + (2 * k + odd) * TT;  // this lane's row: point 2k (even) or 2k+1 (odd)
       const int off = 2 * ((zr >> 4) * (int)a.zhs + (zr & 15) * (int)a.zls);
       float4 f0 = *reinterpret_cast<const float4*>(cp + off);
-      float4 f1 = *reinterpret_cast<const float4*>(cp + 2 * cs + off);
-      float4 f2 = *reinterpret_cast<const float4*>(cp + 4 * cs + off);
+      float4 f1 = *reinterpret_cast<const float4*>(cp1 + off);
+      float4 f2 = *reinterpret_cast<const float4*>(cp2 + off);
       if (ZP && zr >= a.N3) f0 = f1 = f2 = make_float4(0.f, 0.f, 0.f, 0.f);
       pair_in(f0, odd, v0[2 * k], v0[2 * k + 1]);
       pair_in(f1, odd, v1[2 * k], v1[2 * k + 1]);
@@ -270,8 +274,8 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
       const int z = t + q * TT;
       if (q < E / 2 && valid && ((FAST && !ZP) || z < a.N3)) {
         v0[q] = col[zoff[q]];
-        v1[q] = col[cs + zoff[q]];
-        v2[q] = col[2 * cs + zoff[q]];
+        v1[q] = col1[zoff[q]];
+        v2[q] = col2[zoff[q]];
       } else {
         v0[q] = v1[q] = v2[q] = mk<T>(0, 0);
       }
@@ -328,13 +332,15 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
   line_fft_e<T, P, E, true, false, true>(v2, line, t, tr);
   if constexpr (PAIR) {
     float* cp = reinterpret_cast<float*>(col - odd);
+    float* cp1 = reinterpret_cast<float*>(col1 - odd);
+    float* cp2 = reinterpret_cast<float*>(col2 - odd);
 #pragma unroll
     for (int k = 0; k < E / 4; ++k) {
       const int zr = t + (2 * k + odd) * TT;
       const int off = 2 * ((zr >> 4) * (int)a.zhs + (zr & 15) * (int)a.zls);
       *reinterpret_cast<float4*>(cp + off) = pair_out(odd, v0[2 * k], v0[2 * k + 1]);
-      *reinterpret_cast<float4*>(cp + 2 * cs + off) = pair_out(odd, v1[2 * k], v1[2 * k + 1]);
-      *reinterpret_cast<float4*>(cp + 4 * cs + off) = pair_out(odd, v2[2 * k], v2[2 * k + 1]);
+      *reinterpret_cast<float4*>(cp1 + off) = pair_out(odd, v1[2 * k], v1[2 * k + 1]);
+      *reinterpret_cast<float4*>(cp2 + off) = pair_out(odd, v2[2 * k], v2[2 * k + 1]);
     }
     return;
   }
@@ -344,8 +350,8 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
       const int z = t + q * TT;
       if (FAST || z < a.N3) {
         col[zoff[q]] = v0[q];
-        col[cs + zoff[q]] = v1[q];
-        col[2 * cs + zoff[q]] = v2[q];
+        col1[zoff[q]] = v1[q];
+        col2[zoff[q]] = v2[q];
       }
     }
   }
@@ -365,12 +371,12 @@ struct XinvArgs {
 };
 
 template <typename T, int P, int MODE>
-__global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv(
+__global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_inv(
     const cpx<T>* __restrict__ A, const c64* __restrict__ xin, c64* __restrict__ yout,
     const double* __restrict__ chi, const int* __restrict__ rhs_body,
     const cpx<T>* __restrict__ tw, XinvArgs a, c64* __restrict__ aux, c64* __restrict__ partials,
     const c64* __restrict__ pol, const c64* __restrict__ ph, const int* __restrict__ active) {
-  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), L = NT / TT;
+  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines_p<T>(P), L = NT / TT;
   __shared__ cpx<T> lds[L * Pad<P>::LSTR];
   __shared__ double red[4 * (NT / 64 + 1)];
   // hardware order (see the forward x pass)
@@ -447,7 +453,7 @@ static hipError_t x_fwd(const GroupGeom& g, const c64* x, cpx<T>* A, const cpx<T
   const int L = lines_per_block<T>(g.P[0]);
   const int bpr = (lines + L - 1) / L;
   const dim3 grid(bpr * g.nrhs);
-  VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd<double, T, PP, true><<<grid, nt_lines<T>(), 0, s>>>(
+  VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd<double, T, PP, true><<<grid, nt_lines_p<T>(PP), 0, s>>>(
                              x, A, tw, g.N[0], lines, bpr, active)));
   return hipGetLastError();
 }
@@ -480,50 +486,56 @@ int64_t bufB_elems(const GroupGeom& g) {
   return side_B(g, zl).rs;  // per right-hand side
 }
 
-// Workgroup size of the y passes (the host's ntY in y_pass computes the same).
+// Workgroup size of the y passes: enough threads that each row access is a
+// 128-byte run of columns, at least nt_lines; long lines (P > 512) are capped
+// at 1024 threads and about 150 KB of LDS (W padded lines), so they get fewer
+// columns per workgroup.
 template <typename T, int P>
 constexpr int y_threads() {
   constexpr int tt = P / fft_e<P>();
-  constexpr int nt = (int)(128 / sizeof(cpx<T>)) * tt;
-  return nt > nt_lines<T>() ? nt : nt_lines<T>();
+  int v = (int)(128 / sizeof(cpx<T>)) * tt;
+  if (v < nt_lines<T>()) v = nt_lines<T>();
+  while (v > tt && (v > 1024 || (v / tt) * Pad<P>::LSTR * (int)sizeof(cpx<T>) > 150 * 1024))
+    v /= 2;
+  return v < tt ? tt : v;
 }
 
-template <typename T>
-static hipError_t y_pass(const GroupGeom& g, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw,
-                         bool inverse, const int* active, hipStream_t s) {
-  const int P1 = g.P[0], P2 = g.P[1], N2 = g.N[1], N3 = g.N[2];
+template <typename T, int PP>
+static void y_launch(const GroupGeom& g, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw,
+                     bool inverse, const int* active, hipStream_t s) {
+  const int P1 = g.P[0], N2 = g.N[1], N3 = g.N[2];
   const int zl = z_block(g);
+  constexpr int ntY = y_threads<T, PP>();
+  constexpr int W = ntY / (PP / fft_e<PP>());
   StridedArgs a;
   a.ncols = P1;
   a.ncomp = 3;
   a.nz = N3;
   a.zl = zl;
-  // enough threads per workgroup that each row access is a 128-byte run
-  // (long lines have more threads per line)
-  const int TTy = P2 / fft_e_of(P2);
-  const int ntY = std::max(nt_lines<T>(), (int)(128 / sizeof(cpx<T>)) * TTy);
-  const int W = ntY / TTy;
   a.tiles = (P1 + W - 1) / W;
   const SideAddr A = side_A(g, zl), B = side_B(g, zl);
   if (!inverse) {
     a.n_in_rows = N2;
-    a.n_out_rows = P2;
+    a.n_out_rows = PP;
     a.in = A;
     a.out = B;
   } else {
-    a.n_in_rows = P2;
+    a.n_in_rows = PP;
     a.n_out_rows = N2;
     a.in = B;
     a.out = A;
   }
   const dim3 grid(a.tiles * 3 * N3 * g.nrhs);
-  if (!inverse) {
-    VIE_DISPATCH_P(P2, (k_fft_strided<T, PP, true, false, false, y_threads<T, PP>()><<<grid, ntY, 0, s>>>(
-                           in, out, tw, a, active)));
-  } else {
-    VIE_DISPATCH_P(P2, (k_fft_strided<T, PP, false, true, true, y_threads<T, PP>()><<<grid, ntY, 0, s>>>(
-                           in, out, tw, a, active)));
-  }
+  if (!inverse)
+    k_fft_strided<T, PP, true, false, false, ntY><<<grid, ntY, 0, s>>>(in, out, tw, a, active);
+  else
+    k_fft_strided<T, PP, false, true, true, ntY><<<grid, ntY, 0, s>>>(in, out, tw, a, active);
+}
+
+template <typename T>
+static hipError_t y_pass(const GroupGeom& g, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw,
+                         bool inverse, const int* active, hipStream_t s) {
+  VIE_DISPATCH_P(g.P[1], (y_launch<T, PP>(g, in, out, tw, inverse, active, s)));
   return hipGetLastError();
 }
 
@@ -565,7 +577,7 @@ static hipError_t z_pass(const GroupGeom& g, cpx<T>* B, const cpx<T>* spec, cons
   a.rhs_stride = sb.rs;
   a.zhs = sb.zhs;
   a.zls = sb.zls;
-  VIE_DISPATCH_P(g.P[2], ({
+  VIE_DISPATCH_PZ(g.P[2], ({
                    switch (variant) {
                      case 1: z_launch<T, PP, 1>(g, a, B, spec, tw, active, s); break;
                      default: z_launch<T, PP, 0>(g, a, B, spec, tw, active, s); break;
@@ -596,7 +608,7 @@ static hipError_t x_inv(const GroupGeom& g, const cpx<T>* A, const c64* x, c64* 
   e.part_blocks = a.blocks_per_rhs;
   const dim3 grid(a.blocks_per_rhs * g.nrhs);
 #define VIE_XINV(MODE_)                                                                    \
-  VIE_DISPATCH_P(g.P[0], (k_fft_x_inv<T, PP, MODE_><<<grid, nt_lines<T>(), 0, s>>>(           \
+  VIE_DISPATCH_P(g.P[0], (k_fft_x_inv<T, PP, MODE_><<<grid, nt_lines_p<T>(PP), 0, s>>>(       \
                              A, x, y, chi, rhs_body, tw, a, e.aux, e.partials, e.pol, e.ph, \
                              active)))
   switch (e.mode) {
@@ -684,7 +696,7 @@ hipError_t launch_fft3d_full(c64* work, c64* tmp, const GroupGeom& g, const void
     const int lines = P2 * P3;
     const int L = lines_per_block<double>(P1);
     const int bpr = (lines + L - 1) / L;
-    VIE_DISPATCH_P(P1, (k_fft_x_fwd<double, double, PP, false><<<bpr, nt_lines<double>(), 0, s>>>(
+    VIE_DISPATCH_P(P1, (k_fft_x_fwd<double, double, PP, false><<<bpr, nt_lines_p<double>(PP), 0, s>>>(
                            work, tmp, tw0, P1, lines, bpr, nullptr)));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -701,8 +713,8 @@ hipError_t launch_fft3d_full(c64* work, c64* tmp, const GroupGeom& g, const void
     a.in.row = a.out.row = P1;
     a.in.zhs = a.out.zhs = (int64_t)P2 * P1;
     a.in.zls = a.out.zls = a.in.cs = a.out.cs = a.in.rs = a.out.rs = 0;
-    VIE_DISPATCH_P(P2, (k_fft_strided<double, PP, false, false, false>
-                        <<<a.tiles * P3, nt_lines<double>(), 0, s>>>(tmp, work, tw1, a, nullptr)));
+    VIE_DISPATCH_P(P2, (k_fft_strided<double, PP, false, false, false, nt_lines_p<double>(PP)>
+                        <<<a.tiles * P3, nt_lines_p<double>(PP), 0, s>>>(tmp, work, tw1, a, nullptr)));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -718,8 +730,8 @@ hipError_t launch_fft3d_full(c64* work, c64* tmp, const GroupGeom& g, const void
     a.in.row = a.out.row = (int64_t)P2 * P1;
     a.in.zhs = a.out.zhs = P1;
     a.in.zls = a.out.zls = a.in.cs = a.out.cs = a.in.rs = a.out.rs = 0;
-    VIE_DISPATCH_P(P3, (k_fft_strided<double, PP, false, false, false>
-                        <<<a.tiles * P2, nt_lines<double>(), 0, s>>>(work, tmp, tw2, a, nullptr)));
+    VIE_DISPATCH_PZ(P3, (k_fft_strided<double, PP, false, false, false>
+                         <<<a.tiles * P2, nt_lines<double>(), 0, s>>>(work, tmp, tw2, a, nullptr)));
   }
   return hipGetLastError();
 }

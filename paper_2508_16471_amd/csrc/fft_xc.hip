@@ -16,10 +16,10 @@ namespace vie {
 
 // ---------------------------------------------------------------- X forward
 template <typename T, int P, typename TI>
-__global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd_c(
+__global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_fwd_c(
     const cpx<TI>* __restrict__ xc, cpx<T>* __restrict__ out, const cpx<T>* __restrict__ tw,
     BodyIdx bi, int N1, int N2, int N3, int blocks_per_rhs, const int* __restrict__ active) {
-  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), L = NT / TT,
+  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines_p<T>(P), L = NT / TT,
                 LS = Pad<P>::LSTR;
   __shared__ cpx<T> lds[L * LS];
   // Hardware order (consecutive blocks go to consecutive XCDs): the lines of
@@ -65,12 +65,12 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_fwd_c(
 
 // ------------------------------------------------ X inverse + epilogue
 template <typename T, int P, int MODE, typename TIO>
-__global__ __launch_bounds__(nt_lines<T>()) void k_fft_x_inv_c(
+__global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_inv_c(
     const cpx<T>* __restrict__ A, const cpx<TIO>* __restrict__ xin, cpx<TIO>* __restrict__ yout,
     const cpx<T>* __restrict__ tw, BodyIdx bi, int N1, int N2, int N3, int blocks_per_rhs,
     c64* __restrict__ aux, c64* __restrict__ partials, const c64* __restrict__ pol,
     const c64* __restrict__ ph, const int* __restrict__ active) {
-  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), L = NT / TT,
+  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines_p<T>(P), L = NT / TT,
                 LS = Pad<P>::LSTR;
   __shared__ cpx<T> lds[L * LS];
   __shared__ double red[4 * (NT / 64 + 1)];
@@ -161,10 +161,10 @@ hipError_t x_fwd_c(const GroupGeom& g, const void* xc, int in32, cpx<T>* A, cons
   const int bpr = (lines + L - 1) / L;
   const dim3 grid(bpr * g.nrhs);
   if (in32) {
-    VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd_c<T, PP, float><<<grid, nt_lines<T>(), 0, s>>>(
+    VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd_c<T, PP, float><<<grid, nt_lines_p<T>(PP), 0, s>>>(
                                (const c32*)xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active)));
   } else {
-    VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd_c<T, PP, double><<<grid, nt_lines<T>(), 0, s>>>(
+    VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd_c<T, PP, double><<<grid, nt_lines_p<T>(PP), 0, s>>>(
                                (const c64*)xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active)));
   }
   return hipGetLastError();
@@ -181,13 +181,13 @@ hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const void* x, void* y, 
   const dim3 grid(bpr * g.nrhs);
   if (io32) {  // FP32 vectors: the plain product only
     if (e.mode != EPI_PLAIN) return hipErrorInvalidValue;
-    VIE_DISPATCH_P(g.P[0], (k_fft_x_inv_c<T, PP, EPI_PLAIN, float><<<grid, nt_lines<T>(), 0, s>>>(
+    VIE_DISPATCH_P(g.P[0], (k_fft_x_inv_c<T, PP, EPI_PLAIN, float><<<grid, nt_lines_p<T>(PP), 0, s>>>(
                                A, (const c32*)x, (c32*)y, tw, bi, g.N[0], g.N[1], g.N[2], bpr,
                                e.aux, e.partials, e.pol, e.ph, active)));
     return hipGetLastError();
   }
 #define VIE_XINVC(MODE_)                                                                      \
-  VIE_DISPATCH_P(g.P[0], (k_fft_x_inv_c<T, PP, MODE_, double><<<grid, nt_lines<T>(), 0, s>>>(   \
+  VIE_DISPATCH_P(g.P[0], (k_fft_x_inv_c<T, PP, MODE_, double><<<grid, nt_lines_p<T>(PP), 0, s>>>(   \
                              A, (const c64*)x, (c64*)y, tw, bi, g.N[0], g.N[1], g.N[2], bpr,  \
                              e.aux, e.partials, e.pol, e.ph, active)))
   switch (e.mode) {

@@ -18,6 +18,7 @@ from .geometry import (  # noqa: F401
     metasurface_fins,
     metasurface_family,
     pb_metasurface,
+    paper_metasurface,
     cap_directions,
     uv_directions,
     pb_rotation_step,

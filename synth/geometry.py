@@ -191,6 +191,54 @@ def pb_metasurface(n=(256, 256, 48), h=1.0 / 60, count=8):
     return grid, body
 
 
+def paper_metasurface(h=1.0 / 62, n=(2480, 744, 124), substrate_cells=2):
+    """The paper's full-wave PB metasurface at its stated size (lengths in
+    wavelengths, lambda = 1550 nm): a 40 x 12 x 2 box at 62 cells per
+    wavelength (2480 x 744 x 124 voxels).  Unit cell of period 667 nm with a
+    silicon nanofin (n = 3.44, eps = 11.83) of 486 x 219 x 830 nm on a glass
+    substrate of eps 2.25 (the paper's n_glass = 2.25 read as the
+    permittivity).  91 unit cells along x (7 groups of 13) and as many along
+    y as fit the 12-wavelength width (27), centred laterally; fin m along x
+    is rotated by m times 13.44 deg (eq. 32, deflection 10 deg); the
+    substrate is ``substrate_cells`` thick (the paper leaves it open; 2 cells
+    puts the element count near the paper's 18,013,710), fins on top, the
+    stack centred in z.  Built fin by fin on its own bounding box (the
+    lateral fin map is shared by every fin layer)."""
+    lam_nm = 1550.0
+    p = 667.0 / lam_nm
+    fl, fw, fh = 486.0 / lam_nm, 219.0 / lam_nm, 830.0 / lam_nm
+    eps_si, eps_glass = 3.44 ** 2, 2.25
+    grid = Grid.centred(n, h)
+    nx, ny = 91, int(np.floor(n[1] * h / p))
+    dth = pb_rotation_step(2 * np.pi, np.deg2rad(10.0), p)
+    fin_cells = int(round(fh / h))
+    z0 = (n[2] - substrate_cells - fin_cells) // 2
+    # lateral fin map (x fastest): eps of the fin covering each column, 1 elsewhere
+    fmap = np.ones((n[1], n[0]))
+    xs = grid.origin[0] + h * np.arange(n[0])
+    ys = grid.origin[1] + h * np.arange(n[1])
+    x0 = -0.5 * nx * p  # array centred on the grid centre (0, 0)
+    y0 = -0.5 * ny * p
+    half = 0.5 * np.hypot(fl, fw) + h
+    for a in range(nx):
+        t = a * dth
+        c, sn = np.cos(t), np.sin(t)
+        cx = x0 + (a + 0.5) * p
+        i0, i1 = np.searchsorted(xs, cx - half), np.searchsorted(xs, cx + half)
+        for b in range(ny):
+            cy = y0 + (b + 0.5) * p
+            j0, j1 = np.searchsorted(ys, cy - half), np.searchsorted(ys, cy + half)
+            X, Y = np.meshgrid(xs[i0:i1] - cx, ys[j0:j1] - cy, indexing="xy")
+            u = X * c + Y * sn
+            v = -X * sn + Y * c
+            m = (np.abs(u) <= fl / 2) & (np.abs(v) <= fw / 2)
+            fmap[j0:j1, i0:i1][m] = eps_si
+    body = np.ones(n[::-1])
+    body[z0:z0 + substrate_cells] = eps_glass
+    body[z0 + substrate_cells:z0 + substrate_cells + fin_cells] = fmap[None]
+    return grid, body
+
+
 def uv_directions(values=np.arange(-0.3, 0.41, 0.1)):
     """Incident directions (u, v, sqrt(1 - u^2 - v^2)) on the product grid of
     transverse components ``values`` (default -0.3 ... 0.4 in steps of 0.1:
