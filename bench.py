@@ -143,11 +143,13 @@ def fft_length(n):
     return min(p2, p3)
 
 
-def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None):
+def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None, vb=16):
     """Algorithmic HBM bytes of one right-hand-side execution of a pass
     (spectrum excluded; it is charged once per launch).  nb: body voxels when
     the solver's vectors are body-compressed (x passes read/write 3 nb
-    values plus the voxel index and line pointers), None for box vectors."""
+    values plus the voxel index and line pointers), None for box vectors.
+    vb: bytes of a vector element (16, or 8 for the FP32 vectors of the
+    FGMRES products)."""
     N1, N2, N3 = N
     P1, P2, P3 = P
     n = N1 * N2 * N3
@@ -156,7 +158,7 @@ def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None):
     B = 3 * N3 * P2 * P1
     if kind.startswith("fft_x_fwd"):
         if nb is not None:
-            return 3 * nb * (16 + 4) + 3 * (N2 * N3 + 1) * 4 + A * c
+            return 3 * nb * (vb + 4) + 3 * (N2 * N3 + 1) * 4 + A * c
         return 3 * n * 16 + A * c
     if kind.startswith("fft_y_fwd"):
         return A * c + B * c
@@ -166,7 +168,7 @@ def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None):
         return B * c + A * c
     if kind.startswith("fft_x_inv"):
         if nb is not None:
-            return A * c + 3 * nb * (16 * 2 + 8 + 4) + 3 * (N2 * N3 + 1) * 4 + epi_extra
+            return A * c + 3 * nb * (vb * 2 + 8 + 4) + 3 * (N2 * N3 + 1) * 4 + epi_extra
         return A * c + 3 * n * 16 * 2 + n * 8 + epi_extra
     raise KeyError(kind)
 
@@ -241,7 +243,8 @@ def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch):
     """Achieved GB/s of every FFT pass of the FGMRES solve: FP32 outer
     products (one per Arnoldi step), FP64 true-residual products (one per
     cycle) and the FP32 block products (k per step, one execution per block
-    of the right-hand side's body)."""
+    of the right-hand side's body).  FP32 products read and write FP32
+    vectors."""
     iters = np.array([s["iters"] for s in stats])
     cyc = np.array([s["cycles"] for s in stats])
     per_step = len(geom["blocks_per_body"]) * nch  # stats repeat once per timed step
@@ -262,7 +265,7 @@ def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch):
             execs = int(iters.sum()) if f32 else int(cyc.sum())
             launches_active = int(iters.max()) if f32 else int(cyc.max())
         extra = 3 * nbk * 16 if (base.startswith("fft_x_inv") and not f32 and not blk) else 0
-        by = execs * kernel_bytes(base, Nk, Pk, Qk, extra, nb=nbk)
+        by = execs * kernel_bytes(base, Nk, Pk, Qk, extra, nb=nbk, vb=8 if f32 else 16)
         if base.startswith("fft_z_green"):
             by += launches_active * spectrum_bytes(base, Qk)
         rows[kind] = {"ms_total": ms, "launches": int(cnt), "rhs_execs": execs,
