@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2508_16471_amd", "weights",
                                                       "warmstart_metasurface128.npy"))
     ap.add_argument("--mode", choices=["solve", "matvec", "farfield", "uneven", "metasurface",
-                                       "sphere", "precond", "paperscale"],
+                                       "sphere", "precond", "paperscale", "cnn"],
                     default="solve",
                     help="matvec: time device-resident operator products only; farfield: "
                          "the 64,800-direction sweep of one body only (profiling); uneven: "
@@ -610,6 +610,74 @@ def farfield_mode(args):
     print(json.dumps({"mode": "farfield", "grid": list(g.n), "farfield_sweep": sweep}))
 
 
+def cnn_flops_per_voxel(backward=False):
+    """Algorithmic flops of the network per box voxel: 2 x 27 taps x Cin x
+    Cout per layer (forward); a training step adds the weight gradient of
+    every layer and the data gradient of all but the first."""
+    ch = [32, 32, 32, 32, 16]
+    macs = [27 * ci * co for ci, co in zip(ch[:-1], ch[1:])]
+    f = 2 * sum(macs)
+    if backward:
+        f += 2 * sum(macs) + 2 * sum(macs[1:])
+    return f
+
+
+def cnn_mode(args):
+    """The warm-start network alone on the box of one W128 benchmark body
+    (bounding box + 4-voxel halo): `steps` forward inferences, then `steps`
+    training steps (forward, masked loss, backward, Adam), on synthetic bf16
+    features and fp32 targets; HIP events on the stream the library runs on."""
+    import torch
+
+    from paper_2508_16471_amd import vie as V
+
+    torch.cuda.set_device(0)
+    V.lib()
+    bodies, chans = make_workload(1, 1, args.grid)
+    eps, h, o, g = bodies[0]
+    ctx = V.vie_setup([(eps, h, o)], V.make_options(K0, precision=V.VIE_MIXED, tol=1e-2))
+    try:
+        V.vie_solve(ctx, chans, [1])  # sizes the body's channel storage
+        d = V.vie_cnn_sample_dev(ctx, 0, 0)
+    finally:
+        V.vie_destroy(ctx)
+    nv = d[0] * d[1] * d[2]
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    feat = torch.randn((d[2], d[1], d[0], 32), generator=gen, device="cuda").to(torch.bfloat16)
+    feat[..., 0] = (torch.rand((d[2], d[1], d[0]), generator=gen, device="cuda") < 0.3).to(
+        torch.bfloat16)  # channel 0 doubles as the loss mask (body voxels)
+    tgt = torch.randn((d[2], d[1], d[0], 6), generator=gen, device="cuda")
+    out = torch.empty((d[2], d[1], d[0], 16), device="cuda")
+    net = V.vie_cnn_create(0)
+    st = torch.cuda.current_stream()
+    res = {}
+    try:
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            for _ in range(reps):
+                fn()
+            b.record(st)
+            b.synchronize()
+            return a.elapsed_time(b) / reps
+
+        reps = max(1, args.steps)
+        ms_f = timed(lambda: V.vie_cnn_infer_dev(net, d, feat.data_ptr(), out.data_ptr(),
+                                                 st.cuda_stream), 4 * reps)
+        ms_t = timed(lambda: V.vie_cnn_train_step_dev(net, d, feat.data_ptr(), tgt.data_ptr(),
+                                                      1e-4, st.cuda_stream), reps)
+        for name, ms, bw in (("forward", ms_f, False), ("train_step", ms_t, True)):
+            fl = cnn_flops_per_voxel(bw) * nv
+            res[name] = {"ms": ms, "flop": fl, "TFLOPs": fl / (ms * 1e-3) / 1e12,
+                         "frac_bf16_mfma_peak": fl / (ms * 1e-3) / 1e12 / 2500.0}
+    finally:
+        V.vie_cnn_destroy(net)
+    print(json.dumps({"mode": "cnn", "box": list(d), "voxels": nv, "data": "synthetic",
+                      "peak_TFLOPs": 2500.0, **res}))
+
+
 def uneven_mode(args):
     """Uneven batch: `bodies` random ellipsoid unions (1-6 ellipsoids, semi-axes
     U[0.2, 1], eps U[1.5, 6]) on grids drawn from {32, 48, 64, 96}^3 (h = 1/16),
@@ -1067,12 +1135,13 @@ def precond_mode(args):
 def main():
     args = parse()
     if args.mode in ("matvec", "farfield", "uneven", "metasurface", "sphere", "precond",
-                     "paperscale"):
+                     "paperscale", "cnn"):
         if args.gpus != 1:
             sys.exit(2)
         return {"matvec": matvec_mode, "farfield": farfield_mode, "uneven": uneven_mode,
                 "metasurface": metasurface_mode, "sphere": sphere_mode,
-                "precond": precond_mode, "paperscale": paperscale_mode}[args.mode](args)
+                "precond": precond_mode, "paperscale": paperscale_mode,
+                "cnn": cnn_mode}[args.mode](args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the path shards by "
                           "right-hand side / body (see DESIGN.md), --gpus must be 1"}))

@@ -1,5 +1,7 @@
 // Learned warm start: 3x3x3 convolutions as implicit GEMMs on bf16 MFMA
-// (v_mfma_f32_16x16x16_bf16, fp32 accumulation), with training kernels.
+// (gfx950's v_mfma_f32_16x16x32_bf16, fp32 accumulation; the 16-deep
+// v_mfma_f32_16x16x16_bf16 where a reduction step has only 16 channels), with
+// training kernels.
 //
 // Convolution (forward and backward-data): a workgroup of 4 waves computes
 // an 8x8x4 voxel tile (256 GEMM rows) x Cout, K = 27 taps x Cin.  The halo
@@ -19,7 +21,20 @@
 namespace vie {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// One 16x16 output tile += A (16 x K) B (K x 16) over K = 32 (or 16): lane l
+// holds row / column l % 16 and the K slice 8 (l / 16) .. + 7 (4 (l / 16) .. +
+// 3) of its operands, and receives D[4 (l / 16) + i][l % 16], i = 0..3.  Only
+// the pairing of A and B slices matters for the sum, so any fixed K order
+// that both operands share gives the same product.
+__device__ __forceinline__ v4f mfma32(v8bf a, v8bf b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
 
 __device__ __forceinline__ bf16raw f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -41,82 +56,131 @@ CnnLayerOffsets cnn_offsets() {
   return o;
 }
 
-constexpr int TX = 8, TY = 8, TZ = 4;
+constexpr int TX = 8, TY = 8, TZ = 4;  // weight-gradient tile (256 voxels)
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
 constexpr int HV = HX * HY * HZ;
+// Convolution tile: 8 x 8 x FZ voxels, one z-plane per wave of an
+// 8-wave workgroup (two waves per SIMD).
+constexpr int FZ = 8, FNT = 64 * FZ;
+constexpr int HVF = HX * HY * (FZ + 2);
 
 struct ConvDims {
   int d0, d1, d2, tx, ty, tz, ntiles;
 };
 
-static ConvDims conv_dims(const int d[3]) {
+// Tiles of tx x ty x tz voxels (tz = TZ for the weight gradient, FZ for the
+// convolutions) covering the box.
+static ConvDims conv_dims(const int d[3], int tdz) {
   ConvDims c;
   c.d0 = d[0];
   c.d1 = d[1];
   c.d2 = d[2];
   c.tx = (d[0] + TX - 1) / TX;
   c.ty = (d[1] + TY - 1) / TY;
-  c.tz = (d[2] + TZ - 1) / TZ;
+  c.tz = (d[2] + tdz - 1) / tdz;
   c.ntiles = c.tx * c.ty * c.tz;
   return c;
 }
 
 // MODE 0: + bias, ReLU -> bf16; MODE 1: + bias -> fp32; MODE 2: * (ref > 0) -> bf16
+// Persistent workgroups: the weights are staged once; every tile's halo is
+// fetched into registers while the previous tile's MFMAs run, then stored to
+// LDS between two barriers.
 template <int CIN, int COUT, int MODE>
-__global__ __launch_bounds__(256) void k_conv3d(const bf16raw* __restrict__ in,
+__global__ __launch_bounds__(FNT) void k_conv3d(const bf16raw* __restrict__ in,
                                                 const bf16raw* __restrict__ w,
                                                 const float* __restrict__ bias,
                                                 bf16raw* __restrict__ outb,
                                                 float* __restrict__ outf,
                                                 const bf16raw* __restrict__ ref, ConvDims cd) {
-  constexpr int CP = CIN + 4;
+  // 32-deep MFMA steps when the channels allow; padded channel stride keeps
+  // every operand slice 16-byte aligned (8-byte for the 16-deep form)
+  constexpr bool X32 = CIN % 32 == 0;
+  constexpr int KS = X32 ? 32 : 16;
+  constexpr int CP = X32 ? CIN + 8 : CIN + 4;
   constexpr int NCT = COUT / 16;
-  __shared__ __align__(16) bf16raw s_in[HV * CP];
+  constexpr int NQ = HVF * (CIN / 4);  // 8-byte halo items
+  constexpr int PF = (NQ + FNT - 1) / FNT;
+  __shared__ __align__(16) bf16raw s_in[HVF * CP];
   __shared__ __align__(16) bf16raw s_w[27 * COUT * CP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = lane & 15, kq = lane >> 4;
-  for (int i = tid; i < 27 * COUT * (CIN / 4); i += 256) {
+  for (int i = tid; i < 27 * COUT * (CIN / 4); i += FNT) {
     const int c4 = i % (CIN / 4), row = i / (CIN / 4);
     *(uint2*)&s_w[row * CP + 4 * c4] = *(const uint2*)&w[(size_t)row * CIN + 4 * c4];
   }
-  for (int tile = blockIdx.x; tile < cd.ntiles; tile += gridDim.x) {
+  uint2 pre[PF];
+  auto fetch = [&](int tile) {
     const int tx = tile % cd.tx, ty = (tile / cd.tx) % cd.ty, tz = tile / (cd.tx * cd.ty);
-    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
-    __syncthreads();
-    for (int i = tid; i < HV * (CIN / 4); i += 256) {
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * FZ;
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int i = tid + p * FNT;
       const int c4 = i % (CIN / 4), v = i / (CIN / 4);
       const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
       const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
-      uint2 val = make_uint2(0u, 0u);
-      if (gx >= 0 && gx < cd.d0 && gy >= 0 && gy < cd.d1 && gz >= 0 && gz < cd.d2)
-        val = *(const uint2*)&in[((size_t)(gz * cd.d1 + gy) * cd.d0 + gx) * CIN + 4 * c4];
-      *(uint2*)&s_in[v * CP + 4 * c4] = val;
+      pre[p] = make_uint2(0u, 0u);
+      if (i < NQ && gx >= 0 && gx < cd.d0 && gy >= 0 && gy < cd.d1 && gz >= 0 && gz < cd.d2)
+        pre[p] = *(const uint2*)&in[((size_t)(gz * cd.d1 + gy) * cd.d0 + gx) * CIN + 4 * c4];
+    }
+  };
+  if ((int)blockIdx.x < cd.ntiles) fetch(blockIdx.x);
+  for (int tile = blockIdx.x; tile < cd.ntiles; tile += gridDim.x) {
+    const int tx = tile % cd.tx, ty = (tile / cd.tx) % cd.ty, tz = tile / (cd.tx * cd.ty);
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * FZ;
+    __syncthreads();  // the previous tile's operand reads are done
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int i = tid + p * FNT;
+      if (i < NQ) {
+        const int c4 = i % (CIN / 4), v = i / (CIN / 4);
+        *(uint2*)&s_in[v * CP + 4 * c4] = pre[p];
+      }
     }
     __syncthreads();
+    if (tile + (int)gridDim.x < cd.ntiles) fetch(tile + gridDim.x);
     v4f acc[4][NCT];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) acc[rt][ct] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 3
     for (int tap = 0; tap < 27; ++tap) {
       const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
 #pragma unroll
-      for (int kc = 0; kc < CIN / 16; ++kc) {
-        v4s a[4], b[NCT];
+      for (int kc = 0; kc < CIN / KS; ++kc) {
+        const int ko = KS * kc + (KS / 4) * kq;  // this lane's K slice
+        if constexpr (X32) {
+          v8bf a[4], b[NCT];
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-          const int ly = 2 * rt + (r >> 3), lx = r & 7;
-          const int hv = ((wave + 1 + dz) * HY + (ly + 1 + dy)) * HX + (lx + 1 + dx);
-          a[rt] = *(const v4s*)&s_in[hv * CP + 16 * kc + 4 * kq];
-        }
-#pragma unroll
-        for (int ct = 0; ct < NCT; ++ct)
-          b[ct] = *(const v4s*)&s_w[(tap * COUT + ct * 16 + r) * CP + 16 * kc + 4 * kq];
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
+          for (int rt = 0; rt < 4; ++rt) {
+            const int ly = 2 * rt + (r >> 3), lx = r & 7;
+            const int hv = ((wave + 1 + dz) * HY + (ly + 1 + dy)) * HX + (lx + 1 + dx);
+            a[rt] = *(const v8bf*)&s_in[hv * CP + ko];
+          }
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct)
-            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
+            b[ct] = *(const v8bf*)&s_w[(tap * COUT + ct * 16 + r) * CP + ko];
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) acc[rt][ct] = mfma32(a[rt], b[ct], acc[rt][ct]);
+        } else {
+          v4s a[4], b[NCT];
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) {
+            const int ly = 2 * rt + (r >> 3), lx = r & 7;
+            const int hv = ((wave + 1 + dz) * HY + (ly + 1 + dy)) * HX + (lx + 1 + dx);
+            a[rt] = *(const v4s*)&s_in[hv * CP + ko];
+          }
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct)
+            b[ct] = *(const v4s*)&s_w[(tap * COUT + ct * 16 + r) * CP + ko];
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) acc[rt][ct] = mfma16(a[rt], b[ct], acc[rt][ct]);
+        }
       }
     }
     // lane holds D[row = 4 kq + i][col = r]
@@ -154,7 +218,7 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(const bf16raw* __restrict_
   constexpr int NRT = COUT / 16;
   constexpr int CPW = (NCOL + 3) / 4;
   constexpr int HVP = HV + 4;
-  constexpr int MP = 256 + 4;
+  constexpr int MP = 256 + 8;  // 16-byte aligned gradient rows
   constexpr int NW = 27 * COUT * CIN;
   __shared__ __align__(16) bf16raw s_inT[CIN * HVP];
   __shared__ __align__(16) bf16raw s_gT[COUT * MP];
@@ -197,12 +261,12 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(const bf16raw* __restrict_
     if (tid < COUT) {
       for (int m = 0; m < 256; ++m) bsum += bf2f(s_gT[tid * MP + m]);
     }
-    for (int ks = 0; ks < 16; ++ks) {
-      const int m0 = 16 * ks + 4 * kq;  // this lane's 4 voxels m0..m0+3 (same y-row)
-      const int lz = m0 >> 6, ly = (m0 >> 3) & 7, lx = m0 & 7;
-      v4s a[NRT];
+    for (int ks = 0; ks < 8; ++ks) {
+      const int m0 = 32 * ks + 8 * kq;  // this lane's 8 voxels m0..m0+7: one x-row
+      const int lz = m0 >> 6, ly = (m0 >> 3) & 7;
+      v8bf a[NRT];
 #pragma unroll
-      for (int rt = 0; rt < NRT; ++rt) a[rt] = *(const v4s*)&s_gT[(rt * 16 + r) * MP + m0];
+      for (int rt = 0; rt < NRT; ++rt) a[rt] = *(const v8bf*)&s_gT[(rt * 16 + r) * MP + m0];
 #pragma unroll
       for (int j = 0; j < CPW; ++j) {
         const int c = wave + 4 * j;
@@ -210,16 +274,13 @@ __global__ __launch_bounds__(256) void k_conv3d_wgrad(const bf16raw* __restrict_
           const int col = 16 * c + r;
           const int tap = col / CIN, ci = col % CIN;
           const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-          const int hv = ((lz + 1 + dz) * HY + (ly + 1 + dy)) * HX + (lx + 1 + dx);
+          const int hv = ((lz + 1 + dz) * HY + (ly + 1 + dy)) * HX + (1 + dx);
           const bf16raw* p = &s_inT[ci * HVP + hv];
-          v4s b;
-          b.x = (short)p[0];
-          b.y = (short)p[1];
-          b.z = (short)p[2];
-          b.w = (short)p[3];
+          v8bf b;
 #pragma unroll
-          for (int rt = 0; rt < NRT; ++rt)
-            acc[j][rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[rt], b, acc[j][rt], 0, 0, 0);
+          for (int e = 0; e < 8; ++e) b[e] = __builtin_bit_cast(__bf16, p[e]);
+#pragma unroll
+          for (int rt = 0; rt < NRT; ++rt) acc[j][rt] = mfma32(a[rt], b, acc[j][rt]);
         }
       }
     }
@@ -493,7 +554,10 @@ void cnn_free(Cnn& c) {
   c = Cnn();
 }
 
-static constexpr int kMaxConvBlocks = 256;
+// persistent grids: convolutions one 149 KB-LDS workgroup per CU, weight
+// gradients two 4-wave workgroups per CU (per-block partials: kMaxConvBlocks)
+static constexpr int kConvBlocks = 256;
+static constexpr int kMaxConvBlocks = 512;
 
 hipError_t cnn_ensure_ws(Cnn& c, size_t vox) {
   if (vox <= c.ws_vox) return hipSuccess;
@@ -524,8 +588,8 @@ hipError_t cnn_refresh_bf16(Cnn& c, hipStream_t s) {
 template <int CIN, int COUT, int MODE>
 static void conv(const ConvDims& cd, const bf16raw* in, const bf16raw* w, const float* bias,
                  bf16raw* ob, float* of, const bf16raw* ref, hipStream_t s) {
-  const int grid = cd.ntiles < kMaxConvBlocks ? cd.ntiles : kMaxConvBlocks;
-  k_conv3d<CIN, COUT, MODE><<<grid, 256, 0, s>>>(in, w, bias, ob, of, ref, cd);
+  const int grid = cd.ntiles < kConvBlocks ? cd.ntiles : kConvBlocks;
+  k_conv3d<CIN, COUT, MODE><<<grid, FNT, 0, s>>>(in, w, bias, ob, of, ref, cd);
 }
 
 template <int CIN, int COUT>
@@ -538,7 +602,7 @@ static void wgrad(const ConvDims& cd, const bf16raw* in, const bf16raw* g, float
 }
 
 hipError_t cnn_forward(Cnn& c, const int d[3], const bf16raw* feat, float* out, hipStream_t s) {
-  const ConvDims cd = conv_dims(d);
+  const ConvDims cd = conv_dims(d, FZ);
   hipError_t e = cnn_ensure_ws(c, (size_t)d[0] * d[1] * d[2]);
   if (e != hipSuccess) return e;
   c.act[0] = const_cast<bf16raw*>(feat);
@@ -555,7 +619,7 @@ hipError_t cnn_forward(Cnn& c, const int d[3], const bf16raw* feat, float* out, 
 
 hipError_t cnn_backward(Cnn& c, const int d[3], const float* target, float* loss_host,
                         hipStream_t s) {
-  const ConvDims cd = conv_dims(d);
+  const ConvDims cd = conv_dims(d, FZ), cw = conv_dims(d, TZ);
   const size_t nv = (size_t)d[0] * d[1] * d[2];
   const int lb = grid_for((int64_t)nv, 256) < 1024 ? grid_for((int64_t)nv, 256) : 1024;
   k_loss_partial<<<lb, 256, 0, s>>>(c.out, target, c.act[0], nv, c.loss + 2);
@@ -563,16 +627,16 @@ hipError_t cnn_backward(Cnn& c, const int d[3], const float* target, float* loss
   k_loss_grad<<<grid_for((int64_t)nv * 16), 256, 0, s>>>(c.out, target, c.act[0], c.loss, nv,
                                                          c.gbuf[0]);
   // layer 4 (32 -> 16): weight gradient, then data gradient masked by ReLU'
-  wgrad<32, 16>(cd, c.act[3], c.gbuf[0], c.wpart, c.g + c.off.w[3], s);
+  wgrad<32, 16>(cw, c.act[3], c.gbuf[0], c.wpart, c.g + c.off.w[3], s);
   conv<16, 32, 2>(cd, c.gbuf[0], c.wb + bf16_weight_offset(3), nullptr, c.gbuf[1], nullptr,
                   c.act[3], s);
-  wgrad<32, 32>(cd, c.act[2], c.gbuf[1], c.wpart, c.g + c.off.w[2], s);
+  wgrad<32, 32>(cw, c.act[2], c.gbuf[1], c.wpart, c.g + c.off.w[2], s);
   conv<32, 32, 2>(cd, c.gbuf[1], c.wb + bf16_weight_offset(2), nullptr, c.gbuf[0], nullptr,
                   c.act[2], s);
-  wgrad<32, 32>(cd, c.act[1], c.gbuf[0], c.wpart, c.g + c.off.w[1], s);
+  wgrad<32, 32>(cw, c.act[1], c.gbuf[0], c.wpart, c.g + c.off.w[1], s);
   conv<32, 32, 2>(cd, c.gbuf[0], c.wb + bf16_weight_offset(1), nullptr, c.gbuf[1], nullptr,
                   c.act[1], s);
-  wgrad<32, 32>(cd, c.act[0], c.gbuf[1], c.wpart, c.g + c.off.w[0], s);
+  wgrad<32, 32>(cw, c.act[0], c.gbuf[1], c.wpart, c.g + c.off.w[0], s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (loss_host) {
