@@ -3,15 +3,18 @@
 evaluate it against the plain start on held-out bodies.
 
 1. Data: bodies of the Pancharatnam-Berry fin-metasurface family on a
-   128^3 grid (seed 5), several random channels each (20 deg cap about +z,
-   random elliptical polarisation), solved by the library (FP32 product with
-   FP64 refinement, tol 1e-7).  Each (body, channel) gives one sample: the
-   network input features and the scaled solution, kept on the device.
+   128^3 grid (seed 5), random channels (20 deg cap about +z, random
+   elliptical polarisation), solved by the library to a true FP64 relative
+   residual of data_tol (BiCGSTAB, or the block-Jacobi FGMRES of the fast
+   path; FP32 products inside FP64 refinement).  Each (body, channel) gives
+   one sample: the network input features and the scaled solution, kept on
+   the device (about 53 MB per W128 sample).
 2. Training: Adam on the masked relative-L2 loss with the library's own
    forward/backward kernels, cosine learning-rate decay.
-3. Evaluation: held-out bodies (seed 55, the benchmark's bodies): iterations,
-   solves/s and fallback rate with and without the warm start, same
-   tolerance; the final FP64 true residual judges both.
+3. Evaluation: held-out bodies (seed 55, drawn like the benchmark's):
+   iterations, solves/s and fallback rate with and without
+   the warm start, same solver and tolerance, solved in chunks of `chunk`
+   bodies; the final FP64 true residual judges both.
 
 Writes the fp32 parameter vector (numpy .npy) and a JSON summary.
 """
@@ -37,28 +40,46 @@ def log(*a):
     print(*a, flush=True)
 
 
-def family(seed, nbodies, nch, n):
+def family(seed, nch, n):
+    """Bodies of the family with their nch channels each, drawn one at a time
+    from one generator (the same sequence however they are chunked)."""
     from synth import metasurface_family, random_planewave
 
     rng = np.random.default_rng(seed)
-    bodies, chans = [], []
-    for _ in range(nbodies):
+    while True:
         g, eps = metasurface_family(rng, n, 1.0 / 32 * 128 / n)
-        bodies.append((eps, g.h, g.origin))
-        for _ in range(nch):
-            chans.append(random_planewave(rng, cap_deg=20.0, elliptical=True))
+        chans = [random_planewave(rng, cap_deg=20.0, elliptical=True) for _ in range(nch)]
+        yield (eps, g.h, g.origin), chans
+
+
+def take(it, k):
+    bodies, chans = [], []
+    for _ in range(k):
+        b, c = next(it)
+        bodies.append(b)
+        chans += c
     return bodies, chans
 
 
-def generate(V, torch, bodies, chans, nch, chunk, tol):
+def solve_fn(V, solver):
+    """The solve call of `solver` ("bicgstab", or "fgmres": restart 60, 2 x 2
+    block-Jacobi, 8 inner GMRES steps in FP32, as the fast path)."""
+    if solver == "fgmres":
+        fo = V.fgmres_options(60, (2, 2), 8, V.VIE_MIXED)
+        return lambda ctx, cs, nr: V.vie_solve_fgmres(ctx, cs, nr, fo)
+    return lambda ctx, cs, nr: V.vie_solve(ctx, cs, nr)
+
+
+def generate(V, torch, it, nbodies, nch, chunk, tol, solver):
     samples = []
-    for c0 in range(0, len(bodies), chunk):
-        bs = bodies[c0:c0 + chunk]
-        cs = chans[c0 * nch:(c0 + len(bs)) * nch]
+    solve = solve_fn(V, solver)
+    t_start = time.perf_counter()
+    for c0 in range(0, nbodies, chunk):
+        bs, cs = take(it, min(chunk, nbodies - c0))
         t0 = time.perf_counter()
         ctx = V.vie_setup(bs, V.make_options(K0, precision=V.VIE_MIXED, tol=tol, max_iter=20000))
         try:
-            _, st = V.vie_solve(ctx, cs, [nch] * len(bs))
+            _, st = solve(ctx, cs, [nch] * len(bs))
             for b in range(len(bs)):
                 for q in range(nch):
                     d = V.vie_cnn_sample_dev(ctx, b, q)
@@ -68,8 +89,9 @@ def generate(V, torch, bodies, chans, nch, chunk, tol):
                     samples.append((d, ft, tt))
         finally:
             V.vie_destroy(ctx)
-        log(f"data: bodies {c0 + len(bs)}/{len(bodies)}, mean iters {np.mean([s['iters'] for s in st]):.0f}, "
-            f"{time.perf_counter() - t0:.1f} s")
+        log(f"data: bodies {c0 + len(bs)}/{nbodies}, mean iters {np.mean([s['iters'] for s in st]):.0f}, "
+            f"max rel res {max(s['rel_res'] for s in st):.2e}, {time.perf_counter() - t0:.1f} s "
+            f"(total {time.perf_counter() - t_start:.0f} s)")
     return samples
 
 
@@ -93,30 +115,49 @@ def train(V, torch, samples, epochs, lr, seed):
     return net, hist, time.perf_counter() - t0
 
 
-def evaluate(V, torch, net, bodies, chans, nch, tol, inner_tol):
-    out = {}
-    for name, warm in (("plain_start", 0), ("warm_start", 1)):
-        ctx = V.vie_setup(bodies, V.make_options(K0, precision=V.VIE_MIXED, tol=tol, max_iter=20000,
-                                                 inner_tol=inner_tol, warm_start=warm))
+def evaluate(V, torch, net, it, nbodies, nch, tol, inner_tol, solver, chunk):
+    """Solve the held-out bodies in chunks, one context per chunk (untimed
+    setup), with the plain and then the learned start: per start a warm-up
+    solve (autotuning, graph capture), then the timed solve."""
+    solve = solve_fn(V, solver)
+    legs = (("plain_start", 0), ("warm_start", 1))
+    st = {name: [] for name, _ in legs}
+    dt = {name: 0.0 for name, _ in legs}
+    nsol = 0
+    for c0 in range(0, nbodies, chunk):
+        bs, cs = take(it, min(chunk, nbodies - c0))
+        nsol += len(cs)
+        ctx = V.vie_setup(bs, V.make_options(K0, precision=V.VIE_MIXED, tol=tol, max_iter=20000,
+                                             inner_tol=inner_tol))
         try:
-            if warm:
-                V.vie_attach_cnn(ctx, net)
-            V.vie_solve(ctx, chans, [nch] * len(bodies))  # warm-up (autotuning)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, st = V.vie_solve(ctx, chans, [nch] * len(bodies))
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
+            V.vie_attach_cnn(ctx, net)
+            for name, warm in legs:
+                V.vie_set_options(ctx, V.make_options(K0, precision=V.VIE_MIXED, tol=tol,
+                                                      max_iter=20000, inner_tol=inner_tol,
+                                                      warm_start=warm))
+                solve(ctx, cs, [nch] * len(bs))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, s = solve(ctx, cs, [nch] * len(bs))
+                torch.cuda.synchronize()
+                dt[name] += time.perf_counter() - t0
+                st[name] += s
         finally:
             V.vie_destroy(ctx)
+        log(f"eval: bodies {c0 + len(bs)}/{nbodies}, mean iters plain "
+            f"{np.mean([x['iters'] for x in st['plain_start']]):.1f} warm "
+            f"{np.mean([x['iters'] for x in st['warm_start']]):.1f}")
+    out = {}
+    for name, warm in legs:
+        ss = st[name]
         out[name] = {
-            "solves_per_s": len(chans) / dt,
-            "iters_mean": float(np.mean([s["iters"] for s in st])),
-            "products_mean": float(np.mean([s["matvecs"] for s in st])),
-            "max_rel_res": float(max(s["rel_res"] for s in st)),
-            "converged": bool(all(s["converged"] for s in st)),
-            "fallback_rate": float(np.mean([s["fallback"] for s in st])) if warm else None,
-            "rel_res_x0_mean": float(np.mean([s["rel_res_x0"] for s in st])) if warm else 1.0,
+            "solves_per_s": nsol / dt[name],
+            "iters_mean": float(np.mean([x["iters"] for x in ss])),
+            "products_mean": float(np.mean([x["matvecs"] for x in ss])),
+            "max_rel_res": float(max(x["rel_res"] for x in ss)),
+            "converged": bool(all(x["converged"] for x in ss)),
+            "fallback_rate": float(np.mean([x["fallback"] for x in ss])) if warm else None,
+            "rel_res_x0_mean": float(np.mean([x["rel_res_x0"] for x in ss])) if warm else 1.0,
         }
         log(f"eval {name}: {out[name]}")
     out["iteration_ratio"] = out["warm_start"]["iters_mean"] / out["plain_start"]["iters_mean"]
@@ -138,6 +179,9 @@ def main():
     ap.add_argument("--data-tol", type=float, default=1e-7)
     ap.add_argument("--inner-tol", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--solver", choices=["bicgstab", "fgmres"], default="bicgstab",
+                    help="data generation and held-out evaluation")
+    ap.add_argument("--eval-chunk", type=int, default=8, help="held-out bodies per context")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--summary", default=None)
     args = ap.parse_args()
@@ -148,8 +192,8 @@ def main():
 
     torch.cuda.set_device(0)
     V.lib()
-    tb, tc = family(args.seed, args.train_bodies, args.channels, args.grid)
-    samples = generate(V, torch, tb, tc, args.channels, args.chunk, args.data_tol)
+    samples = generate(V, torch, family(args.seed, args.channels, args.grid), args.train_bodies,
+                       args.channels, args.chunk, args.data_tol, args.solver)
     net, hist, ttrain = train(V, torch, samples, args.epochs, args.lr, args.seed)
     p = V.vie_cnn_params(net)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
@@ -157,9 +201,11 @@ def main():
     log(f"saved {p.size} parameters to {args.out}")
     del samples
     torch.cuda.empty_cache()
-    hb, hc = family(55, args.heldout_bodies, args.heldout_channels, args.grid)
-    ev = evaluate(V, torch, net, hb, hc, args.heldout_channels, args.tol, args.inner_tol)
+    ev = evaluate(V, torch, net, family(55, args.heldout_channels, args.grid), args.heldout_bodies,
+                  args.heldout_channels, args.tol, args.inner_tol, args.solver, args.eval_chunk)
     summary = {"train_samples": args.train_bodies * args.channels, "epochs": args.epochs,
+               "train_bodies": args.train_bodies, "channels_per_body": args.channels,
+               "data_tol": args.data_tol, "solver": args.solver, "lr": args.lr,
                "train_seconds": ttrain, "loss_history": hist, "heldout": ev,
                "heldout_bodies": args.heldout_bodies, "heldout_channels": args.heldout_channels,
                "tol": args.tol}

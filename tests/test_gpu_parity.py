@@ -215,9 +215,10 @@ def test_error_paths(V):
     with pytest.raises(V.VieError) as e:
         V.vie_setup([(bad, g.h, g.origin)], V.make_options(K0))
     assert e.value.code == V.VIE_EINVAL
-    with pytest.raises(V.VieError) as e:
-        V.vie_setup([(np.ones((2, 2, 300)), g.h, g.origin)], V.make_options(K0))
-    assert e.value.code == V.VIE_ENOTSUP
+    for shape in [(300, 2, 2), (2, 2, 3100), (2, 3100, 2)]:  # N3 > 256, N1 or N2 > 3072
+        with pytest.raises(V.VieError) as e:
+            V.vie_setup([(np.ones(shape), g.h, g.origin)], V.make_options(K0))
+        assert e.value.code == V.VIE_ENOTSUP
     ctx = V.vie_setup([(eps, g.h, g.origin)], V.make_options(K0, tol=1e-12, max_iter=1))
     try:
         rc, st = V.vie_solve(ctx, [([0, 0, 1.0], [1, 0, 0])], [1], allow_noconv=True)
