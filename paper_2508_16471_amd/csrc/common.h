@@ -54,6 +54,15 @@ __host__ __device__ __forceinline__ cpx<D> cvt(cpx<S> a) {
   return mk((D)a.re, (D)a.im);
 }
 
+// Workgroup barrier for LDS exchanges: orders LDS accesses only, so global
+// loads issued before it (prefetches) stay in flight across it, unlike
+// __syncthreads, whose fence also waits for every outstanding global access.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Workgroups are handed to the 8 XCDs round-robin (block b -> XCD b % 8) and
 // each XCD has its own L2.  Remapping the linear block id makes neighbouring
 // tiles (which share cache lines or spectrum entries) run on one XCD at about

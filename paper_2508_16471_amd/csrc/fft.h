@@ -223,7 +223,7 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[E], cpx<T>* lds, int t,
 #pragma unroll
       for (int r = 0; r < RAD; ++r) v[b + r * NB] = u[b * RAD + r];
   } else {
-    __syncthreads();  // previous readers of lds are done
+    lds_barrier();  // previous readers of lds are done
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int j = t + b * TT;
@@ -231,7 +231,7 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&v)[E], cpx<T>* lds, int t,
 #pragma unroll
       for (int r = 0; r < RAD; ++r) lds[base + r * NS] = u[b * RAD + r];
     }
-    __syncthreads();
+    lds_barrier();
     fft_stages<T, P, E, NS * RAD, INV>(v, lds, t, tw);
   }
 }

@@ -127,7 +127,7 @@ __device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int
 #pragma unroll
       for (int r = 0; r < RAD; ++r) v[b + r * NB] = u[b * RAD + r];
   } else {
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int j = t + b * TT;
@@ -135,7 +135,7 @@ __device__ __forceinline__ void fft_stages_p(cpx<T> (&v)[E], LdsLine<T> lds, int
 #pragma unroll
       for (int r = 0; r < RAD; ++r) lds[base + r * NS] = u[b * RAD + r];
     }
-    __syncthreads();
+    lds_barrier();
     fft_stages_p<T, P, E, NS * RAD, INV, OFF + here, HIN, HOUT, GTW>(v, lds, t, w);
   }
 }

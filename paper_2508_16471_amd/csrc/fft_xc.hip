@@ -45,13 +45,13 @@ __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_fwd_c(
   // zero the line's first P/2 points (the padded half is never read)
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) myl[pidx(t + q * TT)] = mk<T>(0, 0);
-  __syncthreads();
+  lds_barrier();
   if (valid) {
     const int k1 = lp[zy + 1];
     const int base = zy * N1;
     for (int k = lp[zy] + t; k < k1; k += TT) myl[pidx(vox[k] - base)] = cvt<T>(xv[k]);
   }
-  __syncthreads();
+  lds_barrier();
   cpx<T> v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) v[q] = (q < E / 2) ? myl[pidx(t + q * TT)] : mk<T>(0, 0);
@@ -96,10 +96,10 @@ __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_inv_c(
   }
   cpx<T>* myl = lds + li * LS;
   line_fft<T, P, true, false, true>(v, myl, t, tr);  // only x < N1 is used
-  __syncthreads();  // every thread has left the FFT's last LDS read
+  lds_barrier();  // every thread has left the FFT's last LDS read
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) myl[pidx(t + q * TT)] = v[q];
-  __syncthreads();
+  lds_barrier();
   const int comp = lc / lpc, zy = lc % lpc;
   const int body = bi.rhs_body[rhs];
   const int nb = bi.nb[body];
