@@ -215,8 +215,8 @@ int hom_g2(const vie_c64 T[4], const double *omega, double sigma, const double *
            int32_t ndelay, int32_t norm, double *g2, double *Nc_raw, double *Nc_norm);
 
 /* The grid a body is computed on.  With VIE_FLAG_Z_WINDOW a group of bodies
- * sharing (n, h) computes on a window of z layers of their grid: the layers
- * holding any of its bodies' voxels plus a 4-layer margin, clipped.  Voxels
+ * sharing (n, h) computes on a window of z layers of their grid: as many
+ * layers as the tallest body's z extent, placed per body over its voxels.  Voxels
  * outside have chi = 0, so the system for the body's unknowns (and every
  * solve, current and far field) is that of the full grid.  Box vectors at the
  * ABI (vie_matvec, vie_get_current) stay in the body's grid; vie_matvec then

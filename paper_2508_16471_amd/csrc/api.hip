@@ -473,8 +473,8 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
         zmax = std::max(zmax, z);
       }
     if (zmax < 0) zmin = zmax = 0;  // no body voxel: a one-layer window
-    zlo_of[b] = std::max(0, zmin - 4);
-    zhi_of[b] = std::min(B.n[2], zmax + 1 + 4);
+    zlo_of[b] = zmin;
+    zhi_of[b] = zmax + 1;
     if (!(opt->flags & VIE_FLAG_Z_WINDOW)) {
       zlo_of[b] = 0;
       zhi_of[b] = B.n[2];
@@ -527,8 +527,11 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
     G.nb_host.push_back(rec->nb);
     G.max_nb = std::max(G.max_nb, rec->nb);
     G.vox_host.insert(G.vox_host.end(), vox.begin(), vox.end());
-    {  // network box: bounding box of the body voxels, 4-voxel halo, clipped
+    {  // network box: bounding box of the body voxels with a 4-voxel halo,
+       // clipped to the body's grid (not the window: layers outside the window
+       // hold no body voxel, so their features are zero as on the full grid)
       const int* N = G.g.N;
+      const int off[3] = {0, 0, rec->zoff};
       int lo[3] = {N[0], N[1], N[2]}, hi[3] = {0, 0, 0};
       for (int v : vox) {
         const int c[3] = {v % N[0], (v / N[0]) % N[1], v / (N[0] * N[1])};
@@ -542,8 +545,8 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
           lo[a] = 0;
           hi[a] = 1;
         }
-        lo[a] = std::max(0, lo[a] - 4);
-        hi[a] = std::min(N[a], hi[a] + 4);
+        lo[a] = std::max(0, lo[a] + off[a] - 4) - off[a];
+        hi[a] = std::min(G.N0[a], hi[a] + off[a] + 4) - off[a];
         G.box_lo.push_back(lo[a]);
         G.box_d.push_back(hi[a] - lo[a]);
       }

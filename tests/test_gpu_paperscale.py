@@ -3,7 +3,7 @@ GPU: a 40 x 12 x 2 wavelength box at 62 cells per wavelength (2480 x 744 x
 124 voxels), 91 x 27 silicon nanofins with the PB rotation of eq. 32 on a
 glass substrate: 17.5 M body voxels, 52.5 M unknowns (the paper: 18.0 M
 elements, 54.0 M unknowns).  The context computes on the z window that holds
-the body (2480 x 744 x 43, FFT 6144 x 1536 x 96: x lines of 6144 = 3 * 2^11
+the body (2480 x 744 x 35, FFT 6144 x 1536 x 96: x lines of 6144 = 3 * 2^11
 points).  The operator product of a random body-supported vector, FP64 and
 FP32 on the device, equals the oracle's direct O(N_b) sums on sampled rows
 (rel. 1e-12 / 5e-6).  Setup time and device memory are printed.

@@ -1,6 +1,5 @@
 """GPU parity of the z window (VIE_FLAG_Z_WINDOW): a grid group computed on
-the z layers that hold its bodies (plus a 4-layer margin) instead of the whole
-grid.  Voxels outside the window have chi = 0, so the system of the body's
+the z layers that hold its bodies instead of the whole grid.  Voxels outside the window have chi = 0, so the system of the body's
 unknowns is unchanged; the checks are against the oracle on the full grid.
 
 * vie_grid reports the window, its FFT lengths and each body's offset;
@@ -66,12 +65,12 @@ def test_window_geometry_and_product(V):
     ctx = V.vie_setup([(eps, H, g.origin)], V.make_options(K0, flags=V.VIE_FLAG_Z_WINDOW))
     try:
         grid, fft, off = V.vie_grid(ctx, 0)
-        assert grid == (14, 12, 16) and off == (0, 0, 11) and fft[2] == 32
+        assert grid == (14, 12, 8) and off == (0, 0, 15) and fft[2] == 16
         y64 = V.vie_matvec(ctx, 0, xb, V.VIE_FP64)
         y32 = V.vie_matvec(ctx, 0, xb, V.VIE_MIXED)
         # outside the window the input passes through
         xo = x.copy()
-        xo[:, 11:27] = 0
+        xo[:, 15:23] = 0
         yo = V.vie_matvec(ctx, 0, xo, V.VIE_FP64)
     finally:
         V.vie_destroy(ctx)
@@ -132,7 +131,7 @@ def test_window_precond_apply_matches_oracle(V):
     bset = pc.block_index_sets(pc.lateral_blocks(g.n, *blocks)[body])
     ctx = V.vie_setup([(eps, H, g.origin)], V.make_options(K0, flags=V.VIE_FLAG_Z_WINDOW))
     try:
-        assert V.vie_grid(ctx, 0)[2] == (0, 0, 11)
+        assert V.vie_grid(ctx, 0)[2] == (0, 0, 15)
         z = V.vie_precond_apply(ctx, V.fgmres_options(blocks=blocks, inner_iters=k,
                                                       inner_precision=V.VIE_FP64), r)
     finally:
