@@ -203,7 +203,7 @@ __device__ __forceinline__ float4 pair_out(int odd, const cpx<float>& a, const c
 // rounded up to a multiple of 16 equals P/2) and the column tiles cover P1
 // exactly, so the blocked offsets are shifts and no column needs a bounds
 // test.  ZP (FAST with N3 < P/2): rows N3 .. P/2-1 of the layout are padding
-// that nothing else reads; they are loaded as zeros and written freely.
+// that nothing else reads; they are taken as zeros and never stored.
 template <typename T, int P, int E, int NT, bool FAST, bool ZP>
 __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
                                              const cpx<T>* __restrict__ spec,
@@ -338,9 +338,15 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
     for (int k = 0; k < E / 4; ++k) {
       const int zr = t + (2 * k + odd) * TT;
       const int off = 2 * ((zr >> 4) * (int)a.zhs + (zr & 15) * (int)a.zls);
-      *reinterpret_cast<float4*>(cp + off) = pair_out(odd, v0[2 * k], v0[2 * k + 1]);
-      *reinterpret_cast<float4*>(cp1 + off) = pair_out(odd, v1[2 * k], v1[2 * k + 1]);
-      *reinterpret_cast<float4*>(cp2 + off) = pair_out(odd, v2[2 * k], v2[2 * k + 1]);
+      // the lane swaps run on every lane; padding rows are not stored
+      const float4 o0 = pair_out(odd, v0[2 * k], v0[2 * k + 1]);
+      const float4 o1 = pair_out(odd, v1[2 * k], v1[2 * k + 1]);
+      const float4 o2 = pair_out(odd, v2[2 * k], v2[2 * k + 1]);
+      if (!ZP || zr < a.N3) {
+        *reinterpret_cast<float4*>(cp + off) = o0;
+        *reinterpret_cast<float4*>(cp1 + off) = o1;
+        *reinterpret_cast<float4*>(cp2 + off) = o2;
+      }
     }
     return;
   }
@@ -348,7 +354,7 @@ __device__ __forceinline__ void z_green_body(cpx<T>* __restrict__ B,
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
       const int z = t + q * TT;
-      if (FAST || z < a.N3) {
+      if ((FAST && !ZP) || z < a.N3) {
         col[zoff[q]] = v0[q];
         col1[zoff[q]] = v1[q];
         col2[zoff[q]] = v2[q];
