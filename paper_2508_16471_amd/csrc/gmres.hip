@@ -47,13 +47,24 @@ __global__ __launch_bounds__(GT) void k_seg_mdot(SegSet S, const TV* __restrict_
       for (int u = 0; u < GU; ++u)
         if (i0 + u < nv) acc[u] = acc[u] + cmulc(ld64(V + (int64_t)(i0 + u) * stride + off + e), we);
     }
+    // Reduce-scatter across the wave: at each of the first three steps a
+    // lane keeps half of its sums (the half selected by that lane bit) and
+    // adds its partner's copy of them, so 4 + 2 + 1 exchanges replace 3 x 8;
+    // the last three steps sum the one remaining value.  Lane 8 v then holds
+    // the wave's sum for basis vector v (v = lane bits 5, 4, 3).
+    static_assert(GU == 8, "reduce-scatter over 8 sums");
 #pragma unroll
-    for (int u = 0; u < GU; ++u)
-      for (int m = 32; m >= 1; m >>= 1) acc[u] = acc[u] + shfl_xor_c(acc[u], m);
-    if (lane == 0) {
+    for (int h = 4, m = 32; h >= 1; h >>= 1, m >>= 1) {
+      const bool up = (lane & m) != 0;
 #pragma unroll
-      for (int u = 0; u < GU; ++u) red[wv][u] = acc[u];
+      for (int u = 0; u < h; ++u) {
+        const c64 keep = up ? acc[h + u] : acc[u], give = up ? acc[u] : acc[h + u];
+        acc[u] = keep + shfl_xor_c(give, m);
+      }
     }
+#pragma unroll
+    for (int m = 4; m >= 1; m >>= 1) acc[0] = acc[0] + shfl_xor_c(acc[0], m);
+    if ((lane & 7) == 0) red[wv][lane >> 3] = acc[0];
     __syncthreads();
     if (threadIdx.x < GU && i0 + (int)threadIdx.x < nv) {
       c64 t = red[0][threadIdx.x];
