@@ -25,6 +25,9 @@ __device__ __forceinline__ c64 ld64(const c64* p) { return *p; }
 __device__ __forceinline__ c64 ld64(const c32* p) { return cvt<double>(*p); }
 __device__ __forceinline__ void st(c64* p, c64 v) { *p = v; }
 __device__ __forceinline__ void st(c32* p, c64 v) { *p = cvt<float>(v); }
+// v as stored in a T vector (rounded to FP32 for c32), without a reload
+__device__ __forceinline__ c64 stored(const c64*, c64 v) { return v; }
+__device__ __forceinline__ c64 stored(const c32*, c64 v) { return cvt<double>(cvt<float>(v)); }
 
 template <typename TV, typename TW>
 __global__ __launch_bounds__(GT) void k_seg_mdot(SegSet S, const TV* __restrict__ V,
@@ -41,7 +44,20 @@ __global__ __launch_bounds__(GT) void k_seg_mdot(SegSet S, const TV* __restrict_
     c64 acc[GU];
 #pragma unroll
     for (int u = 0; u < GU; ++u) acc[u] = mk(0.0, 0.0);
-    for (int e = blk * GT + threadIdx.x; e < len; e += S.nblk * GT) {
+    // two elements per iteration (twice the loads in flight), then the tail
+    const int step = S.nblk * GT;
+    int e = blk * GT + threadIdx.x;
+    for (; e + step < len; e += 2 * step) {
+      const c64 wa = ld64(w + off + e), wb = ld64(w + off + e + step);
+#pragma unroll
+      for (int u = 0; u < GU; ++u)
+        if (i0 + u < nv) {
+          const TV* vu = V + (int64_t)(i0 + u) * stride + off + e;
+          acc[u] = acc[u] + cmulc(ld64(vu), wa);
+          acc[u] = acc[u] + cmulc(ld64(vu + step), wb);
+        }
+    }
+    if (e < len) {
       const c64 we = ld64(w + off + e);
 #pragma unroll
       for (int u = 0; u < GU; ++u)
@@ -112,7 +128,7 @@ __global__ __launch_bounds__(GT) void k_seg_maxpy(SegSet S, const TV* __restrict
     for (int i = 0; i < n; ++i) a = a - cf[i] * ld64(V + (int64_t)i * stride + off + e);
     if (n > 0) {
       st(w + off + e, a);
-      a = ld64(w + off + e);  // the norm of what is stored (rounded when w is FP32)
+      a = stored(w, a);  // the norm of what is stored (rounded when w is FP32)
     }
     nr += a.re * a.re + a.im * a.im;
   }
