@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--restart", type=int, default=60, help="FGMRES steps per cycle")
     ap.add_argument("--blocks", default="2,2", help="FGMRES lateral block partition bx,by")
     ap.add_argument("--inner-iters", type=int, default=8, help="GMRES steps per block solve")
+    ap.add_argument("--block-basis", choices=["fp32", "bf16"], default="bf16",
+                    help="storage of the block solves' Arnoldi basis (FP32 products either way)")
     ap.add_argument("--precond-body", choices=["family", "metasurface"], default="family",
                     help="precond mode: the benchmark family (--bodies x --channels) or the "
                          "256x256x48 PB metasurface (one body, --channels uv directions x L/R)")
@@ -143,13 +145,14 @@ def fft_length(n):
     return min(p2, p3)
 
 
-def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None, vb=16):
+def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None, vb=16, vin=None):
     """Algorithmic HBM bytes of one right-hand-side execution of a pass
     (spectrum excluded; it is charged once per launch).  nb: body voxels when
     the solver's vectors are body-compressed (x passes read/write 3 nb
     values plus the voxel index and line pointers), None for box vectors.
     vb: bytes of a vector element (16, or 8 for the FP32 vectors of the
-    FGMRES products)."""
+    FGMRES products); vin: bytes of an input-vector element when it differs
+    (4 for the bfloat16 basis vectors the block products read)."""
     N1, N2, N3 = N
     P1, P2, P3 = P
     n = N1 * N2 * N3
@@ -158,7 +161,7 @@ def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None, vb=16):
     B = 3 * N3 * P2 * P1
     if kind.startswith("fft_x_fwd"):
         if nb is not None:
-            return 3 * nb * (vb + 4) + 3 * (N2 * N3 + 1) * 4 + A * c
+            return 3 * nb * ((vin or vb) + 4) + 3 * (N2 * N3 + 1) * 4 + A * c
         return 3 * n * 16 + A * c
     if kind.startswith("fft_y_fwd"):
         return A * c + B * c
@@ -168,7 +171,7 @@ def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None, vb=16):
         return B * c + A * c
     if kind.startswith("fft_x_inv"):
         if nb is not None:
-            return A * c + 3 * nb * (vb * 2 + 8 + 4) + 3 * (N2 * N3 + 1) * 4 + epi_extra
+            return A * c + 3 * nb * (vb + (vin or vb) + 8 + 4) + 3 * (N2 * N3 + 1) * 4 + epi_extra
         return A * c + 3 * n * 16 * 2 + n * 8 + epi_extra
     raise KeyError(kind)
 
@@ -239,12 +242,13 @@ def block_geometry(bodies, blocks):
             "nb_mean": float(np.mean(nbv)) if nbv else 0.0}
 
 
-def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch):
+def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch, block_vin=8):
     """Achieved GB/s of every FFT pass of the FGMRES solve: FP32 outer
     products (one per Arnoldi step), FP64 true-residual products (one per
     cycle) and the FP32 block products (k per step, one execution per block
     of the right-hand side's body).  FP32 products read and write FP32
-    vectors."""
+    vectors, except that block products read their bfloat16 basis vectors
+    (block_vin = 4)."""
     iters = np.array([s["iters"] for s in stats])
     cyc = np.array([s["cycles"] for s in stats])
     per_step = len(geom["blocks_per_body"]) * nch  # stats repeat once per timed step
@@ -265,7 +269,8 @@ def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch):
             execs = int(iters.sum()) if f32 else int(cyc.sum())
             launches_active = int(iters.max()) if f32 else int(cyc.max())
         extra = 3 * nbk * 16 if (base.startswith("fft_x_inv") and not f32 and not blk) else 0
-        by = execs * kernel_bytes(base, Nk, Pk, Qk, extra, nb=nbk, vb=8 if f32 else 16)
+        by = execs * kernel_bytes(base, Nk, Pk, Qk, extra, nb=nbk, vb=8 if f32 else 16,
+                                  vin=block_vin if (blk and f32) else None)
         if base.startswith("fft_z_green"):
             by += launches_active * spectrum_bytes(base, Qk)
         rows[kind] = {"ms_total": ms, "launches": int(cnt), "rhs_execs": execs,
@@ -274,15 +279,17 @@ def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch):
     return rows
 
 
-def arnoldi_bytes(stats, nbv, nch, restart, k):
+def arnoldi_bytes(stats, nbv, nch, restart, k, block_vb=8):
     """Algorithmic HBM bytes of the FGMRES Gram-Schmidt kernels (timing kind
     "arnoldi": one classical Gram-Schmidt pass per step in the mixed path,
-    FP32 basis and work vector): at step j of a cycle, per vector element,
-    the multi-dot reads V_0..V_j and w, the multi-axpy reads V_0..V_j and w
-    and writes w, the normalisation reads w and writes V_{j+1}:
-    (16 j + 56) bytes.  Outer process: every cycle's steps; block solves:
-    k steps per outer step over the same elements (the blocks partition the
-    body).  nbv: body voxels of each body, stats in body-major order."""
+    FP32 work vector, basis elements of vb bytes): at step j of a cycle, per
+    vector element, the multi-dot reads V_0..V_j and w, the multi-axpy reads
+    V_0..V_j and w and writes w, the normalisation reads w and writes
+    V_{j+1}: 2 vb j + 3 vb + 32 bytes (16 j + 56 with the FP32 basis).
+    Outer process (FP32 basis): every cycle's steps; block solves (basis of
+    block_vb bytes: 8, or 4 in bfloat16): k steps per outer step over the
+    same elements (the blocks partition the body).  nbv: body voxels of each
+    body, stats in body-major order."""
     total = 0.0
     per = len(nbv) * nch
     for i, st in enumerate(stats):
@@ -291,7 +298,7 @@ def arnoldi_bytes(stats, nbv, nch, restart, k):
         full, rem = divmod(steps, restart)
         cyc = [restart] * full + ([rem] if rem else [])
         outer = sum(8 * c * (c - 1) + 56 * c for c in cyc)
-        inner = steps * (8 * k * (k - 1) + 56 * k)
+        inner = steps * (block_vb * k * (k - 1) + (3 * block_vb + 32) * k)
         total += n * (outer + inner)
     return total
 
@@ -1176,7 +1183,8 @@ def main():
 
     use_fgmres = args.solver == "fgmres"
     blocks = tuple(int(v) for v in args.blocks.split(","))
-    fo = V.fgmres_options(args.restart, blocks, args.inner_iters, V.VIE_MIXED)
+    inner_prec = V.VIE_MIXED_BF16 if args.block_basis == "bf16" else V.VIE_MIXED
+    fo = V.fgmres_options(args.restart, blocks, args.inner_iters, inner_prec)
     geom = block_geometry(bodies, blocks) if use_fgmres else None
 
     def solve():
@@ -1219,7 +1227,8 @@ def main():
     iters_match = [s["iters"] for s in inst_stats] == [s["iters"] for s in all_stats]
     nb_mean = float(np.mean([(e > 1).sum() for e, _, _, _ in bodies]))
     if use_fgmres:
-        fast_rows = roofline_fgmres(times, inst_stats, N, P, Q, nb_mean, geom, args.inner_iters, nch)
+        fast_rows = roofline_fgmres(times, inst_stats, N, P, Q, nb_mean, geom, args.inner_iters, nch,
+                                    block_vin=4 if args.block_basis == "bf16" else 8)
     else:
         fast_rows = roofline_from_times(times, inst_stats, N, P, Q, mixed=True, nb=nb_mean)
     dom = max(fast_rows, key=lambda k: fast_rows[k]["ms_total"])
@@ -1240,10 +1249,14 @@ def main():
     if use_fgmres and "arnoldi" in times:
         a_ms = times["arnoldi"][0]
         a_by = arnoldi_bytes(inst_stats, [int((e != 1.0).sum()) for e, _, _, _ in bodies], nch,
-                             args.restart, args.inner_iters)
+                             args.restart, args.inner_iters,
+                             block_vb=4 if args.block_basis == "bf16" else 8)
         arn = {"ms_total": a_ms, "launches": int(times["arnoldi"][1]), "bytes": a_by,
                "GBps": a_by / (a_ms * 1e-3) / 1e9, "frac": a_by / (a_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-               "model": "16 j + 56 bytes per element at Gram-Schmidt step j (FP32 basis and w)"}
+               "model": ("2 vb j + 3 vb + 32 bytes per element at Gram-Schmidt step j (FP32 w; "
+                         "basis element vb = 8 B outer, " +
+                         ("4 B (bfloat16)" if args.block_basis == "bf16" else "8 B") +
+                         " in the block solves)")}
     conv = all(s["converged"] for s in all_stats)
     max_res = max(s["rel_res"] for s in all_stats)
     prod_fast = np.mean([s["matvecs"] for s in all_stats])
@@ -1322,6 +1335,7 @@ def main():
                    "solver": ({"method": "FGMRES, block-Jacobi right preconditioner",
                                "restart": args.restart, "blocks": list(blocks),
                                "inner_gmres_steps": args.inner_iters,
+                               "block_basis": args.block_basis,
                                "block_grid": list(geom["N"]), "block_fft": list(geom["P"]),
                                "blocks_per_body": geom["blocks_per_body"]}
                               if use_fgmres else {"method": "BiCGSTAB with FP64 refinement",

@@ -68,7 +68,13 @@ enum vie_status {
   VIE_ESTATE = -6   /* call on a poisoned / unprepared context               */
 };
 
-enum { VIE_FP64 = 0, VIE_MIXED = 1 };
+/* VIE_MIXED_BF16 (inner_precision of vie_solve_fgmres only): FP32 block
+ * products as VIE_MIXED, with the block solves' Arnoldi basis stored in
+ * bfloat16 (8-bit significand; dots and updates in FP64, work vector FP32).
+ * The block solves only approximate M^{-1}, so the basis' rounding (a few
+ * 1e-3 relative) leaves the preconditioner about as good while the basis
+ * traffic halves; the FP64 outer residual still decides convergence. */
+enum { VIE_FP64 = 0, VIE_MIXED = 1, VIE_MIXED_BF16 = 2 };
 enum { VIE_NORM_R1 = 0, VIE_NORM_R2 = 1 };
 enum {
   VIE_FLAG_TIMING = 1,  /* record per-kernel HIP-event durations (disables graphs) */
@@ -160,7 +166,8 @@ typedef struct {
   int32_t restart;         /* Arnoldi steps per cycle, 1..128                      */
   int32_t blocks[2];       /* bx, by: each 1..64 and at most N1 (N2); or {0, 0}    */
   int32_t inner_iters;     /* GMRES steps of every block solve, 1..64              */
-  int32_t inner_precision; /* VIE_FP64 or VIE_MIXED: block products in FP64/FP32  */
+  int32_t inner_precision; /* VIE_FP64 / VIE_MIXED: block products in FP64 / FP32; */
+                           /* VIE_MIXED_BF16: FP32 products, bfloat16 basis     */
 } vie_fgmres_options;
 
 /* Solve like vie_solve (same channels, stats, solution storage and return

@@ -145,7 +145,8 @@ struct ArnoldiBufs {
   // least squares on the device (LsBufs) and the per-segment step counters
   DevBuf lsR, lscs, lssn, lsg, lsnst, mc, steps, cycles, anyf;
   int ls_m = 0;     // columns the least-squares buffers hold
-  int v32 = 0;      // V and Z stored in FP32 (mixed precision) instead of FP64
+  int v32 = 0;      // V and Z stored in FP32 (mixed precision) instead of FP64; 2: V in
+                    // bfloat16 (block solves), w FP32
   // captured step chunks of the outer FGMRES (graph per first step, valid
   // while `key` matches every pointer and size the capture used)
   std::vector<hipGraphExec_t> chunk_exec;
@@ -158,7 +159,8 @@ struct ArnoldiBufs {
   }
   // address of vector j of a multi-vector with `stride` elements per vector
   void* at(const DevBuf& b, int64_t j, int64_t stride) const {
-    return (char*)b.p + (size_t)j * stride * (v32 ? sizeof(c32) : sizeof(c64));
+    const size_t es = v32 == 2 ? sizeof(cb16) : v32 ? sizeof(c32) : sizeof(c64);
+    return (char*)b.p + (size_t)j * stride * es;
   }
   LsBufs ls() const {
     LsBufs L;
@@ -1267,7 +1269,8 @@ static bool valid_fgmres(const vie_fgmres_options* fo, const GroupGeom& g) {
   for (int a = 0; a < 2; ++a)
     if (fo->blocks[a] < 1 || fo->blocks[a] > 64 || fo->blocks[a] > g.N[a]) return false;
   if (fo->inner_iters < 1 || fo->inner_iters > 64) return false;
-  return fo->inner_precision == VIE_FP64 || fo->inner_precision == VIE_MIXED;
+  return fo->inner_precision == VIE_FP64 || fo->inner_precision == VIE_MIXED ||
+         fo->inner_precision == VIE_MIXED_BF16;
 }
 
 // Storage of an Arnoldi process of m steps over nseg segments of at most
@@ -1324,8 +1327,9 @@ static int arnoldi_tables(vie_ctx* ctx, ArnoldiBufs& A, const std::vector<int64_
 static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, int64_t stride,
                                int m, int j, double eta2) {
   const void* V = A.V.p;
-  const int v32 = A.v32;
-  void* w = A.w.p;  // FP32 when the basis is (the products then write FP32)
+  const int v32 = A.v32;       // basis storage (0 FP64, 1 FP32, 2 bfloat16)
+  const int w32 = v32 ? 1 : 0;
+  void* w = A.w.p;  // FP32 when the basis is not FP64 (the products then write FP32)
   const int ldh = m + 1;
   c64* h1 = A.H1.as<c64>() + (size_t)j * S.nseg * (m + 1);
   c64* h2 = A.H2.as<c64>() + (size_t)j * S.nseg * (m + 1);
@@ -1334,27 +1338,27 @@ static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, in
   SegSet S2 = S;
   S2.active = A.act2.as<int>();
   hipError_t e;
-  if (eta2 > 0 && (e = launch_seg_maxpy(S, nullptr, 0, 0, 0, nullptr, nullptr, 0, w, v32, npart,
+  if (eta2 > 0 && (e = launch_seg_maxpy(S, nullptr, 0, 0, 0, nullptr, nullptr, 0, w, w32, npart,
                                          A.W2.as<double>(), 1, ctx->stream)) != hipSuccess)
     return e;
-  if ((e = launch_seg_mdot(S, V, v32, stride, j + 1, w, v32, A.dpart.as<c64>(), h1, ldh,
+  if ((e = launch_seg_mdot(S, V, v32, stride, j + 1, w, w32, A.dpart.as<c64>(), h1, ldh,
                            ctx->stream)) != hipSuccess)
     return e;
-  if ((e = launch_seg_maxpy(S, V, v32, stride, j + 1, nullptr, h1, ldh, w, v32, npart, nr, m + 1,
+  if ((e = launch_seg_maxpy(S, V, v32, stride, j + 1, nullptr, h1, ldh, w, w32, npart, nr, m + 1,
                             ctx->stream)) != hipSuccess)
     return e;
   if (eta2 > 0) {  // otherwise there is no second pass (and H2 is not read)
     if ((e = launch_seg_reorth_flags(S, A.W2.as<double>(), nr, m + 1, eta2, A.act2.as<int>(),
                                      ctx->stream)) != hipSuccess)
       return e;
-    if ((e = launch_seg_mdot(S2, V, v32, stride, j + 1, w, v32, A.dpart.as<c64>(), h2, ldh,
+    if ((e = launch_seg_mdot(S2, V, v32, stride, j + 1, w, w32, A.dpart.as<c64>(), h2, ldh,
                              ctx->stream)) != hipSuccess)
       return e;
-    if ((e = launch_seg_maxpy(S2, V, v32, stride, j + 1, nullptr, h2, ldh, w, v32, npart, nr, m + 1,
+    if ((e = launch_seg_maxpy(S2, V, v32, stride, j + 1, nullptr, h2, ldh, w, w32, npart, nr, m + 1,
                               ctx->stream)) != hipSuccess)
       return e;
   }
-  return launch_seg_normalize(S, w, v32, nr, m + 1, A.at(A.V, j + 1, stride), v32, ctx->stream);
+  return launch_seg_normalize(S, w, w32, nr, m + 1, A.at(A.V, j + 1, stride), v32, ctx->stream);
 }
 
 // Block partition of every body of group G into bx x by lateral blocks:
@@ -1573,15 +1577,16 @@ static int bj_apply(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo, co
   Group& Gp = *sub->groups[0];
   ArnoldiBufs& A = P.ab;
   const int k = fo->inner_iters;
-  const int ip = fo->inner_precision == VIE_MIXED ? 1 : 0;
+  const int ip = fo->inner_precision == VIE_FP64 ? 0 : 1;  // block product precision
   const int nseg = P.nseg;
   const int64_t tot = P.tot;
   if (A.ls_m < k) return VIE_ESTATE;  // bj_prepare sizes the storage first
   SegSet S{A.off.as<int64_t>(), A.len.as<int>(), A.act.as<int>(), nseg, seg_blocks(P.maxlen)};
   VIE_HIP(launch_seg_act_map(nseg, P.seg_rhs_dev.as<int>(), act_rhs, A.act.as<int>(),
                              ctx->stream));
-  // with FP32 block products the block basis is stored in FP32 too
-  A.v32 = ip;
+  // with FP32 block products the block basis is stored in FP32, or in
+  // bfloat16 for VIE_MIXED_BF16; the work vector is FP32 either way
+  A.v32 = fo->inner_precision == VIE_MIXED_BF16 ? 2 : ip;
   c64* R = P.R.as<c64>();
   double* NR = A.NR.as<double>();
   const int ldn = k + 1;
@@ -1619,7 +1624,7 @@ static int bj_prepare(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo) 
   if (rc != VIE_OK) return rc;
   vie_ctx* sub = P.sub;
   sub->stream = ctx->stream;
-  VIE_HIP(tune_z(sub, *sub->groups[0], fo->inner_precision == VIE_MIXED ? 1 : 0));
+  VIE_HIP(tune_z(sub, *sub->groups[0], fo->inner_precision == VIE_FP64 ? 0 : 1));
   return VIE_OK;
 }
 

@@ -14,6 +14,7 @@ struct __align__(2 * sizeof(T)) cpx {
 };
 using c64 = cpx<double>;
 using c32 = cpx<float>;
+using cb16 = cpx<__bf16>;  // storage only (Arnoldi basis of the block solves)
 
 template <typename T>
 __host__ __device__ __forceinline__ cpx<T> mk(T r, T i) {

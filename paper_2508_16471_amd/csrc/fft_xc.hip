@@ -64,9 +64,10 @@ __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_fwd_c(
 }
 
 // ------------------------------------------------ X inverse + epilogue
-template <typename T, int P, int MODE, typename TIO>
+// TX: storage of the input vector (the epilogue's x), TIO of the output.
+template <typename T, int P, int MODE, typename TIO, typename TX = TIO>
 __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_inv_c(
-    const cpx<T>* __restrict__ A, const cpx<TIO>* __restrict__ xin, cpx<TIO>* __restrict__ yout,
+    const cpx<T>* __restrict__ A, const cpx<TX>* __restrict__ xin, cpx<TIO>* __restrict__ yout,
     const cpx<T>* __restrict__ tw, BodyIdx bi, int N1, int N2, int N3, int blocks_per_rhs,
     c64* __restrict__ aux, c64* __restrict__ partials, const c64* __restrict__ pol,
     const c64* __restrict__ ph, const int* __restrict__ active) {
@@ -160,7 +161,14 @@ hipError_t x_fwd_c(const GroupGeom& g, const void* xc, int in32, cpx<T>* A, cons
   const int L = lines_per_block<T>(g.P[0]);
   const int bpr = (lines + L - 1) / L;
   const dim3 grid(bpr * g.nrhs);
-  if (in32) {
+  if (in32 == 2) {  // bfloat16 input (FP32 products only)
+    if constexpr (sizeof(T) == 4) {
+      VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd_c<T, PP, __bf16><<<grid, nt_lines_p<T>(PP), 0, s>>>(
+                                 (const cb16*)xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active)));
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else if (in32) {
     VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd_c<T, PP, float><<<grid, nt_lines_p<T>(PP), 0, s>>>(
                                (const c32*)xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active)));
   } else {
@@ -179,8 +187,19 @@ hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const void* x, void* y, 
   const int bpr = (lines + L - 1) / L;
   e.part_blocks = bpr;
   const dim3 grid(bpr * g.nrhs);
-  if (io32) {  // FP32 vectors: the plain product only
+  if (io32) {  // FP32 output (input FP32, or bfloat16 for io32 = 2): the plain product only
     if (e.mode != EPI_PLAIN) return hipErrorInvalidValue;
+    if (io32 == 2) {
+      if constexpr (sizeof(T) == 4) {
+        VIE_DISPATCH_P(g.P[0], (k_fft_x_inv_c<T, PP, EPI_PLAIN, float, __bf16>
+                                <<<grid, nt_lines_p<T>(PP), 0, s>>>(
+                                    A, (const cb16*)x, (c32*)y, tw, bi, g.N[0], g.N[1], g.N[2],
+                                    bpr, e.aux, e.partials, e.pol, e.ph, active)));
+      } else {
+        return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    }
     VIE_DISPATCH_P(g.P[0], (k_fft_x_inv_c<T, PP, EPI_PLAIN, float><<<grid, nt_lines_p<T>(PP), 0, s>>>(
                                A, (const c32*)x, (c32*)y, tw, bi, g.N[0], g.N[1], g.N[2], bpr,
                                e.aux, e.partials, e.pol, e.ph, active)));

@@ -27,8 +27,9 @@ struct SegSet {
 
 int seg_blocks(int64_t max_len);
 
-// Multi-vectors V may be stored in FP64 (v32 = 0: c64) or FP32 (v32 = 1:
-// c32); arithmetic and the vectors w, x are FP64 either way.
+// Multi-vectors V may be stored in FP64 (v32 = 0: c64), FP32 (v32 = 1:
+// c32) or bfloat16 (v32 = 2: cb16, with an FP32 w); arithmetic is FP64 either
+// way.  The normalisation writes a bfloat16 destination for d32 = 2.
 
 // out[s * ldo + i] = sum_e conj(V_i[e]) w[e] over segment s, for i < nv
 // (zero for skipped segments); w is FP32 when w32.  partials: nseg * nv * nblk

@@ -23,6 +23,16 @@ __device__ __forceinline__ c64 shfl_xor_c(c64 v, int m) {
 
 __device__ __forceinline__ c64 ld64(const c64* p) { return *p; }
 __device__ __forceinline__ c64 ld64(const c32* p) { return cvt<double>(*p); }
+__device__ __forceinline__ c64 ld64(const cb16* p) {
+  const cb16 v = *p;
+  return mk((double)(float)v.re, (double)(float)v.im);
+}
+__device__ __forceinline__ void st(cb16* p, c64 v) {
+  cb16 o;
+  o.re = (__bf16)(float)v.re;
+  o.im = (__bf16)(float)v.im;
+  *p = o;
+}
 __device__ __forceinline__ void st(c64* p, c64 v) { *p = v; }
 __device__ __forceinline__ void st(c32* p, c64 v) { *p = cvt<float>(v); }
 // v as stored in a T vector (rounded to FP32 for c32), without a reload
@@ -381,7 +391,11 @@ hipError_t launch_seg_mdot(const SegSet& S, const void* V, int v32, int64_t stri
                            hipStream_t st) {
   if (S.nseg < 1 || nv < 1) return hipSuccess;
   const dim3 grid(S.nblk, S.nseg);
-  if (v32 && w32)
+  if (v32 == 2 && w32)
+    k_seg_mdot<<<grid, GT, 0, st>>>(S, (const cb16*)V, stride, nv, (const c32*)w, partials);
+  else if (v32 == 2)
+    return hipErrorInvalidValue;  // a bfloat16 basis comes with an FP32 work vector
+  else if (v32 && w32)
     k_seg_mdot<<<grid, GT, 0, st>>>(S, (const c32*)V, stride, nv, (const c32*)w, partials);
   else if (v32)
     k_seg_mdot<<<grid, GT, 0, st>>>(S, (const c32*)V, stride, nv, (const c64*)w, partials);
@@ -400,7 +414,11 @@ hipError_t launch_seg_maxpy(const SegSet& S, const void* V, int v32, int64_t str
   if (nv < 0 || nv > kMaxVec) return hipErrorInvalidValue;
   double* pn = norm2 ? partials : nullptr;
   const dim3 grid(S.nblk, S.nseg);
-  if (v32 && w32)
+  if (v32 == 2 && w32)
+    k_seg_maxpy<<<grid, GT, 0, st>>>(S, (const cb16*)V, stride, nv, nv_seg, coef, ldc, (c32*)w, pn);
+  else if (v32 == 2)
+    return hipErrorInvalidValue;
+  else if (v32 && w32)
     k_seg_maxpy<<<grid, GT, 0, st>>>(S, (const c32*)V, stride, nv, nv_seg, coef, ldc, (c32*)w, pn);
   else if (v32)
     k_seg_maxpy<<<grid, GT, 0, st>>>(S, (const c32*)V, stride, nv, nv_seg, coef, ldc, (c64*)w, pn);
@@ -423,7 +441,11 @@ hipError_t launch_seg_normalize(const SegSet& S, const void* src, int s32, const
                                 int ldn, void* dst, int d32, hipStream_t st) {
   if (S.nseg < 1) return hipSuccess;
   const dim3 grid(S.nblk, S.nseg);
-  if (s32 && d32)
+  if (d32 == 2 && s32)
+    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c32*)src, norm2, ldn, (cb16*)dst);
+  else if (d32 == 2)
+    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c64*)src, norm2, ldn, (cb16*)dst);
+  else if (s32 && d32)
     k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c32*)src, norm2, ldn, (c32*)dst);
   else if (s32)
     k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c32*)src, norm2, ldn, (c64*)dst);
@@ -455,7 +477,10 @@ hipError_t launch_seg_lincomb(const SegSet& S, const void* V, int v32, int64_t s
                               hipStream_t st) {
   if (S.nseg < 1) return hipSuccess;
   if (nv < 0 || nv > kMaxVec) return hipErrorInvalidValue;
-  if (v32)
+  if (v32 == 2)
+    k_seg_lincomb<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const cb16*)V, stride, nv, nv_seg, coef,
+                                                       ldc, x);
+  else if (v32)
     k_seg_lincomb<<<dim3(S.nblk, S.nseg), GT, 0, st>>>(S, (const c32*)V, stride, nv, nv_seg, coef,
                                                        ldc, x);
   else

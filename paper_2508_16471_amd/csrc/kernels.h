@@ -67,7 +67,8 @@ struct MatvecArgs {
   const int* active;       // [nrhs] or nullptr
   int zvar = 0;            // launch shape of the z pass (autotuned per group/precision)
   const BodyIdx* bi = nullptr;  // non-null: x and y are body-compressed
-  int io32 = 0;  // compressed x and y stored in FP32 (FP32 passes, plain epilogue only)
+  int io32 = 0;  // compressed x and y stored in FP32 (FP32 passes, plain epilogue only);
+                 // 2: x stored in bfloat16, y in FP32
 };
 
 // precision 0: FP64 passes, 1: FP32 passes (input/output vectors are FP64)

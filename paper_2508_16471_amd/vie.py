@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvie.so")
 
 VIE_OK, VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_ENOCONV, VIE_ENOTSUP, VIE_ESTATE = 0, -1, -2, -3, -4, -5, -6
-VIE_FP64, VIE_MIXED = 0, 1
+VIE_FP64, VIE_MIXED, VIE_MIXED_BF16 = 0, 1, 2
 VIE_NORM_R1, VIE_NORM_R2 = 0, 1
 VIE_FLAG_TIMING = 1
 VIE_FLAG_NO_GRAPH = 2
