@@ -165,7 +165,7 @@ def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None, vb=16, vin=None):
         return 3 * n * 16 + A * c
     if kind.startswith("fft_y_fwd"):
         return A * c + B * c
-    if kind.startswith("fft_z_green"):
+    if kind.startswith(("fft_z_green", "fft_z_h2")):  # FP32 scratch either way
         return 2 * B * c
     if kind.startswith("fft_y_inv"):
         return B * c + A * c
@@ -271,7 +271,7 @@ def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch, block_vin=8):
         extra = 3 * nbk * 16 if (base.startswith("fft_x_inv") and not f32 and not blk) else 0
         by = execs * kernel_bytes(base, Nk, Pk, Qk, extra, nb=nbk, vb=8 if f32 else 16,
                                   vin=block_vin if (blk and f32) else None)
-        if base.startswith("fft_z_green"):
+        if base.startswith(("fft_z_green", "fft_z_h2")):
             by += launches_active * spectrum_bytes(base, Qk)
         rows[kind] = {"ms_total": ms, "launches": int(cnt), "rhs_execs": execs,
                       "bytes": float(by), "GBps": by / (ms * 1e-3) / 1e9,

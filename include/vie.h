@@ -73,7 +73,13 @@ enum vie_status {
  * bfloat16 (8-bit significand; dots and updates in FP64, work vector FP32).
  * The block solves only approximate M^{-1}, so the basis' rounding (a few
  * 1e-3 relative) leaves the preconditioner about as good while the basis
- * traffic halves; the FP64 outer residual still decides convergence. */
+ * traffic halves; the FP64 outer residual still decides convergence.
+ * Where the block grid allows it (16-layer z tiles, padded z length 32, 48,
+ * 64, 96 or 128), the block products' z pass (z transforms and the Green
+ * tensor product) also runs in packed FP16: the input is scaled by
+ * 1/sqrt(padded length), the spectrum by a power of two that brings its
+ * largest modulus into [1/2, 1), so no intermediate overflows; the FFT
+ * passes around it and the results stay FP32. */
 enum { VIE_FP64 = 0, VIE_MIXED = 1, VIE_MIXED_BF16 = 2 };
 enum { VIE_NORM_R1 = 0, VIE_NORM_R2 = 1 };
 enum {
@@ -167,7 +173,7 @@ typedef struct {
   int32_t blocks[2];       /* bx, by: each 1..64 and at most N1 (N2); or {0, 0}    */
   int32_t inner_iters;     /* GMRES steps of every block solve, 1..64              */
   int32_t inner_precision; /* VIE_FP64 / VIE_MIXED: block products in FP64 / FP32; */
-                           /* VIE_MIXED_BF16: FP32 products, bfloat16 basis     */
+                           /* VIE_MIXED_BF16: bfloat16 basis, FP16 z pass      */
 } vie_fgmres_options;
 
 /* Solve like vie_solve (same channels, stats, solution storage and return

@@ -127,6 +127,11 @@ struct Group {
   } iter_graph;
   int zvar[2] = {-1, -1};        // autotuned z-pass shape per precision (-1: not yet)
   int zvar_nrhs[2] = {0, 0};     // right-hand-side count it was tuned for
+  // packed-FP16 z pass of approximate FP32 products (block solves): tables,
+  // spectrum scale gs, input / output scales, on/off
+  DevBuf spec16, tw16, gmax;
+  float zh_gs = 0.f, zh_in = 0.f, zh_out = 0.f;
+  int zh = 0;
 };
 
 struct TimedEvent {
@@ -208,8 +213,9 @@ struct BlockPrec {
 
 // Timing kinds: the product passes, vector work and setup of the context's
 // own groups (0..14), the product passes of the block solves run on a
-// block-Jacobi sub-context (15..24, same order as 0..9), and the Arnoldi
-// vector kernels of FGMRES (25).
+// block-Jacobi sub-context (15..24, same order as 0..9), the Arnoldi
+// vector kernels of FGMRES (25), and the packed-FP16 z pass of approximate
+// FP32 products (26 the context's own, 27 the block solves').
 static const char* kKindNames[] = {
     "fft_x_fwd_f64",       "fft_y_fwd_f64",       "fft_z_green_f64",       "fft_y_inv_f64",
     "fft_x_inv_f64",       "fft_x_fwd_f32",       "fft_y_fwd_f32",         "fft_z_green_f32",
@@ -217,9 +223,10 @@ static const char* kKindNames[] = {
     "farfield",            "init",                "cnn_forward",           "block_fft_x_fwd_f64",
     "block_fft_y_fwd_f64", "block_fft_z_green_f64", "block_fft_y_inv_f64", "block_fft_x_inv_f64",
     "block_fft_x_fwd_f32", "block_fft_y_fwd_f32", "block_fft_z_green_f32", "block_fft_y_inv_f32",
-    "block_fft_x_inv_f32", "arnoldi"};
-static constexpr int kNumKinds = 26;
-static constexpr int kBlockKind0 = 15, kArnoldiKind = 25;
+    "block_fft_x_inv_f32", "arnoldi",               "fft_z_h2_f32",          "block_fft_z_h2_f32"};
+static constexpr int kNumKinds = 28;
+static constexpr int kBlockKind0 = 15, kArnoldiKind = 25, kBlockZH2Kind = 27;
+static_assert(kZH2Kind == 26, "timing kind table");
 
 struct vie_cnn {
   vie::Cnn c;
@@ -707,6 +714,12 @@ static MatvecArgs matvec_args(Group& G, int precision, const int* active) {
   m.rhs_body = G.rhs_body.as<int>();
   m.spec = precision == 0 ? G.spec64.p : G.spec32.p;
   for (int a = 0; a < 3; ++a) m.tw[a] = precision == 0 ? G.tw64[a].p : G.tw32[a].p;
+  if (precision == 1 && G.zh) {
+    m.spec16 = G.spec16.p;
+    m.tw16 = G.tw16.p;
+    m.zh_in = G.zh_in;
+    m.zh_out = G.zh_out;
+  }
   m.bufA = G.bufA.p;
   m.bufB = G.bufB.p;
   m.active = active;
@@ -1624,7 +1637,41 @@ static int bj_prepare(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo) 
   if (rc != VIE_OK) return rc;
   vie_ctx* sub = P.sub;
   sub->stream = ctx->stream;
-  VIE_HIP(tune_z(sub, *sub->groups[0], fo->inner_precision == VIE_FP64 ? 0 : 1));
+  Group& Gs = *sub->groups[0];
+  VIE_HIP(tune_z(sub, Gs, fo->inner_precision == VIE_FP64 ? 0 : 1));
+  // VIE_MIXED_BF16: the block products' z pass in packed FP16 where the grid
+  // takes it.  Spectrum scale gs = 2^-ceil(log2 max|G|) (entries within 1);
+  // input scale 1/sqrt(longest segment), so that every transform value of a
+  // unit-norm basis vector stays within 1 (|X_k| <= ||x||_1 <= sqrt(n) ||x||_2).
+  Gs.zh = 0;
+  if (fo->inner_precision == VIE_MIXED_BF16 && z_h2_ok(Gs.g)) {
+    const GroupGeom& g = Gs.g;
+    if (!(Gs.zh_gs > 0)) {
+      VIE_HIP(Gs.gmax.reserve(sizeof(unsigned)));
+      VIE_HIP(hipMemsetAsync(Gs.gmax.p, 0, sizeof(unsigned), ctx->stream));
+      VIE_HIP(launch_spec_absmax(Gs.spec32.p, (int64_t)6 * g.Q[0] * g.Q[1] * g.Q[2],
+                                 Gs.gmax.as<unsigned>(), ctx->stream));
+      unsigned bits = 0;
+      VIE_HIP(hipMemcpyAsync(&bits, Gs.gmax.p, sizeof(bits), hipMemcpyDeviceToHost, ctx->stream));
+      VIE_HIP(hipStreamSynchronize(ctx->stream));
+      float mx = 0.f;
+      memcpy(&mx, &bits, sizeof(mx));
+      if (mx > 0.f && std::isfinite(mx)) {
+        const float gs = exp2f(-ceilf(log2f(mx)));
+        VIE_HIP(Gs.spec16.reserve((size_t)6 * g.Q[1] * g.Q[2] * (g.P[0] / 2) * 8));
+        VIE_HIP(launch_spec_pairs(Gs.spec32.p, Gs.spec16.p, g, gs, ctx->stream));
+        VIE_HIP(Gs.tw16.reserve((size_t)g.P[2] * 8));
+        VIE_HIP(launch_tw_h2(Gs.tw32[2].p, Gs.tw16.p, g.P[2], ctx->stream));
+        Gs.zh_gs = gs;
+      }
+    }
+    if (Gs.zh_gs > 0) {
+      const float xs = 1.f / sqrtf((float)std::max(P.maxlen, 1));
+      Gs.zh_in = xs;
+      Gs.zh_out = 1.f / (xs * Gs.zh_gs);
+      Gs.zh = 1;
+    }
+  }
   return VIE_OK;
 }
 
@@ -1641,8 +1688,14 @@ static void key_group(std::vector<const void*>& k, const Group& G) {
                &G.voff_arr, &G.roff, &G.x, &G.r, &G.rh, &G.state, &G.flags, &G.bufA, &G.bufB,
                &G.rhs_body, &G.partials});
   const int ints[] = {G.g.nrhs, G.zvar[0], G.zvar[1], G.g.N[0], G.g.N[1], G.g.N[2], G.g.P[0],
-                      G.g.P[1], G.g.P[2]};
+                      G.g.P[1], G.g.P[2], G.zh};
   for (int v : ints) k.push_back((const void*)(intptr_t)v);
+  key_bufs(k, {&G.spec16, &G.tw16});
+  for (float f : {G.zh_in, G.zh_out}) {
+    uint32_t b = 0;
+    memcpy(&b, &f, sizeof(b));
+    k.push_back((const void*)(uintptr_t)b);
+  }
 }
 static void key_arnoldi(std::vector<const void*>& k, const ArnoldiBufs& A) {
   key_bufs(k, {&A.V, &A.Z, &A.w, &A.H1, &A.H2, &A.NR, &A.dpart, &A.npart, &A.off, &A.len, &A.act,
@@ -2582,11 +2635,12 @@ extern "C" int vie_kernel_times(vie_ctx* ctx, const char** names, double* ms, in
   for (auto& P : ctx->bj) {  // block products of the sub-contexts
     if (!P || !P->sub) continue;
     timing_collect(P->sub);
-    for (int k = 0; k < 10; ++k) {
-      ctx->kind_ms[kBlockKind0 + k] += P->sub->kind_ms[k];
-      ctx->kind_cnt[kBlockKind0 + k] += P->sub->kind_cnt[k];
-      P->sub->kind_ms[k] = 0;
-      P->sub->kind_cnt[k] = 0;
+    for (int k = 0; k < 11; ++k) {
+      const int src = k < 10 ? k : kZH2Kind, dst = k < 10 ? kBlockKind0 + k : kBlockZH2Kind;
+      ctx->kind_ms[dst] += P->sub->kind_ms[src];
+      ctx->kind_cnt[dst] += P->sub->kind_cnt[src];
+      P->sub->kind_ms[src] = 0;
+      P->sub->kind_cnt[src] = 0;
     }
   }
   const int n = std::min<int>(*nkinds, kNumKinds);

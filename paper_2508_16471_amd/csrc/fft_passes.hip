@@ -592,6 +592,267 @@ static hipError_t z_pass(const GroupGeom& g, cpx<T>* B, const cpx<T>* spec, cons
   return hipGetLastError();
 }
 
+// ------------------------------- Z for approximate products: packed FP16
+// The block solves of the block-Jacobi preconditioner only approximate its
+// inverse, so their z pass may run in FP16 arithmetic on packed pairs
+// (v_pk_fma_f16 and friends: two columns per lane, twice the FP32 rate);
+// storage stays FP32.  Each lane takes the two columns of a pair at its
+// rows (one 16-byte row segment per row), inputs are scaled by xs on
+// conversion (xs = 1 / sqrt(segment length) bounds every transform value by
+// one for the unit-norm block basis vectors), the spectrum is an FP16 copy
+// scaled by 1 / max|G| (spec16), and outputs are scaled back by os =
+// 1 / (xs gs) on conversion to FP32.  Layout conditions as the FAST paired
+// FP32 shape (z block 16, P/2 rows, column tiles covering P1).
+// The spectrum copy is pair-packed: record (yo, zo, p) holds the six
+// entries of columns 2p and 2p + 1 as packed halves (octant lookups and the
+// x-mirror signs already applied), scaled by gs.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ cpx<h2> pack2(float ar, float ai, float br, float bi) {
+  return mk<h2>(h2{(_Float16)ar, (_Float16)br}, h2{(_Float16)ai, (_Float16)bi});
+}
+// negate both halves of re and im when neg (sign bits flipped)
+__device__ __forceinline__ cpx<h2> negif(cpx<h2> a, bool neg) {
+  const unsigned m = neg ? 0x80008000u : 0u;
+  return mk<h2>(__builtin_bit_cast(h2, __builtin_bit_cast(unsigned, a.re) ^ m),
+                __builtin_bit_cast(h2, __builtin_bit_cast(unsigned, a.im) ^ m));
+}
+__device__ __forceinline__ void load_g6h(const cpx<h2>* __restrict__ r, cpx<h2> (&g)[6]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = r[k];
+}
+
+// at most 128 registers: two 8-wave workgroups per CU
+template <int P, int E, int NT, bool ZP>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_z_green_h2(
+    c32* __restrict__ B,
+                                                        const cpx<h2>* __restrict__ spec,
+                                                        const cpx<h2>* __restrict__ tw, ZArgs a,
+                                                        float xs, float os,
+                                                        const int* __restrict__ active) {
+  constexpr int TT = P / E, WP = NT / TT, LS = Pad<P>::LSTR;
+  __shared__ cpx<h2> lds[WP * LS];
+  // block order as the FP32 z pass (right-hand side innermost, y mirror
+  // pairs, x tiles in mirror pairs)
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int rhs = b % a.nrhs;
+  const int u = b / a.nrhs;
+  const int m = u & 1;
+  const int it = (u >> 1) % a.tiles_x;
+  const int yp = (u >> 1) / a.tiles_x;
+  if (m && (yp == 0 || 2 * yp == a.P2)) return;
+  const int xy = m ? a.P2 - yp : yp;
+  const int tile = (it & 1) ? a.tiles_x - 1 - (it >> 1) : (it >> 1);
+  if (active && !active[rhs]) return;
+  const int cw = threadIdx.x % WP, t = threadIdx.x / WP;
+  const int x0 = tile * 2 * WP + 2 * cw;  // the pair's even column
+  float* cp0 = reinterpret_cast<float*>(B + rhs * a.rhs_stride + (int64_t)xy * a.zl * a.P1 + x0);
+  float* cp1 = cp0 + 2 * a.comp_stride;
+  float* cp2 = cp1 + 2 * a.comp_stride;
+  TwReg<h2, P, E> tr;
+  tr.load(t, tw);
+  cpx<h2> v0[E], v1[E], v2[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    if (q < E / 2) {
+      // rows below P/2 exist in the blocked layout; padding rows read as zero
+      const int z = t + q * TT;
+      const int off = 2 * ((z >> 4) * (int)a.zhs + (z & 15) * (int)a.zls);
+      const float sc = (!ZP || z < a.N3) ? xs : 0.f;
+      const float4 f0 = *reinterpret_cast<const float4*>(cp0 + off);
+      const float4 f1 = *reinterpret_cast<const float4*>(cp1 + off);
+      const float4 f2 = *reinterpret_cast<const float4*>(cp2 + off);
+      v0[q] = pack2(f0.x * sc, f0.y * sc, f0.z * sc, f0.w * sc);
+      v1[q] = pack2(f1.x * sc, f1.y * sc, f1.z * sc, f1.w * sc);
+      v2[q] = pack2(f2.x * sc, f2.y * sc, f2.z * sc, f2.w * sc);
+    } else {
+      v0[q] = v1[q] = v2[q] = mk<h2>(h2{0, 0}, h2{0, 0});
+    }
+  }
+  cpx<h2>* line = lds + cw * LS;
+  line_fft_e<h2, P, E, false, true, false>(v0, line, t, tr);
+  line_fft_e<h2, P, E, false, true, false>(v1, line, t, tr);
+  line_fft_e<h2, P, E, false, true, false>(v2, line, t, tr);
+  const int ym = xy > a.P2 / 2;
+  const int yo = ym ? a.P2 - xy : xy;
+  const int npair = a.P1 / 2;
+  const cpx<h2>* sp = spec + ((int64_t)yo * a.Q3 * npair + x0 / 2) * 6;
+  auto rec = [&](int q) {
+    const int z = t + q * TT;
+    return sp + (int64_t)(z > P / 2 ? P - z : z) * 6 * npair;
+  };
+  // the next point's record is requested while this point is multiplied
+  // (the empty asm statements keep the compiler from issuing every point's
+  // loads at once, which would hold 12 registers per point)
+  cpx<h2> gn[6];
+  load_g6h(rec(0), gn);
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int z = t + q * TT;
+    const int zm = z > P / 2;
+    cpx<h2> gg[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gg[k] = gn[k];
+    if (q + 1 < E) load_g6h(rec(q + 1), gn);
+    asm volatile("" ::: "memory");
+    // x signs are in the record; G_ab is odd along y (z) iff exactly one of
+    // a, b is y (z)
+    const cpx<h2> gxx = gg[0], gyy = gg[3], gzz = gg[5];
+    const cpx<h2> gxy = negif(gg[1], ym), gxz = negif(gg[2], zm), gyz = negif(gg[4], ym ^ zm);
+    const cpx<h2> ix = v0[q], iy = v1[q], iz = v2[q];
+    v0[q] = cfma(gxz, iz, cfma(gxy, iy, gxx * ix));
+    v1[q] = cfma(gyz, iz, cfma(gyy, iy, gxy * ix));
+    v2[q] = cfma(gzz, iz, cfma(gyz, iy, gxz * ix));
+  }
+  line_fft_e<h2, P, E, true, false, true>(v0, line, t, tr);
+  line_fft_e<h2, P, E, true, false, true>(v1, line, t, tr);
+  line_fft_e<h2, P, E, true, false, true>(v2, line, t, tr);
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int z = t + q * TT;
+    if (!ZP || z < a.N3) {
+      const int off = 2 * ((z >> 4) * (int)a.zhs + (z & 15) * (int)a.zls);
+      *reinterpret_cast<float4*>(cp0 + off) =
+          make_float4((float)v0[q].re.x * os, (float)v0[q].im.x * os, (float)v0[q].re.y * os,
+                      (float)v0[q].im.y * os);
+      *reinterpret_cast<float4*>(cp1 + off) =
+          make_float4((float)v1[q].re.x * os, (float)v1[q].im.x * os, (float)v1[q].re.y * os,
+                      (float)v1[q].im.y * os);
+      *reinterpret_cast<float4*>(cp2 + off) =
+          make_float4((float)v2[q].re.x * os, (float)v2[q].im.x * os, (float)v2[q].re.y * os,
+                      (float)v2[q].im.y * os);
+    }
+  }
+}
+
+// 8 points per thread (6 for 3 * 2^k lines), 512 threads: 64 column pairs
+// per workgroup; the packed data of three components stay within a register
+// budget that keeps several waves per SIMD.
+constexpr int kZH2Threads = 512;
+template <int P>
+constexpr int zh2_e() {
+  return P % 3 == 0 ? 6 : 8;
+}
+template <int P>
+static int zh2_pairs() {
+  return kZH2Threads / (P / zh2_e<P>());
+}
+
+// The packed-FP16 z pass's shape conditions for this grid (P3 = 32 .. 128).
+bool z_h2_ok(const GroupGeom& g) {
+  const int zl = z_block(g);
+  if (zl != 16 || 2 * ((g.N[2] + 15) / 16) * 16 != g.P[2]) return false;
+  int wp = 0;
+  switch (g.P[2]) {
+    case 32: wp = zh2_pairs<32>(); break;
+    case 48: wp = zh2_pairs<48>(); break;
+    case 64: wp = zh2_pairs<64>(); break;
+    case 96: wp = zh2_pairs<96>(); break;
+    case 128: wp = zh2_pairs<128>(); break;
+    default: return false;
+  }
+  return g.P[0] % (2 * wp) == 0;
+}
+
+static hipError_t z_pass_h2(const GroupGeom& g, c32* B, const cpx<h2>* spec, const cpx<h2>* tw,
+                            float xs, float os, const int* active, hipStream_t s) {
+  if (!z_h2_ok(g)) return hipErrorInvalidValue;
+  ZArgs a;
+  a.N3 = g.N[2];
+  a.P1 = g.P[0];
+  a.P2 = g.P[1];
+  a.Q1 = g.Q[0];
+  a.Q2 = g.Q[1];
+  a.Q3 = g.Q[2];
+  a.nrhs = g.nrhs;
+  a.zl = z_block(g);
+  const SideAddr sb = side_B(g, a.zl);
+  a.comp_stride = sb.cs;
+  a.rhs_stride = sb.rs;
+  a.zhs = sb.zhs;
+  a.zls = sb.zls;
+#define VIE_ZH2(P_)                                                                           \
+  case P_: {                                                                                  \
+    a.tiles_x = g.P[0] / (2 * zh2_pairs<P_>());                                               \
+    const dim3 grid((g.P[1] / 2 + 1) * 2 * a.tiles_x * g.nrhs);                               \
+    if (2 * a.N3 == P_)                                                                       \
+      k_fft_z_green_h2<P_, zh2_e<P_>(), kZH2Threads, false>                                   \
+          <<<grid, kZH2Threads, 0, s>>>(B, spec, tw, a, xs, os, active);                      \
+    else                                                                                      \
+      k_fft_z_green_h2<P_, zh2_e<P_>(), kZH2Threads, true>                                    \
+          <<<grid, kZH2Threads, 0, s>>>(B, spec, tw, a, xs, os, active);                      \
+    break;                                                                                    \
+  }
+  switch (g.P[2]) {
+    VIE_ZH2(32)
+    VIE_ZH2(48)
+    VIE_ZH2(64)
+    VIE_ZH2(96)
+    VIE_ZH2(128)
+    default: return hipErrorInvalidValue;
+  }
+#undef VIE_ZH2
+  return hipGetLastError();
+}
+
+// FP16 tables of the packed z pass: the pair-packed spectrum (scaled by gs,
+// x-mirror signs applied: entries xy and xz are odd along x), and the z
+// twiddles splatted to both halves.
+__global__ void k_spec_pairs(const c32* __restrict__ in, cpx<h2>* __restrict__ out, int P1,
+                             int Q1, int64_t nyz, float gs) {
+  const int npair = P1 / 2;
+  const int64_t n = nyz * npair * 6;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int ab = (int)(i % 6);
+    const int p = (int)((i / 6) % npair);
+    const int64_t yz = i / (6 * npair);
+    float re[2], im[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int x = 2 * p + h;
+      const int xm = x > P1 / 2;
+      const int xo = xm ? P1 - x : x;
+      const c32 v = in[(yz * Q1 + xo) * 6 + ab];
+      const float sg = (xm && (ab == 1 || ab == 2)) ? -gs : gs;
+      re[h] = v.re * sg;
+      im[h] = v.im * sg;
+    }
+    out[i] = pack2(re[0], im[0], re[1], im[1]);
+  }
+}
+__global__ void k_tw_h2(const c32* __restrict__ in, cpx<h2>* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const _Float16 re = (_Float16)in[i].re, im = (_Float16)in[i].im;
+    out[i] = mk<h2>(h2{re, re}, h2{im, im});
+  }
+}
+// max |re|, |im| over n complex values into *out (float bits, atomic max)
+__global__ void k_absmax(const c32* __restrict__ in, int64_t n, unsigned* __restrict__ out) {
+  float mx = 0.f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    mx = fmaxf(mx, fmaxf(fabsf(in[i].re), fabsf(in[i].im)));
+  for (int m = 32; m >= 1; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(mx));
+}
+
+hipError_t launch_spec_absmax(const void* spec32, int64_t n, unsigned* dmax, hipStream_t s) {
+  k_absmax<<<512, 256, 0, s>>>((const c32*)spec32, n, dmax);
+  return hipGetLastError();
+}
+hipError_t launch_spec_pairs(const void* spec32, void* spec16, const GroupGeom& g, float gs,
+                             hipStream_t s) {
+  k_spec_pairs<<<1024, 256, 0, s>>>((const c32*)spec32, (cpx<h2>*)spec16, g.P[0], g.Q[0],
+                                    (int64_t)g.Q[1] * g.Q[2], gs);
+  return hipGetLastError();
+}
+hipError_t launch_tw_h2(const void* tw32, void* tw16, int n, hipStream_t s) {
+  k_tw_h2<<<(n + 255) / 256, 256, 0, s>>>((const c32*)tw32, (cpx<h2>*)tw16, n);
+  return hipGetLastError();
+}
+
 int part_blocks_xinv(const GroupGeom& g, int precision) {
   const int lines = 3 * g.N[1] * g.N[2];
   const int L = precision == 0 ? lines_per_block<double>(g.P[0]) : lines_per_block<float>(g.P[0]);
@@ -662,7 +923,15 @@ static hipError_t matvec_t(const MatvecArgs& m, const void* xv, void* yv, EpiArg
     STEP(0, x_fwd<T>(g, x, A, tw0, m.active, s));
   }
   STEP(1, y_pass<T>(g, A, B, tw1, false, m.active, s));
-  STEP(2, z_pass<T>(g, B, (const cpx<T>*)m.spec, tw2, m.active, s, m.zvar));
+  if (m.spec16 && sizeof(T) == 4) {  // approximate products: packed-FP16 z pass
+    if (cb) cb(kZH2Kind, true, u);
+    err = z_pass_h2(g, (c32*)B, (const cpx<h2>*)m.spec16, (const cpx<h2>*)m.tw16, m.zh_in,
+                    m.zh_out, m.active, s);
+    if (cb) cb(kZH2Kind, false, u);
+    if (err != hipSuccess) return err;
+  } else {
+    STEP(2, z_pass<T>(g, B, (const cpx<T>*)m.spec, tw2, m.active, s, m.zvar));
+  }
   STEP(3, y_pass<T>(g, B, A, tw1, true, m.active, s));
   if (m.bi) {
     STEP(4, x_inv_c<T>(g, A, xv, yv, m.io32, tw0, *m.bi, e, m.active, s));

@@ -69,6 +69,12 @@ struct MatvecArgs {
   const BodyIdx* bi = nullptr;  // non-null: x and y are body-compressed
   int io32 = 0;  // compressed x and y stored in FP32 (FP32 passes, plain epilogue only);
                  // 2: x stored in bfloat16, y in FP32
+  // FP32 products only: with spec16 set, the z pass runs in packed FP16 on the
+  // scaled FP16 spectrum copy spec16 and twiddles tw16 (input scale zh_in,
+  // output scale zh_out; see z_h2_ok for the grids it takes)
+  const void* spec16 = nullptr;
+  const void* tw16 = nullptr;
+  float zh_in = 0.f, zh_out = 0.f;
 };
 
 // precision 0: FP64 passes, 1: FP32 passes (input/output vectors are FP64)
@@ -94,6 +100,17 @@ hipError_t launch_matvec(const MatvecArgs& a, int precision, const void* x, void
 int z_variants(int precision);  // z-pass launch shapes (0 = FP64, 1 = FP32)
 // z pass alone on bufB (autotuning; contents are scratch)
 hipError_t launch_z_only(const MatvecArgs& a, int precision, hipStream_t s);
+// Packed-FP16 z pass for approximate FP32 products: whether the grid takes
+// it, and its tables: max |re|, |im| of an FP32 octant spectrum (n complex
+// values) as float bits atomically maxed into *dmax (zeroed by the caller),
+// the pair-packed FP16 copy scaled by gs (Q2 Q3 P1/2 6 packed pairs, 8 bytes
+// each), the splatted FP16 twiddles of n points.
+bool z_h2_ok(const GroupGeom& g);
+static constexpr int kZH2Kind = 26;  // its timing kind in the product's callback
+hipError_t launch_spec_absmax(const void* spec32, int64_t n, unsigned* dmax, hipStream_t s);
+hipError_t launch_spec_pairs(const void* spec32, void* spec16, const GroupGeom& g, float gs,
+                             hipStream_t s);
+hipError_t launch_tw_h2(const void* tw32, void* tw16, int n, hipStream_t s);
 
 // Green spectrum: sample the circulant kernel of component ab into
 // work[P3][P2][P1] (c64).
