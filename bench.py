@@ -152,11 +152,13 @@ def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None, vb=16, vin=None):
     values plus the voxel index and line pointers), None for box vectors.
     vb: bytes of a vector element (16, or 8 for the FP32 vectors of the
     FGMRES products); vin: bytes of an input-vector element when it differs
-    (4 for the bfloat16 basis vectors the block products read)."""
+    (4 for the bfloat16 basis vectors the block products read).  Kinds
+    ending in h16 are the packed-FP16 passes: FP16 scratch (4 bytes a
+    point), FP32 vectors."""
     N1, N2, N3 = N
     P1, P2, P3 = P
     n = N1 * N2 * N3
-    c = 16 if kind.endswith("f64") else 8
+    c = 16 if kind.endswith("f64") else (4 if kind.endswith("h16") else 8)
     A = 3 * N3 * N2 * P1
     B = 3 * N3 * P2 * P1
     if kind.startswith("fft_x_fwd"):
@@ -165,7 +167,7 @@ def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None, vb=16, vin=None):
         return 3 * n * 16 + A * c
     if kind.startswith("fft_y_fwd"):
         return A * c + B * c
-    if kind.startswith(("fft_z_green", "fft_z_h2")):  # FP32 scratch either way
+    if kind.startswith(("fft_z_green", "fft_z_h16")):
         return 2 * B * c
     if kind.startswith("fft_y_inv"):
         return B * c + A * c
@@ -177,6 +179,8 @@ def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None, vb=16, vin=None):
 
 
 def spectrum_bytes(kind, Q):
+    if kind.endswith("h16"):  # pair-packed FP16 copy: six 8-byte records per column pair
+        return 6 * Q[1] * Q[2] * (Q[0] - 1) * 8
     c = 16 if kind.endswith("f64") else 8
     return 6 * Q[0] * Q[1] * Q[2] * c
 
@@ -259,7 +263,7 @@ def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch, block_vin=8):
         base = kind[len("block_"):] if blk else kind
         if not base.startswith("fft_") or cnt == 0 or ms <= 0:
             continue
-        f32 = base.endswith("f32")
+        f32 = base.endswith(("f32", "h16"))  # FP32 vectors
         if blk:
             Nk, Pk, Qk, nbk = geom["N"], geom["P"], geom["Q"], geom["nb_mean"]
             execs = int((iters * k * nblk).sum())
@@ -271,7 +275,7 @@ def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch, block_vin=8):
         extra = 3 * nbk * 16 if (base.startswith("fft_x_inv") and not f32 and not blk) else 0
         by = execs * kernel_bytes(base, Nk, Pk, Qk, extra, nb=nbk, vb=8 if f32 else 16,
                                   vin=block_vin if (blk and f32) else None)
-        if base.startswith(("fft_z_green", "fft_z_h2")):
+        if base.startswith(("fft_z_green", "fft_z_h16")):
             by += launches_active * spectrum_bytes(base, Qk)
         rows[kind] = {"ms_total": ms, "launches": int(cnt), "rhs_execs": execs,
                       "bytes": float(by), "GBps": by / (ms * 1e-3) / 1e9,

@@ -328,9 +328,11 @@ int vie_set_stream(vie_ctx *ctx, void *hip_stream);
  * cnt[k] for k < *nkinds (in: capacity, out: number of kinds).  Kinds: the
  * five product passes per precision ("fft_x_fwd_f64" ... "fft_x_inv_f32"),
  * Krylov vector work, reductions, far field, setup, network; the same five
- * passes of the block solves of vie_solve_fgmres ("block_fft_..."), and its
- * Arnoldi vector kernels ("arnoldi").  reset != 0 clears the accumulators
- * after reading. */
+ * passes of the block solves of vie_solve_fgmres ("block_fft_..."), its
+ * Arnoldi vector kernels ("arnoldi"), and the five packed-FP16 passes
+ * ("fft_x_fwd_h16" ... "fft_x_inv_h16", and "block_fft_..._h16").  Call with
+ * *nkinds = 0 to learn the number of kinds.  reset != 0 clears the
+ * accumulators after reading. */
 int vie_kernel_times(vie_ctx *ctx, const char **names, double *ms, int64_t *cnt,
                      int32_t *nkinds, int32_t reset);
 

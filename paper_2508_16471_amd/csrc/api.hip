@@ -127,10 +127,10 @@ struct Group {
   } iter_graph;
   int zvar[2] = {-1, -1};        // autotuned z-pass shape per precision (-1: not yet)
   int zvar_nrhs[2] = {0, 0};     // right-hand-side count it was tuned for
-  // packed-FP16 z pass of approximate FP32 products (block solves): tables,
-  // spectrum scale gs, input / output scales, on/off
-  DevBuf spec16, tw16, gmax;
-  float zh_gs = 0.f, zh_in = 0.f, zh_out = 0.f;
+  // packed-FP16 y and z passes of approximate FP32 products (block solves):
+  // tables, spectrum scale gs, forward scales along x, y, z, scale back, on/off
+  DevBuf spec16, tw16y, tw16z, gmax;
+  float zh_gs = 0.f, hs[3] = {0.f, 0.f, 0.f}, hout = 0.f;
   int zh = 0;
 };
 
@@ -214,8 +214,9 @@ struct BlockPrec {
 // Timing kinds: the product passes, vector work and setup of the context's
 // own groups (0..14), the product passes of the block solves run on a
 // block-Jacobi sub-context (15..24, same order as 0..9), the Arnoldi
-// vector kernels of FGMRES (25), and the packed-FP16 z pass of approximate
-// FP32 products (26 the context's own, 27 the block solves').
+// vector kernels of FGMRES (25), and the packed-FP16 passes of approximate
+// FP32 products (26..30 the context's own, 31..35 the block solves', same
+// order as 0..4).
 static const char* kKindNames[] = {
     "fft_x_fwd_f64",       "fft_y_fwd_f64",       "fft_z_green_f64",       "fft_y_inv_f64",
     "fft_x_inv_f64",       "fft_x_fwd_f32",       "fft_y_fwd_f32",         "fft_z_green_f32",
@@ -223,10 +224,12 @@ static const char* kKindNames[] = {
     "farfield",            "init",                "cnn_forward",           "block_fft_x_fwd_f64",
     "block_fft_y_fwd_f64", "block_fft_z_green_f64", "block_fft_y_inv_f64", "block_fft_x_inv_f64",
     "block_fft_x_fwd_f32", "block_fft_y_fwd_f32", "block_fft_z_green_f32", "block_fft_y_inv_f32",
-    "block_fft_x_inv_f32", "arnoldi",               "fft_z_h2_f32",          "block_fft_z_h2_f32"};
-static constexpr int kNumKinds = 28;
-static constexpr int kBlockKind0 = 15, kArnoldiKind = 25, kBlockZH2Kind = 27;
-static_assert(kZH2Kind == 26, "timing kind table");
+    "block_fft_x_inv_f32", "arnoldi",               "fft_x_fwd_h16",         "fft_y_fwd_h16",
+    "fft_z_h16",           "fft_y_inv_h16",       "fft_x_inv_h16",         "block_fft_x_fwd_h16",
+    "block_fft_y_fwd_h16", "block_fft_z_h16",     "block_fft_y_inv_h16",   "block_fft_x_inv_h16"};
+static constexpr int kNumKinds = 36;
+static constexpr int kBlockKind0 = 15, kArnoldiKind = 25, kBlockH16Kind0 = 31;
+static_assert(kH16Kind0 == 26, "timing kind table");
 
 struct vie_cnn {
   vie::Cnn c;
@@ -716,9 +719,10 @@ static MatvecArgs matvec_args(Group& G, int precision, const int* active) {
   for (int a = 0; a < 3; ++a) m.tw[a] = precision == 0 ? G.tw64[a].p : G.tw32[a].p;
   if (precision == 1 && G.zh) {
     m.spec16 = G.spec16.p;
-    m.tw16 = G.tw16.p;
-    m.zh_in = G.zh_in;
-    m.zh_out = G.zh_out;
+    m.tw16[0] = G.tw16y.p;
+    m.tw16[1] = G.tw16z.p;
+    for (int d = 0; d < 3; ++d) m.hs[d] = G.hs[d];
+    m.hout = G.hout;
   }
   m.bufA = G.bufA.p;
   m.bufB = G.bufB.p;
@@ -1639,12 +1643,13 @@ static int bj_prepare(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo) 
   sub->stream = ctx->stream;
   Group& Gs = *sub->groups[0];
   VIE_HIP(tune_z(sub, Gs, fo->inner_precision == VIE_FP64 ? 0 : 1));
-  // VIE_MIXED_BF16: the block products' z pass in packed FP16 where the grid
-  // takes it.  Spectrum scale gs = 2^-ceil(log2 max|G|) (entries within 1);
-  // input scale 1/sqrt(longest segment), so that every transform value of a
-  // unit-norm basis vector stays within 1 (|X_k| <= ||x||_1 <= sqrt(n) ||x||_2).
+  // VIE_MIXED_BF16: the block products' y and z passes in packed FP16 where
+  // the grid takes them.  Spectrum scale gs = 2^-ceil(log2 max|G|) (entries
+  // within 1); forward scale along each axis the power of two h_d with
+  // h_d^2 N_d <= 1, so that every forward value of a unit-norm basis vector
+  // stays within 1 (Cauchy-Schwarz along each transformed line).
   Gs.zh = 0;
-  if (fo->inner_precision == VIE_MIXED_BF16 && z_h2_ok(Gs.g)) {
+  if (fo->inner_precision == VIE_MIXED_BF16 && h16_ok(Gs.g)) {
     const GroupGeom& g = Gs.g;
     if (!(Gs.zh_gs > 0)) {
       VIE_HIP(Gs.gmax.reserve(sizeof(unsigned)));
@@ -1660,15 +1665,22 @@ static int bj_prepare(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo) 
         const float gs = exp2f(-ceilf(log2f(mx)));
         VIE_HIP(Gs.spec16.reserve((size_t)6 * g.Q[1] * g.Q[2] * (g.P[0] / 2) * 8));
         VIE_HIP(launch_spec_pairs(Gs.spec32.p, Gs.spec16.p, g, gs, ctx->stream));
-        VIE_HIP(Gs.tw16.reserve((size_t)g.P[2] * 8));
-        VIE_HIP(launch_tw_h2(Gs.tw32[2].p, Gs.tw16.p, g.P[2], ctx->stream));
+        VIE_HIP(Gs.tw16y.reserve((size_t)g.P[1] * 8));
+        VIE_HIP(launch_tw_h2(Gs.tw32[1].p, Gs.tw16y.p, g.P[1], ctx->stream));
+        VIE_HIP(Gs.tw16z.reserve((size_t)g.P[2] * 8));
+        VIE_HIP(launch_tw_h2(Gs.tw32[2].p, Gs.tw16z.p, g.P[2], ctx->stream));
         Gs.zh_gs = gs;
       }
     }
     if (Gs.zh_gs > 0) {
-      const float xs = 1.f / sqrtf((float)std::max(P.maxlen, 1));
-      Gs.zh_in = xs;
-      Gs.zh_out = 1.f / (xs * Gs.zh_gs);
+      float prod = Gs.zh_gs;
+      for (int d = 0; d < 3; ++d) {
+        int e = 0;
+        while (((int64_t)1 << (2 * e)) < Gs.g.N[d]) ++e;
+        Gs.hs[d] = ldexpf(1.f, -e);
+        prod *= Gs.hs[d];
+      }
+      Gs.hout = 1.f / prod;  // a power of two: exact
       Gs.zh = 1;
     }
   }
@@ -1690,8 +1702,8 @@ static void key_group(std::vector<const void*>& k, const Group& G) {
   const int ints[] = {G.g.nrhs, G.zvar[0], G.zvar[1], G.g.N[0], G.g.N[1], G.g.N[2], G.g.P[0],
                       G.g.P[1], G.g.P[2], G.zh};
   for (int v : ints) k.push_back((const void*)(intptr_t)v);
-  key_bufs(k, {&G.spec16, &G.tw16});
-  for (float f : {G.zh_in, G.zh_out}) {
+  key_bufs(k, {&G.spec16, &G.tw16y, &G.tw16z});
+  for (float f : {G.hs[0], G.hs[1], G.hs[2], G.hout}) {
     uint32_t b = 0;
     memcpy(&b, &f, sizeof(b));
     k.push_back((const void*)(uintptr_t)b);
@@ -2635,8 +2647,9 @@ extern "C" int vie_kernel_times(vie_ctx* ctx, const char** names, double* ms, in
   for (auto& P : ctx->bj) {  // block products of the sub-contexts
     if (!P || !P->sub) continue;
     timing_collect(P->sub);
-    for (int k = 0; k < 11; ++k) {
-      const int src = k < 10 ? k : kZH2Kind, dst = k < 10 ? kBlockKind0 + k : kBlockZH2Kind;
+    for (int k = 0; k < 15; ++k) {
+      const int src = k < 10 ? k : kH16Kind0 + k - 10;
+      const int dst = k < 10 ? kBlockKind0 + k : kBlockH16Kind0 + k - 10;
       ctx->kind_ms[dst] += P->sub->kind_ms[src];
       ctx->kind_cnt[dst] += P->sub->kind_cnt[src];
       P->sub->kind_ms[src] = 0;

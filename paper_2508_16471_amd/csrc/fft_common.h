@@ -20,6 +20,48 @@ struct LdsLine {
   __device__ __forceinline__ cpx<T>& operator[](int i) const { return p[pidx(i)]; }
 };
 
+// FP32 column pairs: lanes 2i (column c) and 2i+1 (column c+1) of one row
+// of threads move 16-byte row segments [c, c+1] -- the even lane the row of
+// its point 2k, the odd lane the row of its point 2k+1 -- and one lane swap
+// hands each lane its own column's two points.  Half the memory
+// instructions of one 8-byte access per point.
+__device__ __forceinline__ float swap_pair(float x) {
+  // lanes 2i <-> 2i+1 (DPP quad_perm [1,0,3,2])
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ void pair_in(const float4 f, int odd, cpx<float>& a, cpx<float>& b) {
+  const float sr = odd ? f.x : f.z, si = odd ? f.y : f.w;  // the partner's point
+  const float kr = odd ? f.z : f.x, ki = odd ? f.w : f.y;  // this lane's point
+  const float rr = swap_pair(sr), ri = swap_pair(si);
+  a = odd ? mk<float>(rr, ri) : mk<float>(kr, ki);
+  b = odd ? mk<float>(kr, ki) : mk<float>(rr, ri);
+}
+__device__ __forceinline__ float4 pair_out(int odd, const cpx<float>& a, const cpx<float>& b) {
+  const cpx<float> sd = odd ? a : b;
+  const float rr = swap_pair(sd.re), ri = swap_pair(sd.im);
+  const cpx<float> own = odd ? b : a;
+  return odd ? make_float4(rr, ri, own.re, own.im) : make_float4(own.re, own.im, rr, ri);
+}
+
+// Packed FP16 pairs for approximate products: one register holds the same
+// component of two neighbouring columns (v_pk_* arithmetic on both).
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ cpx<h2> pack2(float ar, float ai, float br, float bi) {
+  return mk<h2>(h2{(_Float16)ar, (_Float16)br}, h2{(_Float16)ai, (_Float16)bi});
+}
+// negate both halves of re and im when neg (sign bits flipped)
+__device__ __forceinline__ cpx<h2> negif(cpx<h2> a, bool neg) {
+  const unsigned m = neg ? 0x80008000u : 0u;
+  return mk<h2>(__builtin_bit_cast(h2, __builtin_bit_cast(unsigned, a.re) ^ m),
+                __builtin_bit_cast(h2, __builtin_bit_cast(unsigned, a.im) ^ m));
+}
+// a packed pair's two points as (re_a, im_a, re_b, im_b)
+__device__ __forceinline__ float4 unpack2(cpx<h2> h) {
+  return make_float4((float)h.re.x, (float)h.im.x, (float)h.re.y, (float)h.im.y);
+}
+__device__ __forceinline__ cpx<h2> hscale(cpx<h2> a, h2 s) { return mk<h2>(a.re * s, a.im * s); }
+
 // Twiddles of a thread's butterflies, loaded once per kernel into registers
 // and reused by every line the thread transforms (forward and inverse).
 // Stage with sub-length NS and radix RAD (not the first): butterfly b of

@@ -176,28 +176,6 @@ __device__ __forceinline__ void load_g6(const cpx<T>* __restrict__ sp, cpx<T> (&
   }
 }
 
-// FP32 column pairs: lanes 2i (column c) and 2i+1 (column c+1) of one row
-// of threads move 16-byte row segments [c, c+1] -- the even lane the row of
-// its point 2k, the odd lane the row of its point 2k+1 -- and one lane swap
-// hands each lane its own column's two points.  Half the memory
-// instructions of one 8-byte access per point.
-__device__ __forceinline__ float swap_pair(float x) {
-  // lanes 2i <-> 2i+1 (DPP quad_perm [1,0,3,2])
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
-}
-__device__ __forceinline__ void pair_in(const float4 f, int odd, cpx<float>& a, cpx<float>& b) {
-  const float sr = odd ? f.x : f.z, si = odd ? f.y : f.w;  // the partner's point
-  const float kr = odd ? f.z : f.x, ki = odd ? f.w : f.y;  // this lane's point
-  const float rr = swap_pair(sr), ri = swap_pair(si);
-  a = odd ? mk<float>(rr, ri) : mk<float>(kr, ki);
-  b = odd ? mk<float>(kr, ki) : mk<float>(rr, ri);
-}
-__device__ __forceinline__ float4 pair_out(int odd, const cpx<float>& a, const cpx<float>& b) {
-  const cpx<float> sd = odd ? a : b;
-  const float rr = swap_pair(sd.re), ri = swap_pair(sd.im);
-  const cpx<float> own = odd ? b : a;
-  return odd ? make_float4(rr, ri, own.re, own.im) : make_float4(own.re, own.im, rr, ri);
-}
 
 // FAST: the z block is 16, the blocked layout holds exactly P/2 rows (N3
 // rounded up to a multiple of 16 equals P/2) and the column tiles cover P1
@@ -592,44 +570,90 @@ static hipError_t z_pass(const GroupGeom& g, cpx<T>* B, const cpx<T>* spec, cons
   return hipGetLastError();
 }
 
-// ------------------------------- Z for approximate products: packed FP16
+// ------------------------------- approximate products: packed FP16 passes
 // The block solves of the block-Jacobi preconditioner only approximate its
-// inverse, so their z pass may run in FP16 arithmetic on packed pairs
-// (v_pk_fma_f16 and friends: two columns per lane, twice the FP32 rate);
-// storage stays FP32.  Each lane takes the two columns of a pair at its
-// rows (one 16-byte row segment per row), inputs are scaled by xs on
-// conversion (xs = 1 / sqrt(segment length) bounds every transform value by
-// one for the unit-norm block basis vectors), the spectrum is an FP16 copy
-// scaled by 1 / max|G| (spec16), and outputs are scaled back by os =
-// 1 / (xs gs) on conversion to FP32.  Layout conditions as the FAST paired
-// FP32 shape (z block 16, P/2 rows, column tiles covering P1).
+// inverse, so their products may run the y and z passes in FP16 arithmetic
+// on packed pairs (v_pk_fma_f16 and friends: two columns per register, twice
+// the FP32 rate) with both scratch buffers in FP16: a cpx<h2> holds columns
+// 2p and 2p + 1 of one row, so the FP32 layouts apply with every stride
+// halved and pair indices for columns.  The x passes transform in FP32 and
+// convert at the scratch side.
+//
+// Range: the input is a unit-norm basis vector x.  Each forward pass scales
+// its input by a power of two h_d <= 1 / sqrt(N_d) (N_d the box extent along
+// the axis), so by Cauchy-Schwarz every forward value of component b is at
+// most the 2-norm of x_b over the lines it sums (|sum of N_d terms| <=
+// sqrt(N_d) times their 2-norm), hence within one.  The spectrum copy is
+// scaled by gs = 2^-ceil(log2 max|G|) (entries within one), so a product
+// point is at most 3.  The inverse passes are unnormalised; with Parseval
+// along each axis the values after the inverse z pass are at most
+// sqrt(3) P3 / sqrt(N3), after the inverse y pass at most
+// sqrt(3) P2 P3 / sqrt(N2 N3) -- a few hundred for these grids, far inside
+// the FP16 range.  The FP32 inverse x pass scales back by 1 / (h1 h2 h3 gs).
+//
 // The spectrum copy is pair-packed: record (yo, zo, p) holds the six
 // entries of columns 2p and 2p + 1 as packed halves (octant lookups and the
 // x-mirror signs already applied), scaled by gs.
-typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ cpx<h2> pack2(float ar, float ai, float br, float bi) {
-  return mk<h2>(h2{(_Float16)ar, (_Float16)br}, h2{(_Float16)ai, (_Float16)bi});
+// y pass on packed pairs (the forward pass scales its input by hs).
+template <int P, bool INV, int NTB>
+__global__ __launch_bounds__(NTB) void k_fft_y_h2(const cpx<h2>* __restrict__ in,
+                                                 cpx<h2>* __restrict__ out,
+                                                 const cpx<h2>* __restrict__ tw, StridedArgs a,
+                                                 float hs, const int* __restrict__ active) {
+  constexpr int E = fft_e<P>(), TT = P / E, W = NTB / TT;
+  __shared__ cpx<h2> lds[W * Pad<P>::LSTR];
+  // block order as the FP32 strided pass
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int per_rhs = a.ncomp * a.nz;
+  const int nrhs_l = gridDim.x / (a.tiles * per_rhs);
+  const int rhs = b % nrhs_l, rest = b / nrhs_l;
+  const int tile = rest % a.tiles, cz = rest / a.tiles;
+  if (active && !active[rhs]) return;
+  const int comp = cz / a.nz, z = cz % a.nz;
+  const int cw = threadIdx.x % W, t = threadIdx.x / W;
+  const int col = tile * W + cw;
+  const bool valid = col < a.ncols;
+  const cpx<h2>* pin = in + slab_base(a.in, rhs, comp, z, a.zl) + (valid ? col : 0);
+  TwReg<h2, P, E> tr;
+  tr.load(t, tw);
+  const h2 sc = {(_Float16)hs, (_Float16)hs};
+  cpx<h2> v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int row = t + q * TT;
+    if ((INV || q < E / 2) && valid && row < a.n_in_rows) {
+      v[q] = pin[(int64_t)row * a.in.row];
+      if constexpr (!INV) v[q] = hscale(v[q], sc);
+    } else {
+      v[q] = mk<h2>(h2{0, 0}, h2{0, 0});
+    }
+  }
+  line_fft<h2, P, INV, !INV, INV>(v, lds + cw * Pad<P>::LSTR, t, tr);
+  if (valid) {
+    cpx<h2>* po = out + slab_base(a.out, rhs, comp, z, a.zl) + col;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int row = t + q * TT;
+      if ((!INV || q < E / 2) && row < a.n_out_rows) po[(int64_t)row * a.out.row] = v[q];
+    }
+  }
 }
-// negate both halves of re and im when neg (sign bits flipped)
-__device__ __forceinline__ cpx<h2> negif(cpx<h2> a, bool neg) {
-  const unsigned m = neg ? 0x80008000u : 0u;
-  return mk<h2>(__builtin_bit_cast(h2, __builtin_bit_cast(unsigned, a.re) ^ m),
-                __builtin_bit_cast(h2, __builtin_bit_cast(unsigned, a.im) ^ m));
-}
+
 __device__ __forceinline__ void load_g6h(const cpx<h2>* __restrict__ r, cpx<h2> (&g)[6]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) g[k] = r[k];
 }
 
-// at most 128 registers: two 8-wave workgroups per CU
+// z pass fused with the spectrum on packed pairs, in place on the packed
+// y/z scratch: each lane takes one column pair at its rows (8 bytes per
+// row), scales the input by hs; layout conditions as the FAST paired FP32
+// shape (z block 16, P/2 rows, column tiles covering P1).  At most 128
+// registers: two 8-wave workgroups per CU.
 template <int P, int E, int NT, bool ZP>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_z_green_h2(
-    c32* __restrict__ B,
-                                                        const cpx<h2>* __restrict__ spec,
-                                                        const cpx<h2>* __restrict__ tw, ZArgs a,
-                                                        float xs, float os,
-                                                        const int* __restrict__ active) {
+    cpx<h2>* __restrict__ B, const cpx<h2>* __restrict__ spec, const cpx<h2>* __restrict__ tw,
+    ZArgs a, float hs, const int* __restrict__ active) {
   constexpr int TT = P / E, WP = NT / TT, LS = Pad<P>::LSTR;
   __shared__ cpx<h2> lds[WP * LS];
   // block order as the FP32 z pass (right-hand side innermost, y mirror
@@ -646,27 +670,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   if (active && !active[rhs]) return;
   const int cw = threadIdx.x % WP, t = threadIdx.x / WP;
   const int x0 = tile * 2 * WP + 2 * cw;  // the pair's even column
-  float* cp0 = reinterpret_cast<float*>(B + rhs * a.rhs_stride + (int64_t)xy * a.zl * a.P1 + x0);
-  float* cp1 = cp0 + 2 * a.comp_stride;
-  float* cp2 = cp1 + 2 * a.comp_stride;
+  // FP32-layout strides are multiples of P1, so every halved one is exact
+  cpx<h2>* hp0 = B + (rhs * a.rhs_stride + (int64_t)xy * a.zl * a.P1 + x0) / 2;
+  cpx<h2>* hp1 = hp0 + a.comp_stride / 2;
+  cpx<h2>* hp2 = hp1 + a.comp_stride / 2;
+  const int zhs = (int)(a.zhs / 2), zls = (int)(a.zls / 2);
   TwReg<h2, P, E> tr;
   tr.load(t, tw);
+  const h2 sc = {(_Float16)hs, (_Float16)hs};
+  const cpx<h2> zero = mk<h2>(h2{0, 0}, h2{0, 0});
   cpx<h2> v0[E], v1[E], v2[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
+    v0[q] = v1[q] = v2[q] = zero;
     if (q < E / 2) {
-      // rows below P/2 exist in the blocked layout; padding rows read as zero
+      // rows below P/2 exist in the blocked layout; padding rows (never
+      // written) are not read
       const int z = t + q * TT;
-      const int off = 2 * ((z >> 4) * (int)a.zhs + (z & 15) * (int)a.zls);
-      const float sc = (!ZP || z < a.N3) ? xs : 0.f;
-      const float4 f0 = *reinterpret_cast<const float4*>(cp0 + off);
-      const float4 f1 = *reinterpret_cast<const float4*>(cp1 + off);
-      const float4 f2 = *reinterpret_cast<const float4*>(cp2 + off);
-      v0[q] = pack2(f0.x * sc, f0.y * sc, f0.z * sc, f0.w * sc);
-      v1[q] = pack2(f1.x * sc, f1.y * sc, f1.z * sc, f1.w * sc);
-      v2[q] = pack2(f2.x * sc, f2.y * sc, f2.z * sc, f2.w * sc);
-    } else {
-      v0[q] = v1[q] = v2[q] = mk<h2>(h2{0, 0}, h2{0, 0});
+      if (!ZP || z < a.N3) {
+        const int off = (z >> 4) * zhs + (z & 15) * zls;
+        v0[q] = hscale(hp0[off], sc);
+        v1[q] = hscale(hp1[off], sc);
+        v2[q] = hscale(hp2[off], sc);
+      }
     }
   }
   cpx<h2>* line = lds + cw * LS;
@@ -711,16 +737,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   for (int q = 0; q < E / 2; ++q) {
     const int z = t + q * TT;
     if (!ZP || z < a.N3) {
-      const int off = 2 * ((z >> 4) * (int)a.zhs + (z & 15) * (int)a.zls);
-      *reinterpret_cast<float4*>(cp0 + off) =
-          make_float4((float)v0[q].re.x * os, (float)v0[q].im.x * os, (float)v0[q].re.y * os,
-                      (float)v0[q].im.y * os);
-      *reinterpret_cast<float4*>(cp1 + off) =
-          make_float4((float)v1[q].re.x * os, (float)v1[q].im.x * os, (float)v1[q].re.y * os,
-                      (float)v1[q].im.y * os);
-      *reinterpret_cast<float4*>(cp2 + off) =
-          make_float4((float)v2[q].re.x * os, (float)v2[q].im.x * os, (float)v2[q].re.y * os,
-                      (float)v2[q].im.y * os);
+      const int off = (z >> 4) * zhs + (z & 15) * zls;
+      hp0[off] = v0[q];
+      hp1[off] = v1[q];
+      hp2[off] = v2[q];
     }
   }
 }
@@ -738,10 +758,15 @@ static int zh2_pairs() {
   return kZH2Threads / (P / zh2_e<P>());
 }
 
-// The packed-FP16 z pass's shape conditions for this grid (P3 = 32 .. 128).
-bool z_h2_ok(const GroupGeom& g) {
+bool x_packed_ok(int P1);
+
+// Whether a grid takes the packed-FP16 passes: the z pass's shape (z block
+// 16, P3 = 32 .. 128 with P3 / 2 rows in the blocked layout, column-pair
+// tiles covering P1) and an even number of threads per x line.
+bool h16_ok(const GroupGeom& g) {
   const int zl = z_block(g);
   if (zl != 16 || 2 * ((g.N[2] + 15) / 16) * 16 != g.P[2]) return false;
+  if (!x_packed_ok(g.P[0])) return false;
   int wp = 0;
   switch (g.P[2]) {
     case 32: wp = zh2_pairs<32>(); break;
@@ -754,9 +779,58 @@ bool z_h2_ok(const GroupGeom& g) {
   return g.P[0] % (2 * wp) == 0;
 }
 
-static hipError_t z_pass_h2(const GroupGeom& g, c32* B, const cpx<h2>* spec, const cpx<h2>* tw,
-                            float xs, float os, const int* active, hipStream_t s) {
-  if (!z_h2_ok(g)) return hipErrorInvalidValue;
+// FP32-layout addresses in units of packed pairs
+static SideAddr halved(SideAddr s) {
+  s.rs /= 2;
+  s.cs /= 2;
+  s.zhs /= 2;
+  s.zls /= 2;
+  s.row /= 2;
+  return s;
+}
+
+template <int PP>
+static void y_launch_h2(const GroupGeom& g, const cpx<h2>* in, cpx<h2>* out, const cpx<h2>* tw,
+                        bool inverse, float hs, const int* active, hipStream_t s) {
+  const int N2 = g.N[1], N3 = g.N[2];
+  const int zl = z_block(g);
+  constexpr int ntY = y_threads<h2, PP>();
+  constexpr int W = ntY / (PP / fft_e<PP>());
+  StridedArgs a;
+  a.ncols = g.P[0] / 2;
+  a.ncomp = 3;
+  a.nz = N3;
+  a.zl = zl;
+  a.tiles = (a.ncols + W - 1) / W;
+  const SideAddr A = halved(side_A(g, zl)), B = halved(side_B(g, zl));
+  if (!inverse) {
+    a.n_in_rows = N2;
+    a.n_out_rows = PP;
+    a.in = A;
+    a.out = B;
+  } else {
+    a.n_in_rows = PP;
+    a.n_out_rows = N2;
+    a.in = B;
+    a.out = A;
+  }
+  const dim3 grid(a.tiles * 3 * N3 * g.nrhs);
+  if (!inverse)
+    k_fft_y_h2<PP, false, ntY><<<grid, ntY, 0, s>>>(in, out, tw, a, hs, active);
+  else
+    k_fft_y_h2<PP, true, ntY><<<grid, ntY, 0, s>>>(in, out, tw, a, 1.f, active);
+}
+
+static hipError_t y_pass_h2(const GroupGeom& g, const cpx<h2>* in, cpx<h2>* out,
+                            const cpx<h2>* tw, bool inverse, float hs, const int* active,
+                            hipStream_t s) {
+  VIE_DISPATCH_P(g.P[1], (y_launch_h2<PP>(g, in, out, tw, inverse, hs, active, s)));
+  return hipGetLastError();
+}
+
+static hipError_t z_pass_h2(const GroupGeom& g, cpx<h2>* B, const cpx<h2>* spec,
+                            const cpx<h2>* tw, float hs, const int* active, hipStream_t s) {
+  if (!h16_ok(g)) return hipErrorInvalidValue;
   ZArgs a;
   a.N3 = g.N[2];
   a.P1 = g.P[0];
@@ -766,7 +840,7 @@ static hipError_t z_pass_h2(const GroupGeom& g, c32* B, const cpx<h2>* spec, con
   a.Q3 = g.Q[2];
   a.nrhs = g.nrhs;
   a.zl = z_block(g);
-  const SideAddr sb = side_B(g, a.zl);
+  const SideAddr sb = side_B(g, a.zl);  // FP32-layout strides (halved in the kernel)
   a.comp_stride = sb.cs;
   a.rhs_stride = sb.rs;
   a.zhs = sb.zhs;
@@ -777,10 +851,10 @@ static hipError_t z_pass_h2(const GroupGeom& g, c32* B, const cpx<h2>* spec, con
     const dim3 grid((g.P[1] / 2 + 1) * 2 * a.tiles_x * g.nrhs);                               \
     if (2 * a.N3 == P_)                                                                       \
       k_fft_z_green_h2<P_, zh2_e<P_>(), kZH2Threads, false>                                   \
-          <<<grid, kZH2Threads, 0, s>>>(B, spec, tw, a, xs, os, active);                      \
+          <<<grid, kZH2Threads, 0, s>>>(B, spec, tw, a, hs, active);                          \
     else                                                                                      \
       k_fft_z_green_h2<P_, zh2_e<P_>(), kZH2Threads, true>                                    \
-          <<<grid, kZH2Threads, 0, s>>>(B, spec, tw, a, xs, os, active);                      \
+          <<<grid, kZH2Threads, 0, s>>>(B, spec, tw, a, hs, active);                          \
     break;                                                                                    \
   }
   switch (g.P[2]) {
@@ -795,9 +869,9 @@ static hipError_t z_pass_h2(const GroupGeom& g, c32* B, const cpx<h2>* spec, con
   return hipGetLastError();
 }
 
-// FP16 tables of the packed z pass: the pair-packed spectrum (scaled by gs,
-// x-mirror signs applied: entries xy and xz are odd along x), and the z
-// twiddles splatted to both halves.
+// FP16 tables of the packed passes: the pair-packed spectrum (scaled by gs,
+// x-mirror signs applied: entries xy and xz are odd along x), and the y and
+// z twiddles splatted to both halves.
 __global__ void k_spec_pairs(const c32* __restrict__ in, cpx<h2>* __restrict__ out, int P1,
                              int Q1, int64_t nyz, float gs) {
   const int npair = P1 / 2;
@@ -889,13 +963,14 @@ static hipError_t x_inv(const GroupGeom& g, const cpx<T>* A, const c64* x, c64* 
   return hipGetLastError();
 }
 
+// hs > 0: packed FP16 lines on the scratch side (see the x passes)
 template <typename T>
 hipError_t x_fwd_c(const GroupGeom& g, const void* xc, int in32, cpx<T>* A, const cpx<T>* tw,
-                   const BodyIdx& bi, const int* active, hipStream_t s);
+                   const BodyIdx& bi, const int* active, hipStream_t s, float hs = 0.f);
 template <typename T>
 hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const void* x, void* y, int io32,
                    const cpx<T>* tw, const BodyIdx& bi, EpiArgs& e, const int* active,
-                   hipStream_t s);
+                   hipStream_t s, float hs = 0.f);
 
 template <typename T>
 static hipError_t matvec_t(const MatvecArgs& m, const void* xv, void* yv, EpiArgs& e,
@@ -911,27 +986,37 @@ static hipError_t matvec_t(const MatvecArgs& m, const void* xv, void* yv, EpiArg
   const cpx<T>* tw1 = (const cpx<T>*)m.tw[1];
   const cpx<T>* tw2 = (const cpx<T>*)m.tw[2];
   hipError_t err;
-  const int base = sizeof(T) == 8 ? 0 : 5;
+  int base = sizeof(T) == 8 ? 0 : 5;
 #define STEP(K, CALL)              \
   if (cb) cb(base + K, true, u);   \
   err = CALL;                      \
   if (cb) cb(base + K, false, u);  \
   if (err != hipSuccess) return err;
+  if (m.spec16) {  // approximate products: packed FP16 y and z passes, FP16 scratch
+    if constexpr (sizeof(T) == 4) {
+      if (!m.bi || m.io32 != 2 || e.mode != EPI_PLAIN) return hipErrorInvalidValue;
+      cpx<h2>* Ah = (cpx<h2>*)m.bufA;
+      cpx<h2>* Bh = (cpx<h2>*)m.bufB;
+      const cpx<h2>* twy = (const cpx<h2>*)m.tw16[0];
+      const cpx<h2>* twz = (const cpx<h2>*)m.tw16[1];
+      base = kH16Kind0;
+      STEP(0, x_fwd_c<T>(g, xv, m.io32, A, tw0, *m.bi, m.active, s, m.hs[0]));
+      STEP(1, y_pass_h2(g, Ah, Bh, twy, false, m.hs[1], m.active, s));
+      STEP(2, z_pass_h2(g, Bh, (const cpx<h2>*)m.spec16, twz, m.hs[2], m.active, s));
+      STEP(3, y_pass_h2(g, Bh, Ah, twy, true, 1.f, m.active, s));
+      STEP(4, x_inv_c<T>(g, A, xv, yv, m.io32, tw0, *m.bi, e, m.active, s, m.hout));
+      return hipSuccess;
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if (m.bi) {
     STEP(0, x_fwd_c<T>(g, xv, m.io32, A, tw0, *m.bi, m.active, s));
   } else {
     STEP(0, x_fwd<T>(g, x, A, tw0, m.active, s));
   }
   STEP(1, y_pass<T>(g, A, B, tw1, false, m.active, s));
-  if (m.spec16 && sizeof(T) == 4) {  // approximate products: packed-FP16 z pass
-    if (cb) cb(kZH2Kind, true, u);
-    err = z_pass_h2(g, (c32*)B, (const cpx<h2>*)m.spec16, (const cpx<h2>*)m.tw16, m.zh_in,
-                    m.zh_out, m.active, s);
-    if (cb) cb(kZH2Kind, false, u);
-    if (err != hipSuccess) return err;
-  } else {
-    STEP(2, z_pass<T>(g, B, (const cpx<T>*)m.spec, tw2, m.active, s, m.zvar));
-  }
+  STEP(2, z_pass<T>(g, B, (const cpx<T>*)m.spec, tw2, m.active, s, m.zvar));
   STEP(3, y_pass<T>(g, B, A, tw1, true, m.active, s));
   if (m.bi) {
     STEP(4, x_inv_c<T>(g, A, xv, yv, m.io32, tw0, *m.bi, e, m.active, s));

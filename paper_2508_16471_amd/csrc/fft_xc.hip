@@ -15,10 +15,14 @@
 namespace vie {
 
 // ---------------------------------------------------------------- X forward
-template <typename T, int P, typename TI>
+// H (FP32 only): the transformed lines are stored as packed FP16 column
+// pairs scaled by hs (cpx<h2> per pair of neighbouring points of a line);
+// lanes t and t + 1 of a line exchange one point per pair of registers.
+template <typename T, int P, typename TI, bool H = false>
 __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_fwd_c(
-    const cpx<TI>* __restrict__ xc, cpx<T>* __restrict__ out, const cpx<T>* __restrict__ tw,
-    BodyIdx bi, int N1, int N2, int N3, int blocks_per_rhs, const int* __restrict__ active) {
+    const cpx<TI>* __restrict__ xc, void* __restrict__ outv, const cpx<T>* __restrict__ tw,
+    BodyIdx bi, int N1, int N2, int N3, int blocks_per_rhs, const int* __restrict__ active,
+    float hs) {
   constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines_p<T>(P), L = NT / TT,
                 LS = Pad<P>::LSTR;
   __shared__ cpx<T> lds[L * LS];
@@ -56,8 +60,19 @@ __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_fwd_c(
 #pragma unroll
   for (int q = 0; q < E; ++q) v[q] = (q < E / 2) ? myl[pidx(t + q * TT)] : mk<T>(0, 0);
   line_fft<T, P, false, true>(v, myl, t, tr);  // upper half is zero padding
-  if (valid) {
-    cpx<T>* o = out + ((size_t)rhs * lines_per_rhs + line) * P;
+  if constexpr (H) {
+    static_assert(sizeof(T) == 4 && TT % 2 == 0, "packed lines need FP32 and lane pairs");
+    // pair q/2 of lane pair (t, t + 1): points t + q TT (even lane's) and
+    // t + 1 + q TT; the even lane stores it for even q, the odd lane for odd q
+    const int odd = t & 1;
+    cpx<h2>* o = reinterpret_cast<cpx<h2>*>(outv) + ((size_t)rhs * lines_per_rhs + lc) * (P / 2);
+#pragma unroll
+    for (int q = 0; q < E; q += 2) {
+      const float4 f = pair_out(odd, v[q], v[q + 1]);
+      if (valid) o[(t - odd + (q + odd) * TT) >> 1] = pack2(f.x * hs, f.y * hs, f.z * hs, f.w * hs);
+    }
+  } else if (valid) {
+    cpx<T>* o = reinterpret_cast<cpx<T>*>(outv) + ((size_t)rhs * lines_per_rhs + line) * P;
 #pragma unroll
     for (int q = 0; q < E; ++q) o[t + q * TT] = v[q];
   }
@@ -65,12 +80,14 @@ __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_fwd_c(
 
 // ------------------------------------------------ X inverse + epilogue
 // TX: storage of the input vector (the epilogue's x), TIO of the output.
-template <typename T, int P, int MODE, typename TIO, typename TX = TIO>
+// H (FP32 only): A holds packed FP16 column pairs (see the forward pass);
+// the convolution is scaled by hs before the epilogue.
+template <typename T, int P, int MODE, typename TIO, typename TX = TIO, bool H = false>
 __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_inv_c(
-    const cpx<T>* __restrict__ A, const cpx<TX>* __restrict__ xin, cpx<TIO>* __restrict__ yout,
+    const void* __restrict__ Av, const cpx<TX>* __restrict__ xin, cpx<TIO>* __restrict__ yout,
     const cpx<T>* __restrict__ tw, BodyIdx bi, int N1, int N2, int N3, int blocks_per_rhs,
     c64* __restrict__ aux, c64* __restrict__ partials, const c64* __restrict__ pol,
-    const c64* __restrict__ ph, const int* __restrict__ active) {
+    const c64* __restrict__ ph, const int* __restrict__ active, float hs) {
   constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines_p<T>(P), L = NT / TT,
                 LS = Pad<P>::LSTR;
   __shared__ cpx<T> lds[L * LS];
@@ -90,8 +107,20 @@ __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_inv_c(
   TwReg<T, P, E> tr;
   tr.load(t, tw);
   cpx<T> v[E];
-  {
-    const cpx<T>* src = A + gl * P;
+  if constexpr (H) {
+    static_assert(sizeof(T) == 4 && TT % 2 == 0, "packed lines need FP32 and lane pairs");
+    // the even lane loads pair q/2 for even q, the odd lane for odd q; one
+    // exchange hands each lane its own point of both
+    const int odd = t & 1;
+    const cpx<h2>* src = reinterpret_cast<const cpx<h2>*>(Av) + gl * (P / 2);
+#pragma unroll
+    for (int q = 0; q < E; q += 2) {
+      float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (valid) f = unpack2(src[(t - odd + (q + odd) * TT) >> 1]);
+      pair_in(f, odd, v[q], v[q + 1]);
+    }
+  } else {
+    const cpx<T>* src = reinterpret_cast<const cpx<T>*>(Av) + gl * P;
 #pragma unroll
     for (int q = 0; q < E; ++q) v[q] = valid ? src[t + q * TT] : mk<T>(0, 0);
   }
@@ -121,7 +150,8 @@ __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_inv_c(
     }
     for (int k = lp[zy] + t; k < k1; k += TT) {
       const int xi = vox[k] - base;
-      const c64 conv = cvt<double>(myl[pidx(xi)]);
+      c64 conv = cvt<double>(myl[pidx(xi)]);
+      if constexpr (H) conv = (double)hs * conv;
       const double c = chic[k];
       const int64_t gi = vb + k;
       const c64 xv = cvt<double>(xin[gi]);
@@ -154,26 +184,52 @@ __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_inv_c(
 }
 
 // ================================================================ launchers
+// Packed FP16 lines need an even number of threads per line (P >= 24).
+template <int P>
+constexpr bool packed_lines_ok() {
+  return (P / fft_e_of(P)) % 2 == 0;
+}
+bool x_packed_ok(int P1) { return (P1 / fft_e_of(P1)) % 2 == 0; }
+
 template <typename T>
 hipError_t x_fwd_c(const GroupGeom& g, const void* xc, int in32, cpx<T>* A, const cpx<T>* tw,
-                   const BodyIdx& bi, const int* active, hipStream_t s) {
+                   const BodyIdx& bi, const int* active, hipStream_t s, float hs) {
   const int lines = 3 * g.N[1] * g.N[2];
   const int L = lines_per_block<T>(g.P[0]);
   const int bpr = (lines + L - 1) / L;
   const dim3 grid(bpr * g.nrhs);
+  if (hs > 0.f) {  // packed FP16 output from bfloat16 input (FP32 arithmetic)
+    if constexpr (sizeof(T) == 4) {
+      if (in32 != 2) return hipErrorInvalidValue;
+      VIE_DISPATCH_P(g.P[0], ({
+                       if constexpr (packed_lines_ok<PP>()) {
+                         k_fft_x_fwd_c<T, PP, __bf16, true><<<grid, nt_lines_p<T>(PP), 0, s>>>(
+                             (const cb16*)xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active, hs);
+                       } else {
+                         return hipErrorInvalidValue;
+                       }
+                     }));
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if (in32 == 2) {  // bfloat16 input (FP32 products only)
     if constexpr (sizeof(T) == 4) {
       VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd_c<T, PP, __bf16><<<grid, nt_lines_p<T>(PP), 0, s>>>(
-                                 (const cb16*)xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active)));
+                                 (const cb16*)xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active,
+                                 0.f)));
     } else {
       return hipErrorInvalidValue;
     }
   } else if (in32) {
     VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd_c<T, PP, float><<<grid, nt_lines_p<T>(PP), 0, s>>>(
-                               (const c32*)xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active)));
+                               (const c32*)xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active,
+                               0.f)));
   } else {
     VIE_DISPATCH_P(g.P[0], (k_fft_x_fwd_c<T, PP, double><<<grid, nt_lines_p<T>(PP), 0, s>>>(
-                               (const c64*)xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active)));
+                               (const c64*)xc, A, tw, bi, g.N[0], g.N[1], g.N[2], bpr, active,
+                               0.f)));
   }
   return hipGetLastError();
 }
@@ -181,12 +237,30 @@ hipError_t x_fwd_c(const GroupGeom& g, const void* xc, int in32, cpx<T>* A, cons
 template <typename T>
 hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const void* x, void* y, int io32,
                    const cpx<T>* tw, const BodyIdx& bi, EpiArgs& e, const int* active,
-                   hipStream_t s) {
+                   hipStream_t s, float hs) {
   const int lines = 3 * g.N[1] * g.N[2];
   const int L = lines_per_block<T>(g.P[0]);
   const int bpr = (lines + L - 1) / L;
   e.part_blocks = bpr;
   const dim3 grid(bpr * g.nrhs);
+  if (hs > 0.f) {  // packed FP16 input lines, bfloat16 x, FP32 y, plain epilogue
+    if constexpr (sizeof(T) == 4) {
+      if (io32 != 2 || e.mode != EPI_PLAIN) return hipErrorInvalidValue;
+      VIE_DISPATCH_P(g.P[0], ({
+                       if constexpr (packed_lines_ok<PP>()) {
+                         k_fft_x_inv_c<T, PP, EPI_PLAIN, float, __bf16, true>
+                             <<<grid, nt_lines_p<T>(PP), 0, s>>>(
+                                 A, (const cb16*)x, (c32*)y, tw, bi, g.N[0], g.N[1], g.N[2], bpr,
+                                 e.aux, e.partials, e.pol, e.ph, active, hs);
+                       } else {
+                         return hipErrorInvalidValue;
+                       }
+                     }));
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if (io32) {  // FP32 output (input FP32, or bfloat16 for io32 = 2): the plain product only
     if (e.mode != EPI_PLAIN) return hipErrorInvalidValue;
     if (io32 == 2) {
@@ -194,7 +268,7 @@ hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const void* x, void* y, 
         VIE_DISPATCH_P(g.P[0], (k_fft_x_inv_c<T, PP, EPI_PLAIN, float, __bf16>
                                 <<<grid, nt_lines_p<T>(PP), 0, s>>>(
                                     A, (const cb16*)x, (c32*)y, tw, bi, g.N[0], g.N[1], g.N[2],
-                                    bpr, e.aux, e.partials, e.pol, e.ph, active)));
+                                    bpr, e.aux, e.partials, e.pol, e.ph, active, 0.f)));
       } else {
         return hipErrorInvalidValue;
       }
@@ -202,13 +276,13 @@ hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const void* x, void* y, 
     }
     VIE_DISPATCH_P(g.P[0], (k_fft_x_inv_c<T, PP, EPI_PLAIN, float><<<grid, nt_lines_p<T>(PP), 0, s>>>(
                                A, (const c32*)x, (c32*)y, tw, bi, g.N[0], g.N[1], g.N[2], bpr,
-                               e.aux, e.partials, e.pol, e.ph, active)));
+                               e.aux, e.partials, e.pol, e.ph, active, 0.f)));
     return hipGetLastError();
   }
 #define VIE_XINVC(MODE_)                                                                      \
   VIE_DISPATCH_P(g.P[0], (k_fft_x_inv_c<T, PP, MODE_, double><<<grid, nt_lines_p<T>(PP), 0, s>>>(   \
                              A, (const c64*)x, (c64*)y, tw, bi, g.N[0], g.N[1], g.N[2], bpr,  \
-                             e.aux, e.partials, e.pol, e.ph, active)))
+                             e.aux, e.partials, e.pol, e.ph, active, 0.f)))
   switch (e.mode) {
     case EPI_PLAIN: VIE_XINVC(EPI_PLAIN); break;
     case EPI_RHV: VIE_XINVC(EPI_RHV); break;
@@ -221,12 +295,14 @@ hipError_t x_inv_c(const GroupGeom& g, const cpx<T>* A, const void* x, void* y, 
 }
 
 template hipError_t x_fwd_c<double>(const GroupGeom&, const void*, int, c64*, const c64*,
-                                    const BodyIdx&, const int*, hipStream_t);
+                                    const BodyIdx&, const int*, hipStream_t, float);
 template hipError_t x_fwd_c<float>(const GroupGeom&, const void*, int, c32*, const c32*,
-                                   const BodyIdx&, const int*, hipStream_t);
+                                   const BodyIdx&, const int*, hipStream_t, float);
 template hipError_t x_inv_c<double>(const GroupGeom&, const c64*, const void*, void*, int,
-                                    const c64*, const BodyIdx&, EpiArgs&, const int*, hipStream_t);
+                                    const c64*, const BodyIdx&, EpiArgs&, const int*, hipStream_t,
+                                    float);
 template hipError_t x_inv_c<float>(const GroupGeom&, const c32*, const void*, void*, int,
-                                   const c32*, const BodyIdx&, EpiArgs&, const int*, hipStream_t);
+                                   const c32*, const BodyIdx&, EpiArgs&, const int*, hipStream_t,
+                                   float);
 
 }  // namespace vie

@@ -69,12 +69,15 @@ struct MatvecArgs {
   const BodyIdx* bi = nullptr;  // non-null: x and y are body-compressed
   int io32 = 0;  // compressed x and y stored in FP32 (FP32 passes, plain epilogue only);
                  // 2: x stored in bfloat16, y in FP32
-  // FP32 products only: with spec16 set, the z pass runs in packed FP16 on the
-  // scaled FP16 spectrum copy spec16 and twiddles tw16 (input scale zh_in,
-  // output scale zh_out; see z_h2_ok for the grids it takes)
+  // Approximate products (FP32, bfloat16 x, FP32 y, plain epilogue): with
+  // spec16 set the y and z passes run in packed FP16 arithmetic on FP16
+  // scratch (see h16_ok for the grids this takes): spec16 the scaled
+  // pair-packed spectrum, tw16 the splatted y and z twiddles, hs the forward
+  // scales along x, y, z, hout the inverse x pass's scale back.
   const void* spec16 = nullptr;
-  const void* tw16 = nullptr;
-  float zh_in = 0.f, zh_out = 0.f;
+  const void* tw16[2] = {nullptr, nullptr};
+  float hs[3] = {0.f, 0.f, 0.f};
+  float hout = 0.f;
 };
 
 // precision 0: FP64 passes, 1: FP32 passes (input/output vectors are FP64)
@@ -100,13 +103,13 @@ hipError_t launch_matvec(const MatvecArgs& a, int precision, const void* x, void
 int z_variants(int precision);  // z-pass launch shapes (0 = FP64, 1 = FP32)
 // z pass alone on bufB (autotuning; contents are scratch)
 hipError_t launch_z_only(const MatvecArgs& a, int precision, hipStream_t s);
-// Packed-FP16 z pass for approximate FP32 products: whether the grid takes
-// it, and its tables: max |re|, |im| of an FP32 octant spectrum (n complex
-// values) as float bits atomically maxed into *dmax (zeroed by the caller),
-// the pair-packed FP16 copy scaled by gs (Q2 Q3 P1/2 6 packed pairs, 8 bytes
-// each), the splatted FP16 twiddles of n points.
-bool z_h2_ok(const GroupGeom& g);
-static constexpr int kZH2Kind = 26;  // its timing kind in the product's callback
+// Packed-FP16 y and z passes of approximate FP32 products: whether the grid
+// takes them, and their tables: max |re|, |im| of an FP32 octant spectrum (n
+// complex values) as float bits atomically maxed into *dmax (zeroed by the
+// caller), the pair-packed FP16 copy scaled by gs (Q2 Q3 P1/2 6 packed
+// pairs, 8 bytes each), the splatted FP16 twiddles of n points.
+bool h16_ok(const GroupGeom& g);
+static constexpr int kH16Kind0 = 26;  // timing kinds of their five passes (26..30)
 hipError_t launch_spec_absmax(const void* spec32, int64_t n, unsigned* dmax, hipStream_t s);
 hipError_t launch_spec_pairs(const void* spec32, void* spec16, const GroupGeom& g, float gs,
                              hipStream_t s);

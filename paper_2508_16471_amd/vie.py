@@ -330,7 +330,9 @@ def vie_set_options(ctx, opt):
 
 
 def vie_kernel_times(ctx, reset=False):
-    cap = 32
+    nk = C.c_int32(0)
+    _check(lib().vie_kernel_times(ctx, None, None, None, C.byref(nk), 0), "vie_kernel_times")
+    cap = nk.value
     names = (C.c_char_p * cap)()
     ms = (C.c_double * cap)()
     cnt = (C.c_int64 * cap)()

@@ -263,9 +263,12 @@ def test_fgmres_empty_body_and_silent_body(V):
         V.vie_destroy(ctx)
 
 
-def test_packed_fp16_block_products(V):
+# block boxes 60 x 60 x 29 (FFT 128 x 128 x 64) and 32 x 24 x 40 (FFT 64 x 48 x 96:
+# 3 * 2^k lines in y and z)
+@pytest.mark.parametrize("n", [(120, 120, 29), (64, 48, 40)])
+def test_packed_fp16_block_products(V, n):
     rng = np.random.default_rng(41)
-    n, h = (120, 120, 29), 0.03
+    h = 0.03
     g = Grid.centred(n, h)
     eps = 1.0 + rng.uniform(0.5, 2.0, size=n[::-1])
     eps[rng.random(eps.shape) < 0.2] = 1.0
@@ -281,8 +284,12 @@ def test_packed_fp16_block_products(V):
             t = V.vie_kernel_times(ctx, reset=True)
         finally:
             V.vie_destroy(ctx)
-        print(inner, "z launches fp32", t["block_fft_z_green_f32"][1], "fp16", t["block_fft_z_h2_f32"][1])
-        assert (t["block_fft_z_h2_f32"][1] > 0) == (inner == V.VIE_MIXED_BF16)
+        passes = ("x_fwd", "y_fwd", "z", "y_inv", "x_inv")
+        n16 = [t["block_fft_%s_h16" % k][1] for k in passes]
+        n32 = [t["block_fft_%s_f32" % ("z_green" if k == "z" else k)][1] for k in passes]
+        print(inner, "block launches fp32", n32, "packed fp16", n16)
+        packed = inner == V.VIE_MIXED_BF16
+        assert all((c > 0) == packed for c in n16) and all((c > 0) != packed for c in n32)
     e = np.linalg.norm(out[V.VIE_MIXED_BF16] - out[V.VIE_MIXED]) / np.linalg.norm(out[V.VIE_MIXED])
     print("packed-FP16 preconditioner vs FP32", e)
     assert e < 2e-2
