@@ -695,10 +695,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       }
     }
   }
-  cpx<h2>* line = lds + cw * LS;
-  line_fft_e<h2, P, E, false, true, false>(v0, line, t, tr);
-  line_fft_e<h2, P, E, false, true, false>(v1, line, t, tr);
-  line_fft_e<h2, P, E, false, true, false>(v2, line, t, tr);
   const int ym = xy > a.P2 / 2;
   const int yo = ym ? a.P2 - xy : xy;
   const int npair = a.P1 / 2;
@@ -707,11 +703,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int z = t + q * TT;
     return sp + (int64_t)(z > P / 2 ? P - z : z) * 6 * npair;
   };
-  // the next point's record is requested while this point is multiplied
-  // (the empty asm statements keep the compiler from issuing every point's
-  // loads at once, which would hold 12 registers per point)
+  cpx<h2>* line = lds + cw * LS;
+  line_fft_e<h2, P, E, false, true, false>(v0, line, t, tr);
+  line_fft_e<h2, P, E, false, true, false>(v1, line, t, tr);
+  // the first point's record is requested before the last forward
+  // transform, each next one while the current point is multiplied (the
+  // empty asm statements keep the compiler from issuing every point's loads
+  // at once, which would hold 12 registers per point)
   cpx<h2> gn[6];
   load_g6h(rec(0), gn);
+  asm volatile("" ::: "memory");
+  line_fft_e<h2, P, E, false, true, false>(v2, line, t, tr);
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int z = t + q * TT;
@@ -748,7 +750,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // 8 points per thread (6 for 3 * 2^k lines), 512 threads: 64 column pairs
 // per workgroup; the packed data of three components stay within a register
 // budget that keeps several waves per SIMD.
-constexpr int kZH2Threads = 512;
+constexpr int kZH2Threads = 256;
 template <int P>
 constexpr int zh2_e() {
   return P % 3 == 0 ? 6 : 8;

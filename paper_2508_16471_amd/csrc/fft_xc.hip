@@ -51,9 +51,23 @@ __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_fwd_c(
   for (int q = 0; q < E / 2; ++q) myl[pidx(t + q * TT)] = mk<T>(0, 0);
   lds_barrier();
   if (valid) {
-    const int k1 = lp[zy + 1];
+    // a line holds at most P/2 voxels, so at most E/2 per thread: all their
+    // loads are issued before the first LDS write
+    const int k0 = lp[zy] + t, k1 = lp[zy + 1];
     const int base = zy * N1;
-    for (int k = lp[zy] + t; k < k1; k += TT) myl[pidx(vox[k] - base)] = cvt<T>(xv[k]);
+    int kv[E / 2];
+    cpx<TI> xr[E / 2];
+#pragma unroll
+    for (int i = 0; i < E / 2; ++i) {
+      const int k = k0 + i * TT;
+      if (k < k1) {
+        kv[i] = vox[k];
+        xr[i] = xv[k];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < E / 2; ++i)
+      if (k0 + i * TT < k1) myl[pidx(kv[i] - base)] = cvt<T>(xr[i]);
   }
   lds_barrier();
   cpx<T> v[E];
@@ -148,13 +162,31 @@ __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_inv_c(
       phyz = phr[N1 + y] * phr[N1 + N2 + z];
       pc = pol[rhs * 3 + comp];
     }
-    for (int k = lp[zy] + t; k < k1; k += TT) {
-      const int xi = vox[k] - base;
+    // a line holds at most P/2 voxels, so at most E/2 per thread: all their
+    // loads are issued before the first use
+    const int k0 = lp[zy] + t;
+    int kv[E / 2];
+    double cv[E / 2];
+    cpx<TX> xr[E / 2];
+#pragma unroll
+    for (int i = 0; i < E / 2; ++i) {
+      const int k = k0 + i * TT;
+      if (k < k1) {
+        kv[i] = vox[k];
+        cv[i] = chic[k];
+        xr[i] = xin[vb + k];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < E / 2; ++i) {
+      const int k = k0 + i * TT;
+      if (k >= k1) continue;
+      const int xi = kv[i] - base;
       c64 conv = cvt<double>(myl[pidx(xi)]);
       if constexpr (H) conv = (double)hs * conv;
-      const double c = chic[k];
+      const double c = cv[i];
       const int64_t gi = vb + k;
-      const c64 xv = cvt<double>(xin[gi]);
+      const c64 xv = cvt<double>(xr[i]);
       const c64 y = xv - c * conv;
       if (MODE == EPI_RESID) {
         const c64 e = pc * (phyz * phr[xi]);
