@@ -161,6 +161,10 @@ def kernel_bytes(kind, N, P, Q, epi_extra=0, nb=None, vb=16, vin=None):
     c = 16 if kind.endswith("f64") else (4 if kind.endswith("h16") else 8)
     A = 3 * N3 * N2 * P1
     B = 3 * N3 * P2 * P1
+    if kind.startswith("fft_xy_fwd"):  # fused packed x-y: compressed input to y/z scratch
+        return 3 * nb * ((vin or vb) + 4) + 3 * (N2 * N3 + 1) * 4 + B * c
+    if kind.startswith("fft_yx_inv"):  # fused packed y-x: y/z scratch to compressed output
+        return B * c + 3 * nb * (vb + (vin or vb) + 8 + 4) + 3 * (N2 * N3 + 1) * 4 + epi_extra
     if kind.startswith("fft_x_fwd"):
         if nb is not None:
             return 3 * nb * ((vin or vb) + 4) + 3 * (N2 * N3 + 1) * 4 + A * c

@@ -215,8 +215,9 @@ struct BlockPrec {
 // own groups (0..14), the product passes of the block solves run on a
 // block-Jacobi sub-context (15..24, same order as 0..9), the Arnoldi
 // vector kernels of FGMRES (25), and the packed-FP16 passes of approximate
-// FP32 products (26..30 the context's own, 31..35 the block solves', same
-// order as 0..4).
+// FP32 products (26..32 the context's own: the five passes in the order of
+// 0..4, then the fused x-y forward and inverse passes; 33..39 the block
+// solves').
 static const char* kKindNames[] = {
     "fft_x_fwd_f64",       "fft_y_fwd_f64",       "fft_z_green_f64",       "fft_y_inv_f64",
     "fft_x_inv_f64",       "fft_x_fwd_f32",       "fft_y_fwd_f32",         "fft_z_green_f32",
@@ -225,10 +226,11 @@ static const char* kKindNames[] = {
     "block_fft_y_fwd_f64", "block_fft_z_green_f64", "block_fft_y_inv_f64", "block_fft_x_inv_f64",
     "block_fft_x_fwd_f32", "block_fft_y_fwd_f32", "block_fft_z_green_f32", "block_fft_y_inv_f32",
     "block_fft_x_inv_f32", "arnoldi",               "fft_x_fwd_h16",         "fft_y_fwd_h16",
-    "fft_z_h16",           "fft_y_inv_h16",       "fft_x_inv_h16",         "block_fft_x_fwd_h16",
-    "block_fft_y_fwd_h16", "block_fft_z_h16",     "block_fft_y_inv_h16",   "block_fft_x_inv_h16"};
-static constexpr int kNumKinds = 36;
-static constexpr int kBlockKind0 = 15, kArnoldiKind = 25, kBlockH16Kind0 = 31;
+    "fft_z_h16",           "fft_y_inv_h16",       "fft_x_inv_h16",         "fft_xy_fwd_h16",
+    "fft_yx_inv_h16",      "block_fft_x_fwd_h16", "block_fft_y_fwd_h16",   "block_fft_z_h16",
+    "block_fft_y_inv_h16", "block_fft_x_inv_h16", "block_fft_xy_fwd_h16",  "block_fft_yx_inv_h16"};
+static constexpr int kNumKinds = 40;
+static constexpr int kBlockKind0 = 15, kArnoldiKind = 25, kBlockH16Kind0 = 33;
 static_assert(kH16Kind0 == 26, "timing kind table");
 
 struct vie_cnn {
@@ -2647,7 +2649,7 @@ extern "C" int vie_kernel_times(vie_ctx* ctx, const char** names, double* ms, in
   for (auto& P : ctx->bj) {  // block products of the sub-contexts
     if (!P || !P->sub) continue;
     timing_collect(P->sub);
-    for (int k = 0; k < 15; ++k) {
+    for (int k = 0; k < 17; ++k) {
       const int src = k < 10 ? k : kH16Kind0 + k - 10;
       const int dst = k < 10 ? kBlockKind0 + k : kBlockH16Kind0 + k - 10;
       ctx->kind_ms[dst] += P->sub->kind_ms[src];

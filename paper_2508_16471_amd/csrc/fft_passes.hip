@@ -640,6 +640,213 @@ __global__ __launch_bounds__(NTB) void k_fft_y_h2(const cpx<h2>* __restrict__ in
   }
 }
 
+// Fused x and y passes of the packed path: one workgroup per (right-hand
+// side, component, z) plane keeps the plane's x-transformed lines in LDS as
+// packed pairs (N2 rows of P1 / 2 pairs), so the x-y scratch never goes to
+// HBM.  Forward: the plane's x lines are scattered from the compressed
+// bfloat16 vector and transformed in FP32 (L1 lines at a time), converted
+// into the plane (scale h1), then the column pairs are transformed along y in
+// packed FP16 (W2 at a time, scale h2) and written to the y/z scratch.
+// Inverse: the reverse, ending in the compressed product epilogue
+// y = x - chi (conv / (h1 h2 h3 gs)).  The x and y phases share one LDS
+// buffer for their transform lines.
+template <int P1, int P2>
+struct XYShape {
+  static constexpr int NT = 256;
+  static constexpr int E1 = fft_e<P1>(), TT1 = P1 / E1, L1 = NT / TT1;
+  static constexpr int E2 = fft_e<P2>(), TT2 = P2 / E2, W2 = NT / TT2;
+  static constexpr int PS = P1 / 2;               // packed pairs per plane row
+  static constexpr int PLANE = (P2 / 2) * PS;     // rows N2 <= P2 / 2
+  static constexpr int XB = L1 * Pad<P1>::LSTR * (int)sizeof(c32);
+  static constexpr int YB = W2 * Pad<P2>::LSTR * (int)sizeof(cpx<h2>);
+  static constexpr int UB = XB > YB ? XB : YB;
+  static_assert(NT % TT1 == 0 && NT % TT2 == 0 && TT1 % 2 == 0, "fused x-y shape");
+};
+
+template <int P1, int P2>
+__global__ __launch_bounds__(256) void k_fft_xy_fwd_h2(
+    const cb16* __restrict__ xc, cpx<h2>* __restrict__ B, const c32* __restrict__ tw1,
+    const cpx<h2>* __restrict__ tw2, BodyIdx bi, int N1, int N2, int N3, SideAddr sb, int zl,
+    float hs1, float hs2, const int* __restrict__ active) {
+  using S = XYShape<P1, P2>;
+  __shared__ cpx<h2> plane[S::PLANE];
+  __shared__ __align__(16) char ubuf[S::UB];
+  const int nrhs = gridDim.x / (3 * N3);
+  const int rhs = blockIdx.x % nrhs, cz = blockIdx.x / nrhs;
+  if (active && !active[rhs]) return;
+  const int comp = cz / N3, z = cz % N3;
+  const int body = bi.rhs_body[rhs];
+  const int nb = bi.nb[body];
+  const int* vox = bi.vox + bi.voff[body];
+  const int* lp = bi.line_ptr + (int64_t)body * (N2 * N3 + 1);
+  const cb16* xv = xc + bi.roff[rhs] + (int64_t)comp * nb;
+  {  // x: FP32 lines into the plane
+    constexpr int E = S::E1, TT = S::TT1;
+    const int li = threadIdx.x / TT, t = threadIdx.x % TT, odd = t & 1;
+    cpx<float>* myl = reinterpret_cast<cpx<float>*>(ubuf) + li * Pad<P1>::LSTR;
+    TwReg<float, P1, E> tr;
+    tr.load(t, tw1);
+    for (int y0 = 0; y0 < N2; y0 += S::L1) {
+      const int y = y0 + li;
+      const bool valid = y < N2;
+      lds_barrier();  // the previous lines' last transform stage has read the buffer
+#pragma unroll
+      for (int q = 0; q < E / 2; ++q) myl[pidx(t + q * TT)] = mk<float>(0, 0);
+      lds_barrier();
+      if (valid) {
+        // at most P1 / 2 voxels a line: all loads issued before the writes
+        const int zy = z * N2 + y;
+        const int k0 = lp[zy] + t, k1 = lp[zy + 1], base = zy * N1;
+        int kv[E / 2];
+        cb16 xr[E / 2];
+#pragma unroll
+        for (int i = 0; i < E / 2; ++i) {
+          const int k = k0 + i * TT;
+          if (k < k1) {
+            kv[i] = vox[k];
+            xr[i] = xv[k];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < E / 2; ++i)
+          if (k0 + i * TT < k1) myl[pidx(kv[i] - base)] = cvt<float>(xr[i]);
+      }
+      lds_barrier();
+      cpx<float> v[E];
+#pragma unroll
+      for (int q = 0; q < E; ++q) v[q] = (q < E / 2) ? myl[pidx(t + q * TT)] : mk<float>(0, 0);
+      line_fft<float, P1, false, true>(v, myl, t, tr);
+      // lanes t, t + 1 hold neighbouring points: one exchange packs a pair
+#pragma unroll
+      for (int q = 0; q < E; q += 2) {
+        const float4 f = pair_out(odd, v[q], v[q + 1]);
+        if (valid)
+          plane[y * S::PS + ((t - odd + (q + odd) * TT) >> 1)] =
+              pack2(f.x * hs1, f.y * hs1, f.z * hs1, f.w * hs1);
+      }
+    }
+  }
+  lds_barrier();  // the plane is complete and the line buffer free
+  {  // y: packed column pairs from the plane to the y/z scratch
+    constexpr int E = S::E2, TT = S::TT2;
+    const int cw = threadIdx.x % S::W2, t = threadIdx.x / S::W2;
+    cpx<h2>* myl = reinterpret_cast<cpx<h2>*>(ubuf) + cw * Pad<P2>::LSTR;
+    TwReg<h2, P2, E> tr;
+    tr.load(t, tw2);
+    const h2 sc = {(_Float16)hs2, (_Float16)hs2};
+    cpx<h2>* po = B + slab_base(sb, rhs, comp, z, zl);
+    for (int p0 = 0; p0 < S::PS; p0 += S::W2) {
+      const int p = p0 + cw;
+      const bool valid = p < S::PS;
+      cpx<h2> v[E];
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int row = t + q * TT;
+        v[q] = (q < E / 2 && valid && row < N2) ? hscale(plane[row * S::PS + p], sc)
+                                               : mk<h2>(h2{0, 0}, h2{0, 0});
+      }
+      line_fft<h2, P2, false, true>(v, myl, t, tr);
+      if (valid) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) po[(int64_t)(t + q * TT) * sb.row + p] = v[q];
+      }
+    }
+  }
+}
+
+template <int P1, int P2>
+__global__ __launch_bounds__(256) void k_fft_yx_inv_h2(
+    const cpx<h2>* __restrict__ B, const cb16* __restrict__ xin, c32* __restrict__ yout,
+    const c32* __restrict__ tw1, const cpx<h2>* __restrict__ tw2, BodyIdx bi, int N1, int N2,
+    int N3, SideAddr sb, int zl, float hs, const int* __restrict__ active) {
+  using S = XYShape<P1, P2>;
+  __shared__ cpx<h2> plane[S::PLANE];
+  __shared__ __align__(16) char ubuf[S::UB];
+  const int nrhs = gridDim.x / (3 * N3);
+  const int rhs = blockIdx.x % nrhs, cz = blockIdx.x / nrhs;
+  if (active && !active[rhs]) return;
+  const int comp = cz / N3, z = cz % N3;
+  {  // inverse y: packed column pairs from the y/z scratch into the plane (rows < N2)
+    constexpr int E = S::E2, TT = S::TT2;
+    const int cw = threadIdx.x % S::W2, t = threadIdx.x / S::W2;
+    cpx<h2>* myl = reinterpret_cast<cpx<h2>*>(ubuf) + cw * Pad<P2>::LSTR;
+    TwReg<h2, P2, E> tr;
+    tr.load(t, tw2);
+    const cpx<h2>* pin = B + slab_base(sb, rhs, comp, z, zl);
+    for (int p0 = 0; p0 < S::PS; p0 += S::W2) {
+      const int p = p0 + cw;
+      const bool valid = p < S::PS;
+      cpx<h2> v[E];
+#pragma unroll
+      for (int q = 0; q < E; ++q)
+        v[q] = valid ? pin[(int64_t)(t + q * TT) * sb.row + p] : mk<h2>(h2{0, 0}, h2{0, 0});
+      line_fft<h2, P2, true, false, true>(v, myl, t, tr);
+      if (valid) {
+#pragma unroll
+        for (int q = 0; q < E / 2; ++q) {
+          const int row = t + q * TT;
+          if (row < N2) plane[row * S::PS + p] = v[q];
+        }
+      }
+    }
+  }
+  lds_barrier();  // the plane is complete and the line buffer free
+  {  // inverse x in FP32 and the compressed epilogue, L1 lines at a time
+    constexpr int E = S::E1, TT = S::TT1;
+    const int li = threadIdx.x / TT, t = threadIdx.x % TT, odd = t & 1;
+    cpx<float>* myl = reinterpret_cast<cpx<float>*>(ubuf) + li * Pad<P1>::LSTR;
+    TwReg<float, P1, E> tr;
+    tr.load(t, tw1);
+    const int body = bi.rhs_body[rhs];
+    const int nb = bi.nb[body];
+    const int* vox = bi.vox + bi.voff[body];
+    const double* chic = bi.chic + bi.voff[body];
+    const int* lp = bi.line_ptr + (int64_t)body * (N2 * N3 + 1);
+    const int64_t vb = bi.roff[rhs] + (int64_t)comp * nb;
+    for (int y0 = 0; y0 < N2; y0 += S::L1) {
+      const int y = y0 + li;
+      const bool valid = y < N2;
+      cpx<float> v[E];
+#pragma unroll
+      for (int q = 0; q < E; q += 2) {
+        float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (valid) f = unpack2(plane[y * S::PS + ((t - odd + (q + odd) * TT) >> 1)]);
+        pair_in(f, odd, v[q], v[q + 1]);
+      }
+      line_fft<float, P1, true, false, true>(v, myl, t, tr);  // only x < N1 is used
+      lds_barrier();  // every thread has left the transform's last LDS read
+#pragma unroll
+      for (int q = 0; q < E / 2; ++q) myl[pidx(t + q * TT)] = v[q];
+      lds_barrier();
+      if (valid) {
+        // at most P1 / 2 voxels a line: all loads issued before the first use
+        const int zy = z * N2 + y;
+        const int k0 = lp[zy] + t, k1 = lp[zy + 1], base = zy * N1;
+        int kv[E / 2];
+        double cv[E / 2];
+        cb16 xr[E / 2];
+#pragma unroll
+        for (int i = 0; i < E / 2; ++i) {
+          const int k = k0 + i * TT;
+          if (k < k1) {
+            kv[i] = vox[k];
+            cv[i] = chic[k];
+            xr[i] = xin[vb + k];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < E / 2; ++i) {
+          const int k = k0 + i * TT;
+          if (k >= k1) continue;
+          const c64 conv = (double)hs * cvt<double>(myl[pidx(kv[i] - base)]);
+          const c64 r = cvt<double>(xr[i]) - cv[i] * conv;
+          yout[vb + k] = cvt<float>(r);
+        }
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ void load_g6h(const cpx<h2>* __restrict__ r, cpx<h2> (&g)[6]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) g[k] = r[k];
@@ -830,6 +1037,52 @@ static hipError_t y_pass_h2(const GroupGeom& g, const cpx<h2>* in, cpx<h2>* out,
   return hipGetLastError();
 }
 
+// The fused x-y passes take FFT lengths 64, 96 and 128 along x and y (the
+// plane and one set of transform lines fit a quarter of the LDS).
+static bool xy_len_ok(int p) { return p == 64 || p == 96 || p == 128; }
+bool xy_fused_ok(const GroupGeom& g) { return xy_len_ok(g.P[0]) && xy_len_ok(g.P[1]); }
+
+#define VIE_DISPATCH_XY(P_, CALL)                    \
+  switch (P_) {                                      \
+    case 64: { constexpr int PP = 64; CALL; break; } \
+    case 96: { constexpr int PP = 96; CALL; break; } \
+    case 128: { constexpr int PP = 128; CALL; break; } \
+    default: return hipErrorInvalidValue;            \
+  }
+
+static hipError_t xy_fwd_h2(const GroupGeom& g, const void* xc, cpx<h2>* B, const c32* tw1,
+                            const cpx<h2>* tw2, const BodyIdx& bi, float hs1, float hs2,
+                            const int* active, hipStream_t s) {
+  if (!xy_fused_ok(g)) return hipErrorInvalidValue;
+  const int zl = z_block(g);
+  const SideAddr sb = halved(side_B(g, zl));
+  const dim3 grid(g.nrhs * 3 * g.N[2]);
+  VIE_DISPATCH_XY(g.P[0], ({
+                    constexpr int Q1 = PP;
+                    VIE_DISPATCH_XY(g.P[1], (k_fft_xy_fwd_h2<Q1, PP><<<grid, 256, 0, s>>>(
+                                                (const cb16*)xc, B, tw1, tw2, bi, g.N[0], g.N[1],
+                                                g.N[2], sb, zl, hs1, hs2, active)));
+                  }));
+  return hipGetLastError();
+}
+
+static hipError_t yx_inv_h2(const GroupGeom& g, const cpx<h2>* B, const void* x, void* y,
+                            const c32* tw1, const cpx<h2>* tw2, const BodyIdx& bi, float hs,
+                            const int* active, hipStream_t s) {
+  if (!xy_fused_ok(g)) return hipErrorInvalidValue;
+  const int zl = z_block(g);
+  const SideAddr sb = halved(side_B(g, zl));
+  const dim3 grid(g.nrhs * 3 * g.N[2]);
+  VIE_DISPATCH_XY(g.P[0], ({
+                    constexpr int Q1 = PP;
+                    VIE_DISPATCH_XY(g.P[1], (k_fft_yx_inv_h2<Q1, PP><<<grid, 256, 0, s>>>(
+                                                B, (const cb16*)x, (c32*)y, tw1, tw2, bi, g.N[0],
+                                                g.N[1], g.N[2], sb, zl, hs, active)));
+                  }));
+  return hipGetLastError();
+}
+#undef VIE_DISPATCH_XY
+
 static hipError_t z_pass_h2(const GroupGeom& g, cpx<h2>* B, const cpx<h2>* spec,
                             const cpx<h2>* tw, float hs, const int* active, hipStream_t s) {
   if (!h16_ok(g)) return hipErrorInvalidValue;
@@ -1002,6 +1255,12 @@ static hipError_t matvec_t(const MatvecArgs& m, const void* xv, void* yv, EpiArg
       const cpx<h2>* twy = (const cpx<h2>*)m.tw16[0];
       const cpx<h2>* twz = (const cpx<h2>*)m.tw16[1];
       base = kH16Kind0;
+      if (xy_fused_ok(g)) {  // x and y fused per plane: no x-y scratch traffic
+        STEP(5, xy_fwd_h2(g, xv, Bh, (const c32*)tw0, twy, *m.bi, m.hs[0], m.hs[1], m.active, s));
+        STEP(2, z_pass_h2(g, Bh, (const cpx<h2>*)m.spec16, twz, m.hs[2], m.active, s));
+        STEP(6, yx_inv_h2(g, Bh, xv, yv, (const c32*)tw0, twy, *m.bi, m.hout, m.active, s));
+        return hipSuccess;
+      }
       STEP(0, x_fwd_c<T>(g, xv, m.io32, A, tw0, *m.bi, m.active, s, m.hs[0]));
       STEP(1, y_pass_h2(g, Ah, Bh, twy, false, m.hs[1], m.active, s));
       STEP(2, z_pass_h2(g, Bh, (const cpx<h2>*)m.spec16, twz, m.hs[2], m.active, s));

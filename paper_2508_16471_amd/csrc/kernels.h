@@ -109,7 +109,10 @@ hipError_t launch_z_only(const MatvecArgs& a, int precision, hipStream_t s);
 // caller), the pair-packed FP16 copy scaled by gs (Q2 Q3 P1/2 6 packed
 // pairs, 8 bytes each), the splatted FP16 twiddles of n points.
 bool h16_ok(const GroupGeom& g);
-static constexpr int kH16Kind0 = 26;  // timing kinds of their five passes (26..30)
+// timing kinds of their passes: the five separate ones (26..30), then the
+// fused x-y forward and inverse passes (31, 32) of grids xy_fused_ok takes
+static constexpr int kH16Kind0 = 26;
+bool xy_fused_ok(const GroupGeom& g);
 hipError_t launch_spec_absmax(const void* spec32, int64_t n, unsigned* dmax, hipStream_t s);
 hipError_t launch_spec_pairs(const void* spec32, void* spec16, const GroupGeom& g, float gs,
                              hipStream_t s);

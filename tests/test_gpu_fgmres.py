@@ -263,10 +263,10 @@ def test_fgmres_empty_body_and_silent_body(V):
         V.vie_destroy(ctx)
 
 
-# block boxes 60 x 60 x 29 (FFT 128 x 128 x 64) and 32 x 24 x 40 (FFT 64 x 48 x 96:
-# 3 * 2^k lines in y and z)
-@pytest.mark.parametrize("n", [(120, 120, 29), (64, 48, 40)])
-def test_packed_fp16_block_products(V, n):
+# block boxes 60 x 60 x 29 (FFT 128 x 128 x 64: fused x-y passes) and
+# 32 x 24 x 40 (FFT 64 x 48 x 96: 3 * 2^k lines in y and z, separate passes)
+@pytest.mark.parametrize("n,fused", [((120, 120, 29), True), ((64, 48, 40), False)])
+def test_packed_fp16_block_products(V, n, fused):
     rng = np.random.default_rng(41)
     h = 0.03
     g = Grid.centred(n, h)
@@ -285,11 +285,13 @@ def test_packed_fp16_block_products(V, n):
         finally:
             V.vie_destroy(ctx)
         passes = ("x_fwd", "y_fwd", "z", "y_inv", "x_inv")
-        n16 = [t["block_fft_%s_h16" % k][1] for k in passes]
+        n16 = {k: t["block_fft_%s_h16" % k][1] for k in passes + ("xy_fwd", "yx_inv")}
         n32 = [t["block_fft_%s_f32" % ("z_green" if k == "z" else k)][1] for k in passes]
         print(inner, "block launches fp32", n32, "packed fp16", n16)
         packed = inner == V.VIE_MIXED_BF16
-        assert all((c > 0) == packed for c in n16) and all((c > 0) != packed for c in n32)
+        want = ({"xy_fwd", "z", "yx_inv"} if fused else set(passes)) if packed else set()
+        assert {k for k, c in n16.items() if c > 0} == want
+        assert all((c > 0) != packed for c in n32)
     e = np.linalg.norm(out[V.VIE_MIXED_BF16] - out[V.VIE_MIXED]) / np.linalg.norm(out[V.VIE_MIXED])
     print("packed-FP16 preconditioner vs FP32", e)
     assert e < 2e-2
