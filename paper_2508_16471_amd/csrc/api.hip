@@ -1363,9 +1363,14 @@ static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, in
   if ((e = launch_seg_mdot(S, V, v32, stride, j + 1, w, w32, A.dpart.as<c64>(), h1, ldh,
                            ctx->stream)) != hipSuccess)
     return e;
+  // one pass with an FP32 work vector: the normalisation reduces the norm
+  const bool defer = eta2 <= 0 && w32;
   if ((e = launch_seg_maxpy(S, V, v32, stride, j + 1, nullptr, h1, ldh, w, w32, npart, nr, m + 1,
-                            ctx->stream)) != hipSuccess)
+                            ctx->stream, defer)) != hipSuccess)
     return e;
+  if (defer)
+    return launch_seg_normalize_sum(S, w, w32, npart, nr, m + 1, A.at(A.V, j + 1, stride), v32,
+                                    ctx->stream);
   if (eta2 > 0) {  // otherwise there is no second pass (and H2 is not read)
     if ((e = launch_seg_reorth_flags(S, A.W2.as<double>(), nr, m + 1, eta2, A.act2.as<int>(),
                                      ctx->stream)) != hipSuccess)

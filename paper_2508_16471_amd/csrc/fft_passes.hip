@@ -655,7 +655,10 @@ struct XYShape {
   static constexpr int NT = 256;
   static constexpr int E1 = fft_e<P1>(), TT1 = P1 / E1, L1 = NT / TT1;
   static constexpr int E2 = fft_e<P2>(), TT2 = P2 / E2, W2 = NT / TT2;
-  static constexpr int PS = P1 / 2;               // packed pairs per plane row
+  // packed pairs per plane row, padded by 8 pairs (16 banks): the x phase's
+  // eight lines per wave then start on four different bank groups
+  static constexpr int PS = P1 / 2 + 8;
+  static constexpr int NP = P1 / 2;               // column pairs
   static constexpr int PLANE = (P2 / 2) * PS;     // rows N2 <= P2 / 2
   static constexpr int XB = L1 * Pad<P1>::LSTR * (int)sizeof(c32);
   static constexpr int YB = W2 * Pad<P2>::LSTR * (int)sizeof(cpx<h2>);
@@ -735,9 +738,9 @@ __global__ __launch_bounds__(256) void k_fft_xy_fwd_h2(
     tr.load(t, tw2);
     const h2 sc = {(_Float16)hs2, (_Float16)hs2};
     cpx<h2>* po = B + slab_base(sb, rhs, comp, z, zl);
-    for (int p0 = 0; p0 < S::PS; p0 += S::W2) {
+    for (int p0 = 0; p0 < S::NP; p0 += S::W2) {
       const int p = p0 + cw;
-      const bool valid = p < S::PS;
+      const bool valid = p < S::NP;
       cpx<h2> v[E];
 #pragma unroll
       for (int q = 0; q < E; ++q) {
@@ -773,9 +776,9 @@ __global__ __launch_bounds__(256) void k_fft_yx_inv_h2(
     TwReg<h2, P2, E> tr;
     tr.load(t, tw2);
     const cpx<h2>* pin = B + slab_base(sb, rhs, comp, z, zl);
-    for (int p0 = 0; p0 < S::PS; p0 += S::W2) {
+    for (int p0 = 0; p0 < S::NP; p0 += S::W2) {
       const int p = p0 + cw;
-      const bool valid = p < S::PS;
+      const bool valid = p < S::NP;
       cpx<h2> v[E];
 #pragma unroll
       for (int q = 0; q < E; ++q)

@@ -41,10 +41,12 @@ hipError_t launch_seg_mdot(const SegSet& S, const void* V, int v32, int64_t stri
 // w[e] -= sum_{i < n_s} coef[s * ldc + i] V_i[e] with n_s = nv, or
 // min(nv, nv_seg[s]) when nv_seg is given (w FP32 when w32, arithmetic FP64).
 // With norm2 != nullptr also norm2[s * ldn] = ||w_s||^2 of the stored result
-// (partials: nseg * nblk doubles).  nv = 0 only measures the norm.
+// (partials: nseg * nblk doubles).  nv = 0 only measures the norm.  defer:
+// only the partials are written (launch_seg_normalize_sum reduces them).
 hipError_t launch_seg_maxpy(const SegSet& S, const void* V, int v32, int64_t stride, int nv,
                             const int* nv_seg, const c64* coef, int ldc, void* w, int w32,
-                            double* partials, double* norm2, int ldn, hipStream_t st);
+                            double* partials, double* norm2, int ldn, hipStream_t st,
+                            bool defer = false);
 
 // act2[s] = 1 where segment s is active and after[s * ldn] < eta2 * before[s]
 // (too much cancellation in a Gram-Schmidt pass: orthogonalise again).
@@ -55,6 +57,12 @@ hipError_t launch_seg_reorth_flags(const SegSet& S, const double* before, const 
 // src is FP32 when s32, dst when d32.
 hipError_t launch_seg_normalize(const SegSet& S, const void* src, int s32, const double* norm2,
                                 int ldn, void* dst, int d32, hipStream_t st);
+// The same after a deferred multi-axpy: norm2[s * ldn] is reduced from its
+// partials npart first (same result as the non-deferred sum) and stored; FP32
+// src only.
+hipError_t launch_seg_normalize_sum(const SegSet& S, const void* src, int s32,
+                                    const double* npart, double* norm2, int ldn, void* dst,
+                                    int d32, hipStream_t st);
 
 // x[e] = -sum_{i < n_s} coef[s * ldc + i] V_i[e] over every active segment
 // (n_s = min(nv, nv_seg[s]); x = 0 where n_s = 0).

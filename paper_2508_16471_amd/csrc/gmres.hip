@@ -172,15 +172,28 @@ __global__ void k_seg_reorth_flags(SegSet S, const double* __restrict__ before,
   act2[s] = (on && eta2 > 0.0 && after[(int64_t)s * ldn] < eta2 * before[s]) ? 1 : 0;
 }
 
-template <typename TS, typename TD>
+// SUM: norm2 is first reduced here from the norm partials of the multi-axpy
+// (every wave in the order of k_seg_sum_r, so the result is the same bits),
+// and workgroup 0 stores it at norm2[s * ldn].
+template <typename TS, typename TD, bool SUM = false>
 __global__ __launch_bounds__(GT) void k_seg_normalize(SegSet S, const TS* __restrict__ src,
-                                                      const double* __restrict__ norm2, int ldn,
-                                                      TD* __restrict__ dst) {
+                                                      double* __restrict__ norm2, int ldn,
+                                                      TD* __restrict__ dst,
+                                                      const double* __restrict__ npart) {
   const int s = blockIdx.y, blk = blockIdx.x;
   if (S.active && !S.active[s]) return;
   const int64_t off = S.off[s];
   const int len = S.len[s];
-  const double n2 = norm2[(int64_t)s * ldn];
+  double n2;
+  if constexpr (SUM) {
+    double t = 0.0;
+    for (int k = threadIdx.x & 63; k < S.nblk; k += 64) t += npart[(int64_t)s * S.nblk + k];
+    for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m);
+    n2 = t;
+    if (blk == 0 && threadIdx.x == 0) norm2[(int64_t)s * ldn] = t;
+  } else {
+    n2 = norm2[(int64_t)s * ldn];
+  }
   const double sc = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
   for (int e = blk * GT + threadIdx.x; e < len; e += S.nblk * GT)
     st(dst + off + e, sc * ld64(src + off + e));
@@ -409,10 +422,11 @@ hipError_t launch_seg_mdot(const SegSet& S, const void* V, int v32, int64_t stri
 
 hipError_t launch_seg_maxpy(const SegSet& S, const void* V, int v32, int64_t stride, int nv,
                             const int* nv_seg, const c64* coef, int ldc, void* w, int w32,
-                            double* partials, double* norm2, int ldn, hipStream_t st) {
+                            double* partials, double* norm2, int ldn, hipStream_t st,
+                            bool defer) {
   if (S.nseg < 1) return hipSuccess;
   if (nv < 0 || nv > kMaxVec) return hipErrorInvalidValue;
-  double* pn = norm2 ? partials : nullptr;
+  double* pn = (norm2 || defer) ? partials : nullptr;
   const dim3 grid(S.nblk, S.nseg);
   if (v32 == 2 && w32)
     k_seg_maxpy<<<grid, GT, 0, st>>>(S, (const cb16*)V, stride, nv, nv_seg, coef, ldc, (c32*)w, pn);
@@ -426,7 +440,7 @@ hipError_t launch_seg_maxpy(const SegSet& S, const void* V, int v32, int64_t str
     k_seg_maxpy<<<grid, GT, 0, st>>>(S, (const c64*)V, stride, nv, nv_seg, coef, ldc, (c32*)w, pn);
   else
     k_seg_maxpy<<<grid, GT, 0, st>>>(S, (const c64*)V, stride, nv, nv_seg, coef, ldc, (c64*)w, pn);
-  if (norm2) k_seg_sum_r<<<S.nseg, 64, 0, st>>>(S, partials, norm2, ldn);
+  if (norm2 && !defer) k_seg_sum_r<<<S.nseg, 64, 0, st>>>(S, partials, norm2, ldn);
   return hipGetLastError();
 }
 
@@ -441,18 +455,36 @@ hipError_t launch_seg_normalize(const SegSet& S, const void* src, int s32, const
                                 int ldn, void* dst, int d32, hipStream_t st) {
   if (S.nseg < 1) return hipSuccess;
   const dim3 grid(S.nblk, S.nseg);
+  double* n2 = const_cast<double*>(norm2);  // read only without SUM
   if (d32 == 2 && s32)
-    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c32*)src, norm2, ldn, (cb16*)dst);
+    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c32*)src, n2, ldn, (cb16*)dst, nullptr);
   else if (d32 == 2)
-    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c64*)src, norm2, ldn, (cb16*)dst);
+    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c64*)src, n2, ldn, (cb16*)dst, nullptr);
   else if (s32 && d32)
-    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c32*)src, norm2, ldn, (c32*)dst);
+    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c32*)src, n2, ldn, (c32*)dst, nullptr);
   else if (s32)
-    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c32*)src, norm2, ldn, (c64*)dst);
+    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c32*)src, n2, ldn, (c64*)dst, nullptr);
   else if (d32)
-    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c64*)src, norm2, ldn, (c32*)dst);
+    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c64*)src, n2, ldn, (c32*)dst, nullptr);
   else
-    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c64*)src, norm2, ldn, (c64*)dst);
+    k_seg_normalize<<<grid, GT, 0, st>>>(S, (const c64*)src, n2, ldn, (c64*)dst, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_normalize_sum(const SegSet& S, const void* src, int s32,
+                                    const double* npart, double* norm2, int ldn, void* dst,
+                                    int d32, hipStream_t st) {
+  if (S.nseg < 1) return hipSuccess;
+  if (!s32) return hipErrorInvalidValue;  // FP32 work vectors only
+  const dim3 grid(S.nblk, S.nseg);
+  if (d32 == 2)
+    k_seg_normalize<c32, cb16, true>
+        <<<grid, GT, 0, st>>>(S, (const c32*)src, norm2, ldn, (cb16*)dst, npart);
+  else if (d32)
+    k_seg_normalize<c32, c32, true>
+        <<<grid, GT, 0, st>>>(S, (const c32*)src, norm2, ldn, (c32*)dst, npart);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
