@@ -11,6 +11,16 @@ template <int P>
 struct Pad {
   static constexpr int LSTR = P + P / 16 + 1;  // padded LDS line stride (bank spread)
 };
+// Line stride of the x passes, where the TT threads of one line are
+// neighbouring lanes and each stage touches TT consecutive points of a line:
+// a stride of TT (mod 16) points puts neighbouring lines' windows side by
+// side in the banks (the odd stride of Pad suits the column passes, whose
+// neighbouring lanes are different lines).
+template <int P, int TT>
+struct PadX {
+  static constexpr int base() { return P + P / 16; }
+  static constexpr int LSTR = base() + ((TT % 16) - base() % 16 + 16) % 16;
+};
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 
 // fft_stages with padded LDS indexing: wrap the line pointer in an accessor.

@@ -660,7 +660,8 @@ struct XYShape {
   static constexpr int PS = P1 / 2 + 8;
   static constexpr int NP = P1 / 2;               // column pairs
   static constexpr int PLANE = (P2 / 2) * PS;     // rows N2 <= P2 / 2
-  static constexpr int XB = L1 * Pad<P1>::LSTR * (int)sizeof(c32);
+  static constexpr int XLS = PadX<P1, TT1>::LSTR;  // x-line stride
+  static constexpr int XB = L1 * XLS * (int)sizeof(c32);
   static constexpr int YB = W2 * Pad<P2>::LSTR * (int)sizeof(cpx<h2>);
   static constexpr int UB = XB > YB ? XB : YB;
   static_assert(NT % TT1 == 0 && NT % TT2 == 0 && TT1 % 2 == 0, "fused x-y shape");
@@ -686,7 +687,7 @@ __global__ __launch_bounds__(256) void k_fft_xy_fwd_h2(
   {  // x: FP32 lines into the plane
     constexpr int E = S::E1, TT = S::TT1;
     const int li = threadIdx.x / TT, t = threadIdx.x % TT, odd = t & 1;
-    cpx<float>* myl = reinterpret_cast<cpx<float>*>(ubuf) + li * Pad<P1>::LSTR;
+    cpx<float>* myl = reinterpret_cast<cpx<float>*>(ubuf) + li * S::XLS;
     TwReg<float, P1, E> tr;
     tr.load(t, tw1);
     for (int y0 = 0; y0 < N2; y0 += S::L1) {
@@ -797,7 +798,7 @@ __global__ __launch_bounds__(256) void k_fft_yx_inv_h2(
   {  // inverse x in FP32 and the compressed epilogue, L1 lines at a time
     constexpr int E = S::E1, TT = S::TT1;
     const int li = threadIdx.x / TT, t = threadIdx.x % TT, odd = t & 1;
-    cpx<float>* myl = reinterpret_cast<cpx<float>*>(ubuf) + li * Pad<P1>::LSTR;
+    cpx<float>* myl = reinterpret_cast<cpx<float>*>(ubuf) + li * S::XLS;
     TwReg<float, P1, E> tr;
     tr.load(t, tw1);
     const int body = bi.rhs_body[rhs];

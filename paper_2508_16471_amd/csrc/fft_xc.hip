@@ -24,7 +24,7 @@ __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_fwd_c(
     BodyIdx bi, int N1, int N2, int N3, int blocks_per_rhs, const int* __restrict__ active,
     float hs) {
   constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines_p<T>(P), L = NT / TT,
-                LS = Pad<P>::LSTR;
+                LS = PadX<P, P / fft_e<P>()>::LSTR;
   __shared__ cpx<T> lds[L * LS];
   // Hardware order (consecutive blocks go to consecutive XCDs): the lines of
   // one right-hand side spread over every XCD, so inactive right-hand sides
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(nt_lines_p<T>(P)) void k_fft_x_inv_c(
     c64* __restrict__ aux, c64* __restrict__ partials, const c64* __restrict__ pol,
     const c64* __restrict__ ph, const int* __restrict__ active, float hs) {
   constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines_p<T>(P), L = NT / TT,
-                LS = Pad<P>::LSTR;
+                LS = PadX<P, P / fft_e<P>()>::LSTR;
   __shared__ cpx<T> lds[L * LS];
   __shared__ double red[4 * (NT / 64 + 1)];
   // Hardware order (consecutive blocks go to consecutive XCDs): the lines of
