@@ -70,9 +70,9 @@ def parse():
     ap.add_argument("--directions", type=int, default=64,
                     help="metasurface mode: incident directions of the 64-point (u, v) grid (x 2 circular polarisations)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32")
-    ap.add_argument("--solver", choices=["fgmres", "bicgstab"], default="fgmres",
+    ap.add_argument("--solver", choices=["fgmres", "bicgstab"], default=None,
                     help="fast leg: block-Jacobi FGMRES (vie_solve_fgmres) or BiCGSTAB with FP64 "
-                         "refinement (vie_solve)")
+                         "refinement (vie_solve); default FGMRES, BiCGSTAB in --mode uneven")
     ap.add_argument("--restart", type=int, default=60, help="FGMRES steps per cycle")
     ap.add_argument("--blocks", default="2,2", help="FGMRES lateral block partition bx,by")
     ap.add_argument("--inner-iters", type=int, default=8, help="GMRES steps per block solve")
@@ -699,8 +699,11 @@ def uneven_mode(args):
     4 channels each (k uniform on the sphere, random linear polarisation).
     Bodies sharing a grid form one batched group; groups are solved in grid
     order, one call each, and a solve's latency is the time from the first
-    call's start to the end of its group's call.  Run with replayed graphs
-    and, for comparison, with eager launches."""
+    call's start to its own completion (its group call's start plus the
+    device-measured completion time `seconds` the library reports), beside
+    the end of its group's call.  Solver as --solver (FGMRES:
+    --blocks, --inner-iters, --restart, --block-basis).  Run with replayed
+    graphs and, for comparison, with eager launches."""
     import torch
 
     from paper_2508_16471_amd import vie as V
@@ -723,7 +726,21 @@ def uneven_mode(args):
             p = np.cross(k, rng.standard_normal(3))
             chans.append((k, p / np.linalg.norm(p)))
     out = {"mode": "uneven", "bodies": nb, "channels_per_body": nch,
-           "grids": {str(n): grid_of.count(n) for n in sizes}, "tol": args.tol}
+           "grids": {str(n): grid_of.count(n) for n in sizes}, "tol": args.tol,
+           "solver": args.solver or "bicgstab"}
+    fo = None
+    if args.solver == "fgmres":
+        fo = V.fgmres_options(args.restart, tuple(int(v) for v in args.blocks.split(",")),
+                              args.inner_iters,
+                              V.VIE_MIXED_BF16 if args.block_basis == "bf16" else V.VIE_MIXED)
+        out["fgmres"] = {"restart": args.restart, "blocks": args.blocks,
+                         "inner_iters": args.inner_iters, "block_basis": args.block_basis}
+
+    def solve(ctx, ch, cnt):
+        if fo is not None:
+            return V.vie_solve_fgmres(ctx, ch, cnt, fo)
+        return V.vie_solve(ctx, ch, cnt)
+
     for label, flags in (("graph", 0), ("eager", V.VIE_FLAG_NO_GRAPH)):
         opt = V.make_options(K0, precision=V.VIE_MIXED, tol=args.tol, max_iter=20000,
                              inner_tol=args.inner_tol, flags=flags)
@@ -734,32 +751,36 @@ def uneven_mode(args):
             for n in sizes:  # warm-up: tuning and graph capture per group
                 cnt = [nch if grid_of[b] == n else 0 for b in range(nb)]
                 if sum(cnt):
-                    V.vie_solve(ctx, [c for b, c in enumerate(chans) if cnt[b // nch]], cnt)
+                    solve(ctx, [c for b, c in enumerate(chans) if cnt[b // nch]], cnt)
                     print(f"uneven {label} warm-up grid {n} done", file=sys.stderr, flush=True)
             torch.cuda.synchronize()
-            lat, groups, iters = [], {}, []
+            lat, lat_end, groups, iters = [], [], {}, []
             t0 = time.perf_counter()
             for n in sizes:
                 cnt = [nch if grid_of[b] == n else 0 for b in range(nb)]
                 if not sum(cnt):
                     continue
                 tg = time.perf_counter()
-                _, st = V.vie_solve(ctx, [c for b, c in enumerate(chans) if cnt[b // nch]], cnt)
+                _, st = solve(ctx, [c for b, c in enumerate(chans) if cnt[b // nch]], cnt)
                 now = time.perf_counter()
                 groups[str(n)] = {"rhs": sum(cnt), "seconds": now - tg,
                                   "iters_mean": float(np.mean([x["iters"] for x in st])),
                                   "converged": all(x["converged"] for x in st)}
-                lat += [now - t0] * len(st)
+                lat += [tg - t0 + x["seconds"] for x in st]
+                lat_end += [now - t0] * len(st)
                 iters += [x["iters"] for x in st]
                 print(f"uneven {label} grid {n}: {groups[str(n)]}", file=sys.stderr, flush=True)
             total = time.perf_counter() - t0
         finally:
             V.vie_destroy(ctx)
-        lat = np.array(lat)
+        lat, lat_end = np.array(lat), np.array(lat_end)
         out[label] = {"solves_per_s": len(lat) / total, "seconds": total, "setup_s": setup,
                       "latency_s": {"p50": float(np.percentile(lat, 50)),
                                     "p90": float(np.percentile(lat, 90)),
                                     "p99": float(np.percentile(lat, 99))},
+                      "group_end_s": {"p50": float(np.percentile(lat_end, 50)),
+                                      "p90": float(np.percentile(lat_end, 90)),
+                                      "p99": float(np.percentile(lat_end, 99))},
                       "iters_mean": float(np.mean(iters)), "groups": groups}
         print(json.dumps({label: out[label]}), file=sys.stderr, flush=True)
     # launch-bound case: one 16^3 sphere (r = lambda/2, eps 2.25), one channel
@@ -1189,7 +1210,7 @@ def main():
     N, P, _ = V.vie_grid(ctx, 0)  # the z window of the group (all bodies share it)
     Q = tuple(p // 2 + 1 for p in P)
 
-    use_fgmres = args.solver == "fgmres"
+    use_fgmres = args.solver in (None, "fgmres")
     blocks = tuple(int(v) for v in args.blocks.split(","))
     inner_prec = V.VIE_MIXED_BF16 if args.block_basis == "bf16" else V.VIE_MIXED
     fo = V.fgmres_options(args.restart, blocks, args.inner_iters, inner_prec)

@@ -135,6 +135,10 @@ typedef struct {
   int32_t warm;       /* 1 if the warm start was used                           */
   double rel_res;     /* final true ||b - A w|| / ||b|| (FP64 operator)         */
   double rel_res_x0;  /* true relative residual of the initial guess            */
+  double seconds;     /* completion time: device wall-clock seconds from the   */
+                      /* start of this call's device work to the FP64 residual */
+                      /* check that first found rel_res <= tol (groups solved  */
+                      /* earlier in the call included); 0 if not converged     */
 } vie_stats;
 
 /* Set up a context for n_bodies bodies: copies eps_r (chi = eps_r - 1) to
@@ -149,9 +153,12 @@ int vie_setup(const vie_body *bodies, int32_t n_bodies, const vie_options *opt,
 
 /* Solve eq. 24 (discretised as above) for every right-hand side: body b gets
  * nrhs_per_body[b] channels taken in order from inc[].  All right-hand sides
- * of all bodies are advanced together (batched kernels); stats (caller array,
- * one entry per right-hand side, may be NULL) report iterations and the final
- * FP64 true residual.  Solutions stay on the device (vie_get_current,
+ * of all bodies are advanced together (batched kernels); each one restarts
+ * (FP64 true residual, then a new refinement cycle) as soon as its own cycle
+ * ends, while the others keep iterating, and stops costing work once
+ * converged.  stats (caller array, one entry per right-hand side, may be
+ * NULL) report iterations, the final FP64 true residual and the completion
+ * time.  Solutions stay on the device (vie_get_current,
  * vie_farfield).  Returns VIE_ENOCONV if any right-hand side missed tol
  * (stats and the best iterate are still filled in). */
 int vie_solve(vie_ctx *ctx, const vie_planewave *inc, const int32_t *nrhs_per_body,

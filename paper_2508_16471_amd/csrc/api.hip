@@ -259,6 +259,9 @@ struct vie_ctx {
   // flexible GMRES and its block-Jacobi preconditioner (built on first use)
   std::unique_ptr<ArnoldiBufs> fgm;
   std::vector<std::unique_ptr<BlockPrec>> bj;  // [group]
+  // device wall clock: its rate, and the stamp taken at the start of a solve call
+  double clock_khz = 0;
+  DevBuf t_call;
 };
 
 // ------------------------------------------------ allocation-free scratch
@@ -451,9 +454,17 @@ extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_opt
       return bail(VIE_EDEVICE);
     }
   }
+  {  // device wall clock for the solves' completion times
+    int khz = 0;
+    if ((he = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->dev)) != hipSuccess)
+      return hip_fail(he, "hipDeviceGetAttribute");
+    ctx->clock_khz = khz;
+    if ((he = ctx->t_call.reserve(sizeof(unsigned long long))) != hipSuccess)
+      return hip_fail(he, "hipMalloc");
+  }
   // Group bodies by (n, h).  With VIE_FLAG_Z_WINDOW a group computes on a
   // window of its grid in z: the layers that hold body voxels of any of its
-  // bodies plus a 4-layer margin (the network box), clipped to the grid.
+  // bodies, clipped to the grid.
   // Voxels outside the window have chi = 0 in every body, so they neither act
   // on the body nor are acted on: the discrete system for the body's unknowns
   // is the same, on a shorter circulant.  Each body sits in the window at its
@@ -689,7 +700,7 @@ static int ensure_solve_storage(vie_ctx* ctx, Group& G, int nrhs) {
                               vec_blocks_group(G));
   VIE_HIP(G.partials.reserve((size_t)nrhs * maxblk * 2 * sizeof(c64)));
   VIE_HIP(G.state.reserve((size_t)nrhs * sizeof(KState)));
-  VIE_HIP(G.flags.reserve((size_t)2 * nrhs * sizeof(int)));
+  VIE_HIP(G.flags.reserve((size_t)3 * nrhs * sizeof(int)));  // active, not done, pending
   VIE_HIP(G.rhs_body.reserve((size_t)nrhs * sizeof(int)));
   VIE_HIP(G.pol.reserve((size_t)nrhs * 3 * sizeof(c64)));
   VIE_HIP(G.ph.reserve((size_t)nrhs * (G.g.N[0] + G.g.N[1] + G.g.N[2]) * sizeof(c64)));
@@ -986,7 +997,7 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
     int rcw = warm_start_init(ctx, G, fp, fallback_out);
     if (rcw != VIE_OK) return rcw;
   }
-  int rc = ensure_hflags(ctx, nrhs);
+  int rc = ensure_hflags(ctx, 3 * nrhs);
   if (rc != VIE_OK) return rc;
 
   // one BiCGSTAB iteration for every active right-hand side
@@ -1058,70 +1069,82 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
     }
   }
 
-  for (int cycle = 0;; ++cycle) {
-    // iterate until every right-hand side has left the cycle (lagged check)
-    int64_t k = 0;
-    for (;; ++k) {
-      if (use_graph) {
-        VIE_HIP(hipGraphLaunch(G.iter_graph.exec, ctx->stream));
-      } else {
-        VIE_HIP(iteration());
-      }
-      const int slot = (int)(k & 1);
-      VIE_HIP(hipMemcpyAsync(ctx->hflags[slot], active, nrhs * sizeof(int), hipMemcpyDeviceToHost,
-                             ctx->stream));
-      VIE_HIP(hipEventRecord(ctx->flag_ev[slot], ctx->stream));
-      if (k > 0) {
-        const int ps = (int)((k - 1) & 1);
-        VIE_HIP(hipEventSynchronize(ctx->flag_ev[ps]));
-        bool any = false;
-        for (int i = 0; i < nrhs; ++i) any |= ctx->hflags[ps][i] != 0;
-        if (!any) break;
-      }
-      if (k * per_launch > (int64_t)ctx->opt.max_iter + 2) break;
-      if ((k & 63) == 63 && getenv("VIE_LOG")) {
-        KState h0;
-        VIE_HIP(hipMemcpyAsync(&h0, st, sizeof(KState), hipMemcpyDeviceToHost, ctx->stream));
-        VIE_HIP(hipStreamSynchronize(ctx->stream));
-        fprintf(stderr, "vie: cycle %d: %lld iterations launched, rhs 0 recursive rel res %.3e\n",
-                cycle, (long long)((k + 1) * per_launch),
-                h0.bnorm2 > 0 ? sqrt(h0.rnorm2 / h0.bnorm2) : 0.0);
-      }
-    }
-    if (getenv("VIE_LOG")) {
-      std::vector<KState> hs(nrhs);
-      VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
-                             ctx->stream));
-      VIE_HIP(hipStreamSynchronize(ctx->stream));
-      for (int i = 0; i < nrhs; ++i)
-        fprintf(stderr,
-                "vie: cycle %d rhs %d: %d iterations, recursive rel res %.3e, breakdown %d, "
-                "|omega| %.3e\n",
-                cycle, i, hs[i].it_cycle, hs[i].bnorm2 > 0 ? sqrt(hs[i].rnorm2 / hs[i].bnorm2) : 0.0,
-                hs[i].breakdown, std::hypot(hs[i].omega.re, hs[i].omega.im));
-    }
-    // true residual with the FP64 product, restart
+  // Each right-hand side restarts on its own: when its cycle ends (the
+  // recursive residual met the cycle target, or a breakdown) its pending flag
+  // is set on the device, and the next check runs the FP64 true-residual
+  // product and the restart for the pending right-hand sides only, while the
+  // others keep iterating.  The host reads the flags one chunk late (the copy
+  // after chunk k - 1 is read once chunk k is queued).  A restart queued
+  // right after that copy covers every right-hand side pending in it (the
+  // device gates the restart on its own pending flags, which only iterations
+  // set), so a restart is queued only when the flags read are not already
+  // covered by one.
+  int* pending = flags + 2 * nrhs;
+  bool restart_queued = false;  // a restart was queued right after the copy being read
+  bool have_prev = false;       // a flag copy of the previous chunk is in flight
+  int prev = 0;                 // its slot
+  auto queue_restart = [&]() -> hipError_t {
     EpiArgs e{EPI_RESID, rh, part, 0, pol, ph};
-    VIE_HIP(run_matvec(ctx, G, 0, x, r, e, notdone));
-    VIE_HIP(timed(ctx, 11, [&] {
-      return launch_finalize(FIN_RESTART, nrhs, e.part_blocks, part, st, flags, fp, ctx->stream);
-    }));
-    VIE_HIP(hipMemcpyAsync(ctx->hflags[0], active, nrhs * sizeof(int), hipMemcpyDeviceToHost,
-                           ctx->stream));
-    VIE_HIP(hipStreamSynchronize(ctx->stream));
-    if (getenv("VIE_LOG")) {
-      std::vector<KState> hs(nrhs);
-      VIE_HIP(hipMemcpyAsync(hs.data(), st, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
+    hipError_t he = run_matvec(ctx, G, 0, x, r, e, pending);
+    if (he != hipSuccess) return he;
+    return timed(ctx, 11, [&] {
+      return launch_finalize(FIN_PENDING, nrhs, e.part_blocks, part, st, flags, fp, ctx->stream);
+    });
+  };
+  for (int64_t k = 0;; ++k) {
+    if (use_graph) {
+      VIE_HIP(hipGraphLaunch(G.iter_graph.exec, ctx->stream));
+    } else {
+      VIE_HIP(iteration());
+    }
+    const int slot = (int)(k & 1);
+    VIE_HIP(hipMemcpyAsync(ctx->hflags[slot], flags, 3 * nrhs * sizeof(int),
+                           hipMemcpyDeviceToHost, ctx->stream));
+    VIE_HIP(hipEventRecord(ctx->flag_ev[slot], ctx->stream));
+    if (!have_prev) {
+      have_prev = true;
+      prev = slot;
+      continue;
+    }
+    const int* hf = ctx->hflags[prev];
+    VIE_HIP(hipEventSynchronize(ctx->flag_ev[prev]));
+    prev = slot;
+    bool any_active = false, any_pending = false;
+    for (int i = 0; i < nrhs; ++i) {
+      any_active |= hf[i] != 0;
+      any_pending |= hf[2 * nrhs + i] != 0;
+    }
+    if (!any_active) {
+      // nothing iterated in the chunk read (nor in the one queued after it,
+      // unless a restart came between): restart what is pending and read the
+      // flags after it directly, instead of replaying empty chunks meanwhile
+      if (any_pending && !restart_queued) VIE_HIP(queue_restart());
+      int* now = ctx->hflags[slot ^ 1];
+      VIE_HIP(hipMemcpyAsync(now, flags, 3 * nrhs * sizeof(int), hipMemcpyDeviceToHost,
                              ctx->stream));
       VIE_HIP(hipStreamSynchronize(ctx->stream));
-      for (int i = 0; i < nrhs; ++i)
-        fprintf(stderr, "vie: restart %d rhs %d: true rel res %.3e after %d iterations\n", cycle,
-                i, hs[i].bnorm2 > 0 ? sqrt(hs[i].rnorm2 / hs[i].bnorm2) : 0.0, hs[i].iters);
+      bool act = false;
+      for (int i = 0; i < nrhs; ++i) act |= now[i] != 0 || now[2 * nrhs + i] != 0;
+      if (!act) break;  // all done (or out of steps)
+      have_prev = false;  // the copy in flight predates the restart
+      restart_queued = false;
+    } else {
+      const bool need = any_pending && !restart_queued;
+      restart_queued = false;
+      if (need) {
+        VIE_HIP(queue_restart());
+        restart_queued = true;
+      }
     }
-    bool any = false;
-    for (int i = 0; i < nrhs; ++i) any |= ctx->hflags[0][i] != 0;
-    if (!any) break;
-    if (cycle > ctx->opt.max_iter) break;
+    if (k * per_launch > 4 * ((int64_t)ctx->opt.max_iter + 2)) break;
+    if ((k & 63) == 63 && getenv("VIE_LOG")) {
+      KState h0;
+      VIE_HIP(hipMemcpyAsync(&h0, st, sizeof(KState), hipMemcpyDeviceToHost, ctx->stream));
+      VIE_HIP(hipStreamSynchronize(ctx->stream));
+      fprintf(stderr, "vie: %lld iterations launched, rhs 0: %d steps, %d restarts, rel res %.3e\n",
+              (long long)((k + 1) * per_launch), h0.iters, h0.cycles,
+              h0.bnorm2 > 0 ? sqrt(h0.rnorm2 / h0.bnorm2) : 0.0);
+    }
   }
   return VIE_OK;
 }
@@ -1220,6 +1243,14 @@ static int bind_rhs(vie_ctx* ctx, Group& G, const vie_planewave* inc,
   return VIE_OK;
 }
 
+// Seconds from the call's start stamp t0 to the residual check that found S
+// converged, on the device wall clock (0 if not converged).
+static double done_seconds(const vie_ctx* ctx, const KState& S, bool conv,
+                           unsigned long long t0) {
+  if (!conv || S.t_done < t0 || !(ctx->clock_khz > 0)) return 0.0;
+  return (double)(S.t_done - t0) / (ctx->clock_khz * 1e3);
+}
+
 extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* nrhs_per_body,
                          vie_stats* stats) {
   if (!ctx) return VIE_EINVAL;
@@ -1229,6 +1260,7 @@ extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* 
   int rc = check_channels(ctx, inc, nrhs_per_body, first);
   if (rc != VIE_OK) return rc;
   if (ctx->opt.warm_start && !ctx->cnn) return VIE_EINVAL;  // warm start needs vie_attach_cnn
+  VIE_HIP(launch_stamp(ctx->t_call.as<unsigned long long>(), ctx->stream));
   for (auto& Gp : ctx->groups) {
     Group& G = *Gp;
     rc = bind_rhs(ctx, G, inc, nrhs_per_body, first);
@@ -1241,6 +1273,8 @@ extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* 
   }
   // statistics
   bool all_conv = true;
+  unsigned long long t0 = 0;
+  VIE_HIP(hipMemcpyAsync(&t0, ctx->t_call.p, sizeof(t0), hipMemcpyDeviceToHost, ctx->stream));
   for (auto& Gp : ctx->groups) {
     Group& G = *Gp;
     if (G.g.nrhs == 0) continue;
@@ -1265,6 +1299,7 @@ extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* 
           o.warm = G.warm_used.empty() ? 0 : G.warm_used[B.rhs0 + q];
           o.rel_res = rel;
           o.rel_res_x0 = G.res_x0.empty() ? 1.0 : G.res_x0[B.rhs0 + q];
+          o.seconds = done_seconds(ctx, S, conv, t0);
         }
       }
     }
@@ -1965,6 +2000,7 @@ extern "C" int vie_solve_fgmres(vie_ctx* ctx, const vie_planewave* inc,
   if (ctx->opt.warm_start && !ctx->cnn) return VIE_EINVAL;  // warm start needs vie_attach_cnn
   const bool blocks = fo->blocks[0] > 0;
   bool all_conv = true;
+  VIE_HIP(launch_stamp(ctx->t_call.as<unsigned long long>(), ctx->stream));
   for (int gi = 0; gi < (int)ctx->groups.size(); ++gi) {
     Group& G = *ctx->groups[gi];
     rc = bind_rhs(ctx, G, inc, nrhs_per_body, first);
@@ -1988,6 +2024,8 @@ extern "C" int vie_solve_fgmres(vie_ctx* ctx, const vie_planewave* inc,
     rc = fgmres_group(ctx, G, P, fo, ctx->opt.warm_start != 0, steps, cycles);
     if (rc != VIE_OK) return rc;
     std::vector<KState> hs(nrhs);
+    unsigned long long t0 = 0;
+    VIE_HIP(hipMemcpyAsync(&t0, ctx->t_call.p, sizeof(t0), hipMemcpyDeviceToHost, ctx->stream));
     VIE_HIP(hipMemcpyAsync(hs.data(), G.state.p, nrhs * sizeof(KState), hipMemcpyDeviceToHost,
                            ctx->stream));
     VIE_HIP(hipStreamSynchronize(ctx->stream));
@@ -2007,6 +2045,7 @@ extern "C" int vie_solve_fgmres(vie_ctx* ctx, const vie_planewave* inc,
         o.warm = G.warm_used[gq];
         o.rel_res = hs[gq].bnorm2 > 0 ? sqrt(hs[gq].rnorm2 / hs[gq].bnorm2) : 0.0;
         o.rel_res_x0 = G.res_x0[gq];
+        o.seconds = done_seconds(ctx, hs[gq], conv, t0);
       }
     }
   }

@@ -24,6 +24,7 @@ struct KState {
   double rh2;      // ||rhat||^2 (shadow residual of the current cycle)
   int cycles;      // FP64 true-residual products (restarts) so far
   int pad_;
+  unsigned long long t_done;  // device wall clock when the true residual first met tol (0: not)
 };
 
 // Epilogue of the inverse-x pass (y = x - chi * conv, then):
@@ -146,7 +147,16 @@ hipError_t launch_update_xr(const GroupGeom& g, const BodyIdx& bi, int vb, const
                             const int* active, c64* x, c64* r, const c64* p, const c64* sv,
                             const c64* t, const c64* rh, c64* partials, hipStream_t s);
 // Finalize reductions (one workgroup per right-hand side, fixed order):
-enum FinWhich { FIN_ALPHA = 0, FIN_OMEGA = 1, FIN_RHO = 2, FIN_INIT = 3, FIN_RESTART = 4 };
+// FIN_RESTART acts on the right-hand sides not done; FIN_PENDING (the same
+// restart) on those whose cycle has ended and waits for its true residual.
+enum FinWhich {
+  FIN_ALPHA = 0,
+  FIN_OMEGA = 1,
+  FIN_RHO = 2,
+  FIN_INIT = 3,
+  FIN_RESTART = 4,
+  FIN_PENDING = 5
+};
 struct FinParams {
   double tol2_done;   // converged when ||r_true||^2 <= tol2_done ||b||^2
   double tol2_inner;  // a cycle may stop at ||r||^2 <= tol2_inner ||b||^2 ...
@@ -189,6 +199,9 @@ hipError_t launch_vec_norm2(int nrhs, const BodyIdx& bi, const c64* v, double* o
                             hipStream_t s);
 // p[i] = v for i < n (device ints), by a kernel (no memset node when captured).
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
+// *out = the device wall clock (constant rate, hipDeviceAttributeWallClockRate
+// kHz) when the stream reaches this launch
+hipError_t launch_stamp(unsigned long long* out, hipStream_t s);
 // Gather a box-layout vector [3][n] into body-compressed storage [3][nb].
 hipError_t launch_compress(const c64* box, c64* comp, const int* vox, int nb, int64_t n,
                            hipStream_t s);

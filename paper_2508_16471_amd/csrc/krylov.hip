@@ -200,8 +200,12 @@ __global__ __launch_bounds__(VT) void k_finalize(int which, int nrhs, int nblk,
                                                  FinParams fp) {
   const int rhs = blockIdx.x;
   KState& S = st[rhs];
-  const bool gate = (which == FIN_RESTART) ? flags[nrhs + rhs] != 0
-                                           : (which == FIN_INIT ? true : flags[rhs] != 0);
+  // flags: [0, nrhs) active, [nrhs, 2 nrhs) not done, [2 nrhs, 3 nrhs) cycle
+  // ended and waiting for its true residual
+  const bool gate = (which == FIN_RESTART)   ? flags[nrhs + rhs] != 0
+                    : (which == FIN_PENDING) ? flags[2 * nrhs + rhs] != 0
+                    : (which == FIN_INIT)    ? true
+                                             : flags[rhs] != 0;
   if (!gate) return;
   c64 a = mk(0.0, 0.0), b = mk(0.0, 0.0);
   for (int k = threadIdx.x; k < nblk; k += VT) {
@@ -222,6 +226,7 @@ __global__ __launch_bounds__(VT) void k_finalize(int which, int nrhs, int nblk,
         S.breakdown = 1;  // rhat . A p vanished
         S.active = 0;
         flags[rhs] = 0;
+        flags[2 * nrhs + rhs] = 1;
       } else {
         S.alpha = cdiv(S.rho, rhv);
       }
@@ -255,11 +260,13 @@ __global__ __launch_bounds__(VT) void k_finalize(int which, int nrhs, int nblk,
       if (stop) {
         S.active = 0;
         flags[rhs] = 0;
+        flags[2 * nrhs + rhs] = 1;
       }
       break;
     }
     case FIN_INIT:
-    case FIN_RESTART: {
+    case FIN_RESTART:
+    case FIN_PENDING: {
       if (which == FIN_INIT) {
         S.bnorm2 = b.re;
         S.iters = 0;
@@ -277,9 +284,13 @@ __global__ __launch_bounds__(VT) void k_finalize(int which, int nrhs, int nblk,
       const double t_in = fp.tol2_inner * S.bnorm2, t_eta = fp.eta2 * S.rnorm2;
       S.target2 = t_in > t_eta ? t_in : t_eta;
       S.notdone = (S.rnorm2 > done2) || !(S.rnorm2 <= 1e300);
+      // completion time: the first true residual at or below tol
+      if (which == FIN_INIT) S.t_done = 0;
+      if (!S.notdone && S.t_done == 0) S.t_done = wall_clock64();
       S.active = (S.notdone && S.iters < fp.max_iter && S.rnorm2 <= 1e300) ? 1 : 0;
       flags[rhs] = S.active;
       flags[nrhs + rhs] = S.notdone;
+      flags[2 * nrhs + rhs] = 0;
       break;
     }
   }
@@ -322,6 +333,14 @@ hipError_t launch_vec_norm2(int nrhs, const BodyIdx& bi, const c64* v, double* o
 __global__ void k_fill_int(int* __restrict__ p, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+__global__ void k_stamp(unsigned long long* __restrict__ out) {
+  if (threadIdx.x == 0) out[0] = wall_clock64();
+}
+hipError_t launch_stamp(unsigned long long* out, hipStream_t s) {
+  k_stamp<<<1, 64, 0, s>>>(out);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s) {

@@ -57,7 +57,7 @@ class vie_fgmres_options(C.Structure):
 class vie_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("matvecs", C.c_int32), ("cycles", C.c_int32),
                 ("converged", C.c_int32), ("fallback", C.c_int32), ("warm", C.c_int32),
-                ("rel_res", C.c_double), ("rel_res_x0", C.c_double)]
+                ("rel_res", C.c_double), ("rel_res_x0", C.c_double), ("seconds", C.c_double)]
 
 
 class VieError(RuntimeError):
