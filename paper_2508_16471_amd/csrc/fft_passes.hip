@@ -140,7 +140,7 @@ constexpr ZShape zshape(int v) {
   return sizeof(T) == 4 ? (v == 0 ? ZShape{16, 256} : ZShape{8, 512})
                         : (v == 0 ? ZShape{8, 256} : ZShape{4, 512});
 }
-static constexpr int kZVariants = 2;
+static constexpr int kZVariants = 3;  // shapes 0 and 1 above, 2 the register-lean kernel
 template <int P, int E0>
 constexpr int zcap() {
   return (P % 3 == 0) ? (E0 >= 8 ? 12 : 6) : (E0 < P ? E0 : P);
@@ -523,9 +523,124 @@ static hipError_t y_pass(const GroupGeom& g, const cpx<T>* in, cpx<T>* out, cons
   return hipGetLastError();
 }
 
+// Register-lean z pass (autotuner shape 2, FAST layouts only): one column
+// per lane at E points (8 FP32, 4 FP64; 6 for 3 * 2^k lines) of all three
+// components, 256 threads, registers capped at 128 so that four waves share
+// each SIMD (twice the FP32 16-point shape) and memory and transform phases
+// of different workgroups overlap.  The spectrum record of the next point is
+// requested while the current one is multiplied (the first one before the
+// last forward transform); the empty asm statements keep the compiler from
+// issuing every point's loads at once.  Block order, octant lookup and signs
+// as the other shapes.
+template <typename T>
+constexpr int lean_e(int P) {
+  return sizeof(T) == 4 ? (P % 3 == 0 ? 6 : 8) : (P % 3 == 0 ? 6 : 4);
+}
+constexpr int kLeanThreads = 256;
+template <typename T, int P, bool ZP>
+__global__ __launch_bounds__(kLeanThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+k_fft_z_green_lean(cpx<T>* __restrict__ B, const cpx<T>* __restrict__ spec,
+                   const cpx<T>* __restrict__ tw, ZArgs a, const int* __restrict__ active) {
+  constexpr int E = lean_e<T>(P), TT = P / E, W = kLeanThreads / TT, LS = Pad<P>::LSTR;
+  __shared__ cpx<T> lds[W * LS];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int rhs = b % a.nrhs;
+  const int u = b / a.nrhs;
+  const int m = u & 1;
+  const int it = (u >> 1) % a.tiles_x;
+  const int yp = (u >> 1) / a.tiles_x;
+  if (m && (yp == 0 || 2 * yp == a.P2)) return;  // self-mirrored row: one block only
+  const int xy = m ? a.P2 - yp : yp;
+  const int tile = (it & 1) ? a.tiles_x - 1 - (it >> 1) : (it >> 1);
+  if (active && !active[rhs]) return;
+  const int cw = threadIdx.x % W, t = threadIdx.x / W;
+  const int xx = tile * W + cw;  // the tiles cover P1 exactly
+  cpx<T>* col = B + rhs * a.rhs_stride + (int64_t)xy * a.zl * a.P1 + xx;
+  cpx<T>* col1 = col + a.comp_stride;
+  cpx<T>* col2 = col1 + a.comp_stride;
+  const int zhs = (int)a.zhs, zls = (int)a.zls;
+  TwReg<T, P, E> tr;
+  tr.load(t, tw);
+  cpx<T> v0[E], v1[E], v2[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    v0[q] = v1[q] = v2[q] = mk<T>(0, 0);
+    const int z = t + q * TT;
+    if (q < E / 2 && (!ZP || z < a.N3)) {  // padding rows are neither read nor written
+      const int off = (z >> 4) * zhs + (z & 15) * zls;
+      v0[q] = col[off];
+      v1[q] = col1[off];
+      v2[q] = col2[off];
+    }
+  }
+  const int xm = xx > a.P1 / 2, ym = xy > a.P2 / 2;
+  const int xo = xm ? a.P1 - xx : xx, yo = ym ? a.P2 - xy : xy;
+  const cpx<T>* sxy = spec + ((int64_t)yo * a.Q3 * a.Q1 + xo) * 6;
+  auto rec = [&](int q) {
+    const int z = t + q * TT;
+    return sxy + (int64_t)(z > P / 2 ? P - z : z) * 6 * a.Q1;
+  };
+  cpx<T>* line = lds + cw * LS;
+  line_fft_e<T, P, E, false, true, false>(v0, line, t, tr);
+  line_fft_e<T, P, E, false, true, false>(v1, line, t, tr);
+  cpx<T> gn[6];
+  load_g6<T>(rec(0), gn);
+  asm volatile("" ::: "memory");
+  line_fft_e<T, P, E, false, true, false>(v2, line, t, tr);
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int zm = t + q * TT > P / 2;
+    cpx<T> gg[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gg[k] = gn[k];
+    if (q + 1 < E) load_g6<T>(rec(q + 1), gn);
+    asm volatile("" ::: "memory");
+    const cpx<T> gxx = gg[0], gyy = gg[3], gzz = gg[5];
+    cpx<T> gxy = gg[1], gxz = gg[2], gyz = gg[4];
+    // G_ab is odd along axis e iff exactly one of a, b equals e
+    if (xm ^ ym) gxy = mk<T>(-gxy.re, -gxy.im);
+    if (xm ^ zm) gxz = mk<T>(-gxz.re, -gxz.im);
+    if (ym ^ zm) gyz = mk<T>(-gyz.re, -gyz.im);
+    const cpx<T> ix = v0[q], iy = v1[q], iz = v2[q];
+    v0[q] = cfma(gxz, iz, cfma(gxy, iy, gxx * ix));
+    v1[q] = cfma(gyz, iz, cfma(gyy, iy, gxy * ix));
+    v2[q] = cfma(gzz, iz, cfma(gyz, iy, gxz * ix));
+  }
+  line_fft_e<T, P, E, true, false, true>(v0, line, t, tr);
+  line_fft_e<T, P, E, true, false, true>(v1, line, t, tr);
+  line_fft_e<T, P, E, true, false, true>(v2, line, t, tr);
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int z = t + q * TT;
+    if (!ZP || z < a.N3) {
+      const int off = (z >> 4) * zhs + (z & 15) * zls;
+      col[off] = v0[q];
+      col1[off] = v1[q];
+      col2[off] = v2[q];
+    }
+  }
+}
+
 template <typename T, int PP, int V>
 static void z_launch(const GroupGeom& g, ZArgs a, cpx<T>* B, const cpx<T>* spec,
                      const cpx<T>* tw, const int* active, hipStream_t s) {
+  if constexpr (V == 2) {
+    // FP64 3 * 2^k lines would spill at the register cap: they keep shape 0
+    if constexpr (PP >= 32 && PP <= 128 && (sizeof(T) == 4 || PP % 3 != 0)) {
+      constexpr int W = kLeanThreads / (PP / lean_e<T>(PP));
+      if (a.zl == 16 && 2 * ((a.N3 + 15) / 16) * 16 == PP && g.P[0] % W == 0) {
+        a.tiles_x = g.P[0] / W;
+        const dim3 grid((g.P[1] / 2 + 1) * 2 * a.tiles_x * g.nrhs);
+        if (2 * a.N3 == PP)
+          k_fft_z_green_lean<T, PP, false><<<grid, kLeanThreads, 0, s>>>(B, spec, tw, a, active);
+        else
+          k_fft_z_green_lean<T, PP, true><<<grid, kLeanThreads, 0, s>>>(B, spec, tw, a, active);
+        return;
+      }
+    }
+    z_launch<T, PP, 0>(g, a, B, spec, tw, active, s);  // layouts the lean kernel does not take
+    return;
+  } else {
   constexpr ZShape sh = zshape<T>(V);
   constexpr int E = zcap<PP, sh.e>();
   constexpr int W = sh.nt / (PP / E);
@@ -542,6 +657,7 @@ static void z_launch(const GroupGeom& g, ZArgs a, cpx<T>* B, const cpx<T>* spec,
     }
   }
   k_fft_z_green<T, PP, E, sh.nt, false><<<grid, sh.nt, 0, s>>>(B, spec, tw, a, active);
+  }
 }
 
 template <typename T>
@@ -564,6 +680,7 @@ static hipError_t z_pass(const GroupGeom& g, cpx<T>* B, const cpx<T>* spec, cons
   VIE_DISPATCH_PZ(g.P[2], ({
                    switch (variant) {
                      case 1: z_launch<T, PP, 1>(g, a, B, spec, tw, active, s); break;
+                     case 2: z_launch<T, PP, 2>(g, a, B, spec, tw, active, s); break;
                      default: z_launch<T, PP, 0>(g, a, B, spec, tw, active, s); break;
                    }
                  }));

@@ -277,14 +277,17 @@ def test_matvec_sampled_rows_large(V, n, rows):
     assert _relerr(y32, ref) < 5e-6
 
 
-@pytest.mark.parametrize("zvar", [0, 1])
+@pytest.mark.parametrize("zvar", [0, 1, 2])
 @pytest.mark.parametrize("n", [(64, 64, 64), (24, 20, 17), (32, 17, 29), (64, 24, 37)])
 def test_every_z_pass_shape_matches_oracle(V, zvar, n):
     """Each fused z-pass shape the autotuner may pick (forced through
     VIE_ZVAR), FP64 and FP32, two vectors per call, against the oracle's
     direct sum on sampled rows.  (32, 17, 29) and (64, 24, 37) have N3 below
     half the z line (64 and 96 points) with the blocked layout holding exactly
-    half a line: the shift-addressed launches with zero-filled padding rows."""
+    half a line: the shift-addressed launches with zero-filled padding rows.
+    Shape 2 (the register-lean kernel) runs on the three layouts with N3
+    rounded to 16 equal to half the z line (FP64 96-point lines and the
+    (24, 20, 17) grid fall back to shape 0)."""
     import os
 
     rng = np.random.default_rng(7 * zvar + n[0])
