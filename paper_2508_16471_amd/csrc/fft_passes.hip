@@ -770,11 +770,11 @@ __global__ __launch_bounds__(NTB) void k_fft_y_h2(const cpx<h2>* __restrict__ in
 template <int P1, int P2>
 struct XYShape {
   static constexpr int NT = 256;
-  static constexpr int E1 = fft_e<P1>(), TT1 = P1 / E1, L1 = NT / TT1;
-  static constexpr int E2 = fft_e<P2>(), TT2 = P2 / E2, W2 = NT / TT2;
-  // packed pairs per plane row, padded by 8 pairs (16 banks): the x phase's
-  // eight lines per wave then start on four different bank groups
-  static constexpr int PS = P1 / 2 + 8;
+  // 8 points per thread on 128-point lines (16 threads a line): fewer lines
+  // in flight per phase, so three workgroups share a CU
+  static constexpr int E1 = P1 == 128 ? 8 : fft_e<P1>(), TT1 = P1 / E1, L1 = NT / TT1;
+  static constexpr int E2 = P2 == 128 ? 8 : fft_e<P2>(), TT2 = P2 / E2, W2 = NT / TT2;
+  static constexpr int PS = P1 / 2;               // packed pairs per plane row
   static constexpr int NP = P1 / 2;               // column pairs
   static constexpr int PLANE = (P2 / 2) * PS;     // rows N2 <= P2 / 2
   static constexpr int XLS = PadX<P1, TT1>::LSTR;  // x-line stride
@@ -836,7 +836,7 @@ __global__ __launch_bounds__(256) void k_fft_xy_fwd_h2(
       cpx<float> v[E];
 #pragma unroll
       for (int q = 0; q < E; ++q) v[q] = (q < E / 2) ? myl[pidx(t + q * TT)] : mk<float>(0, 0);
-      line_fft<float, P1, false, true>(v, myl, t, tr);
+      line_fft_e<float, P1, E, false, true, false>(v, myl, t, tr);
       // lanes t, t + 1 hold neighbouring points: one exchange packs a pair
 #pragma unroll
       for (int q = 0; q < E; q += 2) {
@@ -866,7 +866,7 @@ __global__ __launch_bounds__(256) void k_fft_xy_fwd_h2(
         v[q] = (q < E / 2 && valid && row < N2) ? hscale(plane[row * S::PS + p], sc)
                                                : mk<h2>(h2{0, 0}, h2{0, 0});
       }
-      line_fft<h2, P2, false, true>(v, myl, t, tr);
+      line_fft_e<h2, P2, E, false, true, false>(v, myl, t, tr);
       if (valid) {
 #pragma unroll
         for (int q = 0; q < E; ++q) po[(int64_t)(t + q * TT) * sb.row + p] = v[q];
@@ -901,7 +901,7 @@ __global__ __launch_bounds__(256) void k_fft_yx_inv_h2(
 #pragma unroll
       for (int q = 0; q < E; ++q)
         v[q] = valid ? pin[(int64_t)(t + q * TT) * sb.row + p] : mk<h2>(h2{0, 0}, h2{0, 0});
-      line_fft<h2, P2, true, false, true>(v, myl, t, tr);
+      line_fft_e<h2, P2, E, true, false, true>(v, myl, t, tr);
       if (valid) {
 #pragma unroll
         for (int q = 0; q < E / 2; ++q) {
@@ -934,7 +934,7 @@ __global__ __launch_bounds__(256) void k_fft_yx_inv_h2(
         if (valid) f = unpack2(plane[y * S::PS + ((t - odd + (q + odd) * TT) >> 1)]);
         pair_in(f, odd, v[q], v[q + 1]);
       }
-      line_fft<float, P1, true, false, true>(v, myl, t, tr);  // only x < N1 is used
+      line_fft_e<float, P1, E, true, false, true>(v, myl, t, tr);  // only x < N1 is used
       lds_barrier();  // every thread has left the transform's last LDS read
 #pragma unroll
       for (int q = 0; q < E / 2; ++q) myl[pidx(t + q * TT)] = v[q];
