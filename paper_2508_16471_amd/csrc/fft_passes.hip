@@ -775,6 +775,7 @@ struct XYShape {
   static constexpr int E1 = P1 == 128 ? 8 : fft_e<P1>(), TT1 = P1 / E1, L1 = NT / TT1;
   static constexpr int E2 = P2 == 128 ? 8 : fft_e<P2>(), TT2 = P2 / E2, W2 = NT / TT2;
   static constexpr int PS = P1 / 2;               // packed pairs per plane row
+  static constexpr int NBX = (P2 / 2 + L1 - 1) / L1;  // x-line batches (N2 <= P2 / 2)
   static constexpr int NP = P1 / 2;               // column pairs
   static constexpr int PLANE = (P2 / 2) * PS;     // rows N2 <= P2 / 2
   static constexpr int XLS = PadX<P1, TT1>::LSTR;  // x-line stride
@@ -801,38 +802,56 @@ __global__ __launch_bounds__(256) void k_fft_xy_fwd_h2(
   const int* vox = bi.vox + bi.voff[body];
   const int* lp = bi.line_ptr + (int64_t)body * (N2 * N3 + 1);
   const cb16* xv = xc + bi.roff[rhs] + (int64_t)comp * nb;
-  {  // x: FP32 lines into the plane
+  {  // x: FP32 lines into the plane, S::L1 lines a batch
     constexpr int E = S::E1, TT = S::TT1;
     const int li = threadIdx.x / TT, t = threadIdx.x % TT, odd = t & 1;
     cpx<float>* myl = reinterpret_cast<cpx<float>*>(ubuf) + li * S::XLS;
     TwReg<float, P1, E> tr;
     tr.load(t, tw1);
-    for (int y0 = 0; y0 < N2; y0 += S::L1) {
-      const int y = y0 + li;
+    // the line pointers of this thread's line in every batch, in one round of
+    // loads; each batch's voxels (at most P1 / 2 a line, so E / 2 a thread)
+    // are requested while the previous batch is transformed
+    int lpa[S::NBX], lpb[S::NBX];
+#pragma unroll
+    for (int n = 0; n < S::NBX; ++n) {
+      const int y = n * S::L1 + li;
+      lpa[n] = lpb[n] = 0;
+      if (y < N2) {
+        lpa[n] = lp[z * N2 + y];
+        lpb[n] = lp[z * N2 + y + 1];
+      }
+    }
+    int kv[E / 2];
+    cb16 xr[E / 2];
+    auto fetch = [&](int n) {
+      const int k0 = lpa[n] + t, k1 = lpb[n];
+#pragma unroll
+      for (int i = 0; i < E / 2; ++i) {
+        const int k = k0 + i * TT;
+        if (k < k1) {
+          kv[i] = vox[k];
+          xr[i] = xv[k];
+        }
+      }
+    };
+    fetch(0);
+#pragma unroll
+    for (int n = 0; n < S::NBX; ++n) {
+      if (n * S::L1 >= N2) break;
+      const int y = n * S::L1 + li;
       const bool valid = y < N2;
       lds_barrier();  // the previous lines' last transform stage has read the buffer
 #pragma unroll
       for (int q = 0; q < E / 2; ++q) myl[pidx(t + q * TT)] = mk<float>(0, 0);
       lds_barrier();
-      if (valid) {
-        // at most P1 / 2 voxels a line: all loads issued before the writes
-        const int zy = z * N2 + y;
-        const int k0 = lp[zy] + t, k1 = lp[zy + 1], base = zy * N1;
-        int kv[E / 2];
-        cb16 xr[E / 2];
-#pragma unroll
-        for (int i = 0; i < E / 2; ++i) {
-          const int k = k0 + i * TT;
-          if (k < k1) {
-            kv[i] = vox[k];
-            xr[i] = xv[k];
-          }
-        }
+      {
+        const int k0 = lpa[n] + t, k1 = lpb[n], base = (z * N2 + y) * N1;
 #pragma unroll
         for (int i = 0; i < E / 2; ++i)
           if (k0 + i * TT < k1) myl[pidx(kv[i] - base)] = cvt<float>(xr[i]);
       }
       lds_barrier();
+      if (n + 1 < S::NBX) fetch(n + 1);
       cpx<float> v[E];
 #pragma unroll
       for (int q = 0; q < E; ++q) v[q] = (q < E / 2) ? myl[pidx(t + q * TT)] : mk<float>(0, 0);
@@ -887,6 +906,43 @@ __global__ __launch_bounds__(256) void k_fft_yx_inv_h2(
   const int rhs = blockIdx.x % nrhs, cz = blockIdx.x / nrhs;
   if (active && !active[rhs]) return;
   const int comp = cz / N3, z = cz % N3;
+  // The epilogue's operands of this thread's x line in every batch (line
+  // pointers first, in one round; then each batch's voxels, at most P1 / 2 a
+  // line, so E1 / 2 a thread) are requested ahead: the first batch's before
+  // the y phase, each next one while the current batch is finished.
+  const int body = bi.rhs_body[rhs];
+  const int nb = bi.nb[body];
+  const int* vox = bi.vox + bi.voff[body];
+  const double* chic = bi.chic + bi.voff[body];
+  const int* lp = bi.line_ptr + (int64_t)body * (N2 * N3 + 1);
+  const int64_t vb = bi.roff[rhs] + (int64_t)comp * nb;
+  const int lix = threadIdx.x / S::TT1, tx = threadIdx.x % S::TT1;
+  int lpa[S::NBX], lpb[S::NBX];
+#pragma unroll
+  for (int n = 0; n < S::NBX; ++n) {
+    const int y = n * S::L1 + lix;
+    lpa[n] = lpb[n] = 0;
+    if (y < N2) {
+      lpa[n] = lp[z * N2 + y];
+      lpb[n] = lp[z * N2 + y + 1];
+    }
+  }
+  int kv[S::E1 / 2];
+  double cv[S::E1 / 2];
+  cb16 xr[S::E1 / 2];
+  auto fetch = [&](int n) {
+    const int k0 = lpa[n] + tx, k1 = lpb[n];
+#pragma unroll
+    for (int i = 0; i < S::E1 / 2; ++i) {
+      const int k = k0 + i * S::TT1;
+      if (k < k1) {
+        kv[i] = vox[k];
+        cv[i] = chic[k];
+        xr[i] = xin[vb + k];
+      }
+    }
+  };
+  fetch(0);
   {  // inverse y: packed column pairs from the y/z scratch into the plane (rows < N2)
     constexpr int E = S::E2, TT = S::TT2;
     const int cw = threadIdx.x % S::W2, t = threadIdx.x / S::W2;
@@ -914,18 +970,14 @@ __global__ __launch_bounds__(256) void k_fft_yx_inv_h2(
   lds_barrier();  // the plane is complete and the line buffer free
   {  // inverse x in FP32 and the compressed epilogue, L1 lines at a time
     constexpr int E = S::E1, TT = S::TT1;
-    const int li = threadIdx.x / TT, t = threadIdx.x % TT, odd = t & 1;
+    const int li = lix, t = tx, odd = t & 1;
     cpx<float>* myl = reinterpret_cast<cpx<float>*>(ubuf) + li * S::XLS;
     TwReg<float, P1, E> tr;
     tr.load(t, tw1);
-    const int body = bi.rhs_body[rhs];
-    const int nb = bi.nb[body];
-    const int* vox = bi.vox + bi.voff[body];
-    const double* chic = bi.chic + bi.voff[body];
-    const int* lp = bi.line_ptr + (int64_t)body * (N2 * N3 + 1);
-    const int64_t vb = bi.roff[rhs] + (int64_t)comp * nb;
-    for (int y0 = 0; y0 < N2; y0 += S::L1) {
-      const int y = y0 + li;
+#pragma unroll
+    for (int n = 0; n < S::NBX; ++n) {
+      if (n * S::L1 >= N2) break;
+      const int y = n * S::L1 + li;
       const bool valid = y < N2;
       cpx<float> v[E];
 #pragma unroll
@@ -939,22 +991,8 @@ __global__ __launch_bounds__(256) void k_fft_yx_inv_h2(
 #pragma unroll
       for (int q = 0; q < E / 2; ++q) myl[pidx(t + q * TT)] = v[q];
       lds_barrier();
-      if (valid) {
-        // at most P1 / 2 voxels a line: all loads issued before the first use
-        const int zy = z * N2 + y;
-        const int k0 = lp[zy] + t, k1 = lp[zy + 1], base = zy * N1;
-        int kv[E / 2];
-        double cv[E / 2];
-        cb16 xr[E / 2];
-#pragma unroll
-        for (int i = 0; i < E / 2; ++i) {
-          const int k = k0 + i * TT;
-          if (k < k1) {
-            kv[i] = vox[k];
-            cv[i] = chic[k];
-            xr[i] = xin[vb + k];
-          }
-        }
+      {
+        const int k0 = lpa[n] + t, k1 = lpb[n], base = (z * N2 + y) * N1;
 #pragma unroll
         for (int i = 0; i < E / 2; ++i) {
           const int k = k0 + i * TT;
@@ -964,6 +1002,7 @@ __global__ __launch_bounds__(256) void k_fft_yx_inv_h2(
           yout[vb + k] = cvt<float>(r);
         }
       }
+      if (n + 1 < S::NBX) fetch(n + 1);
     }
   }
 }
