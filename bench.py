@@ -250,13 +250,15 @@ def block_geometry(bodies, blocks):
             "nb_mean": float(np.mean(nbv)) if nbv else 0.0}
 
 
-def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch, block_vin=8):
+def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch, block_vin=8, nrm_fused=False):
     """Achieved GB/s of every FFT pass of the FGMRES solve: FP32 outer
     products (one per Arnoldi step), FP64 true-residual products (one per
     cycle) and the FP32 block products (k per step, one execution per block
     of the right-hand side's body).  FP32 products read and write FP32
     vectors, except that block products read their bfloat16 basis vectors
-    (block_vin = 4)."""
+    (block_vin = 4).  nrm_fused: k - 1 of the k fused forward passes of every
+    block solve read the FP32 work vector instead (8 bytes) and write the
+    normalised bfloat16 basis vector (4 bytes)."""
     iters = np.array([s["iters"] for s in stats])
     cyc = np.array([s["cycles"] for s in stats])
     per_step = len(geom["blocks_per_body"]) * nch  # stats repeat once per timed step
@@ -281,13 +283,15 @@ def roofline_fgmres(times, stats, N, P, Q, nb, geom, k, nch, block_vin=8):
                                   vin=block_vin if (blk and f32) else None)
         if base.startswith(("fft_z_green", "fft_z_h16")):
             by += launches_active * spectrum_bytes(base, Qk)
+        if blk and nrm_fused and base.startswith("fft_xy_fwd"):
+            by += int((iters * (k - 1) * nblk).sum()) * 3 * nbk * (8 - block_vin + 4)
         rows[kind] = {"ms_total": ms, "launches": int(cnt), "rhs_execs": execs,
                       "bytes": float(by), "GBps": by / (ms * 1e-3) / 1e9,
                       "avg_launch_ms": ms / cnt}
     return rows
 
 
-def arnoldi_bytes(stats, nbv, nch, restart, k, block_vb=8):
+def arnoldi_bytes(stats, nbv, nch, restart, k, block_vb=8, block_nrm_fused=False):
     """Algorithmic HBM bytes of the FGMRES Gram-Schmidt kernels (timing kind
     "arnoldi": one classical Gram-Schmidt pass per step in the mixed path,
     FP32 work vector, basis elements of vb bytes): at step j of a cycle, per
@@ -296,8 +300,10 @@ def arnoldi_bytes(stats, nbv, nch, restart, k, block_vb=8):
     V_{j+1}: 2 vb j + 3 vb + 32 bytes (16 j + 56 with the FP32 basis).
     Outer process (FP32 basis): every cycle's steps; block solves (basis of
     block_vb bytes: 8, or 4 in bfloat16): k steps per outer step over the
-    same elements (the blocks partition the body).  nbv: body voxels of each
-    body, stats in body-major order."""
+    same elements (the blocks partition the body).  block_nrm_fused: the
+    block solves' normalisation runs inside the next packed product (its bytes
+    are that kernel's), so a block step is 2 vb j + 2 vb + 24 bytes.  nbv:
+    body voxels of each body, stats in body-major order."""
     total = 0.0
     per = len(nbv) * nch
     for i, st in enumerate(stats):
@@ -306,7 +312,10 @@ def arnoldi_bytes(stats, nbv, nch, restart, k, block_vb=8):
         full, rem = divmod(steps, restart)
         cyc = [restart] * full + ([rem] if rem else [])
         outer = sum(8 * c * (c - 1) + 56 * c for c in cyc)
-        inner = steps * (block_vb * k * (k - 1) + (3 * block_vb + 32) * k)
+        if block_nrm_fused:
+            inner = steps * (block_vb * k * (k - 1) + (2 * block_vb + 24) * k)
+        else:
+            inner = steps * (block_vb * k * (k - 1) + (3 * block_vb + 32) * k)
         total += n * (outer + inner)
     return total
 
@@ -1256,8 +1265,11 @@ def main():
     iters_match = [s["iters"] for s in inst_stats] == [s["iters"] for s in all_stats]
     nb_mean = float(np.mean([(e > 1).sum() for e, _, _, _ in bodies]))
     if use_fgmres:
+        nrm_fused = (args.block_basis == "bf16"
+                     and times.get("block_fft_xy_fwd_h16", (0.0, 0))[1] > 0)
         fast_rows = roofline_fgmres(times, inst_stats, N, P, Q, nb_mean, geom, args.inner_iters, nch,
-                                    block_vin=4 if args.block_basis == "bf16" else 8)
+                                    block_vin=4 if args.block_basis == "bf16" else 8,
+                                    nrm_fused=nrm_fused)
     else:
         fast_rows = roofline_from_times(times, inst_stats, N, P, Q, mixed=True, nb=nb_mean)
     dom = max(fast_rows, key=lambda k: fast_rows[k]["ms_total"])
@@ -1279,13 +1291,16 @@ def main():
         a_ms = times["arnoldi"][0]
         a_by = arnoldi_bytes(inst_stats, [int((e != 1.0).sum()) for e, _, _, _ in bodies], nch,
                              args.restart, args.inner_iters,
-                             block_vb=4 if args.block_basis == "bf16" else 8)
+                             block_vb=4 if args.block_basis == "bf16" else 8,
+                             block_nrm_fused=use_fgmres and nrm_fused)
         arn = {"ms_total": a_ms, "launches": int(times["arnoldi"][1]), "bytes": a_by,
                "GBps": a_by / (a_ms * 1e-3) / 1e9, "frac": a_by / (a_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                "model": ("2 vb j + 3 vb + 32 bytes per element at Gram-Schmidt step j (FP32 w; "
                          "basis element vb = 8 B outer, " +
                          ("4 B (bfloat16)" if args.block_basis == "bf16" else "8 B") +
-                         " in the block solves)")}
+                         " in the block solves" +
+                         ("; 2 vb j + 2 vb + 24 there, their normalisation being done by the "
+                          "next packed product" if use_fgmres and nrm_fused else "") + ")")}
     conv = all(s["converged"] for s in all_stats)
     max_res = max(s["rel_res"] for s in all_stats)
     prod_fast = np.mean([s["matvecs"] for s in all_stats])

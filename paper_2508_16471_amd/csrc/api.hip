@@ -807,6 +807,27 @@ static hipError_t run_matvec(vie_ctx* ctx, Group& G, int precision, const void* 
                        ctx);
 }
 
+// Packed fused product of the block solves whose input is the FP32 work
+// vector w normalised on the way in (MatvecArgs::npart): the normalised
+// bfloat16 vector goes to vout, ||w||^2 of every right-hand side to
+// nrm[q ldn], the product to y (FP32).
+static hipError_t run_matvec_nrm(vie_ctx* ctx, Group& G, const void* w, void* y, void* vout,
+                                 const double* npart, int nblk, double* nrm, int ldn,
+                                 const int* active) {
+  hipError_t te = tune_z(ctx, G, 1);
+  if (te != hipSuccess) return te;
+  MatvecArgs m = matvec_args(G, 1, active);
+  m.bi = &G.bi;
+  m.io32 = 2;
+  m.npart = npart;
+  m.nblk = nblk;
+  m.nrm = nrm;
+  m.ldn = ldn;
+  m.vout = vout;
+  EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
+  return launch_matvec(m, 1, w, y, e, ctx->stream, timing_on(ctx) ? timing_cb : nullptr, ctx);
+}
+
 // ------------------------------------------------------ learned warm start
 // Krylov inputs of the network for every right-hand side, r holding b after
 // the init kernel: v = A r, s = A v, t = A s (FP32 products), and the squared
@@ -1378,8 +1399,12 @@ static int arnoldi_tables(vie_ctx* ctx, ArnoldiBufs& A, const std::vector<int64_
 // fell below eta2 times its value before the pass (eta2 = 1/2: the "twice is
 // enough" criterion of Daniel, Gragg, Kaufman and Stewart 1976; eta2 = 0: one
 // pass); ||w||^2 into NR[s][j+1], V_{j+1} = w / ||w||.
+// nonorm (single pass, FP32 w): w_{j+1} is not normalised here; its norm
+// partials stay for the next product, which normalises it on the way in, or
+// for the last step (j = m - 1, whose vector is not needed) its norm is
+// reduced into NR.
 static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, int64_t stride,
-                               int m, int j, double eta2) {
+                               int m, int j, double eta2, bool nonorm = false) {
   const void* V = A.V.p;
   const int v32 = A.v32;       // basis storage (0 FP64, 1 FP32, 2 bfloat16)
   const int w32 = v32 ? 1 : 0;
@@ -1400,6 +1425,11 @@ static hipError_t arnoldi_orth(vie_ctx* ctx, ArnoldiBufs& A, const SegSet& S, in
     return e;
   // one pass with an FP32 work vector: the normalisation reduces the norm
   const bool defer = eta2 <= 0 && w32;
+  if (nonorm) {
+    if (!defer) return hipErrorInvalidValue;
+    return launch_seg_maxpy(S, V, v32, stride, j + 1, nullptr, h1, ldh, w, w32, npart, nr, m + 1,
+                            ctx->stream, j + 1 < m);
+  }
   if ((e = launch_seg_maxpy(S, V, v32, stride, j + 1, nullptr, h1, ldh, w, w32, npart, nr, m + 1,
                             ctx->stream, defer)) != hipSuccess)
     return e;
@@ -1657,11 +1687,20 @@ static int bj_apply(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo, co
   // the block solves are approximations: with FP32 block products one
   // Gram-Schmidt pass is enough
   const double eta2 = ip ? 0.0 : 0.5;
+  // packed fused products normalise the basis vector on the way in: the
+  // Gram-Schmidt step leaves w and its norm partials, the next product
+  // stores V_j = w / ||w|| and multiplies it
+  const bool nrm_in = A.v32 == 2 && Gp.zh && xy_fused_ok(Gp.g);
   for (int j = 0; j < k; ++j) {
     // with an FP32 basis the FP32 product reads V_j and writes w in FP32
     EpiArgs e{EPI_PLAIN, nullptr, nullptr, 0, nullptr, nullptr};
-    VIE_HIP(run_matvec(sub, Gp, ip, A.at(A.V, j, tot), A.w.p, e, A.act.as<int>(), true, A.v32));
-    VIE_HIP(timed(ctx, kArnoldiKind, [&] { return arnoldi_orth(ctx, A, S, tot, k, j, eta2); }));
+    if (j > 0 && nrm_in)
+      VIE_HIP(run_matvec_nrm(sub, Gp, A.w.p, A.w.p, A.at(A.V, j, tot), A.npart.as<double>(),
+                             S.nblk, NR + j, ldn, A.act.as<int>()));
+    else
+      VIE_HIP(run_matvec(sub, Gp, ip, A.at(A.V, j, tot), A.w.p, e, A.act.as<int>(), true, A.v32));
+    VIE_HIP(timed(ctx, kArnoldiKind,
+                  [&] { return arnoldi_orth(ctx, A, S, tot, k, j, eta2, nrm_in); }));
   }
   // least squares of every block solve on the device, then X = V y
   VIE_HIP(launch_ls_full(nseg, k, A.H1.as<c64>(), A.H2.as<c64>(), eta2 > 0 ? 1 : 0, ldn, NR, ldn,

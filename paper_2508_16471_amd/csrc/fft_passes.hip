@@ -12,6 +12,8 @@
 // outputs.  The 3x3 symmetric spectrum is stored on the octant
 // [0, P/2]^3 only; the other octants follow from the per-axis parity of each
 // Green component.
+#include <type_traits>
+
 #include "fft_common.h"
 #include "kernels.h"
 
@@ -785,11 +787,15 @@ struct XYShape {
   static_assert(NT % TT1 == 0 && NT % TT2 == 0 && TT1 % 2 == 0, "fused x-y shape");
 };
 
-template <int P1, int P2>
+// NRM: the input is an FP32 work vector, normalised per right-hand side
+// (see MatvecArgs::npart) into the bfloat16 vector vout on the way in.
+template <int P1, int P2, bool NRM>
 __global__ __launch_bounds__(256) void k_fft_xy_fwd_h2(
-    const cb16* __restrict__ xc, cpx<h2>* __restrict__ B, const c32* __restrict__ tw1,
+    const void* __restrict__ xcv, cpx<h2>* __restrict__ B, const c32* __restrict__ tw1,
     const cpx<h2>* __restrict__ tw2, BodyIdx bi, int N1, int N2, int N3, SideAddr sb, int zl,
-    float hs1, float hs2, const int* __restrict__ active) {
+    float hs1, float hs2, const int* __restrict__ active, const double* __restrict__ npart,
+    int nblk, double* __restrict__ nrm, int ldn, cb16* __restrict__ vout) {
+  using TXI = typename std::conditional<NRM, c32, cb16>::type;
   using S = XYShape<P1, P2>;
   __shared__ cpx<h2> plane[S::PLANE];
   __shared__ __align__(16) char ubuf[S::UB];
@@ -801,7 +807,18 @@ __global__ __launch_bounds__(256) void k_fft_xy_fwd_h2(
   const int nb = bi.nb[body];
   const int* vox = bi.vox + bi.voff[body];
   const int* lp = bi.line_ptr + (int64_t)body * (N2 * N3 + 1);
-  const cb16* xv = xc + bi.roff[rhs] + (int64_t)comp * nb;
+  const TXI* xv = reinterpret_cast<const TXI*>(xcv) + bi.roff[rhs] + (int64_t)comp * nb;
+  cb16* vo = NRM ? vout + bi.roff[rhs] + (int64_t)comp * nb : nullptr;
+  double sc = 1.0;
+  if constexpr (NRM) {
+    // ||w||^2 of this right-hand side: every wave sums the partials in the
+    // order of the separate reduction (lane-strided, then a fixed butterfly)
+    double t2 = 0.0;
+    for (int k = threadIdx.x & 63; k < nblk; k += 64) t2 += npart[(int64_t)rhs * nblk + k];
+    for (int mk = 32; mk >= 1; mk >>= 1) t2 += __shfl_xor(t2, mk);
+    sc = t2 > 0.0 ? 1.0 / sqrt(t2) : 0.0;
+    if (comp == 0 && z == 0 && threadIdx.x == 0) nrm[(int64_t)rhs * ldn] = t2;
+  }
   {  // x: FP32 lines into the plane, S::L1 lines a batch
     constexpr int E = S::E1, TT = S::TT1;
     const int li = threadIdx.x / TT, t = threadIdx.x % TT, odd = t & 1;
@@ -822,7 +839,7 @@ __global__ __launch_bounds__(256) void k_fft_xy_fwd_h2(
       }
     }
     int kv[E / 2];
-    cb16 xr[E / 2];
+    TXI xr[E / 2];
     auto fetch = [&](int n) {
       const int k0 = lpa[n] + t, k1 = lpb[n];
 #pragma unroll
@@ -847,8 +864,20 @@ __global__ __launch_bounds__(256) void k_fft_xy_fwd_h2(
       {
         const int k0 = lpa[n] + t, k1 = lpb[n], base = (z * N2 + y) * N1;
 #pragma unroll
-        for (int i = 0; i < E / 2; ++i)
-          if (k0 + i * TT < k1) myl[pidx(kv[i] - base)] = cvt<float>(xr[i]);
+        for (int i = 0; i < E / 2; ++i) {
+          if (k0 + i * TT >= k1) continue;
+          if constexpr (NRM) {
+            // the basis vector as stored (bfloat16 through FP32) is what is multiplied
+            const c64 wn = sc * cvt<double>(xr[i]);
+            cb16 b16;
+            b16.re = (__bf16)(float)wn.re;
+            b16.im = (__bf16)(float)wn.im;
+            vo[k0 + i * TT] = b16;
+            myl[pidx(kv[i] - base)] = cvt<float>(b16);
+          } else {
+            myl[pidx(kv[i] - base)] = cvt<float>(xr[i]);
+          }
+        }
       }
       lds_barrier();
       if (n + 1 < S::NBX) fetch(n + 1);
@@ -1210,18 +1239,27 @@ bool xy_fused_ok(const GroupGeom& g) { return xy_len_ok(g.P[0]) && xy_len_ok(g.P
     default: return hipErrorInvalidValue;            \
   }
 
+// m.npart set: normalising FP32 input (see MatvecArgs), else bfloat16 input
 static hipError_t xy_fwd_h2(const GroupGeom& g, const void* xc, cpx<h2>* B, const c32* tw1,
                             const cpx<h2>* tw2, const BodyIdx& bi, float hs1, float hs2,
-                            const int* active, hipStream_t s) {
+                            const MatvecArgs& m, hipStream_t s) {
   if (!xy_fused_ok(g)) return hipErrorInvalidValue;
   const int zl = z_block(g);
   const SideAddr sb = halved(side_B(g, zl));
   const dim3 grid(g.nrhs * 3 * g.N[2]);
   VIE_DISPATCH_XY(g.P[0], ({
                     constexpr int Q1 = PP;
-                    VIE_DISPATCH_XY(g.P[1], (k_fft_xy_fwd_h2<Q1, PP><<<grid, 256, 0, s>>>(
-                                                (const cb16*)xc, B, tw1, tw2, bi, g.N[0], g.N[1],
-                                                g.N[2], sb, zl, hs1, hs2, active)));
+                    VIE_DISPATCH_XY(g.P[1], ({
+                                      if (m.npart)
+                                        k_fft_xy_fwd_h2<Q1, PP, true><<<grid, 256, 0, s>>>(
+                                            xc, B, tw1, tw2, bi, g.N[0], g.N[1], g.N[2], sb, zl,
+                                            hs1, hs2, m.active, m.npart, m.nblk, m.nrm, m.ldn,
+                                            (cb16*)m.vout);
+                                      else
+                                        k_fft_xy_fwd_h2<Q1, PP, false><<<grid, 256, 0, s>>>(
+                                            xc, B, tw1, tw2, bi, g.N[0], g.N[1], g.N[2], sb, zl,
+                                            hs1, hs2, m.active, nullptr, 0, nullptr, 0, nullptr);
+                                    }));
                   }));
   return hipGetLastError();
 }
@@ -1416,11 +1454,14 @@ static hipError_t matvec_t(const MatvecArgs& m, const void* xv, void* yv, EpiArg
       const cpx<h2>* twz = (const cpx<h2>*)m.tw16[1];
       base = kH16Kind0;
       if (xy_fused_ok(g)) {  // x and y fused per plane: no x-y scratch traffic
-        STEP(5, xy_fwd_h2(g, xv, Bh, (const c32*)tw0, twy, *m.bi, m.hs[0], m.hs[1], m.active, s));
+        STEP(5, xy_fwd_h2(g, xv, Bh, (const c32*)tw0, twy, *m.bi, m.hs[0], m.hs[1], m, s));
         STEP(2, z_pass_h2(g, Bh, (const cpx<h2>*)m.spec16, twz, m.hs[2], m.active, s));
-        STEP(6, yx_inv_h2(g, Bh, xv, yv, (const c32*)tw0, twy, *m.bi, m.hout, m.active, s));
+        // with a normalised input the epilogue's x is the stored bfloat16 vector
+        STEP(6, yx_inv_h2(g, Bh, m.npart ? m.vout : xv, yv, (const c32*)tw0, twy, *m.bi, m.hout,
+                          m.active, s));
         return hipSuccess;
       }
+      if (m.npart) return hipErrorInvalidValue;
       STEP(0, x_fwd_c<T>(g, xv, m.io32, A, tw0, *m.bi, m.active, s, m.hs[0]));
       STEP(1, y_pass_h2(g, Ah, Bh, twy, false, m.hs[1], m.active, s));
       STEP(2, z_pass_h2(g, Bh, (const cpx<h2>*)m.spec16, twz, m.hs[2], m.active, s));

@@ -79,6 +79,17 @@ struct MatvecArgs {
   const void* tw16[2] = {nullptr, nullptr};
   float hs[3] = {0.f, 0.f, 0.f};
   float hout = 0.f;
+  // Fused packed passes only (xy_fused_ok), with npart set: x is an FP32 work
+  // vector w; right-hand side q of it is scaled by 1 / ||w_q|| (||w_q||^2
+  // summed from the nblk partials npart[q nblk ..] in a fixed order and
+  // stored at nrm[q ldn]) and rounded to bfloat16, that vector is stored at
+  // vout (bfloat16) and multiplied: the normalisation of an Arnoldi step
+  // done inside the next product
+  const double* npart = nullptr;
+  int nblk = 0;
+  double* nrm = nullptr;
+  int ldn = 0;
+  void* vout = nullptr;
 };
 
 // precision 0: FP64 passes, 1: FP32 passes (input/output vectors are FP64)
