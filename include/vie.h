@@ -75,11 +75,15 @@ enum vie_status {
  * 1e-3 relative) leaves the preconditioner about as good while the basis
  * traffic halves; the FP64 outer residual still decides convergence.
  * Where the block grid allows it (16-layer z tiles, padded z length 32, 48,
- * 64, 96 or 128), the block products' z pass (z transforms and the Green
- * tensor product) also runs in packed FP16: the input is scaled by
- * 1/sqrt(padded length), the spectrum by a power of two that brings its
- * largest modulus into [1/2, 1), so no intermediate overflows; the FFT
- * passes around it and the results stay FP32. */
+ * 64, 96 or 128, and an even number of threads per x line), the block
+ * products' y and z transforms and the Green tensor product run in packed
+ * FP16 on FP16 scratch (two columns per register); the x transforms stay
+ * FP32 and convert at the scratch side, fused with the y transforms per z
+ * plane where the x and y lengths are 64, 96 or 128.  Each forward transform
+ * scales its input by a power of two at most 1/sqrt(extent), the spectrum by
+ * a power of two that brings its largest modulus into [1/2, 1), so no
+ * intermediate overflows for the unit-norm basis vectors the block solves
+ * multiply; the result is scaled back exactly in FP32. */
 enum { VIE_FP64 = 0, VIE_MIXED = 1, VIE_MIXED_BF16 = 2 };
 enum { VIE_NORM_R1 = 0, VIE_NORM_R2 = 1 };
 enum {
@@ -180,7 +184,7 @@ typedef struct {
   int32_t blocks[2];       /* bx, by: each 1..64 and at most N1 (N2); or {0, 0}    */
   int32_t inner_iters;     /* GMRES steps of every block solve, 1..64              */
   int32_t inner_precision; /* VIE_FP64 / VIE_MIXED: block products in FP64 / FP32; */
-                           /* VIE_MIXED_BF16: bfloat16 basis, FP16 z pass      */
+                           /* VIE_MIXED_BF16: bfloat16 basis, FP16 y/z passes  */
 } vie_fgmres_options;
 
 /* Solve like vie_solve (same channels, stats, solution storage and return

@@ -1143,9 +1143,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   }
 }
 
-// 8 points per thread (6 for 3 * 2^k lines), 512 threads: 64 column pairs
-// per workgroup; the packed data of three components stay within a register
-// budget that keeps several waves per SIMD.
+// 8 points per thread (6 for 3 * 2^k lines), 256 threads: 32 column pairs
+// per workgroup (256-byte row runs); the packed data of three components stay
+// within the 128-register cap (four 4-wave workgroups per CU).
 constexpr int kZH2Threads = 256;
 template <int P>
 constexpr int zh2_e() {
