@@ -254,14 +254,18 @@ __device__ __forceinline__ c64 conjc(c64 a) { return mk(a.re, -a.im); }
 __device__ __forceinline__ double cabs2(c64 a) { return hypot(a.re, a.im); }
 
 // Apply the previous j rotations to column j (col[0..j]), form the rotation
-// that annihilates the subdiagonal hn, update g; returns |g[j+1]|.
-__device__ double ls_add(int j, c64* col, double* cs, c64* sn, c64* g, double hn) {
+// that annihilates the subdiagonal hn, update g; returns |g[j+1]|.  The entry
+// each rotation hands to the next stays in a register, so the loads of the
+// rotations and of the column do not wait on the previous rotation's store.
+__device__ double ls_add(int j, c64* __restrict__ col, double* __restrict__ cs,
+                         c64* __restrict__ sn, c64* __restrict__ g, double hn) {
+  c64 carry = col[0];
   for (int i = 0; i < j; ++i) {
-    const c64 a = col[i], b = col[i + 1];
+    const c64 a = carry, b = col[i + 1];
     col[i] = cs[i] * a + sn[i] * b;
-    col[i + 1] = cs[i] * b - conjc(sn[i]) * a;
+    carry = cs[i] * b - conjc(sn[i]) * a;
   }
-  const c64 a = col[j];
+  const c64 a = carry;
   const double aa = cabs2(a);
   const double rho = hypot(aa, hn);
   double c;
@@ -286,7 +290,8 @@ __device__ double ls_add(int j, c64* col, double* cs, c64* sn, c64* g, double hn
 }
 
 // y[0..k) from R y = g (columns of R at stride ldr), written as -y into out.
-__device__ void ls_backsolve(int k, const c64* R, int ldr, const c64* g, c64* out) {
+__device__ void ls_backsolve(int k, const c64* __restrict__ R, int ldr, const c64* __restrict__ g,
+                             c64* __restrict__ out) {
   for (int i = k - 1; i >= 0; --i) {
     c64 t = g[i];
     for (int l = i + 1; l < k; ++l) t = t + R[(size_t)l * ldr + i] * out[l];  // out = -y
