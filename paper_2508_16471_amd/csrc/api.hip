@@ -203,7 +203,7 @@ struct BlockPrec {
   int64_t tot = 0;               // elements of all right-hand sides' vectors
   DevBuf qoff, qpoff, qlen;      // [rhs] vector offset, permutation offset, elements
   ArnoldiBufs ab;
-  DevBuf R, X;                   // permuted input, block solution
+  DevBuf R;                      // permuted input
   ~BlockPrec() {
     if (sub) vie_destroy(sub);
   }
@@ -1638,7 +1638,6 @@ static int bj_bind(vie_ctx* ctx, Group& G, BlockPrec& P, const std::vector<int>&
   VIE_HIP(hipMemcpyAsync(P.qlen.p, qlen.data(), nrhs * sizeof(int), hipMemcpyHostToDevice,
                          ctx->stream));
   VIE_HIP(P.R.reserve((size_t)std::max<int64_t>(tot, 1) * sizeof(c64)));
-  VIE_HIP(P.X.reserve((size_t)std::max<int64_t>(tot, 1) * sizeof(c64)));
   VIE_HIP(P.seg_rhs_dev.reserve((size_t)std::max(nseg, 1) * sizeof(int)));
   VIE_HIP(P.ones.reserve((size_t)std::max(nrhs, 1) * sizeof(int)));
   if (nseg > 0)
@@ -1702,15 +1701,15 @@ static int bj_apply(vie_ctx* ctx, BlockPrec& P, const vie_fgmres_options* fo, co
     VIE_HIP(timed(ctx, kArnoldiKind,
                   [&] { return arnoldi_orth(ctx, A, S, tot, k, j, eta2, nrm_in); }));
   }
-  // least squares of every block solve on the device, then X = V y
+  // least squares of every block solve on the device, then z = V y, written
+  // straight into the right-hand sides' vector order (every segment of an
+  // active right-hand side is active, and the blocks partition its body)
   VIE_HIP(launch_ls_full(nseg, k, A.H1.as<c64>(), A.H2.as<c64>(), eta2 > 0 ? 1 : 0, ldn, NR, ldn,
                          A.act.as<int>(), A.ls(), A.coef.as<c64>(), ldn, A.nvs.as<int>(),
                          ctx->stream));
-  VIE_HIP(launch_seg_lincomb(S, A.V.p, A.v32, tot, k, A.nvs.as<int>(), A.coef.as<c64>(), ldn,
-                             P.X.as<c64>(), ctx->stream));
-  VIE_HIP(launch_permute(nrhs, P.qoff.as<int64_t>(), P.qpoff.as<int64_t>(), P.qlen.as<int>(),
-                         P.maxqlen, P.perm.as<int>(), P.X.as<c64>(), 0, z, vz32, 1, act_rhs,
-                         ctx->stream));
+  VIE_HIP(launch_seg_lincomb_perm(S, A.V.p, A.v32, tot, k, A.nvs.as<int>(), A.coef.as<c64>(), ldn,
+                                  P.seg_rhs_dev.as<int>(), P.qoff.as<int64_t>(),
+                                  P.qpoff.as<int64_t>(), P.perm.as<int>(), z, vz32, ctx->stream));
   return VIE_OK;
 }
 
@@ -1911,7 +1910,7 @@ static int fgmres_group(vie_ctx* ctx, Group& G, BlockPrec* P, const vie_fgmres_o
     if (flex) {
       key_group(key, *P->sub->groups[0]);
       key_arnoldi(key, P->ab);
-      key_bufs(key, {&P->R, &P->X, &P->perm, &P->qoff, &P->qpoff, &P->qlen, &P->seg_rhs_dev});
+      key_bufs(key, {&P->R, &P->perm, &P->qoff, &P->qpoff, &P->qlen, &P->seg_rhs_dev});
       const int64_t pv[] = {P->nseg, P->tot, P->maxlen, P->maxqlen, (int64_t)P->bound_rb.size(),
                             fo->inner_iters, fo->inner_precision};
       for (int64_t v : pv) key.push_back((const void*)(intptr_t)v);

@@ -70,6 +70,14 @@ hipError_t launch_seg_lincomb(const SegSet& S, const void* V, int v32, int64_t s
                               const int* nv_seg, const c64* coef, int ldc, c64* x,
                               hipStream_t st);
 
+// The same combination scattered into the outer vectors' order: element e
+// of segment s (right-hand side q = seg_rhs[s]) goes to
+// dst[qoff[q] + perm[qpoff[q] + off[s] - qoff[q] + e]] (dst FP32 when d32).
+hipError_t launch_seg_lincomb_perm(const SegSet& S, const void* V, int v32, int64_t stride,
+                                   int nv, const int* nv_seg, const c64* coef, int ldc,
+                                   const int* seg_rhs, const int64_t* qoff, const int64_t* qpoff,
+                                   const int* perm, void* dst, int d32, hipStream_t st);
+
 // Permutation of each of nrep vectors (vector q: qlen[q] elements at qoff[q],
 // its permutation at perm + qpoff[q]; maxlen >= every qlen):
 //   gather  (scatter == 0): dst[qoff + j] = src[qoff + perm[j]]

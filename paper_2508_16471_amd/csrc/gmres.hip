@@ -221,6 +221,34 @@ __global__ __launch_bounds__(GT) void k_seg_lincomb(SegSet S, const TV* __restri
   }
 }
 
+// The same combination written straight into the outer vectors' order (the
+// permutation's scatter fused): element e of segment s, whose right-hand side
+// is q = seg_rhs[s], goes to dst[qoff[q] + perm[qpoff[q] + off[s] - qoff[q] + e]].
+template <typename TV, typename TD>
+__global__ __launch_bounds__(GT) void k_seg_lincomb_perm(
+    SegSet S, const TV* __restrict__ V, int64_t stride, int nv, const int* __restrict__ nv_seg,
+    const c64* __restrict__ coef, int ldc, const int* __restrict__ seg_rhs,
+    const int64_t* __restrict__ qoff, const int64_t* __restrict__ qpoff,
+    const int* __restrict__ perm, TD* __restrict__ dst) {
+  const int s = blockIdx.y, blk = blockIdx.x;
+  if (S.active && !S.active[s]) return;
+  const int64_t off = S.off[s];
+  const int len = S.len[s];
+  const int q = seg_rhs[s];
+  const int64_t qo = qoff[q];
+  const int* pm = perm + qpoff[q] + (off - qo);
+  int n = nv;
+  if (nv_seg) n = min(n, nv_seg[s]);
+  __shared__ c64 cf[kMaxVec];
+  for (int i = threadIdx.x; i < n; i += GT) cf[i] = coef[(int64_t)s * ldc + i];
+  __syncthreads();
+  for (int e = blk * GT + threadIdx.x; e < len; e += S.nblk * GT) {
+    c64 a = mk(0.0, 0.0);
+    for (int i = 0; i < n; ++i) a = a - cf[i] * ld64(V + (int64_t)i * stride + off + e);
+    st(dst + qo + pm[e], a);
+  }
+}
+
 __global__ void k_seg_act_map(int nseg, const int* __restrict__ seg_rhs,
                               const int* __restrict__ act_rhs, int* __restrict__ act_seg) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -506,6 +534,27 @@ hipError_t launch_permute(int nrep, const int64_t* qoff, const int64_t* qpoff, c
     k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c64*)src, (c32*)dst, scatter, act);
   else
     k_permute<<<grid, GT, 0, st>>>(qoff, qpoff, qlen, perm, (const c64*)src, (c64*)dst, scatter, act);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_lincomb_perm(const SegSet& S, const void* V, int v32, int64_t stride,
+                                   int nv, const int* nv_seg, const c64* coef, int ldc,
+                                   const int* seg_rhs, const int64_t* qoff, const int64_t* qpoff,
+                                   const int* perm, void* dst, int d32, hipStream_t st) {
+  if (S.nseg < 1) return hipSuccess;
+  if (nv < 0 || nv > kMaxVec) return hipErrorInvalidValue;
+  const dim3 grid(S.nblk, S.nseg);
+#define VIE_LCP(TV_, TD_)                                                                       \
+  k_seg_lincomb_perm<<<grid, GT, 0, st>>>(S, (const TV_*)V, stride, nv, nv_seg, coef, ldc,      \
+                                          seg_rhs, qoff, qpoff, perm, (TD_*)dst)
+  if (v32 == 2) {
+    if (d32) VIE_LCP(cb16, c32); else VIE_LCP(cb16, c64);
+  } else if (v32) {
+    if (d32) VIE_LCP(c32, c32); else VIE_LCP(c32, c64);
+  } else {
+    if (d32) VIE_LCP(c64, c32); else VIE_LCP(c64, c64);
+  }
+#undef VIE_LCP
   return hipGetLastError();
 }
 
