@@ -20,6 +20,10 @@ conv_ref   Plain 3-D convolution forward/backward (learned warm start).
 detect     Finite-aperture detectors: cone quadrature of the far field.
 precond    Block-Jacobi preconditioner on a lateral partition, k-step GMRES
            block solves, restarted flexible GMRES.
+selfterm   Exact-cube self term (the voxel's own singular integral).
+rooftop    Rooftop basis with pulse testing (eq. Js_expand): face unknowns on
+           the staggered grids, surface half-rooftops, dense operator, LU
+           solve and far field.
 
 Every function states the passage of the paper it follows.  Functions with
 no independent pin say "parity unpinned" in their docstring (none at
