@@ -257,6 +257,60 @@ int vie_grid(vie_ctx *ctx, int32_t body, int32_t *grid, int32_t *fft, int32_t *o
  * header.  VIE_EINVAL for another kind or non-positive / non-finite k0, h. */
 int vie_self_term(int32_t kind, double k0, double h, vie_c64 *s);
 
+/* ---------------------------------------------------------------------------
+ * Rooftop basis with pulse testing (Sec. II-C, eq. Js_expand), FP64: the
+ * paper's own discretisation, beside the pulse-basis operator above.
+ *   Unknown w = chi E, component i expanded in rooftops on the faces normal
+ *   to i of the body grid padded by one cell per side ("padded grid", E =
+ *   n + 2 cells per axis; padded cell c is centred at origin + h (c - 1)).
+ *   A face is active if one of its two cells is a body cell (eps_r != 1):
+ *   between two body cells it carries a full rooftop (weight alpha = 1), on
+ *   the body surface the inside half (alpha = 1/2).  Charge per cell
+ *   rho = div w; E_sca = k0^2 A + grad phi, A = g * w, phi = g * rho,
+ *   g = e^{i k0 r} / (4 pi r), collocated at face centres: midpoint weights
+ *   h^3 alpha (rooftop) and h^3 (cell), the integral of g over the cube cell
+ *   for a rooftop's and a cell's own term; grad phi = difference of the
+ *   face's two cell potentials over h.  At an active face
+ *       W - chi_f (k0^2 A_i + grad_i phi) = chi_f e_i(r_f),
+ *   1/chi_f = the mean of 1/chi over the face's body sides.
+ *   Far field (eq. 25, the normalisation above):
+ *       F(r) = k0^2 h^3 / (4 pi) (I - r r) sum_faces alpha W_i e_i e^{-i k0 r . r_f}.
+ * Vectors: [component 0..2][z][y][x] over the padded grid, 3 E1 E2 E3
+ * vie_c64 each; entry c of component i is the face between padded cells c
+ * and c + e_i (r_f = centre of c + (h/2) e_i).  Entries of inactive faces are
+ * ignored on input (they do not couple) and passed through by the product
+ * (y = x there); solutions are zero there.  Host arrays, caller-owned. */
+typedef struct vie_rt vie_rt;
+
+/* Build the operator of one body (n: 1..128 per axis, VIE_ENOTSUP above;
+ * eps_r as vie_body) at wavenumber k0: face data, the spectrum of the scalar
+ * kernel's circulant (length P >= 2 E - 1 per axis), solver storage (about
+ * 6 P1 P2 P3 + 40 E1 E2 E3 doubles).  VIE_EINVAL on bad values. */
+int vie_rt_setup(const vie_body *body, double k0, vie_rt **out);
+
+/* Padded grid E[3] and circulant lengths P[3]; either may be NULL. */
+int vie_rt_grid(const vie_rt *rt, int32_t *ext, int32_t *fft);
+
+/* y = A x for nvec vectors (layout above). */
+int vie_rt_matvec(vie_rt *rt, const vie_c64 *x, vie_c64 *y, int32_t nvec);
+
+/* Solve for nrhs plane-wave channels (b = chi_f e(r_f)) with BiCGSTAB from
+ * w = 0, restarted from the true residual when the recursive one reaches tol;
+ * the true residual ||b - A w|| / ||b|| <= tol decides.  w: nrhs vectors.
+ * stats (nullable, one per channel): iters, matvecs, cycles, converged,
+ * rel_res; seconds = host wall time of the channel's solve (0 if not
+ * converged).  VIE_ENOCONV if a channel missed tol in max_iter iterations
+ * (its best iterate is still returned). */
+int vie_rt_solve(vie_rt *rt, const vie_planewave *inc, int32_t nrhs, double tol,
+                 int32_t max_iter, vie_c64 *w, vie_stats *stats);
+
+/* Far field of nrhs solutions w at ndir directions, laid out as vie_farfield:
+ * F[(rhs * ndir + d) * 2 + {0,1}] = (F_theta, F_phi). */
+int vie_rt_farfield(vie_rt *rt, const vie_c64 *w, int32_t nrhs, const double *theta,
+                    const double *phi, int32_t ndir, vie_c64 *F);
+
+void vie_rt_destroy(vie_rt *rt);
+
 /* Classical comparison observable (eq. 27): for deterministic fields, the
  * product of the two detectors' intensities of the coherent superposition of
  * both channels' responses, P2 = |T_a1 + T_a2|^2 |T_b1 + T_b2|^2 (T ordered

@@ -190,3 +190,51 @@ def farfield_vec(chi, h, origin, k0, w, rhat):
         S[:, i] = ph @ (alpha[i][m] * w[i][m])
     S = S - rhat * np.einsum("dc,dc->d", rhat, S)[:, None]
     return (k0 * k0 * h**3 / FOUR_PI) * S
+
+
+def matvec_rows(chi, h, origin, k0, x, rows):
+    """Rows of the full-layout product y = x - chi_f (k0^2 A + grad phi),
+    summing directly over every active face and every charged cell (O(M) per
+    row, for grids too large for the dense matrix).  rows: flat full-layout
+    indices (comp * M + cell) of active faces."""
+    X = extended_chi(chi)
+    n3, n2, n1 = X.shape
+    M = n1 * n2 * n3
+    active, alpha, chif, pos = face_data(chi, h, origin)
+    W = np.where(active, np.asarray(x, complex).reshape(3, M), 0.0)
+    I = cube_integral(k0, h)
+    # cell charges: + face of the cell minus its - face, per component
+    Wg = W.reshape(3, n3, n2, n1)
+    rho = np.zeros((n3, n2, n1), complex)
+    for i in range(3):
+        ax = 2 - i
+        lower = np.zeros_like(Wg[i])
+        sl_dst = [slice(None)] * 3
+        sl_src = [slice(None)] * 3
+        sl_dst[ax] = slice(1, None)
+        sl_src[ax] = slice(0, -1)
+        lower[tuple(sl_dst)] = Wg[i][tuple(sl_src)]
+        rho += (Wg[i] - lower) / h
+    rho = rho.ravel()
+    z, y, xx = np.meshgrid(np.arange(n3), np.arange(n2), np.arange(n1), indexing="ij")
+    cen = np.stack([origin[0] + h * (xx - 1), origin[1] + h * (y - 1), origin[2] + h * (z - 1)],
+                   -1).reshape(M, 3)
+    qc = np.nonzero(rho != 0)[0]
+    step = np.array([1, n1, n1 * n2])
+
+    def pot(points, src_pos, src_val):
+        return (_scalar_green(points, src_pos, h, k0, I) @ src_val) if len(src_val) else \
+            np.zeros(len(points), complex)
+
+    rows = np.asarray(rows, dtype=np.int64)
+    out = np.zeros(len(rows), complex)
+    xf = np.asarray(x, complex).ravel()
+    for k, f in enumerate(rows):
+        i, c = int(f // M), int(f % M)
+        src = np.nonzero(active[i])[0]
+        A = pot(pos[i][c][None, :], pos[i][src], alpha[i][src] * W[i][src])[0]
+        lo_hi = np.stack([cen[c], cen[c + step[i]]])
+        phi = pot(lo_hi, cen[qc], rho[qc])
+        Es = k0 * k0 * A + (phi[1] - phi[0]) / h
+        out[k] = xf[f] - chif[i][c] * Es
+    return out

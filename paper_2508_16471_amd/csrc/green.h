@@ -12,6 +12,10 @@ void self_term_sphere(double k0, double h, double* re, double* im);
 // e^{i k0 r} / (4 pi r) over the voxel (edge h) about its centre.
 void self_term_cube(double k0, double h, double* re, double* im);
 
+// The integral of e^{i k0 r} / (4 pi r) over the cube of edge h about its
+// centre (the cell's own potential coefficient of the rooftop operator).
+void cube_green_integral(double k0, double h, double* re, double* im);
+
 // launch_green_sample with a given self term s (diagonal samples xx, yy, zz).
 hipError_t launch_green_sample_self(c64* work, const GroupGeom& g, int ab, double h, double k0,
                                     double s_re, double s_im, hipStream_t s);

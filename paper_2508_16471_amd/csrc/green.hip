@@ -129,7 +129,7 @@ static void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>&
   }
 }
 
-void self_term_cube(double k0, double h, double* re, double* im) {
+void cube_green_integral(double k0, double h, double* re, double* im) {
   const double c = 0.5 * h;
   std::vector<double> x, w;
   gauss_legendre01(40, x, w);
@@ -154,10 +154,17 @@ void self_term_cube(double k0, double h, double* re, double* im) {
       sr += wt * fr;
       si += wt * fi;
     }
-  // six faces x four quarters, 1 / (4 pi), radial integral / k0^2, times 2 k0^2 / 3
-  const double f = 24.0 / (4.0 * M_PI) * (2.0 / 3.0);
-  *re = -1.0 / 3.0 + f * sr;
+  // six faces x four quarters, 1 / (4 pi), radial integral / k0^2
+  const double f = 24.0 / (4.0 * M_PI) / (k0 * k0);
+  *re = f * sr;
   *im = f * si;
+}
+
+void self_term_cube(double k0, double h, double* re, double* im) {
+  double ir, ii;
+  cube_green_integral(k0, h, &ir, &ii);
+  *re = -1.0 / 3.0 + (2.0 * k0 * k0 / 3.0) * ir;
+  *im = (2.0 * k0 * k0 / 3.0) * ii;
 }
 
 void self_term_sphere(double k0, double h, double* re, double* im) {

@@ -1,0 +1,701 @@
+// Rooftop basis with pulse testing (Sec. II-C, eq. Js_expand), FP64.
+//
+// The paper expands the current in rooftops along x, y and z on the uniform
+// grid and tests with pulses.  Reading taken (entries and the body surface
+// are not given): the contrast current w = chi E, component i carried by
+// rooftops on the faces normal to i, a full rooftop between two body cells,
+// the inside half on the body surface (alpha = 1 or 1/2); the charge
+// rho = div w is constant per cell, a surface face's sheet charge carried by
+// its outside cell; E_sca = k0^2 A + grad phi with A = g * w, phi = g * rho,
+// both collocated at face centres, midpoint weights h^3 alpha (a rooftop) and
+// h^3 (a cell) off the diagonal and the cube-cell integral of g on it; grad
+// phi across a face is the difference of its two cells' potentials over h;
+// at a face E = W / chi_f with 1/chi_f the mean of its body sides' 1/chi.
+//
+// The grid is the body grid padded by one cell on every side, so every
+// active face has both of its cells on the grid.  A and phi are four scalar
+// convolutions with the same kernel h^3 g (self: the cube integral) over the
+// padded grid: its circulant (length P >= 2 E - 1 per axis) is transformed
+// once at setup, each product transforms alpha W_x, alpha W_y, alpha W_z and
+// rho forward, multiplies by the spectrum and transforms back (the inverse as
+// the conjugate of the forward transform of the conjugate).  The solver is
+// BiCGSTAB (the paper's method) with the true residual deciding convergence.
+#include <math.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "../../include/vie.h"
+#include "green.h"
+#include "kernels.h"
+
+namespace vie {
+
+// Circulant length of an axis of n cells: the smallest supported transform
+// length (2^k >= 8 or 3 * 2^k >= 12) with P >= 2 n - 1.
+static int rt_fft_length(int n) {
+  const int need = std::max(8, 2 * n - 1);
+  int p2 = 8, p3 = 12;
+  while (p2 < need) p2 <<= 1;
+  while (p3 < need) p3 <<= 1;
+  return std::min(p2, p3);
+}
+
+struct RtGeom {
+  int E[3];   // padded grid (body grid + 2)
+  int P[3];   // circulant lengths
+  int64_t m;  // E1 E2 E3
+  int64_t M;  // P1 P2 P3
+};
+
+// Circulant samples of h^3 e^{i k0 r} / (4 pi r) over displacements
+// [-(E-1), E-1] per axis at index d mod P, zero elsewhere; the cube integral
+// at d = 0.
+__global__ void k_rt_green(c64* __restrict__ work, RtGeom q, double h, double k0, double s_re,
+                           double s_im) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < q.M;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int idx[3] = {(int)(e % q.P[0]), (int)((e / q.P[0]) % q.P[1]),
+                        (int)(e / ((int64_t)q.P[0] * q.P[1]))};
+    int d[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+      if (idx[a] <= q.E[a] - 1)
+        d[a] = idx[a];
+      else if (idx[a] >= q.P[a] - (q.E[a] - 1))
+        d[a] = idx[a] - q.P[a];
+      else
+        ok = false;
+    }
+    c64 v = mk(0.0, 0.0);
+    if (ok) {
+      if (d[0] == 0 && d[1] == 0 && d[2] == 0) {
+        v = mk(s_re, s_im);
+      } else {
+        const double r = h * sqrt((double)d[0] * d[0] + (double)d[1] * d[1] + (double)d[2] * d[2]);
+        double sn, cs;
+        sincos(k0 * r, &sn, &cs);
+        const double f = h * h * h / (4.0 * M_PI * r);
+        v = mk(f * cs, f * sn);
+      }
+    }
+    work[e] = v;
+  }
+}
+
+__global__ void k_rt_scale(const c64* __restrict__ in, c64* __restrict__ out, int64_t M,
+                           double s) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = s * in[e];
+}
+
+// One input field of the product on the circulant grid: f < 3 the weighted
+// current alpha W_f, f = 3 the cell charge rho; zero outside the padded grid.
+// Inactive faces (alpha = 0) contribute nothing.
+__global__ void k_rt_gather(const c64* __restrict__ x, const double* __restrict__ alpha,
+                            c64* __restrict__ work, RtGeom q, int f, double inv_h) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < q.M;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int px = (int)(e % q.P[0]);
+    const int py = (int)((e / q.P[0]) % q.P[1]);
+    const int pz = (int)(e / ((int64_t)q.P[0] * q.P[1]));
+    c64 v = mk(0.0, 0.0);
+    if (px < q.E[0] && py < q.E[1] && pz < q.E[2]) {
+      const int64_t c = ((int64_t)pz * q.E[1] + py) * q.E[0] + px;
+      if (f < 3) {
+        const double a = alpha[f * q.m + c];
+        v = a * x[f * q.m + c];
+      } else {
+        const int pc[3] = {px, py, pz};
+        const int64_t step[3] = {1, q.E[0], (int64_t)q.E[0] * q.E[1]};
+        for (int i = 0; i < 3; ++i) {
+          const int64_t o = i * q.m + c;
+          if (alpha[o] != 0.0) v = v + x[o];  // + face of the cell
+          if (pc[i] > 0 && alpha[o - step[i]] != 0.0) v = v - x[o - step[i]];  // - face
+        }
+        v = inv_h * v;
+      }
+    }
+    work[e] = v;
+  }
+}
+
+// work = conj(spectrum * ghat)
+__global__ void k_rt_mulconj(const c64* __restrict__ in, const c64* __restrict__ ghat,
+                             c64* __restrict__ out, int64_t M) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const c64 p = in[e] * ghat[e];
+    out[e] = mk(p.re, -p.im);
+  }
+}
+
+// R[c] = conj(tmp) over the padded grid (the inverse transform's result).
+__global__ void k_rt_store(const c64* __restrict__ tmp, c64* __restrict__ R, RtGeom q) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < q.m;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(c % q.E[0]);
+    const int y = (int)((c / q.E[0]) % q.E[1]);
+    const int z = (int)(c / ((int64_t)q.E[0] * q.E[1]));
+    const c64 v = tmp[((int64_t)z * q.P[1] + y) * q.P[0] + x];
+    R[c] = mk(v.re, -v.im);
+  }
+}
+
+// y = x - chi_f (k0^2 A_i + (phi(c + e_i) - phi(c)) / h) on active faces,
+// y = x on the others.  R holds A_x, A_y, A_z, phi (m each).
+__global__ void k_rt_epilogue(const c64* __restrict__ x, const c64* __restrict__ R,
+                              const double* __restrict__ chif, c64* __restrict__ y, RtGeom q,
+                              double k0sq, double inv_h) {
+  const int64_t step[3] = {1, q.E[0], (int64_t)q.E[0] * q.E[1]};
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 3 * q.m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double cf = chif[e];
+    if (cf == 0.0) {
+      y[e] = x[e];
+      continue;
+    }
+    const int i = (int)(e / q.m);
+    const int64_t c = e - i * q.m;
+    // an active face has its upper cell on the padded grid (c + e_i < m)
+    const c64 grad = inv_h * (R[3 * q.m + c + step[i]] - R[3 * q.m + c]);
+    const c64 Es = k0sq * R[e] + grad;
+    y[e] = x[e] - cf * Es;
+  }
+}
+
+// b = chi_f pol_i e^{i k0 khat . r_f}, face i of padded cell c at
+// origin + h (c - 1) + (h/2) e_i.
+__global__ void k_rt_rhs(c64* __restrict__ b, const double* __restrict__ chif, RtGeom q, double h,
+                         double o0, double o1, double o2, double k0, double kx, double ky,
+                         double kz, c64 p0, c64 p1, c64 p2) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 3 * q.m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double cf = chif[e];
+    if (cf == 0.0) {
+      b[e] = mk(0.0, 0.0);
+      continue;
+    }
+    const int i = (int)(e / q.m);
+    const int64_t c = e - i * q.m;
+    double r[3] = {o0 + h * ((int)(c % q.E[0]) - 1), o1 + h * ((int)((c / q.E[0]) % q.E[1]) - 1),
+                   o2 + h * ((int)(c / ((int64_t)q.E[0] * q.E[1])) - 1)};
+    r[i] += 0.5 * h;
+    double sn, cs;
+    sincos(k0 * (kx * r[0] + ky * r[1] + kz * r[2]), &sn, &cs);
+    const c64 pol = i == 0 ? p0 : (i == 1 ? p1 : p2);
+    b[e] = cf * (pol * mk(cs, sn));
+  }
+}
+
+constexpr int kRtThreads = 256;
+constexpr int kRtDotBlocks = 256;
+
+// Per-block partial sums of conj(a) . b (fixed reduction order).
+__global__ void __launch_bounds__(kRtThreads) k_rt_dot(const c64* __restrict__ a,
+                                                       const c64* __restrict__ b, int64_t n,
+                                                       c64* __restrict__ part) {
+  __shared__ double sr[kRtThreads], si[kRtThreads];
+  double re = 0.0, im = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const c64 p = cmulc(a[e], b[e]);
+    re += p.re;
+    im += p.im;
+  }
+  sr[threadIdx.x] = re;
+  si[threadIdx.x] = im;
+  __syncthreads();
+  for (int s = kRtThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = mk(sr[0], si[0]);
+}
+
+// out = a + ca b + cc c (c nullable)
+__global__ void k_rt_lin(c64* __restrict__ out, const c64* __restrict__ a, c64 cb,
+                         const c64* __restrict__ b, c64 cc, const c64* __restrict__ c, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    c64 v = cfma(cb, b[e], a[e]);
+    if (c) v = cfma(cc, c[e], v);
+    out[e] = v;
+  }
+}
+
+// Far field of eq. 25: one workgroup per (right-hand side, direction),
+// S = sum_faces alpha W_i e_i e^{-i k0 r . r_f}, F = k0^2 h^3 / (4 pi) (t . S, p . S).
+__global__ void __launch_bounds__(kRtThreads) k_rt_far(const c64* __restrict__ w,
+                                                       const double* __restrict__ alpha, RtGeom q,
+                                                       double h, double o0, double o1, double o2,
+                                                       double k0, const double* __restrict__ th,
+                                                       const double* __restrict__ ph, int ndir,
+                                                       c64* __restrict__ F) {
+  const int d = blockIdx.x % ndir;
+  const int rhs = blockIdx.x / ndir;
+  const c64* W = w + (int64_t)rhs * 3 * q.m;
+  double st, ct, sp, cp;
+  sincos(th[d], &st, &ct);
+  sincos(ph[d], &sp, &cp);
+  const double rh[3] = {st * cp, st * sp, ct};
+  __shared__ double red[6][kRtThreads];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t e = threadIdx.x; e < 3 * q.m; e += blockDim.x) {
+    const double a = alpha[e];
+    if (a == 0.0) continue;
+    const int i = (int)(e / q.m);
+    const int64_t c = e - i * q.m;
+    double r[3] = {o0 + h * ((int)(c % q.E[0]) - 1), o1 + h * ((int)((c / q.E[0]) % q.E[1]) - 1),
+                   o2 + h * ((int)(c / ((int64_t)q.E[0] * q.E[1])) - 1)};
+    r[i] += 0.5 * h;
+    double sn, cs;
+    sincos(-k0 * (rh[0] * r[0] + rh[1] * r[1] + rh[2] * r[2]), &sn, &cs);
+    const c64 v = a * (W[e] * mk(cs, sn));
+    acc[2 * i] += v.re;
+    acc[2 * i + 1] += v.im;
+  }
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = kRtThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double tv[3] = {ct * cp, ct * sp, -st};
+    const double pv[3] = {-sp, cp, 0.0};
+    const double C = k0 * k0 * h * h * h / (4.0 * M_PI);
+    double ftr = 0, fti = 0, fpr = 0, fpi = 0;
+    for (int i = 0; i < 3; ++i) {
+      ftr += tv[i] * red[2 * i][0];
+      fti += tv[i] * red[2 * i + 1][0];
+      fpr += pv[i] * red[2 * i][0];
+      fpi += pv[i] * red[2 * i + 1][0];
+    }
+    F[((int64_t)rhs * ndir + d) * 2 + 0] = mk(C * ftr, C * fti);
+    F[((int64_t)rhs * ndir + d) * 2 + 1] = mk(C * fpr, C * fpi);
+  }
+}
+
+}  // namespace vie
+
+using namespace vie;
+
+struct vie_rt {
+  int N[3] = {0, 0, 0};
+  double h = 0, k0 = 0, origin[3] = {0, 0, 0};
+  RtGeom q{};
+  GroupGeom g{};
+  hipStream_t stream = nullptr;
+  bool poisoned = false;
+  double* alpha = nullptr;  // [3][m]
+  double* chif = nullptr;   // [3][m]
+  c64* ghat = nullptr;      // [M] spectrum / M
+  c64* tw[3] = {nullptr, nullptr, nullptr};
+  c64* work = nullptr;  // [M]
+  c64* tmp = nullptr;   // [M]
+  c64* R = nullptr;     // [4][m]
+  c64* vec[9] = {};     // solver vectors [3m] each
+  c64* part = nullptr;  // dot partials
+  std::vector<c64> hpart;
+};
+
+namespace {
+
+constexpr int kRtMaxN = 128;
+
+int blocks_for(int64_t n) {
+  int64_t b = (n + kRtThreads - 1) / kRtThreads;
+  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 4096);
+}
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+void rt_free(vie_rt* r) {
+  auto f = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  f(r->alpha);
+  f(r->chif);
+  f(r->ghat);
+  for (auto* t : r->tw) f(t);
+  f(r->work);
+  f(r->tmp);
+  f(r->R);
+  for (auto* v : r->vec) f(v);
+  f(r->part);
+  if (r->stream) (void)hipStreamDestroy(r->stream);
+}
+
+#define RT_HIP(call)                 \
+  do {                               \
+    hipError_t e_ = (call);          \
+    if (e_ != hipSuccess) {          \
+      r->poisoned = true;            \
+      return VIE_EDEVICE;            \
+    }                                \
+  } while (0)
+
+// y = A x for one full-layout vector (device pointers).
+int rt_apply(vie_rt* r, const c64* x, c64* y) {
+  const RtGeom& q = r->q;
+  const void* tw[3] = {r->tw[0], r->tw[1], r->tw[2]};
+  const double inv_h = 1.0 / r->h;
+  for (int f = 0; f < 4; ++f) {
+    k_rt_gather<<<blocks_for(q.M), kRtThreads, 0, r->stream>>>(x, r->alpha, r->work, q, f, inv_h);
+    RT_HIP(hipGetLastError());
+    RT_HIP(launch_fft3d_full(r->work, r->tmp, r->g, tw, r->stream));
+    k_rt_mulconj<<<blocks_for(q.M), kRtThreads, 0, r->stream>>>(r->tmp, r->ghat, r->work, q.M);
+    RT_HIP(hipGetLastError());
+    RT_HIP(launch_fft3d_full(r->work, r->tmp, r->g, tw, r->stream));
+    k_rt_store<<<blocks_for(q.m), kRtThreads, 0, r->stream>>>(r->tmp, r->R + f * q.m, q);
+    RT_HIP(hipGetLastError());
+  }
+  k_rt_epilogue<<<blocks_for(3 * q.m), kRtThreads, 0, r->stream>>>(x, r->R, r->chif, y, q,
+                                                                   r->k0 * r->k0, inv_h);
+  RT_HIP(hipGetLastError());
+  return VIE_OK;
+}
+
+// conj(a) . b over n entries (synchronous).
+int rt_dot(vie_rt* r, const c64* a, const c64* b, int64_t n, c64* out) {
+  k_rt_dot<<<kRtDotBlocks, kRtThreads, 0, r->stream>>>(a, b, n, r->part);
+  RT_HIP(hipGetLastError());
+  RT_HIP(hipMemcpyAsync(r->hpart.data(), r->part, kRtDotBlocks * sizeof(c64),
+                        hipMemcpyDeviceToHost, r->stream));
+  RT_HIP(hipStreamSynchronize(r->stream));
+  c64 s = mk(0.0, 0.0);
+  for (int k = 0; k < kRtDotBlocks; ++k) s = s + r->hpart[k];
+  *out = s;
+  return VIE_OK;
+}
+
+int rt_lin(vie_rt* r, c64* out, const c64* a, c64 cb, const c64* b, c64 cc, const c64* c,
+           int64_t n) {
+  k_rt_lin<<<blocks_for(n), kRtThreads, 0, r->stream>>>(out, a, cb, b, cc, c, n);
+  RT_HIP(hipGetLastError());
+  return VIE_OK;
+}
+
+c64 cdiv(c64 a, c64 b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return mk((a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d);
+}
+
+#define RT_TRY(call)          \
+  do {                        \
+    int rc_ = (call);         \
+    if (rc_ != VIE_OK) return rc_; \
+  } while (0)
+
+}  // namespace
+
+extern "C" int vie_rt_setup(const vie_body* body, double k0, vie_rt** out) {
+  if (!out) return VIE_EINVAL;
+  *out = nullptr;
+  if (!body || !body->eps_r || !(body->h > 0) || !std::isfinite(body->h) || !(k0 > 0) ||
+      !std::isfinite(k0))
+    return VIE_EINVAL;
+  for (int a = 0; a < 3; ++a) {
+    if (body->n[a] < 1) return VIE_EINVAL;
+    if (!std::isfinite(body->origin[a])) return VIE_EINVAL;
+  }
+  for (int a = 0; a < 3; ++a)
+    if (body->n[a] > kRtMaxN) return VIE_ENOTSUP;
+  const int64_t nvox = (int64_t)body->n[0] * body->n[1] * body->n[2];
+  for (int64_t v = 0; v < nvox; ++v)
+    if (!std::isfinite(body->eps_r[v]) || body->eps_r[v] < 1.0) return VIE_EINVAL;
+
+  vie_rt* r = new (std::nothrow) vie_rt();
+  if (!r) return VIE_ENOMEM;
+  for (int a = 0; a < 3; ++a) {
+    r->N[a] = body->n[a];
+    r->origin[a] = body->origin[a];
+    r->q.E[a] = body->n[a] + 2;
+    r->q.P[a] = rt_fft_length(r->q.E[a]);
+    r->g.N[a] = r->q.E[a];
+    r->g.P[a] = r->q.P[a];
+    r->g.Q[a] = r->q.P[a] / 2 + 1;
+  }
+  r->h = body->h;
+  r->k0 = k0;
+  const RtGeom& q = r->q;
+  r->q.m = (int64_t)q.E[0] * q.E[1] * q.E[2];
+  r->q.M = (int64_t)q.P[0] * q.P[1] * q.P[2];
+  r->g.n = r->q.m;
+  r->g.nrhs = 1;
+  const int64_t m = r->q.m, M = r->q.M;
+
+  // face data: chi on the padded grid, then alpha and chi_f per face
+  std::vector<double> chi(m, 0.0), alpha(3 * m, 0.0), chif(3 * m, 0.0);
+  for (int z = 0; z < r->N[2]; ++z)
+    for (int y = 0; y < r->N[1]; ++y)
+      for (int x = 0; x < r->N[0]; ++x)
+        chi[((int64_t)(z + 1) * q.E[1] + (y + 1)) * q.E[0] + (x + 1)] =
+            body->eps_r[((int64_t)z * r->N[1] + y) * r->N[0] + x] - 1.0;
+  const int64_t step[3] = {1, q.E[0], (int64_t)q.E[0] * q.E[1]};
+  for (int i = 0; i < 3; ++i)
+    for (int z = 0; z < q.E[2]; ++z)
+      for (int y = 0; y < q.E[1]; ++y)
+        for (int x = 0; x < q.E[0]; ++x) {
+          const int pc[3] = {x, y, z};
+          const int64_t c = ((int64_t)z * q.E[1] + y) * q.E[0] + x;
+          const double ca = chi[c];
+          const double cb = pc[i] + 1 < q.E[i] ? chi[c + step[i]] : 0.0;
+          double a = 0.0, cf = 0.0;
+          if (ca != 0.0 && cb != 0.0) {
+            a = 1.0;
+            cf = 1.0 / (0.5 * (1.0 / ca + 1.0 / cb));
+          } else if (ca != 0.0) {
+            a = 0.5;
+            cf = ca;
+          } else if (cb != 0.0) {
+            a = 0.5;
+            cf = cb;
+          }
+          alpha[i * m + c] = a;
+          chif[i * m + c] = cf;
+        }
+
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  chk(hipStreamCreate(&r->stream));
+  chk(dalloc(&r->alpha, 3 * m));
+  chk(dalloc(&r->chif, 3 * m));
+  chk(dalloc(&r->ghat, M));
+  chk(dalloc(&r->work, M));
+  chk(dalloc(&r->tmp, M));
+  chk(dalloc(&r->R, 4 * m));
+  for (auto& v : r->vec) chk(dalloc(&v, 3 * m));
+  chk(dalloc(&r->part, kRtDotBlocks));
+  for (int a = 0; a < 3; ++a) chk(dalloc(&r->tw[a], q.P[a]));
+  if (e != hipSuccess) {
+    rt_free(r);
+    delete r;
+    return e == hipErrorOutOfMemory ? VIE_ENOMEM : VIE_EDEVICE;
+  }
+  r->hpart.resize(kRtDotBlocks);
+  for (int a = 0; a < 3; ++a) {
+    std::vector<c64> t(q.P[a]);
+    for (int k = 0; k < q.P[a]; ++k) {
+      const long double ang = -2.0L * 3.14159265358979323846264338327950288L * k / q.P[a];
+      t[k] = mk((double)cosl(ang), (double)sinl(ang));
+    }
+    chk(hipMemcpy(r->tw[a], t.data(), q.P[a] * sizeof(c64), hipMemcpyHostToDevice));
+  }
+  chk(hipMemcpy(r->alpha, alpha.data(), 3 * m * sizeof(double), hipMemcpyHostToDevice));
+  chk(hipMemcpy(r->chif, chif.data(), 3 * m * sizeof(double), hipMemcpyHostToDevice));
+  double s_re, s_im;
+  cube_green_integral(k0, r->h, &s_re, &s_im);
+  const void* tw[3] = {r->tw[0], r->tw[1], r->tw[2]};
+  if (e == hipSuccess) {
+    k_rt_green<<<blocks_for(M), kRtThreads, 0, r->stream>>>(r->work, q, r->h, k0, s_re, s_im);
+    chk(hipGetLastError());
+  }
+  if (e == hipSuccess) chk(launch_fft3d_full(r->work, r->tmp, r->g, tw, r->stream));
+  if (e == hipSuccess) {
+    k_rt_scale<<<blocks_for(M), kRtThreads, 0, r->stream>>>(r->tmp, r->ghat, M, 1.0 / (double)M);
+    chk(hipGetLastError());
+  }
+  if (e == hipSuccess) chk(hipStreamSynchronize(r->stream));
+  if (e != hipSuccess) {
+    rt_free(r);
+    delete r;
+    return VIE_EDEVICE;
+  }
+  *out = r;
+  return VIE_OK;
+}
+
+extern "C" int vie_rt_grid(const vie_rt* r, int32_t* ext, int32_t* fft) {
+  if (!r) return VIE_EINVAL;
+  for (int a = 0; a < 3; ++a) {
+    if (ext) ext[a] = r->q.E[a];
+    if (fft) fft[a] = r->q.P[a];
+  }
+  return VIE_OK;
+}
+
+extern "C" int vie_rt_matvec(vie_rt* r, const vie_c64* x, vie_c64* y, int32_t nvec) {
+  if (!r || !x || !y || nvec < 1) return VIE_EINVAL;
+  if (r->poisoned) return VIE_ESTATE;
+  const int64_t n = 3 * r->q.m;
+  for (int v = 0; v < nvec; ++v) {
+    RT_HIP(hipMemcpyAsync(r->vec[0], x + v * n, n * sizeof(c64), hipMemcpyHostToDevice,
+                          r->stream));
+    RT_TRY(rt_apply(r, r->vec[0], r->vec[1]));
+    RT_HIP(hipMemcpyAsync(y + v * n, r->vec[1], n * sizeof(c64), hipMemcpyDeviceToHost,
+                          r->stream));
+    RT_HIP(hipStreamSynchronize(r->stream));
+  }
+  return VIE_OK;
+}
+
+extern "C" int vie_rt_solve(vie_rt* r, const vie_planewave* inc, int32_t nrhs, double tol,
+                            int32_t max_iter, vie_c64* w, vie_stats* stats) {
+  if (!r || !inc || !w || nrhs < 1 || !(tol > 0) || !(tol < 1) || max_iter < 1)
+    return VIE_EINVAL;
+  if (r->poisoned) return VIE_ESTATE;
+  for (int k = 0; k < nrhs; ++k)
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(inc[k].khat[a]) || !std::isfinite(inc[k].pol[a].re) ||
+          !std::isfinite(inc[k].pol[a].im))
+        return VIE_EINVAL;
+  const RtGeom& q = r->q;
+  const int64_t n = 3 * q.m;
+  c64 *x = r->vec[0], *b = r->vec[1], *rr = r->vec[2], *rh = r->vec[3], *p = r->vec[4],
+      *v = r->vec[5], *s = r->vec[6], *t = r->vec[7];
+  const c64 one = mk(1.0, 0.0), zero = mk(0.0, 0.0);
+  int status = VIE_OK;
+  for (int k = 0; k < nrhs; ++k) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const vie_planewave& pw = inc[k];
+    k_rt_rhs<<<blocks_for(n), kRtThreads, 0, r->stream>>>(
+        b, r->chif, q, r->h, r->origin[0], r->origin[1], r->origin[2], r->k0, pw.khat[0],
+        pw.khat[1], pw.khat[2], mk(pw.pol[0].re, pw.pol[0].im), mk(pw.pol[1].re, pw.pol[1].im),
+        mk(pw.pol[2].re, pw.pol[2].im));
+    RT_HIP(hipGetLastError());
+    RT_HIP(hipMemsetAsync(x, 0, n * sizeof(c64), r->stream));
+    c64 bb;
+    RT_TRY(rt_dot(r, b, b, n, &bb));
+    const double bnorm = sqrt(bb.re);
+    vie_stats st{};
+    st.rel_res_x0 = 1.0;
+    st.cycles = 0;
+    double rel = bnorm > 0 ? 1.0 : 0.0;
+    int it = 0, mv = 0;
+    bool conv = bnorm == 0.0;
+    while (!conv && it < max_iter) {
+      // (re)start from the true residual
+      if (it > 0 || st.cycles > 0) {
+        RT_TRY(rt_apply(r, x, t));
+        ++mv;
+        RT_TRY(rt_lin(r, rr, b, mk(-1.0, 0.0), t, zero, nullptr, n));
+      } else {
+        RT_HIP(hipMemcpyAsync(rr, b, n * sizeof(c64), hipMemcpyDeviceToDevice, r->stream));
+      }
+      ++st.cycles;
+      RT_HIP(hipMemcpyAsync(rh, rr, n * sizeof(c64), hipMemcpyDeviceToDevice, r->stream));
+      RT_HIP(hipMemsetAsync(p, 0, n * sizeof(c64), r->stream));
+      RT_HIP(hipMemsetAsync(v, 0, n * sizeof(c64), r->stream));
+      c64 rho = one, alp = one, om = one;
+      bool cycle_done = false;
+      while (!cycle_done && it < max_iter) {
+        c64 rho1;
+        RT_TRY(rt_dot(r, rh, rr, n, &rho1));
+        if (rho1.re == 0.0 && rho1.im == 0.0) break;
+        const c64 beta = cdiv(rho1, rho) * cdiv(alp, om);
+        // p = r + beta (p - om v)
+        RT_TRY(rt_lin(r, p, p, mk(-om.re, -om.im), v, zero, nullptr, n));
+        RT_TRY(rt_lin(r, p, rr, beta, p, zero, nullptr, n));
+        RT_TRY(rt_apply(r, p, v));
+        ++mv;
+        c64 rv;
+        RT_TRY(rt_dot(r, rh, v, n, &rv));
+        if (rv.re == 0.0 && rv.im == 0.0) break;
+        alp = cdiv(rho1, rv);
+        RT_TRY(rt_lin(r, s, rr, mk(-alp.re, -alp.im), v, zero, nullptr, n));
+        RT_TRY(rt_apply(r, s, t));
+        ++mv;
+        c64 ts, tt;
+        RT_TRY(rt_dot(r, t, s, n, &ts));
+        RT_TRY(rt_dot(r, t, t, n, &tt));
+        om = tt.re > 0 ? mk(ts.re / tt.re, ts.im / tt.re) : zero;
+        RT_TRY(rt_lin(r, x, x, alp, p, om, s, n));
+        RT_TRY(rt_lin(r, rr, s, mk(-om.re, -om.im), t, zero, nullptr, n));
+        rho = rho1;
+        ++it;
+        c64 r2;
+        RT_TRY(rt_dot(r, rr, rr, n, &r2));
+        if (sqrt(r2.re) <= tol * bnorm || (om.re == 0.0 && om.im == 0.0)) cycle_done = true;
+      }
+      // true residual decides
+      RT_TRY(rt_apply(r, x, t));
+      ++mv;
+      RT_TRY(rt_lin(r, t, b, mk(-1.0, 0.0), t, zero, nullptr, n));
+      c64 r2;
+      RT_TRY(rt_dot(r, t, t, n, &r2));
+      rel = sqrt(r2.re) / bnorm;
+      conv = rel <= tol;
+      if (!cycle_done) break;  // breakdown or iteration cap
+    }
+    RT_HIP(hipMemcpyAsync(w + k * n, x, n * sizeof(c64), hipMemcpyDeviceToHost, r->stream));
+    RT_HIP(hipStreamSynchronize(r->stream));
+    const double sec =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    st.iters = it;
+    st.matvecs = mv;
+    st.converged = conv ? 1 : 0;
+    st.rel_res = rel;
+    st.seconds = conv ? sec : 0.0;
+    if (stats) stats[k] = st;
+    if (!conv) status = VIE_ENOCONV;
+  }
+  return status;
+}
+
+extern "C" int vie_rt_farfield(vie_rt* r, const vie_c64* w, int32_t nrhs, const double* theta,
+                               const double* phi, int32_t ndir, vie_c64* F) {
+  if (!r || !w || !theta || !phi || !F || nrhs < 1 || ndir < 1) return VIE_EINVAL;
+  if (r->poisoned) return VIE_ESTATE;
+  for (int d = 0; d < ndir; ++d)
+    if (!std::isfinite(theta[d]) || !std::isfinite(phi[d])) return VIE_EINVAL;
+  if ((int64_t)nrhs * ndir > (int64_t)1 << 30) return VIE_EINVAL;
+  const int64_t n = 3 * r->q.m;
+  c64* dw = nullptr;
+  double *dth = nullptr, *dph = nullptr;
+  c64* dF = nullptr;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  chk(dalloc(&dw, (size_t)nrhs * n));
+  chk(dalloc(&dth, ndir));
+  chk(dalloc(&dph, ndir));
+  chk(dalloc(&dF, (size_t)nrhs * ndir * 2));
+  if (e == hipSuccess) {
+    chk(hipMemcpyAsync(dw, w, (size_t)nrhs * n * sizeof(c64), hipMemcpyHostToDevice, r->stream));
+    chk(hipMemcpyAsync(dth, theta, ndir * sizeof(double), hipMemcpyHostToDevice, r->stream));
+    chk(hipMemcpyAsync(dph, phi, ndir * sizeof(double), hipMemcpyHostToDevice, r->stream));
+  }
+  if (e == hipSuccess) {
+    k_rt_far<<<nrhs * ndir, kRtThreads, 0, r->stream>>>(dw, r->alpha, r->q, r->h, r->origin[0],
+                                                        r->origin[1], r->origin[2], r->k0, dth,
+                                                        dph, ndir, dF);
+    chk(hipGetLastError());
+  }
+  if (e == hipSuccess)
+    chk(hipMemcpyAsync(F, dF, (size_t)nrhs * ndir * 2 * sizeof(c64), hipMemcpyDeviceToHost,
+                       r->stream));
+  if (e == hipSuccess) chk(hipStreamSynchronize(r->stream));
+  (void)hipFree(dw);
+  (void)hipFree(dth);
+  (void)hipFree(dph);
+  (void)hipFree(dF);
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) return VIE_ENOMEM;
+    r->poisoned = true;
+    return VIE_EDEVICE;
+  }
+  return VIE_OK;
+}
+
+extern "C" void vie_rt_destroy(vie_rt* r) {
+  if (!r) return;
+  if (r->stream) (void)hipStreamSynchronize(r->stream);
+  rt_free(r);
+  delete r;
+}

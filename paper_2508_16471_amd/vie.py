@@ -108,6 +108,14 @@ def lib():
             "vie_set_options": (C.c_int, [C.c_void_p, P(vie_options)]),
             "vie_destroy": (None, [C.c_void_p]),
             "vie_strerror": (C.c_char_p, [C.c_int]),
+            "vie_rt_setup": (C.c_int, [P(vie_body), C.c_double, P(C.c_void_p)]),
+            "vie_rt_grid": (C.c_int, [C.c_void_p, P(C.c_int32), P(C.c_int32)]),
+            "vie_rt_matvec": (C.c_int, [C.c_void_p, P(vie_c64), P(vie_c64), C.c_int32]),
+            "vie_rt_solve": (C.c_int, [C.c_void_p, P(vie_planewave), C.c_int32, C.c_double,
+                                       C.c_int32, P(vie_c64), P(vie_stats)]),
+            "vie_rt_farfield": (C.c_int, [C.c_void_p, P(vie_c64), C.c_int32, P(C.c_double),
+                                          P(C.c_double), C.c_int32, P(vie_c64)]),
+            "vie_rt_destroy": (None, [C.c_void_p]),
             "vie_cnn_num_params": (C.c_int64, []),
             "vie_cnn_create": (C.c_int, [C.c_uint64, P(C.c_void_p)]),
             "vie_cnn_destroy": (None, [C.c_void_p]),
@@ -245,6 +253,69 @@ def vie_self_term(kind, k0, h):
     out = vie_c64()
     _check(lib().vie_self_term(int(kind), float(k0), float(h), C.byref(out)), "vie_self_term")
     return complex(out.re, out.im)
+
+
+def vie_rt_setup(eps, h, origin, k0):
+    """Rooftop-basis operator of one body (eps_r[N3,N2,N1]).  Returns a handle."""
+    e = np.ascontiguousarray(eps, dtype=np.float64)
+    b = vie_body()
+    b.n[0], b.n[1], b.n[2] = e.shape[2], e.shape[1], e.shape[0]
+    b.h = float(h)
+    for a in range(3):
+        b.origin[a] = float(origin[a])
+    b.eps_r = _dptr(e)
+    rt = C.c_void_p()
+    _check(lib().vie_rt_setup(C.byref(b), float(k0), C.byref(rt)), "vie_rt_setup")
+    return rt
+
+
+def vie_rt_grid(rt):
+    """(padded grid E, circulant lengths P), each (x, y, z)."""
+    e, f = (C.c_int32 * 3)(), (C.c_int32 * 3)()
+    _check(lib().vie_rt_grid(rt, e, f), "vie_rt_grid")
+    return tuple(e), tuple(f)
+
+
+def vie_rt_matvec(rt, x):
+    """y = A x for x[nvec, 3, E3, E2, E1] (or one vector) on the padded grid."""
+    xs = np.ascontiguousarray(x, dtype=np.complex128)
+    single = xs.ndim == 4
+    if single:
+        xs = xs[None]
+    y = np.zeros_like(xs)
+    _check(lib().vie_rt_matvec(rt, _cptr(xs), _cptr(y), xs.shape[0]), "vie_rt_matvec")
+    return y[0] if single else y
+
+
+def vie_rt_solve(rt, channels, tol=1e-8, max_iter=2000, allow_noconv=False):
+    """BiCGSTAB solves of the channels; returns (status, w[nrhs, 3, E3, E2, E1], stats)."""
+    E, _ = vie_rt_grid(rt)
+    pw = planewaves(channels)
+    n = len(channels)
+    w = np.zeros((n, 3, E[2], E[1], E[0]), dtype=np.complex128)
+    st = (vie_stats * max(1, n))()
+    rc = lib().vie_rt_solve(rt, pw, n, float(tol), int(max_iter), _cptr(w), st)
+    _check(rc, "vie_rt_solve", allow=(VIE_ENOCONV,) if allow_noconv else ())
+    out = [{f: getattr(st[i], f) for f, _ in vie_stats._fields_} for i in range(n)]
+    return rc, w, out
+
+
+def vie_rt_farfield(rt, w, theta, phi):
+    """(F_theta, F_phi) of solutions w[nrhs, 3, E3, E2, E1]: array [nrhs, ndir, 2]."""
+    ws = np.ascontiguousarray(w, dtype=np.complex128)
+    if ws.ndim == 4:
+        ws = ws[None]
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    F = np.zeros((ws.shape[0], len(th), 2), dtype=np.complex128)
+    _check(lib().vie_rt_farfield(rt, _cptr(ws), ws.shape[0], _dptr(th), _dptr(ph), len(th),
+                                 _cptr(F)), "vie_rt_farfield")
+    return F
+
+
+def vie_rt_destroy(rt):
+    if rt:
+        lib().vie_rt_destroy(rt)
 
 
 def hom_classical_p2(T):

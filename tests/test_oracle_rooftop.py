@@ -138,3 +138,15 @@ def test_structure_inactive_faces_and_equal_split():
     chi2[:, :, 2:] = np.where(chi2[:, :, 2:] != 0, 1.5, 0.0)
     K2, i2, c2, _, _, _ = rt.system(chi2, g.h, g.origin, K0)
     assert np.array_equal(i1, i2) and np.allclose(c1, c2) and np.allclose(K1, K2)
+
+
+def test_matvec_rows_equals_dense():
+    rng = np.random.default_rng(9)
+    g = Grid.centred((5, 6, 4), 0.12)
+    chi = np.where(rng.random(g.n[::-1]) < 0.5, rng.uniform(0.3, 4.0, g.n[::-1]), 0.0)
+    act, _, _, _ = rt.face_data(chi, g.h, g.origin)
+    x = rng.standard_normal(act.shape) + 1j * rng.standard_normal(act.shape)
+    y = rt.matvec(chi, g.h, g.origin, 1.3 * K0, x).ravel()
+    rows = rng.choice(np.nonzero(act.ravel())[0], 25, replace=False)
+    got = rt.matvec_rows(chi, g.h, g.origin, 1.3 * K0, x, rows)
+    assert np.max(np.abs(got - y[rows])) < 1e-12 * np.max(np.abs(y))
