@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2508_16471_amd", "weights",
                                                       "warmstart_metasurface128.npy"))
     ap.add_argument("--mode", choices=["solve", "matvec", "farfield", "uneven", "metasurface",
-                                       "sphere", "precond", "paperscale", "cnn"],
+                                       "sphere", "precond", "paperscale", "cnn", "rooftop"],
                     default="solve",
                     help="matvec: time device-resident operator products only; farfield: "
                          "the 64,800-direction sweep of one body only (profiling); uneven: "
@@ -1082,6 +1082,61 @@ def sphere_mode(args):
     print(json.dumps(out))
 
 
+def rooftop_mode(args):
+    """The rooftop-basis operator (eq. Js_expand) on the paper's sphere (r = 1
+    lambda, eps 4, 64^3, h = 2.05/64, padded grid 66^3, circulant 192^3): setup,
+    --steps products of host vectors (PCIe copies included; the device time per
+    product is in the kernel trace), the two theta = +-30 deg channels solved
+    to 1e-6 with BiCGSTAB, and a 180 x 360 far-field sweep per channel."""
+    import torch
+
+    from paper_2508_16471_amd import vie as V
+    from synth import Grid, sphere
+
+    torch.cuda.set_device(0)
+    V.lib()
+    g = Grid.centred((64, 64, 64), 2.05 / 64)
+    eps = sphere(g, 1.0, 4.0)
+    a = np.deg2rad(30.0)
+    chans = [((np.sin(a), 0, np.cos(a)), (0, 1.0, 0)), ((-np.sin(a), 0, np.cos(a)), (0, 1.0, 0))]
+    t0 = time.perf_counter()
+    rt = V.vie_rt_setup(eps, g.h, g.origin, K0)
+    t_setup = time.perf_counter() - t0
+    try:
+        E, P = V.vie_rt_grid(rt)
+        rng = np.random.default_rng(0)
+        x = rng.standard_normal((3, E[2], E[1], E[0])) + 1j * rng.standard_normal((3, E[2], E[1], E[0]))
+        V.vie_rt_matvec(rt, x)
+        ts = []
+        for _ in range(max(1, args.steps)):
+            t0 = time.perf_counter()
+            V.vie_rt_matvec(rt, x)
+            ts.append(time.perf_counter() - t0)
+        print(f"rooftop: {len(ts)} products done", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        rc, w, st = V.vie_rt_solve(rt, chans, tol=1e-6, max_iter=5000, allow_noconv=True)
+        t_solve = time.perf_counter() - t0
+        print("rooftop: solve done", file=sys.stderr, flush=True)
+        th = (np.arange(180) + 0.5) * np.pi / 180
+        ph = np.arange(360) * 2 * np.pi / 360 - np.pi
+        TH, PH = np.meshgrid(th, ph, indexing="ij")
+        t0 = time.perf_counter()
+        V.vie_rt_farfield(rt, w, TH.ravel(), PH.ravel())
+        t_far = time.perf_counter() - t0
+    finally:
+        V.vie_rt_destroy(rt)
+    M = P[0] * P[1] * P[2]
+    out = {"mode": "rooftop", "workload": "rooftop basis, sphere r=1 lambda, eps 4, 64^3, "
+           "h=2.05/64, channels theta=+-30 deg (y-pol)", "padded_grid": E, "circulant": P,
+           "body_voxels": int((eps != 1.0).sum()), "setup_s": t_setup,
+           "product_ms_host_vectors": 1e3 * float(np.median(ts)),
+           "product_transform_bytes": 8 * 3 * 2 * 16 * M,
+           "solve_s": t_solve, "status": int(rc), "iters": [v["iters"] for v in st],
+           "matvecs": [v["matvecs"] for v in st], "rel_res": [v["rel_res"] for v in st],
+           "farfield_64800x2_s": t_far}
+    print(json.dumps(out))
+
+
 # ------------------------------------------------------------------ main
 def precond_mode(args):
     """The paper's block preconditioner (7 x 7 lateral blocks, read as block
@@ -1180,13 +1235,13 @@ def precond_mode(args):
 def main():
     args = parse()
     if args.mode in ("matvec", "farfield", "uneven", "metasurface", "sphere", "precond",
-                     "paperscale", "cnn"):
+                     "paperscale", "cnn", "rooftop"):
         if args.gpus != 1:
             sys.exit(2)
         return {"matvec": matvec_mode, "farfield": farfield_mode, "uneven": uneven_mode,
                 "metasurface": metasurface_mode, "sphere": sphere_mode,
                 "precond": precond_mode, "paperscale": paperscale_mode,
-                "cnn": cnn_mode}[args.mode](args)
+                "cnn": cnn_mode, "rooftop": rooftop_mode}[args.mode](args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the path shards by "
                           "right-hand side / body (see DESIGN.md), --gpus must be 1"}))

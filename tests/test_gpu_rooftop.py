@@ -175,3 +175,35 @@ def test_empty_body_and_errors(V):
     with pytest.raises(V.VieError) as ei:
         V.vie_rt_setup(np.full((2, 2, 2), 0.5), 0.1, (0, 0, 0), K0)
     assert ei.value.code == V.VIE_EINVAL
+
+
+def test_paper_sphere_both_bases_against_mie(V):
+    """The paper's sphere (r = 1 lambda, eps 4, 64^3, h = 2.05/64), x-polarised
+    +z incidence: far-field error against Mie of the rooftop basis and of the
+    pulse basis (FP64 solves to 1e-8), printed for the record."""
+    g = Grid.centred(64, 2.05 / 64)
+    eps = sphere(g, 1.0, 4.0)
+    th = np.deg2rad(np.arange(0, 181, 5.0))
+    thh = np.concatenate([th, th])
+    phh = np.concatenate([0 * th, 0 * th + np.pi / 2])
+    chan = [([0, 0, 1], [1, 0, 0])]
+    r = vd.direction(thh, phh)[0]
+    M = _project(mie.farfield_vec(K0, 1.0, 4.0, [0, 0, 1], [1, 0, 0], r), thh, phh)
+    h = V.vie_rt_setup(eps, g.h, g.origin, K0)
+    try:
+        rc, w, st = V.vie_rt_solve(h, chan, tol=1e-8, max_iter=5000)
+        assert rc == V.VIE_OK
+        Fr = V.vie_rt_farfield(h, w, thh, phh)[0]
+    finally:
+        V.vie_rt_destroy(h)
+    ctx = V.vie_setup([(eps, g.h, g.origin)], V.make_options(K0, tol=1e-8, max_iter=20000))
+    try:
+        V.vie_solve(ctx, chan, [1])
+        Fp = V.vie_farfield(ctx, 0, thh, phh, 1)[0]
+    finally:
+        V.vie_destroy(ctx)
+    er = np.linalg.norm(Fr - M) / np.linalg.norm(M)
+    ep = np.linalg.norm(Fp - M) / np.linalg.norm(M)
+    print(f"paper sphere vs Mie: rooftop {er:.4f} ({st[0]['iters']} iterations), pulse {ep:.4f}",
+          flush=True)
+    assert er < 0.15 and ep < 0.15
