@@ -18,7 +18,9 @@
 // padded grid: its circulant (length P >= 2 E - 1 per axis) is transformed
 // once at setup, each product transforms alpha W_x, alpha W_y, alpha W_z and
 // rho forward, multiplies by the spectrum and transforms back (the inverse as
-// the conjugate of the forward transform of the conjugate).  The solver is
+// the conjugate of the forward transform of the conjugate).  The transforms
+// are pruned: the forward one skips the zero padding, the inverse one
+// computes only the padded grid's outputs.  The solver is
 // BiCGSTAB (the paper's method) with the true residual deciding convergence.
 #include <math.h>
 
@@ -29,6 +31,7 @@
 #include <vector>
 
 #include "../../include/vie.h"
+#include "fft_common.h"
 #include "green.h"
 #include "kernels.h"
 
@@ -93,55 +96,83 @@ __global__ void k_rt_scale(const c64* __restrict__ in, c64* __restrict__ out, in
     out[e] = s * in[e];
 }
 
-// One input field of the product on the circulant grid: f < 3 the weighted
-// current alpha W_f, f = 3 the cell charge rho; zero outside the padded grid.
-// Inactive faces (alpha = 0) contribute nothing.
+// One input field of the product over the padded grid ([E3][E2][E1]): f < 3
+// the weighted current alpha W_f, f = 3 the cell charge rho.  Inactive faces
+// (alpha = 0) contribute nothing.
 __global__ void k_rt_gather(const c64* __restrict__ x, const double* __restrict__ alpha,
-                            c64* __restrict__ work, RtGeom q, int f, double inv_h) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < q.M;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int px = (int)(e % q.P[0]);
-    const int py = (int)((e / q.P[0]) % q.P[1]);
-    const int pz = (int)(e / ((int64_t)q.P[0] * q.P[1]));
+                            c64* __restrict__ out, RtGeom q, int f, double inv_h) {
+  const int64_t step[3] = {1, q.E[0], (int64_t)q.E[0] * q.E[1]};
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < q.m;
+       c += (int64_t)gridDim.x * blockDim.x) {
     c64 v = mk(0.0, 0.0);
-    if (px < q.E[0] && py < q.E[1] && pz < q.E[2]) {
-      const int64_t c = ((int64_t)pz * q.E[1] + py) * q.E[0] + px;
-      if (f < 3) {
-        const double a = alpha[f * q.m + c];
-        v = a * x[f * q.m + c];
-      } else {
-        const int pc[3] = {px, py, pz};
-        const int64_t step[3] = {1, q.E[0], (int64_t)q.E[0] * q.E[1]};
-        for (int i = 0; i < 3; ++i) {
-          const int64_t o = i * q.m + c;
-          if (alpha[o] != 0.0) v = v + x[o];  // + face of the cell
-          if (pc[i] > 0 && alpha[o - step[i]] != 0.0) v = v - x[o - step[i]];  // - face
-        }
-        v = inv_h * v;
+    if (f < 3) {
+      v = alpha[f * q.m + c] * x[f * q.m + c];
+    } else {
+      const int pc[3] = {(int)(c % q.E[0]), (int)((c / q.E[0]) % q.E[1]),
+                         (int)(c / ((int64_t)q.E[0] * q.E[1]))};
+      for (int i = 0; i < 3; ++i) {
+        const int64_t o = i * q.m + c;
+        if (alpha[o] != 0.0) v = v + x[o];  // + face of the cell
+        if (pc[i] > 0 && alpha[o - step[i]] != 0.0) v = v - x[o - step[i]];  // - face
       }
+      v = inv_h * v;
     }
-    work[e] = v;
+    out[c] = v;
   }
 }
 
-// work = conj(spectrum * ghat)
-__global__ void k_rt_mulconj(const c64* __restrict__ in, const c64* __restrict__ ghat,
-                             c64* __restrict__ out, int64_t M) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const c64 p = in[e] * ghat[e];
-    out[e] = mk(p.re, -p.im);
+// The z stage with the kernel's spectrum, one workgroup per W neighbouring x
+// columns at one y of the y-transformed field t [E3][P2][P1] (rows z < E3
+// non-zero): forward z transform (zero half skipped), product with the
+// spectrum (1/M folded in), conjugate, forward z transform keeping rows
+// z < E3.  With the y and x stages run forward afterwards and a final
+// conjugate, that is the inverse transform of the product (the conjugate of
+// the forward transform of the conjugate).
+template <int P>
+__global__ __launch_bounds__(nt_lines<double>()) void k_rt_zconv(
+    const c64* __restrict__ in, c64* __restrict__ out, const c64* __restrict__ ghat,
+    const c64* __restrict__ tw, int E3, int P1, int P2, int tiles) {
+  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<double>(), W = NT / TT;
+  __shared__ c64 lds[W * Pad<P>::LSTR];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = b % tiles, y = b / tiles;
+  const int cw = threadIdx.x % W, t = threadIdx.x / W;
+  const int col = tile * W + cw;
+  const bool valid = col < P1;
+  const int64_t plane = (int64_t)P2 * P1;
+  const int64_t base = (int64_t)y * P1 + (valid ? col : 0);
+  TwReg<double, P, E> tr;
+  tr.load(t, tw);
+  c64 v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int row = t + q * TT;
+    v[q] = (q < E / 2 && valid && row < E3) ? in[base + row * plane] : mk(0.0, 0.0);
+  }
+  line_fft<double, P, false, true, false>(v, lds + cw * Pad<P>::LSTR, t, tr);
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const c64 p = v[q] * ghat[base + (int64_t)(t + q * TT) * plane];
+    v[q] = mk(p.re, -p.im);
+  }
+  line_fft<double, P, false, false, true>(v, lds + cw * Pad<P>::LSTR, t, tr);
+  if (valid) {
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) {
+      const int row = t + q * TT;
+      if (row < E3) out[base + row * plane] = v[q];
+    }
   }
 }
 
-// R[c] = conj(tmp) over the padded grid (the inverse transform's result).
-__global__ void k_rt_store(const c64* __restrict__ tmp, c64* __restrict__ R, RtGeom q) {
+// R[c] = conj(t) over the padded grid, t the truncated transform
+// [E3][E2][P1] (the inverse transform's result).
+__global__ void k_rt_store(const c64* __restrict__ t, c64* __restrict__ R, RtGeom q) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < q.m;
        c += (int64_t)gridDim.x * blockDim.x) {
     const int x = (int)(c % q.E[0]);
-    const int y = (int)((c / q.E[0]) % q.E[1]);
-    const int z = (int)(c / ((int64_t)q.E[0] * q.E[1]));
-    const c64 v = tmp[((int64_t)z * q.P[1] + y) * q.P[0] + x];
+    const int64_t yz = c / q.E[0];  // z E2 + y
+    const c64 v = t[yz * q.P[0] + x];
     R[c] = mk(v.re, -v.im);
   }
 }
@@ -302,6 +333,11 @@ struct vie_rt {
   c64* tw[3] = {nullptr, nullptr, nullptr};
   c64* work = nullptr;  // [M]
   c64* tmp = nullptr;   // [M]
+  c64* c0 = nullptr;    // [m] gathered field
+  c64* t1 = nullptr;    // [E3 E2 P1]
+  c64* t2 = nullptr;    // [E3 P2 P1]
+  c64* t3 = nullptr;    // [E3 P2 P1]
+  c64* c1 = nullptr;    // [E3 E2 P1]
   c64* R = nullptr;     // [4][m]
   c64* vec[9] = {};     // solver vectors [3m] each
   c64* part = nullptr;  // dot partials
@@ -332,6 +368,11 @@ void rt_free(vie_rt* r) {
   for (auto* t : r->tw) f(t);
   f(r->work);
   f(r->tmp);
+  f(r->c0);
+  f(r->t1);
+  f(r->t2);
+  f(r->t3);
+  f(r->c1);
   f(r->R);
   for (auto* v : r->vec) f(v);
   f(r->part);
@@ -352,14 +393,19 @@ int rt_apply(vie_rt* r, const c64* x, c64* y) {
   const RtGeom& q = r->q;
   const void* tw[3] = {r->tw[0], r->tw[1], r->tw[2]};
   const double inv_h = 1.0 / r->h;
+  const int tiles = (q.P[0] + lines_per_block<double>(q.P[2]) - 1) / lines_per_block<double>(q.P[2]);
   for (int f = 0; f < 4; ++f) {
-    k_rt_gather<<<blocks_for(q.M), kRtThreads, 0, r->stream>>>(x, r->alpha, r->work, q, f, inv_h);
+    k_rt_gather<<<blocks_for(q.m), kRtThreads, 0, r->stream>>>(x, r->alpha, r->c0, q, f, inv_h);
     RT_HIP(hipGetLastError());
-    RT_HIP(launch_fft3d_full(r->work, r->tmp, r->g, tw, r->stream));
-    k_rt_mulconj<<<blocks_for(q.M), kRtThreads, 0, r->stream>>>(r->tmp, r->ghat, r->work, q.M);
-    RT_HIP(hipGetLastError());
-    RT_HIP(launch_fft3d_full(r->work, r->tmp, r->g, tw, r->stream));
-    k_rt_store<<<blocks_for(q.m), kRtThreads, 0, r->stream>>>(r->tmp, r->R + f * q.m, q);
+    RT_HIP(launch_fft_xy_pad(r->c0, r->t1, r->t2, q.E, q.P, tw, r->stream));
+    auto zconv = [&]() -> hipError_t {
+      VIE_DISPATCH_PZ(q.P[2], (k_rt_zconv<PP><<<tiles * q.P[1], nt_lines<double>(), 0, r->stream>>>(
+                                  r->t2, r->t3, r->ghat, r->tw[2], q.E[2], q.P[0], q.P[1], tiles)));
+      return hipGetLastError();
+    };
+    RT_HIP(zconv());
+    RT_HIP(launch_fft_yx_trunc(r->t3, r->t1, r->c1, q.E, q.P, tw, r->stream));
+    k_rt_store<<<blocks_for(q.m), kRtThreads, 0, r->stream>>>(r->c1, r->R + f * q.m, q);
     RT_HIP(hipGetLastError());
   }
   k_rt_epilogue<<<blocks_for(3 * q.m), kRtThreads, 0, r->stream>>>(x, r->R, r->chif, y, q,
@@ -479,6 +525,11 @@ extern "C" int vie_rt_setup(const vie_body* body, double k0, vie_rt** out) {
   chk(dalloc(&r->work, M));
   chk(dalloc(&r->tmp, M));
   chk(dalloc(&r->R, 4 * m));
+  chk(dalloc(&r->c0, m));
+  chk(dalloc(&r->t1, (size_t)q.E[2] * q.E[1] * q.P[0]));
+  chk(dalloc(&r->t2, (size_t)q.E[2] * q.P[1] * q.P[0]));
+  chk(dalloc(&r->t3, (size_t)q.E[2] * q.P[1] * q.P[0]));
+  chk(dalloc(&r->c1, (size_t)q.E[2] * q.E[1] * q.P[0]));
   for (auto& v : r->vec) chk(dalloc(&v, 3 * m));
   chk(dalloc(&r->part, kRtDotBlocks));
   for (int a = 0; a < 3; ++a) chk(dalloc(&r->tw[a], q.P[a]));
@@ -516,6 +567,10 @@ extern "C" int vie_rt_setup(const vie_body* body, double k0, vie_rt** out) {
     delete r;
     return VIE_EDEVICE;
   }
+  // the full circulant buffers serve the spectrum only
+  (void)hipFree(r->work);
+  (void)hipFree(r->tmp);
+  r->work = r->tmp = nullptr;
   *out = r;
   return VIE_OK;
 }
