@@ -297,8 +297,10 @@ int vie_rt_grid(const vie_rt *rt, int32_t *ext, int32_t *fft);
 int vie_rt_matvec(vie_rt *rt, const vie_c64 *x, vie_c64 *y, int32_t nvec);
 
 /* Solve for nrhs plane-wave channels (b = chi_f e(r_f)) with BiCGSTAB from
- * w = 0, restarted from the true residual when the recursive one reaches tol;
- * the true residual ||b - A w|| / ||b|| <= tol decides.  w: nrhs vectors.
+ * w = 0 (scalars on the device, the host checking them every 8 iterations),
+ * restarted from the true residual when the recursive one reaches tol or the
+ * iteration breaks down (a zero denominator); the true residual
+ * ||b - A w|| / ||b|| <= tol decides.  w: nrhs vectors.
  * stats (nullable, one per channel): iters, matvecs, cycles, converged,
  * rel_res; seconds = host wall time of the channel's solve (0 if not
  * converged).  VIE_ENOCONV if a channel missed tol in max_iter iterations

@@ -262,6 +262,120 @@ __global__ void k_rt_lin(c64* __restrict__ out, const c64* __restrict__ a, c64 c
   }
 }
 
+// BiCGSTAB scalars, kept on the device between host checks.
+struct RtScal {
+  c64 rho, alpha, omega, beta, rho1;
+  double tol2;          // tol^2 ||b||^2 (recursive residual threshold)
+  int it, max_it;       // iterations done (all cycles), cap
+  int stop;             // 0 running, 1 recursive residual reached, 2 breakdown, 3 cap
+};
+enum { kScRho = 0, kScAlpha = 1, kScOmega = 2, kScRes = 3 };
+
+__device__ __forceinline__ c64 rt_cdiv(c64 a, c64 b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return mk((a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d);
+}
+
+__global__ void k_rt_sinit(RtScal* sc, double tol2, int it, int max_it) {
+  RtScal S;
+  S.rho = S.alpha = S.omega = S.beta = S.rho1 = mk(1.0, 0.0);
+  S.tol2 = tol2;
+  S.it = it;
+  S.max_it = max_it;
+  S.stop = 0;
+  *sc = S;
+}
+
+// Reduces the dot partials of slot 0 (and 1) in a fixed order and takes one
+// scalar step of the iteration:
+//   kScRho:   rho1 = (rh, r); beta = (rho1 / rho)(alpha / omega)
+//   kScAlpha: alpha = rho1 / (rh, v)
+//   kScOmega: omega = (t, s) / (t, t); rho = rho1; one iteration done
+//   kScRes:   stop when (r, r) <= tol^2 ||b||^2, or after omega = 0
+// A zero denominator stops the cycle (breakdown); so does the iteration cap.
+__global__ void __launch_bounds__(kRtThreads) k_rt_scal(const c64* __restrict__ part,
+                                                        RtScal* __restrict__ sc, int op) {
+  __shared__ double red[4][kRtThreads];
+  const int i = threadIdx.x;
+  const c64 a = part[i];
+  const c64 b = op == kScOmega ? part[kRtDotBlocks + i] : mk(0.0, 0.0);
+  red[0][i] = a.re;
+  red[1][i] = a.im;
+  red[2][i] = b.re;
+  red[3][i] = b.im;
+  __syncthreads();
+  for (int st = kRtThreads / 2; st > 0; st >>= 1) {
+    if (i < st)
+      for (int k = 0; k < 4; ++k) red[k][i] += red[k][i + st];
+    __syncthreads();
+  }
+  if (i != 0) return;
+  RtScal S = *sc;
+  if (S.stop) return;
+  const c64 d0 = mk(red[0][0], red[1][0]);
+  const bool zero0 = d0.re == 0.0 && d0.im == 0.0;
+  if (op == kScRho) {
+    if (S.it >= S.max_it) {
+      S.stop = 3;
+    } else if (zero0) {
+      S.stop = 2;
+    } else {
+      S.rho1 = d0;
+      S.beta = rt_cdiv(d0, S.rho) * rt_cdiv(S.alpha, S.omega);
+    }
+  } else if (op == kScAlpha) {
+    if (zero0)
+      S.stop = 2;
+    else
+      S.alpha = rt_cdiv(S.rho1, d0);
+  } else if (op == kScOmega) {
+    const double tt = red[2][0];
+    S.omega = tt > 0 ? mk(d0.re / tt, d0.im / tt) : mk(0.0, 0.0);
+    S.rho = S.rho1;
+    S.it += 1;
+  } else {
+    if (d0.re <= S.tol2)
+      S.stop = 1;
+    else if (S.omega.re == 0.0 && S.omega.im == 0.0)
+      S.stop = 2;
+  }
+  *sc = S;
+}
+
+// p = r + beta (p - omega v)
+__global__ void k_rt_pupd(c64* __restrict__ p, const c64* __restrict__ r,
+                          const c64* __restrict__ v, const RtScal* __restrict__ sc, int64_t n) {
+  if (sc->stop) return;
+  const c64 beta = sc->beta, om = sc->omega;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = r[e] + beta * (p[e] - om * v[e]);
+}
+
+// s = r - alpha v
+__global__ void k_rt_supd(c64* __restrict__ s, const c64* __restrict__ r,
+                          const c64* __restrict__ v, const RtScal* __restrict__ sc, int64_t n) {
+  if (sc->stop) return;
+  const c64 al = sc->alpha;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    s[e] = r[e] - al * v[e];
+}
+
+// x = x + alpha p + omega s; r = s - omega t
+__global__ void k_rt_xrupd(c64* __restrict__ x, c64* __restrict__ r, const c64* __restrict__ p,
+                           const c64* __restrict__ s, const c64* __restrict__ t,
+                           const RtScal* __restrict__ sc, int64_t n) {
+  if (sc->stop) return;
+  const c64 al = sc->alpha, om = sc->omega;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const c64 se = s[e];
+    x[e] = x[e] + al * p[e] + om * se;
+    r[e] = se - om * t[e];
+  }
+}
+
 // Far field of eq. 25: one workgroup per (right-hand side, direction),
 // S = sum_faces alpha W_i e_i e^{-i k0 r . r_f}, F = k0^2 h^3 / (4 pi) (t . S, p . S).
 __global__ void __launch_bounds__(kRtThreads) k_rt_far(const c64* __restrict__ w,
@@ -340,7 +454,8 @@ struct vie_rt {
   c64* c1 = nullptr;    // [E3 E2 P1]
   c64* R = nullptr;     // [4][m]
   c64* vec[9] = {};     // solver vectors [3m] each
-  c64* part = nullptr;  // dot partials
+  c64* part = nullptr;  // dot partials, two slots
+  RtScal* sc = nullptr; // device-resident iteration scalars
   std::vector<c64> hpart;
 };
 
@@ -376,6 +491,7 @@ void rt_free(vie_rt* r) {
   f(r->R);
   for (auto* v : r->vec) f(v);
   f(r->part);
+  f(r->sc);
   if (r->stream) (void)hipStreamDestroy(r->stream);
 }
 
@@ -432,11 +548,6 @@ int rt_lin(vie_rt* r, c64* out, const c64* a, c64 cb, const c64* b, c64 cc, cons
   k_rt_lin<<<blocks_for(n), kRtThreads, 0, r->stream>>>(out, a, cb, b, cc, c, n);
   RT_HIP(hipGetLastError());
   return VIE_OK;
-}
-
-c64 cdiv(c64 a, c64 b) {
-  const double d = b.re * b.re + b.im * b.im;
-  return mk((a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d);
 }
 
 #define RT_TRY(call)          \
@@ -531,7 +642,8 @@ extern "C" int vie_rt_setup(const vie_body* body, double k0, vie_rt** out) {
   chk(dalloc(&r->t3, (size_t)q.E[2] * q.P[1] * q.P[0]));
   chk(dalloc(&r->c1, (size_t)q.E[2] * q.E[1] * q.P[0]));
   for (auto& v : r->vec) chk(dalloc(&v, 3 * m));
-  chk(dalloc(&r->part, kRtDotBlocks));
+  chk(dalloc(&r->part, 2 * kRtDotBlocks));
+  chk(dalloc(&r->sc, 1));
   for (int a = 0; a < 3; ++a) chk(dalloc(&r->tw[a], q.P[a]));
   if (e != hipSuccess) {
     rt_free(r);
@@ -613,7 +725,7 @@ extern "C" int vie_rt_solve(vie_rt* r, const vie_planewave* inc, int32_t nrhs, d
   const int64_t n = 3 * q.m;
   c64 *x = r->vec[0], *b = r->vec[1], *rr = r->vec[2], *rh = r->vec[3], *p = r->vec[4],
       *v = r->vec[5], *s = r->vec[6], *t = r->vec[7];
-  const c64 one = mk(1.0, 0.0), zero = mk(0.0, 0.0);
+  const c64 zero = mk(0.0, 0.0);
   int status = VIE_OK;
   for (int k = 0; k < nrhs; ++k) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -635,7 +747,7 @@ extern "C" int vie_rt_solve(vie_rt* r, const vie_planewave* inc, int32_t nrhs, d
     bool conv = bnorm == 0.0;
     while (!conv && it < max_iter) {
       // (re)start from the true residual
-      if (it > 0 || st.cycles > 0) {
+      if (st.cycles > 0) {
         RT_TRY(rt_apply(r, x, t));
         ++mv;
         RT_TRY(rt_lin(r, rr, b, mk(-1.0, 0.0), t, zero, nullptr, n));
@@ -646,37 +758,39 @@ extern "C" int vie_rt_solve(vie_rt* r, const vie_planewave* inc, int32_t nrhs, d
       RT_HIP(hipMemcpyAsync(rh, rr, n * sizeof(c64), hipMemcpyDeviceToDevice, r->stream));
       RT_HIP(hipMemsetAsync(p, 0, n * sizeof(c64), r->stream));
       RT_HIP(hipMemsetAsync(v, 0, n * sizeof(c64), r->stream));
-      c64 rho = one, alp = one, om = one;
-      bool cycle_done = false;
-      while (!cycle_done && it < max_iter) {
-        c64 rho1;
-        RT_TRY(rt_dot(r, rh, rr, n, &rho1));
-        if (rho1.re == 0.0 && rho1.im == 0.0) break;
-        const c64 beta = cdiv(rho1, rho) * cdiv(alp, om);
-        // p = r + beta (p - om v)
-        RT_TRY(rt_lin(r, p, p, mk(-om.re, -om.im), v, zero, nullptr, n));
-        RT_TRY(rt_lin(r, p, rr, beta, p, zero, nullptr, n));
-        RT_TRY(rt_apply(r, p, v));
-        ++mv;
-        c64 rv;
-        RT_TRY(rt_dot(r, rh, v, n, &rv));
-        if (rv.re == 0.0 && rv.im == 0.0) break;
-        alp = cdiv(rho1, rv);
-        RT_TRY(rt_lin(r, s, rr, mk(-alp.re, -alp.im), v, zero, nullptr, n));
-        RT_TRY(rt_apply(r, s, t));
-        ++mv;
-        c64 ts, tt;
-        RT_TRY(rt_dot(r, t, s, n, &ts));
-        RT_TRY(rt_dot(r, t, t, n, &tt));
-        om = tt.re > 0 ? mk(ts.re / tt.re, ts.im / tt.re) : zero;
-        RT_TRY(rt_lin(r, x, x, alp, p, om, s, n));
-        RT_TRY(rt_lin(r, rr, s, mk(-om.re, -om.im), t, zero, nullptr, n));
-        rho = rho1;
-        ++it;
-        c64 r2;
-        RT_TRY(rt_dot(r, rr, rr, n, &r2));
-        if (sqrt(r2.re) <= tol * bnorm || (om.re == 0.0 && om.im == 0.0)) cycle_done = true;
+      k_rt_sinit<<<1, 1, 0, r->stream>>>(r->sc, tol * tol * bb.re, it, max_iter);
+      RT_HIP(hipGetLastError());
+      // iterations run in chunks with the scalars on the device; the host
+      // looks at them once per chunk (iterations after a stop are no-ops)
+      constexpr int kChunk = 8;
+      const int it0 = it;
+      RtScal S{};
+      for (;;) {
+        for (int j = 0; j < kChunk; ++j) {
+          k_rt_dot<<<kRtDotBlocks, kRtThreads, 0, r->stream>>>(rh, rr, n, r->part);
+          k_rt_scal<<<1, kRtThreads, 0, r->stream>>>(r->part, r->sc, kScRho);
+          k_rt_pupd<<<blocks_for(n), kRtThreads, 0, r->stream>>>(p, rr, v, r->sc, n);
+          RT_HIP(hipGetLastError());
+          RT_TRY(rt_apply(r, p, v));
+          k_rt_dot<<<kRtDotBlocks, kRtThreads, 0, r->stream>>>(rh, v, n, r->part);
+          k_rt_scal<<<1, kRtThreads, 0, r->stream>>>(r->part, r->sc, kScAlpha);
+          k_rt_supd<<<blocks_for(n), kRtThreads, 0, r->stream>>>(s, rr, v, r->sc, n);
+          RT_HIP(hipGetLastError());
+          RT_TRY(rt_apply(r, s, t));
+          k_rt_dot<<<kRtDotBlocks, kRtThreads, 0, r->stream>>>(t, s, n, r->part);
+          k_rt_dot<<<kRtDotBlocks, kRtThreads, 0, r->stream>>>(t, t, n, r->part + kRtDotBlocks);
+          k_rt_scal<<<1, kRtThreads, 0, r->stream>>>(r->part, r->sc, kScOmega);
+          k_rt_xrupd<<<blocks_for(n), kRtThreads, 0, r->stream>>>(x, rr, p, s, t, r->sc, n);
+          k_rt_dot<<<kRtDotBlocks, kRtThreads, 0, r->stream>>>(rr, rr, n, r->part);
+          k_rt_scal<<<1, kRtThreads, 0, r->stream>>>(r->part, r->sc, kScRes);
+          RT_HIP(hipGetLastError());
+        }
+        RT_HIP(hipMemcpyAsync(&S, r->sc, sizeof(RtScal), hipMemcpyDeviceToHost, r->stream));
+        RT_HIP(hipStreamSynchronize(r->stream));
+        if (S.stop) break;
       }
+      it = S.it;
+      mv += 2 * (it - it0);
       // true residual decides
       RT_TRY(rt_apply(r, x, t));
       ++mv;
@@ -685,7 +799,9 @@ extern "C" int vie_rt_solve(vie_rt* r, const vie_planewave* inc, int32_t nrhs, d
       RT_TRY(rt_dot(r, t, t, n, &r2));
       rel = sqrt(r2.re) / bnorm;
       conv = rel <= tol;
-      if (!cycle_done) break;  // breakdown or iteration cap
+      // the cap, or a cycle that could not take a single step, ends the solve;
+      // otherwise restart from the true residual
+      if (S.stop == 3 || it == it0) break;
     }
     RT_HIP(hipMemcpyAsync(w + k * n, x, n * sizeof(c64), hipMemcpyDeviceToHost, r->stream));
     RT_HIP(hipStreamSynchronize(r->stream));
