@@ -8,7 +8,8 @@ convolves four scalar fields with the kernel's circulant spectrum).
   sums at 32^3 (circulant 96, a 3 * 2^k length) and 48^3 (128), with the
   inactive entries passed through exactly;
 * solve and far field: BiCGSTAB to 1e-11 against the oracle's LU solution
-  (rel. 1e-9) for two channels, far field against the oracle's radiation sum;
+  (rel. 1e-9) for two channels on a sphere and for the two-material body,
+  far field against the oracle's radiation sum;
 * physics: the 16^3 sphere's far-field error against Mie equals the oracle's
   (4.21 %), and refinement to 24^3 lowers it;
 * edges: a body without voxels solves to zero; bad shapes and values are
@@ -207,3 +208,21 @@ def test_paper_sphere_both_bases_against_mie(V):
     print(f"paper sphere vs Mie: rooftop {er:.4f} ({st[0]['iters']} iterations), pulse {ep:.4f}",
           flush=True)
     assert er < 0.15 and ep < 0.15
+
+
+def test_two_material_solve_matches_lu(V):
+    """A body with holes and two permittivities touching the grid's edges
+    (interface faces carry the mean-of-inverses chi_f), oblique incidence:
+    BiCGSTAB to 1e-11 against the oracle's LU solution."""
+    name, g, chi, k0 = next(b for b in _bodies() if b[0] == "two_material")
+    kh = np.array([np.sin(1.0) * np.cos(2.0), np.sin(1.0) * np.sin(2.0), np.cos(1.0)])
+    pol = np.cross(kh, [0.0, 0.0, 1.0])
+    pol /= np.linalg.norm(pol)
+    h = V.vie_rt_setup(chi + 1, g.h, g.origin, k0)
+    try:
+        rc, w, st = V.vie_rt_solve(h, [(kh, pol)], tol=1e-11, max_iter=2000)
+        assert rc == V.VIE_OK and st[0]["rel_res"] <= 1e-11
+        ref = rt.solve_lu(chi, g.h, g.origin, k0, kh, pol)
+        assert np.max(np.abs(w[0].reshape(3, -1) - ref)) <= 1e-9 * np.max(np.abs(ref))
+    finally:
+        V.vie_rt_destroy(h)
