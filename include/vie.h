@@ -45,6 +45,17 @@
  *     VIE_EDEVICE the context is poisoned: later calls return VIE_ESTATE and
  *     the caller must vie_destroy() it.
  *   - A context is not thread-safe; use one per host thread.
+ *
+ * Environment
+ *   - VIE_LOG: progress and tuning lines on stderr.
+ *   - VIE_ZVAR=<k>: use z-pass launch shape k instead of timing them.
+ *   - VIE_DETERMINISTIC=1: use shape 0 instead of timing, so that results are
+ *     bit-for-bit the same from run to run and context to context (every
+ *     reduction has a fixed order; the timed shape choice is the only
+ *     run-dependent decision).
+ *   - VIE_TUNE_CACHE=<file>: reuse the timed shape choices recorded in the
+ *     file (lines "zshape P1 P2 P3 N1 N2 N3 precision nrhs shape") and append
+ *     new ones; an unreadable or unwritable file is ignored.
  */
 #ifndef VIE_H
 #define VIE_H

@@ -5,10 +5,12 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/vie.h"
@@ -743,16 +745,65 @@ static MatvecArgs matvec_args(Group& G, int precision, const int* active) {
   return m;
 }
 
+// Tuned z shapes kept across processes (VIE_TUNE_CACHE=<file>): one line
+// per decision, "zshape P1 P2 P3 N1 N2 N3 precision nrhs variant", read once
+// per process and path, appended to after every new tuning.
+using TuneKey = std::array<int, 8>;
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_tune;
+static std::string g_tune_path;
+
+static void tune_cache_load(const char* path) {
+  if (g_tune_path == path) return;
+  g_tune.clear();
+  g_tune_path = path;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char tag[16];
+  TuneKey k;
+  int v;
+  while (fscanf(f, "%15s %d %d %d %d %d %d %d %d %d", tag, &k[0], &k[1], &k[2], &k[3], &k[4],
+                &k[5], &k[6], &k[7], &v) == 10)
+    if (strcmp(tag, "zshape") == 0) g_tune[k] = v;
+  fclose(f);
+}
+
+static void tune_cache_store(const char* path, const TuneKey& k, int v) {
+  g_tune[k] = v;
+  FILE* f = fopen(path, "a");
+  if (!f) return;  // the cache is an optimisation: an unwritable file is ignored
+  fprintf(f, "zshape %d %d %d %d %d %d %d %d %d\n", k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7],
+          v);
+  fclose(f);
+}
+
 // Autotuner: time every z-pass launch shape on this group's scratch with the
-// current right-hand-side count and keep the fastest, by a clear margin
-// (VIE_ZVAR=<k> forces one).
+// current right-hand-side count and keep the fastest, by a clear margin.
+// VIE_ZVAR=<k> forces shape k; VIE_DETERMINISTIC=1 fixes shape 0, so that
+// results do not depend on timing (every reduction already has a fixed
+// order); VIE_TUNE_CACHE=<file> reuses and records decisions.
 static hipError_t tune_z(vie_ctx* ctx, Group& G, int precision) {
   if (G.zvar[precision] >= 0 && G.zvar_nrhs[precision] == G.g.nrhs) return hipSuccess;
   const char* force = getenv("VIE_ZVAR");
-  if (force) {
-    G.zvar[precision] = std::max(0, std::min(z_variants(precision) - 1, atoi(force)));
+  const char* det = getenv("VIE_DETERMINISTIC");
+  if (force || (det && atoi(det) != 0)) {
+    G.zvar[precision] =
+        force ? std::max(0, std::min(z_variants(precision) - 1, atoi(force))) : 0;
     G.zvar_nrhs[precision] = G.g.nrhs;
     return hipSuccess;
+  }
+  const char* cache = getenv("VIE_TUNE_CACHE");
+  const TuneKey key = {G.g.P[0], G.g.P[1], G.g.P[2], G.g.N[0],
+                       G.g.N[1], G.g.N[2], precision, G.g.nrhs};
+  if (cache && *cache) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load(cache);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end() && it->second >= 0 && it->second < z_variants(precision)) {
+      G.zvar[precision] = it->second;
+      G.zvar_nrhs[precision] = G.g.nrhs;
+      return hipSuccess;
+    }
   }
   hipError_t e = hipMemsetAsync(G.bufB.p, 0, G.bufB.bytes, ctx->stream);
   if (e != hipSuccess) return e;
@@ -790,6 +841,11 @@ static hipError_t tune_z(vie_ctx* ctx, Group& G, int precision) {
   if (e == hipSuccess) {
     G.zvar[precision] = bestv;
     G.zvar_nrhs[precision] = G.g.nrhs;
+    if (cache && *cache) {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      tune_cache_load(cache);
+      tune_cache_store(cache, key, bestv);
+    }
   }
   return e;
 }
@@ -994,7 +1050,6 @@ static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fall
   KState* st = G.state.as<KState>();
   int* flags = G.flags.as<int>();
   int* active = flags;
-  int* notdone = flags + nrhs;
   c64* part = G.partials.as<c64>();
   const int vb = vec_blocks_group(G);
   const BodyIdx& bi = G.bi;
