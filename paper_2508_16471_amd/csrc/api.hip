@@ -18,6 +18,7 @@
 #include "gmres.h"
 #include "green.h"
 #include "kernels.h"
+#include "trace.h"
 
 using namespace vie;
 
@@ -413,6 +414,7 @@ static int build_spectrum(vie_ctx* ctx, Group& G) {
 
 extern "C" int vie_setup(const vie_body* bodies, int32_t n_bodies, const vie_options* opt,
                          vie_ctx** out) {
+  TraceRange trace_("vie_setup");
   if (!out) return VIE_EINVAL;
   *out = nullptr;
   if (!bodies || n_bodies < 1 || !valid_options(opt)) return VIE_EINVAL;
@@ -1039,6 +1041,7 @@ static int warm_start_init(vie_ctx* ctx, Group& G, const FinParams& fp,
 }
 
 static int solve_group(vie_ctx* ctx, Group& G, bool warm, std::vector<int>& fallback_out) {
+  TraceRange trace_("solve_group");
   const GroupGeom& g = G.g;
   const int nrhs = g.nrhs;
   const int prec = ctx->opt.precision == VIE_MIXED ? 1 : 0;
@@ -1329,6 +1332,7 @@ static double done_seconds(const vie_ctx* ctx, const KState& S, bool conv,
 
 extern "C" int vie_solve(vie_ctx* ctx, const vie_planewave* inc, const int32_t* nrhs_per_body,
                          vie_stats* stats) {
+  TraceRange trace_("vie_solve");
   if (!ctx) return VIE_EINVAL;
   if (ctx->poisoned) return VIE_ESTATE;
   if (!inc || !nrhs_per_body) return VIE_EINVAL;
@@ -1869,6 +1873,7 @@ static void key_arnoldi(std::vector<const void*>& k, const ArnoldiBufs& A) {
 // flag after the FP64 residual.
 static int fgmres_group(vie_ctx* ctx, Group& G, BlockPrec* P, const vie_fgmres_options* fo,
                         bool warm, std::vector<int>& steps_out, std::vector<int>& cycles_out) {
+  TraceRange trace_("fgmres_group");
   const int nrhs = G.g.nrhs;
   const int m = fo->restart;
   const bool flex = P != nullptr;
@@ -2082,6 +2087,7 @@ static std::vector<int> rhs_slots(vie_ctx* ctx, const Group& G) {
 extern "C" int vie_solve_fgmres(vie_ctx* ctx, const vie_planewave* inc,
                                 const int32_t* nrhs_per_body, const vie_fgmres_options* fo,
                                 vie_stats* stats) {
+  TraceRange trace_("vie_solve_fgmres");
   if (!ctx) return VIE_EINVAL;
   if (ctx->poisoned) return VIE_ESTATE;
   if (!inc || !nrhs_per_body || !fo) return VIE_EINVAL;
@@ -2324,6 +2330,7 @@ extern "C" int vie_matvec_dev_static(vie_ctx* ctx, int32_t body, int32_t precisi
 
 extern "C" int vie_matvec(vie_ctx* ctx, int32_t body, int32_t precision, const vie_c64* x,
                           vie_c64* y, int32_t nvec) {
+  TraceRange trace_("vie_matvec");
   if (!ctx) return VIE_EINVAL;
   if (ctx->poisoned) return VIE_ESTATE;
   if (body < 0 || body >= (int)ctx->bodies.size() || nvec < 1 || !x || !y) return VIE_EINVAL;
@@ -2420,6 +2427,7 @@ static void sph_frame(double t, double p, double* D) {
 
 extern "C" int vie_farfield(vie_ctx* ctx, int32_t body, const double* theta, const double* phi,
                             int32_t ndir, vie_c64* F) {
+  TraceRange trace_("vie_farfield");
   if (!ctx) return VIE_EINVAL;
   if (ctx->poisoned) return VIE_ESTATE;
   if (body < 0 || body >= (int)ctx->bodies.size() || ndir < 1 || !theta || !phi || !F)
@@ -2463,6 +2471,7 @@ static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w
 
 extern "C" int vie_transfer_na(vie_ctx* ctx, int32_t body, const vie_na_detector* det,
                                int32_t ndet, int32_t n_rad, int32_t n_az, vie_c64* T) {
+  TraceRange trace_("vie_transfer_na");
   if (!ctx) return VIE_EINVAL;
   if (ctx->poisoned) return VIE_ESTATE;
   if (body < 0 || body >= (int)ctx->bodies.size() || ndet < 1 || !det || !T || n_rad < 1 ||

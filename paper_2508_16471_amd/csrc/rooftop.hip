@@ -34,6 +34,7 @@
 #include "fft_common.h"
 #include "green.h"
 #include "kernels.h"
+#include "trace.h"
 
 namespace vie {
 
@@ -559,6 +560,7 @@ int rt_lin(vie_rt* r, c64* out, const c64* a, c64 cb, const c64* b, c64 cc, cons
 }  // namespace
 
 extern "C" int vie_rt_setup(const vie_body* body, double k0, vie_rt** out) {
+  TraceRange trace_("vie_rt_setup");
   if (!out) return VIE_EINVAL;
   *out = nullptr;
   if (!body || !body->eps_r || !(body->h > 0) || !std::isfinite(body->h) || !(k0 > 0) ||
@@ -713,6 +715,7 @@ extern "C" int vie_rt_matvec(vie_rt* r, const vie_c64* x, vie_c64* y, int32_t nv
 
 extern "C" int vie_rt_solve(vie_rt* r, const vie_planewave* inc, int32_t nrhs, double tol,
                             int32_t max_iter, vie_c64* w, vie_stats* stats) {
+  TraceRange trace_("vie_rt_solve");
   if (!r || !inc || !w || nrhs < 1 || !(tol > 0) || !(tol < 1) || max_iter < 1)
     return VIE_EINVAL;
   if (r->poisoned) return VIE_ESTATE;
@@ -820,6 +823,7 @@ extern "C" int vie_rt_solve(vie_rt* r, const vie_planewave* inc, int32_t nrhs, d
 
 extern "C" int vie_rt_farfield(vie_rt* r, const vie_c64* w, int32_t nrhs, const double* theta,
                                const double* phi, int32_t ndir, vie_c64* F) {
+  TraceRange trace_("vie_rt_farfield");
   if (!r || !w || !theta || !phi || !F || nrhs < 1 || ndir < 1) return VIE_EINVAL;
   if (r->poisoned) return VIE_ESTATE;
   for (int d = 0; d < ndir; ++d)
