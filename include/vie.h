@@ -457,6 +457,12 @@ void vie_cnn_destroy(vie_cnn *net);
 /* set != 0: load n = vie_cnn_num_params() host fp32 parameters (resets the
  * optimiser state); set == 0: read them back. */
 int vie_cnn_params(vie_cnn *net, float *params, int64_t n, int32_t set);
+/* Adam optimiser state for checkpoints: set == 0 reads the first and second
+ * moments m, v (n = vie_cnn_num_params() host fp32 each, parameter order)
+ * and the step count; set != 0 loads them (after vie_cnn_params, which
+ * resets them), so that training resumes exactly where it was saved.
+ * VIE_EINVAL for non-finite moments, v < 0 or step < 0. */
+int vie_cnn_adam_state(vie_cnn *net, float *m, float *v, int64_t n, int64_t *step, int32_t set);
 /* Use net for warm starts of ctx (vie_options.warm_start = 1); NULL detaches.
  * The network must outlive its use by ctx. */
 int vie_attach_cnn(vie_ctx *ctx, vie_cnn *net);

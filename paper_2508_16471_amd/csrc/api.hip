@@ -2696,6 +2696,27 @@ extern "C" int vie_cnn_params(vie_cnn* net, float* host, int64_t n, int32_t set)
   return VIE_OK;
 }
 
+extern "C" int vie_cnn_adam_state(vie_cnn* net, float* m, float* v, int64_t n, int64_t* step,
+                                  int32_t set) {
+  if (!net || !m || !v || !step || n != cnn_offsets().total) return VIE_EINVAL;
+  vie_ctx* ctx = nullptr;
+  if (set) {
+    if (*step < 0) return VIE_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+      if (!isfinite(m[i]) || !isfinite(v[i]) || v[i] < 0) return VIE_EINVAL;
+    VIE_HIP(hipDeviceSynchronize());
+    VIE_HIP(hipMemcpy(net->c.m, m, n * 4, hipMemcpyHostToDevice));
+    VIE_HIP(hipMemcpy(net->c.v, v, n * 4, hipMemcpyHostToDevice));
+    net->c.step = *step;
+  } else {
+    VIE_HIP(hipDeviceSynchronize());
+    VIE_HIP(hipMemcpy(m, net->c.m, n * 4, hipMemcpyDeviceToHost));
+    VIE_HIP(hipMemcpy(v, net->c.v, n * 4, hipMemcpyDeviceToHost));
+    *step = net->c.step;
+  }
+  return VIE_OK;
+}
+
 extern "C" int vie_attach_cnn(vie_ctx* ctx, vie_cnn* net) {
   if (!ctx) return VIE_EINVAL;
   if (ctx->poisoned) return VIE_ESTATE;

@@ -95,14 +95,31 @@ def generate(V, torch, it, nbodies, nch, chunk, tol, solver):
     return samples
 
 
-def train(V, torch, samples, epochs, lr, seed):
+def train(V, torch, samples, epochs, lr, seed, checkpoint=None, resume=None, stop_after=None):
+    """Adam with cosine decay over epochs x samples steps.  checkpoint: .npz
+    path written after every epoch (parameters, Adam moments and step, epoch,
+    step, shuffling generator state, loss history); resume: such a file to
+    continue from, bit for bit; stop_after: return after that many epochs."""
     net = V.vie_cnn_create(seed)
     rng = np.random.default_rng(seed)
     nsteps = epochs * len(samples)
     step = 0
-    t0 = time.perf_counter()
+    ep0 = 0
     hist = []
-    for ep in range(epochs):
+    if resume:
+        with np.load(resume, allow_pickle=False) as z:
+            V.vie_cnn_params(net, z["params"])
+            V.vie_cnn_adam_state(net, (z["adam_m"], z["adam_v"], int(z["adam_step"])))
+            rng.bit_generator.state = json.loads(str(z["rng_state"]))
+            ep0, step = int(z["epoch"]), int(z["step"])
+            hist = [float(v) for v in z["hist"]]
+            if int(z["nsteps"]) != nsteps:
+                raise ValueError("checkpoint was written for another schedule")
+        log(f"train: resumed after epoch {ep0} from {resume}")
+    t0 = time.perf_counter()
+    for ep in range(ep0, epochs):
+        if stop_after is not None and ep >= stop_after:
+            break
         order = rng.permutation(len(samples))
         losses = []
         for i in order:
@@ -112,6 +129,13 @@ def train(V, torch, samples, epochs, lr, seed):
             step += 1
         hist.append(float(np.mean(losses)))
         log(f"train: epoch {ep + 1}/{epochs} mean loss {hist[-1]:.4f} ({time.perf_counter() - t0:.1f} s)")
+        if checkpoint:
+            m, v, astep = V.vie_cnn_adam_state(net)
+            tmp = checkpoint + ".tmp.npz"
+            np.savez(tmp, params=V.vie_cnn_params(net), adam_m=m, adam_v=v, adam_step=astep,
+                     epoch=ep + 1, step=step, nsteps=nsteps, hist=np.asarray(hist),
+                     rng_state=json.dumps(rng.bit_generator.state))
+            os.replace(tmp, checkpoint)
     return net, hist, time.perf_counter() - t0
 
 
@@ -184,6 +208,8 @@ def main():
     ap.add_argument("--eval-chunk", type=int, default=8, help="held-out bodies per context")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--summary", default=None)
+    ap.add_argument("--checkpoint", default=None, help=".npz written after every epoch")
+    ap.add_argument("--resume", default=None, help="continue training from a checkpoint")
     args = ap.parse_args()
 
     import torch
@@ -194,7 +220,8 @@ def main():
     V.lib()
     samples = generate(V, torch, family(args.seed, args.channels, args.grid), args.train_bodies,
                        args.channels, args.chunk, args.data_tol, args.solver)
-    net, hist, ttrain = train(V, torch, samples, args.epochs, args.lr, args.seed)
+    net, hist, ttrain = train(V, torch, samples, args.epochs, args.lr, args.seed,
+                              checkpoint=args.checkpoint, resume=args.resume)
     p = V.vie_cnn_params(net)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, p.astype(np.float32))

@@ -120,6 +120,8 @@ def lib():
             "vie_cnn_create": (C.c_int, [C.c_uint64, P(C.c_void_p)]),
             "vie_cnn_destroy": (None, [C.c_void_p]),
             "vie_cnn_params": (C.c_int, [C.c_void_p, P(C.c_float), C.c_int64, C.c_int32]),
+            "vie_cnn_adam_state": (C.c_int, [C.c_void_p, P(C.c_float), P(C.c_float), C.c_int64,
+                                             P(C.c_int64), C.c_int32]),
             "vie_attach_cnn": (C.c_int, [C.c_void_p, C.c_void_p]),
             "vie_cnn_sample_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                              C.c_void_p, P(C.c_int32)]),
@@ -438,6 +440,25 @@ def vie_cnn_params(net, params=None):
     p = np.ascontiguousarray(params, dtype=np.float32)
     _check(lib().vie_cnn_params(net, p.ctypes.data_as(C.POINTER(C.c_float)), n, 1), "vie_cnn_params")
     return p
+
+
+def vie_cnn_adam_state(net, state=None):
+    """Get (state None) or set the Adam state (m, v, step) of a network."""
+    n = vie_cnn_num_params()
+    fp = C.POINTER(C.c_float)
+    if state is None:
+        m = np.zeros(n, dtype=np.float32)
+        v = np.zeros(n, dtype=np.float32)
+        step = C.c_int64()
+        _check(lib().vie_cnn_adam_state(net, m.ctypes.data_as(fp), v.ctypes.data_as(fp), n,
+                                        C.byref(step), 0), "vie_cnn_adam_state")
+        return m, v, int(step.value)
+    m = np.ascontiguousarray(state[0], dtype=np.float32)
+    v = np.ascontiguousarray(state[1], dtype=np.float32)
+    step = C.c_int64(int(state[2]))
+    _check(lib().vie_cnn_adam_state(net, m.ctypes.data_as(fp), v.ctypes.data_as(fp), n,
+                                    C.byref(step), 1), "vie_cnn_adam_state")
+    return state
 
 
 def vie_attach_cnn(ctx, net):

@@ -153,3 +153,39 @@ def test_sample_tensors_and_warm_started_solve(env):
     finally:
         V.vie_destroy(ctx)
         V.vie_cnn_destroy(net)
+
+
+def test_checkpoint_resume_is_exact(env, tmp_path):
+    """Training interrupted after 2 of 4 epochs and resumed from its checkpoint
+    (parameters, Adam moments and step, shuffling state) ends bit for bit where
+    the uninterrupted run does; the Adam state round-trips through the ABI."""
+    V, torch = env
+    from paper_2508_16471_amd.train_warmstart import train
+
+    rng = np.random.default_rng(8)
+    d = (16, 16, 8)
+    samples = []
+    for _ in range(3):
+        feat, _ = _features(rng, d)
+        tgt = np.tanh(feat[..., 1:7]) * 0.5
+        samples.append((d, torch.tensor(feat, dtype=torch.float32).to(torch.bfloat16).cuda().contiguous(),
+                        torch.tensor(tgt, dtype=torch.float32).cuda().contiguous()))
+    nets = []
+    try:
+        a, ha, _ = train(V, torch, samples, 4, 3e-3, 3)
+        nets.append(a)
+        ck = str(tmp_path / "ck.npz")
+        b0, _, _ = train(V, torch, samples, 4, 3e-3, 3, checkpoint=ck, stop_after=2)
+        nets.append(b0)
+        b, hb, _ = train(V, torch, samples, 4, 3e-3, 3, resume=ck)
+        nets.append(b)
+        assert np.array_equal(V.vie_cnn_params(a), V.vie_cnn_params(b))
+        ma, va, sa = V.vie_cnn_adam_state(a)
+        mb, vb, sb = V.vie_cnn_adam_state(b)
+        assert sa == sb == 12 and np.array_equal(ma, mb) and np.array_equal(va, vb)
+        assert ha == hb
+        with pytest.raises(V.VieError):
+            V.vie_cnn_adam_state(b, (ma, -np.abs(va) - 1, sa))
+    finally:
+        for n in nets:
+            V.vie_cnn_destroy(n)
