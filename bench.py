@@ -1085,9 +1085,11 @@ def sphere_mode(args):
 def rooftop_mode(args):
     """The rooftop-basis operator (eq. Js_expand) on the paper's sphere (r = 1
     lambda, eps 4, 64^3, h = 2.05/64, padded grid 66^3, circulant 192^3): setup,
-    --steps products of host vectors (PCIe copies included; the device time per
-    product is in the kernel trace), the two theta = +-30 deg channels solved
-    to 1e-6 with BiCGSTAB, and a 180 x 360 far-field sweep per channel."""
+    per precision (FP64, and FP32 products inside FP64 refinement) --steps
+    products of host vectors (PCIe copies included; the device time per
+    product is in the kernel trace) and the two theta = +-30 deg channels
+    solved to 1e-6 with BiCGSTAB, then a 180 x 360 far-field sweep per channel
+    of the mixed solution."""
     import torch
 
     from paper_2508_16471_amd import vie as V
@@ -1106,17 +1108,24 @@ def rooftop_mode(args):
         E, P = V.vie_rt_grid(rt)
         rng = np.random.default_rng(0)
         x = rng.standard_normal((3, E[2], E[1], E[0])) + 1j * rng.standard_normal((3, E[2], E[1], E[0]))
-        V.vie_rt_matvec(rt, x)
-        ts = []
-        for _ in range(max(1, args.steps)):
+        prod_ms, solves = {}, {}
+        for label, prec in (("fp64", V.VIE_FP64), ("mixed", V.VIE_MIXED)):
+            V.vie_rt_matvec(rt, x, precision=prec)
+            ts = []
+            for _ in range(max(1, args.steps)):
+                t0 = time.perf_counter()
+                V.vie_rt_matvec(rt, x, precision=prec)
+                ts.append(time.perf_counter() - t0)
+            prod_ms[label] = 1e3 * float(np.median(ts))
+            print(f"rooftop: {len(ts)} {label} products done", file=sys.stderr, flush=True)
             t0 = time.perf_counter()
-            V.vie_rt_matvec(rt, x)
-            ts.append(time.perf_counter() - t0)
-        print(f"rooftop: {len(ts)} products done", file=sys.stderr, flush=True)
-        t0 = time.perf_counter()
-        rc, w, st = V.vie_rt_solve(rt, chans, tol=1e-6, max_iter=5000, allow_noconv=True)
-        t_solve = time.perf_counter() - t0
-        print("rooftop: solve done", file=sys.stderr, flush=True)
+            rc, w, st = V.vie_rt_solve(rt, chans, tol=1e-6, max_iter=8000, allow_noconv=True,
+                                       precision=prec)
+            solves[label] = {"solve_s": time.perf_counter() - t0, "status": int(rc),
+                             "iters": [v["iters"] for v in st], "cycles": [v["cycles"] for v in st],
+                             "matvecs": [v["matvecs"] for v in st],
+                             "rel_res": [v["rel_res"] for v in st]}
+            print(f"rooftop: {label} solve done", file=sys.stderr, flush=True)
         th = (np.arange(180) + 0.5) * np.pi / 180
         ph = np.arange(360) * 2 * np.pi / 360 - np.pi
         TH, PH = np.meshgrid(th, ph, indexing="ij")
@@ -1129,11 +1138,8 @@ def rooftop_mode(args):
     out = {"mode": "rooftop", "workload": "rooftop basis, sphere r=1 lambda, eps 4, 64^3, "
            "h=2.05/64, channels theta=+-30 deg (y-pol)", "padded_grid": E, "circulant": P,
            "body_voxels": int((eps != 1.0).sum()), "setup_s": t_setup,
-           "product_ms_host_vectors": 1e3 * float(np.median(ts)),
-           "product_transform_bytes": 8 * 3 * 2 * 16 * M,
-           "solve_s": t_solve, "status": int(rc), "iters": [v["iters"] for v in st],
-           "matvecs": [v["matvecs"] for v in st], "rel_res": [v["rel_res"] for v in st],
-           "farfield_64800x2_s": t_far}
+           "product_ms_host_vectors": prod_ms, "fp64": solves["fp64"], "mixed": solves["mixed"],
+           "farfield_64800x2_s": t_far, "spectrum_bytes_fp64": 16 * M}
     print(json.dumps(out))
 
 

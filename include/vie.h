@@ -296,7 +296,8 @@ typedef struct vie_rt vie_rt;
 /* Build the operator of one body (n: 1..128 per axis, VIE_ENOTSUP above;
  * eps_r as vie_body) at wavenumber k0: face data, the spectrum of the scalar
  * kernel's circulant (length P >= 2 E - 1 per axis, P1 P2 P3 complex
- * doubles), transform scratch (2 E3 P2 P1 + 2 E3 E2 P1 complex) and fields
+ * doubles and an FP32 copy), transform scratch (2 E3 P2 P1 + 2 E3 E2 P1
+ * complex) and fields
  * and solver vectors (36 E1 E2 E3 complex); setup needs two more P1 P2 P3
  * complex for the duration of the call.  VIE_EINVAL on bad values. */
 int vie_rt_setup(const vie_body *body, double k0, vie_rt **out);
@@ -304,20 +305,24 @@ int vie_rt_setup(const vie_body *body, double k0, vie_rt **out);
 /* Padded grid E[3] and circulant lengths P[3]; either may be NULL. */
 int vie_rt_grid(const vie_rt *rt, int32_t *ext, int32_t *fft);
 
-/* y = A x for nvec vectors (layout above). */
-int vie_rt_matvec(vie_rt *rt, const vie_c64 *x, vie_c64 *y, int32_t nvec);
+/* y = A x for nvec vectors (layout above).  precision VIE_FP64: FP64
+ * transforms; VIE_MIXED: FP32 transforms and spectrum (gather, epilogue and
+ * y in FP64). */
+int vie_rt_matvec(vie_rt *rt, const vie_c64 *x, vie_c64 *y, int32_t nvec, int32_t precision);
 
 /* Solve for nrhs plane-wave channels (b = chi_f e(r_f)) with BiCGSTAB from
  * w = 0 (scalars on the device, the host checking them every 8 iterations),
- * restarted from the true residual when the recursive one reaches tol or the
- * iteration breaks down (a zero denominator); the true residual
- * ||b - A w|| / ||b|| <= tol decides.  w: nrhs vectors.
- * stats (nullable, one per channel): iters, matvecs, cycles, converged,
- * rel_res; seconds = host wall time of the channel's solve (0 if not
- * converged).  VIE_ENOCONV if a channel missed tol in max_iter iterations
- * (its best iterate is still returned). */
+ * restarted from the FP64 true residual when the recursive one reaches its
+ * target or the iteration breaks down (a zero denominator); the true residual
+ * ||b - A w|| / ||b|| <= tol decides.  precision VIE_FP64: FP64 products;
+ * VIE_MIXED: FP32 products inside FP64 iterative refinement, every cycle
+ * reducing its starting residual by 1e-3 (or to tol), the vectors and dots
+ * FP64.  w: nrhs vectors.  stats (nullable, one per channel): iters (all
+ * cycles), matvecs, cycles, converged, rel_res; seconds = host wall time of
+ * the channel's solve (0 if not converged).  VIE_ENOCONV if a channel missed
+ * tol in max_iter iterations (its best iterate is still returned). */
 int vie_rt_solve(vie_rt *rt, const vie_planewave *inc, int32_t nrhs, double tol,
-                 int32_t max_iter, vie_c64 *w, vie_stats *stats);
+                 int32_t max_iter, int32_t precision, vie_c64 *w, vie_stats *stats);
 
 /* Far field of nrhs solutions w at ndir directions, laid out as vie_farfield:
  * F[(rhs * ndir + d) * 2 + {0,1}] = (F_theta, F_phi). */

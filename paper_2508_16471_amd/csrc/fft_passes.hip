@@ -1559,29 +1559,31 @@ hipError_t launch_fft3d_full(c64* work, c64* tmp, const GroupGeom& g, const void
 }
 
 
-// --------------------------- pruned FP64 x and y transforms of one field
+// ---------------------------- pruned x and y transforms of one field
 // For a field non-zero only on the first E[a] points of each axis
 // (E[a] <= P[a] / 2), the x and y stages of its forward 3-D transform, and
 // the y and x stages of a forward transform that keeps only the first E[1]
 // y and E[2] z outputs; both skip the zero halves like the operator's passes.
-static hipError_t px_pass(const c64* src, c64* dst, int n1, bool pad, const int E[3],
-                          const int P[3], const c64* tw0, hipStream_t s) {
+template <typename T>
+static hipError_t px_pass(const cpx<T>* src, cpx<T>* dst, int n1, bool pad, const int E[3],
+                          const int P[3], const cpx<T>* tw0, hipStream_t s) {
   const int P1 = P[0];
   const int lines = E[1] * E[2];
-  const int L = lines_per_block<double>(P1);
+  const int L = lines_per_block<T>(P1);
   const int bpr = (lines + L - 1) / L;
   if (pad) {
-    VIE_DISPATCH_P(P1, (k_fft_x_fwd<double, double, PP, true><<<bpr, nt_lines_p<double>(PP), 0, s>>>(
+    VIE_DISPATCH_P(P1, (k_fft_x_fwd<T, T, PP, true><<<bpr, nt_lines_p<T>(PP), 0, s>>>(
                            src, dst, tw0, n1, lines, bpr, nullptr)));
   } else {
-    VIE_DISPATCH_P(P1, (k_fft_x_fwd<double, double, PP, false><<<bpr, nt_lines_p<double>(PP), 0, s>>>(
+    VIE_DISPATCH_P(P1, (k_fft_x_fwd<T, T, PP, false><<<bpr, nt_lines_p<T>(PP), 0, s>>>(
                            src, dst, tw0, n1, lines, bpr, nullptr)));
   }
   return hipGetLastError();
 }
 
-static hipError_t py_pass(const c64* src, c64* dst, int rin, int rout, bool pad, const int E[3],
-                          const int P[3], const c64* tw1, hipStream_t s) {
+template <typename T>
+static hipError_t py_pass(const cpx<T>* src, cpx<T>* dst, int rin, int rout, bool pad,
+                          const int E[3], const int P[3], const cpx<T>* tw1, hipStream_t s) {
   const int P1 = P[0], P2 = P[1];
   StridedArgs a;
   a.n_in_rows = rin;
@@ -1590,18 +1592,18 @@ static hipError_t py_pass(const c64* src, c64* dst, int rin, int rout, bool pad,
   a.ncomp = 1;
   a.nz = E[2];
   a.zl = 1;
-  const int W = lines_per_block<double>(P2);
+  const int W = lines_per_block<T>(P2);
   a.tiles = (P1 + W - 1) / W;
   a.in.row = a.out.row = P1;
   a.in.zhs = (int64_t)rin * P1;
   a.out.zhs = (int64_t)rout * P1;
   a.in.zls = a.out.zls = a.in.cs = a.out.cs = a.in.rs = a.out.rs = 0;
   if (pad) {
-    VIE_DISPATCH_P(P2, (k_fft_strided<double, PP, true, false, false, nt_lines_p<double>(PP)>
-                        <<<a.tiles * E[2], nt_lines_p<double>(PP), 0, s>>>(src, dst, tw1, a, nullptr)));
+    VIE_DISPATCH_P(P2, (k_fft_strided<T, PP, true, false, false, nt_lines_p<T>(PP)>
+                        <<<a.tiles * E[2], nt_lines_p<T>(PP), 0, s>>>(src, dst, tw1, a, nullptr)));
   } else {
-    VIE_DISPATCH_P(P2, (k_fft_strided<double, PP, false, true, false, nt_lines_p<double>(PP)>
-                        <<<a.tiles * E[2], nt_lines_p<double>(PP), 0, s>>>(src, dst, tw1, a, nullptr)));
+    VIE_DISPATCH_P(P2, (k_fft_strided<T, PP, false, true, false, nt_lines_p<T>(PP)>
+                        <<<a.tiles * E[2], nt_lines_p<T>(PP), 0, s>>>(src, dst, tw1, a, nullptr)));
   }
   return hipGetLastError();
 }
@@ -1612,20 +1614,39 @@ static bool pruned_ok(const int E[3], const int P[3]) {
   return true;
 }
 
-hipError_t launch_fft_xy_pad(const c64* in, c64* t1, c64* out, const int E[3], const int P[3],
-                             const void* tw[3], hipStream_t s) {
+template <typename T>
+static hipError_t xy_pad_t(const cpx<T>* in, cpx<T>* t1, cpx<T>* out, const int E[3],
+                           const int P[3], const void* tw[3], hipStream_t s) {
   if (!pruned_ok(E, P)) return hipErrorInvalidValue;
-  hipError_t e = px_pass(in, t1, E[0], true, E, P, (const c64*)tw[0], s);
+  hipError_t e = px_pass<T>(in, t1, E[0], true, E, P, (const cpx<T>*)tw[0], s);
   if (e != hipSuccess) return e;
-  return py_pass(t1, out, E[1], P[1], true, E, P, (const c64*)tw[1], s);
+  return py_pass<T>(t1, out, E[1], P[1], true, E, P, (const cpx<T>*)tw[1], s);
 }
 
+template <typename T>
+static hipError_t yx_trunc_t(const cpx<T>* in, cpx<T>* t1, cpx<T>* out, const int E[3],
+                             const int P[3], const void* tw[3], hipStream_t s) {
+  if (!pruned_ok(E, P)) return hipErrorInvalidValue;
+  hipError_t e = py_pass<T>(in, t1, P[1], E[1], false, E, P, (const cpx<T>*)tw[1], s);
+  if (e != hipSuccess) return e;
+  return px_pass<T>(t1, out, P[0], false, E, P, (const cpx<T>*)tw[0], s);
+}
+
+hipError_t launch_fft_xy_pad(const c64* in, c64* t1, c64* out, const int E[3], const int P[3],
+                             const void* tw[3], hipStream_t s) {
+  return xy_pad_t<double>(in, t1, out, E, P, tw, s);
+}
+hipError_t launch_fft_xy_pad(const c32* in, c32* t1, c32* out, const int E[3], const int P[3],
+                             const void* tw[3], hipStream_t s) {
+  return xy_pad_t<float>(in, t1, out, E, P, tw, s);
+}
 hipError_t launch_fft_yx_trunc(const c64* in, c64* t1, c64* out, const int E[3], const int P[3],
                                const void* tw[3], hipStream_t s) {
-  if (!pruned_ok(E, P)) return hipErrorInvalidValue;
-  hipError_t e = py_pass(in, t1, P[1], E[1], false, E, P, (const c64*)tw[1], s);
-  if (e != hipSuccess) return e;
-  return px_pass(t1, out, P[0], false, E, P, (const c64*)tw[0], s);
+  return yx_trunc_t<double>(in, t1, out, E, P, tw, s);
+}
+hipError_t launch_fft_yx_trunc(const c32* in, c32* t1, c32* out, const int E[3], const int P[3],
+                               const void* tw[3], hipStream_t s) {
+  return yx_trunc_t<float>(in, t1, out, E, P, tw, s);
 }
 
 }  // namespace vie

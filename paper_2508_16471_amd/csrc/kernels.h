@@ -137,14 +137,19 @@ hipError_t launch_green_sample(c64* work, const GroupGeom& g, int ab, double h, 
 // In-place unpadded 3-D FFT of one P3 x P2 x P1 c64 array (forward).
 hipError_t launch_fft3d_full(c64* work, c64* tmp, const GroupGeom& g, const void* tw[3],
                              hipStream_t s);
-// Pruned x and y stages of the forward FP64 3-D FFT of one c64 field, with
-// E[a] <= P[a] / 2.  xy_pad: input non-zero on the first E[a] points per
-// axis, in [E3][E2][E1] -> t1 [E3][E2][P1] -> out [E3][P2][P1].  yx_trunc:
-// the y and x stages of a transform keeping the first E[1] y outputs, in
-// [E3][P2][P1] -> t1 [E3][E2][P1] -> out [E3][E2][P1] (all P1 x outputs).
+// Pruned x and y stages of the forward 3-D FFT of one field (FP64 or FP32),
+// with E[a] <= P[a] / 2.  xy_pad: input non-zero on the first E[a] points
+// per axis, in [E3][E2][E1] -> t1 [E3][E2][P1] -> out [E3][P2][P1].
+// yx_trunc: the y and x stages of a transform keeping the first E[1] y
+// outputs, in [E3][P2][P1] -> t1 [E3][E2][P1] -> out [E3][E2][P1] (all P1 x
+// outputs).  tw: the twiddle tables of the field's precision.
 hipError_t launch_fft_xy_pad(const c64* in, c64* t1, c64* out, const int E[3], const int P[3],
                              const void* tw[3], hipStream_t s);
+hipError_t launch_fft_xy_pad(const c32* in, c32* t1, c32* out, const int E[3], const int P[3],
+                             const void* tw[3], hipStream_t s);
 hipError_t launch_fft_yx_trunc(const c64* in, c64* t1, c64* out, const int E[3], const int P[3],
+                               const void* tw[3], hipStream_t s);
+hipError_t launch_fft_yx_trunc(const c32* in, c32* t1, c32* out, const int E[3], const int P[3],
                                const void* tw[3], hipStream_t s);
 // Octant compression with 1/M scaling into spec64 (and spec32 if non-null).
 hipError_t launch_octant(const c64* work, c64* spec64, c32* spec32, const GroupGeom& g, int ab,

@@ -100,8 +100,9 @@ __global__ void k_rt_scale(const c64* __restrict__ in, c64* __restrict__ out, in
 // One input field of the product over the padded grid ([E3][E2][E1]): f < 3
 // the weighted current alpha W_f, f = 3 the cell charge rho.  Inactive faces
 // (alpha = 0) contribute nothing.
+template <typename T>
 __global__ void k_rt_gather(const c64* __restrict__ x, const double* __restrict__ alpha,
-                            c64* __restrict__ out, RtGeom q, int f, double inv_h) {
+                            cpx<T>* __restrict__ out, RtGeom q, int f, double inv_h) {
   const int64_t step[3] = {1, q.E[0], (int64_t)q.E[0] * q.E[1]};
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < q.m;
        c += (int64_t)gridDim.x * blockDim.x) {
@@ -118,7 +119,7 @@ __global__ void k_rt_gather(const c64* __restrict__ x, const double* __restrict_
       }
       v = inv_h * v;
     }
-    out[c] = v;
+    out[c] = cvt<T>(v);
   }
 }
 
@@ -129,12 +130,12 @@ __global__ void k_rt_gather(const c64* __restrict__ x, const double* __restrict_
 // z < E3.  With the y and x stages run forward afterwards and a final
 // conjugate, that is the inverse transform of the product (the conjugate of
 // the forward transform of the conjugate).
-template <int P>
-__global__ __launch_bounds__(nt_lines<double>()) void k_rt_zconv(
-    const c64* __restrict__ in, c64* __restrict__ out, const c64* __restrict__ ghat,
-    const c64* __restrict__ tw, int E3, int P1, int P2, int tiles) {
-  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<double>(), W = NT / TT;
-  __shared__ c64 lds[W * Pad<P>::LSTR];
+template <typename T, int P>
+__global__ __launch_bounds__(nt_lines<T>()) void k_rt_zconv(
+    const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, const cpx<T>* __restrict__ ghat,
+    const cpx<T>* __restrict__ tw, int E3, int P1, int P2, int tiles) {
+  constexpr int E = fft_e<P>(), TT = P / E, NT = nt_lines<T>(), W = NT / TT;
+  __shared__ cpx<T> lds[W * Pad<P>::LSTR];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = b % tiles, y = b / tiles;
   const int cw = threadIdx.x % W, t = threadIdx.x / W;
@@ -142,21 +143,21 @@ __global__ __launch_bounds__(nt_lines<double>()) void k_rt_zconv(
   const bool valid = col < P1;
   const int64_t plane = (int64_t)P2 * P1;
   const int64_t base = (int64_t)y * P1 + (valid ? col : 0);
-  TwReg<double, P, E> tr;
+  TwReg<T, P, E> tr;
   tr.load(t, tw);
-  c64 v[E];
+  cpx<T> v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int row = t + q * TT;
-    v[q] = (q < E / 2 && valid && row < E3) ? in[base + row * plane] : mk(0.0, 0.0);
+    v[q] = (q < E / 2 && valid && row < E3) ? in[base + row * plane] : mk<T>(0, 0);
   }
-  line_fft<double, P, false, true, false>(v, lds + cw * Pad<P>::LSTR, t, tr);
+  line_fft<T, P, false, true, false>(v, lds + cw * Pad<P>::LSTR, t, tr);
 #pragma unroll
   for (int q = 0; q < E; ++q) {
-    const c64 p = v[q] * ghat[base + (int64_t)(t + q * TT) * plane];
+    const cpx<T> p = v[q] * ghat[base + (int64_t)(t + q * TT) * plane];
     v[q] = mk(p.re, -p.im);
   }
-  line_fft<double, P, false, false, true>(v, lds + cw * Pad<P>::LSTR, t, tr);
+  line_fft<T, P, false, false, true>(v, lds + cw * Pad<P>::LSTR, t, tr);
   if (valid) {
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
@@ -168,14 +169,22 @@ __global__ __launch_bounds__(nt_lines<double>()) void k_rt_zconv(
 
 // R[c] = conj(t) over the padded grid, t the truncated transform
 // [E3][E2][P1] (the inverse transform's result).
-__global__ void k_rt_store(const c64* __restrict__ t, c64* __restrict__ R, RtGeom q) {
+template <typename T>
+__global__ void k_rt_store(const cpx<T>* __restrict__ t, c64* __restrict__ R, RtGeom q) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < q.m;
        c += (int64_t)gridDim.x * blockDim.x) {
     const int x = (int)(c % q.E[0]);
     const int64_t yz = c / q.E[0];  // z E2 + y
-    const c64 v = t[yz * q.P[0] + x];
-    R[c] = mk(v.re, -v.im);
+    const cpx<T> v = t[yz * q.P[0] + x];
+    R[c] = mk((double)v.re, -(double)v.im);
   }
+}
+
+// FP32 copy of the spectrum.
+__global__ void k_rt_to32(const c64* __restrict__ in, c32* __restrict__ out, int64_t M) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = cvt<float>(in[e]);
 }
 
 // y = x - chi_f (k0^2 A_i + (phi(c + e_i) - phi(c)) / h) on active faces,
@@ -445,7 +454,9 @@ struct vie_rt {
   double* alpha = nullptr;  // [3][m]
   double* chif = nullptr;   // [3][m]
   c64* ghat = nullptr;      // [M] spectrum / M
+  c32* ghat32 = nullptr;    // [M] its FP32 copy
   c64* tw[3] = {nullptr, nullptr, nullptr};
+  c32* tw32[3] = {nullptr, nullptr, nullptr};
   c64* work = nullptr;  // [M]
   c64* tmp = nullptr;   // [M]
   c64* c0 = nullptr;    // [m] gathered field
@@ -481,6 +492,8 @@ void rt_free(vie_rt* r) {
   f(r->alpha);
   f(r->chif);
   f(r->ghat);
+  f(r->ghat32);
+  for (auto* t : r->tw32) f(t);
   for (auto* t : r->tw) f(t);
   f(r->work);
   f(r->tmp);
@@ -505,30 +518,47 @@ void rt_free(vie_rt* r) {
     }                                \
   } while (0)
 
-// y = A x for one full-layout vector (device pointers).
-int rt_apply(vie_rt* r, const c64* x, c64* y) {
+// y = A x for one full-layout vector (device pointers).  The transforms of
+// the four fields run in T (FP64, or FP32 for the inner products of a mixed
+// solve); gather, epilogue and y stay FP64.
+template <typename T>
+int rt_apply_t(vie_rt* r, const c64* x, c64* y) {
   const RtGeom& q = r->q;
-  const void* tw[3] = {r->tw[0], r->tw[1], r->tw[2]};
+  const bool f64 = sizeof(T) == 8;
+  const void* tw[3];
+  for (int a = 0; a < 3; ++a) tw[a] = f64 ? (const void*)r->tw[a] : (const void*)r->tw32[a];
+  const cpx<T>* ghat = (const cpx<T>*)(f64 ? (const void*)r->ghat : (const void*)r->ghat32);
+  cpx<T>* c0 = (cpx<T>*)r->c0;
+  cpx<T>* t1 = (cpx<T>*)r->t1;
+  cpx<T>* t2 = (cpx<T>*)r->t2;
+  cpx<T>* t3 = (cpx<T>*)r->t3;
+  cpx<T>* c1 = (cpx<T>*)r->c1;
   const double inv_h = 1.0 / r->h;
-  const int tiles = (q.P[0] + lines_per_block<double>(q.P[2]) - 1) / lines_per_block<double>(q.P[2]);
+  const int lpb = lines_per_block<T>(q.P[2]);
+  const int tiles = (q.P[0] + lpb - 1) / lpb;
   for (int f = 0; f < 4; ++f) {
-    k_rt_gather<<<blocks_for(q.m), kRtThreads, 0, r->stream>>>(x, r->alpha, r->c0, q, f, inv_h);
+    k_rt_gather<T><<<blocks_for(q.m), kRtThreads, 0, r->stream>>>(x, r->alpha, c0, q, f, inv_h);
     RT_HIP(hipGetLastError());
-    RT_HIP(launch_fft_xy_pad(r->c0, r->t1, r->t2, q.E, q.P, tw, r->stream));
+    RT_HIP(launch_fft_xy_pad(c0, t1, t2, q.E, q.P, tw, r->stream));
     auto zconv = [&]() -> hipError_t {
-      VIE_DISPATCH_PZ(q.P[2], (k_rt_zconv<PP><<<tiles * q.P[1], nt_lines<double>(), 0, r->stream>>>(
-                                  r->t2, r->t3, r->ghat, r->tw[2], q.E[2], q.P[0], q.P[1], tiles)));
+      VIE_DISPATCH_PZ(q.P[2], (k_rt_zconv<T, PP><<<tiles * q.P[1], nt_lines<T>(), 0, r->stream>>>(
+                                  t2, t3, ghat, (const cpx<T>*)tw[2], q.E[2], q.P[0], q.P[1],
+                                  tiles)));
       return hipGetLastError();
     };
     RT_HIP(zconv());
-    RT_HIP(launch_fft_yx_trunc(r->t3, r->t1, r->c1, q.E, q.P, tw, r->stream));
-    k_rt_store<<<blocks_for(q.m), kRtThreads, 0, r->stream>>>(r->c1, r->R + f * q.m, q);
+    RT_HIP(launch_fft_yx_trunc(t3, t1, c1, q.E, q.P, tw, r->stream));
+    k_rt_store<T><<<blocks_for(q.m), kRtThreads, 0, r->stream>>>(c1, r->R + f * q.m, q);
     RT_HIP(hipGetLastError());
   }
   k_rt_epilogue<<<blocks_for(3 * q.m), kRtThreads, 0, r->stream>>>(x, r->R, r->chif, y, q,
                                                                    r->k0 * r->k0, inv_h);
   RT_HIP(hipGetLastError());
   return VIE_OK;
+}
+
+int rt_apply(vie_rt* r, const c64* x, c64* y, bool fp32 = false) {
+  return fp32 ? rt_apply_t<float>(r, x, y) : rt_apply_t<double>(r, x, y);
 }
 
 // conj(a) . b over n entries (synchronous).
@@ -635,6 +665,7 @@ extern "C" int vie_rt_setup(const vie_body* body, double k0, vie_rt** out) {
   chk(dalloc(&r->alpha, 3 * m));
   chk(dalloc(&r->chif, 3 * m));
   chk(dalloc(&r->ghat, M));
+  chk(dalloc(&r->ghat32, M));
   chk(dalloc(&r->work, M));
   chk(dalloc(&r->tmp, M));
   chk(dalloc(&r->R, 4 * m));
@@ -647,6 +678,7 @@ extern "C" int vie_rt_setup(const vie_body* body, double k0, vie_rt** out) {
   chk(dalloc(&r->part, 2 * kRtDotBlocks));
   chk(dalloc(&r->sc, 1));
   for (int a = 0; a < 3; ++a) chk(dalloc(&r->tw[a], q.P[a]));
+  for (int a = 0; a < 3; ++a) chk(dalloc(&r->tw32[a], q.P[a]));
   if (e != hipSuccess) {
     rt_free(r);
     delete r;
@@ -655,11 +687,14 @@ extern "C" int vie_rt_setup(const vie_body* body, double k0, vie_rt** out) {
   r->hpart.resize(kRtDotBlocks);
   for (int a = 0; a < 3; ++a) {
     std::vector<c64> t(q.P[a]);
+    std::vector<c32> t32(q.P[a]);
     for (int k = 0; k < q.P[a]; ++k) {
       const long double ang = -2.0L * 3.14159265358979323846264338327950288L * k / q.P[a];
       t[k] = mk((double)cosl(ang), (double)sinl(ang));
+      t32[k] = mk((float)cosl(ang), (float)sinl(ang));
     }
     chk(hipMemcpy(r->tw[a], t.data(), q.P[a] * sizeof(c64), hipMemcpyHostToDevice));
+    chk(hipMemcpy(r->tw32[a], t32.data(), q.P[a] * sizeof(c32), hipMemcpyHostToDevice));
   }
   chk(hipMemcpy(r->alpha, alpha.data(), 3 * m * sizeof(double), hipMemcpyHostToDevice));
   chk(hipMemcpy(r->chif, chif.data(), 3 * m * sizeof(double), hipMemcpyHostToDevice));
@@ -673,6 +708,8 @@ extern "C" int vie_rt_setup(const vie_body* body, double k0, vie_rt** out) {
   if (e == hipSuccess) chk(launch_fft3d_full(r->work, r->tmp, r->g, tw, r->stream));
   if (e == hipSuccess) {
     k_rt_scale<<<blocks_for(M), kRtThreads, 0, r->stream>>>(r->tmp, r->ghat, M, 1.0 / (double)M);
+    chk(hipGetLastError());
+    k_rt_to32<<<blocks_for(M), kRtThreads, 0, r->stream>>>(r->ghat, r->ghat32, M);
     chk(hipGetLastError());
   }
   if (e == hipSuccess) chk(hipStreamSynchronize(r->stream));
@@ -698,14 +735,16 @@ extern "C" int vie_rt_grid(const vie_rt* r, int32_t* ext, int32_t* fft) {
   return VIE_OK;
 }
 
-extern "C" int vie_rt_matvec(vie_rt* r, const vie_c64* x, vie_c64* y, int32_t nvec) {
-  if (!r || !x || !y || nvec < 1) return VIE_EINVAL;
+extern "C" int vie_rt_matvec(vie_rt* r, const vie_c64* x, vie_c64* y, int32_t nvec,
+                             int32_t precision) {
+  if (!r || !x || !y || nvec < 1 || (precision != VIE_FP64 && precision != VIE_MIXED))
+    return VIE_EINVAL;
   if (r->poisoned) return VIE_ESTATE;
   const int64_t n = 3 * r->q.m;
   for (int v = 0; v < nvec; ++v) {
     RT_HIP(hipMemcpyAsync(r->vec[0], x + v * n, n * sizeof(c64), hipMemcpyHostToDevice,
                           r->stream));
-    RT_TRY(rt_apply(r, r->vec[0], r->vec[1]));
+    RT_TRY(rt_apply(r, r->vec[0], r->vec[1], precision == VIE_MIXED));
     RT_HIP(hipMemcpyAsync(y + v * n, r->vec[1], n * sizeof(c64), hipMemcpyDeviceToHost,
                           r->stream));
     RT_HIP(hipStreamSynchronize(r->stream));
@@ -714,10 +753,13 @@ extern "C" int vie_rt_matvec(vie_rt* r, const vie_c64* x, vie_c64* y, int32_t nv
 }
 
 extern "C" int vie_rt_solve(vie_rt* r, const vie_planewave* inc, int32_t nrhs, double tol,
-                            int32_t max_iter, vie_c64* w, vie_stats* stats) {
+                            int32_t max_iter, int32_t precision, vie_c64* w, vie_stats* stats) {
   TraceRange trace_("vie_rt_solve");
-  if (!r || !inc || !w || nrhs < 1 || !(tol > 0) || !(tol < 1) || max_iter < 1)
+  if (!r || !inc || !w || nrhs < 1 || !(tol > 0) || !(tol < 1) || max_iter < 1 ||
+      (precision != VIE_FP64 && precision != VIE_MIXED))
     return VIE_EINVAL;
+  const bool mixed = precision == VIE_MIXED;
+  constexpr double kInnerTol = 1e-3;  // residual reduction per refinement cycle (mixed)
   if (r->poisoned) return VIE_ESTATE;
   for (int k = 0; k < nrhs; ++k)
     for (int a = 0; a < 3; ++a)
@@ -761,7 +803,15 @@ extern "C" int vie_rt_solve(vie_rt* r, const vie_planewave* inc, int32_t nrhs, d
       RT_HIP(hipMemcpyAsync(rh, rr, n * sizeof(c64), hipMemcpyDeviceToDevice, r->stream));
       RT_HIP(hipMemsetAsync(p, 0, n * sizeof(c64), r->stream));
       RT_HIP(hipMemsetAsync(v, 0, n * sizeof(c64), r->stream));
-      k_rt_sinit<<<1, 1, 0, r->stream>>>(r->sc, tol * tol * bb.re, it, max_iter);
+      // the cycle's target: tol ||b||, and for a mixed solve no deeper than
+      // kInnerTol times its starting residual (the FP32 products' accuracy)
+      double tol2 = tol * tol * bb.re;
+      if (mixed) {
+        c64 r0;
+        RT_TRY(rt_dot(r, rr, rr, n, &r0));
+        tol2 = std::max(tol2, kInnerTol * kInnerTol * r0.re);
+      }
+      k_rt_sinit<<<1, 1, 0, r->stream>>>(r->sc, tol2, it, max_iter);
       RT_HIP(hipGetLastError());
       // iterations run in chunks with the scalars on the device; the host
       // looks at them once per chunk (iterations after a stop are no-ops)
@@ -774,12 +824,12 @@ extern "C" int vie_rt_solve(vie_rt* r, const vie_planewave* inc, int32_t nrhs, d
           k_rt_scal<<<1, kRtThreads, 0, r->stream>>>(r->part, r->sc, kScRho);
           k_rt_pupd<<<blocks_for(n), kRtThreads, 0, r->stream>>>(p, rr, v, r->sc, n);
           RT_HIP(hipGetLastError());
-          RT_TRY(rt_apply(r, p, v));
+          RT_TRY(rt_apply(r, p, v, mixed));
           k_rt_dot<<<kRtDotBlocks, kRtThreads, 0, r->stream>>>(rh, v, n, r->part);
           k_rt_scal<<<1, kRtThreads, 0, r->stream>>>(r->part, r->sc, kScAlpha);
           k_rt_supd<<<blocks_for(n), kRtThreads, 0, r->stream>>>(s, rr, v, r->sc, n);
           RT_HIP(hipGetLastError());
-          RT_TRY(rt_apply(r, s, t));
+          RT_TRY(rt_apply(r, s, t, mixed));
           k_rt_dot<<<kRtDotBlocks, kRtThreads, 0, r->stream>>>(t, s, n, r->part);
           k_rt_dot<<<kRtDotBlocks, kRtThreads, 0, r->stream>>>(t, t, n, r->part + kRtDotBlocks);
           k_rt_scal<<<1, kRtThreads, 0, r->stream>>>(r->part, r->sc, kScOmega);

@@ -110,9 +110,10 @@ def lib():
             "vie_strerror": (C.c_char_p, [C.c_int]),
             "vie_rt_setup": (C.c_int, [P(vie_body), C.c_double, P(C.c_void_p)]),
             "vie_rt_grid": (C.c_int, [C.c_void_p, P(C.c_int32), P(C.c_int32)]),
-            "vie_rt_matvec": (C.c_int, [C.c_void_p, P(vie_c64), P(vie_c64), C.c_int32]),
+            "vie_rt_matvec": (C.c_int, [C.c_void_p, P(vie_c64), P(vie_c64), C.c_int32,
+                                        C.c_int32]),
             "vie_rt_solve": (C.c_int, [C.c_void_p, P(vie_planewave), C.c_int32, C.c_double,
-                                       C.c_int32, P(vie_c64), P(vie_stats)]),
+                                       C.c_int32, C.c_int32, P(vie_c64), P(vie_stats)]),
             "vie_rt_farfield": (C.c_int, [C.c_void_p, P(vie_c64), C.c_int32, P(C.c_double),
                                           P(C.c_double), C.c_int32, P(vie_c64)]),
             "vie_rt_destroy": (None, [C.c_void_p]),
@@ -278,25 +279,26 @@ def vie_rt_grid(rt):
     return tuple(e), tuple(f)
 
 
-def vie_rt_matvec(rt, x):
+def vie_rt_matvec(rt, x, precision=VIE_FP64):
     """y = A x for x[nvec, 3, E3, E2, E1] (or one vector) on the padded grid."""
     xs = np.ascontiguousarray(x, dtype=np.complex128)
     single = xs.ndim == 4
     if single:
         xs = xs[None]
     y = np.zeros_like(xs)
-    _check(lib().vie_rt_matvec(rt, _cptr(xs), _cptr(y), xs.shape[0]), "vie_rt_matvec")
+    _check(lib().vie_rt_matvec(rt, _cptr(xs), _cptr(y), xs.shape[0], int(precision)),
+           "vie_rt_matvec")
     return y[0] if single else y
 
 
-def vie_rt_solve(rt, channels, tol=1e-8, max_iter=2000, allow_noconv=False):
+def vie_rt_solve(rt, channels, tol=1e-8, max_iter=2000, allow_noconv=False, precision=VIE_FP64):
     """BiCGSTAB solves of the channels; returns (status, w[nrhs, 3, E3, E2, E1], stats)."""
     E, _ = vie_rt_grid(rt)
     pw = planewaves(channels)
     n = len(channels)
     w = np.zeros((n, 3, E[2], E[1], E[0]), dtype=np.complex128)
     st = (vie_stats * max(1, n))()
-    rc = lib().vie_rt_solve(rt, pw, n, float(tol), int(max_iter), _cptr(w), st)
+    rc = lib().vie_rt_solve(rt, pw, n, float(tol), int(max_iter), int(precision), _cptr(w), st)
     _check(rc, "vie_rt_solve", allow=(VIE_ENOCONV,) if allow_noconv else ())
     out = [{f: getattr(st[i], f) for f, _ in vie_stats._fields_} for i in range(n)]
     return rc, w, out

@@ -4,12 +4,14 @@ convolves four scalar fields with the kernel's circulant spectrum).
 
 * product: every entry against the dense oracle on a sphere, a two-material
   body with holes touching the grid's edges, a single cell and a one-cell-thick
-  line (rel. 1e-12 of max |y|); sampled rows against the oracle's direct row
+  line (FP64 rel. 1e-12 of max |y|, FP32 transforms 5e-6); sampled rows against the oracle's direct row
   sums at 32^3 (circulant 96, a 3 * 2^k length) and 48^3 (128), with the
   inactive entries passed through exactly;
 * solve and far field: BiCGSTAB to 1e-11 against the oracle's LU solution
   (rel. 1e-9) for two channels on a sphere and for the two-material body,
   far field against the oracle's radiation sum;
+* mixed precision: FP32 products inside FP64 refinement solve to the LU
+  solution (rel. 1e-8);
 * physics: the 16^3 sphere's far-field error against Mie equals the oracle's
   (4.21 %), and refinement to 24^3 lowers it;
 * edges: a body without voxels solves to zero; bad shapes and values are
@@ -69,6 +71,8 @@ def test_product_matches_dense_oracle(V, case):
         y = V.vie_rt_matvec(h, x)
         want = rt.matvec(chi, g.h, g.origin, k0, x.reshape(3, -1)).reshape(y.shape)
         assert np.max(np.abs(y - want)) <= 1e-12 * np.max(np.abs(want))
+        y32 = V.vie_rt_matvec(h, x, precision=V.VIE_MIXED)
+        assert np.max(np.abs(y32 - want)) <= 5e-6 * np.max(np.abs(want))
     finally:
         V.vie_rt_destroy(h)
 
@@ -128,6 +132,22 @@ def test_solve_and_farfield_match_lu(V):
             r = vd.direction(th, ph)[0]
             Fref = _project(rt.farfield_vec(chi, g.h, g.origin, K0, ref, r), th, ph)
             assert np.max(np.abs(F[k] - Fref)) <= 1e-9 * np.max(np.abs(Fref))
+    finally:
+        V.vie_rt_destroy(h)
+
+
+def test_mixed_solve_matches_lu(V):
+    """FP32 products inside FP64 refinement to 1e-10: the same solution as the
+    oracle's LU (rel. 1e-8), more iterations than FP64 but the FP64 residual."""
+    g = Grid.centred(12, 1.0 / 12)
+    chi = sphere(g, 0.5, 2.25) - 1
+    h = V.vie_rt_setup(chi + 1, g.h, g.origin, K0)
+    try:
+        rc, w, st = V.vie_rt_solve(h, [([0, 0, 1], [1, 0, 0])], tol=1e-10, max_iter=3000,
+                                   precision=V.VIE_MIXED)
+        assert rc == V.VIE_OK and st[0]["rel_res"] <= 1e-10 and st[0]["cycles"] >= 2
+        ref = rt.solve_lu(chi, g.h, g.origin, K0, [0, 0, 1], [1, 0, 0])
+        assert np.max(np.abs(w[0].reshape(3, -1) - ref)) <= 1e-8 * np.max(np.abs(ref))
     finally:
         V.vie_rt_destroy(h)
 
