@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvie.so")
+# VIE_LIB selects another build of the library (the host-ASan one in tests)
+LIB_PATH = os.environ.get("VIE_LIB") or os.path.join(_HERE, "libvie.so")
 
 VIE_OK, VIE_EINVAL, VIE_ENOMEM, VIE_EDEVICE, VIE_ENOCONV, VIE_ENOTSUP, VIE_ESTATE = 0, -1, -2, -3, -4, -5, -6
 VIE_FP64, VIE_MIXED, VIE_MIXED_BF16 = 0, 1, 2
