@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--solver", choices=["fgmres", "bicgstab"], default=None,
                     help="fast leg: block-Jacobi FGMRES (vie_solve_fgmres) or BiCGSTAB with FP64 "
                          "refinement (vie_solve); default FGMRES, BiCGSTAB in --mode uneven")
-    ap.add_argument("--restart", type=int, default=60, help="FGMRES steps per cycle")
+    ap.add_argument("--restart", type=int, default=40, help="FGMRES steps per cycle")
     ap.add_argument("--blocks", default="2,2", help="FGMRES lateral block partition bx,by")
     ap.add_argument("--inner-iters", type=int, default=8, help="GMRES steps per block solve")
     ap.add_argument("--block-basis", choices=["fp32", "bf16"], default="bf16",
