@@ -14,7 +14,7 @@ evaluate it against the plain start on held-out bodies.
 3. Evaluation: held-out bodies (seed 55, drawn like the benchmark's):
    iterations, solves/s and fallback rate with and without
    the warm start, same solver and tolerance, solved in chunks of `chunk`
-   bodies; the final FP64 true residual judges both.
+   bodies; the final FP64 true residual decides for both.
 
 Writes the fp32 parameter vector (numpy .npy) and a JSON summary.
 """
