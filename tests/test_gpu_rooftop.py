@@ -5,8 +5,8 @@ convolves four scalar fields with the kernel's circulant spectrum).
 * product: every entry against the dense oracle on a sphere, a two-material
   body with holes touching the grid's edges, a single cell and a one-cell-thick
   line (FP64 rel. 1e-12 of max |y|, FP32 transforms 5e-6); sampled rows against the oracle's direct row
-  sums at 32^3 (circulant 96, a 3 * 2^k length) and 48^3 (128), with the
-  inactive entries passed through exactly;
+  sums at 32^3 (circulant 96, a 3 * 2^k length) and 48^3 (128), FP64 and
+  FP32 transforms, with the inactive entries passed through exactly;
 * solve and far field: BiCGSTAB to 1e-11 against the oracle's LU solution
   (rel. 1e-9) for two channels on a sphere and for the two-material body,
   far field against the oracle's radiation sum;
@@ -99,6 +99,9 @@ def test_product_sampled_rows_large(V, n, P):
         want = rt.matvec_rows(chi, g.h, g.origin, K0, x.reshape(3, -1), rows)
         got = y.ravel()[rows]
         assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))
+        y32 = V.vie_rt_matvec(h, x, precision=V.VIE_MIXED)
+        assert np.array_equal(y32[~act], x[~act])
+        assert np.max(np.abs(y32.ravel()[rows] - want)) <= 5e-6 * np.max(np.abs(want))
     finally:
         V.vie_rt_destroy(h)
 
