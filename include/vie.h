@@ -269,8 +269,9 @@ int vie_grid(vie_ctx *ctx, int32_t body, int32_t *grid, int32_t *fft, int32_t *o
 int vie_self_term(int32_t kind, double k0, double h, vie_c64 *s);
 
 /* ---------------------------------------------------------------------------
- * Rooftop basis with pulse testing (Sec. II-C, eq. Js_expand), FP64: the
- * paper's own discretisation, beside the pulse-basis operator above.
+ * Rooftop basis with pulse testing (Sec. II-C, eq. Js_expand): the paper's
+ * own discretisation, beside the pulse-basis operator above (FP64, or FP32
+ * products inside FP64 refinement).
  *   Unknown w = chi E, component i expanded in rooftops on the faces normal
  *   to i of the body grid padded by one cell per side ("padded grid", E =
  *   n + 2 cells per axis; padded cell c is centred at origin + h (c - 1)).

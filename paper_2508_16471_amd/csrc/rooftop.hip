@@ -1,4 +1,5 @@
-// Rooftop basis with pulse testing (Sec. II-C, eq. Js_expand), FP64.
+// Rooftop basis with pulse testing (Sec. II-C, eq. Js_expand): FP64 products,
+// or FP32 products inside FP64 refinement.
 //
 // The paper expands the current in rooftops along x, y and z on the uniform
 // grid and tests with pulses.  Reading taken (entries and the body surface
