@@ -264,3 +264,23 @@ def test_two_material_solve_matches_lu(V):
         assert np.max(np.abs(w[0].reshape(3, -1) - ref)) <= 1e-9 * np.max(np.abs(ref))
     finally:
         V.vie_rt_destroy(h)
+
+
+def test_iteration_cap_and_restart_accounting(V):
+    """A cap of 5 iterations ends the solve with VIE_ENOCONV, exactly 5
+    iterations counted (the device-side cap), a finite residual below 1 and
+    the best iterate returned; FP64 and mixed."""
+    g = Grid.centred(12, 1.0 / 12)
+    chi = sphere(g, 0.5, 2.25) - 1
+    h = V.vie_rt_setup(chi + 1, g.h, g.origin, K0)
+    try:
+        for prec in (V.VIE_FP64, V.VIE_MIXED):
+            rc, w, st = V.vie_rt_solve(h, [([0, 0, 1], [1, 0, 0]), ([1, 0, 0], [0, 1, 0])],
+                                       tol=1e-10, max_iter=5, allow_noconv=True, precision=prec)
+            assert rc == V.VIE_ENOCONV
+            for s in st:
+                assert s["iters"] == 5 and s["converged"] == 0
+                assert np.isfinite(s["rel_res"]) and 0 < s["rel_res"] < 1
+            assert np.all(np.isfinite(w)) and np.any(w)
+    finally:
+        V.vie_rt_destroy(h)
