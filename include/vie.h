@@ -296,11 +296,11 @@ typedef struct vie_rt vie_rt;
 
 /* Build the operator of one body (n: 1..128 per axis, VIE_ENOTSUP above;
  * eps_r as vie_body) at wavenumber k0: face data, the spectrum of the scalar
- * kernel's circulant (length P >= 2 E - 1 per axis, P1 P2 P3 complex
- * doubles and an FP32 copy), transform scratch (2 E3 P2 P1 + 2 E3 E2 P1
- * complex) and fields
- * and solver vectors (36 E1 E2 E3 complex); setup needs two more P1 P2 P3
- * complex for the duration of the call.  VIE_EINVAL on bad values. */
+ * kernel's circulant (length P >= 2 E - 1 per axis; kept on its octant,
+ * (P1/2 + 1)(P2/2 + 1)(P3/2 + 1) complex doubles and an FP32 copy), transform
+ * scratch (2 E3 P2 P1 + 2 E3 E2 P1 complex), fields and solver vectors
+ * (36 E1 E2 E3 complex); setup needs two P1 P2 P3 complex arrays for the
+ * duration of the call.  VIE_EINVAL on bad values. */
 int vie_rt_setup(const vie_body *body, double k0, vie_rt **out);
 
 /* Padded grid E[3] and circulant lengths P[3]; either may be NULL. */

@@ -91,11 +91,20 @@ __global__ void k_rt_green(c64* __restrict__ work, RtGeom q, double h, double k0
   }
 }
 
-__global__ void k_rt_scale(const c64* __restrict__ in, c64* __restrict__ out, int64_t M,
-                           double s) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M;
-       e += (int64_t)gridDim.x * blockDim.x)
-    out[e] = s * in[e];
+// The kernel samples are even along every axis (they depend on |d| per
+// axis), so is their transform: only the octant [0, P/2]^3 is kept,
+// [z][y][x] with extents Q = P/2 + 1, scaled by s (= 1/M), with an FP32 copy.
+__global__ void k_rt_octant(const c64* __restrict__ in, c64* __restrict__ out,
+                            c32* __restrict__ out32, RtGeom q, double s) {
+  const int Q0 = q.P[0] / 2 + 1, Q1 = q.P[1] / 2 + 1, Q2 = q.P[2] / 2 + 1;
+  const int64_t n = (int64_t)Q0 * Q1 * Q2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(e % Q0), y = (int)((e / Q0) % Q1), z = (int)(e / ((int64_t)Q0 * Q1));
+    const c64 v = s * in[((int64_t)z * q.P[1] + y) * q.P[0] + x];
+    out[e] = v;
+    out32[e] = cvt<float>(v);
+  }
 }
 
 // One input field of the product over the padded grid ([E3][E2][E1]): f < 3
@@ -144,6 +153,12 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_rt_zconv(
   const bool valid = col < P1;
   const int64_t plane = (int64_t)P2 * P1;
   const int64_t base = (int64_t)y * P1 + (valid ? col : 0);
+  // the spectrum's octant record of this column (mirrored x and y)
+  const int Q0 = P1 / 2 + 1, Q1 = P2 / 2 + 1;
+  const int xo = valid ? (col <= P1 / 2 ? col : P1 - col) : 0;
+  const int yo = y <= P2 / 2 ? y : P2 - y;
+  const cpx<T>* gcol = ghat + (int64_t)yo * Q0 + xo;
+  const int64_t gplane = (int64_t)Q0 * Q1;
   TwReg<T, P, E> tr;
   tr.load(t, tw);
   cpx<T> v[E];
@@ -155,7 +170,8 @@ __global__ __launch_bounds__(nt_lines<T>()) void k_rt_zconv(
   line_fft<T, P, false, true, false>(v, lds + cw * Pad<P>::LSTR, t, tr);
 #pragma unroll
   for (int q = 0; q < E; ++q) {
-    const cpx<T> p = v[q] * ghat[base + (int64_t)(t + q * TT) * plane];
+    const int z = t + q * TT;
+    const cpx<T> p = v[q] * gcol[(int64_t)(z <= P / 2 ? z : P - z) * gplane];
     v[q] = mk(p.re, -p.im);
   }
   line_fft<T, P, false, false, true>(v, lds + cw * Pad<P>::LSTR, t, tr);
@@ -179,13 +195,6 @@ __global__ void k_rt_store(const cpx<T>* __restrict__ t, c64* __restrict__ R, Rt
     const cpx<T> v = t[yz * q.P[0] + x];
     R[c] = mk((double)v.re, -(double)v.im);
   }
-}
-
-// FP32 copy of the spectrum.
-__global__ void k_rt_to32(const c64* __restrict__ in, c32* __restrict__ out, int64_t M) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M;
-       e += (int64_t)gridDim.x * blockDim.x)
-    out[e] = cvt<float>(in[e]);
 }
 
 // y = x - chi_f (k0^2 A_i + (phi(c + e_i) - phi(c)) / h) on active faces,
@@ -515,8 +524,8 @@ struct vie_rt {
   bool poisoned = false;
   double* alpha = nullptr;  // [3][m]
   double* chif = nullptr;   // [3][m]
-  c64* ghat = nullptr;      // [M] spectrum / M
-  c32* ghat32 = nullptr;    // [M] its FP32 copy
+  c64* ghat = nullptr;      // spectrum / M on the octant [0, P/2]^3
+  c32* ghat32 = nullptr;    // its FP32 copy
   c64* tw[3] = {nullptr, nullptr, nullptr};
   c32* tw32[3] = {nullptr, nullptr, nullptr};
   c64* work = nullptr;  // [M]
@@ -726,8 +735,9 @@ extern "C" int vie_rt_setup(const vie_body* body, double k0, vie_rt** out) {
   chk(hipStreamCreate(&r->stream));
   chk(dalloc(&r->alpha, 3 * m));
   chk(dalloc(&r->chif, 3 * m));
-  chk(dalloc(&r->ghat, M));
-  chk(dalloc(&r->ghat32, M));
+  const int64_t noct = (int64_t)(q.P[0] / 2 + 1) * (q.P[1] / 2 + 1) * (q.P[2] / 2 + 1);
+  chk(dalloc(&r->ghat, noct));
+  chk(dalloc(&r->ghat32, noct));
   chk(dalloc(&r->work, M));
   chk(dalloc(&r->tmp, M));
   chk(dalloc(&r->R, 4 * m));
@@ -769,9 +779,8 @@ extern "C" int vie_rt_setup(const vie_body* body, double k0, vie_rt** out) {
   }
   if (e == hipSuccess) chk(launch_fft3d_full(r->work, r->tmp, r->g, tw, r->stream));
   if (e == hipSuccess) {
-    k_rt_scale<<<blocks_for(M), kRtThreads, 0, r->stream>>>(r->tmp, r->ghat, M, 1.0 / (double)M);
-    chk(hipGetLastError());
-    k_rt_to32<<<blocks_for(M), kRtThreads, 0, r->stream>>>(r->ghat, r->ghat32, M);
+    k_rt_octant<<<blocks_for(noct), kRtThreads, 0, r->stream>>>(r->tmp, r->ghat, r->ghat32, q,
+                                                                   1.0 / (double)M);
     chk(hipGetLastError());
   }
   if (e == hipSuccess) chk(hipStreamSynchronize(r->stream));
